@@ -1,0 +1,108 @@
+/*
+ * oracle.h -- plain FP64 CPU oracle of the raspberry-colloid / lattice-Boltzmann step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct reference that the
+ * GPU library is checked against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no source, header, table or generator with the
+ * GPU library (paper_1604_01829_amd/csrc, include/lbrb.h), and it includes none of them.
+ *
+ * What it computes (Ustach & Faller, "The Raspberry model for protein-like particles",
+ * arXiv:1604.01829):
+ *   - the lattice-Boltzmann stream / collide cycle with multiple relaxation times
+ *     (Sec. 1.1, "Hydrodynamic Interactions"), on the D3Q19 lattice;
+ *   - bounce-back boundary nodes (Sec. 1.1, last paragraph; Sec. 2.2 for the pore wall);
+ *   - the stochastic (thermal) variant of the fluid (Sec. 1.1);
+ *   - the frictional bead/fluid coupling, eq. (latticeboltzmannfriction) in Sec. 1.1,
+ *     with the fluid velocity interpolated between the nearest nodes and a bead noise
+ *     obeying fluctuation-dissipation;
+ *   - raspberry rigid bodies whose beads are virtual sites of a centre (Sec. 1.2), with
+ *     forces/torques summed onto the centre in the body frame and a velocity-Verlet /
+ *     quaternion update of the centre (Sec. 2.3, "Simulation parameters").
+ * The paper names these steps but gives no formulas for the lattice scheme, forcing,
+ * noise or integrator; every such choice made here is listed, with its reason, in the
+ * design document of the repository ("readings").  All quantities are in lattice units
+ * (spacing 1, time step 1).
+ *
+ * parity pinned: every function here is checked by tests/test_oracle_*.py against closed
+ * forms, invariants, special cases or an independent implementation (rocRAND's Philox).
+ */
+#ifndef LBRB_ORACLE_H
+#define LBRB_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_sim orc_sim;
+
+typedef struct {
+    double rho0;          /* rest density                                            */
+    double u0[3];         /* initial uniform velocity                                */
+    double tau_shear;     /* relaxation time of the shear modes 5..9                  */
+    double tau_bulk;      /* relaxation time of the bulk mode 4                       */
+    double tau_odd;       /* relaxation time of the odd (kinetic) modes 10..15        */
+    double tau_even;      /* relaxation time of the even (kinetic) modes 16..18       */
+    double kT;            /* thermal energy; 0 = deterministic fluid and beads        */
+    double g_ext[3];      /* body-force density acting on every fluid node            */
+    uint64_t seed;        /* Philox key of this box                                   */
+} orc_params;
+
+/* ---- lattice and mode tables (exposed so the tests can pin them) ---- */
+int    orc_velocity(int i, int axis);           /* c_i[axis], i = 0..18                 */
+double orc_weight(int i);                        /* w_i                                   */
+int    orc_opposite(int i);                      /* index of -c_i                         */
+double orc_basis(int k, int i);                  /* e_k(c_i)                              */
+double orc_basis_norm(int k);                    /* b_k = sum_i w_i e_k(c_i)^2           */
+
+/* ---- counter-based random numbers ---- */
+void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_uniform16(uint32_t h);                /* 16-bit integer -> (-1/2, 1/2)        */
+
+/* ---- single-node pieces (pure functions of their arguments) ---- */
+/* post-collision populations of one node: f_in[19] pre-collision, force density F[3],
+ * noise uniforms unoise[19] (entries 4..18 used; pass NULL for a deterministic node). */
+void   orc_collide_node(const orc_params* p, const double f_in[19], const double F[3],
+                        const double* unoise, double f_out[19]);
+/* equilibrium populations for density rho and velocity u                                  */
+void   orc_equilibrium(double rho, const double u[3], double f_out[19]);
+/* trilinear stencil of a point r in a periodic nx*ny*nz lattice whose node (i,j,k) sits
+ * at (i+1/2, j+1/2, k+1/2): 8 dense node indices and their weights.                      */
+void   orc_trilinear(int nx, int ny, int nz, const double r[3], int64_t idx[8], double w[8]);
+
+/* ---- whole box ---- */
+orc_sim* orc_create(int nx, int ny, int nz, const orc_params* p);
+void     orc_destroy(orc_sim* s);
+/* mask[nx*ny*nz], x fastest, 1 = solid.  Only before the first step. 0 ok, -1 error.     */
+int      orc_set_mask(orc_sim* s, const uint8_t* mask);
+/* A raspberry: bead offsets in the body frame (n*3), mass, principal inertia, pose,
+ * lab velocity, body-frame angular velocity, bead friction gamma, fixed flag.
+ * Returns the body id (>= 0) or -1.                                                       */
+int      orc_add_body(orc_sim* s, const double* offsets, int n_beads, double mass,
+                      const double inertia[3], const double pos[3], const double quat[4],
+                      const double vel[3], const double omega_body[3], double gamma,
+                      int fixed);
+int      orc_step(orc_sim* s, int n_steps);
+int64_t  orc_step_count(const orc_sim* s);
+/* rho and u = (j + g_ext/2)/rho of the current pre-collision state, 4*N, node-major
+ * (rho,ux,uy,uz per node); solid nodes give zeros.                                        */
+void     orc_fields(const orc_sim* s, double* rho_u);
+/* the 19 current pre-collision populations, [i][node] (19*N)                              */
+void     orc_populations(const orc_sim* s, double* f);
+/* overwrite the current pre-collision populations (19*N, [i][node]); boundary nodes are
+ * kept at zero.  Test hook for prescribed initial states.                                 */
+void     orc_set_populations(orc_sim* s, const double* f);
+/* out[0] = sum rho, out[1..3] = sum j, out[4..6] = sum of M V over free bodies,
+ * out[7] = 1 if every population is finite else 0                                        */
+void     orc_totals(const orc_sim* s, double out[8]);
+/* pos3 quat4 vel3 omega_body3 force3 (lab, last step) torque3 (body frame, last step)    */
+int      orc_body_state(const orc_sim* s, int body, double out[19]);
+/* per-bead force of the last step, lab frame, n_beads*3 for the body                     */
+int      orc_bead_forces(const orc_sim* s, int body, double* out);
+int      orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

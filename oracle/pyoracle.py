@@ -1,0 +1,269 @@
+"""ctypes wrapper of the FP64 CPU oracle (``oracle/liborc.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU-baseline leg of
+the benchmark.  Argument marshalling only; all arithmetic is in the C sources of ``oracle/``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liborc.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [
+        ("rho0", ctypes.c_double),
+        ("u0", ctypes.c_double * 3),
+        ("tau_shear", ctypes.c_double),
+        ("tau_bulk", ctypes.c_double),
+        ("tau_odd", ctypes.c_double),
+        ("tau_even", ctypes.c_double),
+        ("kT", ctypes.c_double),
+        ("g_ext", ctypes.c_double * 3),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build
+            build.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.orc_velocity.restype = ctypes.c_int
+        L.orc_velocity.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_weight.restype = ctypes.c_double
+        L.orc_weight.argtypes = [ctypes.c_int]
+        L.orc_opposite.restype = ctypes.c_int
+        L.orc_opposite.argtypes = [ctypes.c_int]
+        L.orc_basis.restype = ctypes.c_double
+        L.orc_basis.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_basis_norm.restype = ctypes.c_double
+        L.orc_basis_norm.argtypes = [ctypes.c_int]
+        L.orc_philox4x32_10.restype = None
+        L.orc_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+        L.orc_uniform16.restype = ctypes.c_double
+        L.orc_uniform16.argtypes = [ctypes.c_uint32]
+        L.orc_collide_node.restype = None
+        L.orc_collide_node.argtypes = [ctypes.POINTER(OrcParams), _D, _D, _D, _D]
+        L.orc_equilibrium.restype = None
+        L.orc_equilibrium.argtypes = [ctypes.c_double, _D, _D]
+        L.orc_trilinear.restype = None
+        L.orc_trilinear.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _D,
+                                    ctypes.POINTER(ctypes.c_int64), _D]
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(OrcParams)]
+        L.orc_destroy.restype = None
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_set_mask.restype = ctypes.c_int
+        L.orc_set_mask.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8)]
+        L.orc_add_body.restype = ctypes.c_int
+        L.orc_add_body.argtypes = [ctypes.c_void_p, _D, ctypes.c_int, ctypes.c_double, _D, _D,
+                                   _D, _D, _D, ctypes.c_double, ctypes.c_int]
+        L.orc_step.restype = ctypes.c_int
+        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_step_count.restype = ctypes.c_int64
+        L.orc_step_count.argtypes = [ctypes.c_void_p]
+        L.orc_fields.restype = None
+        L.orc_fields.argtypes = [ctypes.c_void_p, _D]
+        L.orc_populations.restype = None
+        L.orc_populations.argtypes = [ctypes.c_void_p, _D]
+        L.orc_set_populations.restype = None
+        L.orc_set_populations.argtypes = [ctypes.c_void_p, _D]
+        L.orc_totals.restype = None
+        L.orc_totals.argtypes = [ctypes.c_void_p, _D]
+        L.orc_body_state.restype = ctypes.c_int
+        L.orc_body_state.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
+        L.orc_bead_forces.restype = ctypes.c_int
+        L.orc_bead_forces.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_num_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+def _vec(x, n):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(n))
+    return a
+
+
+def make_params(rho0=1.0, u0=(0.0, 0.0, 0.0), tau_shear=1.0, tau_bulk=None, tau_odd=1.0,
+                tau_even=1.0, kT=0.0, g_ext=(0.0, 0.0, 0.0), seed=0):
+    p = OrcParams()
+    p.rho0 = rho0
+    p.u0[:] = list(u0)
+    p.tau_shear = tau_shear
+    p.tau_bulk = tau_shear if tau_bulk is None else tau_bulk
+    p.tau_odd = tau_odd
+    p.tau_even = tau_even
+    p.kT = kT
+    p.g_ext[:] = list(g_ext)
+    p.seed = seed
+    return p
+
+
+# ---------------------------------------------------------------- tables and pure functions
+
+def velocities():
+    L = lib()
+    return np.array([[L.orc_velocity(i, a) for a in range(3)] for i in range(19)], dtype=np.int64)
+
+
+def weights():
+    L = lib()
+    return np.array([L.orc_weight(i) for i in range(19)])
+
+
+def opposite():
+    L = lib()
+    return np.array([L.orc_opposite(i) for i in range(19)], dtype=np.int64)
+
+
+def basis():
+    L = lib()
+    return np.array([[L.orc_basis(k, i) for i in range(19)] for k in range(19)])
+
+
+def basis_norms():
+    L = lib()
+    return np.array([L.orc_basis_norm(k) for k in range(19)])
+
+
+def philox(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def uniform16(h):
+    return lib().orc_uniform16(int(h))
+
+
+def equilibrium(rho, u):
+    out = np.zeros(19)
+    lib().orc_equilibrium(float(rho), _dp(_vec(u, 3)), _dp(out))
+    return out
+
+
+def collide_node(params, f_in, F, unoise=None):
+    out = np.zeros(19)
+    fin = _vec(f_in, 19)
+    Fv = _vec(F, 3)
+    un = None if unoise is None else _vec(unoise, 19)
+    lib().orc_collide_node(ctypes.byref(params), _dp(fin), _dp(Fv),
+                           None if un is None else _dp(un), _dp(out))
+    return out
+
+
+def trilinear(shape, r):
+    idx = np.zeros(8, dtype=np.int64)
+    w = np.zeros(8)
+    nx, ny, nz = shape
+    lib().orc_trilinear(nx, ny, nz, _dp(_vec(r, 3)), idx.ctypes.data_as(
+        ctypes.POINTER(ctypes.c_int64)), _dp(w))
+    return idx, w
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+# ---------------------------------------------------------------- a box
+
+class OracleSim:
+    """One box of the oracle: same call sequence as the GPU library's C-ABI."""
+
+    def __init__(self, shape, params):
+        self.shape = tuple(int(v) for v in shape)
+        self.n = self.shape[0] * self.shape[1] * self.shape[2]
+        self.params = params
+        self._h = lib().orc_create(self.shape[0], self.shape[1], self.shape[2],
+                                   ctypes.byref(params))
+        if not self._h:
+            raise RuntimeError("orc_create failed")
+        self.n_bodies = 0
+        self.beads_per_body = []
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    def set_mask(self, mask):
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(-1))
+        assert m.size == self.n
+        rc = lib().orc_set_mask(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        if rc != 0:
+            raise RuntimeError("orc_set_mask failed")
+
+    def add_body(self, offsets, mass, inertia, pos, quat=(1, 0, 0, 0), vel=(0, 0, 0),
+                 omega=(0, 0, 0), gamma=0.0, fixed=False):
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.float64).reshape(-1, 3))
+        bid = lib().orc_add_body(self._h, _dp(off), off.shape[0], float(mass),
+                                 _dp(_vec(inertia, 3)), _dp(_vec(pos, 3)), _dp(_vec(quat, 4)),
+                                 _dp(_vec(vel, 3)), _dp(_vec(omega, 3)), float(gamma),
+                                 1 if fixed else 0)
+        if bid < 0:
+            raise RuntimeError("orc_add_body failed")
+        self.n_bodies += 1
+        self.beads_per_body.append(off.shape[0])
+        return bid
+
+    def step(self, n=1):
+        if lib().orc_step(self._h, int(n)) != 0:
+            raise RuntimeError("orc_step failed")
+
+    @property
+    def step_count(self):
+        return lib().orc_step_count(self._h)
+
+    def fields(self):
+        """(nz, ny, nx, 4) array of rho, ux, uy, uz; zeros on boundary nodes."""
+        out = np.zeros(self.n * 4)
+        lib().orc_fields(self._h, _dp(out))
+        return out.reshape(self.shape[2], self.shape[1], self.shape[0], 4)
+
+    def populations(self):
+        """(19, nz, ny, nx) pre-collision populations."""
+        out = np.zeros(19 * self.n)
+        lib().orc_populations(self._h, _dp(out))
+        return out.reshape(19, self.shape[2], self.shape[1], self.shape[0])
+
+    def set_populations(self, f):
+        a = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1))
+        assert a.size == 19 * self.n
+        lib().orc_set_populations(self._h, _dp(a))
+
+    def totals(self):
+        out = np.zeros(8)
+        lib().orc_totals(self._h, _dp(out))
+        return {"mass": out[0], "momentum": out[1:4].copy(), "body_momentum": out[4:7].copy(),
+                "finite": bool(out[7])}
+
+    def body_state(self, b):
+        out = np.zeros(19)
+        if lib().orc_body_state(self._h, int(b), _dp(out)) != 0:
+            raise IndexError(b)
+        return {"pos": out[0:3].copy(), "quat": out[3:7].copy(), "vel": out[7:10].copy(),
+                "omega": out[10:13].copy(), "force": out[13:16].copy(),
+                "torque": out[16:19].copy()}
+
+    def bead_forces(self, b):
+        out = np.zeros(self.beads_per_body[b] * 3)
+        if lib().orc_bead_forces(self._h, int(b), _dp(out)) != 0:
+            raise IndexError(b)
+        return out.reshape(-1, 3)
