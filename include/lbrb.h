@@ -1,0 +1,175 @@
+/*
+ * lbrb.h -- C-ABI of the MI355X (gfx950) raspberry-colloid / lattice-Boltzmann library.
+ *
+ * The method is the one of Ustach & Faller, "The Raspberry model for protein-like
+ * particles: ellipsoids and confinement in cylindrical pores" (arXiv:1604.01829):
+ *   - a lattice-Boltzmann fluid that streams and collides with multiple relaxation times
+ *     (Sec. 1.1), here on the D3Q19 lattice, thermal (stochastic) or deterministic (Sec. 1.1),
+ *     with bounce-back boundary nodes (Sec. 1.1; the pore wall of Sec. 2.2);
+ *   - rigid raspberries: beads that are virtual sites of a centre (Sec. 1.2), each coupled to
+ *     the fluid by the frictional force of eq. (latticeboltzmannfriction) with the fluid
+ *     velocity interpolated between the nearest nodes and a fluctuation-dissipation noise;
+ *     the opposite force goes to the fluid;
+ *   - forces and torques of the beads summed onto the centre and turned into the body frame;
+ *     velocity Verlet for the centre and a quaternion update for its orientation (Sec. 2.3).
+ *
+ * Conventions.  Lattice units: spacing 1, time step 1.  Node (x,y,z) of a box of nx*ny*nz
+ * nodes sits at (x+1/2, y+1/2, z+1/2); the box is periodic in every direction and boundary
+ * nodes (a mask) make walls.  Host arrays are x-fastest.  Quaternions are (w,x,y,z) and
+ * rotate body-frame vectors into the lab frame.
+ *
+ * Memory and streams.  The library never allocates device memory for its state: the caller
+ * passes one device workspace of lb_workspace_bytes() bytes (for instance a torch tensor)
+ * and a HIP stream; the workspace must outlive the context.  Every call enqueues work on
+ * that stream.  lb_observables, lb_save_state, lb_load_state, lb_set_boundary_mask and
+ * rb_add_raspberry synchronise the stream before returning; lb_rb_step does not.
+ *
+ * Errors.  Every call returns LB_OK (0) or a negative code; lb_last_error() gives a message.
+ * After LB_ERR_HIP the context should be destroyed; after any other code it stays usable.
+ * A context is not thread-safe.
+ */
+#ifndef LBRB_H
+#define LBRB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_OK 0
+#define LB_ERR_ARG (-1)       /* an argument is out of range or inconsistent              */
+#define LB_ERR_STATE (-2)     /* the call is not allowed in the context's current state    */
+#define LB_ERR_HIP (-3)       /* a HIP runtime call failed                                  */
+#define LB_ERR_UNSTABLE (-4)  /* non-finite populations, or a spread force out of range     */
+#define LB_ERR_CAPACITY (-5)  /* more bodies/beads than the context was sized for           */
+
+#define LB_PRECISION_F64 0    /* populations and node arithmetic in FP64                     */
+#define LB_PRECISION_F32 1    /* FP32 populations stored as f_i - w_i rho0, FP32 arithmetic  */
+
+typedef struct lb_ctx lb_ctx;
+
+/* One independent box.  seed keys all random numbers of the box (Philox4x32-10).          */
+typedef struct {
+    int32_t nx, ny, nz;
+    uint64_t seed;
+} lb_replica;
+
+typedef struct {
+    int32_t precision;        /* LB_PRECISION_F64 or LB_PRECISION_F32                      */
+    double rho0;              /* rest density (> 0)                                         */
+    double u0[3];             /* initial uniform fluid velocity                             */
+    double tau_shear;         /* relaxation time of the 5 shear modes (> 1/2)               */
+    double tau_bulk;          /* relaxation time of the bulk mode (> 1/2)                   */
+    double tau_odd;           /* relaxation time of the 6 odd kinetic modes (> 1/2)         */
+    double tau_even;          /* relaxation time of the 3 even kinetic modes (> 1/2)        */
+    double kT;                /* thermal energy (>= 0); 0 = deterministic fluid and beads   */
+    double g_ext[3];          /* force density on every fluid node (not on bodies)          */
+    int32_t max_bodies;       /* capacity over all replicas                                 */
+    int32_t max_beads;        /* capacity over all replicas                                 */
+} lb_params;
+
+/* Device bytes needed for these parameters and boxes (upper bound, all nodes fluid).
+ * Returns 0 if the arguments are invalid.                                                 */
+size_t lb_workspace_bytes(const lb_params* params, const lb_replica* replicas,
+                          int32_t n_replicas);
+
+/* Create a context.  Lays out the workspace, fills every fluid node with the equilibrium
+ * of (rho0, u0) just before a streaming step, and returns the context in *out.
+ * dev_workspace: device pointer, 256-byte aligned, ws_bytes >= lb_workspace_bytes().
+ * hip_stream: a hipStream_t (NULL = the null stream).                                      */
+int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_replicas,
+            void* dev_workspace, size_t ws_bytes, void* hip_stream, lb_ctx** out);
+
+/* Boundary nodes of one replica (the bounce-back rule of Sec. 1.1; the pore wall nodes of
+ * Sec. 2.2).  host_mask: nx*ny*nz bytes, x fastest, nonzero = boundary node; copied.
+ * Every (y,z) row may hold at most one contiguous run of fluid nodes (a row that is fluid
+ * everywhere counts as one run), which covers cylindrical pores along z, slabs and
+ * channels; other masks return LB_ERR_ARG.  Only before the first step (LB_ERR_STATE
+ * otherwise).  Re-initialises that replica's fluid to equilibrium.                        */
+int lb_set_boundary_mask(lb_ctx* ctx, int32_t replica, const uint8_t* host_mask);
+
+/* Add a raspberry (Sec. 1.2) to a replica.  bead_offsets_body: n_beads*3 body-frame bead
+ * positions relative to the centre (a centre bead is just an offset (0,0,0)); mass and
+ * principal moments of inertia (ignored when fixed); centre position (lab, unwrapped),
+ * orientation quaternion (w,x,y,z; normalised here), lab velocity, body-frame angular
+ * velocity; gamma = bead friction of eq. (latticeboltzmannfriction); fixed != 0 holds the
+ * body still (its beads have zero velocity, forces are still measured).  All host arrays
+ * are copied.  *body_id receives the body's index within its replica.  Bodies may be added
+ * at any step; a new body starts with zero force and torque.                              */
+int rb_add_raspberry(lb_ctx* ctx, int32_t replica, const double* bead_offsets_body,
+                     int32_t n_beads, double mass, const double inertia_body[3],
+                     const double pos[3], const double quat_wxyz[4], const double vel[3],
+                     const double omega_body[3], double gamma, int32_t fixed,
+                     int32_t* body_id);
+
+/* Advance every replica by n_steps time steps (n_steps >= 0).  Each step: half kick and
+ * drift of free bodies, bead coupling and force spreading, per-body force/torque sums and
+ * the second half kick, then the fused collide-and-stream update of every fluid node.
+ * Asynchronous on the context's stream.                                                    */
+int lb_rb_step(lb_ctx* ctx, int32_t n_steps);
+
+typedef struct {
+    double mass;              /* sum of rho over the replica's fluid nodes (FP64 sum)       */
+    double momentum[3];       /* sum of j = sum_i c_i f_i over the fluid nodes              */
+    double body_momentum[3];  /* sum of M V over the replica's free bodies                  */
+    int64_t step;             /* number of completed steps                                  */
+    int32_t finite;           /* 1 if every node's rho and j are finite                     */
+} lb_totals;
+
+typedef struct {
+    double pos[3];            /* centre, lab frame, unwrapped                               */
+    double quat[4];           /* (w,x,y,z)                                                  */
+    double vel[3];            /* lab frame                                                  */
+    double omega_body[3];     /* body frame                                                 */
+    double force[3];          /* sum of bead forces of the last step, lab frame            */
+    double torque[3];         /* sum of bead torques of the last step, body frame          */
+} rb_state;
+
+/* Observables of one replica after the last completed step (synchronises the stream).
+ * out: totals (may be NULL).  bodies: host array of at least (bodies in the replica)
+ * records, in the order they were added (may be NULL).  dev_rho_u: device array of
+ * 4*nx*ny*nz values of the context precision, node-major (rho, ux, uy, uz) with
+ * u = (j + g_ext/2)/rho; boundary nodes get zeros (may be NULL).
+ * Returns LB_ERR_UNSTABLE (after filling the outputs) if a population is non-finite or a
+ * spread force left the fixed-point range.                                                 */
+int lb_observables(lb_ctx* ctx, int32_t replica, lb_totals* out, rb_state* bodies,
+                   void* dev_rho_u);
+
+/* Number of bodies in a replica, and the per-bead forces (lab frame, FP64, n_beads*3, in
+ * the order the beads were given) of the last step of one body, copied to host memory.   */
+int lb_body_count(const lb_ctx* ctx, int32_t replica);
+int rb_bead_forces(lb_ctx* ctx, int32_t replica, int32_t body_id, double* host_out,
+                   int32_t n_beads);
+
+/* The pre-collision populations f_i (not shifted) of one replica as FP64, [i][z][y][x]
+ * (19*nx*ny*nz values, zeros on boundary nodes), into a device array.                    */
+int lb_export_populations(lb_ctx* ctx, int32_t replica, double* dev_out);
+
+/* Checkpointing: the complete dynamic state (populations, bodies, step) in bytes that a
+ * later lb_load_state of a context with the same parameters, boxes, masks and bodies
+ * restores bit for bit.  dev_buf may be NULL to query the size: *bytes receives it.     */
+int lb_save_state(lb_ctx* ctx, void* dev_buf, size_t* bytes);
+int lb_load_state(lb_ctx* ctx, const void* dev_buf, size_t bytes);
+
+/* Execution options.  graph_steps: lb_rb_step replays a HIP graph of this many steps
+ * (even, >= 2) and runs the remainder eagerly; 0 = always eager (default 100).
+ * timing: when nonzero, every node-update and coupling launch is bracketed by HIP events
+ * on the context stream (eager launches only) and lb_kernel_times reports the summed
+ * durations (ms) and launch counts since timing was enabled.                              */
+int lb_set_graph_steps(lb_ctx* ctx, int32_t graph_steps);
+int lb_set_timing(lb_ctx* ctx, int32_t enable);
+int lb_kernel_times(lb_ctx* ctx, double* node_ms, int64_t* node_launches, double* couple_ms,
+                    int64_t* couple_launches);
+
+/* Node counts of one replica: all nodes and fluid nodes.                                  */
+int lb_node_counts(const lb_ctx* ctx, int32_t replica, int64_t* n_nodes, int64_t* n_fluid);
+
+void lb_destroy(lb_ctx* ctx);
+const char* lb_last_error(const lb_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,850 @@
+// lbrb_api.cpp -- host side of the C-ABI declared in include/lbrb.h.
+//
+// Owns the layout of the caller's workspace, the compact fluid-row tables built from the
+// boundary masks, the tile lists of the launches, the body/bead tables, the HIP-graph replay
+// of many steps and the per-kernel event timing.  Every step runs on the caller's stream;
+// graphs are captured on a private stream (default priority) and replayed on the caller's.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbrb.h"
+#include "lbrb_layout.h"
+
+using namespace lbrb;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr uint64_t kStateMagic = 0x4C42524253544154ull;  // "LBRBSTAT"
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int64_t pad_nodes(int64_t n) { return (n + kNodeBlock - 1) / kNodeBlock * kNodeBlock; }
+
+struct Plan {
+    int64_t N = 0;            // padded total node count (stride between populations)
+    int64_t rows_cap = 0;     // sum of ny*nz
+    int64_t tiles_cap = 0;    // sum of ceil(nodes / 256)
+    int64_t bead_cap = 0, body_cap = 0;
+    int gforce_words = 3;     // fixed-point words per node: 3 axes x (1 in FP32, 2 in FP64)
+    size_t off_hdr, off_reps, off_rows, off_rowmap, off_tiles_d, off_tiles_m, off_fa, off_fb,
+        off_gforce, off_flags, off_bodies, off_bead_off, off_bead_body, off_bead_force,
+        off_bead_torque, off_partials, total;
+};
+
+bool valid_params(const lb_params* p)
+{
+    if (!p) return false;
+    if (p->precision != LB_PRECISION_F64 && p->precision != LB_PRECISION_F32) return false;
+    if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return false;
+    const double taus[4] = {p->tau_shear, p->tau_bulk, p->tau_odd, p->tau_even};
+    for (double t : taus)
+        if (!(t > 0.5) || !std::isfinite(t)) return false;
+    if (!(p->kT >= 0) || !std::isfinite(p->kT)) return false;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->u0[a]) || !std::isfinite(p->g_ext[a])) return false;
+    if (p->max_bodies < 0 || p->max_beads < 0) return false;
+    return true;
+}
+
+bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
+{
+    if (!valid_params(p) || !reps || n < 1) return false;
+    pl = Plan();
+    for (int r = 0; r < n; ++r) {
+        const lb_replica& R = reps[r];
+        if (R.nx < 1 || R.ny < 1 || R.nz < 1 || R.nx > 32767 || R.ny > 65535 || R.nz > 32767)
+            return false;
+        const int64_t nodes = (int64_t)R.nx * R.ny * R.nz;
+        if (nodes >= (int64_t(1) << 31)) return false;
+        pl.N += pad_nodes(nodes);
+        pl.rows_cap += (int64_t)R.ny * R.nz;
+        pl.tiles_cap += pad_nodes(nodes) / kNodeBlock;
+    }
+    const size_t real = p->precision == LB_PRECISION_F32 ? sizeof(float) : sizeof(double);
+    pl.body_cap = p->max_bodies;
+    pl.bead_cap = p->max_beads;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes, kAlign); return at; };
+    pl.off_hdr = take(sizeof(DeviceHeader));
+    pl.off_reps = take(sizeof(ReplicaDesc) * n);
+    pl.off_rows = take(sizeof(RowDesc) * pl.rows_cap);
+    pl.off_rowmap = take(sizeof(int32_t) * pl.rows_cap);
+    pl.off_tiles_d = take(sizeof(NodeTile) * pl.tiles_cap);
+    pl.off_tiles_m = take(sizeof(NodeTile) * pl.tiles_cap);
+    pl.off_fa = take(real * Q * pl.N);
+    pl.off_fb = take(real * Q * pl.N);
+    pl.gforce_words = p->precision == LB_PRECISION_F32 ? 3 : 6;
+    pl.off_gforce = take(sizeof(long long) * pl.gforce_words * pl.N);
+    pl.off_flags = take(sizeof(uint32_t) * (pl.N / 32 + 1));
+    pl.off_bodies = take(sizeof(Body) * std::max<int64_t>(pl.body_cap, 1));
+    pl.off_bead_off = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
+    pl.off_bead_body = take(sizeof(int32_t) * std::max<int64_t>(pl.bead_cap, 1));
+    pl.off_bead_force = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
+    pl.off_bead_torque = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
+    pl.off_partials = take(sizeof(double) * 5 * pl.tiles_cap);
+    pl.total = o;
+    return true;
+}
+
+struct ReplicaHost {
+    int group = 0;            // 0 = dense tiles, 1 = masked tiles
+    int32_t tile0 = 0, n_tiles = 0;
+    std::vector<int32_t> bodies;
+};
+
+struct EventPair { hipEvent_t a, b; };
+
+}  // namespace
+
+struct lb_ctx {
+    lb_params p{};
+    Plan plan;
+    int32_t n_rep = 0;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    // device views
+    DeviceHeader* hdr = nullptr;
+    ReplicaDesc* d_reps = nullptr;
+    RowDesc* d_rows = nullptr;
+    int32_t* d_rowmap = nullptr;
+    NodeTile* d_tiles[2] = {nullptr, nullptr};
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    long long* gforce = nullptr;
+    uint32_t* flags = nullptr;
+    Body* d_bodies = nullptr;
+    double* d_bead_off = nullptr;
+    int32_t* d_bead_body = nullptr;
+    double* d_bead_force = nullptr;
+    double* d_bead_torque = nullptr;
+    double* d_partials = nullptr;
+    // host mirrors
+    std::vector<ReplicaDesc> reps;
+    std::vector<RowDesc> rows;
+    std::vector<int32_t> rowmap;
+    std::vector<NodeTile> tiles[2];
+    std::vector<ReplicaHost> rh;
+    std::vector<Body> bodies0;          // bodies as added (device copy is authoritative)
+    int32_t n_bodies = 0, n_beads = 0;
+    int64_t step = 0;
+    std::string err;
+    // graphs
+    int32_t graph_steps = 100;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipStream_t cap_stream = nullptr, side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // timing
+    bool timing = false;
+    std::vector<EventPair> ev_node, ev_couple, ev_pool;
+};
+
+namespace {
+
+int fail(lb_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((ctx), LB_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_f32(const lb_ctx* c) { return c->p.precision == LB_PRECISION_F32; }
+
+template <typename Real>
+CollideParams<Real> collide_params(const lb_params& p)
+{
+    CollideParams<Real> cp{};
+    const double gb = 1.0 - 1.0 / p.tau_bulk, gs = 1.0 - 1.0 / p.tau_shear;
+    const double go = 1.0 - 1.0 / p.tau_odd, ge = 1.0 - 1.0 / p.tau_even;
+    cp.rho0 = (Real)p.rho0;
+    cp.g_bulk = (Real)gb; cp.g_shear = (Real)gs; cp.g_odd = (Real)go; cp.g_even = (Real)ge;
+    cp.h_bulk = (Real)(0.5 * (1.0 + gb));
+    cp.h_shear = (Real)(0.5 * (1.0 + gs));
+    // b_k of the orthogonal basis
+    const double b[Q] = {1.0, 1.0 / 3, 1.0 / 3, 1.0 / 3, 2.0 / 3, 4.0 / 3, 4.0 / 9, 1.0 / 9,
+                         1.0 / 9, 1.0 / 9, 2.0 / 3, 2.0 / 3, 2.0 / 3, 2.0 / 9, 2.0 / 9, 2.0 / 9,
+                         2.0, 4.0 / 3, 4.0 / 9};
+    const double mu = 3.0 * p.kT;
+    for (int k = 0; k < Q; ++k) {
+        double g = 0.0;
+        if (k == 4) g = gb;
+        else if (k >= 5 && k <= 9) g = gs;
+        else if (k >= 10 && k <= 15) g = go;
+        else if (k >= 16) g = ge;
+        cp.a_noise[k] = k < 4 ? (Real)0 : (Real)(std::sqrt(mu * p.rho0 * b[k] * (1.0 - g * g)) * std::sqrt(12.0));
+    }
+    return cp;
+}
+
+template <typename Real>
+StepArgs<Real> step_args(const lb_ctx* c, int group, int src_buf)
+{
+    StepArgs<Real> a{};
+    a.src = (const Real*)c->f[src_buf];
+    a.dst = (Real*)c->f[src_buf ^ 1];
+    a.N = c->plan.N;
+    a.reps = c->d_reps;
+    a.rows = c->d_rows;
+    a.rowmap = c->d_rowmap;
+    a.tiles = c->d_tiles[group];
+    a.n_tiles = (int32_t)c->tiles[group].size();
+    a.thermal = c->p.kT > 0.0 ? 1 : 0;
+    a.gforce = c->gforce;
+    a.flags = c->flags;
+    a.cp = collide_params<Real>(c->p);
+    for (int ax = 0; ax < 3; ++ax) a.gext[ax] = (Real)c->p.g_ext[ax];
+    a.step_ptr = nullptr;
+    a.step_arg = c->step;
+    return a;
+}
+
+CoupleArgs couple_args(const lb_ctx* c)
+{
+    CoupleArgs ca{};
+    ca.bodies = c->d_bodies;
+    ca.bead_off = c->d_bead_off;
+    ca.bead_body = c->d_bead_body;
+    ca.bead_force = c->d_bead_force;
+    ca.bead_torque = c->d_bead_torque;
+    ca.n_beads = c->n_beads;
+    ca.kT = c->p.kT;
+    ca.hdr = c->hdr;
+    return ca;
+}
+
+bool any_masked(const lb_ctx* c) { return !c->tiles[1].empty(); }
+
+EventPair get_pair(lb_ctx* c)
+{
+    if (!c->ev_pool.empty()) {
+        EventPair e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    EventPair e{};
+    if (hipEventCreate(&e.a) != hipSuccess) e.a = nullptr;
+    if (hipEventCreate(&e.b) != hipSuccess) e.b = nullptr;
+    return e;
+}
+
+// Enqueue one step.  In capture mode (step_ptr set) the kernels read the step counter from
+// device memory; body_finish runs on a side branch in parallel with the node update.
+// Returns the first HIP error of the enqueued calls.
+template <typename Real>
+hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* step_ptr,
+                        int64_t step_arg, bool capture)
+{
+    hipError_t err = hipSuccess;
+    auto note = [&](hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; };
+    StepArgs<Real> a0 = step_args<Real>(c, 0, src_buf);
+    StepArgs<Real> a1 = step_args<Real>(c, 1, src_buf);
+    a0.step_ptr = a1.step_ptr = step_ptr;
+    a0.step_arg = a1.step_arg = step_arg;
+    const bool timed = c->timing && !capture;
+    if (c->n_beads > 0) {
+        EventPair e{};
+        if (timed) { e = get_pair(c); note(hipEventRecord(e.a, s)); }
+        launch_couple<Real>(any_masked(c) ? a1 : a0, couple_args(c), any_masked(c), s);
+        note(hipGetLastError());
+        if (timed) { note(hipEventRecord(e.b, s)); c->ev_couple.push_back(e); }
+        if (capture) {
+            note(hipEventRecord(c->ev_fork, s));
+            note(hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
+            launch_body_finish(c->d_bodies, c->d_bead_force, c->d_bead_torque, c->n_bodies,
+                               c->side_stream);
+            note(hipGetLastError());
+            note(hipEventRecord(c->ev_join, c->side_stream));
+        } else {
+            launch_body_finish(c->d_bodies, c->d_bead_force, c->d_bead_torque, c->n_bodies, s);
+            note(hipGetLastError());
+        }
+    }
+    for (int g = 0; g < 2; ++g) {
+        StepArgs<Real>& a = g == 0 ? a0 : a1;
+        if (a.n_tiles == 0) continue;
+        EventPair e{};
+        if (timed) { e = get_pair(c); note(hipEventRecord(e.a, s)); }
+        launch_node_update<Real>(a, g == 1, s);
+        note(hipGetLastError());
+        if (timed) { note(hipEventRecord(e.b, s)); c->ev_node.push_back(e); }
+    }
+    if (capture && c->n_beads > 0) note(hipStreamWaitEvent(s, c->ev_join, 0));
+    return err;
+}
+
+void destroy_graphs(lb_ctx* c)
+{
+    for (int k = 0; k < 2; ++k)
+        if (c->gexec[k]) { (void)hipGraphExecDestroy(c->gexec[k]); c->gexec[k] = nullptr; }
+}
+
+int build_graph(lb_ctx* c, int parity)
+{
+    if (!c->cap_stream) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int buf = parity;
+    hipError_t cap_err = hipSuccess;
+    for (int k = 0; k < c->graph_steps && cap_err == hipSuccess; ++k) {
+        cap_err = is_f32(c) ? enqueue_step<float>(c, c->cap_stream, buf, &c->hdr->step, k, true)
+                            : enqueue_step<double>(c, c->cap_stream, buf, &c->hdr->step, k, true);
+        buf ^= 1;
+    }
+    hipError_t end_err = hipStreamEndCapture(c->cap_stream, &graph);
+    if (cap_err != hipSuccess || end_err != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        const hipError_t e = cap_err != hipSuccess ? cap_err : end_err;
+        return fail(c, LB_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    hipError_t e = hipGraphInstantiate(&c->gexec[parity], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        c->gexec[parity] = nullptr;
+        return fail(c, LB_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    return LB_OK;
+}
+
+// Build the fluid-row tables and tiles of every replica from the host masks.
+void rebuild_tiles(lb_ctx* c)
+{
+    c->tiles[0].clear();
+    c->tiles[1].clear();
+    for (int r = 0; r < c->n_rep; ++r) {
+        const ReplicaDesc& R = c->reps[r];
+        ReplicaHost& H = c->rh[r];
+        H.group = R.masked ? 1 : 0;
+        std::vector<NodeTile>& T = c->tiles[H.group];
+        H.tile0 = (int32_t)T.size();
+        const int64_t n = R.n_fluid;
+        int row = R.row_base;  // first row of the replica (masked)
+        int last_row = row;
+        if (R.masked) {
+            // rows of this replica are rows[row_base .. row_base + n_rows)
+            int64_t nr = 0;
+            for (int64_t k = 0; k < (int64_t)R.ny * R.nz; ++k)
+                if (c->rowmap[R.row_base + k] >= 0) ++nr;
+            last_row = R.row_base + (int)nr - 1;
+        }
+        for (int64_t b = 0; b < n; b += kNodeBlock) {
+            NodeTile t{};
+            t.replica = r;
+            t.begin = b;
+            t.count = (int32_t)std::min<int64_t>(kNodeBlock, n - b);
+            if (R.masked) {
+                while (row < last_row && c->rows[row + 1].start <= b) ++row;
+                int hi = row;
+                while (hi < last_row && c->rows[hi + 1].start <= b + t.count - 1) ++hi;
+                t.row_lo = row;
+                t.row_hi = hi;
+            }
+            T.push_back(t);
+        }
+        H.n_tiles = (int32_t)T.size() - H.tile0;
+    }
+}
+
+int upload_tables(lb_ctx* c)
+{
+    HIP_TRY(c, hipMemcpyAsync(c->d_reps, c->reps.data(), sizeof(ReplicaDesc) * c->n_rep,
+                              hipMemcpyHostToDevice, c->stream));
+    if (!c->rows.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_rows, c->rows.data(), sizeof(RowDesc) * c->rows.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+    if (!c->rowmap.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_rowmap, c->rowmap.data(), sizeof(int32_t) * c->rowmap.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+    for (int g = 0; g < 2; ++g)
+        if (!c->tiles[g].empty())
+            HIP_TRY(c, hipMemcpyAsync(c->d_tiles[g], c->tiles[g].data(),
+                                      sizeof(NodeTile) * c->tiles[g].size(), hipMemcpyHostToDevice,
+                                      c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+// equilibrium of (rho0, u0) in the current buffer for the tiles of one replica (or all)
+int init_fluid(lb_ctx* c, int replica)
+{
+    for (int g = 0; g < 2; ++g) {
+        int32_t t0 = 0, nt = (int32_t)c->tiles[g].size();
+        if (replica >= 0) {
+            if (c->rh[replica].group != g) continue;
+            t0 = c->rh[replica].tile0;
+            nt = c->rh[replica].n_tiles;
+        }
+        if (is_f32(c))
+            launch_init_equilibrium<float>((float*)c->f[c->cur], c->plan.N, c->d_reps,
+                                           c->d_tiles[g] + t0, nt, (float)c->p.rho0, c->p.u0,
+                                           c->stream);
+        else
+            launch_init_equilibrium<double>((double*)c->f[c->cur], c->plan.N, c->d_reps,
+                                            c->d_tiles[g] + t0, nt, c->p.rho0, c->p.u0,
+                                            c->stream);
+    }
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+bool check_replica(lb_ctx* c, int32_t r)
+{
+    if (r < 0 || r >= c->n_rep) { c->err = "replica index out of range"; return false; }
+    return true;
+}
+
+}  // namespace
+
+// ============================================================================ C-ABI
+
+extern "C" {
+
+size_t lb_workspace_bytes(const lb_params* params, const lb_replica* replicas,
+                          int32_t n_replicas)
+{
+    Plan pl;
+    if (!make_plan(params, replicas, n_replicas, pl)) return 0;
+    return pl.total;
+}
+
+int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_replicas,
+            void* dev_workspace, size_t ws_bytes, void* hip_stream, lb_ctx** out)
+{
+    if (!out) return LB_ERR_ARG;
+    *out = nullptr;
+    Plan pl;
+    if (!make_plan(params, replicas, n_replicas, pl)) return LB_ERR_ARG;
+    if (!dev_workspace || ((uintptr_t)dev_workspace % kAlign) != 0 || ws_bytes < pl.total)
+        return LB_ERR_ARG;
+    lb_ctx* c = new (std::nothrow) lb_ctx();
+    if (!c) return LB_ERR_ARG;
+    c->p = *params;
+    c->plan = pl;
+    c->n_rep = n_replicas;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char*)dev_workspace;
+    c->hdr = (DeviceHeader*)(c->ws + pl.off_hdr);
+    c->d_reps = (ReplicaDesc*)(c->ws + pl.off_reps);
+    c->d_rows = (RowDesc*)(c->ws + pl.off_rows);
+    c->d_rowmap = (int32_t*)(c->ws + pl.off_rowmap);
+    c->d_tiles[0] = (NodeTile*)(c->ws + pl.off_tiles_d);
+    c->d_tiles[1] = (NodeTile*)(c->ws + pl.off_tiles_m);
+    c->f[0] = c->ws + pl.off_fa;
+    c->f[1] = c->ws + pl.off_fb;
+    c->gforce = (long long*)(c->ws + pl.off_gforce);
+    c->flags = (uint32_t*)(c->ws + pl.off_flags);
+    c->d_bodies = (Body*)(c->ws + pl.off_bodies);
+    c->d_bead_off = (double*)(c->ws + pl.off_bead_off);
+    c->d_bead_body = (int32_t*)(c->ws + pl.off_bead_body);
+    c->d_bead_force = (double*)(c->ws + pl.off_bead_force);
+    c->d_bead_torque = (double*)(c->ws + pl.off_bead_torque);
+    c->d_partials = (double*)(c->ws + pl.off_partials);
+
+    c->reps.resize(n_replicas);
+    c->rh.resize(n_replicas);
+    c->rows.assign(pl.rows_cap, RowDesc{0, 0, 0, 0});
+    c->rowmap.assign(pl.rows_cap, -1);
+    int64_t base = 0, row_base = 0;
+    for (int r = 0; r < n_replicas; ++r) {
+        const lb_replica& in = replicas[r];
+        ReplicaDesc& R = c->reps[r];
+        R = ReplicaDesc{};
+        R.nx = in.nx; R.ny = in.ny; R.nz = in.nz;
+        R.masked = 0;
+        R.base = base;
+        R.n_nodes = (int64_t)in.nx * in.ny * in.nz;
+        R.n_fluid = R.n_nodes;
+        R.row_base = (int32_t)row_base;
+        R.key0 = (uint32_t)(in.seed & 0xFFFFFFFFu);
+        R.key1 = (uint32_t)(in.seed >> 32);
+        R.inv_nx = 1.0 / in.nx;
+        R.inv_ny = 1.0 / in.ny;
+        base += pad_nodes(R.n_nodes);
+        row_base += (int64_t)in.ny * in.nz;
+    }
+    rebuild_tiles(c);
+    // zero the header, the spread-force accumulators and the flags once
+    hipError_t e = hipMemsetAsync(c->ws + pl.off_hdr, 0, sizeof(DeviceHeader), c->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->gforce, 0, sizeof(long long) * pl.gforce_words * pl.N, c->stream);
+    // padding nodes are never written by the kernels: clear both buffers once so that a saved
+    // state is a deterministic function of the run
+    const size_t real = is_f32(c) ? sizeof(float) : sizeof(double);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = hipMemsetAsync(c->f[k], 0, real * Q * pl.N, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->flags, 0, sizeof(uint32_t) * (pl.N / 32 + 1), c->stream);
+    if (e != hipSuccess) { delete c; return LB_ERR_HIP; }
+    int rc = upload_tables(c);
+    if (rc == LB_OK) rc = init_fluid(c, -1);
+    if (rc != LB_OK) { delete c; return rc; }
+    *out = c;
+    return LB_OK;
+}
+
+int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!check_replica(c, replica) || !mask) return fail(c, LB_ERR_ARG, "bad replica or mask");
+    if (c->step != 0) return fail(c, LB_ERR_STATE, "masks can only be set before the first step");
+    ReplicaDesc& R = c->reps[replica];
+    const int nx = R.nx, ny = R.ny, nz = R.nz;
+    bool any_solid = false;
+    std::vector<RowDesc> rows;
+    std::vector<int32_t> rmap((size_t)ny * nz, -1);
+    int64_t start = 0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y) {
+            const uint8_t* m = mask + (size_t)nx * (y + (size_t)ny * z);
+            int xlo = -1, xhi = -1, runs = 0;
+            for (int x = 0; x < nx; ++x) {
+                if (m[x]) { any_solid = true; continue; }
+                if (x == 0 || m[x - 1]) { ++runs; if (xlo < 0) xlo = x; }
+                xhi = x;
+            }
+            if (runs == 0) continue;
+            if (runs > 1) return fail(c, LB_ERR_ARG, "a mask row holds more than one fluid run");
+            RowDesc d{};
+            d.start = (int32_t)start;
+            d.xlo = xlo;
+            d.len = xhi - xlo + 1;
+            d.yz = y | (z << 16);
+            rmap[(size_t)y + (size_t)ny * z] = R.row_base + (int32_t)rows.size();
+            rows.push_back(d);
+            start += d.len;
+        }
+    // rows of this replica go to rows[row_base ...]; clear the old ones first
+    for (int64_t k = 0; k < (int64_t)ny * nz; ++k) {
+        c->rowmap[R.row_base + k] = -1;
+        c->rows[R.row_base + k] = RowDesc{0, 0, 0, 0};
+    }
+    if (any_solid) {
+        for (size_t k = 0; k < rows.size(); ++k) c->rows[R.row_base + k] = rows[k];
+        for (int64_t k = 0; k < (int64_t)ny * nz; ++k) c->rowmap[R.row_base + k] = rmap[k];
+        R.masked = 1;
+        R.n_fluid = start;
+    } else {
+        R.masked = 0;
+        R.n_fluid = R.n_nodes;
+    }
+    destroy_graphs(c);
+    rebuild_tiles(c);
+    int rc = upload_tables(c);
+    if (rc != LB_OK) return rc;
+    return init_fluid(c, replica);
+}
+
+int rb_add_raspberry(lb_ctx* c, int32_t replica, const double* offs, int32_t n_beads,
+                     double mass, const double inertia[3], const double pos[3],
+                     const double quat[4], const double vel[3], const double omega[3],
+                     double gamma, int32_t fixed, int32_t* body_id)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!check_replica(c, replica)) return LB_ERR_ARG;
+    if (!offs || n_beads < 1 || !pos || !quat || !inertia || !vel || !omega)
+        return fail(c, LB_ERR_ARG, "missing body arrays or no beads");
+    if (!(gamma >= 0) || !std::isfinite(gamma)) return fail(c, LB_ERR_ARG, "gamma must be >= 0");
+    if (!fixed && (!(mass > 0) || !(inertia[0] > 0) || !(inertia[1] > 0) || !(inertia[2] > 0)))
+        return fail(c, LB_ERR_ARG, "a free body needs positive mass and inertia");
+    const double qn = std::sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] +
+                                quat[3] * quat[3]);
+    if (!(qn > 0) || !std::isfinite(qn)) return fail(c, LB_ERR_ARG, "zero quaternion");
+    for (int k = 0; k < 3 * n_beads; ++k)
+        if (!std::isfinite(offs[k])) return fail(c, LB_ERR_ARG, "non-finite bead offset");
+    if (c->n_bodies + 1 > c->plan.body_cap || (int64_t)c->n_beads + n_beads > c->plan.bead_cap)
+        return fail(c, LB_ERR_CAPACITY, "body or bead capacity exceeded");
+    Body B{};
+    for (int a = 0; a < 3; ++a) {
+        B.pos[a] = pos[a];
+        B.vel[a] = fixed ? 0.0 : vel[a];
+        B.omega[a] = fixed ? 0.0 : omega[a];
+        B.inertia[a] = inertia[a];
+    }
+    for (int a = 0; a < 4; ++a) B.quat[a] = quat[a] / qn;
+    B.mass = mass;
+    B.gamma = gamma;
+    B.fixed = fixed ? 1 : 0;
+    B.replica = replica;
+    B.first_bead = c->n_beads;
+    B.n_beads = n_beads;
+    int32_t in_rep = 0;
+    for (int32_t b : c->rh[replica].bodies) in_rep += c->bodies0[b].n_beads;
+    B.first_bead_in_replica = in_rep;
+    std::vector<int32_t> owner(n_beads, c->n_bodies);
+    HIP_TRY(c, hipMemcpyAsync(c->d_bodies + c->n_bodies, &B, sizeof(Body), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_bead_off + 3 * (int64_t)c->n_beads, offs,
+                              sizeof(double) * 3 * n_beads, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_bead_body + c->n_beads, owner.data(),
+                              sizeof(int32_t) * n_beads, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (body_id) *body_id = (int32_t)c->rh[replica].bodies.size();
+    c->rh[replica].bodies.push_back(c->n_bodies);
+    c->bodies0.push_back(B);
+    c->n_bodies += 1;
+    c->n_beads += n_beads;
+    destroy_graphs(c);
+    return LB_OK;
+}
+
+int lb_rb_step(lb_ctx* c, int32_t n_steps)
+{
+    if (!c) return LB_ERR_ARG;
+    if (n_steps < 0) return fail(c, LB_ERR_ARG, "negative step count");
+    int32_t left = n_steps;
+    const bool use_graph = c->graph_steps > 0 && !c->timing;
+    while (use_graph && left >= c->graph_steps) {
+        if (!c->gexec[c->cur]) {
+            int rc = build_graph(c, c->cur);
+            if (rc != LB_OK) return rc;
+        }
+        launch_set_step(&c->hdr->step, c->step, c->stream);
+        HIP_TRY(c, hipGraphLaunch(c->gexec[c->cur], c->stream));
+        c->step += c->graph_steps;
+        // an even number of steps leaves the current buffer in place
+        left -= c->graph_steps;
+    }
+    for (; left > 0; --left) {
+        HIP_TRY(c, is_f32(c) ? enqueue_step<float>(c, c->stream, c->cur, nullptr, c->step, false)
+                             : enqueue_step<double>(c, c->stream, c->cur, nullptr, c->step, false));
+        c->cur ^= 1;
+        c->step += 1;
+    }
+    HIP_TRY(c, hipGetLastError());
+    return LB_OK;
+}
+
+int lb_observables(lb_ctx* c, int32_t replica, lb_totals* out, rb_state* bodies,
+                   void* dev_rho_u)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!check_replica(c, replica)) return LB_ERR_ARG;
+    const ReplicaDesc& R = c->reps[replica];
+    const ReplicaHost& H = c->rh[replica];
+    const size_t real = is_f32(c) ? sizeof(float) : sizeof(double);
+    if (dev_rho_u)
+        HIP_TRY(c, hipMemsetAsync(dev_rho_u, 0, real * 4 * R.n_nodes, c->stream));
+    if (is_f32(c)) {
+        StepArgs<float> a = step_args<float>(c, H.group, c->cur);
+        launch_observe<float>(a, H.group == 1, H.tile0, H.n_tiles, (float*)dev_rho_u,
+                              c->d_partials, nullptr, c->stream);
+    } else {
+        StepArgs<double> a = step_args<double>(c, H.group, c->cur);
+        launch_observe<double>(a, H.group == 1, H.tile0, H.n_tiles, (double*)dev_rho_u,
+                               c->d_partials, nullptr, c->stream);
+    }
+    HIP_TRY(c, hipGetLastError());
+    std::vector<double> part(5 * (size_t)H.n_tiles);
+    if (H.n_tiles > 0)
+        HIP_TRY(c, hipMemcpyAsync(part.data(), c->d_partials, sizeof(double) * part.size(),
+                                  hipMemcpyDeviceToHost, c->stream));
+    std::vector<Body> bs(c->n_bodies);
+    if (c->n_bodies > 0)
+        HIP_TRY(c, hipMemcpyAsync(bs.data(), c->d_bodies, sizeof(Body) * c->n_bodies,
+                                  hipMemcpyDeviceToHost, c->stream));
+    DeviceHeader hdr{};
+    HIP_TRY(c, hipMemcpyAsync(&hdr, c->hdr, sizeof(DeviceHeader), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int32_t t = 0; t < H.n_tiles; ++t)
+        for (int k = 0; k < 5; ++k) s[k] += part[5 * (size_t)t + k];
+    lb_totals T{};
+    T.mass = (double)R.n_fluid * c->p.rho0 + s[0];
+    for (int a = 0; a < 3; ++a) T.momentum[a] = s[1 + a];
+    for (int32_t b : H.bodies) {
+        if (bs[b].fixed) continue;
+        for (int a = 0; a < 3; ++a) T.body_momentum[a] += bs[b].mass * bs[b].vel[a];
+    }
+    T.step = c->step;
+    T.finite = (s[4] == 0.0 && std::isfinite(T.mass)) ? 1 : 0;
+    if (out) *out = T;
+    if (bodies) {
+        for (size_t k = 0; k < H.bodies.size(); ++k) {
+            const Body& B = bs[H.bodies[k]];
+            rb_state& o = bodies[k];
+            for (int a = 0; a < 3; ++a) {
+                o.pos[a] = B.pos[a]; o.vel[a] = B.vel[a]; o.omega_body[a] = B.omega[a];
+                o.force[a] = B.force[a]; o.torque[a] = B.torque[a];
+            }
+            for (int a = 0; a < 4; ++a) o.quat[a] = B.quat[a];
+        }
+    }
+    if (!T.finite) return fail(c, LB_ERR_UNSTABLE, "non-finite populations");
+    if (hdr.err_flags & 1u) return fail(c, LB_ERR_UNSTABLE, "spread force out of range");
+    return LB_OK;
+}
+
+int lb_body_count(const lb_ctx* c, int32_t replica)
+{
+    if (!c || replica < 0 || replica >= c->n_rep) return LB_ERR_ARG;
+    return (int)c->rh[replica].bodies.size();
+}
+
+int rb_bead_forces(lb_ctx* c, int32_t replica, int32_t body_id, double* host_out, int32_t n)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!check_replica(c, replica)) return LB_ERR_ARG;
+    const ReplicaHost& H = c->rh[replica];
+    if (body_id < 0 || body_id >= (int32_t)H.bodies.size() || !host_out)
+        return fail(c, LB_ERR_ARG, "bad body id");
+    const Body& B = c->bodies0[H.bodies[body_id]];
+    if (n < B.n_beads) return fail(c, LB_ERR_ARG, "output too small");
+    HIP_TRY(c, hipMemcpyAsync(host_out, c->d_bead_force + 3 * (int64_t)B.first_bead,
+                              sizeof(double) * 3 * B.n_beads, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+int lb_export_populations(lb_ctx* c, int32_t replica, double* dev_out)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!check_replica(c, replica) || !dev_out) return fail(c, LB_ERR_ARG, "bad arguments");
+    const ReplicaDesc& R = c->reps[replica];
+    const ReplicaHost& H = c->rh[replica];
+    HIP_TRY(c, hipMemsetAsync(dev_out, 0, sizeof(double) * Q * R.n_nodes, c->stream));
+    if (is_f32(c)) {
+        StepArgs<float> a = step_args<float>(c, H.group, c->cur);
+        launch_observe<float>(a, H.group == 1, H.tile0, H.n_tiles, nullptr, nullptr, dev_out,
+                              c->stream);
+    } else {
+        StepArgs<double> a = step_args<double>(c, H.group, c->cur);
+        launch_observe<double>(a, H.group == 1, H.tile0, H.n_tiles, nullptr, nullptr, dev_out,
+                               c->stream);
+    }
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+int lb_save_state(lb_ctx* c, void* dev_buf, size_t* bytes)
+{
+    if (!c || !bytes) return LB_ERR_ARG;
+    const size_t real = is_f32(c) ? sizeof(float) : sizeof(double);
+    const size_t pops = real * Q * c->plan.N;
+    const size_t head = 256, bod = align_up(sizeof(Body) * c->n_bodies, 256);
+    const size_t need = head + bod + pops;
+    if (!dev_buf) { *bytes = need; return LB_OK; }
+    if (*bytes < need) return fail(c, LB_ERR_ARG, "state buffer too small");
+    uint64_t h[6] = {kStateMagic, (uint64_t)c->step, (uint64_t)c->n_bodies,
+                     (uint64_t)c->p.precision, (uint64_t)c->plan.N, (uint64_t)c->n_beads};
+    char* d = (char*)dev_buf;
+    HIP_TRY(c, hipMemcpyAsync(d, h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+    if (c->n_bodies > 0)
+        HIP_TRY(c, hipMemcpyAsync(d + head, c->d_bodies, sizeof(Body) * c->n_bodies,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d + head + bod, c->f[c->cur], pops, hipMemcpyDeviceToDevice,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *bytes = need;
+    return LB_OK;
+}
+
+int lb_load_state(lb_ctx* c, const void* dev_buf, size_t bytes)
+{
+    if (!c || !dev_buf) return LB_ERR_ARG;
+    const size_t real = is_f32(c) ? sizeof(float) : sizeof(double);
+    const size_t pops = real * Q * c->plan.N;
+    const size_t head = 256, bod = align_up(sizeof(Body) * c->n_bodies, 256);
+    if (bytes < head + bod + pops) return fail(c, LB_ERR_ARG, "state buffer too small");
+    uint64_t h[6] = {0, 0, 0, 0, 0, 0};
+    const char* d = (const char*)dev_buf;
+    HIP_TRY(c, hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (h[0] != kStateMagic || h[2] != (uint64_t)c->n_bodies || h[3] != (uint64_t)c->p.precision ||
+        h[4] != (uint64_t)c->plan.N || h[5] != (uint64_t)c->n_beads)
+        return fail(c, LB_ERR_STATE, "state does not match this context");
+    if (c->n_bodies > 0)
+        HIP_TRY(c, hipMemcpyAsync(c->d_bodies, d + head, sizeof(Body) * c->n_bodies,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->f[c->cur], d + head + bod, pops, hipMemcpyDeviceToDevice,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->step = (int64_t)h[1];
+    return LB_OK;
+}
+
+int lb_set_graph_steps(lb_ctx* c, int32_t k)
+{
+    if (!c) return LB_ERR_ARG;
+    if (k < 0 || (k > 0 && (k < 2 || (k & 1)))) return fail(c, LB_ERR_ARG, "graph steps must be 0 or even >= 2");
+    destroy_graphs(c);
+    c->graph_steps = k;
+    return LB_OK;
+}
+
+int lb_set_timing(lb_ctx* c, int32_t enable)
+{
+    if (!c) return LB_ERR_ARG;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto& e : c->ev_node) c->ev_pool.push_back(e);
+    for (auto& e : c->ev_couple) c->ev_pool.push_back(e);
+    c->ev_node.clear();
+    c->ev_couple.clear();
+    c->timing = enable != 0;
+    return LB_OK;
+}
+
+int lb_kernel_times(lb_ctx* c, double* node_ms, int64_t* node_n, double* couple_ms,
+                    int64_t* couple_n)
+{
+    if (!c) return LB_ERR_ARG;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double tn = 0, tc = 0;
+    for (auto& e : c->ev_node) { float ms = 0; HIP_TRY(c, hipEventElapsedTime(&ms, e.a, e.b)); tn += ms; }
+    for (auto& e : c->ev_couple) { float ms = 0; HIP_TRY(c, hipEventElapsedTime(&ms, e.a, e.b)); tc += ms; }
+    if (node_ms) *node_ms = tn;
+    if (node_n) *node_n = (int64_t)c->ev_node.size();
+    if (couple_ms) *couple_ms = tc;
+    if (couple_n) *couple_n = (int64_t)c->ev_couple.size();
+    return LB_OK;
+}
+
+int lb_node_counts(const lb_ctx* c, int32_t replica, int64_t* n_nodes, int64_t* n_fluid)
+{
+    if (!c || replica < 0 || replica >= c->n_rep) return LB_ERR_ARG;
+    if (n_nodes) *n_nodes = c->reps[replica].n_nodes;
+    if (n_fluid) *n_fluid = c->reps[replica].n_fluid;
+    return LB_OK;
+}
+
+void lb_destroy(lb_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    destroy_graphs(c);
+    for (auto& e : c->ev_node) c->ev_pool.push_back(e);
+    for (auto& e : c->ev_couple) c->ev_pool.push_back(e);
+    for (auto& e : c->ev_pool) {
+        if (e.a) (void)hipEventDestroy(e.a);
+        if (e.b) (void)hipEventDestroy(e.b);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+    delete c;
+}
+
+const char* lb_last_error(const lb_ctx* c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+}  // extern "C"

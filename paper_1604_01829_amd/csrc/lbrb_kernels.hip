@@ -1,0 +1,527 @@
+// lbrb_kernels.hip -- gfx950 kernels of the raspberry / lattice-Boltzmann step.
+//
+//   node_update  : the fused lattice-Boltzmann step of every fluid node (Sec. 1.1 of the
+//                  paper): pull of the 19 populations along the links with halfway
+//                  bounce-back at boundary nodes, moments, multiple-relaxation-time
+//                  collision with the force density (external + spread bead forces) and
+//                  thermal noise, back-transform, store.  One thread per node, 256 nodes per
+//                  workgroup, SoA loads/stores coalesced along x.  Bandwidth bound:
+//                  19 loads + 19 stores per node.
+//   couple       : the bead/fluid friction of eq. (latticeboltzmannfriction): 8 threads per
+//                  bead, one per corner of the trilinear stencil; each corner thread pulls
+//                  its node's populations to get the fluid velocity, the 8 weighted
+//                  velocities are summed with a lane butterfly, the friction + noise force is
+//                  formed and each corner spreads its share of the opposite force with
+//                  64-bit fixed-point atomics (order-independent, hence deterministic).
+//   body_finish  : one workgroup per raspberry: sums the bead forces and torques (shuffle +
+//                  LDS tree, fixed order), turns the torque into the body frame and applies
+//                  the second half kick (Sec. 2.3).
+#include <hip/hip_runtime.h>
+
+#include "lbrb_layout.h"
+
+namespace lbrb {
+
+__device__ __forceinline__ int wrap1(int v, int n)
+{
+    return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+__device__ __forceinline__ int64_t current_step(const int64_t* p, int64_t arg)
+{
+    return (p ? *p : 0) + arg;
+}
+
+// exact floor(v / n) for 0 <= v < 2^52 via a double reciprocal and one correction
+__device__ __forceinline__ int64_t div_exact(int64_t v, int32_t n, double inv)
+{
+    int64_t q = (int64_t)((double)v * inv);
+    int64_t r = v - q * n;
+    if (r < 0) q -= 1;
+    else if (r >= n) q += 1;
+    return q;
+}
+
+// coordinates of a local node index
+template <bool MASKED>
+__device__ __forceinline__ void locate(const ReplicaDesc& R, const RowDesc* __restrict__ rows,
+                                       int row_lo, int row_hi, int64_t local, int& x, int& y,
+                                       int& z, RowDesc& self)
+{
+    if constexpr (MASKED) {
+        // largest row whose start <= local
+        int lo = row_lo, hi = row_hi;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rows[mid].start <= local) lo = mid; else hi = mid - 1;
+        }
+        self = rows[lo];
+        x = self.xlo + (int)(local - self.start);
+        y = self.yz & 0xFFFF;
+        z = self.yz >> 16;
+    } else {
+        const int64_t row = div_exact(local, R.nx, R.inv_nx);
+        x = (int)(local - row * R.nx);
+        const int64_t zz = div_exact(row, R.ny, R.inv_ny);
+        y = (int)(row - zz * R.ny);
+        z = (int)zz;
+        self.start = 0; self.xlo = 0; self.len = R.nx; self.yz = 0;
+    }
+}
+
+// Pre-collision populations of node (x,y,z) (shifted), pulled from the post-collision
+// buffer: population i comes from x - c_i, or, if that node is a boundary node, from the
+// opposite population of the node itself (halfway bounce-back).
+template <typename Real, bool MASKED>
+__device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
+                                     const ReplicaDesc& R, const RowDesc* __restrict__ rows,
+                                     const int32_t* __restrict__ rowmap, int x, int y, int z,
+                                     int64_t local, const RowDesc& self, Real d[Q])
+{
+    const int64_t own = R.base + local;
+    if constexpr (MASKED) {
+        // fluid runs of the 9 rows (y - cy, z - cz), cy, cz in {-1,0,1}: index (cy+1)+3(cz+1)
+        int32_t st[9], lo[9], ln[9];
+#pragma unroll
+        for (int r9 = 0; r9 < 9; ++r9) {
+            const int cy = r9 % 3 - 1, cz = r9 / 3 - 1;
+            if (cy == 0 && cz == 0) {
+                st[r9] = self.start; lo[r9] = self.xlo; ln[r9] = self.len;
+            } else {
+                const int yy = wrap1(y - cy, R.ny), zz = wrap1(z - cz, R.nz);
+                const int32_t rm = rowmap[R.row_base + yy + R.ny * zz];
+                if (rm >= 0) {
+                    const RowDesc rd = rows[rm];
+                    st[r9] = rd.start; lo[r9] = rd.xlo; ln[r9] = rd.len;
+                } else {
+                    st[r9] = 0; lo[r9] = 0; ln[r9] = 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+            const int r9 = (cy + 1) + 3 * (cz + 1);
+            const int xs = wrap1(x - cx, R.nx);
+            const int off = xs - lo[r9];
+            const bool fluid = (unsigned)off < (unsigned)ln[r9];
+            const int64_t g = fluid ? R.base + st[r9] + off : own;
+            const int p = fluid ? i : opposite_of(i);
+            d[i] = src[(int64_t)p * N + g];
+        }
+    } else {
+        const int xm = wrap1(x - 1, R.nx), xp = wrap1(x + 1, R.nx);
+        const int ym = wrap1(y - 1, R.ny), yp = wrap1(y + 1, R.ny);
+        const int zm = wrap1(z - 1, R.nz), zp = wrap1(z + 1, R.nz);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+            const int xs = cx == 0 ? x : (cx > 0 ? xm : xp);
+            const int ys = cy == 0 ? y : (cy > 0 ? ym : yp);
+            const int zs = cz == 0 ? z : (cz > 0 ? zm : zp);
+            const int64_t g = R.base + xs + (int64_t)R.nx * (ys + (int64_t)R.ny * zs);
+            d[i] = src[(int64_t)i * N + g];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ spread force
+// Bead forces are spread as sums of 64-bit integers, so the total on a node does not depend
+// on the order of the atomic additions.  Word 0 counts units of 2^-56; in FP64 a second
+// word carries the remainder in units of 2^-112, which makes the spread exact to far below
+// FP64 rounding.  Layout: word w of axis ax of node g at gforce[(w*3 + ax) * N + g].
+template <typename Real>
+__device__ __forceinline__ void add_spread_force(long long* gforce, int64_t N, int ax, int64_t g,
+                                                 double val)
+{
+    const double x = val * 0x1p56;
+    const double hi = floor(x);
+    atomicAdd((unsigned long long*)(gforce + (int64_t)ax * N + g),
+              (unsigned long long)(long long)hi);
+    if constexpr (sizeof(Real) == 8) {
+        const long long lo = (long long)((x - hi) * 0x1p56);
+        atomicAdd((unsigned long long*)(gforce + (int64_t)(3 + ax) * N + g), (unsigned long long)lo);
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ Real take_spread_force(long long* gforce, int64_t N, int ax, int64_t g)
+{
+    long long* p = gforce + (int64_t)ax * N + g;
+    double v = (double)(*p) * 0x1p-56;
+    *p = 0;
+    if constexpr (sizeof(Real) == 8) {
+        long long* q = gforce + (int64_t)(3 + ax) * N + g;
+        v += (double)(*q) * 0x1p-112;
+        *q = 0;
+    }
+    return (Real)v;
+}
+
+// ------------------------------------------------------------------ node update
+
+template <typename Real, bool MASKED, bool THERMAL>
+__global__ __launch_bounds__(kNodeBlock) void node_update_kernel(const StepArgs<Real> a)
+{
+    const NodeTile t = a.tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const ReplicaDesc R = a.reps[t.replica];
+    const int64_t local = t.begin + threadIdx.x;
+    int x, y, z;
+    RowDesc self;
+    locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
+
+    Real d[Q];
+    pull<Real, MASKED>(a.src, a.N, R, a.rows, a.rowmap, x, y, z, local, self, d);
+
+    const int64_t g = R.base + local;
+    Real F[3] = {a.gext[0], a.gext[1], a.gext[2]};
+    const uint32_t word = a.flags[g >> 5];
+    if (word) {
+        if ((word >> (g & 31)) & 1u) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) F[ax] += take_spread_force<Real>(a.gforce, a.N, ax, g);
+        }
+        if ((g & 31) == 0) a.flags[g >> 5] = 0u;
+    }
+
+    if constexpr (THERMAL) {
+        const int64_t step = current_step(a.step_ptr, a.step_arg);
+        const uint32_t dense = (uint32_t)(x + (int64_t)R.nx * (y + (int64_t)R.ny * z));
+        const U4 b0 = noise_block((uint64_t)step, dense, 0u, 0u, R.key0, R.key1);
+        const U4 b1 = noise_block((uint64_t)step, dense, 0u, 1u, R.key0, R.key1);
+        const uint32_t w[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+        Real U[15];
+#pragma unroll
+        for (int h = 0; h < 15; ++h) U[h] = uniform16<Real>((h & 1) ? (w[h >> 1] >> 16) : w[h >> 1]);
+        collide<Real>(a.cp, d, F, U);
+    } else {
+        collide<Real>(a.cp, d, F, nullptr);
+    }
+
+    Real* __restrict__ dst = a.dst;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[(int64_t)i * a.N + g] = d[i];
+}
+
+template <typename Real>
+void launch_node_update(const StepArgs<Real>& a, bool masked, hipStream_t s)
+{
+    if (a.n_tiles <= 0) return;
+    const dim3 grid(a.n_tiles), block(kNodeBlock);
+    if (masked) {
+        if (a.thermal) hipLaunchKernelGGL((node_update_kernel<Real, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((node_update_kernel<Real, true, false>), grid, block, 0, s, a);
+    } else {
+        if (a.thermal) hipLaunchKernelGGL((node_update_kernel<Real, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((node_update_kernel<Real, false, false>), grid, block, 0, s, a);
+    }
+}
+
+// ------------------------------------------------------------------ bead coupling
+
+// local index of node (x,y,z) of a replica, or -1 for a boundary node
+__device__ __forceinline__ int64_t node_local(const ReplicaDesc& R, const RowDesc* __restrict__ rows,
+                                              const int32_t* __restrict__ rowmap, int x, int y,
+                                              int z, RowDesc& self)
+{
+    if (!R.masked) {
+        self.start = 0; self.xlo = 0; self.len = R.nx; self.yz = 0;
+        return x + (int64_t)R.nx * (y + (int64_t)R.ny * z);
+    }
+    const int32_t rm = rowmap[R.row_base + y + R.ny * z];
+    if (rm < 0) return -1;
+    self = rows[rm];
+    const int off = x - self.xlo;
+    if ((unsigned)off >= (unsigned)self.len) return -1;
+    return self.start + off;
+}
+
+// periodic cell index and fraction of a coordinate; a non-finite or absurdly large
+// coordinate (a diverged body) maps to cell 0 so that no access leaves the box
+__device__ __forceinline__ int wrap_floor(double v, int n, double& frac)
+{
+    if (!(fabs(v) < 1e15)) { frac = 0.0; return 0; }
+    const double fl = floor(v);
+    frac = v - fl;
+    int64_t i = (int64_t)fl % n;
+    if (i < 0) i += n;
+    return (int)i;
+}
+
+template <typename Real, bool ANY_MASKED>
+__global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Real> a,
+                                                              const CoupleArgs c)
+{
+    const int tid = blockIdx.x * kCoupleBlock + threadIdx.x;
+    const int bead = tid >> 3, corner = tid & 7;
+    if (bead >= c.n_beads) return;   // the 8 lanes of a bead leave together
+    const int bi = c.bead_body[bead];
+    const Body B = c.bodies[bi];
+    double pos[3], q[4], vel[3], om[3];
+    first_half(B, pos, q, vel, om);
+    double M[3][3];
+    quat_to_matrix(q, M);
+    const double off[3] = {c.bead_off[3 * bead], c.bead_off[3 * bead + 1], c.bead_off[3 * bead + 2]};
+    double dv[3], r[3], v[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        dv[ax] = M[ax][0] * off[0] + M[ax][1] * off[1] + M[ax][2] * off[2];
+        r[ax] = pos[ax] + dv[ax];
+    }
+    if (B.fixed) {
+        v[0] = v[1] = v[2] = 0.0;
+    } else {
+        const double wb[3] = {om[1] * off[2] - om[2] * off[1], om[2] * off[0] - om[0] * off[2],
+                              om[0] * off[1] - om[1] * off[0]};
+        for (int ax = 0; ax < 3; ++ax)
+            v[ax] = vel[ax] + M[ax][0] * wb[0] + M[ax][1] * wb[1] + M[ax][2] * wb[2];
+    }
+    const ReplicaDesc R = a.reps[B.replica];
+
+    // corner of the trilinear stencil handled by this lane
+    double fr[3];
+    int i0[3];
+    i0[0] = wrap_floor(r[0] - 0.5, R.nx, fr[0]);
+    i0[1] = wrap_floor(r[1] - 0.5, R.ny, fr[1]);
+    i0[2] = wrap_floor(r[2] - 0.5, R.nz, fr[2]);
+    const int ox = corner & 1, oy = (corner >> 1) & 1, oz = corner >> 2;
+    const int px = i0[0] + ox == R.nx ? 0 : i0[0] + ox;
+    const int py = i0[1] + oy == R.ny ? 0 : i0[1] + oy;
+    const int pz = i0[2] + oz == R.nz ? 0 : i0[2] + oz;
+    const double w = (ox ? fr[0] : 1.0 - fr[0]) * (oy ? fr[1] : 1.0 - fr[1]) *
+                     (oz ? fr[2] : 1.0 - fr[2]);
+
+    RowDesc self;
+    const int64_t local = node_local(R, a.rows, a.rowmap, px, py, pz, self);
+    double wu[3] = {0.0, 0.0, 0.0};
+    if (local >= 0) {
+        Real d[Q];
+        if (ANY_MASKED && R.masked)
+            pull<Real, true>(a.src, a.N, R, a.rows, a.rowmap, px, py, pz, local, self, d);
+        else
+            pull<Real, false>(a.src, a.N, R, a.rows, a.rowmap, px, py, pz, local, self, d);
+        Real drho, j[3];
+        density_momentum<Real>(d, drho, j);
+        const double rho = (double)a.cp.rho0 + (double)drho;
+        for (int ax = 0; ax < 3; ++ax)
+            wu[ax] = w * (((double)j[ax] + 0.5 * (double)a.gext[ax]) / rho);
+    }
+    // sum over the 8 corner lanes (same association on every lane)
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1)
+        for (int ax = 0; ax < 3; ++ax) wu[ax] += __shfl_xor(wu[ax], m, 8);
+
+    double F[3];
+    for (int ax = 0; ax < 3; ++ax) F[ax] = -B.gamma * (v[ax] - wu[ax]);
+    if (c.kT > 0.0) {
+        const int64_t step = current_step(a.step_ptr, a.step_arg);
+        const uint32_t idx = (uint32_t)(B.first_bead_in_replica + (bead - B.first_bead));
+        const U4 blk = noise_block((uint64_t)step, idx, 1u, 0u, R.key0, R.key1);
+        const double amp = sqrt(2.0 * c.kT * B.gamma) * sqrt(12.0);
+        F[0] += amp * uniform16<double>(blk.x);
+        F[1] += amp * uniform16<double>(blk.x >> 16);
+        F[2] += amp * uniform16<double>(blk.y);
+    }
+
+    if (local >= 0) {
+        const int64_t g = R.base + local;
+        bool overflow = false;
+        for (int ax = 0; ax < 3; ++ax) {
+            const double val = -(w * F[ax]);
+            const bool bad = !(fabs(val) < 16.0);
+            overflow |= bad;
+            add_spread_force<Real>(a.gforce, a.N, ax, g, bad ? 0.0 : val);
+        }
+        atomicOr(a.flags + (g >> 5), 1u << (g & 31));
+        if (overflow) atomicOr(&c.hdr->err_flags, 1u);
+    }
+    if (corner == 0) {
+        for (int ax = 0; ax < 3; ++ax) c.bead_force[3 * bead + ax] = F[ax];
+        c.bead_torque[3 * bead + 0] = dv[1] * F[2] - dv[2] * F[1];
+        c.bead_torque[3 * bead + 1] = dv[2] * F[0] - dv[0] * F[2];
+        c.bead_torque[3 * bead + 2] = dv[0] * F[1] - dv[1] * F[0];
+    }
+}
+
+template <typename Real>
+void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, bool any_masked, hipStream_t s)
+{
+    if (c.n_beads <= 0) return;
+    const int threads = c.n_beads * kBeadLanes;
+    const dim3 grid((threads + kCoupleBlock - 1) / kCoupleBlock), block(kCoupleBlock);
+    if (any_masked) hipLaunchKernelGGL((couple_kernel<Real, true>), grid, block, 0, s, a, c);
+    else hipLaunchKernelGGL((couple_kernel<Real, false>), grid, block, 0, s, a, c);
+}
+
+// ------------------------------------------------------------------ body update
+
+__global__ __launch_bounds__(256) void body_finish_kernel(Body* __restrict__ bodies,
+                                                          const double* __restrict__ bf,
+                                                          const double* __restrict__ bt)
+{
+    __shared__ double part[4][6];
+    const int b = blockIdx.x;
+    const Body B = bodies[b];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = threadIdx.x; k < B.n_beads; k += 256) {
+        const int64_t e = 3 * (int64_t)(B.first_bead + k);
+        acc[0] += bf[e]; acc[1] += bf[e + 1]; acc[2] += bf[e + 2];
+        acc[3] += bt[e]; acc[4] += bt[e + 1]; acc[5] += bt[e + 2];
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        for (int k = 0; k < 6; ++k) acc[k] += __shfl_down(acc[k], m, 64);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 6; ++k) part[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double F[3], T[3];
+    for (int k = 0; k < 3; ++k) {
+        F[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
+        T[k] = (part[0][3 + k] + part[1][3 + k]) + (part[2][3 + k] + part[3][3 + k]);
+    }
+    double pos[3], q[4], vel[3], om[3];
+    first_half(B, pos, q, vel, om);
+    double M[3][3];
+    quat_to_matrix(q, M);
+    double Tb[3];
+    for (int ax = 0; ax < 3; ++ax) Tb[ax] = M[0][ax] * T[0] + M[1][ax] * T[1] + M[2][ax] * T[2];
+    if (!B.fixed) {
+        for (int ax = 0; ax < 3; ++ax) vel[ax] += 0.5 * F[ax] / B.mass;
+        half_kick(om, B.inertia, Tb);
+    }
+    Body* o = bodies + b;
+    for (int ax = 0; ax < 3; ++ax) {
+        o->pos[ax] = pos[ax];
+        o->vel[ax] = vel[ax];
+        o->omega[ax] = om[ax];
+        o->force[ax] = F[ax];
+        o->torque[ax] = Tb[ax];
+    }
+    for (int k = 0; k < 4; ++k) o->quat[k] = q[k];
+}
+
+void launch_body_finish(Body* bodies, const double* bead_force, const double* bead_torque,
+                        int32_t n_bodies, hipStream_t s)
+{
+    if (n_bodies <= 0) return;
+    hipLaunchKernelGGL(body_finish_kernel, dim3(n_bodies), dim3(256), 0, s, bodies, bead_force,
+                       bead_torque);
+}
+
+__global__ void set_step_kernel(int64_t* p, int64_t v) { *p = v; }
+
+void launch_set_step(int64_t* step_ptr, int64_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(1), 0, s, step_ptr, value);
+}
+
+// ------------------------------------------------------------------ initial state
+
+template <typename Real>
+__global__ __launch_bounds__(kNodeBlock) void init_equilibrium_kernel(
+    Real* f, int64_t N, const ReplicaDesc* reps, const NodeTile* tiles, Real rho0, double ux,
+    double uy, double uz)
+{
+    const NodeTile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const ReplicaDesc R = reps[t.replica];
+    const int64_t g = R.base + t.begin + threadIdx.x;
+    const double r0 = (double)rho0, uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double cu = cx_of(i) * ux + cy_of(i) * uy + cz_of(i) * uz;
+        f[(int64_t)i * N + g] = (Real)(weight_of(i) * r0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    }
+}
+
+template <typename Real>
+void launch_init_equilibrium(Real* f, int64_t N, const ReplicaDesc* reps, const NodeTile* tiles,
+                             int32_t n_tiles, Real rho0, const double u0[3], hipStream_t s)
+{
+    if (n_tiles <= 0) return;
+    hipLaunchKernelGGL((init_equilibrium_kernel<Real>), dim3(n_tiles), dim3(kNodeBlock), 0, s, f, N,
+                       reps, tiles, rho0, u0[0], u0[1], u0[2]);
+}
+
+// ------------------------------------------------------------------ observables
+
+template <typename Real, bool MASKED>
+__global__ __launch_bounds__(kNodeBlock) void observe_kernel(const StepArgs<Real> a,
+                                                             const NodeTile* tiles, Real* fields,
+                                                             double* partials, double* pops)
+{
+    __shared__ double part[kNodeBlock / 64][5];
+    const NodeTile t = tiles[blockIdx.x];
+    const ReplicaDesc R = a.reps[t.replica];
+    double acc[5] = {0, 0, 0, 0, 0};
+    if ((int)threadIdx.x < t.count) {
+        const int64_t local = t.begin + threadIdx.x;
+        int x, y, z;
+        RowDesc self;
+        locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
+        Real d[Q];
+        pull<Real, MASKED>(a.src, a.N, R, a.rows, a.rowmap, x, y, z, local, self, d);
+        Real drho, j[3];
+        density_momentum<Real>(d, drho, j);
+        const int64_t dense = x + (int64_t)R.nx * (y + (int64_t)R.ny * z);
+        if (fields) {
+            const Real rho = a.cp.rho0 + drho;
+            Real* o = fields + 4 * dense;
+            o[0] = rho;
+            for (int ax = 0; ax < 3; ++ax) o[1 + ax] = (j[ax] + (Real)0.5 * a.gext[ax]) / rho;
+        }
+        if (pops) {
+            for (int i = 0; i < Q; ++i)
+                pops[(int64_t)i * R.n_nodes + dense] = (double)d[i] + weight_of(i) * (double)a.cp.rho0;
+        }
+        acc[0] = (double)drho;
+        acc[1] = (double)j[0]; acc[2] = (double)j[1]; acc[3] = (double)j[2];
+        bool fin = isfinite((double)drho) && isfinite((double)j[0]) && isfinite((double)j[1]) &&
+                   isfinite((double)j[2]);
+        for (int i = 0; i < Q; ++i) fin = fin && isfinite((double)d[i]);
+        acc[4] = fin ? 0.0 : 1.0;
+    }
+    if (!partials) return;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        for (int k = 0; k < 5; ++k) acc[k] += __shfl_down(acc[k], m, 64);
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 5; ++k) part[threadIdx.x >> 6][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 5; ++k)
+            partials[5 * (int64_t)blockIdx.x + k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
+}
+
+template <typename Real>
+void launch_observe(const StepArgs<Real>& a, bool masked, int32_t tile0, int32_t n_tiles,
+                    Real* fields, double* partials, double* pops_out, hipStream_t s)
+{
+    if (n_tiles <= 0) return;
+    const NodeTile* tiles = a.tiles + tile0;
+    if (masked)
+        hipLaunchKernelGGL((observe_kernel<Real, true>), dim3(n_tiles), dim3(kNodeBlock), 0, s, a,
+                           tiles, fields, partials, pops_out);
+    else
+        hipLaunchKernelGGL((observe_kernel<Real, false>), dim3(n_tiles), dim3(kNodeBlock), 0, s, a,
+                           tiles, fields, partials, pops_out);
+}
+
+// explicit instantiations
+template void launch_node_update<float>(const StepArgs<float>&, bool, hipStream_t);
+template void launch_node_update<double>(const StepArgs<double>&, bool, hipStream_t);
+template void launch_couple<float>(const StepArgs<float>&, const CoupleArgs&, bool, hipStream_t);
+template void launch_couple<double>(const StepArgs<double>&, const CoupleArgs&, bool, hipStream_t);
+template void launch_init_equilibrium<float>(float*, int64_t, const ReplicaDesc*, const NodeTile*,
+                                             int32_t, float, const double*, hipStream_t);
+template void launch_init_equilibrium<double>(double*, int64_t, const ReplicaDesc*,
+                                              const NodeTile*, int32_t, double, const double*,
+                                              hipStream_t);
+template void launch_observe<float>(const StepArgs<float>&, bool, int32_t, int32_t, float*,
+                                    double*, double*, hipStream_t);
+template void launch_observe<double>(const StepArgs<double>&, bool, int32_t, int32_t, double*,
+                                     double*, double*, hipStream_t);
+
+}  // namespace lbrb

@@ -1,0 +1,106 @@
+// lbrb_layout.h -- device data structures of the library and the kernel launchers.
+//
+// Fluid storage ("compact rows").  Each replica keeps only its fluid nodes.  A (y,z) row of a
+// replica holds at most one contiguous run of fluid nodes [xlo, xlo+len); the runs of all
+// non-empty rows are stored back to back in (z, y) order, so node (x,y,z) of the run of row
+// r lives at local index rows[r].start + x - xlo.  A replica without boundary nodes is
+// "dense": every row is full and the local index is x + nx (y + ny z), computed without
+// tables.  Populations are structure-of-arrays: population i of global node g sits at
+// f[i * N + g], N = total padded node count, g = replica base + local index; each replica's
+// base is a multiple of 256.  Two such buffers alternate between steps: one holds the
+// post-collision populations of the previous step, the kernel pulls from it and writes the
+// next post-collision state into the other.
+#ifndef LBRB_LAYOUT_H
+#define LBRB_LAYOUT_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbrb_core.h"
+
+namespace lbrb {
+
+constexpr int kNodeBlock = 256;   // threads (= nodes) per node-update workgroup
+constexpr int kBeadLanes = 8;     // threads per bead in the coupling kernel (one per corner)
+constexpr int kCoupleBlock = 256;
+
+struct ReplicaDesc {
+    int32_t nx, ny, nz, masked;
+    int64_t base;           // global index of local node 0
+    int64_t n_nodes;        // nx*ny*nz
+    int64_t n_fluid;
+    int32_t row_base;       // first entry of this replica in rows[] and rowmap[]
+    uint32_t key0, key1;    // Philox key (seed)
+    int32_t pad;
+    double inv_nx, inv_ny;  // for exact index division
+};
+
+struct RowDesc {
+    int32_t start;          // local index of the first fluid node of the row
+    int32_t xlo, len;       // fluid run [xlo, xlo+len)
+    int32_t yz;             // y | z << 16
+};
+
+struct NodeTile {
+    int32_t replica;
+    int32_t count;          // nodes in this tile (<= kNodeBlock)
+    int64_t begin;          // local index of the first node
+    int32_t row_lo, row_hi; // rows[] range that covers the tile (masked replicas)
+};
+
+struct DeviceHeader {
+    int64_t step;           // completed steps (read by graph-replayed kernels)
+    uint32_t err_flags;     // bit 0: spread force out of the fixed-point range
+    uint32_t pad;
+};
+
+template <typename Real>
+struct StepArgs {
+    const Real* src;        // post-collision populations of the previous step
+    Real* dst;              // post-collision populations of this step
+    int64_t N;              // stride between populations
+    const ReplicaDesc* reps;
+    const RowDesc* rows;
+    const int32_t* rowmap;
+    const NodeTile* tiles;
+    int32_t n_tiles;
+    int32_t thermal;
+    long long* gforce;      // fixed-point spread force, [word][axis][node] (1 or 2 words)
+    uint32_t* flags;        // 1 bit per node: spread force present
+    CollideParams<Real> cp;
+    Real gext[3];
+    const int64_t* step_ptr;  // if set, step = *step_ptr + step_arg
+    int64_t step_arg;
+};
+
+struct CoupleArgs {
+    const Body* bodies;
+    const double* bead_off;     // 3 per bead, body frame
+    const int32_t* bead_body;
+    double* bead_force;         // 3 per bead, lab frame
+    double* bead_torque;        // 3 per bead, lab frame
+    int32_t n_beads;
+    double kT;
+    DeviceHeader* hdr;
+};
+
+template <typename Real>
+void launch_node_update(const StepArgs<Real>& a, bool masked, hipStream_t s);
+template <typename Real>
+void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, bool any_masked,
+                   hipStream_t s);
+void launch_body_finish(Body* bodies, const double* bead_force, const double* bead_torque,
+                        int32_t n_bodies, hipStream_t s);
+void launch_set_step(int64_t* step_ptr, int64_t value, hipStream_t s);
+template <typename Real>
+void launch_init_equilibrium(Real* f, int64_t N, const ReplicaDesc* reps, const NodeTile* tiles,
+                             int32_t n_tiles, Real rho0, const double u0[3], hipStream_t s);
+// per-replica observables over a tile range: fields (may be null), partial sums (5 doubles per
+// tile: drho, jx, jy, jz, nonfinite count), exported FP64 populations (may be null)
+template <typename Real>
+void launch_observe(const StepArgs<Real>& a, bool masked, int32_t tile0, int32_t n_tiles,
+                    Real* fields, double* partials, double* pops_out, hipStream_t s);
+
+}  // namespace lbrb
+
+#endif

@@ -1,0 +1,362 @@
+"""Python binding of the gfx950 raspberry / lattice-Boltzmann library (``liblbrb.so``).
+
+The functions carry the C-ABI's names (``lb_init``, ``lb_set_boundary_mask``,
+``rb_add_raspberry``, ``lb_rb_step``, ``lb_observables``, ...) and only marshal arguments:
+every step of the method runs in the HIP kernels of the library.  ``Simulation`` wraps one
+context and takes its device workspace and stream from PyTorch.
+
+There is no CPU fallback: importing works anywhere, but loading the library raises if it
+has not been built (``python -m paper_1604_01829_amd.build``) and creating a context raises if
+no GPU is visible.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbrb.so")
+
+LB_OK = 0
+LB_ERR_ARG = -1
+LB_ERR_STATE = -2
+LB_ERR_HIP = -3
+LB_ERR_UNSTABLE = -4
+LB_ERR_CAPACITY = -5
+LB_PRECISION_F64 = 0
+LB_PRECISION_F32 = 1
+
+# every symbol declared in include/lbrb.h
+EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "rb_add_raspberry",
+            "lb_rb_step", "lb_observables", "lb_body_count", "rb_bead_forces",
+            "lb_export_populations", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
+            "lb_set_timing", "lb_kernel_times", "lb_node_counts", "lb_destroy", "lb_last_error"]
+
+
+class lb_replica(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class lb_params(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("rho0", ctypes.c_double),
+                ("u0", ctypes.c_double * 3), ("tau_shear", ctypes.c_double),
+                ("tau_bulk", ctypes.c_double), ("tau_odd", ctypes.c_double),
+                ("tau_even", ctypes.c_double), ("kT", ctypes.c_double),
+                ("g_ext", ctypes.c_double * 3), ("max_bodies", ctypes.c_int32),
+                ("max_beads", ctypes.c_int32)]
+
+
+class lb_totals(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3),
+                ("body_momentum", ctypes.c_double * 3), ("step", ctypes.c_int64),
+                ("finite", ctypes.c_int32)]
+
+
+class rb_state(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_double * 3), ("quat", ctypes.c_double * 4),
+                ("vel", ctypes.c_double * 3), ("omega_body", ctypes.c_double * 3),
+                ("force", ctypes.c_double * 3), ("torque", ctypes.c_double * 3)]
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_VP = ctypes.c_void_p
+
+
+def library():
+    """Load liblbrb.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1604_01829_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.lb_workspace_bytes.restype = ctypes.c_size_t
+    L.lb_workspace_bytes.argtypes = [ctypes.POINTER(lb_params), ctypes.POINTER(lb_replica),
+                                     ctypes.c_int32]
+    L.lb_init.restype = ctypes.c_int
+    L.lb_init.argtypes = [ctypes.POINTER(lb_params), ctypes.POINTER(lb_replica), ctypes.c_int32,
+                          _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]
+    L.lb_set_boundary_mask.restype = ctypes.c_int
+    L.lb_set_boundary_mask.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8)]
+    L.rb_add_raspberry.restype = ctypes.c_int
+    L.rb_add_raspberry.argtypes = [_VP, ctypes.c_int32, _D, ctypes.c_int32, ctypes.c_double, _D,
+                                   _D, _D, _D, _D, ctypes.c_double, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)]
+    L.lb_rb_step.restype = ctypes.c_int
+    L.lb_rb_step.argtypes = [_VP, ctypes.c_int32]
+    L.lb_observables.restype = ctypes.c_int
+    L.lb_observables.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(lb_totals),
+                                 ctypes.POINTER(rb_state), _VP]
+    L.lb_body_count.restype = ctypes.c_int
+    L.lb_body_count.argtypes = [_VP, ctypes.c_int32]
+    L.rb_bead_forces.restype = ctypes.c_int
+    L.rb_bead_forces.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32, _D, ctypes.c_int32]
+    L.lb_export_populations.restype = ctypes.c_int
+    L.lb_export_populations.argtypes = [_VP, ctypes.c_int32, _VP]
+    L.lb_save_state.restype = ctypes.c_int
+    L.lb_save_state.argtypes = [_VP, _VP, ctypes.POINTER(ctypes.c_size_t)]
+    L.lb_load_state.restype = ctypes.c_int
+    L.lb_load_state.argtypes = [_VP, _VP, ctypes.c_size_t]
+    L.lb_set_graph_steps.restype = ctypes.c_int
+    L.lb_set_graph_steps.argtypes = [_VP, ctypes.c_int32]
+    L.lb_set_timing.restype = ctypes.c_int
+    L.lb_set_timing.argtypes = [_VP, ctypes.c_int32]
+    L.lb_kernel_times.restype = ctypes.c_int
+    L.lb_kernel_times.argtypes = [_VP, _D, ctypes.POINTER(ctypes.c_int64), _D,
+                                  ctypes.POINTER(ctypes.c_int64)]
+    L.lb_node_counts.restype = ctypes.c_int
+    L.lb_node_counts.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int64)]
+    L.lb_destroy.restype = None
+    L.lb_destroy.argtypes = [_VP]
+    L.lb_last_error.restype = ctypes.c_char_p
+    L.lb_last_error.argtypes = [_VP]
+    _lib = L
+    return L
+
+
+class LBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbrb error {code}: {msg}")
+        self.code = code
+
+
+def _arr(x, n):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(n))
+    return a
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+# ------------------------------------------------------------------ C-ABI names
+
+def make_params(precision="f32", rho0=1.0, u0=(0.0, 0.0, 0.0), tau_shear=1.0, tau_bulk=None,
+                tau_odd=1.0, tau_even=1.0, kT=0.0, g_ext=(0.0, 0.0, 0.0), max_bodies=0,
+                max_beads=0):
+    p = lb_params()
+    p.precision = LB_PRECISION_F32 if precision in ("f32", LB_PRECISION_F32) else LB_PRECISION_F64
+    p.rho0 = rho0
+    p.u0[:] = list(u0)
+    p.tau_shear = tau_shear
+    p.tau_bulk = tau_shear if tau_bulk is None else tau_bulk
+    p.tau_odd = tau_odd
+    p.tau_even = tau_even
+    p.kT = kT
+    p.g_ext[:] = list(g_ext)
+    p.max_bodies = max_bodies
+    p.max_beads = max_beads
+    return p
+
+
+def make_replicas(shapes_seeds):
+    arr = (lb_replica * len(shapes_seeds))()
+    for k, (shape, seed) in enumerate(shapes_seeds):
+        arr[k].nx, arr[k].ny, arr[k].nz = (int(v) for v in shape)
+        arr[k].seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    return arr
+
+
+def lb_workspace_bytes(params, replicas):
+    return library().lb_workspace_bytes(ctypes.byref(params), replicas, len(replicas))
+
+
+def lb_init(params, replicas, dev_workspace, ws_bytes, hip_stream):
+    h = _VP()
+    rc = library().lb_init(ctypes.byref(params), replicas, len(replicas), _VP(dev_workspace),
+                           ws_bytes, _VP(hip_stream), ctypes.byref(h))
+    if rc != LB_OK:
+        raise LBError(rc, "lb_init failed")
+    return h
+
+
+def _check(ctx, rc, what):
+    if rc != LB_OK:
+        raise LBError(rc, f"{what}: {library().lb_last_error(ctx).decode()}")
+
+
+def lb_set_boundary_mask(ctx, replica, mask):
+    m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(-1))
+    _check(ctx, library().lb_set_boundary_mask(ctx, replica,
+                                               m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))),
+           "lb_set_boundary_mask")
+
+
+def rb_add_raspberry(ctx, replica, offsets, mass, inertia, pos, quat=(1, 0, 0, 0),
+                     vel=(0, 0, 0), omega=(0, 0, 0), gamma=0.0, fixed=False):
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.float64).reshape(-1, 3))
+    bid = ctypes.c_int32(-1)
+    rc = library().rb_add_raspberry(ctx, replica, _dp(off), off.shape[0], float(mass),
+                                    _dp(_arr(inertia, 3)), _dp(_arr(pos, 3)), _dp(_arr(quat, 4)),
+                                    _dp(_arr(vel, 3)), _dp(_arr(omega, 3)), float(gamma),
+                                    1 if fixed else 0, ctypes.byref(bid))
+    _check(ctx, rc, "rb_add_raspberry")
+    return bid.value
+
+
+def lb_rb_step(ctx, n_steps):
+    _check(ctx, library().lb_rb_step(ctx, int(n_steps)), "lb_rb_step")
+
+
+def lb_observables(ctx, replica, n_bodies, dev_rho_u=None, check=True):
+    tot = lb_totals()
+    bodies = (rb_state * max(1, n_bodies))()
+    rc = library().lb_observables(ctx, replica, ctypes.byref(tot), bodies,
+                                  _VP(dev_rho_u) if dev_rho_u else None)
+    if check:
+        _check(ctx, rc, "lb_observables")
+    return rc, tot, list(bodies)[:n_bodies]
+
+
+def lb_destroy(ctx):
+    library().lb_destroy(ctx)
+
+
+# ------------------------------------------------------------------ convenience wrapper
+
+class Simulation:
+    """One context with its workspace held as a torch uint8 tensor on ``device``."""
+
+    def __init__(self, params, replicas, device="cuda:0", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lbrb library has no CPU path")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = params
+        self.replicas = replicas
+        self.shapes = [(r.nx, r.ny, r.nz) for r in replicas]
+        self.f32 = params.precision == LB_PRECISION_F32
+        self.dtype = torch.float32 if self.f32 else torch.float64
+        nbytes = lb_workspace_bytes(params, replicas)
+        if nbytes == 0:
+            raise LBError(LB_ERR_ARG, "invalid parameters or boxes")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = lb_init(params, replicas, aligned, nbytes, self.stream.cuda_stream)
+        self.n_bodies = [0] * len(replicas)
+        self.n_beads = {}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mask(self, replica, mask):
+        lb_set_boundary_mask(self.ctx, replica, mask)
+
+    def add_body(self, replica, offsets, mass, inertia, pos, quat=(1, 0, 0, 0), vel=(0, 0, 0),
+                 omega=(0, 0, 0), gamma=0.0, fixed=False):
+        bid = rb_add_raspberry(self.ctx, replica, offsets, mass, inertia, pos, quat, vel, omega,
+                               gamma, fixed)
+        self.n_bodies[replica] += 1
+        self.n_beads[(replica, bid)] = int(np.asarray(offsets).reshape(-1, 3).shape[0])
+        return bid
+
+    def step(self, n=1):
+        lb_rb_step(self.ctx, n)
+
+    def set_graph_steps(self, k):
+        _check(self.ctx, library().lb_set_graph_steps(self.ctx, int(k)), "lb_set_graph_steps")
+
+    def set_timing(self, on):
+        _check(self.ctx, library().lb_set_timing(self.ctx, 1 if on else 0), "lb_set_timing")
+
+    def kernel_times(self):
+        tn, tc = ctypes.c_double(), ctypes.c_double()
+        nn, nc = ctypes.c_int64(), ctypes.c_int64()
+        _check(self.ctx, library().lb_kernel_times(self.ctx, ctypes.byref(tn), ctypes.byref(nn),
+                                                   ctypes.byref(tc), ctypes.byref(nc)),
+               "lb_kernel_times")
+        return {"node_ms": tn.value, "node_launches": nn.value, "couple_ms": tc.value,
+                "couple_launches": nc.value}
+
+    def node_counts(self, replica=0):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(self.ctx, library().lb_node_counts(self.ctx, replica, ctypes.byref(a),
+                                                  ctypes.byref(b)), "lb_node_counts")
+        return a.value, b.value
+
+    def observables(self, replica=0, fields=False, check=True):
+        """(totals dict, [body dicts], fields (nz,ny,nx,4) numpy or None, return code)."""
+        torch = self.torch
+        nx, ny, nz = self.shapes[replica]
+        buf = None
+        if fields:
+            buf = torch.empty(4 * nx * ny * nz, dtype=self.dtype, device=self.device)
+        rc, tot, bodies = lb_observables(self.ctx, replica, self.n_bodies[replica],
+                                         buf.data_ptr() if buf is not None else None, check)
+        t = {"mass": tot.mass, "momentum": np.array(tot.momentum[:]),
+             "body_momentum": np.array(tot.body_momentum[:]), "step": tot.step,
+             "finite": bool(tot.finite)}
+        bs = [{"pos": np.array(b.pos[:]), "quat": np.array(b.quat[:]), "vel": np.array(b.vel[:]),
+               "omega": np.array(b.omega_body[:]), "force": np.array(b.force[:]),
+               "torque": np.array(b.torque[:])} for b in bodies]
+        f = None
+        if buf is not None:
+            f = buf.double().cpu().numpy().reshape(nz, ny, nx, 4)
+        return t, bs, f, rc
+
+    def fields(self, replica=0):
+        return self.observables(replica, fields=True)[2]
+
+    def populations(self, replica=0):
+        torch = self.torch
+        nx, ny, nz = self.shapes[replica]
+        buf = torch.empty(19 * nx * ny * nz, dtype=torch.float64, device=self.device)
+        _check(self.ctx, library().lb_export_populations(self.ctx, replica, _VP(buf.data_ptr())),
+               "lb_export_populations")
+        return buf.cpu().numpy().reshape(19, nz, ny, nx)
+
+    def bead_forces(self, replica, body):
+        n = self.n_beads[(replica, body)]
+        out = np.zeros(3 * n)
+        _check(self.ctx, library().rb_bead_forces(self.ctx, replica, body, _dp(out), n),
+               "rb_bead_forces")
+        return out.reshape(n, 3)
+
+    def save_state(self):
+        torch = self.torch
+        n = ctypes.c_size_t(0)
+        _check(self.ctx, library().lb_save_state(self.ctx, None, ctypes.byref(n)), "lb_save_state")
+        buf = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        _check(self.ctx, library().lb_save_state(self.ctx, _VP(buf.data_ptr()), ctypes.byref(n)),
+               "lb_save_state")
+        return buf
+
+    def load_state(self, buf):
+        _check(self.ctx, library().lb_load_state(self.ctx, _VP(buf.data_ptr()), buf.numel()),
+               "lb_load_state")
+
+
+def simulation_from_workload(wl, precision=None, device="cuda:0", replicas=None,
+                             max_extra_bodies=0, max_extra_beads=0):
+    """Build a Simulation from a record of ``paper_1604_01829_amd.workloads.workload``."""
+    reps = wl["replicas"] if replicas is None else [wl["replicas"][r] for r in replicas]
+    prec = precision or wl["precision"]
+    n_bodies = sum(len(r["bodies"]) for r in reps) + max_extra_bodies
+    n_beads = sum(b["offsets"].shape[0] for r in reps for b in r["bodies"]) + max_extra_beads
+    pp = dict(wl["params"])
+    params = make_params(precision=prec, max_bodies=max(1, n_bodies), max_beads=max(1, n_beads),
+                         **pp)
+    rr = make_replicas([(r["shape"], r["seed"]) for r in reps])
+    sim = Simulation(params, rr, device=device)
+    for k, r in enumerate(reps):
+        if r["mask"] is not None:
+            sim.set_mask(k, r["mask"])
+        for b in r["bodies"]:
+            sim.add_body(k, b["offsets"], b["mass"], b["inertia"], b["pos"], b["quat"], b["vel"],
+                         b["omega"], b["gamma"], b["fixed"])
+    return sim

@@ -1,0 +1,88 @@
+"""Shared test plumbing: build the same workload in the oracle and in the GPU library and
+compare them.  Only marshalling lives here; the arithmetic is in oracle/ and in the HIP
+library respectively."""
+import numpy as np
+
+from oracle import pyoracle as po
+
+
+def oracle_params(wl, rep):
+    p = wl["params"]
+    return po.make_params(rho0=p["rho0"], u0=p["u0"], tau_shear=p["tau_shear"],
+                          tau_bulk=p["tau_bulk"], tau_odd=p["tau_odd"], tau_even=p["tau_even"],
+                          kT=p["kT"], g_ext=p["g_ext"], seed=rep["seed"])
+
+
+def orc_offsets(orc, b):
+    return orc._offsets[b]
+
+
+def oracle_from_workload(wl, r=0):
+    rep = wl["replicas"][r]
+    sim = po.OracleSim(rep["shape"], oracle_params(wl, rep))
+    sim._offsets = [np.asarray(bd["offsets"]) for bd in rep["bodies"]]
+    if rep["mask"] is not None:
+        sim.set_mask(rep["mask"])
+    for b in rep["bodies"]:
+        sim.add_body(b["offsets"], b["mass"], b["inertia"], b["pos"], b["quat"], b["vel"],
+                     b["omega"], b["gamma"], b["fixed"])
+    return sim
+
+
+def gpu_from_workload(wl, precision=None, replicas=None):
+    from paper_1604_01829_amd import lbrb
+    return lbrb.simulation_from_workload(wl, precision=precision, replicas=replicas)
+
+
+def exact_totals(orc):
+    """Oracle mass and momentum summed exactly (math.fsum) over its populations."""
+    import math
+    f = orc.populations().reshape(19, -1)
+    c = po.velocities().astype(float)
+    t = orc.totals()
+    t["mass"] = math.fsum(f.reshape(-1))
+    t["momentum"] = np.array([math.fsum((c[:, a:a + 1] * f).reshape(-1)) for a in range(3)])
+    return t
+
+
+def compare(gpu, orc, r=0, n_bodies=None):
+    """Max errors between a GPU replica and its oracle box: dict of scalars."""
+    tg, bg, fg, rc = gpu.observables(r, fields=True, check=False)
+    fo = orc.fields()
+    to = exact_totals(orc)
+    fluid = fo[..., 0] != 0.0
+    out = {"rc": rc}
+    rho_o, rho_g = fo[..., 0][fluid], fg[..., 0][fluid]
+    out["rho"] = float(np.abs(rho_g - rho_o).max()) if rho_o.size else 0.0
+    uo, ug = fo[..., 1:][fluid], fg[..., 1:][fluid]
+    out["u_abs"] = float(np.abs(ug - uo).max()) if uo.size else 0.0
+    out["u_scale"] = float(np.abs(uo).max()) if uo.size else 0.0
+    out["solid_zero"] = bool(np.all(fg[~fluid] == 0.0))
+    out["mass"] = abs(tg["mass"] - to["mass"]) / max(1.0, abs(to["mass"]))
+    out["momentum"] = float(np.abs(tg["momentum"] - to["momentum"]).max())
+    # gross momentum scale: sum over nodes of |j| (the total is a cancelling sum)
+    f = orc.populations().reshape(19, -1)
+    c = po.velocities().astype(float)
+    out["momentum_scale"] = float(np.abs(c.T @ f).sum())
+    out["finite"] = tg["finite"] == to["finite"]
+    nb = orc.n_bodies if n_bodies is None else n_bodies
+    errs = {"pos": 0.0, "quat": 0.0, "vel": 0.0, "omega": 0.0, "force": 0.0, "torque": 0.0}
+    scale = {"vel": 0.0, "omega": 0.0, "force": 0.0, "torque": 0.0}
+    for b in range(nb):
+        so = orc.body_state(b)
+        sg = bg[b]
+        for k in errs:
+            errs[k] = max(errs[k], float(np.abs(sg[k] - so[k]).max()))
+        # force and torque are sums of per-bead terms that largely cancel; their error scale
+        # is the gross sum of the terms, sum_k |F_k| and sum_k |r_k - R| |F_k|
+        fb = orc.bead_forces(b)
+        radius = np.linalg.norm(orc_offsets(orc, b), axis=1)
+        gross_f = float(np.linalg.norm(fb, axis=1).sum())
+        gross_t = float((radius * np.linalg.norm(fb, axis=1)).sum())
+        scale["force"] = max(scale["force"], gross_f)
+        scale["torque"] = max(scale["torque"], gross_t)
+        for k in ("vel", "omega"):
+            scale[k] = max(scale[k], float(np.abs(so[k]).max()))
+    out.update({"body_" + k: v for k, v in errs.items()})
+    out.update({"scale_" + k: v for k, v in scale.items()})
+    return out

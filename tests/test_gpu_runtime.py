@@ -1,0 +1,178 @@
+"""GPU runtime behaviour through the C-ABI: graphs, determinism, checkpoints, batching of
+uneven replicas, edge cases and error codes.  Parity cases compare with the FP64 oracle."""
+import numpy as np
+import pytest
+
+from paper_1604_01829_amd import lbrb
+from paper_1604_01829_amd import workloads as W
+from tests.helpers import compare, gpu_from_workload, oracle_from_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _thermal_sphere(precision="f32"):
+    wl = W.workload(1)
+    wl["params"]["kT"] = 4e-5
+    wl["precision"] = precision
+    return wl
+
+
+def _state_bytes(sim):
+    return sim.save_state().cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_graph_replay_matches_eager_bitwise(precision):
+    wl = _thermal_sphere(precision)
+    a = gpu_from_workload(wl)
+    a.set_graph_steps(0)
+    b = gpu_from_workload(wl)
+    b.set_graph_steps(20)
+    a.step(47)
+    b.step(47)   # two graph replays of 20 + 7 eager steps
+    assert np.array_equal(_state_bytes(a), _state_bytes(b))
+    a.step(40)
+    b.step(40)   # graph of the other buffer parity
+    assert np.array_equal(_state_bytes(a), _state_bytes(b))
+
+
+def test_runs_are_deterministic():
+    wl = pore_batch()
+    a = gpu_from_workload(wl)
+    b = gpu_from_workload(wl)
+    a.step(25)
+    b.step(25)
+    assert np.array_equal(_state_bytes(a), _state_bytes(b))
+
+
+def test_checkpoint_resume_is_bit_identical():
+    wl = _thermal_sphere("f32")
+    a = gpu_from_workload(wl)
+    a.step(30)
+    ck = a.save_state()
+    a.step(30)
+    end_a = _state_bytes(a)
+    b = gpu_from_workload(wl)
+    b.load_state(ck)
+    b.step(30)
+    assert np.array_equal(end_a, _state_bytes(b))
+    t, bodies, _, rc = b.observables(0)
+    assert t["step"] == 60 and rc == 0
+
+
+def pore_batch():
+    """Uneven replicas: three pores of different sides with one ellipsoid each, one periodic
+    box with a sphere and one periodic box without bodies (ragged sizes)."""
+    rng = np.random.default_rng(404)
+    reps = []
+    for k, L in enumerate((16, 20, 24)):
+        phi = 1.5 + k
+        req = 0.12 * L
+        b = req / phi ** (1 / 3)
+        a = phi * b
+        offs = W.ellipsoid_beads(a, b, b)
+        m, I = W.solid_body_mass_inertia(1.0, a, b, b)
+        c = np.array([L / 2 + 0.7, L / 2 - 0.4, rng.uniform(0, L)])
+        reps.append(dict(shape=(L, L, L + 3), seed=1000 + k, mask=W.pore_mask(L, L, L + 3, 0.4 * L),
+                         bodies=[W.body_record(offs, m, I, c, quat=W.random_quaternion(rng),
+                                               gamma=W.GAMMA_FREE)]))
+    offs = W.sphere_beads(2.0, 35)
+    m, I = W.solid_body_mass_inertia(1.0, 2.0, 2.0, 2.0)
+    reps.append(dict(shape=(13, 11, 9), seed=77, mask=None,
+                     bodies=[W.body_record(offs, m, I, (12.6, 0.3, 4.4), vel=(1e-3, 0, 0),
+                                           gamma=W.GAMMA_FREE)]))
+    reps.append(dict(shape=(33, 17, 5), seed=78, mask=None, bodies=[]))
+    return dict(name="batch", precision="f32", steps=20,
+                params=W.default_params(kT=4e-5, g_ext=(1e-6, 0.0, 3e-6)), replicas=reps)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_batched_uneven_replicas_match_independent_oracles(precision):
+    wl = pore_batch()
+    wl["precision"] = precision
+    gpu = gpu_from_workload(wl)
+    gpu.set_graph_steps(0)
+    orcs = [oracle_from_workload(wl, r) for r in range(len(wl["replicas"]))]
+    for o in orcs:
+        o.step(12)
+    gpu.step(12)
+    tol_u = 1e-11 if precision == "f64" else 1e-5
+    tol_r = 1e-13 if precision == "f64" else 1e-6
+    for r, o in enumerate(orcs):
+        e = compare(gpu, o, r)
+        print(f"replica {r} {precision}", {k: f"{v:.3g}" for k, v in e.items()
+                                          if isinstance(v, float)}, flush=True)
+        assert e["rc"] == 0 and e["solid_zero"] and e["finite"]
+        assert e["rho"] <= tol_r
+        assert e["u_abs"] <= tol_u * max(e["u_scale"], 1e-12)
+        assert e["body_pos"] <= tol_r and e["body_quat"] <= tol_r
+
+
+def test_batched_replica_equals_standalone_run():
+    """A replica's trajectory does not depend on what it is batched with."""
+    wl = pore_batch()
+    batch = gpu_from_workload(wl)
+    alone = gpu_from_workload(wl, replicas=[1])
+    batch.step(15)
+    alone.step(15)
+    fb = batch.fields(1)
+    fa = alone.fields(0)
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(batch.observables(1)[1][0]["pos"], alone.observables(0)[1][0]["pos"])
+
+
+def test_one_node_box_and_empty_replica():
+    p = lbrb.make_params("f64", kT=1e-4, max_bodies=1, max_beads=1)
+    reps = lbrb.make_replicas([((1, 1, 1), 5), ((2, 3, 1), 6)])
+    sim = lbrb.Simulation(p, reps)
+    sim.set_mask(1, np.ones(6, dtype=np.uint8))   # all boundary: no fluid node at all
+    sim.step(10)
+    t0, _, f0, rc0 = sim.observables(0, fields=True)
+    t1, _, f1, rc1 = sim.observables(1, fields=True)
+    assert rc0 == 0 and rc1 == 0
+    assert abs(t0["mass"] - 1.0) < 1e-14
+    assert t1["mass"] == 0.0 and np.all(f1 == 0.0)
+    assert sim.node_counts(1) == (6, 0)
+    from oracle import pyoracle as po
+    o = po.OracleSim((1, 1, 1), po.make_params(kT=1e-4, seed=5))
+    o.step(10)
+    assert np.abs(sim.populations(0).reshape(19) - o.populations().reshape(19)).max() < 1e-15
+
+
+def test_error_codes():
+    p = lbrb.make_params("f32", max_bodies=1, max_beads=4)
+    reps = lbrb.make_replicas([((8, 8, 8), 1)])
+    sim = lbrb.Simulation(p, reps)
+    # a row with two fluid runs
+    m = np.zeros((8, 8, 8), dtype=np.uint8)
+    m[:, :, 3] = 1
+    with pytest.raises(lbrb.LBError) as e:
+        sim.set_mask(0, m)
+    assert e.value.code == lbrb.LB_ERR_ARG
+    with pytest.raises(lbrb.LBError) as e:
+        sim.add_body(0, np.zeros((5, 3)), 1.0, (1, 1, 1), (4, 4, 4))
+    assert e.value.code == lbrb.LB_ERR_CAPACITY
+    with pytest.raises(lbrb.LBError) as e:
+        sim.add_body(0, np.zeros((1, 3)), -1.0, (1, 1, 1), (4, 4, 4))
+    assert e.value.code == lbrb.LB_ERR_ARG
+    with pytest.raises(lbrb.LBError) as e:
+        sim.add_body(3, np.zeros((1, 3)), 1.0, (1, 1, 1), (4, 4, 4))
+    assert e.value.code == lbrb.LB_ERR_ARG
+    sim.step(1)
+    with pytest.raises(lbrb.LBError) as e:
+        sim.set_mask(0, np.zeros((8, 8, 8), dtype=np.uint8))
+    assert e.value.code == lbrb.LB_ERR_STATE
+    with pytest.raises(lbrb.LBError):
+        sim.set_graph_steps(3)
+    bad = lbrb.make_params("f32", tau_shear=0.5)
+    assert lbrb.lb_workspace_bytes(bad, reps) == 0
+
+
+def test_unstable_run_is_reported():
+    """gamma as specified (20) diverges; the library reports it instead of failing silently."""
+    wl = W.workload(1, gamma=W.GAMMA_AS_SPECIFIED)
+    wl["precision"] = "f32"
+    sim = gpu_from_workload(wl)
+    sim.step(60)
+    t, _, _, rc = sim.observables(0, check=False)
+    assert rc == lbrb.LB_ERR_UNSTABLE
