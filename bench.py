@@ -33,6 +33,11 @@ def parse():
     ap.add_argument("--timing-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--graph-steps", type=int, default=100,
+                    help="steps per HIP-graph replay (0 = eager launches, for profilers)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="before the run, copy a buffer of this many MiB three times with a "
+                         "plain device copy (reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -93,12 +98,20 @@ def main():
     from paper_1604_01829_amd import lbrb
     from paper_1604_01829_amd import workloads as W
 
+    dev = torch.device("cuda:0")
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize(dev)
+        del a, b
     wl = W.workload(2)
     sim = lbrb.simulation_from_workload(wl, precision=args.precision)
     n_nodes, n_fluid = sim.node_counts(0)
     n_beads = sum(b["offsets"].shape[0] for b in wl["replicas"][0]["bodies"])
-    sim.set_graph_steps(100)
-    dev = torch.device("cuda:0")
+    sim.set_graph_steps(args.graph_steps)
 
     sim.step(args.warmup)
     torch.cuda.synchronize(dev)
@@ -138,7 +151,7 @@ def main():
                                "spheres R~U[2,6], thermal kT=4e-5, FP32 shifted populations"
                    if args.precision == "f32" else "same pore workload, FP64 populations",
                    "fluid_nodes": n_fluid, "all_nodes": n_nodes, "beads": n_beads,
-                   "bodies": len(wl["replicas"][0]["bodies"]), "graph_steps": 100,
+                   "bodies": len(wl["replicas"][0]["bodies"]), "graph_steps": args.graph_steps,
                    "finite_after_run": bool(t["finite"]) and rc == 0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

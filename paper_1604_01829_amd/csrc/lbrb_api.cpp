@@ -33,7 +33,7 @@ struct Plan {
     int64_t tiles_cap = 0;    // sum of ceil(nodes / 256)
     int64_t bead_cap = 0, body_cap = 0;
     int gforce_words = 3;     // fixed-point words per node: 3 axes x (1 in FP32, 2 in FP64)
-    size_t off_hdr, off_reps, off_rows, off_rowmap, off_tiles_d, off_tiles_m, off_fa, off_fb,
+    size_t off_hdr, off_reps, off_rows, off_rowinfo, off_tiles_d, off_tiles_m, off_fa, off_fb,
         off_gforce, off_flags, off_bodies, off_bead_off, off_bead_body, off_bead_force,
         off_bead_torque, off_partials, total;
 };
@@ -75,14 +75,14 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
     pl.off_hdr = take(sizeof(DeviceHeader));
     pl.off_reps = take(sizeof(ReplicaDesc) * n);
     pl.off_rows = take(sizeof(RowDesc) * pl.rows_cap);
-    pl.off_rowmap = take(sizeof(int32_t) * pl.rows_cap);
+    pl.off_rowinfo = take(sizeof(RowDesc) * pl.rows_cap);
     pl.off_tiles_d = take(sizeof(NodeTile) * pl.tiles_cap);
     pl.off_tiles_m = take(sizeof(NodeTile) * pl.tiles_cap);
     pl.off_fa = take(real * Q * pl.N);
     pl.off_fb = take(real * Q * pl.N);
     pl.gforce_words = p->precision == LB_PRECISION_F32 ? 3 : 6;
     pl.off_gforce = take(sizeof(long long) * pl.gforce_words * pl.N);
-    pl.off_flags = take(sizeof(uint32_t) * (pl.N / 32 + 1));
+    pl.off_flags = take(pl.N);
     pl.off_bodies = take(sizeof(Body) * std::max<int64_t>(pl.body_cap, 1));
     pl.off_bead_off = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
     pl.off_bead_body = take(sizeof(int32_t) * std::max<int64_t>(pl.bead_cap, 1));
@@ -113,12 +113,12 @@ struct lb_ctx {
     DeviceHeader* hdr = nullptr;
     ReplicaDesc* d_reps = nullptr;
     RowDesc* d_rows = nullptr;
-    int32_t* d_rowmap = nullptr;
+    RowDesc* d_rowinfo = nullptr;
     NodeTile* d_tiles[2] = {nullptr, nullptr};
     void* f[2] = {nullptr, nullptr};
     int cur = 0;
     long long* gforce = nullptr;
-    uint32_t* flags = nullptr;
+    uint8_t* flags = nullptr;
     Body* d_bodies = nullptr;
     double* d_bead_off = nullptr;
     int32_t* d_bead_body = nullptr;
@@ -128,12 +128,13 @@ struct lb_ctx {
     // host mirrors
     std::vector<ReplicaDesc> reps;
     std::vector<RowDesc> rows;
-    std::vector<int32_t> rowmap;
+    std::vector<RowDesc> rowinfo;
     std::vector<NodeTile> tiles[2];
     std::vector<ReplicaHost> rh;
     std::vector<Body> bodies0;          // bodies as added (device copy is authoritative)
     int32_t n_bodies = 0, n_beads = 0;
     int64_t step = 0;
+    bool pose_stale = true;   // body poses must be recomputed before the next step
     std::string err;
     // graphs
     int32_t graph_steps = 100;
@@ -197,7 +198,7 @@ StepArgs<Real> step_args(const lb_ctx* c, int group, int src_buf)
     a.N = c->plan.N;
     a.reps = c->d_reps;
     a.rows = c->d_rows;
-    a.rowmap = c->d_rowmap;
+    a.rowinfo = c->d_rowinfo;
     a.tiles = c->d_tiles[group];
     a.n_tiles = (int32_t)c->tiles[group].size();
     a.thermal = c->p.kT > 0.0 ? 1 : 0;
@@ -340,7 +341,7 @@ void rebuild_tiles(lb_ctx* c)
             // rows of this replica are rows[row_base .. row_base + n_rows)
             int64_t nr = 0;
             for (int64_t k = 0; k < (int64_t)R.ny * R.nz; ++k)
-                if (c->rowmap[R.row_base + k] >= 0) ++nr;
+                if (c->rowinfo[R.row_base + k].len > 0) ++nr;
             last_row = R.row_base + (int)nr - 1;
         }
         for (int64_t b = 0; b < n; b += kNodeBlock) {
@@ -368,8 +369,8 @@ int upload_tables(lb_ctx* c)
     if (!c->rows.empty())
         HIP_TRY(c, hipMemcpyAsync(c->d_rows, c->rows.data(), sizeof(RowDesc) * c->rows.size(),
                                   hipMemcpyHostToDevice, c->stream));
-    if (!c->rowmap.empty())
-        HIP_TRY(c, hipMemcpyAsync(c->d_rowmap, c->rowmap.data(), sizeof(int32_t) * c->rowmap.size(),
+    if (!c->rowinfo.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_rowinfo, c->rowinfo.data(), sizeof(RowDesc) * c->rowinfo.size(),
                                   hipMemcpyHostToDevice, c->stream));
     for (int g = 0; g < 2; ++g)
         if (!c->tiles[g].empty())
@@ -443,13 +444,13 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     c->hdr = (DeviceHeader*)(c->ws + pl.off_hdr);
     c->d_reps = (ReplicaDesc*)(c->ws + pl.off_reps);
     c->d_rows = (RowDesc*)(c->ws + pl.off_rows);
-    c->d_rowmap = (int32_t*)(c->ws + pl.off_rowmap);
+    c->d_rowinfo = (RowDesc*)(c->ws + pl.off_rowinfo);
     c->d_tiles[0] = (NodeTile*)(c->ws + pl.off_tiles_d);
     c->d_tiles[1] = (NodeTile*)(c->ws + pl.off_tiles_m);
     c->f[0] = c->ws + pl.off_fa;
     c->f[1] = c->ws + pl.off_fb;
     c->gforce = (long long*)(c->ws + pl.off_gforce);
-    c->flags = (uint32_t*)(c->ws + pl.off_flags);
+    c->flags = (uint8_t*)(c->ws + pl.off_flags);
     c->d_bodies = (Body*)(c->ws + pl.off_bodies);
     c->d_bead_off = (double*)(c->ws + pl.off_bead_off);
     c->d_bead_body = (int32_t*)(c->ws + pl.off_bead_body);
@@ -460,7 +461,7 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     c->reps.resize(n_replicas);
     c->rh.resize(n_replicas);
     c->rows.assign(pl.rows_cap, RowDesc{0, 0, 0, 0});
-    c->rowmap.assign(pl.rows_cap, -1);
+    c->rowinfo.assign(pl.rows_cap, RowDesc{0, 0, 0, 0});
     int64_t base = 0, row_base = 0;
     for (int r = 0; r < n_replicas; ++r) {
         const lb_replica& in = replicas[r];
@@ -489,7 +490,7 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     const size_t real = is_f32(c) ? sizeof(float) : sizeof(double);
     for (int k = 0; k < 2 && e == hipSuccess; ++k)
         e = hipMemsetAsync(c->f[k], 0, real * Q * pl.N, c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->flags, 0, sizeof(uint32_t) * (pl.N / 32 + 1), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->flags, 0, pl.N, c->stream);
     if (e != hipSuccess) { delete c; return LB_ERR_HIP; }
     int rc = upload_tables(c);
     if (rc == LB_OK) rc = init_fluid(c, -1);
@@ -507,7 +508,7 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
     const int nx = R.nx, ny = R.ny, nz = R.nz;
     bool any_solid = false;
     std::vector<RowDesc> rows;
-    std::vector<int32_t> rmap((size_t)ny * nz, -1);
+    std::vector<RowDesc> info((size_t)ny * nz, RowDesc{0, 0, 0, 0});
     int64_t start = 0;
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y) {
@@ -525,18 +526,18 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
             d.xlo = xlo;
             d.len = xhi - xlo + 1;
             d.yz = y | (z << 16);
-            rmap[(size_t)y + (size_t)ny * z] = R.row_base + (int32_t)rows.size();
+            info[(size_t)y + (size_t)ny * z] = d;
             rows.push_back(d);
             start += d.len;
         }
     // rows of this replica go to rows[row_base ...]; clear the old ones first
     for (int64_t k = 0; k < (int64_t)ny * nz; ++k) {
-        c->rowmap[R.row_base + k] = -1;
+        c->rowinfo[R.row_base + k] = RowDesc{0, 0, 0, 0};
         c->rows[R.row_base + k] = RowDesc{0, 0, 0, 0};
     }
     if (any_solid) {
         for (size_t k = 0; k < rows.size(); ++k) c->rows[R.row_base + k] = rows[k];
-        for (int64_t k = 0; k < (int64_t)ny * nz; ++k) c->rowmap[R.row_base + k] = rmap[k];
+        for (int64_t k = 0; k < (int64_t)ny * nz; ++k) c->rowinfo[R.row_base + k] = info[k];
         R.masked = 1;
         R.n_fluid = start;
     } else {
@@ -599,6 +600,7 @@ int rb_add_raspberry(lb_ctx* c, int32_t replica, const double* offs, int32_t n_b
     c->bodies0.push_back(B);
     c->n_bodies += 1;
     c->n_beads += n_beads;
+    c->pose_stale = true;
     destroy_graphs(c);
     return LB_OK;
 }
@@ -609,6 +611,11 @@ int lb_rb_step(lb_ctx* c, int32_t n_steps)
     if (n_steps < 0) return fail(c, LB_ERR_ARG, "negative step count");
     int32_t left = n_steps;
     const bool use_graph = c->graph_steps > 0 && !c->timing;
+    if (c->pose_stale && n_steps > 0) {
+        launch_body_predict(c->d_bodies, c->n_bodies, c->stream);
+        HIP_TRY(c, hipGetLastError());
+        c->pose_stale = false;
+    }
     while (use_graph && left >= c->graph_steps) {
         if (!c->gexec[c->cur]) {
             int rc = build_graph(c, c->cur);
@@ -776,6 +783,7 @@ int lb_load_state(lb_ctx* c, const void* dev_buf, size_t bytes)
                               c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->step = (int64_t)h[1];
+    c->pose_stale = true;
     return LB_OK;
 }
 

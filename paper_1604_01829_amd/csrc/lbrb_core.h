@@ -257,6 +257,9 @@ struct Body {
     int32_t first_bead, n_beads;     // global bead range
     int32_t first_bead_in_replica;   // index of the first bead within its replica
     int32_t pad;
+    // pose of the coming step: the state after the first half kick, the drift and the
+    // rotation, with its rotation matrix and the lab-frame angular velocity
+    double ppos[3], pquat[4], pvel[3], pomega[3], prot[9], pomega_lab[3];
 };
 
 LBRB_HD void quat_to_matrix(const double q[4], double m[3][3])
@@ -308,6 +311,18 @@ LBRB_HD void first_half(const Body& b, double pos[3], double quat[4], double vel
         n[3] = q[0] * p[3] + q[1] * p[2] - q[2] * p[1] + q[3] * p[0];
         const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2] + n[3] * n[3]);
         for (int a = 0; a < 4; ++a) quat[a] = n[a] / nn;
+    }
+}
+
+// fill the pose of the coming step from the state of a body
+LBRB_HD void predict_pose(Body& b)
+{
+    first_half(b, b.ppos, b.pquat, b.pvel, b.pomega);
+    double m[3][3];
+    quat_to_matrix(b.pquat, m);
+    for (int r = 0; r < 3; ++r) {
+        for (int k = 0; k < 3; ++k) b.prot[3 * r + k] = m[r][k];
+        b.pomega_lab[r] = m[r][0] * b.pomega[0] + m[r][1] * b.pomega[1] + m[r][2] * b.pomega[2];
     }
 }
 

@@ -74,9 +74,9 @@ __device__ __forceinline__ void locate(const ReplicaDesc& R, const RowDesc* __re
 // opposite population of the node itself (halfway bounce-back).
 template <typename Real, bool MASKED>
 __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
-                                     const ReplicaDesc& R, const RowDesc* __restrict__ rows,
-                                     const int32_t* __restrict__ rowmap, int x, int y, int z,
-                                     int64_t local, const RowDesc& self, Real d[Q])
+                                     const ReplicaDesc& R, const RowDesc* __restrict__ rowinfo,
+                                     int x, int y, int z, int64_t local, const RowDesc& self,
+                                     Real d[Q])
 {
     const int64_t own = R.base + local;
     if constexpr (MASKED) {
@@ -89,13 +89,8 @@ __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
                 st[r9] = self.start; lo[r9] = self.xlo; ln[r9] = self.len;
             } else {
                 const int yy = wrap1(y - cy, R.ny), zz = wrap1(z - cz, R.nz);
-                const int32_t rm = rowmap[R.row_base + yy + R.ny * zz];
-                if (rm >= 0) {
-                    const RowDesc rd = rows[rm];
-                    st[r9] = rd.start; lo[r9] = rd.xlo; ln[r9] = rd.len;
-                } else {
-                    st[r9] = 0; lo[r9] = 0; ln[r9] = 0;
-                }
+                const RowDesc rd = rowinfo[R.row_base + yy + R.ny * zz];
+                st[r9] = rd.start; lo[r9] = rd.xlo; ln[r9] = rd.len;
             }
         }
 #pragma unroll
@@ -160,10 +155,19 @@ __device__ __forceinline__ Real take_spread_force(long long* gforce, int64_t N, 
 
 // ------------------------------------------------------------------ node update
 
+// Workgroups are dealt round-robin to the 8 XCDs (separate L2 caches).  Give each XCD a
+// contiguous run of tiles so that the halo lines shared by neighbouring tiles are mostly
+// reused from the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, xcd = b & 7, k = b >> 3;
+    return xcd * q + min(xcd, r) + k;
+}
+
 template <typename Real, bool MASKED, bool THERMAL>
 __global__ __launch_bounds__(kNodeBlock) void node_update_kernel(const StepArgs<Real> a)
 {
-    const NodeTile t = a.tiles[blockIdx.x];
+    const NodeTile t = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
     if ((int)threadIdx.x >= t.count) return;
     const ReplicaDesc R = a.reps[t.replica];
     const int64_t local = t.begin + threadIdx.x;
@@ -172,17 +176,14 @@ __global__ __launch_bounds__(kNodeBlock) void node_update_kernel(const StepArgs<
     locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
 
     Real d[Q];
-    pull<Real, MASKED>(a.src, a.N, R, a.rows, a.rowmap, x, y, z, local, self, d);
+    pull<Real, MASKED>(a.src, a.N, R, a.rowinfo, x, y, z, local, self, d);
 
     const int64_t g = R.base + local;
     Real F[3] = {a.gext[0], a.gext[1], a.gext[2]};
-    const uint32_t word = a.flags[g >> 5];
-    if (word) {
-        if ((word >> (g & 31)) & 1u) {
+    if (a.flags[g]) {
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) F[ax] += take_spread_force<Real>(a.gforce, a.N, ax, g);
-        }
-        if ((g & 31) == 0) a.flags[g >> 5] = 0u;
+        for (int ax = 0; ax < 3; ++ax) F[ax] += take_spread_force<Real>(a.gforce, a.N, ax, g);
+        a.flags[g] = 0;
     }
 
     if constexpr (THERMAL) {
@@ -221,17 +222,15 @@ void launch_node_update(const StepArgs<Real>& a, bool masked, hipStream_t s)
 // ------------------------------------------------------------------ bead coupling
 
 // local index of node (x,y,z) of a replica, or -1 for a boundary node
-__device__ __forceinline__ int64_t node_local(const ReplicaDesc& R, const RowDesc* __restrict__ rows,
-                                              const int32_t* __restrict__ rowmap, int x, int y,
+__device__ __forceinline__ int64_t node_local(const ReplicaDesc& R,
+                                              const RowDesc* __restrict__ rowinfo, int x, int y,
                                               int z, RowDesc& self)
 {
     if (!R.masked) {
         self.start = 0; self.xlo = 0; self.len = R.nx; self.yz = 0;
         return x + (int64_t)R.nx * (y + (int64_t)R.ny * z);
     }
-    const int32_t rm = rowmap[R.row_base + y + R.ny * z];
-    if (rm < 0) return -1;
-    self = rows[rm];
+    self = rowinfo[R.row_base + y + R.ny * z];
     const int off = x - self.xlo;
     if ((unsigned)off >= (unsigned)self.len) return -1;
     return self.start + off;
@@ -257,24 +256,21 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
     const int bead = tid >> 3, corner = tid & 7;
     if (bead >= c.n_beads) return;   // the 8 lanes of a bead leave together
     const int bi = c.bead_body[bead];
-    const Body B = c.bodies[bi];
-    double pos[3], q[4], vel[3], om[3];
-    first_half(B, pos, q, vel, om);
-    double M[3][3];
-    quat_to_matrix(q, M);
+    const Body& B = c.bodies[bi];
     const double off[3] = {c.bead_off[3 * bead], c.bead_off[3 * bead + 1], c.bead_off[3 * bead + 2]};
+    // bead position r = R + Q b and velocity v = V + w_lab x (Q b) from the step's pose
     double dv[3], r[3], v[3];
     for (int ax = 0; ax < 3; ++ax) {
-        dv[ax] = M[ax][0] * off[0] + M[ax][1] * off[1] + M[ax][2] * off[2];
-        r[ax] = pos[ax] + dv[ax];
+        dv[ax] = B.prot[3 * ax] * off[0] + B.prot[3 * ax + 1] * off[1] + B.prot[3 * ax + 2] * off[2];
+        r[ax] = B.ppos[ax] + dv[ax];
     }
     if (B.fixed) {
         v[0] = v[1] = v[2] = 0.0;
     } else {
-        const double wb[3] = {om[1] * off[2] - om[2] * off[1], om[2] * off[0] - om[0] * off[2],
-                              om[0] * off[1] - om[1] * off[0]};
-        for (int ax = 0; ax < 3; ++ax)
-            v[ax] = vel[ax] + M[ax][0] * wb[0] + M[ax][1] * wb[1] + M[ax][2] * wb[2];
+        const double* w = B.pomega_lab;
+        v[0] = B.pvel[0] + (w[1] * dv[2] - w[2] * dv[1]);
+        v[1] = B.pvel[1] + (w[2] * dv[0] - w[0] * dv[2]);
+        v[2] = B.pvel[2] + (w[0] * dv[1] - w[1] * dv[0]);
     }
     const ReplicaDesc R = a.reps[B.replica];
 
@@ -292,14 +288,14 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
                      (oz ? fr[2] : 1.0 - fr[2]);
 
     RowDesc self;
-    const int64_t local = node_local(R, a.rows, a.rowmap, px, py, pz, self);
+    const int64_t local = node_local(R, a.rowinfo, px, py, pz, self);
     double wu[3] = {0.0, 0.0, 0.0};
     if (local >= 0) {
         Real d[Q];
         if (ANY_MASKED && R.masked)
-            pull<Real, true>(a.src, a.N, R, a.rows, a.rowmap, px, py, pz, local, self, d);
+            pull<Real, true>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
         else
-            pull<Real, false>(a.src, a.N, R, a.rows, a.rowmap, px, py, pz, local, self, d);
+            pull<Real, false>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
         Real drho, j[3];
         density_momentum<Real>(d, drho, j);
         const double rho = (double)a.cp.rho0 + (double)drho;
@@ -332,7 +328,7 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
             overflow |= bad;
             add_spread_force<Real>(a.gforce, a.N, ax, g, bad ? 0.0 : val);
         }
-        atomicOr(a.flags + (g >> 5), 1u << (g & 31));
+        a.flags[g] = 1;   // every writer stores the same value
         if (overflow) atomicOr(&c.hdr->err_flags, 1u);
     }
     if (corner == 0) {
@@ -381,25 +377,45 @@ __global__ __launch_bounds__(256) void body_finish_kernel(Body* __restrict__ bod
         F[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
         T[k] = (part[0][3 + k] + part[1][3 + k]) + (part[2][3 + k] + part[3][3 + k]);
     }
-    double pos[3], q[4], vel[3], om[3];
-    first_half(B, pos, q, vel, om);
-    double M[3][3];
-    quat_to_matrix(q, M);
-    double Tb[3];
-    for (int ax = 0; ax < 3; ++ax) Tb[ax] = M[0][ax] * T[0] + M[1][ax] * T[1] + M[2][ax] * T[2];
+    // second half kick with this step's force and body-frame torque, from the step's pose
+    Body* o = bodies + b;
+    double vel[3], om[3], Tb[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        vel[ax] = B.pvel[ax];
+        om[ax] = B.pomega[ax];
+        Tb[ax] = B.prot[ax] * T[0] + B.prot[3 + ax] * T[1] + B.prot[6 + ax] * T[2];
+    }
     if (!B.fixed) {
         for (int ax = 0; ax < 3; ++ax) vel[ax] += 0.5 * F[ax] / B.mass;
         half_kick(om, B.inertia, Tb);
     }
-    Body* o = bodies + b;
+    Body nb = B;
     for (int ax = 0; ax < 3; ++ax) {
-        o->pos[ax] = pos[ax];
-        o->vel[ax] = vel[ax];
-        o->omega[ax] = om[ax];
-        o->force[ax] = F[ax];
-        o->torque[ax] = Tb[ax];
+        nb.pos[ax] = B.ppos[ax];
+        nb.vel[ax] = vel[ax];
+        nb.omega[ax] = om[ax];
+        nb.force[ax] = F[ax];
+        nb.torque[ax] = Tb[ax];
     }
-    for (int k = 0; k < 4; ++k) o->quat[k] = q[k];
+    for (int k = 0; k < 4; ++k) nb.quat[k] = B.pquat[k];
+    predict_pose(nb);
+    *o = nb;
+}
+
+__global__ void body_predict_kernel(Body* __restrict__ bodies, int32_t n)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    Body B = bodies[b];
+    predict_pose(B);
+    bodies[b] = B;
+}
+
+void launch_body_predict(Body* bodies, int32_t n_bodies, hipStream_t s)
+{
+    if (n_bodies <= 0) return;
+    hipLaunchKernelGGL(body_predict_kernel, dim3((n_bodies + 63) / 64), dim3(64), 0, s, bodies,
+                       n_bodies);
 }
 
 void launch_body_finish(Body* bodies, const double* bead_force, const double* bead_torque,
@@ -462,7 +478,7 @@ __global__ __launch_bounds__(kNodeBlock) void observe_kernel(const StepArgs<Real
         RowDesc self;
         locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
         Real d[Q];
-        pull<Real, MASKED>(a.src, a.N, R, a.rows, a.rowmap, x, y, z, local, self, d);
+        pull<Real, MASKED>(a.src, a.N, R, a.rowinfo, x, y, z, local, self, d);
         Real drho, j[3];
         density_momentum<Real>(d, drho, j);
         const int64_t dense = x + (int64_t)R.nx * (y + (int64_t)R.ny * z);

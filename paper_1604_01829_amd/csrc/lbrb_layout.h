@@ -3,7 +3,9 @@
 // Fluid storage ("compact rows").  Each replica keeps only its fluid nodes.  A (y,z) row of a
 // replica holds at most one contiguous run of fluid nodes [xlo, xlo+len); the runs of all
 // non-empty rows are stored back to back in (z, y) order, so node (x,y,z) of the run of row
-// r lives at local index rows[r].start + x - xlo.  A replica without boundary nodes is
+// (y,z) lives at local index start + x - xlo.  rowinfo[row_base + y + ny z] holds
+// (start, xlo, len) of every row (len = 0 for a row without fluid), so a neighbour lookup is
+// one load; rows[] lists the non-empty rows in storage order for the thread -> node map.  A replica without boundary nodes is
 // "dense": every row is full and the local index is x + nx (y + ny z), computed without
 // tables.  Populations are structure-of-arrays: population i of global node g sits at
 // f[i * N + g], N = total padded node count, g = replica base + local index; each replica's
@@ -29,7 +31,7 @@ struct ReplicaDesc {
     int64_t base;           // global index of local node 0
     int64_t n_nodes;        // nx*ny*nz
     int64_t n_fluid;
-    int32_t row_base;       // first entry of this replica in rows[] and rowmap[]
+    int32_t row_base;       // first entry of this replica in rows[] and rowinfo[]
     uint32_t key0, key1;    // Philox key (seed)
     int32_t pad;
     double inv_nx, inv_ny;  // for exact index division
@@ -37,7 +39,7 @@ struct ReplicaDesc {
 
 struct RowDesc {
     int32_t start;          // local index of the first fluid node of the row
-    int32_t xlo, len;       // fluid run [xlo, xlo+len)
+    int32_t xlo, len;       // fluid run [xlo, xlo+len); len = 0: no fluid in the row
     int32_t yz;             // y | z << 16
 };
 
@@ -60,13 +62,13 @@ struct StepArgs {
     Real* dst;              // post-collision populations of this step
     int64_t N;              // stride between populations
     const ReplicaDesc* reps;
-    const RowDesc* rows;
-    const int32_t* rowmap;
+    const RowDesc* rows;      // non-empty rows in storage order
+    const RowDesc* rowinfo;   // every row, indexed by row_base + y + ny z
     const NodeTile* tiles;
     int32_t n_tiles;
     int32_t thermal;
     long long* gforce;      // fixed-point spread force, [word][axis][node] (1 or 2 words)
-    uint32_t* flags;        // 1 bit per node: spread force present
+    uint8_t* flags;         // 1 byte per node: spread force present
     CollideParams<Real> cp;
     Real gext[3];
     const int64_t* step_ptr;  // if set, step = *step_ptr + step_arg
@@ -91,6 +93,7 @@ void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, bool any_masked
                    hipStream_t s);
 void launch_body_finish(Body* bodies, const double* bead_force, const double* bead_torque,
                         int32_t n_bodies, hipStream_t s);
+void launch_body_predict(Body* bodies, int32_t n_bodies, hipStream_t s);
 void launch_set_step(int64_t* step_ptr, int64_t value, hipStream_t s);
 template <typename Real>
 void launch_init_equilibrium(Real* f, int64_t N, const ReplicaDesc* reps, const NodeTile* tiles,
