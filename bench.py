@@ -9,10 +9,10 @@ and second half kick, fused collide-and-stream of every fluid node.  Inputs are 
 and resident in HBM before timing; the steps run as HIP-graph replays.
 
 Prints one JSON line.  `value` = fluid-node updates per second / 1e6 (MLUPS) over the timed
-steps.  `roofline` is for the node-update kernel: algorithmic bytes 152 B (FP32) per fluid
-node (19 populations read + written) divided by its mean duration from HIP events
-recorded around each launch on the library's stream, in a separate eager window of the same
-run.  `cpu_baseline` times the FP64 CPU oracle on a few steps of the same box.
+steps.  `roofline` is for the dominant kernel, node_step (the update of every fluid node; its
+few leading workgroups finish the bodies): algorithmic bytes 152 B (FP32) per fluid node (19
+populations read + written) divided by its mean duration from HIP events recorded around each
+launch on the library's stream, in a separate eager window of the same run.  `cpu_baseline` times the FP64 CPU oracle on a few steps of the same box.
 """
 import argparse
 import json
@@ -127,11 +127,13 @@ def main():
     sim.step(args.timing_steps)
     kt = sim.kernel_times()
     sim.set_timing(False)
+    # node_step: every fluid node's update (its leading workgroups finish the bodies)
     node_s = kt["node_ms"] / max(1, kt["node_launches"]) / 1e3
+    # couple: bead coupling and force spreading
     couple_s = kt["couple_ms"] / max(1, kt["couple_launches"]) / 1e3
     bpn = algorithmic_bytes_per_node(args.precision)
     achieved = bpn * n_fluid / node_s / 1e9
-    tag = f"node_update_{args.precision}_pore128x128x256"
+    tag = f"node_step_{args.precision}_pore128x128x256"
     traffic = traffic_from_profiles(tag)
 
     out = {
@@ -155,7 +157,7 @@ def main():
                    "finite_after_run": bool(t["finite"]) and rc == 0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "node_update",
+                     "traffic": traffic, "kernel": "node_step",
                      "algorithmic_bytes_per_launch": bpn * n_fluid,
                      "mean_launch_us": round(node_s * 1e6, 3),
                      "couple_mean_launch_us": round(couple_s * 1e6, 3)},

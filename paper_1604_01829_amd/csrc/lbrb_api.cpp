@@ -84,8 +84,8 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
     pl.off_gforce = take(sizeof(long long) * pl.gforce_words * pl.N);
     pl.off_flags = take(pl.N);
     pl.off_bodies = take(sizeof(Body) * std::max<int64_t>(pl.body_cap, 1));
-    pl.off_bead_off = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
-    pl.off_bead_body = take(sizeof(int32_t) * std::max<int64_t>(pl.bead_cap, 1));
+    pl.off_bead_off = take(sizeof(Bead) * std::max<int64_t>(pl.bead_cap, 1));
+    pl.off_bead_body = 0;
     pl.off_bead_force = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
     pl.off_bead_torque = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
     pl.off_partials = take(sizeof(double) * 5 * pl.tiles_cap);
@@ -120,8 +120,7 @@ struct lb_ctx {
     long long* gforce = nullptr;
     uint8_t* flags = nullptr;
     Body* d_bodies = nullptr;
-    double* d_bead_off = nullptr;
-    int32_t* d_bead_body = nullptr;
+    Bead* d_beads = nullptr;
     double* d_bead_force = nullptr;
     double* d_bead_torque = nullptr;
     double* d_partials = nullptr;
@@ -136,14 +135,13 @@ struct lb_ctx {
     int64_t step = 0;
     bool pose_stale = true;   // body poses must be recomputed before the next step
     std::string err;
-    // graphs
+    // graphs are captured on a private stream and replayed on the caller's
     int32_t graph_steps = 100;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    hipStream_t cap_stream = nullptr, side_stream = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t cap_stream = nullptr;
     // timing
     bool timing = false;
-    std::vector<EventPair> ev_node, ev_couple, ev_pool;
+    std::vector<EventPair> ev_node, ev_couple_t, ev_pool;
 };
 
 namespace {
@@ -215,8 +213,7 @@ CoupleArgs couple_args(const lb_ctx* c)
 {
     CoupleArgs ca{};
     ca.bodies = c->d_bodies;
-    ca.bead_off = c->d_bead_off;
-    ca.bead_body = c->d_bead_body;
+    ca.beads = c->d_beads;
     ca.bead_force = c->d_bead_force;
     ca.bead_torque = c->d_bead_torque;
     ca.n_beads = c->n_beads;
@@ -240,48 +237,38 @@ EventPair get_pair(lb_ctx* c)
     return e;
 }
 
-// Enqueue one step.  In capture mode (step_ptr set) the kernels read the step counter from
-// device memory; body_finish runs on a side branch in parallel with the node update.
-// Returns the first HIP error of the enqueued calls.
+// Enqueue one step on stream s: the coupling (with bodies), then the node update of each
+// tile group; the first node launch also finishes the bodies.  In capture mode the kernels
+// read the step counter from device memory (step_ptr + step_arg).  Returns the first HIP
+// error of the enqueued calls.
 template <typename Real>
 hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* step_ptr,
                         int64_t step_arg, bool capture)
 {
     hipError_t err = hipSuccess;
     auto note = [&](hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; };
-    StepArgs<Real> a0 = step_args<Real>(c, 0, src_buf);
-    StepArgs<Real> a1 = step_args<Real>(c, 1, src_buf);
-    a0.step_ptr = a1.step_ptr = step_ptr;
-    a0.step_arg = a1.step_arg = step_arg;
+    StepArgs<Real> ag[2] = {step_args<Real>(c, 0, src_buf), step_args<Real>(c, 1, src_buf)};
+    for (auto& a : ag) { a.step_ptr = step_ptr; a.step_arg = step_arg; }
     const bool timed = c->timing && !capture;
     if (c->n_beads > 0) {
         EventPair e{};
         if (timed) { e = get_pair(c); note(hipEventRecord(e.a, s)); }
-        launch_couple<Real>(any_masked(c) ? a1 : a0, couple_args(c), any_masked(c), s);
+        launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], couple_args(c), s);
         note(hipGetLastError());
-        if (timed) { note(hipEventRecord(e.b, s)); c->ev_couple.push_back(e); }
-        if (capture) {
-            note(hipEventRecord(c->ev_fork, s));
-            note(hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
-            launch_body_finish(c->d_bodies, c->d_bead_force, c->d_bead_torque, c->n_bodies,
-                               c->side_stream);
-            note(hipGetLastError());
-            note(hipEventRecord(c->ev_join, c->side_stream));
-        } else {
-            launch_body_finish(c->d_bodies, c->d_bead_force, c->d_bead_torque, c->n_bodies, s);
-            note(hipGetLastError());
-        }
+        if (timed) { note(hipEventRecord(e.b, s)); c->ev_couple_t.push_back(e); }
     }
+    bool finished = c->n_bodies == 0;
     for (int g = 0; g < 2; ++g) {
-        StepArgs<Real>& a = g == 0 ? a0 : a1;
-        if (a.n_tiles == 0) continue;
+        const bool last = g == 1 || ag[1].n_tiles == 0;
+        if (ag[g].n_tiles == 0 && !(last && !finished)) continue;
         EventPair e{};
         if (timed) { e = get_pair(c); note(hipEventRecord(e.a, s)); }
-        launch_node_update<Real>(a, g == 1, s);
+        launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, finished ? nullptr : c->d_bodies,
+                               c->d_bead_force, c->d_bead_torque, c->n_bodies, s);
         note(hipGetLastError());
         if (timed) { note(hipEventRecord(e.b, s)); c->ev_node.push_back(e); }
+        finished = true;
     }
-    if (capture && c->n_beads > 0) note(hipStreamWaitEvent(s, c->ev_join, 0));
     return err;
 }
 
@@ -293,16 +280,12 @@ void destroy_graphs(lb_ctx* c)
 
 int build_graph(lb_ctx* c, int parity)
 {
-    if (!c->cap_stream) {
+    if (!c->cap_stream)
         HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-        HIP_TRY(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
-        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-    }
     hipGraph_t graph = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int buf = parity;
     hipError_t cap_err = hipSuccess;
+    int buf = parity;
     for (int k = 0; k < c->graph_steps && cap_err == hipSuccess; ++k) {
         cap_err = is_f32(c) ? enqueue_step<float>(c, c->cap_stream, buf, &c->hdr->step, k, true)
                             : enqueue_step<double>(c, c->cap_stream, buf, &c->hdr->step, k, true);
@@ -349,12 +332,13 @@ void rebuild_tiles(lb_ctx* c)
             t.replica = r;
             t.begin = b;
             t.count = (int32_t)std::min<int64_t>(kNodeBlock, n - b);
+            const int64_t e = b + t.count - 1;   // last local index of the tile
             if (R.masked) {
                 while (row < last_row && c->rows[row + 1].start <= b) ++row;
-                int hi = row;
-                while (hi < last_row && c->rows[hi + 1].start <= b + t.count - 1) ++hi;
+                int rh = row;
+                while (rh < last_row && c->rows[rh + 1].start <= e) ++rh;
                 t.row_lo = row;
-                t.row_hi = hi;
+                t.row_hi = rh;
             }
             T.push_back(t);
         }
@@ -405,6 +389,16 @@ int init_fluid(lb_ctx* c, int replica)
     return LB_OK;
 }
 
+BodyBox body_box(const ReplicaDesc& R)
+{
+    BodyBox x{};
+    x.nx = R.nx; x.ny = R.ny; x.nz = R.nz; x.masked = R.masked;
+    x.base = R.base;
+    x.row_base = R.row_base;
+    x.key0 = R.key0; x.key1 = R.key1;
+    return x;
+}
+
 bool check_replica(lb_ctx* c, int32_t r)
 {
     if (r < 0 || r >= c->n_rep) { c->err = "replica index out of range"; return false; }
@@ -452,8 +446,7 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     c->gforce = (long long*)(c->ws + pl.off_gforce);
     c->flags = (uint8_t*)(c->ws + pl.off_flags);
     c->d_bodies = (Body*)(c->ws + pl.off_bodies);
-    c->d_bead_off = (double*)(c->ws + pl.off_bead_off);
-    c->d_bead_body = (int32_t*)(c->ws + pl.off_bead_body);
+    c->d_beads = (Bead*)(c->ws + pl.off_bead_off);
     c->d_bead_force = (double*)(c->ws + pl.off_bead_force);
     c->d_bead_torque = (double*)(c->ws + pl.off_bead_torque);
     c->d_partials = (double*)(c->ws + pl.off_partials);
@@ -477,6 +470,7 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
         R.key1 = (uint32_t)(in.seed >> 32);
         R.inv_nx = 1.0 / in.nx;
         R.inv_ny = 1.0 / in.ny;
+
         base += pad_nodes(R.n_nodes);
         row_base += (int64_t)in.ny * in.nz;
     }
@@ -491,10 +485,10 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     for (int k = 0; k < 2 && e == hipSuccess; ++k)
         e = hipMemsetAsync(c->f[k], 0, real * Q * pl.N, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->flags, 0, pl.N, c->stream);
-    if (e != hipSuccess) { delete c; return LB_ERR_HIP; }
+    if (e != hipSuccess) { lb_destroy(c); return LB_ERR_HIP; }
     int rc = upload_tables(c);
     if (rc == LB_OK) rc = init_fluid(c, -1);
-    if (rc != LB_OK) { delete c; return rc; }
+    if (rc != LB_OK) { lb_destroy(c); return rc; }
     *out = c;
     return LB_OK;
 }
@@ -548,6 +542,14 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
     rebuild_tiles(c);
     int rc = upload_tables(c);
     if (rc != LB_OK) return rc;
+    // bodies already in this replica carry a copy of its geometry (no step has run yet, so
+    // the host records are still the bodies' state)
+    for (int32_t b : c->rh[replica].bodies) {
+        c->bodies0[b].box = body_box(R);
+        HIP_TRY(c, hipMemcpyAsync(c->d_bodies + b, &c->bodies0[b], sizeof(Body),
+                                  hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return init_fluid(c, replica);
 }
 
@@ -587,13 +589,17 @@ int rb_add_raspberry(lb_ctx* c, int32_t replica, const double* offs, int32_t n_b
     int32_t in_rep = 0;
     for (int32_t b : c->rh[replica].bodies) in_rep += c->bodies0[b].n_beads;
     B.first_bead_in_replica = in_rep;
-    std::vector<int32_t> owner(n_beads, c->n_bodies);
+    B.box = body_box(c->reps[replica]);
+    std::vector<Bead> beads(n_beads);
+    for (int k = 0; k < n_beads; ++k) {
+        for (int a = 0; a < 3; ++a) beads[k].off[a] = offs[3 * k + a];
+        beads[k].body = c->n_bodies;
+        beads[k].pad = 0;
+    }
     HIP_TRY(c, hipMemcpyAsync(c->d_bodies + c->n_bodies, &B, sizeof(Body), hipMemcpyHostToDevice,
                               c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->d_bead_off + 3 * (int64_t)c->n_beads, offs,
-                              sizeof(double) * 3 * n_beads, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->d_bead_body + c->n_beads, owner.data(),
-                              sizeof(int32_t) * n_beads, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_beads + c->n_beads, beads.data(), sizeof(Bead) * n_beads,
+                              hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (body_id) *body_id = (int32_t)c->rh[replica].bodies.size();
     c->rh[replica].bodies.push_back(c->n_bodies);
@@ -609,13 +615,14 @@ int lb_rb_step(lb_ctx* c, int32_t n_steps)
 {
     if (!c) return LB_ERR_ARG;
     if (n_steps < 0) return fail(c, LB_ERR_ARG, "negative step count");
-    int32_t left = n_steps;
-    const bool use_graph = c->graph_steps > 0 && !c->timing;
-    if (c->pose_stale && n_steps > 0) {
-        launch_body_predict(c->d_bodies, c->n_bodies, c->stream);
+    if (n_steps == 0) return LB_OK;
+    if (c->pose_stale) {
+        launch_body_predict(c->d_bodies, c->n_bodies, (int)(c->step & 1), c->stream);
         HIP_TRY(c, hipGetLastError());
         c->pose_stale = false;
     }
+    int32_t left = n_steps;
+    const bool use_graph = c->graph_steps > 0 && !c->timing;
     while (use_graph && left >= c->graph_steps) {
         if (!c->gexec[c->cur]) {
             int rc = build_graph(c, c->cur);
@@ -801,9 +808,9 @@ int lb_set_timing(lb_ctx* c, int32_t enable)
     if (!c) return LB_ERR_ARG;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     for (auto& e : c->ev_node) c->ev_pool.push_back(e);
-    for (auto& e : c->ev_couple) c->ev_pool.push_back(e);
+    for (auto& e : c->ev_couple_t) c->ev_pool.push_back(e);
     c->ev_node.clear();
-    c->ev_couple.clear();
+    c->ev_couple_t.clear();
     c->timing = enable != 0;
     return LB_OK;
 }
@@ -815,11 +822,11 @@ int lb_kernel_times(lb_ctx* c, double* node_ms, int64_t* node_n, double* couple_
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     double tn = 0, tc = 0;
     for (auto& e : c->ev_node) { float ms = 0; HIP_TRY(c, hipEventElapsedTime(&ms, e.a, e.b)); tn += ms; }
-    for (auto& e : c->ev_couple) { float ms = 0; HIP_TRY(c, hipEventElapsedTime(&ms, e.a, e.b)); tc += ms; }
+    for (auto& e : c->ev_couple_t) { float ms = 0; HIP_TRY(c, hipEventElapsedTime(&ms, e.a, e.b)); tc += ms; }
     if (node_ms) *node_ms = tn;
     if (node_n) *node_n = (int64_t)c->ev_node.size();
     if (couple_ms) *couple_ms = tc;
-    if (couple_n) *couple_n = (int64_t)c->ev_couple.size();
+    if (couple_n) *couple_n = (int64_t)c->ev_couple_t.size();
     return LB_OK;
 }
 
@@ -837,15 +844,12 @@ void lb_destroy(lb_ctx* c)
     (void)hipStreamSynchronize(c->stream);
     destroy_graphs(c);
     for (auto& e : c->ev_node) c->ev_pool.push_back(e);
-    for (auto& e : c->ev_couple) c->ev_pool.push_back(e);
+    for (auto& e : c->ev_couple_t) c->ev_pool.push_back(e);
     for (auto& e : c->ev_pool) {
         if (e.a) (void)hipEventDestroy(e.a);
         if (e.b) (void)hipEventDestroy(e.b);
     }
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
     delete c;
 }
 

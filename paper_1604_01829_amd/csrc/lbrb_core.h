@@ -249,6 +249,24 @@ LBRB_HD void density_momentum(const Real d[Q], Real& drho, Real j[3])
 }
 
 // ------------------------------------------------------------------ rigid bodies (FP64)
+// Pose of a body for one step: its state after the first half kick, the drift and the
+// rotation, with the rotation matrix and the lab-frame angular velocity.
+struct Pose {
+    double pos[3], quat[4], vel[3], omega[3];
+    double rot[9];
+    double omega_lab[3];
+};
+
+// Geometry of the replica a body lives in, copied into the body record so that the
+// coupling reaches it without another dependent load.
+struct BodyBox {
+    int32_t nx, ny, nz, masked;
+    int64_t base;                    // global index of the replica's local node 0
+    int32_t row_base;
+    uint32_t key0, key1;             // Philox key of the replica
+    int32_t pad;
+};
+
 struct Body {
     double pos[3], quat[4], vel[3], omega[3];
     double force[3], torque[3];      // last step's sum (lab) and body-frame torque
@@ -257,9 +275,8 @@ struct Body {
     int32_t first_bead, n_beads;     // global bead range
     int32_t first_bead_in_replica;   // index of the first bead within its replica
     int32_t pad;
-    // pose of the coming step: the state after the first half kick, the drift and the
-    // rotation, with its rotation matrix and the lab-frame angular velocity
-    double ppos[3], pquat[4], pvel[3], pomega[3], prot[9], pomega_lab[3];
+    BodyBox box;
+    Pose pose[2];                    // the pose used by step n is pose[n & 1]
 };
 
 LBRB_HD void quat_to_matrix(const double q[4], double m[3][3])
@@ -314,15 +331,15 @@ LBRB_HD void first_half(const Body& b, double pos[3], double quat[4], double vel
     }
 }
 
-// fill the pose of the coming step from the state of a body
-LBRB_HD void predict_pose(Body& b)
+// Fill a pose from the state of a body (the first half of a step).
+LBRB_HD void predict_pose(const Body& b, Pose& p)
 {
-    first_half(b, b.ppos, b.pquat, b.pvel, b.pomega);
+    first_half(b, p.pos, p.quat, p.vel, p.omega);
     double m[3][3];
-    quat_to_matrix(b.pquat, m);
+    quat_to_matrix(p.quat, m);
     for (int r = 0; r < 3; ++r) {
-        for (int k = 0; k < 3; ++k) b.prot[3 * r + k] = m[r][k];
-        b.pomega_lab[r] = m[r][0] * b.pomega[0] + m[r][1] * b.pomega[1] + m[r][2] * b.pomega[2];
+        for (int k = 0; k < 3; ++k) p.rot[3 * r + k] = m[r][k];
+        p.omega_lab[r] = m[r][0] * p.omega[0] + m[r][1] * p.omega[1] + m[r][2] * p.omega[2];
     }
 }
 

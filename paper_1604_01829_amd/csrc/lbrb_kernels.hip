@@ -1,21 +1,20 @@
 // lbrb_kernels.hip -- gfx950 kernels of the raspberry / lattice-Boltzmann step.
 //
-//   node_update  : the fused lattice-Boltzmann step of every fluid node (Sec. 1.1 of the
-//                  paper): pull of the 19 populations along the links with halfway
-//                  bounce-back at boundary nodes, moments, multiple-relaxation-time
-//                  collision with the force density (external + spread bead forces) and
-//                  thermal noise, back-transform, store.  One thread per node, 256 nodes per
-//                  workgroup, SoA loads/stores coalesced along x.  Bandwidth bound:
-//                  19 loads + 19 stores per node.
-//   couple       : the bead/fluid friction of eq. (latticeboltzmannfriction): 8 threads per
-//                  bead, one per corner of the trilinear stencil; each corner thread pulls
-//                  its node's populations to get the fluid velocity, the 8 weighted
-//                  velocities are summed with a lane butterfly, the friction + noise force is
-//                  formed and each corner spreads its share of the opposite force with
-//                  64-bit fixed-point atomics (order-independent, hence deterministic).
-//   body_finish  : one workgroup per raspberry: sums the bead forces and torques (shuffle +
-//                  LDS tree, fixed order), turns the torque into the body frame and applies
-//                  the second half kick (Sec. 2.3).
+// A step is two launches on one stream:
+//   couple     : the bead coupling of eq. (latticeboltzmannfriction) of the paper: 8 threads
+//                per bead, one per corner of the trilinear stencil; bead kinematics from the
+//                body's pose of the step, fluid velocity from the corner node's pulled
+//                populations, lane-butterfly sum, friction + noise, spreading of the opposite
+//                force with 64-bit fixed-point atomics (order-independent, hence
+//                deterministic), per-bead force and torque.
+//   node_step  : the fused lattice-Boltzmann update of every fluid node (Sec. 1.1) -- pull of
+//                the 19 populations along the links with halfway bounce-back at boundary
+//                nodes, moments, multiple-relaxation-time collision with the external and
+//                spread force and thermal noise, back-transform, store; one thread per node,
+//                256 nodes per workgroup, SoA loads/stores coalesced along x.  Its leading
+//                workgroups finish the raspberries: per-body force/torque sums (shuffle +
+//                LDS tree, fixed order), torque into the body frame, second half kick
+//                (Sec. 2.3), pose of the next step.
 #include <hip/hip_runtime.h>
 
 #include "lbrb_layout.h"
@@ -164,30 +163,27 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return xcd * q + min(xcd, r) + k;
 }
 
-template <typename Real, bool MASKED, bool THERMAL>
-__global__ __launch_bounds__(kNodeBlock) void node_update_kernel(const StepArgs<Real> a)
+// One fluid node: pull, add the force density (external, plus the spread force when the
+// node's flag is set and FORCES), collide with the node's noise, store.
+template <typename Real, bool MASKED, bool THERMAL, bool FORCES>
+__device__ __forceinline__ void update_node(const StepArgs<Real>& a, const ReplicaDesc& R,
+                                            int64_t local, int x, int y, int z,
+                                            const RowDesc& self, int64_t step)
 {
-    const NodeTile t = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
-    if ((int)threadIdx.x >= t.count) return;
-    const ReplicaDesc R = a.reps[t.replica];
-    const int64_t local = t.begin + threadIdx.x;
-    int x, y, z;
-    RowDesc self;
-    locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
-
     Real d[Q];
     pull<Real, MASKED>(a.src, a.N, R, a.rowinfo, x, y, z, local, self, d);
 
     const int64_t g = R.base + local;
     Real F[3] = {a.gext[0], a.gext[1], a.gext[2]};
-    if (a.flags[g]) {
+    if constexpr (FORCES) {
+        if (a.flags[g]) {
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) F[ax] += take_spread_force<Real>(a.gforce, a.N, ax, g);
-        a.flags[g] = 0;
+            for (int ax = 0; ax < 3; ++ax) F[ax] += take_spread_force<Real>(a.gforce, a.N, ax, g);
+            a.flags[g] = 0;
+        }
     }
 
     if constexpr (THERMAL) {
-        const int64_t step = current_step(a.step_ptr, a.step_arg);
         const uint32_t dense = (uint32_t)(x + (int64_t)R.nx * (y + (int64_t)R.ny * z));
         const U4 b0 = noise_block((uint64_t)step, dense, 0u, 0u, R.key0, R.key1);
         const U4 b1 = noise_block((uint64_t)step, dense, 0u, 1u, R.key0, R.key1);
@@ -205,159 +201,13 @@ __global__ __launch_bounds__(kNodeBlock) void node_update_kernel(const StepArgs<
     for (int i = 0; i < Q; ++i) dst[(int64_t)i * a.N + g] = d[i];
 }
 
-template <typename Real>
-void launch_node_update(const StepArgs<Real>& a, bool masked, hipStream_t s)
-{
-    if (a.n_tiles <= 0) return;
-    const dim3 grid(a.n_tiles), block(kNodeBlock);
-    if (masked) {
-        if (a.thermal) hipLaunchKernelGGL((node_update_kernel<Real, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((node_update_kernel<Real, true, false>), grid, block, 0, s, a);
-    } else {
-        if (a.thermal) hipLaunchKernelGGL((node_update_kernel<Real, false, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((node_update_kernel<Real, false, false>), grid, block, 0, s, a);
-    }
-}
-
-// ------------------------------------------------------------------ bead coupling
-
-// local index of node (x,y,z) of a replica, or -1 for a boundary node
-__device__ __forceinline__ int64_t node_local(const ReplicaDesc& R,
-                                              const RowDesc* __restrict__ rowinfo, int x, int y,
-                                              int z, RowDesc& self)
-{
-    if (!R.masked) {
-        self.start = 0; self.xlo = 0; self.len = R.nx; self.yz = 0;
-        return x + (int64_t)R.nx * (y + (int64_t)R.ny * z);
-    }
-    self = rowinfo[R.row_base + y + R.ny * z];
-    const int off = x - self.xlo;
-    if ((unsigned)off >= (unsigned)self.len) return -1;
-    return self.start + off;
-}
-
-// periodic cell index and fraction of a coordinate; a non-finite or absurdly large
-// coordinate (a diverged body) maps to cell 0 so that no access leaves the box
-__device__ __forceinline__ int wrap_floor(double v, int n, double& frac)
-{
-    if (!(fabs(v) < 1e15)) { frac = 0.0; return 0; }
-    const double fl = floor(v);
-    frac = v - fl;
-    int64_t i = (int64_t)fl % n;
-    if (i < 0) i += n;
-    return (int)i;
-}
-
-template <typename Real, bool ANY_MASKED>
-__global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Real> a,
-                                                              const CoupleArgs c)
-{
-    const int tid = blockIdx.x * kCoupleBlock + threadIdx.x;
-    const int bead = tid >> 3, corner = tid & 7;
-    if (bead >= c.n_beads) return;   // the 8 lanes of a bead leave together
-    const int bi = c.bead_body[bead];
-    const Body& B = c.bodies[bi];
-    const double off[3] = {c.bead_off[3 * bead], c.bead_off[3 * bead + 1], c.bead_off[3 * bead + 2]};
-    // bead position r = R + Q b and velocity v = V + w_lab x (Q b) from the step's pose
-    double dv[3], r[3], v[3];
-    for (int ax = 0; ax < 3; ++ax) {
-        dv[ax] = B.prot[3 * ax] * off[0] + B.prot[3 * ax + 1] * off[1] + B.prot[3 * ax + 2] * off[2];
-        r[ax] = B.ppos[ax] + dv[ax];
-    }
-    if (B.fixed) {
-        v[0] = v[1] = v[2] = 0.0;
-    } else {
-        const double* w = B.pomega_lab;
-        v[0] = B.pvel[0] + (w[1] * dv[2] - w[2] * dv[1]);
-        v[1] = B.pvel[1] + (w[2] * dv[0] - w[0] * dv[2]);
-        v[2] = B.pvel[2] + (w[0] * dv[1] - w[1] * dv[0]);
-    }
-    const ReplicaDesc R = a.reps[B.replica];
-
-    // corner of the trilinear stencil handled by this lane
-    double fr[3];
-    int i0[3];
-    i0[0] = wrap_floor(r[0] - 0.5, R.nx, fr[0]);
-    i0[1] = wrap_floor(r[1] - 0.5, R.ny, fr[1]);
-    i0[2] = wrap_floor(r[2] - 0.5, R.nz, fr[2]);
-    const int ox = corner & 1, oy = (corner >> 1) & 1, oz = corner >> 2;
-    const int px = i0[0] + ox == R.nx ? 0 : i0[0] + ox;
-    const int py = i0[1] + oy == R.ny ? 0 : i0[1] + oy;
-    const int pz = i0[2] + oz == R.nz ? 0 : i0[2] + oz;
-    const double w = (ox ? fr[0] : 1.0 - fr[0]) * (oy ? fr[1] : 1.0 - fr[1]) *
-                     (oz ? fr[2] : 1.0 - fr[2]);
-
-    RowDesc self;
-    const int64_t local = node_local(R, a.rowinfo, px, py, pz, self);
-    double wu[3] = {0.0, 0.0, 0.0};
-    if (local >= 0) {
-        Real d[Q];
-        if (ANY_MASKED && R.masked)
-            pull<Real, true>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
-        else
-            pull<Real, false>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
-        Real drho, j[3];
-        density_momentum<Real>(d, drho, j);
-        const double rho = (double)a.cp.rho0 + (double)drho;
-        for (int ax = 0; ax < 3; ++ax)
-            wu[ax] = w * (((double)j[ax] + 0.5 * (double)a.gext[ax]) / rho);
-    }
-    // sum over the 8 corner lanes (same association on every lane)
-#pragma unroll
-    for (int m = 1; m < 8; m <<= 1)
-        for (int ax = 0; ax < 3; ++ax) wu[ax] += __shfl_xor(wu[ax], m, 8);
-
-    double F[3];
-    for (int ax = 0; ax < 3; ++ax) F[ax] = -B.gamma * (v[ax] - wu[ax]);
-    if (c.kT > 0.0) {
-        const int64_t step = current_step(a.step_ptr, a.step_arg);
-        const uint32_t idx = (uint32_t)(B.first_bead_in_replica + (bead - B.first_bead));
-        const U4 blk = noise_block((uint64_t)step, idx, 1u, 0u, R.key0, R.key1);
-        const double amp = sqrt(2.0 * c.kT * B.gamma) * sqrt(12.0);
-        F[0] += amp * uniform16<double>(blk.x);
-        F[1] += amp * uniform16<double>(blk.x >> 16);
-        F[2] += amp * uniform16<double>(blk.y);
-    }
-
-    if (local >= 0) {
-        const int64_t g = R.base + local;
-        bool overflow = false;
-        for (int ax = 0; ax < 3; ++ax) {
-            const double val = -(w * F[ax]);
-            const bool bad = !(fabs(val) < 16.0);
-            overflow |= bad;
-            add_spread_force<Real>(a.gforce, a.N, ax, g, bad ? 0.0 : val);
-        }
-        a.flags[g] = 1;   // every writer stores the same value
-        if (overflow) atomicOr(&c.hdr->err_flags, 1u);
-    }
-    if (corner == 0) {
-        for (int ax = 0; ax < 3; ++ax) c.bead_force[3 * bead + ax] = F[ax];
-        c.bead_torque[3 * bead + 0] = dv[1] * F[2] - dv[2] * F[1];
-        c.bead_torque[3 * bead + 1] = dv[2] * F[0] - dv[0] * F[2];
-        c.bead_torque[3 * bead + 2] = dv[0] * F[1] - dv[1] * F[0];
-    }
-}
-
-template <typename Real>
-void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, bool any_masked, hipStream_t s)
-{
-    if (c.n_beads <= 0) return;
-    const int threads = c.n_beads * kBeadLanes;
-    const dim3 grid((threads + kCoupleBlock - 1) / kCoupleBlock), block(kCoupleBlock);
-    if (any_masked) hipLaunchKernelGGL((couple_kernel<Real, true>), grid, block, 0, s, a, c);
-    else hipLaunchKernelGGL((couple_kernel<Real, false>), grid, block, 0, s, a, c);
-}
-
-// ------------------------------------------------------------------ body update
-
-__global__ __launch_bounds__(256) void body_finish_kernel(Body* __restrict__ bodies,
-                                                          const double* __restrict__ bf,
-                                                          const double* __restrict__ bt)
+// one workgroup per body: sum the bead forces and torques (shuffle + LDS tree, fixed order),
+// turn the torque into the body frame, second half kick, pose of the next step
+__device__ __forceinline__ void body_finish(Body* __restrict__ bodies, const double* __restrict__ bf,
+                                            const double* __restrict__ bt, int b, int parity)
 {
     __shared__ double part[4][6];
-    const int b = blockIdx.x;
-    const Body B = bodies[b];
+    const Body& B = bodies[b];
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int k = threadIdx.x; k < B.n_beads; k += 256) {
         const int64_t e = 3 * (int64_t)(B.first_bead + k);
@@ -378,52 +228,225 @@ __global__ __launch_bounds__(256) void body_finish_kernel(Body* __restrict__ bod
         T[k] = (part[0][3 + k] + part[1][3 + k]) + (part[2][3 + k] + part[3][3 + k]);
     }
     // second half kick with this step's force and body-frame torque, from the step's pose
-    Body* o = bodies + b;
+    const Pose& P = B.pose[parity];
     double vel[3], om[3], Tb[3];
     for (int ax = 0; ax < 3; ++ax) {
-        vel[ax] = B.pvel[ax];
-        om[ax] = B.pomega[ax];
-        Tb[ax] = B.prot[ax] * T[0] + B.prot[3 + ax] * T[1] + B.prot[6 + ax] * T[2];
+        vel[ax] = P.vel[ax];
+        om[ax] = P.omega[ax];
+        Tb[ax] = P.rot[ax] * T[0] + P.rot[3 + ax] * T[1] + P.rot[6 + ax] * T[2];
     }
     if (!B.fixed) {
         for (int ax = 0; ax < 3; ++ax) vel[ax] += 0.5 * F[ax] / B.mass;
         half_kick(om, B.inertia, Tb);
     }
-    Body nb = B;
+    Body& o = bodies[b];
     for (int ax = 0; ax < 3; ++ax) {
-        nb.pos[ax] = B.ppos[ax];
-        nb.vel[ax] = vel[ax];
-        nb.omega[ax] = om[ax];
-        nb.force[ax] = F[ax];
-        nb.torque[ax] = Tb[ax];
+        o.pos[ax] = P.pos[ax];
+        o.vel[ax] = vel[ax];
+        o.omega[ax] = om[ax];
+        o.force[ax] = F[ax];
+        o.torque[ax] = Tb[ax];
     }
-    for (int k = 0; k < 4; ++k) nb.quat[k] = B.pquat[k];
-    predict_pose(nb);
-    *o = nb;
+    for (int k = 0; k < 4; ++k) o.quat[k] = P.quat[k];
+    predict_pose(o, o.pose[parity ^ 1]);
 }
 
-__global__ void body_predict_kernel(Body* __restrict__ bodies, int32_t n)
+// The node update of one tile group.  With FORCES the nodes consume the spread force of the
+// coupling.  The first n_lead workgroups (0, or a multiple of 8 so that blockIdx % 8 still
+// picks the XCD of the node tiles) finish the bodies: they read only the per-bead forces of
+// the coupling and write only body records, which no node thread touches.
+template <typename Real, bool MASKED, bool THERMAL, bool FORCES>
+__global__ __launch_bounds__(kNodeBlock) void node_step_kernel(const StepArgs<Real> a,
+                                                               Body* __restrict__ bodies,
+                                                               const double* __restrict__ bf,
+                                                               const double* __restrict__ bt,
+                                                               int n_bodies, int n_lead)
+{
+    const int64_t step = current_step(a.step_ptr, a.step_arg);
+    int b = blockIdx.x;
+    if (b < n_lead) {
+        if (b < n_bodies) body_finish(bodies, bf, bt, b, (int)(step & 1));
+        return;
+    }
+    b -= n_lead;
+    const NodeTile t = a.tiles[xcd_tile(b, gridDim.x - n_lead)];
+    if ((int)threadIdx.x >= t.count) return;
+    const ReplicaDesc R = a.reps[t.replica];
+    const int64_t local = t.begin + threadIdx.x;
+    int x, y, z;
+    RowDesc self;
+    locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
+    update_node<Real, MASKED, THERMAL, FORCES>(a, R, local, x, y, z, self, step);
+}
+
+template <typename Real, bool MASKED, bool THERMAL>
+void launch_node_t(const StepArgs<Real>& a, bool forces, Body* bodies, const double* bf,
+                   const double* bt, int32_t n_bodies, hipStream_t s)
+{
+    const int n_lead = bodies && n_bodies > 0 ? (n_bodies + 7) & ~7 : 0;
+    const dim3 grid(a.n_tiles + n_lead), block(kNodeBlock);
+    if (forces)
+        hipLaunchKernelGGL((node_step_kernel<Real, MASKED, THERMAL, true>), grid, block, 0, s, a,
+                           bodies, bf, bt, n_bodies, n_lead);
+    else
+        hipLaunchKernelGGL((node_step_kernel<Real, MASKED, THERMAL, false>), grid, block, 0, s, a,
+                           bodies, bf, bt, n_bodies, n_lead);
+}
+
+template <typename Real>
+void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, Body* bodies,
+                      const double* bead_force, const double* bead_torque, int32_t n_bodies,
+                      hipStream_t s)
+{
+    if (a.n_tiles <= 0 && !(bodies && n_bodies > 0)) return;
+    if (masked) {
+        if (a.thermal) launch_node_t<Real, true, true>(a, forces, bodies, bead_force, bead_torque, n_bodies, s);
+        else launch_node_t<Real, true, false>(a, forces, bodies, bead_force, bead_torque, n_bodies, s);
+    } else {
+        if (a.thermal) launch_node_t<Real, false, true>(a, forces, bodies, bead_force, bead_torque, n_bodies, s);
+        else launch_node_t<Real, false, false>(a, forces, bodies, bead_force, bead_torque, n_bodies, s);
+    }
+}
+
+// ------------------------------------------------------------------ bead coupling
+
+// periodic cell index and fraction of a coordinate; a non-finite or absurdly large
+// coordinate (a diverged body) maps to cell 0 so that no access leaves the box
+__device__ __forceinline__ int wrap_floor(double v, int n, double& frac)
+{
+    if (!(fabs(v) < 1e15)) { frac = 0.0; return 0; }
+    const double fl = floor(v);
+    frac = v - fl;
+    int64_t i = (int64_t)fl % n;
+    if (i < 0) i += n;
+    return (int)i;
+}
+
+// Thread t handles corner t & 7 of bead t >> 3.  The dependent loads are kept to four
+// rounds: bead record (offset + body index) -> body record (pose, friction, replica
+// geometry) -> the 9 row descriptors around the corner node -> its 19 populations.
+template <typename Real>
+__global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Real> a,
+                                                              const CoupleArgs c)
+{
+    const int tid = blockIdx.x * kCoupleBlock + threadIdx.x;
+    const int bead = tid >> 3, corner = tid & 7;
+    if (bead >= c.n_beads) return;   // the 8 lanes of a bead leave together
+    const int64_t step = current_step(a.step_ptr, a.step_arg);
+    const Bead bd = c.beads[bead];
+    const Body& B = c.bodies[bd.body];
+    const Pose& P = B.pose[step & 1];
+    const BodyBox& X = B.box;
+    // bead position r = R + Q b and velocity v = V + w_lab x (Q b) from the step's pose
+    double dv[3], r[3], v[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        dv[ax] = P.rot[3 * ax] * bd.off[0] + P.rot[3 * ax + 1] * bd.off[1] + P.rot[3 * ax + 2] * bd.off[2];
+        r[ax] = P.pos[ax] + dv[ax];
+    }
+    if (B.fixed) {
+        v[0] = v[1] = v[2] = 0.0;
+    } else {
+        const double* w = P.omega_lab;
+        v[0] = P.vel[0] + (w[1] * dv[2] - w[2] * dv[1]);
+        v[1] = P.vel[1] + (w[2] * dv[0] - w[0] * dv[2]);
+        v[2] = P.vel[2] + (w[0] * dv[1] - w[1] * dv[0]);
+    }
+
+    // corner of the trilinear stencil handled by this lane
+    double fr[3];
+    int i0[3];
+    i0[0] = wrap_floor(r[0] - 0.5, X.nx, fr[0]);
+    i0[1] = wrap_floor(r[1] - 0.5, X.ny, fr[1]);
+    i0[2] = wrap_floor(r[2] - 0.5, X.nz, fr[2]);
+    const int ox = corner & 1, oy = (corner >> 1) & 1, oz = corner >> 2;
+    const int px = i0[0] + ox == X.nx ? 0 : i0[0] + ox;
+    const int py = i0[1] + oy == X.ny ? 0 : i0[1] + oy;
+    const int pz = i0[2] + oz == X.nz ? 0 : i0[2] + oz;
+    const double w = (ox ? fr[0] : 1.0 - fr[0]) * (oy ? fr[1] : 1.0 - fr[1]) *
+                     (oz ? fr[2] : 1.0 - fr[2]);
+
+    // the node's populations (pre-collision of this step): local index and pull
+    ReplicaDesc R{};
+    R.nx = X.nx; R.ny = X.ny; R.nz = X.nz; R.masked = X.masked;
+    R.base = X.base; R.row_base = X.row_base;
+    int64_t local;
+    Real d[Q];
+    if (X.masked) {
+        const RowDesc self = a.rowinfo[X.row_base + py + X.ny * pz];
+        const int off = px - self.xlo;
+        local = (unsigned)off < (unsigned)self.len ? self.start + off : -1;
+        if (local >= 0) pull<Real, true>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
+    } else {
+        local = px + (int64_t)X.nx * (py + (int64_t)X.ny * pz);
+        const RowDesc self{0, 0, X.nx, 0};
+        pull<Real, false>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
+    }
+    double wu[3] = {0.0, 0.0, 0.0};
+    if (local >= 0) {
+        Real drho, j[3];
+        density_momentum<Real>(d, drho, j);
+        const double rho = (double)a.cp.rho0 + (double)drho;
+        for (int ax = 0; ax < 3; ++ax)
+            wu[ax] = w * (((double)j[ax] + 0.5 * (double)a.gext[ax]) / rho);
+    }
+    // sum over the 8 corner lanes (same association on every lane)
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1)
+        for (int ax = 0; ax < 3; ++ax) wu[ax] += __shfl_xor(wu[ax], m, 8);
+
+    double F[3];
+    for (int ax = 0; ax < 3; ++ax) F[ax] = -B.gamma * (v[ax] - wu[ax]);
+    if (c.kT > 0.0) {
+        const uint32_t idx = (uint32_t)(B.first_bead_in_replica + (bead - B.first_bead));
+        const U4 blk = noise_block((uint64_t)step, idx, 1u, 0u, X.key0, X.key1);
+        const double amp = sqrt(2.0 * c.kT * B.gamma) * sqrt(12.0);
+        F[0] += amp * uniform16<double>(blk.x);
+        F[1] += amp * uniform16<double>(blk.x >> 16);
+        F[2] += amp * uniform16<double>(blk.y);
+    }
+
+    if (local >= 0) {
+        const int64_t g = X.base + local;
+        bool overflow = false;
+        for (int ax = 0; ax < 3; ++ax) {
+            const double val = -(w * F[ax]);
+            const bool bad = !(fabs(val) < 16.0);
+            overflow |= bad;
+            add_spread_force<Real>(a.gforce, a.N, ax, g, bad ? 0.0 : val);
+        }
+        a.flags[g] = 1;   // every writer stores the same value
+        if (overflow) atomicOr(&c.hdr->err_flags, 1u);
+    }
+    if (corner == 0) {
+        for (int ax = 0; ax < 3; ++ax) c.bead_force[3 * bead + ax] = F[ax];
+        c.bead_torque[3 * bead + 0] = dv[1] * F[2] - dv[2] * F[1];
+        c.bead_torque[3 * bead + 1] = dv[2] * F[0] - dv[0] * F[2];
+        c.bead_torque[3 * bead + 2] = dv[0] * F[1] - dv[1] * F[0];
+    }
+}
+
+template <typename Real>
+void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s)
+{
+    if (c.n_beads <= 0) return;
+    const int threads = c.n_beads * kBeadLanes;
+    hipLaunchKernelGGL((couple_kernel<Real>), dim3((threads + kCoupleBlock - 1) / kCoupleBlock),
+                       dim3(kCoupleBlock), 0, s, a, c);
+}
+
+__global__ void body_predict_kernel(Body* __restrict__ bodies, int32_t n, int parity)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
-    Body B = bodies[b];
-    predict_pose(B);
-    bodies[b] = B;
+    Body& B = bodies[b];
+    predict_pose(B, B.pose[parity]);
 }
 
-void launch_body_predict(Body* bodies, int32_t n_bodies, hipStream_t s)
+void launch_body_predict(Body* bodies, int32_t n_bodies, int parity, hipStream_t s)
 {
     if (n_bodies <= 0) return;
     hipLaunchKernelGGL(body_predict_kernel, dim3((n_bodies + 63) / 64), dim3(64), 0, s, bodies,
-                       n_bodies);
-}
-
-void launch_body_finish(Body* bodies, const double* bead_force, const double* bead_torque,
-                        int32_t n_bodies, hipStream_t s)
-{
-    if (n_bodies <= 0) return;
-    hipLaunchKernelGGL(body_finish_kernel, dim3(n_bodies), dim3(256), 0, s, bodies, bead_force,
-                       bead_torque);
+                       n_bodies, parity);
 }
 
 __global__ void set_step_kernel(int64_t* p, int64_t v) { *p = v; }
@@ -526,10 +549,12 @@ void launch_observe(const StepArgs<Real>& a, bool masked, int32_t tile0, int32_t
 }
 
 // explicit instantiations
-template void launch_node_update<float>(const StepArgs<float>&, bool, hipStream_t);
-template void launch_node_update<double>(const StepArgs<double>&, bool, hipStream_t);
-template void launch_couple<float>(const StepArgs<float>&, const CoupleArgs&, bool, hipStream_t);
-template void launch_couple<double>(const StepArgs<double>&, const CoupleArgs&, bool, hipStream_t);
+template void launch_couple<float>(const StepArgs<float>&, const CoupleArgs&, hipStream_t);
+template void launch_couple<double>(const StepArgs<double>&, const CoupleArgs&, hipStream_t);
+template void launch_node_step<float>(const StepArgs<float>&, bool, bool, Body*, const double*,
+                                      const double*, int32_t, hipStream_t);
+template void launch_node_step<double>(const StepArgs<double>&, bool, bool, Body*, const double*,
+                                       const double*, int32_t, hipStream_t);
 template void launch_init_equilibrium<float>(float*, int64_t, const ReplicaDesc*, const NodeTile*,
                                              int32_t, float, const double*, hipStream_t);
 template void launch_init_equilibrium<double>(double*, int64_t, const ReplicaDesc*,

@@ -25,6 +25,8 @@ namespace lbrb {
 constexpr int kNodeBlock = 256;   // threads (= nodes) per node-update workgroup
 constexpr int kBeadLanes = 8;     // threads per bead in the coupling kernel (one per corner)
 constexpr int kCoupleBlock = 256;
+// A step is two launches on one stream: the bead coupling, then the node update whose
+// leading workgroups finish the bodies (force/torque sums, second half kick).
 
 struct ReplicaDesc {
     int32_t nx, ny, nz, masked;
@@ -33,7 +35,7 @@ struct ReplicaDesc {
     int64_t n_fluid;
     int32_t row_base;       // first entry of this replica in rows[] and rowinfo[]
     uint32_t key0, key1;    // Philox key (seed)
-    int32_t pad;
+    int32_t pad0, pad1;
     double inv_nx, inv_ny;  // for exact index division
 };
 
@@ -75,10 +77,15 @@ struct StepArgs {
     int64_t step_arg;
 };
 
+// a bead: body-frame offset and the index of its body, read in one 32-byte load
+struct Bead {
+    double off[3];
+    int32_t body, pad;
+};
+
 struct CoupleArgs {
     const Body* bodies;
-    const double* bead_off;     // 3 per bead, body frame
-    const int32_t* bead_body;
+    const Bead* beads;
     double* bead_force;         // 3 per bead, lab frame
     double* bead_torque;        // 3 per bead, lab frame
     int32_t n_beads;
@@ -87,13 +94,14 @@ struct CoupleArgs {
 };
 
 template <typename Real>
-void launch_node_update(const StepArgs<Real>& a, bool masked, hipStream_t s);
+void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s);
+// the node update of one tile group; with forces the nodes consume the spread force, with
+// bodies != null its leading workgroups finish the bodies
 template <typename Real>
-void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, bool any_masked,
-                   hipStream_t s);
-void launch_body_finish(Body* bodies, const double* bead_force, const double* bead_torque,
-                        int32_t n_bodies, hipStream_t s);
-void launch_body_predict(Body* bodies, int32_t n_bodies, hipStream_t s);
+void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, Body* bodies,
+                      const double* bead_force, const double* bead_torque, int32_t n_bodies,
+                      hipStream_t s);
+void launch_body_predict(Body* bodies, int32_t n_bodies, int parity, hipStream_t s);
 void launch_set_step(int64_t* step_ptr, int64_t value, hipStream_t s);
 template <typename Real>
 void launch_init_equilibrium(Real* f, int64_t N, const ReplicaDesc* reps, const NodeTile* tiles,
