@@ -582,6 +582,7 @@ int rb_add_raspberry(lb_ctx* c, int32_t replica, const double* offs, int32_t n_b
     for (int a = 0; a < 4; ++a) B.quat[a] = quat[a] / qn;
     B.mass = mass;
     B.gamma = gamma;
+    B.noise_amp = std::sqrt(2.0 * c->p.kT * gamma) * std::sqrt(12.0);
     B.fixed = fixed ? 1 : 0;
     B.replica = replica;
     B.first_bead = c->n_beads;

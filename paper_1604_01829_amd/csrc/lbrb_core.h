@@ -271,6 +271,7 @@ struct Body {
     double pos[3], quat[4], vel[3], omega[3];
     double force[3], torque[3];      // last step's sum (lab) and body-frame torque
     double mass, inertia[3], gamma;
+    double noise_amp;                // sqrt(2 kT gamma) sqrt(12): bead noise per uniform variate
     int32_t fixed, replica;
     int32_t first_bead, n_beads;     // global bead range
     int32_t first_bead_in_replica;   // index of the first bead within its replica

@@ -317,9 +317,11 @@ __device__ __forceinline__ int wrap_floor(double v, int n, double& frac)
     if (!(fabs(v) < 1e15)) { frac = 0.0; return 0; }
     const double fl = floor(v);
     frac = v - fl;
-    int64_t i = (int64_t)fl % n;
-    if (i < 0) i += n;
-    return (int)i;
+    // fl - n floor(fl / n) is exact for |fl| < 2^52; the guard absorbs a quotient rounded up
+    double m = fl - (double)n * floor(fl / (double)n);
+    if (m >= (double)n) m -= (double)n;
+    if (m < 0.0) m += (double)n;
+    return (int)m;
 }
 
 // Thread t handles corner t & 7 of bead t >> 3.  The dependent loads are kept to four
@@ -385,9 +387,8 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
     if (local >= 0) {
         Real drho, j[3];
         density_momentum<Real>(d, drho, j);
-        const double rho = (double)a.cp.rho0 + (double)drho;
-        for (int ax = 0; ax < 3; ++ax)
-            wu[ax] = w * (((double)j[ax] + 0.5 * (double)a.gext[ax]) / rho);
+        const double wr = w / ((double)a.cp.rho0 + (double)drho);
+        for (int ax = 0; ax < 3; ++ax) wu[ax] = wr * ((double)j[ax] + 0.5 * (double)a.gext[ax]);
     }
     // sum over the 8 corner lanes (same association on every lane)
 #pragma unroll
@@ -399,7 +400,7 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
     if (c.kT > 0.0) {
         const uint32_t idx = (uint32_t)(B.first_bead_in_replica + (bead - B.first_bead));
         const U4 blk = noise_block((uint64_t)step, idx, 1u, 0u, X.key0, X.key1);
-        const double amp = sqrt(2.0 * c.kT * B.gamma) * sqrt(12.0);
+        const double amp = B.noise_amp;
         F[0] += amp * uniform16<double>(blk.x);
         F[1] += amp * uniform16<double>(blk.x >> 16);
         F[2] += amp * uniform16<double>(blk.y);
