@@ -102,6 +102,19 @@ int      orc_body_state(const orc_sim* s, int body, double out[19]);
 int      orc_bead_forces(const orc_sim* s, int body, double* out);
 int      orc_num_threads(void);
 
+/* ---- reverse-mode derivative (orc_adjoint.c) ---- */
+/* vector-Jacobian product of orc_collide_node (deterministic): given the adjoint lam_out of
+ * the post-collision populations, the adjoints of f_in and of the force density F.        */
+void     orc_collide_vjp(const orc_params* p, const double f_in[19], const double F[3],
+                         const double lam_out[19], double lam_in[19], double lam_F[3]);
+/* Advance the box by n_steps while computing J = sum_n sum_b dJ_dF[n][b] . F_b(n)
+ * (dJ_dF: n_steps * n_bodies * 3) and its derivatives with respect to each body's gamma
+ * (dJ_dgamma[n_bodies]) and every bead offset (dJ_doffsets: total beads * 3, bodies in
+ * order).  Requires kT = 0 and all bodies fixed; p must be the box's parameters.
+ * Returns 0, or -1 on a violated requirement.                                              */
+int      orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies,
+                     const double* dJ_dF, double* J_out, double* dJ_dgamma, double* dJ_doffsets);
+
 #ifdef __cplusplus
 }
 #endif

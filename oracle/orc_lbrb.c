@@ -600,6 +600,30 @@ int orc_bead_forces(const orc_sim* s, int body, double* out)
     return 0;
 }
 
+/* ---- read access for the adjoint (orc_adjoint.c) ---- */
+int orc_box_dims(const orc_sim* s, int dims[3])
+{
+    dims[0] = s->nx; dims[1] = s->ny; dims[2] = s->nz;
+    return 0;
+}
+const double* orc_box_f(const orc_sim* s) { return s->f; }
+void orc_box_set_f(orc_sim* s, const double* f) { memcpy(s->f, f, sizeof(double) * 19 * (size_t)s->n); }
+const uint8_t* orc_box_mask(const orc_sim* s) { return s->mask; }
+double orc_box_kT(const orc_sim* s) { return s->p.kT; }
+int orc_box_body(const orc_sim* s, int b, const double** offsets, int* n_beads, double pos[3],
+                 double quat[4], double* gamma, int* fixed)
+{
+    if (b < 0 || b >= s->n_bodies) return -1;
+    const orc_body* B = &s->bodies[b];
+    *offsets = B->offsets;
+    *n_beads = B->n_beads;
+    for (int a = 0; a < 3; ++a) pos[a] = B->pos[a];
+    for (int a = 0; a < 4; ++a) quat[a] = B->quat[a];
+    *gamma = B->gamma;
+    *fixed = B->fixed;
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -85,6 +85,11 @@ def lib():
         L.orc_bead_forces.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_collide_vjp.restype = None
+        L.orc_collide_vjp.argtypes = [ctypes.POINTER(OrcParams), _D, _D, _D, _D, _D]
+        L.orc_adjoint.restype = ctypes.c_int
+        L.orc_adjoint.argtypes = [ctypes.c_void_p, ctypes.POINTER(OrcParams), ctypes.c_int,
+                                  ctypes.c_int, _D, _D, _D, _D]
         _lib = L
     return _lib
 
@@ -166,6 +171,14 @@ def collide_node(params, f_in, F, unoise=None):
     lib().orc_collide_node(ctypes.byref(params), _dp(fin), _dp(Fv),
                            None if un is None else _dp(un), _dp(out))
     return out
+
+
+def collide_vjp(params, f_in, F, lam_out):
+    lam_in = np.zeros(19)
+    lam_F = np.zeros(3)
+    lib().orc_collide_vjp(ctypes.byref(params), _dp(_vec(f_in, 19)), _dp(_vec(F, 3)),
+                          _dp(_vec(lam_out, 19)), _dp(lam_in), _dp(lam_F))
+    return lam_in, lam_F
 
 
 def trilinear(shape, r):
@@ -261,6 +274,19 @@ class OracleSim:
         return {"pos": out[0:3].copy(), "quat": out[3:7].copy(), "vel": out[7:10].copy(),
                 "omega": out[10:13].copy(), "force": out[13:16].copy(),
                 "torque": out[16:19].copy()}
+
+    def adjoint(self, n_steps, dJ_dF):
+        """Advance n_steps and return (J, dJ/dgamma per body, dJ/doffsets per bead (n, 3))."""
+        a = np.ascontiguousarray(np.asarray(dJ_dF, dtype=np.float64).reshape(-1))
+        assert a.size == n_steps * self.n_bodies * 3
+        J = np.zeros(1)
+        dg = np.zeros(self.n_bodies)
+        do = np.zeros(3 * sum(self.beads_per_body))
+        rc = lib().orc_adjoint(self._h, ctypes.byref(self.params), int(n_steps), self.n_bodies,
+                               _dp(a), _dp(J), _dp(dg), _dp(do))
+        if rc != 0:
+            raise RuntimeError("orc_adjoint: needs kT = 0 and fixed bodies")
+        return float(J[0]), dg, do.reshape(-1, 3)
 
     def bead_forces(self, b):
         out = np.zeros(self.beads_per_body[b] * 3)
