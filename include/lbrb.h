@@ -163,6 +163,33 @@ int lb_set_timing(lb_ctx* ctx, int32_t enable);
 int lb_kernel_times(lb_ctx* ctx, double* node_ms, int64_t* node_launches, double* couple_ms,
                     int64_t* couple_launches);
 
+/* Reverse-mode derivative of a window of steps (not in the paper: the hand adjoint of the
+ * coupled update of Sec. 1.1-1.2 -- streaming with bounce-back, the mode-space collision
+ * with its force source, the frictional coupling of eq. (latticeboltzmannfriction) with its
+ * interpolated fluid velocity, and the opposite force spread onto the fluid).
+ * Objective J = sum_n sum_b a(n,b) . F_b(n) over the next n_steps steps, F_b(n) the summed
+ * bead force on body b in step n (a = (1/T,0,0) for every step: time-averaged drag along x).
+ * Derivatives with respect to every body's friction gamma and every bead's body-frame
+ * offset.  Requires kT = 0 and every body fixed.
+ * The call advances the context by n_steps steps (its state afterwards is that of
+ * lb_rb_step(n_steps)), keeping the post-collision state every checkpoint_every steps in the
+ * caller's device workspace dev_ws (256-byte aligned, at least
+ * lb_adjoint_workspace_bytes(ctx, n_steps, checkpoint_every) bytes), then walks the window
+ * backwards one segment at a time, recomputing each segment's states from its checkpoint.
+ * Host arrays, global body and bead order (the order of the rb_add_raspberry calls over
+ * all replicas):
+ *   dJ_dF       [n_steps][n_bodies][3]  the weights a(n,b), lab frame;
+ *   J           the objective (may be NULL);
+ *   dJ_dgamma   [n_bodies];
+ *   dJ_doffsets [n_beads][3], body frame.
+ * Synchronises the stream.  Errors: LB_ERR_ARG (window, workspace, missing arrays),
+ * LB_ERR_STATE (kT > 0 or a free body).  The adjoint runs in the context precision; its
+ * atomic accumulation of sampled-velocity adjoints is not order-deterministic.          */
+size_t lb_adjoint_workspace_bytes(const lb_ctx* ctx, int32_t n_steps, int32_t checkpoint_every);
+int lb_rb_adjoint(lb_ctx* ctx, int32_t n_steps, int32_t checkpoint_every, void* dev_ws,
+                  size_t ws_bytes, const double* dJ_dF, double* J, double* dJ_dgamma,
+                  double* dJ_doffsets);
+
 /* Node counts of one replica: all nodes and fluid nodes.                                  */
 int lb_node_counts(const lb_ctx* ctx, int32_t replica, int64_t* n_nodes, int64_t* n_fluid);
 

@@ -187,12 +187,13 @@ CollideParams<Real> collide_params(const lb_params& p)
     return cp;
 }
 
+// launch arguments of one tile group pulling from src and writing dst
 template <typename Real>
-StepArgs<Real> step_args(const lb_ctx* c, int group, int src_buf)
+StepArgs<Real> step_args_on(const lb_ctx* c, int group, const void* src, void* dst)
 {
     StepArgs<Real> a{};
-    a.src = (const Real*)c->f[src_buf];
-    a.dst = (Real*)c->f[src_buf ^ 1];
+    a.src = (const Real*)src;
+    a.dst = (Real*)dst;
     a.N = c->plan.N;
     a.reps = c->d_reps;
     a.rows = c->d_rows;
@@ -207,6 +208,12 @@ StepArgs<Real> step_args(const lb_ctx* c, int group, int src_buf)
     a.step_ptr = nullptr;
     a.step_arg = c->step;
     return a;
+}
+
+template <typename Real>
+StepArgs<Real> step_args(const lb_ctx* c, int group, int src_buf)
+{
+    return step_args_on<Real>(c, group, c->f[src_buf], c->f[src_buf ^ 1]);
 }
 
 CoupleArgs couple_args(const lb_ctx* c)
@@ -403,6 +410,136 @@ bool check_replica(lb_ctx* c, int32_t r)
 {
     if (r < 0 || r >= c->n_rep) { c->err = "replica index out of range"; return false; }
     return true;
+}
+
+// ------------------------------------------------------------------ reverse pass
+// Layout of the caller's reverse-pass workspace: checkpoints of the post-collision state
+// every K steps, K-1 slots for the states recomputed inside one segment, two adjoint
+// population buffers, the adjoints of the node force and velocity, the per-step objective
+// weights, the per-bead accumulators, and room to restore the bead forces afterwards.
+struct AdjPlan {
+    int32_t n_ck = 0, n_seg = 0;
+    size_t state = 0;
+    size_t off_ck, off_seg, off_lam0, off_lam1, off_lamF, off_lamU, off_uflag, off_w, off_dr,
+        off_dg, off_J, off_save, total;
+};
+
+bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
+{
+    if (!c || T < 1 || K < 1) return false;
+    K = std::min(K, T);
+    ap = AdjPlan();
+    const size_t real = is_f32(c) ? sizeof(float) : sizeof(double);
+    const int64_t N = c->plan.N;
+    const int64_t nb = std::max<int32_t>(c->n_beads, 1), nbod = std::max<int32_t>(c->n_bodies, 1);
+    ap.n_ck = (T + K - 1) / K;
+    ap.n_seg = K - 1;
+    ap.state = align_up(real * Q * N, kAlign);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes, kAlign); return at; };
+    ap.off_ck = take(ap.state * ap.n_ck);
+    ap.off_seg = take(ap.state * ap.n_seg);
+    ap.off_lam0 = take(ap.state);
+    ap.off_lam1 = take(ap.state);
+    ap.off_lamF = take(real * 3 * N);
+    ap.off_lamU = take(real * 3 * N);
+    ap.off_uflag = take(N);
+    ap.off_w = take(sizeof(double) * 3 * nbod * (size_t)T);
+    ap.off_dr = take(sizeof(double) * 3 * nb);
+    ap.off_dg = take(sizeof(double) * nb);
+    ap.off_J = take(sizeof(double) * nb);
+    ap.off_save = take(sizeof(double) * 6 * nb);
+    ap.total = o;
+    return true;
+}
+
+// forward step without finishing the bodies (fixed bodies: nothing to finish), src -> dst
+template <typename Real>
+void enqueue_replay(lb_ctx* c, hipStream_t s, const void* src, void* dst, int64_t step)
+{
+    StepArgs<Real> ag[2] = {step_args_on<Real>(c, 0, src, dst), step_args_on<Real>(c, 1, src, dst)};
+    for (auto& a : ag) a.step_arg = step;
+    if (c->n_beads > 0) launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], couple_args(c), s);
+    for (int g = 0; g < 2; ++g)
+        if (ag[g].n_tiles > 0)
+            launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, nullptr, c->d_bead_force,
+                                   c->d_bead_torque, 0, s);
+}
+
+// one reverse step at forward step `step` (index n of the window), forward state pulled from src
+template <typename Real>
+void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, const Real* lam_next,
+                     Real* lam_cur, char* ws, const AdjPlan& ap, int64_t n)
+{
+    AdjArgs<Real> A[2];
+    for (int g = 0; g < 2; ++g) {
+        AdjArgs<Real>& X = A[g];
+        X = AdjArgs<Real>{};
+        X.a = step_args_on<Real>(c, g, src, nullptr);
+        X.a.step_arg = step;
+        X.lam_next = lam_next;
+        X.lam_cur = lam_cur;
+        X.lamF = (Real*)(ws + ap.off_lamF);
+        X.lamU = (Real*)(ws + ap.off_lamU);
+        X.uflag = (uint8_t*)(ws + ap.off_uflag);
+        X.bodies = c->d_bodies;
+        X.beads = c->d_beads;
+        X.bead_force = c->d_bead_force;
+        X.weights = (const double*)(ws + ap.off_w) + 3 * (int64_t)c->n_bodies * n;
+        X.dr = (double*)(ws + ap.off_dr);
+        X.dgam = (double*)(ws + ap.off_dg);
+        X.Jpart = (double*)(ws + ap.off_J);
+        X.n_beads = c->n_beads;
+    }
+    const int cg = any_masked(c) ? 1 : 0;
+    if (c->n_beads > 0) launch_couple<Real>(A[cg].a, couple_args(c), s);
+    for (int g = 0; g < 2; ++g) launch_adjoint_step<Real>(A[g], g == 1, s);
+    if (c->n_beads > 0) {
+        launch_adjoint_beads<Real>(A[cg], s);
+        for (int g = 0; g < 2; ++g) launch_adjoint_vel<Real>(A[g], g == 1, s);
+    }
+}
+
+template <typename Real>
+int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
+{
+    hipStream_t s = c->stream;
+    K = std::min(K, T);
+    auto ck = [&](int k) { return (void*)(ws + ap.off_ck + ap.state * k); };
+    auto seg = [&](int k) { return (void*)(ws + ap.off_seg + ap.state * k); };
+    const int64_t step0 = c->step;
+    // forward window, keeping a checkpoint every K steps
+    for (int32_t n = 0; n < T; ++n) {
+        if (n % K == 0)
+            HIP_TRY(c, hipMemcpyAsync(ck(n / K), c->f[c->cur], ap.state, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(c, enqueue_step<Real>(c, s, c->cur, nullptr, c->step, false));
+        c->cur ^= 1;
+        c->step += 1;
+    }
+    const size_t nb = (size_t)std::max<int32_t>(c->n_beads, 1);
+    double* save = (double*)(ws + ap.off_save);
+    HIP_TRY(c, hipMemcpyAsync(save, c->d_bead_force, sizeof(double) * 3 * nb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(save + 3 * nb, c->d_bead_torque, sizeof(double) * 3 * nb,
+                              hipMemcpyDeviceToDevice, s));
+    // reverse, one segment at a time: recompute the segment's states, then walk it backwards
+    Real* lam[2] = {(Real*)(ws + ap.off_lam0), (Real*)(ws + ap.off_lam1)};
+    int nxt = 0;
+    for (int32_t sg = ap.n_ck - 1; sg >= 0; --sg) {
+        const int32_t n0 = sg * K, n1 = std::min(T, n0 + K);
+        auto state = [&](int32_t j) { return j == 0 ? ck(sg) : seg(j - 1); };
+        for (int32_t j = 0; j + 1 < n1 - n0; ++j)
+            enqueue_replay<Real>(c, s, state(j), state(j + 1), step0 + n0 + j);
+        HIP_TRY(c, hipGetLastError());
+        for (int32_t n = n1 - 1; n >= n0; --n) {
+            enqueue_adjoint<Real>(c, s, state(n - n0), step0 + n, lam[nxt], lam[nxt ^ 1], ws, ap, n);
+            nxt ^= 1;
+        }
+        HIP_TRY(c, hipGetLastError());
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_bead_force, save, sizeof(double) * 3 * nb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->d_bead_torque, save + 3 * nb, sizeof(double) * 3 * nb,
+                              hipMemcpyDeviceToDevice, s));
+    return LB_OK;
 }
 
 }  // namespace
@@ -852,6 +989,79 @@ void lb_destroy(lb_ctx* c)
     }
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
+}
+
+size_t lb_adjoint_workspace_bytes(const lb_ctx* c, int32_t n_steps, int32_t checkpoint_every)
+{
+    AdjPlan ap;
+    if (!make_adj_plan(c, n_steps, checkpoint_every, ap)) return 0;
+    return ap.total;
+}
+
+int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* dev_ws,
+                  size_t ws_bytes, const double* dJ_dF, double* J, double* dJ_dgamma,
+                  double* dJ_doffsets)
+{
+    if (!c) return LB_ERR_ARG;
+    AdjPlan ap;
+    if (!make_adj_plan(c, n_steps, checkpoint_every, ap))
+        return fail(c, LB_ERR_ARG, "the window needs n_steps >= 1 and checkpoint_every >= 1");
+    if (!dev_ws || ((uintptr_t)dev_ws % kAlign) != 0 || ws_bytes < ap.total)
+        return fail(c, LB_ERR_ARG, "reverse-pass workspace missing, misaligned or too small");
+    if (c->p.kT != 0.0) return fail(c, LB_ERR_STATE, "the reverse pass needs kT = 0");
+    for (const Body& B : c->bodies0)
+        if (!B.fixed) return fail(c, LB_ERR_STATE, "the reverse pass needs fixed bodies");
+    if (c->n_bodies > 0 && (!dJ_dF || !dJ_dgamma || !dJ_doffsets))
+        return fail(c, LB_ERR_ARG, "missing objective weights or gradient outputs");
+    char* ws = (char*)dev_ws;
+    hipStream_t s = c->stream;
+    const size_t real = is_f32(c) ? sizeof(float) : sizeof(double);
+    const int64_t N = c->plan.N;
+    const size_t nb = (size_t)std::max<int32_t>(c->n_beads, 1);
+    if (c->n_bodies > 0)
+        HIP_TRY(c, hipMemcpyAsync(ws + ap.off_w, dJ_dF, sizeof(double) * 3 * c->n_bodies * (size_t)n_steps,
+                                  hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemsetAsync(ws + ap.off_lam0, 0, ap.state, s));
+    HIP_TRY(c, hipMemsetAsync(ws + ap.off_lam1, 0, ap.state, s));
+    HIP_TRY(c, hipMemsetAsync(ws + ap.off_lamU, 0, real * 3 * N, s));
+    HIP_TRY(c, hipMemsetAsync(ws + ap.off_uflag, 0, N, s));
+    HIP_TRY(c, hipMemsetAsync(ws + ap.off_dr, 0, sizeof(double) * 3 * nb, s));
+    HIP_TRY(c, hipMemsetAsync(ws + ap.off_dg, 0, sizeof(double) * nb, s));
+    HIP_TRY(c, hipMemsetAsync(ws + ap.off_J, 0, sizeof(double) * nb, s));
+    if (c->pose_stale) {
+        launch_body_predict(c->d_bodies, c->n_bodies, (int)(c->step & 1), s);
+        HIP_TRY(c, hipGetLastError());
+        c->pose_stale = false;
+    }
+    const int parity = (int)(c->step & 1);
+    const int rc = is_f32(c) ? run_adjoint<float>(c, n_steps, checkpoint_every, ws, ap)
+                             : run_adjoint<double>(c, n_steps, checkpoint_every, ws, ap);
+    if (rc != LB_OK) return rc;
+    std::vector<double> dr(3 * nb), dg(nb), jp(nb);
+    std::vector<Body> bs(c->n_bodies);
+    HIP_TRY(c, hipMemcpyAsync(dr.data(), ws + ap.off_dr, sizeof(double) * dr.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(dg.data(), ws + ap.off_dg, sizeof(double) * dg.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(jp.data(), ws + ap.off_J, sizeof(double) * jp.size(), hipMemcpyDeviceToHost, s));
+    if (c->n_bodies > 0)
+        HIP_TRY(c, hipMemcpyAsync(bs.data(), c->d_bodies, sizeof(Body) * c->n_bodies,
+                                  hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    double Jsum = 0.0;
+    for (int32_t k = 0; k < c->n_beads; ++k) Jsum += jp[k];
+    if (J) *J = Jsum;
+    for (int32_t b = 0; b < c->n_bodies; ++b) {
+        const Body& B = bs[b];
+        const double* R = B.pose[parity].rot;   // body -> lab; a fixed body keeps one pose
+        double g = 0.0;
+        for (int32_t k = B.first_bead; k < B.first_bead + B.n_beads; ++k) {
+            g += dg[k];
+            const double* d = &dr[3 * (size_t)k];
+            for (int a = 0; a < 3; ++a)
+                dJ_doffsets[3 * (size_t)k + a] = R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2];
+        }
+        dJ_dgamma[b] = g;
+    }
+    return LB_OK;
 }
 
 const char* lb_last_error(const lb_ctx* c)

@@ -233,6 +233,128 @@ LBRB_HD void collide(const CollideParams<Real>& P, Real d[Q], const Real F[3], c
     }
 }
 
+// ------------------------------------------------------------------ collision adjoint
+// Orthogonal basis vector e_k at velocity c_i and its norm b_k = sum_i w_i e_k(c_i)^2.
+LBRB_HD double basis_e(int k, int i)
+{
+    const double cx = cx_of(i), cy = cy_of(i), cz = cz_of(i), c2 = cx * cx + cy * cy + cz * cz;
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return cx;
+    case 2: return cy;
+    case 3: return cz;
+    case 4: return c2 - 1.0;
+    case 5: return 3.0 * cx * cx - c2;
+    case 6: return cy * cy - cz * cz;
+    case 7: return cx * cy;
+    case 8: return cy * cz;
+    case 9: return cz * cx;
+    case 10: return (3.0 * c2 - 5.0) * cx;
+    case 11: return (3.0 * c2 - 5.0) * cy;
+    case 12: return (3.0 * c2 - 5.0) * cz;
+    case 13: return (cy * cy - cz * cz) * cx;
+    case 14: return (cz * cz - cx * cx) * cy;
+    case 15: return (cx * cx - cy * cy) * cz;
+    case 16: return 3.0 * c2 * c2 - 6.0 * c2 + 1.0;
+    case 17: return (2.0 * c2 - 3.0) * (3.0 * cx * cx - c2);
+    default: return (2.0 * c2 - 3.0) * (cy * cy - cz * cz);
+    }
+}
+LBRB_HD double basis_b(int k)
+{
+    constexpr double b[Q] = {1.0, 1.0 / 3, 1.0 / 3, 1.0 / 3, 2.0 / 3, 4.0 / 3, 4.0 / 9, 1.0 / 9,
+                             1.0 / 9, 1.0 / 9, 2.0 / 3, 2.0 / 3, 2.0 / 3, 2.0 / 9, 2.0 / 9, 2.0 / 9,
+                             2.0, 4.0 / 3, 4.0 / 9};
+    return b[k];
+}
+
+// Vector-Jacobian product of the deterministic collision: given lam (adjoint of the
+// post-collision populations) return the adjoints of the pre-collision populations (in lam,
+// overwritten) and of the force density (lamF).  d: shifted pre-collision populations.
+// The derivative runs backwards through: back-transform, relaxation towards the equilibrium
+// of (rho, u) plus the force source, u = (j + F/2)/rho, and the forward transform.
+template <typename Real>
+LBRB_HD void collide_vjp(const CollideParams<Real>& P, const Real d[Q], const Real F[3], Real lam[Q],
+                         Real lamF[3])
+{
+    Real m[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        Real acc = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc += (Real)basis_e(k, i) * d[i];
+        m[k] = acc;
+    }
+    const Real rho = P.rho0 + m[0];
+    const Real u[3] = {(m[1] + (Real)0.5 * F[0]) / rho, (m[2] + (Real)0.5 * F[1]) / rho,
+                       (m[3] + (Real)0.5 * F[2]) / rho};
+    const Real ux = u[0], uy = u[1], uz = u[2];
+    Real ls[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        Real acc = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc += (Real)(basis_e(k, i) * weight_of(i)) * lam[i];
+        ls[k] = acc * (Real)(1.0 / basis_b(k));
+    }
+    Real lm[Q];
+    lm[0] = ls[0];
+    Real lrho = 0, lu[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) { lm[1 + a] = ls[1 + a]; lamF[a] = ls[1 + a]; }
+    // relaxation rates per mode
+#pragma unroll
+    for (int k = 4; k < Q; ++k) {
+        const Real g = k == 4 ? P.g_bulk : (k <= 9 ? P.g_shear : (k <= 15 ? P.g_odd : P.g_even));
+        lm[k] = g * ls[k];
+    }
+    // stress modes: equilibrium (via rho and u) and force source (via u and F)
+    const Real Ab = ((Real)1 - P.g_bulk) * ls[4], Bb = P.h_bulk * ls[4];
+    Real A[10], B[10];
+    for (int k = 5; k <= 9; ++k) { A[k] = ((Real)1 - P.g_shear) * ls[k]; B[k] = P.h_shear * ls[k]; }
+    // k = 4: e = rho u.u, S = 2 u.F
+    lrho += Ab * (ux * ux + uy * uy + uz * uz);
+    for (int a = 0; a < 3; ++a) { lu[a] += Ab * (Real)2 * rho * u[a] + Bb * (Real)2 * F[a]; lamF[a] += Bb * (Real)2 * u[a]; }
+    // k = 5: e = rho (2ux^2 - uy^2 - uz^2), S = 2 (2 ux Fx - uy Fy - uz Fz)
+    lrho += A[5] * ((Real)2 * ux * ux - uy * uy - uz * uz);
+    lu[0] += A[5] * (Real)4 * rho * ux + B[5] * (Real)4 * F[0];
+    lu[1] -= A[5] * (Real)2 * rho * uy + B[5] * (Real)2 * F[1];
+    lu[2] -= A[5] * (Real)2 * rho * uz + B[5] * (Real)2 * F[2];
+    lamF[0] += B[5] * (Real)4 * ux; lamF[1] -= B[5] * (Real)2 * uy; lamF[2] -= B[5] * (Real)2 * uz;
+    // k = 6: e = rho (uy^2 - uz^2), S = 2 (uy Fy - uz Fz)
+    lrho += A[6] * (uy * uy - uz * uz);
+    lu[1] += A[6] * (Real)2 * rho * uy + B[6] * (Real)2 * F[1];
+    lu[2] -= A[6] * (Real)2 * rho * uz + B[6] * (Real)2 * F[2];
+    lamF[1] += B[6] * (Real)2 * uy; lamF[2] -= B[6] * (Real)2 * uz;
+    // k = 7: e = rho ux uy, S = ux Fy + uy Fx
+    lrho += A[7] * ux * uy;
+    lu[0] += A[7] * rho * uy + B[7] * F[1]; lu[1] += A[7] * rho * ux + B[7] * F[0];
+    lamF[0] += B[7] * uy; lamF[1] += B[7] * ux;
+    // k = 8: e = rho uy uz, S = uy Fz + uz Fy
+    lrho += A[8] * uy * uz;
+    lu[1] += A[8] * rho * uz + B[8] * F[2]; lu[2] += A[8] * rho * uy + B[8] * F[1];
+    lamF[1] += B[8] * uz; lamF[2] += B[8] * uy;
+    // k = 9: e = rho uz ux, S = uz Fx + ux Fz
+    lrho += A[9] * uz * ux;
+    lu[0] += A[9] * rho * uz + B[9] * F[2]; lu[2] += A[9] * rho * ux + B[9] * F[0];
+    lamF[0] += B[9] * uz; lamF[2] += B[9] * ux;
+    // u = (j + F/2) / rho
+    const Real irho = (Real)1 / rho;
+    for (int a = 0; a < 3; ++a) {
+        lm[1 + a] += lu[a] * irho;
+        lamF[a] += (Real)0.5 * lu[a] * irho;
+        lrho -= lu[a] * u[a] * irho;
+    }
+    lm[0] += lrho;
+    // m = E f
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        Real acc = 0;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) acc += (Real)basis_e(k, i) * lm[k];
+        lam[i] = acc;
+    }
+}
+
 // density and momentum of shifted populations
 template <typename Real>
 LBRB_HD void density_momentum(const Real d[Q], Real& drho, Real j[3])

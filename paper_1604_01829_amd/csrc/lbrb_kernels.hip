@@ -17,151 +17,11 @@
 //                (Sec. 2.3), pose of the next step.
 #include <hip/hip_runtime.h>
 
-#include "lbrb_layout.h"
+#include "lbrb_device.h"
 
 namespace lbrb {
 
-__device__ __forceinline__ int wrap1(int v, int n)
-{
-    return v < 0 ? v + n : (v >= n ? v - n : v);
-}
-
-__device__ __forceinline__ int64_t current_step(const int64_t* p, int64_t arg)
-{
-    return (p ? *p : 0) + arg;
-}
-
-// exact floor(v / n) for 0 <= v < 2^52 via a double reciprocal and one correction
-__device__ __forceinline__ int64_t div_exact(int64_t v, int32_t n, double inv)
-{
-    int64_t q = (int64_t)((double)v * inv);
-    int64_t r = v - q * n;
-    if (r < 0) q -= 1;
-    else if (r >= n) q += 1;
-    return q;
-}
-
-// coordinates of a local node index
-template <bool MASKED>
-__device__ __forceinline__ void locate(const ReplicaDesc& R, const RowDesc* __restrict__ rows,
-                                       int row_lo, int row_hi, int64_t local, int& x, int& y,
-                                       int& z, RowDesc& self)
-{
-    if constexpr (MASKED) {
-        // largest row whose start <= local
-        int lo = row_lo, hi = row_hi;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (rows[mid].start <= local) lo = mid; else hi = mid - 1;
-        }
-        self = rows[lo];
-        x = self.xlo + (int)(local - self.start);
-        y = self.yz & 0xFFFF;
-        z = self.yz >> 16;
-    } else {
-        const int64_t row = div_exact(local, R.nx, R.inv_nx);
-        x = (int)(local - row * R.nx);
-        const int64_t zz = div_exact(row, R.ny, R.inv_ny);
-        y = (int)(row - zz * R.ny);
-        z = (int)zz;
-        self.start = 0; self.xlo = 0; self.len = R.nx; self.yz = 0;
-    }
-}
-
-// Pre-collision populations of node (x,y,z) (shifted), pulled from the post-collision
-// buffer: population i comes from x - c_i, or, if that node is a boundary node, from the
-// opposite population of the node itself (halfway bounce-back).
-template <typename Real, bool MASKED>
-__device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
-                                     const ReplicaDesc& R, const RowDesc* __restrict__ rowinfo,
-                                     int x, int y, int z, int64_t local, const RowDesc& self,
-                                     Real d[Q])
-{
-    const int64_t own = R.base + local;
-    if constexpr (MASKED) {
-        // fluid runs of the 9 rows (y - cy, z - cz), cy, cz in {-1,0,1}: index (cy+1)+3(cz+1)
-        int32_t st[9], lo[9], ln[9];
-#pragma unroll
-        for (int r9 = 0; r9 < 9; ++r9) {
-            const int cy = r9 % 3 - 1, cz = r9 / 3 - 1;
-            if (cy == 0 && cz == 0) {
-                st[r9] = self.start; lo[r9] = self.xlo; ln[r9] = self.len;
-            } else {
-                const int yy = wrap1(y - cy, R.ny), zz = wrap1(z - cz, R.nz);
-                const RowDesc rd = rowinfo[R.row_base + yy + R.ny * zz];
-                st[r9] = rd.start; lo[r9] = rd.xlo; ln[r9] = rd.len;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
-            const int r9 = (cy + 1) + 3 * (cz + 1);
-            const int xs = wrap1(x - cx, R.nx);
-            const int off = xs - lo[r9];
-            const bool fluid = (unsigned)off < (unsigned)ln[r9];
-            const int64_t g = fluid ? R.base + st[r9] + off : own;
-            const int p = fluid ? i : opposite_of(i);
-            d[i] = src[(int64_t)p * N + g];
-        }
-    } else {
-        const int xm = wrap1(x - 1, R.nx), xp = wrap1(x + 1, R.nx);
-        const int ym = wrap1(y - 1, R.ny), yp = wrap1(y + 1, R.ny);
-        const int zm = wrap1(z - 1, R.nz), zp = wrap1(z + 1, R.nz);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
-            const int xs = cx == 0 ? x : (cx > 0 ? xm : xp);
-            const int ys = cy == 0 ? y : (cy > 0 ? ym : yp);
-            const int zs = cz == 0 ? z : (cz > 0 ? zm : zp);
-            const int64_t g = R.base + xs + (int64_t)R.nx * (ys + (int64_t)R.ny * zs);
-            d[i] = src[(int64_t)i * N + g];
-        }
-    }
-}
-
-// ------------------------------------------------------------------ spread force
-// Bead forces are spread as sums of 64-bit integers, so the total on a node does not depend
-// on the order of the atomic additions.  Word 0 counts units of 2^-56; in FP64 a second
-// word carries the remainder in units of 2^-112, which makes the spread exact to far below
-// FP64 rounding.  Layout: word w of axis ax of node g at gforce[(w*3 + ax) * N + g].
-template <typename Real>
-__device__ __forceinline__ void add_spread_force(long long* gforce, int64_t N, int ax, int64_t g,
-                                                 double val)
-{
-    const double x = val * 0x1p56;
-    const double hi = floor(x);
-    atomicAdd((unsigned long long*)(gforce + (int64_t)ax * N + g),
-              (unsigned long long)(long long)hi);
-    if constexpr (sizeof(Real) == 8) {
-        const long long lo = (long long)((x - hi) * 0x1p56);
-        atomicAdd((unsigned long long*)(gforce + (int64_t)(3 + ax) * N + g), (unsigned long long)lo);
-    }
-}
-
-template <typename Real>
-__device__ __forceinline__ Real take_spread_force(long long* gforce, int64_t N, int ax, int64_t g)
-{
-    long long* p = gforce + (int64_t)ax * N + g;
-    double v = (double)(*p) * 0x1p-56;
-    *p = 0;
-    if constexpr (sizeof(Real) == 8) {
-        long long* q = gforce + (int64_t)(3 + ax) * N + g;
-        v += (double)(*q) * 0x1p-112;
-        *q = 0;
-    }
-    return (Real)v;
-}
-
 // ------------------------------------------------------------------ node update
-
-// Workgroups are dealt round-robin to the 8 XCDs (separate L2 caches).  Give each XCD a
-// contiguous run of tiles so that the halo lines shared by neighbouring tiles are mostly
-// reused from the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int n)
-{
-    const int q = n >> 3, r = n & 7, xcd = b & 7, k = b >> 3;
-    return xcd * q + min(xcd, r) + k;
-}
 
 // One fluid node: pull, add the force density (external, plus the spread force when the
 // node's flag is set and FORCES), collide with the node's noise, store.
@@ -309,20 +169,6 @@ void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, Body* b
 }
 
 // ------------------------------------------------------------------ bead coupling
-
-// periodic cell index and fraction of a coordinate; a non-finite or absurdly large
-// coordinate (a diverged body) maps to cell 0 so that no access leaves the box
-__device__ __forceinline__ int wrap_floor(double v, int n, double& frac)
-{
-    if (!(fabs(v) < 1e15)) { frac = 0.0; return 0; }
-    const double fl = floor(v);
-    frac = v - fl;
-    // fl - n floor(fl / n) is exact for |fl| < 2^52; the guard absorbs a quotient rounded up
-    double m = fl - (double)n * floor(fl / (double)n);
-    if (m >= (double)n) m -= (double)n;
-    if (m < 0.0) m += (double)n;
-    return (int)m;
-}
 
 // Thread t handles corner t & 7 of bead t >> 3.  The dependent loads are kept to four
 // rounds: bead record (offset + body index) -> body record (pose, friction, replica

@@ -112,6 +112,38 @@ template <typename Real>
 void launch_observe(const StepArgs<Real>& a, bool masked, int32_t tile0, int32_t n_tiles,
                     Real* fields, double* partials, double* pops_out, hipStream_t s);
 
+// ------------------------------------------------------------------ reverse pass
+// Arguments of one reverse step (fixed bodies, deterministic fluid).  The forward state of the
+// step is pulled from a.src (post-collision populations of the previous step); the spread
+// force of the step must have been recomputed into a.gforce / a.flags by the coupling kernel.
+template <typename Real>
+struct AdjArgs {
+    StepArgs<Real> a;
+    const Real* lam_next;       // adjoint of the pre-collision populations of the next step
+    Real* lam_cur;              // adjoint of the pre-collision populations of this step
+    Real* lamF;                 // adjoint of the node force density, [axis][node]
+    Real* lamU;                 // adjoint of the sampled node velocities, [axis][node], zeroed
+    uint8_t* uflag;             // 1 byte per node: velocity sampled by a bead, zeroed
+    const Body* bodies;
+    const Bead* beads;
+    const double* bead_force;   // bead forces of this step (lab frame)
+    const double* weights;      // dJ/dF_b of this step, 3 per body (global body order)
+    double* dr;                 // accumulated dJ/d(bead lab position), 3 per bead
+    double* dgam;               // accumulated dJ/dgamma, per bead
+    double* Jpart;              // accumulated objective, per bead
+    int32_t n_beads;
+};
+
+// node pass: transposed streaming + collision VJP (writes lam_cur, lamF, consumes the force)
+template <typename Real>
+void launch_adjoint_step(const AdjArgs<Real>& A, bool masked, hipStream_t s);
+// bead pass: transpose of spreading, friction and interpolation
+template <typename Real>
+void launch_adjoint_beads(const AdjArgs<Real>& A, hipStream_t s);
+// velocity-sampling pass: adds (c_i - u).lamU/rho to lam_cur at sampled nodes, clears lamU
+template <typename Real>
+void launch_adjoint_vel(const AdjArgs<Real>& A, bool masked, hipStream_t s);
+
 }  // namespace lbrb
 
 #endif

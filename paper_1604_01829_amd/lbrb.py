@@ -30,7 +30,8 @@ LB_PRECISION_F32 = 1
 EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "rb_add_raspberry",
             "lb_rb_step", "lb_observables", "lb_body_count", "rb_bead_forces",
             "lb_export_populations", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
-            "lb_set_timing", "lb_kernel_times", "lb_node_counts", "lb_destroy", "lb_last_error"]
+            "lb_set_timing", "lb_kernel_times", "lb_adjoint_workspace_bytes", "lb_rb_adjoint",
+            "lb_node_counts", "lb_destroy", "lb_last_error"]
 
 
 class lb_replica(ctypes.Structure):
@@ -106,6 +107,11 @@ def library():
     L.lb_kernel_times.restype = ctypes.c_int
     L.lb_kernel_times.argtypes = [_VP, _D, ctypes.POINTER(ctypes.c_int64), _D,
                                   ctypes.POINTER(ctypes.c_int64)]
+    L.lb_adjoint_workspace_bytes.restype = ctypes.c_size_t
+    L.lb_adjoint_workspace_bytes.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
+    L.lb_rb_adjoint.restype = ctypes.c_int
+    L.lb_rb_adjoint.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_size_t, _D, _D,
+                                _D, _D]
     L.lb_node_counts.restype = ctypes.c_int
     L.lb_node_counts.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64)]
@@ -211,6 +217,24 @@ def lb_observables(ctx, replica, n_bodies, dev_rho_u=None, check=True):
     return rc, tot, list(bodies)[:n_bodies]
 
 
+def lb_adjoint_workspace_bytes(ctx, n_steps, checkpoint_every):
+    return library().lb_adjoint_workspace_bytes(ctx, int(n_steps), int(checkpoint_every))
+
+
+def lb_rb_adjoint(ctx, n_steps, checkpoint_every, dev_ws, ws_bytes, dJ_dF, n_bodies, n_beads):
+    """Returns (J, dJ/dgamma [n_bodies], dJ/doffsets [n_beads, 3]) in global body/bead order."""
+    w = np.ascontiguousarray(np.asarray(dJ_dF, dtype=np.float64).reshape(-1))
+    if w.size != 3 * n_bodies * int(n_steps):
+        raise ValueError("dJ_dF must hold n_steps * n_bodies * 3 values")
+    J = ctypes.c_double(0.0)
+    dg = np.zeros(max(1, n_bodies))
+    do = np.zeros((max(1, n_beads), 3))
+    rc = library().lb_rb_adjoint(ctx, int(n_steps), int(checkpoint_every), _VP(dev_ws), ws_bytes,
+                                 _dp(w), ctypes.byref(J), _dp(dg), _dp(do))
+    _check(ctx, rc, "lb_rb_adjoint")
+    return J.value, dg[:n_bodies], do[:n_beads]
+
+
 def lb_destroy(ctx):
     library().lb_destroy(ctx)
 
@@ -242,6 +266,7 @@ class Simulation:
         self.ctx = lb_init(params, replicas, aligned, nbytes, self.stream.cuda_stream)
         self.n_bodies = [0] * len(replicas)
         self.n_beads = {}
+        self.body_order = []    # (replica, body id) in the order the bodies were added
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -263,7 +288,23 @@ class Simulation:
                                gamma, fixed)
         self.n_bodies[replica] += 1
         self.n_beads[(replica, bid)] = int(np.asarray(offsets).reshape(-1, 3).shape[0])
+        self.body_order.append((replica, bid))
         return bid
+
+    def adjoint(self, n_steps, dJ_dF, checkpoint_every=20):
+        """Advance n_steps steps and return (J, dJ/dgamma, dJ/doffsets) of
+        J = sum_n sum_b dJ_dF[n, b] . F_b(n) (global body order, body-frame offsets)."""
+        torch = self.torch
+        nbytes = lb_adjoint_workspace_bytes(self.ctx, n_steps, checkpoint_every)
+        if nbytes == 0:
+            raise LBError(LB_ERR_ARG, "invalid adjoint window")
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (ws.data_ptr() + 255) // 256 * 256
+        n_beads = sum(self.n_beads[k] for k in self.body_order)
+        out = lb_rb_adjoint(self.ctx, n_steps, checkpoint_every, aligned, nbytes, dJ_dF,
+                            len(self.body_order), n_beads)
+        del ws
+        return out
 
     def step(self, n=1):
         lb_rb_step(self.ctx, n)
@@ -360,3 +401,46 @@ def simulation_from_workload(wl, precision=None, device="cuda:0", replicas=None,
             sim.add_body(k, b["offsets"], b["mass"], b["inertia"], b["pos"], b["quat"], b["vel"],
                          b["omega"], b["gamma"], b["fixed"])
     return sim
+
+
+# ------------------------------------------------------------------ autograd
+
+def _window_objective_class():
+    import torch
+
+    class WindowObjective(torch.autograd.Function):
+        """J(gamma, offsets) = sum_n sum_b a(n,b) . F_b(n) over a window of steps of a fresh
+        simulation made by ``builder(gamma, offsets)``; the backward pass returns the hand
+        adjoint of the library (lb_rb_adjoint), computed together with J in the forward."""
+
+        @staticmethod
+        def forward(ctx, gamma, offsets, builder, n_steps, weights, checkpoint_every):
+            sim = builder(gamma.detach().cpu().numpy().astype(np.float64),
+                          offsets.detach().cpu().numpy().astype(np.float64))
+            try:
+                J, dg, do = sim.adjoint(n_steps, weights, checkpoint_every)
+            finally:
+                sim.close()
+            ctx.save_for_backward(torch.as_tensor(dg, dtype=gamma.dtype),
+                                  torch.as_tensor(do, dtype=offsets.dtype))
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, grad):
+            dg, do = ctx.saved_tensors
+            return grad * dg, grad * do, None, None, None, None
+
+    return WindowObjective
+
+
+_WO = None
+
+
+def window_objective(gamma, offsets, builder, n_steps, weights, checkpoint_every=20):
+    """Differentiable window objective: gamma [n_bodies] and offsets [n_beads, 3] are torch
+    tensors (CPU, float64); builder(gamma_np, offsets_np) returns a Simulation whose bodies
+    use them.  Gradients flow through the library's reverse pass."""
+    global _WO
+    if _WO is None:
+        _WO = _window_objective_class()
+    return _WO.apply(gamma, offsets, builder, n_steps, weights, checkpoint_every)
