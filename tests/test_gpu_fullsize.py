@@ -1,0 +1,149 @@
+"""Full-size workloads on the GPU, through the C-ABI.
+
+- 256^3 periodic box, 16 thermal ellipsoids: FP64 and FP32 against the FP64 oracle over the
+  first steps (whole fields and every body), then the FP32 run against the FP64 run of the
+  library over all 5000 steps (same noise streams): body positions, orientations, drag.
+- 512 uneven pore replicas with one ellipsoid each, FP32 thermal, all in one batch: sampled
+  replicas against independent oracle boxes, and graph replay of 100 steps against eager
+  launches, bit for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_1604_01829_amd import workloads as W
+from tests.helpers import gpu_from_workload, oracle_from_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _field_errors(gpu, orc, r=0):
+    """Max errors of rho and u over fluid nodes, and of every body's state."""
+    _, bg, fg, rc = gpu.observables(r, fields=True, check=False)
+    fo = orc.fields()
+    fluid = fo[..., 0] != 0.0
+    out = {"rc": rc,
+           "rho": float(np.abs(fg[..., 0][fluid] - fo[..., 0][fluid]).max()),
+           "u": float(np.abs(fg[..., 1:][fluid] - fo[..., 1:][fluid]).max()),
+           "u_scale": float(np.abs(fo[..., 1:][fluid]).max()),
+           "solid_zero": bool(np.all(fg[~fluid] == 0.0))}
+    for k in ("pos", "quat", "vel", "omega", "force", "torque"):
+        out[k] = 0.0
+    out["vel_scale"] = out["omega_scale"] = out["force_scale"] = out["torque_scale"] = 0.0
+    for b in range(orc.n_bodies):
+        so, sg = orc.body_state(b), bg[b]
+        for k in ("pos", "quat", "vel", "omega", "force", "torque"):
+            out[k] = max(out[k], float(np.abs(sg[k] - so[k]).max()))
+        fb = orc.bead_forces(b)
+        rad = np.linalg.norm(orc._offsets[b], axis=1)
+        out["force_scale"] = max(out["force_scale"], float(np.linalg.norm(fb, axis=1).sum()))
+        out["torque_scale"] = max(out["torque_scale"],
+                                  float((rad * np.linalg.norm(fb, axis=1)).sum()))
+        out["vel_scale"] = max(out["vel_scale"], float(np.abs(so["vel"]).max()))
+        out["omega_scale"] = max(out["omega_scale"], float(np.abs(so["omega"]).max()))
+    return out
+
+
+def _check(e, tol_u, tol_rho, tol_body):
+    assert e["rc"] == 0 and e["solid_zero"]
+    assert e["rho"] <= tol_rho
+    assert e["u"] <= tol_u * e["u_scale"]
+    assert e["pos"] <= tol_body and e["quat"] <= tol_body
+    for k in ("vel", "omega", "force", "torque"):
+        assert e[k] <= tol_u * max(e[k + "_scale"], 1e-14) + 1e-15, k
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_ellipsoids_256_first_steps_match_oracle(precision):
+    wl = W.workload(3)
+    print(f"256^3, 16 ellipsoids, {precision}: oracle and GPU, 2 steps", flush=True)
+    gpu = gpu_from_workload(wl, precision=precision)
+    gpu.set_graph_steps(0)
+    orc = oracle_from_workload(wl)
+    for s in (1, 2):
+        gpu.step(1)
+        orc.step(1)
+        e = _field_errors(gpu, orc)
+        print(f"  step {s}:", {k: f"{v:.3g}" for k, v in e.items() if isinstance(v, float)},
+              flush=True)
+        if precision == "f64":
+            _check(e, 1e-11, 1e-13, 1e-12)
+        else:
+            _check(e, 1e-5, 1e-6, 1e-6)
+    gpu.close()
+
+
+def test_ellipsoids_256_fp32_follows_fp64_over_the_full_run():
+    """Precision study: the FP32 shifted-population run against the FP64 run over the 5000
+    steps of the workload, same seeds (identical noise draws)."""
+    wl = W.workload(3)
+    T = wl["steps"]
+    sims = {p: gpu_from_workload(wl, precision=p) for p in ("f64", "f32")}
+    n_b = len(wl["replicas"][0]["bodies"])
+    traj = {p: [] for p in sims}
+    drag = {p: np.zeros((n_b, 3)) for p in sims}
+    chunk = 100
+    for done in range(0, T, chunk):
+        for p, s in sims.items():
+            s.step(chunk)
+            _, bs, _, rc = s.observables(0)
+            assert rc == 0
+            traj[p].append([(b["pos"].copy(), b["quat"].copy()) for b in bs])
+            drag[p] += np.array([b["force"] for b in bs])
+        if (done // chunk) % 10 == 9:
+            print(f"  step {done + chunk}", flush=True)
+    dpos = max(float(np.abs(a[0] - b[0]).max())
+               for ta, tb in zip(traj["f32"], traj["f64"]) for a, b in zip(ta, tb))
+    dq = max(float(np.abs(a[1] - b[1]).max())
+             for ta, tb in zip(traj["f32"], traj["f64"]) for a, b in zip(ta, tb))
+    moved = max(float(np.abs(traj["f64"][-1][b][0] - wl["replicas"][0]["bodies"][b]["pos"]).max())
+                for b in range(n_b))
+    ddrag = float(np.abs(drag["f32"] - drag["f64"]).max() / np.abs(drag["f64"]).max())
+    print(f"  FP32 vs FP64 over {T} steps: max |dR| {dpos:.3g} (bodies moved up to {moved:.3g}),"
+          f" max |dq| {dq:.3g}, sampled drag sum rel {ddrag:.3g}", flush=True)
+    assert moved > 10 * dpos
+    assert dpos <= 2e-5 and dq <= 5e-7 and ddrag <= 1e-6
+    for s in sims.values():
+        s.close()
+
+
+def _batch():
+    return W.workload(4)
+
+
+def test_512_replicas_sampled_against_oracle():
+    wl = _batch()
+    reps = wl["replicas"]
+    sides = np.array([r["shape"][0] for r in reps])
+    print(f"512 replicas: {int(sum(np.prod(r['shape']) for r in reps))} nodes", flush=True)
+    gpu = gpu_from_workload(wl)
+    gpu.set_graph_steps(0)
+    steps = 12
+    gpu.step(steps)
+    rng = np.random.default_rng(4)
+    sample = sorted({int(np.argmin(sides)), int(np.argmax(sides)), 0, len(reps) - 1,
+                     *rng.choice(len(reps), 4, replace=False).tolist()})
+    for r in sample:
+        orc = oracle_from_workload(wl, r)
+        orc.step(steps)
+        e = _field_errors(gpu, orc, r)
+        print(f"  replica {r} side {sides[r]}:",
+              {k: f"{v:.3g}" for k, v in e.items() if isinstance(v, float)}, flush=True)
+        _check(e, 1e-5, 1e-6, 1e-6)
+    gpu.close()
+
+
+def test_512_replicas_graph_replay_equals_eager():
+    wl = _batch()
+    a = gpu_from_workload(wl)
+    b = gpu_from_workload(wl)
+    a.set_graph_steps(100)
+    b.set_graph_steps(0)
+    a.step(200)
+    b.step(200)
+    for r in (0, 137, 511):
+        assert np.array_equal(a.fields(r), b.fields(r))
+        _, ba, _, _ = a.observables(r)
+        _, bb, _, _ = b.observables(r)
+        assert np.array_equal(ba[0]["pos"], bb[0]["pos"])
+    a.close()
+    b.close()
