@@ -10,11 +10,24 @@ and resident in HBM before timing; the steps run as HIP-graph replays.
 
 Prints one JSON line.  `value` = fluid-node updates per second / 1e6 (MLUPS) over the timed
 steps.  `roofline` is for the dominant kernel, node_step (the update of every fluid node; its
-few leading workgroups finish the bodies): algorithmic bytes 152 B (FP32) per fluid node (19
-populations read + written) divided by its mean duration from HIP events recorded around each
-launch on the library's stream, in a separate eager window of the same run.  `cpu_baseline` times the FP64 CPU oracle on a few steps of the same box.
+few leading workgroups finish the bodies): algorithmic bytes 152 B (FP32) or 304 B (FP64) per
+fluid node (19 populations read + written) divided by its mean duration from HIP events
+recorded around each launch on the library's stream, in a separate eager window of the same
+run.  `cpu_baseline` times the FP64 CPU oracle on a few steps of the same box.
+
+`compare` (default workload only) measures, on the same GPU in the same process:
+  fp64            the same workload with FP64 populations;
+  batched_fp32    512 uneven pore replicas (sides 32-64, one ellipsoid each, thermal) in one
+                  batch, 100-step graph replays, with its node_step roofline;
+  plain_fp64      a sample of those replicas run one context at a time in FP64;
+  box256_fp32/64  the 256^3 periodic box with 16 ellipsoids (larger than the on-package
+                  cache, so its node_step bandwidth is HBM bandwidth);
+  adjoint         64^3 box, fixed sphere of 401 beads, 200-step window with checkpoints every
+                  20 steps: the reverse pass (forward + recompute + reverse) against 200
+                  forward steps.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +35,7 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
+WORKLOAD_TAGS = {2: "pore128x128x256", 3: "box256", 4: "batch512"}
 
 
 def parse():
@@ -30,8 +44,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4],
+                    help="2 = pore with 32 spheres (default), 3 = 256^3 box with 16 "
+                         "ellipsoids, 4 = 512 pore replicas")
     ap.add_argument("--timing-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--graph-steps", type=int, default=100,
                     help="steps per HIP-graph replay (0 = eager launches, for profilers)")
@@ -45,21 +63,23 @@ def algorithmic_bytes_per_node(precision):
     return 19 * 2 * (4 if precision == "f32" else 8)
 
 
+def kernel_source_hash():
+    """sha256 (first 16 hex) of the sources the step kernels are built from."""
+    h = hashlib.sha256()
+    for name in ("lbrb_kernels.hip", "lbrb_core.h", "lbrb_device.h", "lbrb_layout.h"):
+        h.update(open(os.path.join(ROOT, "paper_1604_01829_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profiles(kernel_tag):
-    """HBM bytes per launch measured with rocprofv3 PMC counters (profiles/*.json), if the
-    record matches the current kernel source; else None."""
+    """HBM bytes per launch measured with rocprofv3 PMC counters (profiles/traffic.json), if
+    the record matches the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path)).get(kernel_tag)
-        if not rec:
-            return None
-        import hashlib
-        src = open(os.path.join(ROOT, "paper_1604_01829_amd", "csrc", "lbrb_kernels.hip"),
-                   "rb").read() + open(os.path.join(ROOT, "paper_1604_01829_amd", "csrc",
-                                                    "lbrb_core.h"), "rb").read()
-        if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_hash"):
+        if not rec or kernel_source_hash() != rec.get("source_hash"):
             return None
         return rec.get("bytes_per_launch")
     except Exception:
@@ -88,6 +108,123 @@ def cpu_baseline(wl, seconds):
             "sample": f"{k} steps (after 1 sizing step) of the same box, FP64, {dt:.1f} s"}
 
 
+def measure(sim, steps, warmup, timing_steps, graph_steps, precision):
+    """Timed graph-replayed steps, then an eager window with per-launch HIP events."""
+    import torch
+    n_nodes = n_fluid = 0
+    for r in range(len(sim.shapes)):
+        a, b = sim.node_counts(r)
+        n_nodes += a
+        n_fluid += b
+    sim.set_graph_steps(graph_steps)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    finite = True
+    for r in range(len(sim.shapes)):
+        t, _, _, rc = sim.observables(r, check=False)
+        finite = finite and bool(t["finite"]) and rc == 0
+    sim.set_timing(True)
+    sim.step(timing_steps)
+    kt = sim.kernel_times()
+    sim.set_timing(False)
+    node_s = kt["node_ms"] / max(1, kt["node_launches"]) / 1e3
+    couple_s = kt["couple_ms"] / max(1, kt["couple_launches"]) / 1e3
+    bpn = algorithmic_bytes_per_node(precision)
+    achieved = bpn * n_fluid / node_s / 1e9
+    return {"mlups": n_fluid * steps / dt / 1e6, "all_node_mlups": n_nodes * steps / dt / 1e6,
+            "ms_per_step": dt / steps * 1e3, "n_fluid": n_fluid, "n_nodes": n_nodes,
+            "finite": finite, "node_us": node_s * 1e6, "couple_us": couple_s * 1e6,
+            "node_gbs": achieved, "bytes_per_launch": bpn * n_fluid}
+
+
+def compare_runs(args):
+    import numpy as np
+    import torch
+    from paper_1604_01829_amd import lbrb
+    from paper_1604_01829_amd import workloads as W
+
+    out = {}
+    # same pore workload, FP64 populations
+    wl2 = W.workload(2)
+    sim = lbrb.simulation_from_workload(wl2, precision="f64")
+    m = measure(sim, 1000, 100, 100, 100, "f64")
+    sim.close()
+    out["fp64"] = {"mlups": round(m["mlups"], 1), "ms_per_step": round(m["ms_per_step"], 5),
+                   "node_step_us": round(m["node_us"], 2),
+                   "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4)}
+    # 512 uneven pore replicas in one batch, FP32
+    wl4 = W.workload(4)
+    sim = lbrb.simulation_from_workload(wl4, precision="f32")
+    m = measure(sim, 400, 100, 100, 100, "f32")
+    sim.close()
+    out["batched_fp32"] = {
+        "replicas": len(wl4["replicas"]), "fluid_nodes": m["n_fluid"], "all_nodes": m["n_nodes"],
+        "mlups": round(m["mlups"], 1), "all_node_mlups": round(m["all_node_mlups"], 1),
+        "ms_per_step": round(m["ms_per_step"], 5), "node_step_us": round(m["node_us"], 2),
+        "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
+        "couple_us": round(m["couple_us"], 2), "finite": m["finite"]}
+    del sim
+    torch.cuda.empty_cache()
+    # the plain path: a sample of the same replicas, one FP64 context at a time
+    rng = np.random.default_rng(1)
+    sample = sorted(rng.choice(len(wl4["replicas"]), 16, replace=False).tolist())
+    upd, tsum = 0, 0.0
+    for r in sample:
+        sim = lbrb.simulation_from_workload(wl4, precision="f64", replicas=[r])
+        sim.set_graph_steps(100)
+        sim.step(100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(200)
+        torch.cuda.synchronize()
+        tsum += time.perf_counter() - t0
+        upd += sim.node_counts(0)[1] * 200
+        sim.close()
+    out["plain_fp64"] = {"replicas_sampled": len(sample), "mlups": round(upd / tsum / 1e6, 1)}
+    out["batched_fp32_over_plain_fp64"] = round(out["batched_fp32"]["mlups"] /
+                                                out["plain_fp64"]["mlups"], 2)
+    # 256^3 box, 16 ellipsoids: HBM-resident
+    wl3 = W.workload(3)
+    for prec in ("f32", "f64"):
+        sim = lbrb.simulation_from_workload(wl3, precision=prec)
+        m = measure(sim, 400, 100, 100, 100, prec)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        out["box256_" + prec] = {"mlups": round(m["mlups"], 1),
+                                 "ms_per_step": round(m["ms_per_step"], 5),
+                                 "node_step_us": round(m["node_us"], 2),
+                                 "node_step_gbs": round(m["node_gbs"], 1),
+                                 "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
+                                 "traffic": traffic_from_profiles(f"node_step_{prec}_box256")}
+    # reverse pass on the fixed sphere in uniform flow
+    wl5 = W.workload(5)
+    wl5["params"]["kT"] = 0.0
+    T, K = 200, 20
+    a = np.zeros((T, 1, 3))
+    a[:, 0, 0] = 1.0 / T
+    sim = lbrb.simulation_from_workload(wl5, precision="f32")
+    sim.set_graph_steps(100)
+    sim.step(200)
+    sim.adjoint(T, a, K)                    # warm-up of the reverse pass
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(T)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sim.adjoint(T, a, K)
+    t_adj = time.perf_counter() - t0
+    sim.close()
+    out["adjoint"] = {"window_steps": T, "checkpoint_every": K, "forward_ms": round(t_fwd * 1e3, 3),
+                      "adjoint_ms": round(t_adj * 1e3, 3), "ratio": round(t_adj / t_fwd, 2)}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -107,65 +244,50 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize(dev)
         del a, b
-    wl = W.workload(2)
+    wl = W.workload(args.workload)
     sim = lbrb.simulation_from_workload(wl, precision=args.precision)
-    n_nodes, n_fluid = sim.node_counts(0)
-    n_beads = sum(b["offsets"].shape[0] for b in wl["replicas"][0]["bodies"])
-    sim.set_graph_steps(args.graph_steps)
-
-    sim.step(args.warmup)
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    torch.cuda.synchronize(dev)
-    dt = time.perf_counter() - t0
-    t, _, _, rc = sim.observables(0, check=False)
-    mlups = n_fluid * args.steps / dt / 1e6
-
-    # kernel timing window: eager launches bracketed by HIP events on the library's stream
-    sim.set_timing(True)
-    sim.step(args.timing_steps)
-    kt = sim.kernel_times()
-    sim.set_timing(False)
-    # node_step: every fluid node's update (its leading workgroups finish the bodies)
-    node_s = kt["node_ms"] / max(1, kt["node_launches"]) / 1e3
-    # couple: bead coupling and force spreading
-    couple_s = kt["couple_ms"] / max(1, kt["couple_launches"]) / 1e3
-    bpn = algorithmic_bytes_per_node(args.precision)
-    achieved = bpn * n_fluid / node_s / 1e9
-    tag = f"node_step_{args.precision}_pore128x128x256"
-    traffic = traffic_from_profiles(tag)
-
+    n_beads = sum(b["offsets"].shape[0] for r in wl["replicas"] for b in r["bodies"])
+    n_bodies = sum(len(r["bodies"]) for r in wl["replicas"])
+    m = measure(sim, args.steps, args.warmup, args.timing_steps, args.graph_steps, args.precision)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    tag = f"node_step_{args.precision}_{WORKLOAD_TAGS[args.workload]}"
+    names = {2: "pore 128x128x256 (radius 40, 1,286,144 fluid nodes), 32 raspberry spheres "
+                "R~U[2,6], thermal kT=4e-5",
+             3: "256^3 periodic box, 16 raspberry ellipsoids, thermal kT=4e-5",
+             4: "512 uneven pore replicas (sides 32-64, pore radius 0.4 side), one ellipsoid "
+                "each, thermal kT=4e-5"}
     out = {
         "metric": "MLUPS (D3Q19 LB + raspberry coupling) and % HBM roofline",
-        "value": round(mlups, 1),
+        "value": round(m["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "ms_per_step": round(m["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": "pore 128x128x256 (radius 40, 1,286,144 fluid nodes), 32 raspberry "
-                               "spheres R~U[2,6], thermal kT=4e-5, FP32 shifted populations"
-                   if args.precision == "f32" else "same pore workload, FP64 populations",
-                   "fluid_nodes": n_fluid, "all_nodes": n_nodes, "beads": n_beads,
-                   "bodies": len(wl["replicas"][0]["bodies"]), "graph_steps": args.graph_steps,
-                   "finite_after_run": bool(t["finite"]) and rc == 0},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "node_step",
-                     "algorithmic_bytes_per_launch": bpn * n_fluid,
-                     "mean_launch_us": round(node_s * 1e6, 3),
-                     "couple_mean_launch_us": round(couple_s * 1e6, 3)},
+        "config": {"workload": names[args.workload] + (", FP32 shifted populations"
+                                                       if args.precision == "f32"
+                                                       else ", FP64 populations"),
+                   "fluid_nodes": m["n_fluid"], "all_nodes": m["n_nodes"],
+                   "all_node_mlups": round(m["all_node_mlups"], 1), "beads": n_beads,
+                   "bodies": n_bodies, "graph_steps": args.graph_steps,
+                   "finite_after_run": m["finite"]},
+        "roofline": {"bound": "hbm", "achieved": round(m["node_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profiles(tag), "kernel": "node_step",
+                     "algorithmic_bytes_per_launch": m["bytes_per_launch"],
+                     "mean_launch_us": round(m["node_us"], 3),
+                     "couple_mean_launch_us": round(m["couple_us"], 3)},
     }
-    sim.close()
-    del sim
-    torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
+    if args.workload == 2 and not args.no_compare:
+        out["compare"] = compare_runs(args)
+    if not args.no_cpu_baseline and args.workload == 2:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

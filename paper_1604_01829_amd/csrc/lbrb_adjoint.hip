@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kNodeBlock) void adj_node_kernel(const AdjArgs<Real
     Real lF[3];
     collide_vjp<Real>(a.cp, d, F, lam, lF);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) A.lam_cur[(int64_t)i * a.N + g] = lam[i];
+    for (int i = 0; i < Q; ++i) A.lam_cur[pop_at(i, g)] = lam[i];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) A.lamF[(int64_t)ax * a.N + g] = lF[ax];
 }
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kNodeBlock) void adj_vel_kernel(const AdjArgs<Real>
     for (int i = 0; i < Q; ++i) {
         const Real acc = ((Real)cx_of(i) - u[0]) * lu[0] + ((Real)cy_of(i) - u[1]) * lu[1] +
                          ((Real)cz_of(i) - u[2]) * lu[2];
-        A.lam_cur[(int64_t)i * a.N + g] += acc * ir;
+        A.lam_cur[pop_at(i, g)] += acc * ir;
     }
     A.uflag[g] = 0;
 }

@@ -93,7 +93,7 @@ __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
             const bool fluid = (unsigned)off < (unsigned)ln[r9];
             const int64_t g = fluid ? R.base + st[r9] + off : own;
             const int p = fluid ? i : opposite_of(i);
-            d[i] = src[(int64_t)p * N + g];
+            d[i] = src[pop_at(p, g)];
         }
     } else {
         const int xm = wrap1(x - 1, R.nx), xp = wrap1(x + 1, R.nx);
@@ -106,7 +106,7 @@ __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
             const int ys = cy == 0 ? y : (cy > 0 ? ym : yp);
             const int zs = cz == 0 ? z : (cz > 0 ? zm : zp);
             const int64_t g = R.base + xs + (int64_t)R.nx * (ys + (int64_t)R.ny * zs);
-            d[i] = src[(int64_t)i * N + g];
+            d[i] = src[pop_at(i, g)];
         }
     }
 }

@@ -58,7 +58,7 @@ __device__ __forceinline__ void update_node(const StepArgs<Real>& a, const Repli
 
     Real* __restrict__ dst = a.dst;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dst[(int64_t)i * a.N + g] = d[i];
+    for (int i = 0; i < Q; ++i) dst[pop_at(i, g)] = d[i];
 }
 
 // one workgroup per body: sum the bead forces and torques (shuffle + LDS tree, fixed order),
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kNodeBlock) void init_equilibrium_kernel(
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const double cu = cx_of(i) * ux + cy_of(i) * uy + cz_of(i) * uz;
-        f[(int64_t)i * N + g] = (Real)(weight_of(i) * r0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+        f[pop_at(i, g)] = (Real)(weight_of(i) * r0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
     }
 }
 

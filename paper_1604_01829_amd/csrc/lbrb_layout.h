@@ -7,11 +7,15 @@
 // (start, xlo, len) of every row (len = 0 for a row without fluid), so a neighbour lookup is
 // one load; rows[] lists the non-empty rows in storage order for the thread -> node map.  A replica without boundary nodes is
 // "dense": every row is full and the local index is x + nx (y + ny z), computed without
-// tables.  Populations are structure-of-arrays: population i of global node g sits at
-// f[i * N + g], N = total padded node count, g = replica base + local index; each replica's
-// base is a multiple of 256.  Two such buffers alternate between steps: one holds the
-// post-collision populations of the previous step, the kernel pulls from it and writes the
-// next post-collision state into the other.
+// tables.  Populations are blocked structure-of-arrays: the nodes are cut into blocks of 256
+// consecutive global indices g (g = replica base + local index; each replica's base is a
+// multiple of 256, N = total padded node count), and a block stores its 19 populations one
+// after the other, 256 values each: population i of node g sits at
+// f[((g / 256) * 19 + i) * 256 + g % 256] (pop_at below).  A workgroup's stores fill one
+// contiguous 19 x 256 block, and the loads of a wavefront stay within a few such blocks,
+// which keeps the DRAM streams of the 38 population accesses close together.  Two such
+// buffers alternate between steps: one holds the post-collision populations of the previous
+// step, the kernel pulls from it and writes the next post-collision state into the other.
 #ifndef LBRB_LAYOUT_H
 #define LBRB_LAYOUT_H
 
@@ -25,6 +29,14 @@ namespace lbrb {
 constexpr int kNodeBlock = 256;   // threads (= nodes) per node-update workgroup
 constexpr int kBeadLanes = 8;     // threads per bead in the coupling kernel (one per corner)
 constexpr int kCoupleBlock = 256;
+constexpr int kPopBlockLog = 8;   // populations are blocked per 256 nodes
+
+// index of population i of global node g in a population buffer
+__host__ __device__ __forceinline__ int64_t pop_at(int i, int64_t g)
+{
+    const int64_t blk = g >> kPopBlockLog;
+    return ((blk * Q + i) << kPopBlockLog) + (g & ((1 << kPopBlockLog) - 1));
+}
 // A step is two launches on one stream: the bead coupling, then the node update whose
 // leading workgroups finish the bodies (force/torque sums, second half kick).
 
