@@ -34,7 +34,7 @@ struct Plan {
     int64_t bead_cap = 0, body_cap = 0;
     int gforce_words = 3;     // fixed-point words per node: 3 axes x (1 in FP32, 2 in FP64)
     size_t off_hdr, off_reps, off_rows, off_rowinfo, off_tiles_d, off_tiles_m, off_fa, off_fb,
-        off_gforce, off_flags, off_bodies, off_bead_off, off_bead_body, off_bead_force,
+        off_gforce, off_flags, off_bodies, off_bead_off, off_bead_rec, off_bead_force,
         off_bead_torque, off_partials, total;
 };
 
@@ -85,7 +85,7 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
     pl.off_flags = take(pl.N);
     pl.off_bodies = take(sizeof(Body) * std::max<int64_t>(pl.body_cap, 1));
     pl.off_bead_off = take(sizeof(Bead) * std::max<int64_t>(pl.bead_cap, 1));
-    pl.off_bead_body = 0;
+    pl.off_bead_rec = take(sizeof(BeadRec) * std::max<int64_t>(pl.bead_cap, 1));
     pl.off_bead_force = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
     pl.off_bead_torque = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
     pl.off_partials = take(sizeof(double) * 5 * pl.tiles_cap);
@@ -121,6 +121,7 @@ struct lb_ctx {
     uint8_t* flags = nullptr;
     Body* d_bodies = nullptr;
     Bead* d_beads = nullptr;
+    BeadRec* d_recs = nullptr;
     double* d_bead_force = nullptr;
     double* d_bead_torque = nullptr;
     double* d_partials = nullptr;
@@ -219,14 +220,25 @@ StepArgs<Real> step_args(const lb_ctx* c, int group, int src_buf)
 CoupleArgs couple_args(const lb_ctx* c)
 {
     CoupleArgs ca{};
-    ca.bodies = c->d_bodies;
-    ca.beads = c->d_beads;
+    ca.recs = c->d_recs;
     ca.bead_force = c->d_bead_force;
     ca.bead_torque = c->d_bead_torque;
     ca.n_beads = c->n_beads;
     ca.kT = c->p.kT;
     ca.hdr = c->hdr;
     return ca;
+}
+
+BodyArgs body_args(const lb_ctx* c)
+{
+    BodyArgs ba{};
+    ba.bodies = c->d_bodies;
+    ba.beads = c->d_beads;
+    ba.recs = c->d_recs;
+    ba.bead_force = c->d_bead_force;
+    ba.bead_torque = c->d_bead_torque;
+    ba.n_bodies = c->n_bodies;
+    return ba;
 }
 
 bool any_masked(const lb_ctx* c) { return !c->tiles[1].empty(); }
@@ -270,8 +282,8 @@ hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* st
         if (ag[g].n_tiles == 0 && !(last && !finished)) continue;
         EventPair e{};
         if (timed) { e = get_pair(c); note(hipEventRecord(e.a, s)); }
-        launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, finished ? nullptr : c->d_bodies,
-                               c->d_bead_force, c->d_bead_torque, c->n_bodies, s);
+        const BodyArgs ba = body_args(c);
+        launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, finished ? nullptr : &ba, s);
         note(hipGetLastError());
         if (timed) { note(hipEventRecord(e.b, s)); c->ev_node.push_back(e); }
         finished = true;
@@ -462,8 +474,7 @@ void enqueue_replay(lb_ctx* c, hipStream_t s, const void* src, void* dst, int64_
     if (c->n_beads > 0) launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], couple_args(c), s);
     for (int g = 0; g < 2; ++g)
         if (ag[g].n_tiles > 0)
-            launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, nullptr, c->d_bead_force,
-                                   c->d_bead_torque, 0, s);
+            launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, nullptr, s);
 }
 
 // one reverse step at forward step `step` (index n of the window), forward state pulled from src
@@ -584,6 +595,7 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     c->flags = (uint8_t*)(c->ws + pl.off_flags);
     c->d_bodies = (Body*)(c->ws + pl.off_bodies);
     c->d_beads = (Bead*)(c->ws + pl.off_bead_off);
+    c->d_recs = (BeadRec*)(c->ws + pl.off_bead_rec);
     c->d_bead_force = (double*)(c->ws + pl.off_bead_force);
     c->d_bead_torque = (double*)(c->ws + pl.off_bead_torque);
     c->d_partials = (double*)(c->ws + pl.off_partials);
@@ -687,6 +699,7 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
                                   hipMemcpyHostToDevice, c->stream));
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->pose_stale = true;   // the bead records carry the replica geometry
     return init_fluid(c, replica);
 }
 
@@ -755,7 +768,7 @@ int lb_rb_step(lb_ctx* c, int32_t n_steps)
     if (n_steps < 0) return fail(c, LB_ERR_ARG, "negative step count");
     if (n_steps == 0) return LB_OK;
     if (c->pose_stale) {
-        launch_body_predict(c->d_bodies, c->n_bodies, (int)(c->step & 1), c->stream);
+        launch_body_predict(body_args(c), (int)(c->step & 1), c->stream);
         HIP_TRY(c, hipGetLastError());
         c->pose_stale = false;
     }
@@ -1029,7 +1042,7 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_dg, 0, sizeof(double) * nb, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_J, 0, sizeof(double) * nb, s));
     if (c->pose_stale) {
-        launch_body_predict(c->d_bodies, c->n_bodies, (int)(c->step & 1), s);
+        launch_body_predict(body_args(c), (int)(c->step & 1), s);
         HIP_TRY(c, hipGetLastError());
         c->pose_stale = false;
     }

@@ -58,6 +58,42 @@ __device__ __forceinline__ void locate(const ReplicaDesc& R, const RowDesc* __re
     }
 }
 
+// Fluid runs of the 9 rows (y - cy, z - cz), cy, cz in {-1, 0, 1}, at index (cy+1) + 3 (cz+1).
+struct Rows9 {
+    int32_t st[9], lo[9], ln[9];
+};
+
+__device__ __forceinline__ void load_rows9(const RowDesc* __restrict__ rowinfo, int32_t row_base,
+                                           int ny, int nz, int y, int z, Rows9& rw)
+{
+#pragma unroll
+    for (int r9 = 0; r9 < 9; ++r9) {
+        const int cy = r9 % 3 - 1, cz = r9 / 3 - 1;
+        const int yy = wrap1(y - cy, ny), zz = wrap1(z - cz, nz);
+        const RowDesc rd = rowinfo[row_base + yy + ny * zz];
+        rw.st[r9] = rd.start; rw.lo[r9] = rd.xlo; rw.ln[r9] = rd.len;
+    }
+}
+
+// Masked gather over preloaded rows: element i from x - S c_i (periodic in x) if that node is
+// fluid, else population opposite(i) of the node itself (own = its global index).
+template <typename Real, int S>
+__device__ __forceinline__ void pull_rows(const Real* __restrict__ src, int64_t base, int nx,
+                                          const Rows9& rw, int x, int64_t own, Real d[Q])
+{
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = S * cx_of(i), cy = S * cy_of(i), cz = S * cz_of(i);
+        const int r9 = (cy + 1) + 3 * (cz + 1);
+        const int xs = wrap1(x - cx, nx);
+        const int off = xs - rw.lo[r9];
+        const bool fluid = (unsigned)off < (unsigned)rw.ln[r9];
+        const int64_t g = fluid ? base + rw.st[r9] + off : own;
+        const int p = fluid ? i : opposite_of(i);
+        d[i] = src[pop_at(p, g)];
+    }
+}
+
 // Pre-collision populations of node (x,y,z) (shifted), pulled from the post-collision
 // buffer: population i comes from x - c_i, or, if that node is a boundary node, from the
 // opposite population of the node itself (halfway bounce-back).  With S = -1 the same gather
@@ -71,30 +107,20 @@ __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
 {
     const int64_t own = R.base + local;
     if constexpr (MASKED) {
-        // fluid runs of the 9 rows (y - S cy, z - S cz): index (S cy + 1) + 3 (S cz + 1)
-        int32_t st[9], lo[9], ln[9];
+        // the node's own row is known; the other 8 rows (y - S cy, z - S cz) are loaded
+        Rows9 rw;
 #pragma unroll
         for (int r9 = 0; r9 < 9; ++r9) {
             const int cy = r9 % 3 - 1, cz = r9 / 3 - 1;
             if (cy == 0 && cz == 0) {
-                st[r9] = self.start; lo[r9] = self.xlo; ln[r9] = self.len;
+                rw.st[r9] = self.start; rw.lo[r9] = self.xlo; rw.ln[r9] = self.len;
             } else {
                 const int yy = wrap1(y - cy, R.ny), zz = wrap1(z - cz, R.nz);
                 const RowDesc rd = rowinfo[R.row_base + yy + R.ny * zz];
-                st[r9] = rd.start; lo[r9] = rd.xlo; ln[r9] = rd.len;
+                rw.st[r9] = rd.start; rw.lo[r9] = rd.xlo; rw.ln[r9] = rd.len;
             }
         }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int cx = S * cx_of(i), cy = S * cy_of(i), cz = S * cz_of(i);
-            const int r9 = (cy + 1) + 3 * (cz + 1);
-            const int xs = wrap1(x - cx, R.nx);
-            const int off = xs - lo[r9];
-            const bool fluid = (unsigned)off < (unsigned)ln[r9];
-            const int64_t g = fluid ? R.base + st[r9] + off : own;
-            const int p = fluid ? i : opposite_of(i);
-            d[i] = src[pop_at(p, g)];
-        }
+        pull_rows<Real, S>(src, R.base, R.nx, rw, x, own, d);
     } else {
         const int xm = wrap1(x - 1, R.nx), xp = wrap1(x + 1, R.nx);
         const int ym = wrap1(y - 1, R.ny), yp = wrap1(y + 1, R.ny);

@@ -2,19 +2,19 @@
 //
 // A step is two launches on one stream:
 //   couple     : the bead coupling of eq. (latticeboltzmannfriction) of the paper: 8 threads
-//                per bead, one per corner of the trilinear stencil; bead kinematics from the
-//                body's pose of the step, fluid velocity from the corner node's pulled
-//                populations, lane-butterfly sum, friction + noise, spreading of the opposite
-//                force with 64-bit fixed-point atomics (order-independent, hence
+//                per bead, one per corner of the trilinear stencil; bead position and velocity
+//                from the bead's record of the step, fluid velocity from the corner node's
+//                pulled populations, lane-butterfly sum, friction + noise, spreading of the
+//                opposite force with 64-bit fixed-point atomics (order-independent, hence
 //                deterministic), per-bead force and torque.
 //   node_step  : the fused lattice-Boltzmann update of every fluid node (Sec. 1.1) -- pull of
 //                the 19 populations along the links with halfway bounce-back at boundary
 //                nodes, moments, multiple-relaxation-time collision with the external and
 //                spread force and thermal noise, back-transform, store; one thread per node,
-//                256 nodes per workgroup, SoA loads/stores coalesced along x.  Its leading
-//                workgroups finish the raspberries: per-body force/torque sums (shuffle +
-//                LDS tree, fixed order), torque into the body frame, second half kick
-//                (Sec. 2.3), pose of the next step.
+//                256 nodes per workgroup (one population block), loads/stores coalesced
+//                along x.  Its leading workgroups finish the raspberries: per-body
+//                force/torque sums (shuffle + LDS tree, fixed order), torque into the body
+//                frame, second half kick (Sec. 2.3), pose and bead records of the next step.
 #include <hip/hip_runtime.h>
 
 #include "lbrb_device.h"
@@ -61,12 +61,50 @@ __device__ __forceinline__ void update_node(const StepArgs<Real>& a, const Repli
     for (int i = 0; i < Q; ++i) dst[pop_at(i, g)] = d[i];
 }
 
+// bead records of body b for the step whose pose is P (all threads of the workgroup)
+__device__ __forceinline__ void write_bead_records(const Body& B, const Pose& P,
+                                                   const Bead* __restrict__ beads,
+                                                   BeadRec* __restrict__ recs)
+{
+    const BodyBox& X = B.box;
+    for (int k = threadIdx.x; k < B.n_beads; k += blockDim.x) {
+        const int e = B.first_bead + k;
+        const Bead bd = beads[e];
+        BeadRec o;
+        for (int ax = 0; ax < 3; ++ax) {
+            o.dv[ax] = P.rot[3 * ax] * bd.off[0] + P.rot[3 * ax + 1] * bd.off[1] +
+                       P.rot[3 * ax + 2] * bd.off[2];
+            o.r[ax] = P.pos[ax] + o.dv[ax];
+        }
+        if (B.fixed) {
+            o.v[0] = o.v[1] = o.v[2] = 0.0;
+        } else {
+            const double* w = P.omega_lab;
+            o.v[0] = P.vel[0] + (w[1] * o.dv[2] - w[2] * o.dv[1]);
+            o.v[1] = P.vel[1] + (w[2] * o.dv[0] - w[0] * o.dv[2]);
+            o.v[2] = P.vel[2] + (w[0] * o.dv[1] - w[1] * o.dv[0]);
+        }
+        o.gamma = B.gamma;
+        o.noise_amp = B.noise_amp;
+        o.noise_idx = B.first_bead_in_replica + k;
+        o.row_base = X.row_base;
+        o.nx = X.nx; o.ny = X.ny; o.nz = X.nz; o.masked = X.masked;
+        o.base = X.base;
+        o.key0 = X.key0; o.key1 = X.key1;
+        recs[e] = o;
+    }
+}
+
 // one workgroup per body: sum the bead forces and torques (shuffle + LDS tree, fixed order),
-// turn the torque into the body frame, second half kick, pose of the next step
-__device__ __forceinline__ void body_finish(Body* __restrict__ bodies, const double* __restrict__ bf,
-                                            const double* __restrict__ bt, int b, int parity)
+// turn the torque into the body frame, second half kick, pose and bead records of the next
+// step
+__device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parity)
 {
     __shared__ double part[4][6];
+    __shared__ Pose next;
+    Body* __restrict__ bodies = ba.bodies;
+    const double* __restrict__ bf = ba.bead_force;
+    const double* __restrict__ bt = ba.bead_torque;
     const Body& B = bodies[b];
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int k = threadIdx.x; k < B.n_beads; k += 256) {
@@ -81,34 +119,38 @@ __device__ __forceinline__ void body_finish(Body* __restrict__ bodies, const dou
     if ((threadIdx.x & 63) == 0)
         for (int k = 0; k < 6; ++k) part[wave][k] = acc[k];
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    double F[3], T[3];
-    for (int k = 0; k < 3; ++k) {
-        F[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
-        T[k] = (part[0][3 + k] + part[1][3 + k]) + (part[2][3 + k] + part[3][3 + k]);
+    if (threadIdx.x == 0) {
+        double F[3], T[3];
+        for (int k = 0; k < 3; ++k) {
+            F[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
+            T[k] = (part[0][3 + k] + part[1][3 + k]) + (part[2][3 + k] + part[3][3 + k]);
+        }
+        // second half kick with this step's force and body-frame torque, from the step's pose
+        const Pose& P = B.pose[parity];
+        double vel[3], om[3], Tb[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            vel[ax] = P.vel[ax];
+            om[ax] = P.omega[ax];
+            Tb[ax] = P.rot[ax] * T[0] + P.rot[3 + ax] * T[1] + P.rot[6 + ax] * T[2];
+        }
+        if (!B.fixed) {
+            for (int ax = 0; ax < 3; ++ax) vel[ax] += 0.5 * F[ax] / B.mass;
+            half_kick(om, B.inertia, Tb);
+        }
+        Body& o = bodies[b];
+        for (int ax = 0; ax < 3; ++ax) {
+            o.pos[ax] = P.pos[ax];
+            o.vel[ax] = vel[ax];
+            o.omega[ax] = om[ax];
+            o.force[ax] = F[ax];
+            o.torque[ax] = Tb[ax];
+        }
+        for (int k = 0; k < 4; ++k) o.quat[k] = P.quat[k];
+        predict_pose(o, o.pose[parity ^ 1]);
+        next = o.pose[parity ^ 1];
     }
-    // second half kick with this step's force and body-frame torque, from the step's pose
-    const Pose& P = B.pose[parity];
-    double vel[3], om[3], Tb[3];
-    for (int ax = 0; ax < 3; ++ax) {
-        vel[ax] = P.vel[ax];
-        om[ax] = P.omega[ax];
-        Tb[ax] = P.rot[ax] * T[0] + P.rot[3 + ax] * T[1] + P.rot[6 + ax] * T[2];
-    }
-    if (!B.fixed) {
-        for (int ax = 0; ax < 3; ++ax) vel[ax] += 0.5 * F[ax] / B.mass;
-        half_kick(om, B.inertia, Tb);
-    }
-    Body& o = bodies[b];
-    for (int ax = 0; ax < 3; ++ax) {
-        o.pos[ax] = P.pos[ax];
-        o.vel[ax] = vel[ax];
-        o.omega[ax] = om[ax];
-        o.force[ax] = F[ax];
-        o.torque[ax] = Tb[ax];
-    }
-    for (int k = 0; k < 4; ++k) o.quat[k] = P.quat[k];
-    predict_pose(o, o.pose[parity ^ 1]);
+    __syncthreads();
+    write_bead_records(B, next, ba.beads, ba.recs);
 }
 
 // The node update of one tile group.  With FORCES the nodes consume the spread force of the
@@ -117,15 +159,12 @@ __device__ __forceinline__ void body_finish(Body* __restrict__ bodies, const dou
 // the coupling and write only body records, which no node thread touches.
 template <typename Real, bool MASKED, bool THERMAL, bool FORCES>
 __global__ __launch_bounds__(kNodeBlock) void node_step_kernel(const StepArgs<Real> a,
-                                                               Body* __restrict__ bodies,
-                                                               const double* __restrict__ bf,
-                                                               const double* __restrict__ bt,
-                                                               int n_bodies, int n_lead)
+                                                               const BodyArgs ba, int n_lead)
 {
     const int64_t step = current_step(a.step_ptr, a.step_arg);
     int b = blockIdx.x;
     if (b < n_lead) {
-        if (b < n_bodies) body_finish(bodies, bf, bt, b, (int)(step & 1));
+        if (b < ba.n_bodies) body_finish(ba, b, (int)(step & 1));
         return;
     }
     b -= n_lead;
@@ -140,39 +179,39 @@ __global__ __launch_bounds__(kNodeBlock) void node_step_kernel(const StepArgs<Re
 }
 
 template <typename Real, bool MASKED, bool THERMAL>
-void launch_node_t(const StepArgs<Real>& a, bool forces, Body* bodies, const double* bf,
-                   const double* bt, int32_t n_bodies, hipStream_t s)
+void launch_node_t(const StepArgs<Real>& a, bool forces, const BodyArgs* bodies, hipStream_t s)
 {
-    const int n_lead = bodies && n_bodies > 0 ? (n_bodies + 7) & ~7 : 0;
+    BodyArgs ba{};
+    if (bodies) ba = *bodies;
+    const int n_lead = ba.n_bodies > 0 ? (ba.n_bodies + 7) & ~7 : 0;
     const dim3 grid(a.n_tiles + n_lead), block(kNodeBlock);
     if (forces)
         hipLaunchKernelGGL((node_step_kernel<Real, MASKED, THERMAL, true>), grid, block, 0, s, a,
-                           bodies, bf, bt, n_bodies, n_lead);
+                           ba, n_lead);
     else
         hipLaunchKernelGGL((node_step_kernel<Real, MASKED, THERMAL, false>), grid, block, 0, s, a,
-                           bodies, bf, bt, n_bodies, n_lead);
+                           ba, n_lead);
 }
 
 template <typename Real>
-void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, Body* bodies,
-                      const double* bead_force, const double* bead_torque, int32_t n_bodies,
+void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const BodyArgs* bodies,
                       hipStream_t s)
 {
-    if (a.n_tiles <= 0 && !(bodies && n_bodies > 0)) return;
+    if (a.n_tiles <= 0 && !(bodies && bodies->n_bodies > 0)) return;
     if (masked) {
-        if (a.thermal) launch_node_t<Real, true, true>(a, forces, bodies, bead_force, bead_torque, n_bodies, s);
-        else launch_node_t<Real, true, false>(a, forces, bodies, bead_force, bead_torque, n_bodies, s);
+        if (a.thermal) launch_node_t<Real, true, true>(a, forces, bodies, s);
+        else launch_node_t<Real, true, false>(a, forces, bodies, s);
     } else {
-        if (a.thermal) launch_node_t<Real, false, true>(a, forces, bodies, bead_force, bead_torque, n_bodies, s);
-        else launch_node_t<Real, false, false>(a, forces, bodies, bead_force, bead_torque, n_bodies, s);
+        if (a.thermal) launch_node_t<Real, false, true>(a, forces, bodies, s);
+        else launch_node_t<Real, false, false>(a, forces, bodies, s);
     }
 }
 
 // ------------------------------------------------------------------ bead coupling
 
-// Thread t handles corner t & 7 of bead t >> 3.  The dependent loads are kept to four
-// rounds: bead record (offset + body index) -> body record (pose, friction, replica
-// geometry) -> the 9 row descriptors around the corner node -> its 19 populations.
+// Thread t handles corner t & 7 of bead t >> 3.  The dependent loads are kept to three
+// rounds: the bead's record of the step (position, velocity, friction, replica geometry) ->
+// the 9 row descriptors around the corner node -> its 19 populations.
 template <typename Real>
 __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Real> a,
                                                               const CoupleArgs c)
@@ -181,52 +220,38 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
     const int bead = tid >> 3, corner = tid & 7;
     if (bead >= c.n_beads) return;   // the 8 lanes of a bead leave together
     const int64_t step = current_step(a.step_ptr, a.step_arg);
-    const Bead bd = c.beads[bead];
-    const Body& B = c.bodies[bd.body];
-    const Pose& P = B.pose[step & 1];
-    const BodyBox& X = B.box;
-    // bead position r = R + Q b and velocity v = V + w_lab x (Q b) from the step's pose
-    double dv[3], r[3], v[3];
-    for (int ax = 0; ax < 3; ++ax) {
-        dv[ax] = P.rot[3 * ax] * bd.off[0] + P.rot[3 * ax + 1] * bd.off[1] + P.rot[3 * ax + 2] * bd.off[2];
-        r[ax] = P.pos[ax] + dv[ax];
-    }
-    if (B.fixed) {
-        v[0] = v[1] = v[2] = 0.0;
-    } else {
-        const double* w = P.omega_lab;
-        v[0] = P.vel[0] + (w[1] * dv[2] - w[2] * dv[1]);
-        v[1] = P.vel[1] + (w[2] * dv[0] - w[0] * dv[2]);
-        v[2] = P.vel[2] + (w[0] * dv[1] - w[1] * dv[0]);
-    }
+    const BeadRec& B = c.recs[bead];
+    const double r[3] = {B.r[0], B.r[1], B.r[2]};
+    const int nx = B.nx, ny = B.ny, nz = B.nz;
 
     // corner of the trilinear stencil handled by this lane
     double fr[3];
     int i0[3];
-    i0[0] = wrap_floor(r[0] - 0.5, X.nx, fr[0]);
-    i0[1] = wrap_floor(r[1] - 0.5, X.ny, fr[1]);
-    i0[2] = wrap_floor(r[2] - 0.5, X.nz, fr[2]);
+    i0[0] = wrap_floor(r[0] - 0.5, nx, fr[0]);
+    i0[1] = wrap_floor(r[1] - 0.5, ny, fr[1]);
+    i0[2] = wrap_floor(r[2] - 0.5, nz, fr[2]);
     const int ox = corner & 1, oy = (corner >> 1) & 1, oz = corner >> 2;
-    const int px = i0[0] + ox == X.nx ? 0 : i0[0] + ox;
-    const int py = i0[1] + oy == X.ny ? 0 : i0[1] + oy;
-    const int pz = i0[2] + oz == X.nz ? 0 : i0[2] + oz;
+    const int px = i0[0] + ox == nx ? 0 : i0[0] + ox;
+    const int py = i0[1] + oy == ny ? 0 : i0[1] + oy;
+    const int pz = i0[2] + oz == nz ? 0 : i0[2] + oz;
     const double w = (ox ? fr[0] : 1.0 - fr[0]) * (oy ? fr[1] : 1.0 - fr[1]) *
                      (oz ? fr[2] : 1.0 - fr[2]);
 
     // the node's populations (pre-collision of this step): local index and pull
-    ReplicaDesc R{};
-    R.nx = X.nx; R.ny = X.ny; R.nz = X.nz; R.masked = X.masked;
-    R.base = X.base; R.row_base = X.row_base;
     int64_t local;
     Real d[Q];
-    if (X.masked) {
-        const RowDesc self = a.rowinfo[X.row_base + py + X.ny * pz];
-        const int off = px - self.xlo;
-        local = (unsigned)off < (unsigned)self.len ? self.start + off : -1;
-        if (local >= 0) pull<Real, true>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
+    if (B.masked) {
+        Rows9 rw;
+        load_rows9(a.rowinfo, B.row_base, ny, nz, py, pz, rw);
+        const int off = px - rw.lo[4];
+        local = (unsigned)off < (unsigned)rw.ln[4] ? rw.st[4] + off : -1;
+        if (local >= 0) pull_rows<Real, 1>(a.src, B.base, nx, rw, px, B.base + local, d);
     } else {
-        local = px + (int64_t)X.nx * (py + (int64_t)X.ny * pz);
-        const RowDesc self{0, 0, X.nx, 0};
+        ReplicaDesc R{};
+        R.nx = nx; R.ny = ny; R.nz = nz;
+        R.base = B.base;
+        local = px + (int64_t)nx * (py + (int64_t)ny * pz);
+        const RowDesc self{0, 0, nx, 0};
         pull<Real, false>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
     }
     double wu[3] = {0.0, 0.0, 0.0};
@@ -242,10 +267,9 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
         for (int ax = 0; ax < 3; ++ax) wu[ax] += __shfl_xor(wu[ax], m, 8);
 
     double F[3];
-    for (int ax = 0; ax < 3; ++ax) F[ax] = -B.gamma * (v[ax] - wu[ax]);
+    for (int ax = 0; ax < 3; ++ax) F[ax] = -B.gamma * (B.v[ax] - wu[ax]);
     if (c.kT > 0.0) {
-        const uint32_t idx = (uint32_t)(B.first_bead_in_replica + (bead - B.first_bead));
-        const U4 blk = noise_block((uint64_t)step, idx, 1u, 0u, X.key0, X.key1);
+        const U4 blk = noise_block((uint64_t)step, (uint32_t)B.noise_idx, 1u, 0u, B.key0, B.key1);
         const double amp = B.noise_amp;
         F[0] += amp * uniform16<double>(blk.x);
         F[1] += amp * uniform16<double>(blk.x >> 16);
@@ -253,7 +277,7 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
     }
 
     if (local >= 0) {
-        const int64_t g = X.base + local;
+        const int64_t g = B.base + local;
         bool overflow = false;
         for (int ax = 0; ax < 3; ++ax) {
             const double val = -(w * F[ax]);
@@ -265,6 +289,7 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
         if (overflow) atomicOr(&c.hdr->err_flags, 1u);
     }
     if (corner == 0) {
+        const double* dv = B.dv;
         for (int ax = 0; ax < 3; ++ax) c.bead_force[3 * bead + ax] = F[ax];
         c.bead_torque[3 * bead + 0] = dv[1] * F[2] - dv[2] * F[1];
         c.bead_torque[3 * bead + 1] = dv[2] * F[0] - dv[0] * F[2];
@@ -281,19 +306,23 @@ void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s)
                        dim3(kCoupleBlock), 0, s, a, c);
 }
 
-__global__ void body_predict_kernel(Body* __restrict__ bodies, int32_t n, int parity)
+// pose of the coming step and its bead records, one workgroup per body
+__global__ __launch_bounds__(256) void body_predict_kernel(const BodyArgs ba, int parity)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n) return;
-    Body& B = bodies[b];
-    predict_pose(B, B.pose[parity]);
+    __shared__ Pose next;
+    Body& B = ba.bodies[blockIdx.x];
+    if (threadIdx.x == 0) {
+        predict_pose(B, B.pose[parity]);
+        next = B.pose[parity];
+    }
+    __syncthreads();
+    write_bead_records(B, next, ba.beads, ba.recs);
 }
 
-void launch_body_predict(Body* bodies, int32_t n_bodies, int parity, hipStream_t s)
+void launch_body_predict(const BodyArgs& b, int parity, hipStream_t s)
 {
-    if (n_bodies <= 0) return;
-    hipLaunchKernelGGL(body_predict_kernel, dim3((n_bodies + 63) / 64), dim3(64), 0, s, bodies,
-                       n_bodies, parity);
+    if (b.n_bodies <= 0) return;
+    hipLaunchKernelGGL(body_predict_kernel, dim3(b.n_bodies), dim3(256), 0, s, b, parity);
 }
 
 __global__ void set_step_kernel(int64_t* p, int64_t v) { *p = v; }
@@ -398,10 +427,10 @@ void launch_observe(const StepArgs<Real>& a, bool masked, int32_t tile0, int32_t
 // explicit instantiations
 template void launch_couple<float>(const StepArgs<float>&, const CoupleArgs&, hipStream_t);
 template void launch_couple<double>(const StepArgs<double>&, const CoupleArgs&, hipStream_t);
-template void launch_node_step<float>(const StepArgs<float>&, bool, bool, Body*, const double*,
-                                      const double*, int32_t, hipStream_t);
-template void launch_node_step<double>(const StepArgs<double>&, bool, bool, Body*, const double*,
-                                       const double*, int32_t, hipStream_t);
+template void launch_node_step<float>(const StepArgs<float>&, bool, bool, const BodyArgs*,
+                                      hipStream_t);
+template void launch_node_step<double>(const StepArgs<double>&, bool, bool, const BodyArgs*,
+                                       hipStream_t);
 template void launch_init_equilibrium<float>(float*, int64_t, const ReplicaDesc*, const NodeTile*,
                                              int32_t, float, const double*, hipStream_t);
 template void launch_init_equilibrium<double>(double*, int64_t, const ReplicaDesc*,

@@ -95,9 +95,24 @@ struct Bead {
     int32_t body, pad;
 };
 
+// What the coupling needs of a bead in the coming step, written when the body's pose of that
+// step is known (the body finishing of the previous step, or the pose prediction after a body
+// was added or a state loaded), so that the coupling reads one 128-byte record per bead.
+struct BeadRec {
+    double r[3];            // lab position, unwrapped
+    double dv[3];           // r - centre (lab), for the torque
+    double v[3];            // bead velocity (0 for a fixed body)
+    double gamma, noise_amp;
+    int32_t noise_idx;      // bead index within its replica (counter of its noise)
+    int32_t row_base;       // replica geometry: rows of the replica, box, storage base, seed
+    int32_t nx, ny, nz, masked;
+    int64_t base;
+    uint32_t key0, key1;
+};
+static_assert(sizeof(BeadRec) == 128, "bead record is two 64-byte lines");
+
 struct CoupleArgs {
-    const Body* bodies;
-    const Bead* beads;
+    const BeadRec* recs;
     double* bead_force;         // 3 per bead, lab frame
     double* bead_torque;        // 3 per bead, lab frame
     int32_t n_beads;
@@ -107,13 +122,23 @@ struct CoupleArgs {
 
 template <typename Real>
 void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s);
+// Bodies to finish in a node launch: per-bead forces/torques of the coupling in, body records
+// and the bead records of the next step out.
+struct BodyArgs {
+    Body* bodies;
+    const Bead* beads;
+    BeadRec* recs;
+    const double* bead_force;
+    const double* bead_torque;
+    int32_t n_bodies;
+};
 // the node update of one tile group; with forces the nodes consume the spread force, with
 // bodies != null its leading workgroups finish the bodies
 template <typename Real>
-void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, Body* bodies,
-                      const double* bead_force, const double* bead_torque, int32_t n_bodies,
+void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const BodyArgs* bodies,
                       hipStream_t s);
-void launch_body_predict(Body* bodies, int32_t n_bodies, int parity, hipStream_t s);
+// pose of the coming step (parity = step & 1) and bead records of every body
+void launch_body_predict(const BodyArgs& b, int parity, hipStream_t s);
 void launch_set_step(int64_t* step_ptr, int64_t value, hipStream_t s);
 template <typename Real>
 void launch_init_equilibrium(Real* f, int64_t N, const ReplicaDesc* reps, const NodeTile* tiles,
