@@ -70,19 +70,21 @@ __device__ __forceinline__ void write_bead_records(const Body& B, const Pose& P,
     for (int k = threadIdx.x; k < B.n_beads; k += blockDim.x) {
         const int e = B.first_bead + k;
         const Bead bd = beads[e];
-        BeadRec o;
+        BeadRec& o = recs[e];   // written field by field: few live registers in the node kernel
+        double dv[3];
         for (int ax = 0; ax < 3; ++ax) {
-            o.dv[ax] = P.rot[3 * ax] * bd.off[0] + P.rot[3 * ax + 1] * bd.off[1] +
-                       P.rot[3 * ax + 2] * bd.off[2];
-            o.r[ax] = P.pos[ax] + o.dv[ax];
+            dv[ax] = P.rot[3 * ax] * bd.off[0] + P.rot[3 * ax + 1] * bd.off[1] +
+                     P.rot[3 * ax + 2] * bd.off[2];
+            o.dv[ax] = dv[ax];
+            o.r[ax] = P.pos[ax] + dv[ax];
         }
         if (B.fixed) {
             o.v[0] = o.v[1] = o.v[2] = 0.0;
         } else {
             const double* w = P.omega_lab;
-            o.v[0] = P.vel[0] + (w[1] * o.dv[2] - w[2] * o.dv[1]);
-            o.v[1] = P.vel[1] + (w[2] * o.dv[0] - w[0] * o.dv[2]);
-            o.v[2] = P.vel[2] + (w[0] * o.dv[1] - w[1] * o.dv[0]);
+            o.v[0] = P.vel[0] + (w[1] * dv[2] - w[2] * dv[1]);
+            o.v[1] = P.vel[1] + (w[2] * dv[0] - w[0] * dv[2]);
+            o.v[2] = P.vel[2] + (w[0] * dv[1] - w[1] * dv[0]);
         }
         o.gamma = B.gamma;
         o.noise_amp = B.noise_amp;
@@ -91,7 +93,6 @@ __device__ __forceinline__ void write_bead_records(const Body& B, const Pose& P,
         o.nx = X.nx; o.ny = X.ny; o.nz = X.nz; o.masked = X.masked;
         o.base = X.base;
         o.key0 = X.key0; o.key1 = X.key1;
-        recs[e] = o;
     }
 }
 
@@ -157,8 +158,11 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
 // coupling.  The first n_lead workgroups (0, or a multiple of 8 so that blockIdx % 8 still
 // picks the XCD of the node tiles) finish the bodies: they read only the per-bead forces of
 // the coupling and write only body records, which no node thread touches.
+// FP32: 72 registers give 7 wavefronts per SIMD (the FP32 paths fit without spills; FP64 is
+// left to the compiler)
 template <typename Real, bool MASKED, bool THERMAL, bool FORCES>
-__global__ __launch_bounds__(kNodeBlock) void node_step_kernel(const StepArgs<Real> a,
+__global__ __launch_bounds__(kNodeBlock) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 7 : 1)))
+void node_step_kernel(const StepArgs<Real> a,
                                                                const BodyArgs ba, int n_lead)
 {
     const int64_t step = current_step(a.step_ptr, a.step_arg);

@@ -444,3 +444,27 @@ def window_objective(gamma, offsets, builder, n_steps, weights, checkpoint_every
     if _WO is None:
         _WO = _window_objective_class()
     return _WO.apply(gamma, offsets, builder, n_steps, weights, checkpoint_every)
+
+
+def calibrate_gamma(builder, n_steps, weights, target, gamma0, checkpoint_every=20, tol=1e-10,
+                    max_iter=20):
+    """Newton iteration for the bead friction gamma (one value for every body of the
+    simulation) such that the window objective J(gamma) = sum_n sum_b weights[n, b] . F_b(n)
+    equals `target`; dJ/dgamma comes from the reverse pass.  builder(gamma) returns a fresh
+    Simulation whose bodies use that friction.  Returns (gamma, J, iterations)."""
+    g = float(gamma0)
+    for it in range(1, max_iter + 1):
+        sim = builder(g)
+        try:
+            J, dg, _ = sim.adjoint(n_steps, weights, checkpoint_every)
+        finally:
+            sim.close()
+        slope = float(np.sum(dg))
+        if not np.isfinite(J) or slope == 0.0:
+            raise LBError(LB_ERR_UNSTABLE, "calibration: non-finite objective or zero slope")
+        if abs(J - target) <= tol * max(1.0, abs(target)):
+            return g, J, it
+        g_new = g - (J - target) / slope
+        # stay positive: halve towards zero instead of stepping through it
+        g = g_new if g_new > 0 else 0.5 * g
+    raise LBError(LB_ERR_UNSTABLE, "calibration did not converge")

@@ -268,3 +268,26 @@ def test_adjoint_error_codes():
         sim.adjoint(4, a[:, :1])
     assert e.value.code == lbrb.LB_ERR_STATE
     sim.close()
+
+
+def test_gamma_calibration_recovers_a_known_friction():
+    """Newton on gamma with the adjoint slope: the drag window of the 64^3 fixed sphere run
+    at gamma = 0.5 is the target; starting from the workload's gamma the iteration must
+    return 0.5."""
+    from paper_1604_01829_amd import lbrb
+    T, K = 100, 20
+    wl = W.workload(5)
+    a = np.zeros((T, 1, 3))
+    a[:, 0, 0] = 1.0 / T
+
+    def builder(g):
+        return _config5_sim(wl, "f64", g, None)
+
+    sim = builder(0.5)
+    target, _, _ = sim.adjoint(T, a, K)
+    sim.close()
+    g, J, it = lbrb.calibrate_gamma(builder, T, a, target, wl["replicas"][0]["bodies"][0]["gamma"],
+                                    checkpoint_every=K, tol=1e-12)
+    print(f"  calibrated gamma {g:.12f} in {it} iterations (J {J:.9e}, target {target:.9e})",
+          flush=True)
+    assert abs(g - 0.5) < 1e-9 and it <= 8
