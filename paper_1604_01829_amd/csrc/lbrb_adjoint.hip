@@ -54,7 +54,7 @@ template <typename Real>
 __global__ __launch_bounds__(kCoupleBlock) void adj_bead_kernel(const AdjArgs<Real> A)
 {
     const StepArgs<Real>& a = A.a;
-    const int tid = blockIdx.x * kCoupleBlock + threadIdx.x;
+    const int tid = xcd_tile(blockIdx.x, gridDim.x) * kCoupleBlock + threadIdx.x;
     const int bead = tid >> 3, corner = tid & 7;
     if (bead >= A.n_beads) return;   // the 8 lanes of a bead leave together
     const int64_t step = current_step(a.step_ptr, a.step_arg);

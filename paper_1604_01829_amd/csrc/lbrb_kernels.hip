@@ -220,7 +220,9 @@ template <typename Real>
 __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Real> a,
                                                               const CoupleArgs c)
 {
-    const int tid = blockIdx.x * kCoupleBlock + threadIdx.x;
+    // consecutive bead blocks (neighbouring beads of one body, sharing stencil rows) stay on
+    // one XCD and its L2
+    const int tid = xcd_tile(blockIdx.x, gridDim.x) * kCoupleBlock + threadIdx.x;
     const int bead = tid >> 3, corner = tid & 7;
     if (bead >= c.n_beads) return;   // the 8 lanes of a bead leave together
     const int64_t step = current_step(a.step_ptr, a.step_arg);
