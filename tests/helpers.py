@@ -86,3 +86,51 @@ def compare(gpu, orc, r=0, n_bodies=None):
     out.update({"body_" + k: v for k, v in errs.items()})
     out.update({"scale_" + k: v for k, v in scale.items()})
     return out
+
+
+def first_step_expected(shape, mask, params, seed, kT, nodes):
+    """Oracle value of (rho, u) after one step from the initial state, node by node.  The
+    initial pre-collision state is the streamed image of the uniform equilibrium (population
+    i of x is feq_i, or feq_opp(i) when x - c_i is a boundary node); after one step the
+    pre-collision population i at x is the post-collision population i of x - c_i, or the
+    opposite population of x itself when x - c_i is a boundary node; each post-collision
+    population is the oracle's collision of that node with its own noise."""
+    nx, ny, nz = shape
+    c = po.velocities()
+    opp = po.opposite()
+    feq = po.equilibrium(params.rho0, np.array(params.u0[:]))
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    gext = np.array(params.g_ext[:])
+    cache = {}
+
+    def solid(x, y, z):
+        return mask is not None and bool(mask[z % nz, y % ny, x % nx])
+
+    def post(x, y, z):
+        k = (x, y, z)
+        if k not in cache:
+            fin = np.array([feq[opp[i]] if solid(x - c[i, 0], y - c[i, 1], z - c[i, 2])
+                            else feq[i] for i in range(19)])
+            un = None
+            if kT > 0:
+                node = x + nx * (y + ny * z)
+                w = po.philox([0, node, 0, 0], key) + po.philox([0, node, 1, 0], key)
+                halves = [(v >> (16 * h)) & 0xFFFF for v in w for h in range(2)]
+                un = np.zeros(19)
+                un[4:] = [po.uniform16(halves[k4]) for k4 in range(15)]
+            cache[k] = po.collide_node(params, fin, gext, un)
+        return cache[k]
+
+    out = []
+    for (x, y, z) in nodes:
+        f = np.zeros(19)
+        for i in range(19):
+            xs, ys, zs = (x - c[i, 0]) % nx, (y - c[i, 1]) % ny, (z - c[i, 2]) % nz
+            if solid(xs, ys, zs):
+                f[i] = post(x, y, z)[opp[i]]
+            else:
+                f[i] = post(xs, ys, zs)[i]
+        rho = f.sum()
+        u = (c.T @ f + 0.5 * gext) / rho
+        out.append((rho, u))
+    return out

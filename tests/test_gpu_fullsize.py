@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_1604_01829_amd import workloads as W
-from tests.helpers import gpu_from_workload, oracle_from_workload
+from tests.helpers import first_step_expected, gpu_from_workload, oracle_from_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -147,3 +147,52 @@ def test_512_replicas_graph_replay_equals_eager():
         assert np.array_equal(ba[0]["pos"], bb[0]["pos"])
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("masked", [False, True], ids=["periodic", "pore"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_512_cubed_first_step_sampled(precision, masked):
+    """The largest box here: 512^3 (20 GB per FP64 population buffer, so indices and byte
+    offsets pass 2^32), thermal, one step, checked at sampled nodes (box edges included)."""
+    import torch
+    from oracle import pyoracle as po
+    from paper_1604_01829_amd import lbrb
+    L, seed, kT = 512, 0x5120_5120, 4e-5
+    shape = (L, L, L)
+    mask = W.pore_mask(L, L, L, 200.0) if masked else None
+    pp = dict(u0=(0.01, -0.004, 0.002), tau_shear=0.9, tau_bulk=1.1, tau_odd=1.2,
+              tau_even=0.8, g_ext=(1e-5, 0.0, -2e-6))
+    print(f"512^3 {precision} {'pore' if masked else 'periodic'}", flush=True)
+    sim = lbrb.Simulation(lbrb.make_params(precision, kT=kT, **pp),
+                          lbrb.make_replicas([(shape, seed)]))
+    if masked:
+        sim.set_mask(0, mask)
+    sim.set_graph_steps(0)
+    sim.step(1)
+    f = sim.fields(0)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(512)
+    nodes = [tuple(int(v) for v in rng.integers(0, L, 3)) for _ in range(300)]
+    nodes += [(0, 0, 0), (L - 1, L - 1, L - 1), (0, L - 1, 0), (L - 1, 0, L - 1)]
+    if masked:
+        # fluid nodes next to the wall and on the axis
+        zs = rng.integers(0, L, 40)
+        for z in zs:
+            row = np.flatnonzero(mask[z, L // 2] == 0)
+            nodes += [(int(row[0]), L // 2, int(z)), (int(row[-1]), L // 2, int(z))]
+        nodes = [n for n in nodes if not mask[n[2], n[1], n[0]]]
+    want = first_step_expected(shape, mask, po.make_params(kT=kT, seed=seed, **pp), seed, kT,
+                                nodes)
+    err_rho = max(abs(f[z, y, x, 0] - w[0]) for (x, y, z), w in zip(nodes, want))
+    err_u = max(np.abs(f[z, y, x, 1:] - w[1]).max() for (x, y, z), w in zip(nodes, want))
+    scale_u = max(np.abs(w[1]).max() for w in want)
+    print(f"  {len(nodes)} nodes: rho err {err_rho:.3g}, u err {err_u:.3g} (scale {scale_u:.3g})",
+          flush=True)
+    if precision == "f64":
+        assert err_rho < 1e-14 and err_u < 1e-14 * max(scale_u, 1.0)
+    else:
+        assert err_rho < 1e-6 and err_u < 1e-5 * scale_u
+    if masked:
+        assert np.all(f[mask.astype(bool)] == 0.0)

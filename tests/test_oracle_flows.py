@@ -146,3 +146,28 @@ def test_mass_and_momentum_bookkeeping():
         mass, Pn = P()
         assert abs(mass - m0) < 1e-13 * m0
         assert np.abs(Pn - P0 - n * N * g_ext).max() < 1e-13 * N
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_node_by_node_first_step_equals_the_box_step(masked):
+    """The node-by-node expectation used for sampled checks of large boxes (neighbour
+    collisions with their own noise, streamed or bounced back) equals the oracle's own step of
+    the whole box."""
+    from paper_1604_01829_amd import workloads as W
+    from tests.helpers import first_step_expected
+    shape, seed, kT = (12, 12, 9), 77, 4e-5
+    mask = W.pore_mask(*shape, 4.5) if masked else None
+    pp = dict(u0=(0.01, -0.004, 0.002), tau_shear=0.9, tau_bulk=1.1, tau_odd=1.2,
+              tau_even=0.8, g_ext=(1e-5, 0.0, -2e-6))
+    prm = po.make_params(kT=kT, seed=seed, **pp)
+    sim = po.OracleSim(shape, prm)
+    if masked:
+        sim.set_mask(mask)
+    sim.step(1)
+    f = sim.fields()
+    nodes = [(x, y, z) for z in range(9) for y in range(12) for x in range(12)
+             if mask is None or not mask[z, y, x]]
+    want = first_step_expected(shape, mask, prm, seed, kT, nodes)
+    for (x, y, z), (rho, u) in zip(nodes, want):
+        assert abs(f[z, y, x, 0] - rho) < 1e-14
+        assert np.abs(f[z, y, x, 1:] - u).max() < 1e-15
