@@ -176,3 +176,33 @@ def test_unstable_run_is_reported():
     sim.step(60)
     t, _, _, rc = sim.observables(0, check=False)
     assert rc == lbrb.LB_ERR_UNSTABLE
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 24), (24, 1, 1), (1, 16, 1), (3, 2, 1)])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_degenerate_boxes_with_a_body(shape, precision):
+    """Boxes one node thick: periodic neighbours are the node itself, and the 8 stencil corners
+    of a bead fall onto the same few nodes (several lanes of one bead spread to one node)."""
+    rng = np.random.default_rng(sum(shape))
+    offs = np.vstack([np.zeros(3), rng.normal(0, 0.8, (6, 3))])
+    m, I = 5.0, (2.0, 2.0, 2.0)
+    centre = np.array(shape, float) / 2 + 0.13
+    wl = dict(name="degenerate", precision=precision, steps=10,
+              params=W.default_params(kT=4e-5, g_ext=(1e-5, -2e-6, 3e-6)),
+              replicas=[dict(shape=shape, seed=31, mask=None,
+                             bodies=[W.body_record(offs, m, I, centre,
+                                                   quat=W.random_quaternion(rng),
+                                                   vel=(1e-3, 0, -1e-3), gamma=W.GAMMA_FREE)])])
+    gpu = gpu_from_workload(wl)
+    gpu.set_graph_steps(0)
+    orc = oracle_from_workload(wl)
+    gpu.step(10)
+    orc.step(10)
+    e = compare(gpu, orc)
+    print(shape, precision, {k: f"{v:.3g}" for k, v in e.items() if isinstance(v, float)})
+    tol_u, tol_r = (1e-11, 1e-13) if precision == "f64" else (1e-5, 1e-6)
+    assert e["rc"] == 0 and e["finite"]
+    assert e["rho"] <= tol_r and e["u_abs"] <= tol_u * max(e["u_scale"], 1e-12)
+    for k in ("vel", "omega", "force", "torque"):
+        assert e["body_" + k] <= tol_u * max(e["scale_" + k], 1e-14) + 1e-15, k
+    assert e["body_pos"] <= tol_r * 100 and e["body_quat"] <= tol_r * 100
