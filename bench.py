@@ -24,7 +24,7 @@ run.  `cpu_baseline` times the FP64 CPU oracle on a few steps of the same box.
                   cache, so its node_step bandwidth is HBM bandwidth);
   adjoint         64^3 box, fixed sphere of 401 beads, 200-step window with checkpoints every
                   20 steps: the reverse pass (forward + recompute + reverse) against 200
-                  forward steps.
+                  forward steps; and the same window with every state kept (no recompute).
 """
 import argparse
 import hashlib
@@ -219,9 +219,15 @@ def compare_runs(args):
     t0 = time.perf_counter()
     sim.adjoint(T, a, K)
     t_adj = time.perf_counter() - t0
+    sim.adjoint(T, a, 1)                    # every state kept: no recompute
+    t0 = time.perf_counter()
+    sim.adjoint(T, a, 1)
+    t_all = time.perf_counter() - t0
     sim.close()
     out["adjoint"] = {"window_steps": T, "checkpoint_every": K, "forward_ms": round(t_fwd * 1e3, 3),
-                      "adjoint_ms": round(t_adj * 1e3, 3), "ratio": round(t_adj / t_fwd, 2)}
+                      "adjoint_ms": round(t_adj * 1e3, 3), "ratio": round(t_adj / t_fwd, 2),
+                      "all_states_kept_ms": round(t_all * 1e3, 3),
+                      "all_states_kept_ratio": round(t_all / t_fwd, 2)}
     return out
 
 
