@@ -130,6 +130,7 @@ struct lb_ctx {
     std::vector<RowDesc> rows;
     std::vector<RowDesc> rowinfo;
     std::vector<NodeTile> tiles[2];
+    bool narrow[2] = {true, true};   // tile group addressable with 32-bit byte offsets
     std::vector<ReplicaHost> rh;
     std::vector<Body> bodies0;          // bodies as added (device copy is authoritative)
     int32_t n_bodies = 0, n_beads = 0;
@@ -202,6 +203,7 @@ StepArgs<Real> step_args_on(const lb_ctx* c, int group, const void* src, void* d
     a.tiles = c->d_tiles[group];
     a.n_tiles = (int32_t)c->tiles[group].size();
     a.thermal = c->p.kT > 0.0 ? 1 : 0;
+    a.narrow = c->narrow[group] ? 1 : 0;
     a.gforce = c->gforce;
     a.flags = c->flags;
     a.cp = collide_params<Real>(c->p);
@@ -330,6 +332,14 @@ void rebuild_tiles(lb_ctx* c)
 {
     c->tiles[0].clear();
     c->tiles[1].clear();
+    // a group uses 32-bit byte offsets when each of its replicas' populations fit in 4 GiB
+    const uint64_t real = is_f32(c) ? sizeof(float) : sizeof(double);
+    c->narrow[0] = c->narrow[1] = true;
+    for (int r = 0; r < c->n_rep; ++r) {
+        const ReplicaDesc& R = c->reps[r];
+        if ((uint64_t)Q * (uint64_t)pad_nodes(R.n_nodes) * real > (uint64_t(1) << 32))
+            c->narrow[R.masked ? 1 : 0] = false;
+    }
     for (int r = 0; r < c->n_rep; ++r) {
         const ReplicaDesc& R = c->reps[r];
         ReplicaHost& H = c->rh[r];

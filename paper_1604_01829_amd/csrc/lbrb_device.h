@@ -75,9 +75,31 @@ __device__ __forceinline__ void load_rows9(const RowDesc* __restrict__ rowinfo, 
     }
 }
 
+// Byte offset of population i of local node loc from the replica's first population block:
+// 32-bit arithmetic, valid when the replica's populations span at most 4 GiB (a node
+// update then addresses memory as one uniform base plus a 32-bit offset per lane).
+template <typename Real>
+__device__ __forceinline__ uint32_t pop_byte32(uint32_t i, uint32_t loc)
+{
+    return ((((loc >> kPopBlockLog) * (uint32_t)Q + i) << kPopBlockLog) | (loc & 255u)) *
+           (uint32_t)sizeof(Real);
+}
+
+template <typename Real, bool NARROW>
+__device__ __forceinline__ Real load_pop(const Real* __restrict__ src, int64_t base, int i,
+                                         int64_t local)
+{
+    if constexpr (NARROW) {
+        const char* rb = (const char*)(src + (int64_t)Q * base);   // base: multiple of 256
+        return *(const Real*)(rb + pop_byte32<Real>((uint32_t)i, (uint32_t)local));
+    } else {
+        return src[pop_at(i, base + local)];
+    }
+}
+
 // Masked gather over preloaded rows: element i from x - S c_i (periodic in x) if that node is
-// fluid, else population opposite(i) of the node itself (own = its global index).
-template <typename Real, int S>
+// fluid, else population opposite(i) of the node itself (own = its local index).
+template <typename Real, int S, bool NARROW = false>
 __device__ __forceinline__ void pull_rows(const Real* __restrict__ src, int64_t base, int nx,
                                           const Rows9& rw, int x, int64_t own, Real d[Q])
 {
@@ -88,9 +110,9 @@ __device__ __forceinline__ void pull_rows(const Real* __restrict__ src, int64_t 
         const int xs = wrap1(x - cx, nx);
         const int off = xs - rw.lo[r9];
         const bool fluid = (unsigned)off < (unsigned)rw.ln[r9];
-        const int64_t g = fluid ? base + rw.st[r9] + off : own;
+        const int64_t l = fluid ? (int64_t)rw.st[r9] + off : own;
         const int p = fluid ? i : opposite_of(i);
-        d[i] = src[pop_at(p, g)];
+        d[i] = load_pop<Real, NARROW>(src, base, p, l);
     }
 }
 
@@ -99,13 +121,12 @@ __device__ __forceinline__ void pull_rows(const Real* __restrict__ src, int64_t 
 // opposite population of the node itself (halfway bounce-back).  With S = -1 the same gather
 // runs along +c_i: element i is taken from x + c_i, or from the opposite population of x
 // when x + c_i is a boundary node -- the transpose of streaming, used by the adjoint.
-template <typename Real, bool MASKED, int S = 1>
+template <typename Real, bool MASKED, int S = 1, bool NARROW = false>
 __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
                                      const ReplicaDesc& R, const RowDesc* __restrict__ rowinfo,
                                      int x, int y, int z, int64_t local, const RowDesc& self,
                                      Real d[Q])
 {
-    const int64_t own = R.base + local;
     if constexpr (MASKED) {
         // the node's own row is known; the other 8 rows (y - S cy, z - S cz) are loaded
         Rows9 rw;
@@ -120,7 +141,7 @@ __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
                 rw.st[r9] = rd.start; rw.lo[r9] = rd.xlo; rw.ln[r9] = rd.len;
             }
         }
-        pull_rows<Real, S>(src, R.base, R.nx, rw, x, own, d);
+        pull_rows<Real, S, NARROW>(src, R.base, R.nx, rw, x, local, d);
     } else {
         const int xm = wrap1(x - 1, R.nx), xp = wrap1(x + 1, R.nx);
         const int ym = wrap1(y - 1, R.ny), yp = wrap1(y + 1, R.ny);
@@ -131,8 +152,8 @@ __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
             const int xs = cx == 0 ? x : (cx > 0 ? xm : xp);
             const int ys = cy == 0 ? y : (cy > 0 ? ym : yp);
             const int zs = cz == 0 ? z : (cz > 0 ? zm : zp);
-            const int64_t g = R.base + xs + (int64_t)R.nx * (ys + (int64_t)R.ny * zs);
-            d[i] = src[pop_at(i, g)];
+            const int64_t l = xs + (int64_t)R.nx * (ys + (int64_t)R.ny * zs);
+            d[i] = load_pop<Real, NARROW>(src, R.base, i, l);
         }
     }
 }

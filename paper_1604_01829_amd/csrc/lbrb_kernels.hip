@@ -25,13 +25,13 @@ namespace lbrb {
 
 // One fluid node: pull, add the force density (external, plus the spread force when the
 // node's flag is set and FORCES), collide with the node's noise, store.
-template <typename Real, bool MASKED, bool THERMAL, bool FORCES>
+template <typename Real, bool MASKED, bool THERMAL, bool FORCES, bool NARROW>
 __device__ __forceinline__ void update_node(const StepArgs<Real>& a, const ReplicaDesc& R,
                                             int64_t local, int x, int y, int z,
                                             const RowDesc& self, int64_t step)
 {
     Real d[Q];
-    pull<Real, MASKED>(a.src, a.N, R, a.rowinfo, x, y, z, local, self, d);
+    pull<Real, MASKED, 1, NARROW>(a.src, a.N, R, a.rowinfo, x, y, z, local, self, d);
 
     const int64_t g = R.base + local;
     Real F[3] = {a.gext[0], a.gext[1], a.gext[2]};
@@ -56,9 +56,16 @@ __device__ __forceinline__ void update_node(const StepArgs<Real>& a, const Repli
         collide<Real>(a.cp, d, F, nullptr);
     }
 
-    Real* __restrict__ dst = a.dst;
+    if constexpr (NARROW) {
+        char* __restrict__ rb = (char*)(a.dst + (int64_t)Q * R.base);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dst[pop_at(i, g)] = d[i];
+        for (int i = 0; i < Q; ++i)
+            *(Real*)(rb + pop_byte32<Real>((uint32_t)i, (uint32_t)local)) = d[i];
+    } else {
+        Real* __restrict__ dst = a.dst;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dst[pop_at(i, g)] = d[i];
+    }
 }
 
 // bead records of body b for the step whose pose is P (all threads of the workgroup)
@@ -160,7 +167,7 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
 // the coupling and write only body records, which no node thread touches.
 // FP32: 72 registers give 7 wavefronts per SIMD (the FP32 paths fit without spills; FP64 is
 // left to the compiler)
-template <typename Real, bool MASKED, bool THERMAL, bool FORCES>
+template <typename Real, bool MASKED, bool THERMAL, bool FORCES, bool NARROW>
 __global__ __launch_bounds__(kNodeBlock) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 7 : 1)))
 void node_step_kernel(const StepArgs<Real> a,
                                                                const BodyArgs ba, int n_lead)
@@ -179,10 +186,10 @@ void node_step_kernel(const StepArgs<Real> a,
     int x, y, z;
     RowDesc self;
     locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
-    update_node<Real, MASKED, THERMAL, FORCES>(a, R, local, x, y, z, self, step);
+    update_node<Real, MASKED, THERMAL, FORCES, NARROW>(a, R, local, x, y, z, self, step);
 }
 
-template <typename Real, bool MASKED, bool THERMAL>
+template <typename Real, bool MASKED, bool THERMAL, bool NARROW>
 void launch_node_t(const StepArgs<Real>& a, bool forces, const BodyArgs* bodies, hipStream_t s)
 {
     BodyArgs ba{};
@@ -190,11 +197,24 @@ void launch_node_t(const StepArgs<Real>& a, bool forces, const BodyArgs* bodies,
     const int n_lead = ba.n_bodies > 0 ? (ba.n_bodies + 7) & ~7 : 0;
     const dim3 grid(a.n_tiles + n_lead), block(kNodeBlock);
     if (forces)
-        hipLaunchKernelGGL((node_step_kernel<Real, MASKED, THERMAL, true>), grid, block, 0, s, a,
-                           ba, n_lead);
+        hipLaunchKernelGGL((node_step_kernel<Real, MASKED, THERMAL, true, NARROW>), grid, block, 0,
+                           s, a, ba, n_lead);
     else
-        hipLaunchKernelGGL((node_step_kernel<Real, MASKED, THERMAL, false>), grid, block, 0, s, a,
-                           ba, n_lead);
+        hipLaunchKernelGGL((node_step_kernel<Real, MASKED, THERMAL, false, NARROW>), grid, block, 0,
+                           s, a, ba, n_lead);
+}
+
+// 32-bit offsets pay in FP32 (+2 % on a pore, +1 % on a batch); FP64 keeps 64-bit indices
+template <typename Real, bool MASKED, bool THERMAL>
+void launch_node_w(const StepArgs<Real>& a, bool forces, const BodyArgs* bodies, hipStream_t s)
+{
+    if constexpr (sizeof(Real) == 4) {
+        if (a.narrow) {
+            launch_node_t<Real, MASKED, THERMAL, true>(a, forces, bodies, s);
+            return;
+        }
+    }
+    launch_node_t<Real, MASKED, THERMAL, false>(a, forces, bodies, s);
 }
 
 template <typename Real>
@@ -203,11 +223,11 @@ void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const B
 {
     if (a.n_tiles <= 0 && !(bodies && bodies->n_bodies > 0)) return;
     if (masked) {
-        if (a.thermal) launch_node_t<Real, true, true>(a, forces, bodies, s);
-        else launch_node_t<Real, true, false>(a, forces, bodies, s);
+        if (a.thermal) launch_node_w<Real, true, true>(a, forces, bodies, s);
+        else launch_node_w<Real, true, false>(a, forces, bodies, s);
     } else {
-        if (a.thermal) launch_node_t<Real, false, true>(a, forces, bodies, s);
-        else launch_node_t<Real, false, false>(a, forces, bodies, s);
+        if (a.thermal) launch_node_w<Real, false, true>(a, forces, bodies, s);
+        else launch_node_w<Real, false, false>(a, forces, bodies, s);
     }
 }
 
@@ -251,7 +271,7 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
         load_rows9(a.rowinfo, B.row_base, ny, nz, py, pz, rw);
         const int off = px - rw.lo[4];
         local = (unsigned)off < (unsigned)rw.ln[4] ? rw.st[4] + off : -1;
-        if (local >= 0) pull_rows<Real, 1>(a.src, B.base, nx, rw, px, B.base + local, d);
+        if (local >= 0) pull_rows<Real, 1>(a.src, B.base, nx, rw, px, local, d);
     } else {
         ReplicaDesc R{};
         R.nx = nx; R.ny = ny; R.nz = nz;

@@ -81,6 +81,8 @@ struct StepArgs {
     const NodeTile* tiles;
     int32_t n_tiles;
     int32_t thermal;
+    int32_t narrow;         // every replica of the group spans at most 4 GiB of populations:
+                            // 32-bit byte offsets from a per-replica base
     long long* gforce;      // fixed-point spread force, [word][axis][node] (1 or 2 words)
     uint8_t* flags;         // 1 byte per node: spread force present
     CollideParams<Real> cp;
