@@ -163,18 +163,15 @@ __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
 // on the order of the atomic additions.  Word 0 counts units of 2^-56; in FP64 a second
 // word carries the remainder in units of 2^-112, which makes the spread exact to far below
 // FP64 rounding.  Layout: word w of axis ax of node g at gforce[(w*3 + ax) * N + g].
+// the fixed-point words of one contribution: hi in units of 2^-56, lo (FP64 only) the
+// remainder in units of 2^-112
 template <typename Real>
-__device__ __forceinline__ void add_spread_force(long long* gforce, int64_t N, int ax, int64_t g,
-                                                 double val)
+__device__ __forceinline__ void spread_words(double val, long long& hi, long long& lo)
 {
     const double x = val * 0x1p56;
-    const double hi = floor(x);
-    atomicAdd((unsigned long long*)(gforce + (int64_t)ax * N + g),
-              (unsigned long long)(long long)hi);
-    if constexpr (sizeof(Real) == 8) {
-        const long long lo = (long long)((x - hi) * 0x1p56);
-        atomicAdd((unsigned long long*)(gforce + (int64_t)(3 + ax) * N + g), (unsigned long long)lo);
-    }
+    const double h = floor(x);
+    hi = (long long)h;
+    lo = sizeof(Real) == 8 ? (long long)((x - h) * 0x1p56) : 0;
 }
 
 template <typename Real>

@@ -235,18 +235,34 @@ void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const B
 
 // Thread t handles corner t & 7 of bead t >> 3.  The dependent loads are kept to three
 // rounds: the bead's record of the step (position, velocity, friction, replica geometry) ->
-// the 9 row descriptors around the corner node -> its 19 populations.
+// the 9 row descriptors around the corner node -> its 19 populations.  Within a workgroup
+// (32 beads) the stencil nodes are deduplicated through an LDS hash table keyed by node:
+// the first lane to claim a node pulls its populations once and publishes (drho, j); the
+// lanes' force contributions are summed as fixed-point words in LDS and the node's owner
+// adds each sum to the node with one device atomic per word.  Integer sums do not depend on
+// their order, so the result is the same as one atomic per lane.
 template <typename Real>
 __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Real> a,
                                                               const CoupleArgs c)
 {
+    constexpr int TS = 2 * kCoupleBlock;                 // hash slots (power of two)
+    constexpr int NW = sizeof(Real) == 8 ? 6 : 3;       // fixed-point words per node
+    constexpr unsigned long long EMPTY = ~0ull;
+    __shared__ unsigned long long key[TS];
+    __shared__ Real mom[4][TS];
+    __shared__ unsigned long long acc[NW][TS];
+    for (int k = threadIdx.x; k < TS; k += kCoupleBlock) {
+        key[k] = EMPTY;
+        for (int w = 0; w < NW; ++w) acc[w][k] = 0;
+    }
+
     // consecutive bead blocks (neighbouring beads of one body, sharing stencil rows) stay on
     // one XCD and its L2
     const int tid = xcd_tile(blockIdx.x, gridDim.x) * kCoupleBlock + threadIdx.x;
     const int bead = tid >> 3, corner = tid & 7;
-    if (bead >= c.n_beads) return;   // the 8 lanes of a bead leave together
+    const bool active = bead < c.n_beads;   // the 8 lanes of a bead share this
     const int64_t step = current_step(a.step_ptr, a.step_arg);
-    const BeadRec& B = c.recs[bead];
+    const BeadRec& B = c.recs[active ? bead : 0];
     const double r[3] = {B.r[0], B.r[1], B.r[2]};
     const int nx = B.nx, ny = B.ny, nz = B.nz;
 
@@ -263,29 +279,57 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
     const double w = (ox ? fr[0] : 1.0 - fr[0]) * (oy ? fr[1] : 1.0 - fr[1]) *
                      (oz ? fr[2] : 1.0 - fr[2]);
 
-    // the node's populations (pre-collision of this step): local index and pull
-    int64_t local;
-    Real d[Q];
-    if (B.masked) {
-        Rows9 rw;
-        load_rows9(a.rowinfo, B.row_base, ny, nz, py, pz, rw);
-        const int off = px - rw.lo[4];
-        local = (unsigned)off < (unsigned)rw.ln[4] ? rw.st[4] + off : -1;
-        if (local >= 0) pull_rows<Real, 1>(a.src, B.base, nx, rw, px, local, d);
-    } else {
-        ReplicaDesc R{};
-        R.nx = nx; R.ny = ny; R.nz = nz;
-        R.base = B.base;
-        local = px + (int64_t)nx * (py + (int64_t)ny * pz);
-        const RowDesc self{0, 0, nx, 0};
-        pull<Real, false>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
+    // the node's local index (-1: boundary node or no bead)
+    int64_t local = -1;
+    Rows9 rw;
+    if (active) {
+        if (B.masked) {
+            load_rows9(a.rowinfo, B.row_base, ny, nz, py, pz, rw);
+            const int off = px - rw.lo[4];
+            local = (unsigned)off < (unsigned)rw.ln[4] ? rw.st[4] + off : -1;
+        } else {
+            local = px + (int64_t)nx * (py + (int64_t)ny * pz);
+        }
     }
-    double wu[3] = {0.0, 0.0, 0.0};
+    const int64_t g = B.base + local;
+    __syncthreads();   // the table is cleared
+
+    // claim the node's slot
+    int slot = -1;
+    bool owner = false;
     if (local >= 0) {
+        slot = (int)(((uint32_t)g * 2654435761u) >> 23) & (TS - 1);
+        while (true) {
+            const unsigned long long prev = atomicCAS(&key[slot], EMPTY, (unsigned long long)g);
+            if (prev == EMPTY) { owner = true; break; }
+            if (prev == (unsigned long long)g) break;
+            slot = (slot + 1) & (TS - 1);
+        }
+    }
+    // the owner pulls the node's populations (pre-collision of this step)
+    if (owner) {
+        Real d[Q];
+        if (B.masked) {
+            pull_rows<Real, 1>(a.src, B.base, nx, rw, px, local, d);
+        } else {
+            ReplicaDesc R{};
+            R.nx = nx; R.ny = ny; R.nz = nz;
+            R.base = B.base;
+            const RowDesc self{0, 0, nx, 0};
+            pull<Real, false>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
+        }
         Real drho, j[3];
         density_momentum<Real>(d, drho, j);
-        const double wr = w / ((double)a.cp.rho0 + (double)drho);
-        for (int ax = 0; ax < 3; ++ax) wu[ax] = wr * ((double)j[ax] + 0.5 * (double)a.gext[ax]);
+        mom[0][slot] = drho;
+        for (int ax = 0; ax < 3; ++ax) mom[1 + ax][slot] = j[ax];
+    }
+    __syncthreads();
+
+    double wu[3] = {0.0, 0.0, 0.0};
+    if (local >= 0) {
+        const double wr = w / ((double)a.cp.rho0 + (double)mom[0][slot]);
+        for (int ax = 0; ax < 3; ++ax)
+            wu[ax] = wr * ((double)mom[1 + ax][slot] + 0.5 * (double)a.gext[ax]);
     }
     // sum over the 8 corner lanes (same association on every lane)
 #pragma unroll
@@ -303,23 +347,33 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
     }
 
     if (local >= 0) {
-        const int64_t g = B.base + local;
         bool overflow = false;
         for (int ax = 0; ax < 3; ++ax) {
             const double val = -(w * F[ax]);
             const bool bad = !(fabs(val) < 16.0);
             overflow |= bad;
-            add_spread_force<Real>(a.gforce, a.N, ax, g, bad ? 0.0 : val);
+            long long hi, lo;
+            spread_words<Real>(bad ? 0.0 : val, hi, lo);
+            atomicAdd(&acc[ax][slot], (unsigned long long)hi);
+            if constexpr (NW == 6) atomicAdd(&acc[3 + ax][slot], (unsigned long long)lo);
         }
-        a.flags[g] = 1;   // every writer stores the same value
         if (overflow) atomicOr(&c.hdr->err_flags, 1u);
     }
-    if (corner == 0) {
+    if (active && corner == 0) {
         const double* dv = B.dv;
         for (int ax = 0; ax < 3; ++ax) c.bead_force[3 * bead + ax] = F[ax];
         c.bead_torque[3 * bead + 0] = dv[1] * F[2] - dv[2] * F[1];
         c.bead_torque[3 * bead + 1] = dv[2] * F[0] - dv[0] * F[2];
         c.bead_torque[3 * bead + 2] = dv[0] * F[1] - dv[1] * F[0];
+    }
+    __syncthreads();
+    // one device atomic per node and word
+    if (owner) {
+        for (int wd = 0; wd < NW; ++wd) {
+            const unsigned long long v = acc[wd][slot];
+            if (v != 0) atomicAdd((unsigned long long*)(a.gforce + (int64_t)wd * a.N + g), v);
+        }
+        a.flags[g] = 1;
     }
 }
 
