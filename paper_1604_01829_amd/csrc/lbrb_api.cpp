@@ -133,6 +133,7 @@ struct lb_ctx {
     bool narrow[2] = {true, true};   // tile group addressable with 32-bit byte offsets
     std::vector<ReplicaHost> rh;
     std::vector<Body> bodies0;          // bodies as added (device copy is authoritative)
+    std::vector<int32_t> bead_user;     // per stored bead: its index in the caller's order
     int32_t n_bodies = 0, n_beads = 0;
     int64_t step = 0;
     bool pose_stale = true;   // body poses must be recomputed before the next step
@@ -416,6 +417,27 @@ int init_fluid(lb_ctx* c, int replica)
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return LB_OK;
+}
+
+// Morton (Z-order) ranking of body-frame offsets on a half-lattice-unit grid
+std::vector<int32_t> spatial_order(const double* offs, int32_t n)
+{
+    double lo[3] = {offs[0], offs[1], offs[2]};
+    for (int32_t k = 1; k < n; ++k)
+        for (int a = 0; a < 3; ++a) lo[a] = std::min(lo[a], offs[3 * k + a]);
+    std::vector<uint64_t> key(n);
+    for (int32_t k = 0; k < n; ++k) {
+        uint64_t m = 0;
+        for (int a = 0; a < 3; ++a) {
+            const uint64_t q = (uint64_t)std::min(2097151.0, std::floor((offs[3 * k + a] - lo[a]) * 2.0));
+            for (int bit = 0; bit < 21; ++bit) m |= ((q >> bit) & 1ull) << (3 * bit + a);
+        }
+        key[k] = m;
+    }
+    std::vector<int32_t> order(n);
+    for (int32_t k = 0; k < n; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+    return order;
 }
 
 BodyBox body_box(const ReplicaDesc& R)
@@ -751,11 +773,15 @@ int rb_add_raspberry(lb_ctx* c, int32_t replica, const double* offs, int32_t n_b
     for (int32_t b : c->rh[replica].bodies) in_rep += c->bodies0[b].n_beads;
     B.first_bead_in_replica = in_rep;
     B.box = body_box(c->reps[replica]);
+    // store the beads in spatial (Morton) order of their body-frame offsets, so that the 32
+    // beads of a coupling workgroup are neighbours and share stencil nodes; each keeps its
+    // index in the caller's order (noise stream, per-bead outputs)
+    const std::vector<int32_t> order = spatial_order(offs, n_beads);
     std::vector<Bead> beads(n_beads);
     for (int k = 0; k < n_beads; ++k) {
-        for (int a = 0; a < 3; ++a) beads[k].off[a] = offs[3 * k + a];
+        for (int a = 0; a < 3; ++a) beads[k].off[a] = offs[3 * order[k] + a];
         beads[k].body = c->n_bodies;
-        beads[k].pad = 0;
+        beads[k].user = order[k];
     }
     HIP_TRY(c, hipMemcpyAsync(c->d_bodies + c->n_bodies, &B, sizeof(Body), hipMemcpyHostToDevice,
                               c->stream));
@@ -767,6 +793,7 @@ int rb_add_raspberry(lb_ctx* c, int32_t replica, const double* offs, int32_t n_b
     c->bodies0.push_back(B);
     c->n_bodies += 1;
     c->n_beads += n_beads;
+    c->bead_user.insert(c->bead_user.end(), order.begin(), order.end());
     c->pose_stale = true;
     destroy_graphs(c);
     return LB_OK;
@@ -880,9 +907,14 @@ int rb_bead_forces(lb_ctx* c, int32_t replica, int32_t body_id, double* host_out
         return fail(c, LB_ERR_ARG, "bad body id");
     const Body& B = c->bodies0[H.bodies[body_id]];
     if (n < B.n_beads) return fail(c, LB_ERR_ARG, "output too small");
-    HIP_TRY(c, hipMemcpyAsync(host_out, c->d_bead_force + 3 * (int64_t)B.first_bead,
-                              sizeof(double) * 3 * B.n_beads, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> f(3 * (size_t)B.n_beads);
+    HIP_TRY(c, hipMemcpyAsync(f.data(), c->d_bead_force + 3 * (int64_t)B.first_bead,
+                              sizeof(double) * f.size(), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int32_t k = 0; k < B.n_beads; ++k) {
+        const int32_t u = c->bead_user[B.first_bead + k];
+        for (int a = 0; a < 3; ++a) host_out[3 * (size_t)u + a] = f[3 * (size_t)k + a];
+    }
     return LB_OK;
 }
 
@@ -1079,8 +1111,9 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
         for (int32_t k = B.first_bead; k < B.first_bead + B.n_beads; ++k) {
             g += dg[k];
             const double* d = &dr[3 * (size_t)k];
+            const size_t u = (size_t)B.first_bead + c->bead_user[k];   // caller's order
             for (int a = 0; a < 3; ++a)
-                dJ_doffsets[3 * (size_t)k + a] = R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2];
+                dJ_doffsets[3 * u + a] = R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2];
         }
         dJ_dgamma[b] = g;
     }

@@ -95,7 +95,7 @@ __device__ __forceinline__ void write_bead_records(const Body& B, const Pose& P,
         }
         o.gamma = B.gamma;
         o.noise_amp = B.noise_amp;
-        o.noise_idx = B.first_bead_in_replica + k;
+        o.noise_idx = B.first_bead_in_replica + bd.user;   // noise follows the caller's order
         o.row_base = X.row_base;
         o.nx = X.nx; o.ny = X.ny; o.nz = X.nz; o.masked = X.masked;
         o.base = X.base;

@@ -91,10 +91,12 @@ struct StepArgs {
     int64_t step_arg;
 };
 
-// a bead: body-frame offset and the index of its body, read in one 32-byte load
+// a bead: body-frame offset, the index of its body and its index in the caller's order, read
+// in one 32-byte load (a body's beads are stored in spatial order, see rb_add_raspberry)
 struct Bead {
     double off[3];
-    int32_t body, pad;
+    int32_t body;
+    int32_t user;           // index of the bead within its body in the caller's order
 };
 
 // What the coupling needs of a bead in the coming step, written when the body's pose of that
