@@ -12,7 +12,7 @@ Prints one JSON line.  `value` = fluid-node updates per second / 1e6 (MLUPS) ove
 steps.  `roofline` is for the dominant kernel, node_step (the update of every fluid node; its
 few leading workgroups finish the bodies): algorithmic bytes 152 B (FP32) or 304 B (FP64) per
 fluid node (19 populations read + written) divided by its mean duration from HIP events
-recorded around each launch on the library's stream, in a separate eager window of the same
+recorded by the dispatch of each launch on the library's stream, in a separate eager window of the same
 run.  `cpu_baseline` times the FP64 CPU oracle on a few steps of the same box.
 
 `compare` (default workload only) measures, on the same GPU in the same process:

@@ -155,9 +155,10 @@ int lb_load_state(lb_ctx* ctx, const void* dev_buf, size_t bytes);
 
 /* Execution options.  graph_steps: lb_rb_step replays a HIP graph of this many steps
  * (even, >= 2) and runs the remainder eagerly; 0 = always eager (default 100).
- * timing: when nonzero, every node-update and coupling launch is bracketed by HIP events
- * on the context stream (eager launches only) and lb_kernel_times reports the summed
- * durations (ms) and launch counts since timing was enabled.                              */
+ * timing: when nonzero, every node-update and coupling launch carries a start and a stop
+ * HIP event recorded by its dispatch (hipExtLaunchKernel; eager launches only, graphs are
+ * not replayed while timing) and lb_kernel_times reports the summed kernel durations (ms)
+ * and launch counts since timing was enabled.                                            */
 int lb_set_graph_steps(lb_ctx* ctx, int32_t graph_steps);
 int lb_set_timing(lb_ctx* ctx, int32_t enable);
 int lb_kernel_times(lb_ctx* ctx, double* node_ms, int64_t* node_launches, double* couple_ms,

@@ -271,24 +271,27 @@ hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* st
     auto note = [&](hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; };
     StepArgs<Real> ag[2] = {step_args<Real>(c, 0, src_buf), step_args<Real>(c, 1, src_buf)};
     for (auto& a : ag) { a.step_ptr = step_ptr; a.step_arg = step_arg; }
+    // timed launches carry their own start/stop events (recorded by the dispatch)
     const bool timed = c->timing && !capture;
     if (c->n_beads > 0) {
         EventPair e{};
-        if (timed) { e = get_pair(c); note(hipEventRecord(e.a, s)); }
-        launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], couple_args(c), s);
+        if (timed) e = get_pair(c);
+        launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], couple_args(c), s,
+                            LaunchEvents{e.a, e.b});
         note(hipGetLastError());
-        if (timed) { note(hipEventRecord(e.b, s)); c->ev_couple_t.push_back(e); }
+        if (timed && e.a && e.b) c->ev_couple_t.push_back(e);
     }
     bool finished = c->n_bodies == 0;
     for (int g = 0; g < 2; ++g) {
         const bool last = g == 1 || ag[1].n_tiles == 0;
         if (ag[g].n_tiles == 0 && !(last && !finished)) continue;
         EventPair e{};
-        if (timed) { e = get_pair(c); note(hipEventRecord(e.a, s)); }
+        if (timed) e = get_pair(c);
         const BodyArgs ba = body_args(c);
-        launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, finished ? nullptr : &ba, s);
+        launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, finished ? nullptr : &ba, s,
+                               LaunchEvents{e.a, e.b});
         note(hipGetLastError());
-        if (timed) { note(hipEventRecord(e.b, s)); c->ev_node.push_back(e); }
+        if (timed && e.a && e.b) c->ev_node.push_back(e);
         finished = true;
     }
     return err;

@@ -15,11 +15,23 @@
 //                along x.  Its leading workgroups finish the raspberries: per-body
 //                force/torque sums (shuffle + LDS tree, fixed order), torque into the body
 //                frame, second half kick (Sec. 2.3), pose and bead records of the next step.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "lbrb_device.h"
 
 namespace lbrb {
+
+// launch, timed by events of the dispatch itself when ev.start is set
+template <typename K, typename... Args>
+void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, const LaunchEvents& ev,
+                  Args... args)
+{
+    if (ev.start)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ev.start, ev.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
 
 // ------------------------------------------------------------------ node update
 
@@ -190,44 +202,46 @@ void node_step_kernel(const StepArgs<Real> a,
 }
 
 template <typename Real, bool MASKED, bool THERMAL, bool NARROW>
-void launch_node_t(const StepArgs<Real>& a, bool forces, const BodyArgs* bodies, hipStream_t s)
+void launch_node_t(const StepArgs<Real>& a, bool forces, const BodyArgs* bodies, hipStream_t s,
+                   const LaunchEvents& ev)
 {
     BodyArgs ba{};
     if (bodies) ba = *bodies;
     const int n_lead = ba.n_bodies > 0 ? (ba.n_bodies + 7) & ~7 : 0;
     const dim3 grid(a.n_tiles + n_lead), block(kNodeBlock);
     if (forces)
-        hipLaunchKernelGGL((node_step_kernel<Real, MASKED, THERMAL, true, NARROW>), grid, block, 0,
-                           s, a, ba, n_lead);
+        launch_timed(node_step_kernel<Real, MASKED, THERMAL, true, NARROW>, grid, block, s, ev, a,
+                     ba, n_lead);
     else
-        hipLaunchKernelGGL((node_step_kernel<Real, MASKED, THERMAL, false, NARROW>), grid, block, 0,
-                           s, a, ba, n_lead);
+        launch_timed(node_step_kernel<Real, MASKED, THERMAL, false, NARROW>, grid, block, s, ev, a,
+                     ba, n_lead);
 }
 
 // 32-bit offsets pay in FP32 (+2 % on a pore, +1 % on a batch); FP64 keeps 64-bit indices
 template <typename Real, bool MASKED, bool THERMAL>
-void launch_node_w(const StepArgs<Real>& a, bool forces, const BodyArgs* bodies, hipStream_t s)
+void launch_node_w(const StepArgs<Real>& a, bool forces, const BodyArgs* bodies, hipStream_t s,
+                   const LaunchEvents& ev)
 {
     if constexpr (sizeof(Real) == 4) {
         if (a.narrow) {
-            launch_node_t<Real, MASKED, THERMAL, true>(a, forces, bodies, s);
+            launch_node_t<Real, MASKED, THERMAL, true>(a, forces, bodies, s, ev);
             return;
         }
     }
-    launch_node_t<Real, MASKED, THERMAL, false>(a, forces, bodies, s);
+    launch_node_t<Real, MASKED, THERMAL, false>(a, forces, bodies, s, ev);
 }
 
 template <typename Real>
 void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const BodyArgs* bodies,
-                      hipStream_t s)
+                      hipStream_t s, const LaunchEvents& ev)
 {
     if (a.n_tiles <= 0 && !(bodies && bodies->n_bodies > 0)) return;
     if (masked) {
-        if (a.thermal) launch_node_w<Real, true, true>(a, forces, bodies, s);
-        else launch_node_w<Real, true, false>(a, forces, bodies, s);
+        if (a.thermal) launch_node_w<Real, true, true>(a, forces, bodies, s, ev);
+        else launch_node_w<Real, true, false>(a, forces, bodies, s, ev);
     } else {
-        if (a.thermal) launch_node_w<Real, false, true>(a, forces, bodies, s);
-        else launch_node_w<Real, false, false>(a, forces, bodies, s);
+        if (a.thermal) launch_node_w<Real, false, true>(a, forces, bodies, s, ev);
+        else launch_node_w<Real, false, false>(a, forces, bodies, s, ev);
     }
 }
 
@@ -378,12 +392,13 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
 }
 
 template <typename Real>
-void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s)
+void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s,
+                   const LaunchEvents& ev)
 {
     if (c.n_beads <= 0) return;
     const int threads = c.n_beads * kBeadLanes;
-    hipLaunchKernelGGL((couple_kernel<Real>), dim3((threads + kCoupleBlock - 1) / kCoupleBlock),
-                       dim3(kCoupleBlock), 0, s, a, c);
+    launch_timed(couple_kernel<Real>, dim3((threads + kCoupleBlock - 1) / kCoupleBlock),
+                 dim3(kCoupleBlock), s, ev, a, c);
 }
 
 // pose of the coming step and its bead records, one workgroup per body
@@ -505,12 +520,14 @@ void launch_observe(const StepArgs<Real>& a, bool masked, int32_t tile0, int32_t
 }
 
 // explicit instantiations
-template void launch_couple<float>(const StepArgs<float>&, const CoupleArgs&, hipStream_t);
-template void launch_couple<double>(const StepArgs<double>&, const CoupleArgs&, hipStream_t);
+template void launch_couple<float>(const StepArgs<float>&, const CoupleArgs&, hipStream_t,
+                                   const LaunchEvents&);
+template void launch_couple<double>(const StepArgs<double>&, const CoupleArgs&, hipStream_t,
+                                    const LaunchEvents&);
 template void launch_node_step<float>(const StepArgs<float>&, bool, bool, const BodyArgs*,
-                                      hipStream_t);
+                                      hipStream_t, const LaunchEvents&);
 template void launch_node_step<double>(const StepArgs<double>&, bool, bool, const BodyArgs*,
-                                       hipStream_t);
+                                       hipStream_t, const LaunchEvents&);
 template void launch_init_equilibrium<float>(float*, int64_t, const ReplicaDesc*, const NodeTile*,
                                              int32_t, float, const double*, hipStream_t);
 template void launch_init_equilibrium<double>(double*, int64_t, const ReplicaDesc*,

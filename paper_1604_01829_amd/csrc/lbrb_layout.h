@@ -124,8 +124,15 @@ struct CoupleArgs {
     DeviceHeader* hdr;
 };
 
+// Optional timing of one launch: start/stop events recorded by the dispatch itself
+// (hipExtLaunchKernel), so their interval is the kernel's own duration.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 template <typename Real>
-void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s);
+void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s,
+                   const LaunchEvents& ev = LaunchEvents{});
 // Bodies to finish in a node launch: per-bead forces/torques of the coupling in, body records
 // and the bead records of the next step out.
 struct BodyArgs {
@@ -140,7 +147,7 @@ struct BodyArgs {
 // bodies != null its leading workgroups finish the bodies
 template <typename Real>
 void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const BodyArgs* bodies,
-                      hipStream_t s);
+                      hipStream_t s, const LaunchEvents& ev = LaunchEvents{});
 // pose of the coming step (parity = step & 1) and bead records of every body
 void launch_body_predict(const BodyArgs& b, int parity, hipStream_t s);
 void launch_set_step(int64_t* step_ptr, int64_t value, hipStream_t s);
