@@ -74,8 +74,13 @@ void   orc_trilinear(int nx, int ny, int nz, const double r[3], int64_t idx[8], 
 /* ---- whole box ---- */
 orc_sim* orc_create(int nx, int ny, int nz, const orc_params* p);
 void     orc_destroy(orc_sim* s);
-/* mask[nx*ny*nz], x fastest, 1 = solid.  Only before the first step. 0 ok, -1 error.     */
+/* mask[nx*ny*nz], x fastest: 0 = fluid, k = 1..255 = boundary node of wall k.  Only before
+ * the first step; re-initialises the fluid.  0 ok, -1 error.                              */
 int      orc_set_mask(orc_sim* s, const uint8_t* mask);
+/* Velocity of wall k (1..255; default zero): halfway bounce-back off a moving wall (Ladd)
+ * adds 2 w_i rho0 (c_i . u_w) / c_s^2 to each reflected population.  Only before the first
+ * step; re-initialises the fluid.  0 ok, -1 error.                                        */
+int      orc_set_wall_velocity(orc_sim* s, int wall, const double u[3]);
 /* A raspberry: bead offsets in the body frame (n*3), mass, principal inertia, pose,
  * lab velocity, body-frame angular velocity, bead friction gamma, fixed flag.
  * Returns the body id (>= 0) or -1.                                                       */

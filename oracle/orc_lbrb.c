@@ -50,7 +50,8 @@ struct orc_sim {
     double* f;        /* 19*n, pre-collision */
     double* fpost;    /* 19*n, post-collision scratch */
     double* g;        /* 3*n spread force */
-    uint8_t* mask;
+    uint8_t* mask;    /* 0 = fluid, k > 0 = boundary node of wall k */
+    double uwall[256][3];   /* velocity of wall k (zero unless set) */
     int64_t step;
     int n_bodies, cap_bodies;
     orc_body* bodies;
@@ -274,10 +275,15 @@ static void stream(orc_sim* s)
                     const int sy = wrap(y - TC[i][1], ny);
                     const int sz = wrap(z - TC[i][2], nz);
                     const int64_t src = node_index(s, sx, sy, sz);
-                    if (s->mask[src])
-                        s->f[i * n + here] = s->fpost[TOPP[i] * n + here];
-                    else
+                    if (s->mask[src]) {
+                        /* halfway bounce-back; a wall moving with velocity u_w adds
+                         * 2 w_i rho0 (c_i . u_w) / c_s^2 to the reflected population */
+                        const double* uw = s->uwall[s->mask[src]];
+                        const double cu = TC[i][0] * uw[0] + TC[i][1] * uw[1] + TC[i][2] * uw[2];
+                        s->f[i * n + here] = s->fpost[TOPP[i] * n + here] + 6.0 * TW[i] * s->p.rho0 * cu;
+                    } else {
                         s->f[i * n + here] = s->fpost[i * n + src];
+                    }
                 }
             }
 }
@@ -325,7 +331,15 @@ void orc_destroy(orc_sim* s)
 int orc_set_mask(orc_sim* s, const uint8_t* mask)
 {
     if (!s || !mask || s->step != 0) return -1;
-    for (int64_t x = 0; x < s->n; ++x) s->mask[x] = mask[x] ? 1 : 0;
+    for (int64_t x = 0; x < s->n; ++x) s->mask[x] = mask[x];
+    initialise_fluid(s);
+    return 0;
+}
+
+int orc_set_wall_velocity(orc_sim* s, int wall, const double u[3])
+{
+    if (!s || !u || wall < 1 || wall > 255 || s->step != 0) return -1;
+    for (int a = 0; a < 3; ++a) s->uwall[wall][a] = u[a];
     initialise_fluid(s);
     return 0;
 }

@@ -64,6 +64,8 @@ def lib():
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_set_mask.restype = ctypes.c_int
         L.orc_set_mask.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8)]
+        L.orc_set_wall_velocity.restype = ctypes.c_int
+        L.orc_set_wall_velocity.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
         L.orc_add_body.restype = ctypes.c_int
         L.orc_add_body.argtypes = [ctypes.c_void_p, _D, ctypes.c_int, ctypes.c_double, _D, _D,
                                    _D, _D, _D, ctypes.c_double, ctypes.c_int]
@@ -222,6 +224,11 @@ class OracleSim:
         rc = lib().orc_set_mask(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
         if rc != 0:
             raise RuntimeError("orc_set_mask failed")
+
+    def set_wall_velocity(self, wall, u):
+        rc = lib().orc_set_wall_velocity(self._h, int(wall), _dp(_vec(u, 3)))
+        if rc != 0:
+            raise RuntimeError("orc_set_wall_velocity failed")
 
     def add_body(self, offsets, mass, inertia, pos, quat=(1, 0, 0, 0), vel=(0, 0, 0),
                  omega=(0, 0, 0), gamma=0.0, fixed=False):
