@@ -5,7 +5,7 @@
  * particles: ellipsoids and confinement in cylindrical pores" (arXiv:1604.01829):
  *   - a lattice-Boltzmann fluid that streams and collides with multiple relaxation times
  *     (Sec. 1.1), here on the D3Q19 lattice, thermal (stochastic) or deterministic (Sec. 1.1),
- *     with bounce-back boundary nodes (Sec. 1.1; the pore wall of Sec. 2.2);
+ *     with bounce-back boundary nodes (Sec. 1.1; the pore wall of Sec. 2.3);
  *   - rigid raspberries: beads that are virtual sites of a centre (Sec. 1.2), each coupled to
  *     the fluid by the frictional force of eq. (latticeboltzmannfriction) with the fluid
  *     velocity interpolated between the nearest nodes and a fluctuation-dissipation noise;
@@ -68,6 +68,9 @@ typedef struct {
     double g_ext[3];          /* force density on every fluid node (not on bodies)          */
     int32_t max_bodies;       /* capacity over all replicas                                 */
     int32_t max_beads;        /* capacity over all replicas                                 */
+    int32_t max_wall_links;   /* capacity for moving walls (lb_set_wall_velocity): links
+                                 between a fluid node and a moving boundary node, over all
+                                 replicas (0 = walls at rest only)                           */
 } lb_params;
 
 /* Device bytes needed for these parameters and boxes (upper bound, all nodes fluid).
@@ -83,12 +86,22 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
             void* dev_workspace, size_t ws_bytes, void* hip_stream, lb_ctx** out);
 
 /* Boundary nodes of one replica (the bounce-back rule of Sec. 1.1; the pore wall nodes of
- * Sec. 2.2).  host_mask: nx*ny*nz bytes, x fastest, nonzero = boundary node; copied.
+ * Sec. 2.3).  host_mask: nx*ny*nz bytes, x fastest, 0 = fluid node, k = 1..255 = boundary
+ * node of wall k (walls are at rest unless lb_set_wall_velocity moves them); copied.
  * Every (y,z) row may hold at most one contiguous run of fluid nodes (a row that is fluid
  * everywhere counts as one run), which covers cylindrical pores along z, slabs and
  * channels; other masks return LB_ERR_ARG.  Only before the first step (LB_ERR_STATE
  * otherwise).  Re-initialises that replica's fluid to equilibrium.                        */
 int lb_set_boundary_mask(lb_ctx* ctx, int32_t replica, const uint8_t* host_mask);
+
+/* Velocity u[3] (lab frame) of wall `wall` (1..255) of one replica: the walls of the
+ * Stokes-flow resistance set-up of Sec. 2.3 (eq. (stokesflow)), e.g. the +-y faces of a box.
+ * Halfway bounce-back off a moving wall adds 2 w_i rho0 (c_i . u) / c_s^2 to each reflected
+ * population (Ladd's moving-wall rule).  Only before the first step (LB_ERR_STATE
+ * otherwise); re-initialises that replica's fluid (equilibrium of (rho0, u0) streamed with
+ * the moving walls).  LB_ERR_ARG for a bad replica or wall id, LB_ERR_CAPACITY when the
+ * links between fluid nodes and moving boundary nodes exceed max_wall_links.             */
+int lb_set_wall_velocity(lb_ctx* ctx, int32_t replica, int32_t wall, const double u[3]);
 
 /* Add a raspberry (Sec. 1.2) to a replica.  bead_offsets_body: n_beads*3 body-frame bead
  * positions relative to the centre (a centre bead is just an offset (0,0,0)); mass and
@@ -148,8 +161,9 @@ int rb_bead_forces(lb_ctx* ctx, int32_t replica, int32_t body_id, double* host_o
 int lb_export_populations(lb_ctx* ctx, int32_t replica, double* dev_out);
 
 /* Checkpointing: the complete dynamic state (populations, bodies, step) in bytes that a
- * later lb_load_state of a context with the same parameters, boxes, masks and bodies
- * restores bit for bit.  dev_buf may be NULL to query the size: *bytes receives it.     */
+ * later lb_load_state of a context with the same parameters, boxes, masks, wall velocities
+ * and bodies restores bit for bit.  dev_buf may be NULL to query the size: *bytes
+ * receives it.                                                                            */
 int lb_save_state(lb_ctx* ctx, void* dev_buf, size_t* bytes);
 int lb_load_state(lb_ctx* ctx, const void* dev_buf, size_t bytes);
 

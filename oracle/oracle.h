@@ -10,7 +10,7 @@
  * arXiv:1604.01829):
  *   - the lattice-Boltzmann stream / collide cycle with multiple relaxation times
  *     (Sec. 1.1, "Hydrodynamic Interactions"), on the D3Q19 lattice;
- *   - bounce-back boundary nodes (Sec. 1.1, last paragraph; Sec. 2.2 for the pore wall);
+ *   - bounce-back boundary nodes (Sec. 1.1, last paragraph; Sec. 2.3 for the pore wall);
  *   - the stochastic (thermal) variant of the fluid (Sec. 1.1);
  *   - the frictional bead/fluid coupling, eq. (latticeboltzmannfriction) in Sec. 1.1,
  *     with the fluid velocity interpolated between the nearest nodes and a bead noise

@@ -16,6 +16,7 @@
 
 #include "../../include/lbrb.h"
 #include "lbrb_layout.h"
+#include "lbrb_walls.h"
 
 using namespace lbrb;
 
@@ -32,10 +33,11 @@ struct Plan {
     int64_t rows_cap = 0;     // sum of ny*nz
     int64_t tiles_cap = 0;    // sum of ceil(nodes / 256)
     int64_t bead_cap = 0, body_cap = 0;
+    int64_t link_cap = 0;     // moving-wall links
     int gforce_words = 3;     // fixed-point words per node: 3 axes x (1 in FP32, 2 in FP64)
     size_t off_hdr, off_reps, off_rows, off_rowinfo, off_tiles_d, off_tiles_m, off_fa, off_fb,
         off_gforce, off_flags, off_bodies, off_bead_off, off_bead_rec, off_bead_force,
-        off_bead_torque, off_partials, total;
+        off_bead_torque, off_partials, off_links, total;
 };
 
 bool valid_params(const lb_params* p)
@@ -49,7 +51,7 @@ bool valid_params(const lb_params* p)
     if (!(p->kT >= 0) || !std::isfinite(p->kT)) return false;
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(p->u0[a]) || !std::isfinite(p->g_ext[a])) return false;
-    if (p->max_bodies < 0 || p->max_beads < 0) return false;
+    if (p->max_bodies < 0 || p->max_beads < 0 || p->max_wall_links < 0) return false;
     return true;
 }
 
@@ -70,6 +72,7 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
     const size_t real = p->precision == LB_PRECISION_F32 ? sizeof(float) : sizeof(double);
     pl.body_cap = p->max_bodies;
     pl.bead_cap = p->max_beads;
+    pl.link_cap = p->max_wall_links;
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes, kAlign); return at; };
     pl.off_hdr = take(sizeof(DeviceHeader));
@@ -89,6 +92,7 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
     pl.off_bead_force = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
     pl.off_bead_torque = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
     pl.off_partials = take(sizeof(double) * 5 * pl.tiles_cap);
+    pl.off_links = take(sizeof(WallLink) * std::max<int64_t>(pl.link_cap, 1));
     pl.total = o;
     return true;
 }
@@ -97,6 +101,10 @@ struct ReplicaHost {
     int group = 0;            // 0 = dense tiles, 1 = masked tiles
     int32_t tile0 = 0, n_tiles = 0;
     std::vector<int32_t> bodies;
+    std::vector<uint8_t> mask;      // boundary mask as set (wall ids), empty = all fluid
+    std::vector<double> uwall;      // 3 per wall id 0..255 once a wall velocity was set
+    std::vector<WallLink> links;    // moving-wall links of this replica
+    int64_t link0 = 0;              // their first entry in the device list
 };
 
 struct EventPair { hipEvent_t a, b; };
@@ -125,6 +133,8 @@ struct lb_ctx {
     double* d_bead_force = nullptr;
     double* d_bead_torque = nullptr;
     double* d_partials = nullptr;
+    WallLink* d_links = nullptr;
+    int64_t n_links = 0;
     // host mirrors
     std::vector<ReplicaDesc> reps;
     std::vector<RowDesc> rows;
@@ -294,6 +304,10 @@ hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* st
         if (timed && e.a && e.b) c->ev_node.push_back(e);
         finished = true;
     }
+    if (c->n_links > 0) {
+        launch_wall_links<Real>(ag[0].dst, c->d_links, c->n_links, s);
+        note(hipGetLastError());
+    }
     return err;
 }
 
@@ -417,8 +431,82 @@ int init_fluid(lb_ctx* c, int replica)
                                             c->d_tiles[g] + t0, nt, c->p.rho0, c->p.u0,
                                             c->stream);
     }
+    // the fluid starts just before a streaming step: the moving walls' terms go in now
+    for (int r = 0; r < c->n_rep; ++r) {
+        if (replica >= 0 && r != replica) continue;
+        const ReplicaHost& H = c->rh[r];
+        if (H.links.empty()) continue;
+        if (is_f32(c))
+            launch_wall_links<float>((float*)c->f[c->cur], c->d_links + H.link0,
+                                     (int64_t)H.links.size(), c->stream);
+        else
+            launch_wall_links<double>((double*)c->f[c->cur], c->d_links + H.link0,
+                                      (int64_t)H.links.size(), c->stream);
+    }
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+// Moving-wall links of one replica: every fluid node x and direction i whose neighbour
+// x - c_i (periodic) is a boundary node of a wall k with c_i . u_k != 0.  info holds the
+// replica's (start, xlo, len) per (y,z) row, mask its wall ids, uwall 3 velocities per id.
+std::vector<WallLink> build_links(const ReplicaDesc& R, const uint8_t* mask,
+                                  const RowDesc* info, const std::vector<double>& uwall,
+                                  double rho0)
+{
+    std::vector<WallLink> out;
+    if (!mask || uwall.empty()) return out;
+    const int nx = R.nx, ny = R.ny, nz = R.nz;
+    auto wrapi = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y) {
+            const RowDesc& row = info[(size_t)y + (size_t)ny * z];
+            for (int x = row.xlo; x < row.xlo + row.len; ++x)
+                for (int i = 1; i < Q; ++i) {
+                    const int bx = wrapi(x - cx_of(i), nx), by = wrapi(y - cy_of(i), ny),
+                              bz = wrapi(z - cz_of(i), nz);
+                    const uint8_t k = mask[bx + (size_t)nx * (by + (size_t)ny * bz)];
+                    if (!k) continue;
+                    const double* u = &uwall[3 * (size_t)k];
+                    const double cu = cx_of(i) * u[0] + cy_of(i) * u[1] + cz_of(i) * u[2];
+                    if (cu == 0.0) continue;
+                    WallLink L{};
+                    L.g = R.base + row.start + (x - row.xlo);
+                    L.pop = opposite_of(i);
+                    L.delta = 6.0 * weight_of(i) * rho0 * cu;
+                    out.push_back(L);
+                }
+        }
+    // in storage order of the slots they update
+    std::sort(out.begin(), out.end(), [](const WallLink& a, const WallLink& b) {
+        return pop_at(a.pop, a.g) < pop_at(b.pop, b.g);
+    });
+    return out;
+}
+
+int64_t links_without(const lb_ctx* c, int32_t replica)
+{
+    int64_t n = 0;
+    for (int r = 0; r < c->n_rep; ++r)
+        if (r != replica) n += (int64_t)c->rh[r].links.size();
+    return n;
+}
+
+// concatenate the replicas' links (replica order) into the device list
+int upload_links(lb_ctx* c)
+{
+    std::vector<WallLink> all;
+    for (int r = 0; r < c->n_rep; ++r) {
+        c->rh[r].link0 = (int64_t)all.size();
+        all.insert(all.end(), c->rh[r].links.begin(), c->rh[r].links.end());
+    }
+    c->n_links = (int64_t)all.size();
+    if (!all.empty()) {
+        HIP_TRY(c, hipMemcpyAsync(c->d_links, all.data(), sizeof(WallLink) * all.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
     return LB_OK;
 }
 
@@ -510,6 +598,7 @@ void enqueue_replay(lb_ctx* c, hipStream_t s, const void* src, void* dst, int64_
     for (int g = 0; g < 2; ++g)
         if (ag[g].n_tiles > 0)
             launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, nullptr, s);
+    if (c->n_links > 0) launch_wall_links<Real>(ag[0].dst, c->d_links, c->n_links, s);
 }
 
 // one reverse step at forward step `step` (index n of the window), forward state pulled from src
@@ -634,6 +723,7 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     c->d_bead_force = (double*)(c->ws + pl.off_bead_force);
     c->d_bead_torque = (double*)(c->ws + pl.off_bead_torque);
     c->d_partials = (double*)(c->ws + pl.off_partials);
+    c->d_links = (WallLink*)(c->ws + pl.off_links);
 
     c->reps.resize(n_replicas);
     c->rh.resize(n_replicas);
@@ -708,6 +798,12 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
             rows.push_back(d);
             start += d.len;
         }
+    // links of the replica's moving walls under the new mask, checked before anything changes
+    ReplicaHost& H = c->rh[replica];
+    std::vector<WallLink> links;
+    if (any_solid) links = build_links(R, mask, info.data(), H.uwall, c->p.rho0);
+    if (links_without(c, replica) + (int64_t)links.size() > c->plan.link_cap)
+        return fail(c, LB_ERR_CAPACITY, "moving-wall links exceed max_wall_links");
     // rows of this replica go to rows[row_base ...]; clear the old ones first
     for (int64_t k = 0; k < (int64_t)ny * nz; ++k) {
         c->rowinfo[R.row_base + k] = RowDesc{0, 0, 0, 0};
@@ -718,23 +814,54 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
         for (int64_t k = 0; k < (int64_t)ny * nz; ++k) c->rowinfo[R.row_base + k] = info[k];
         R.masked = 1;
         R.n_fluid = start;
+        H.mask.assign(mask, mask + (size_t)nx * ny * nz);
     } else {
         R.masked = 0;
         R.n_fluid = R.n_nodes;
+        H.mask.clear();
     }
+    H.links.swap(links);
     destroy_graphs(c);
     rebuild_tiles(c);
     int rc = upload_tables(c);
+    if (rc == LB_OK) rc = upload_links(c);
     if (rc != LB_OK) return rc;
     // bodies already in this replica carry a copy of its geometry (no step has run yet, so
     // the host records are still the bodies' state)
-    for (int32_t b : c->rh[replica].bodies) {
+    for (int32_t b : H.bodies) {
         c->bodies0[b].box = body_box(R);
         HIP_TRY(c, hipMemcpyAsync(c->d_bodies + b, &c->bodies0[b], sizeof(Body),
                                   hipMemcpyHostToDevice, c->stream));
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->pose_stale = true;   // the bead records carry the replica geometry
+    return init_fluid(c, replica);
+}
+
+int lb_set_wall_velocity(lb_ctx* c, int32_t replica, int32_t wall, const double u[3])
+{
+    if (!c) return LB_ERR_ARG;
+    if (!check_replica(c, replica)) return LB_ERR_ARG;
+    if (wall < 1 || wall > 255) return fail(c, LB_ERR_ARG, "wall ids are 1..255");
+    if (!u || !std::isfinite(u[0]) || !std::isfinite(u[1]) || !std::isfinite(u[2]))
+        return fail(c, LB_ERR_ARG, "missing or non-finite wall velocity");
+    if (c->step != 0)
+        return fail(c, LB_ERR_STATE, "wall velocities can only be set before the first step");
+    const ReplicaDesc& R = c->reps[replica];
+    ReplicaHost& H = c->rh[replica];
+    std::vector<double> uw = H.uwall;
+    if (uw.empty()) uw.assign(3 * 256, 0.0);
+    for (int a = 0; a < 3; ++a) uw[3 * (size_t)wall + a] = u[a];
+    std::vector<WallLink> links;
+    if (!H.mask.empty())
+        links = build_links(R, H.mask.data(), &c->rowinfo[R.row_base], uw, c->p.rho0);
+    if (links_without(c, replica) + (int64_t)links.size() > c->plan.link_cap)
+        return fail(c, LB_ERR_CAPACITY, "moving-wall links exceed max_wall_links");
+    H.uwall.swap(uw);
+    H.links.swap(links);
+    destroy_graphs(c);
+    int rc = upload_links(c);
+    if (rc != LB_OK) return rc;
     return init_fluid(c, replica);
 }
 

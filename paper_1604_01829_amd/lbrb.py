@@ -27,7 +27,8 @@ LB_PRECISION_F64 = 0
 LB_PRECISION_F32 = 1
 
 # every symbol declared in include/lbrb.h
-EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "rb_add_raspberry",
+EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wall_velocity",
+            "rb_add_raspberry",
             "lb_rb_step", "lb_observables", "lb_body_count", "rb_bead_forces",
             "lb_export_populations", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
             "lb_set_timing", "lb_kernel_times", "lb_adjoint_workspace_bytes", "lb_rb_adjoint",
@@ -45,7 +46,7 @@ class lb_params(ctypes.Structure):
                 ("tau_bulk", ctypes.c_double), ("tau_odd", ctypes.c_double),
                 ("tau_even", ctypes.c_double), ("kT", ctypes.c_double),
                 ("g_ext", ctypes.c_double * 3), ("max_bodies", ctypes.c_int32),
-                ("max_beads", ctypes.c_int32)]
+                ("max_beads", ctypes.c_int32), ("max_wall_links", ctypes.c_int32)]
 
 
 class lb_totals(ctypes.Structure):
@@ -81,6 +82,8 @@ def library():
                           _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]
     L.lb_set_boundary_mask.restype = ctypes.c_int
     L.lb_set_boundary_mask.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8)]
+    L.lb_set_wall_velocity.restype = ctypes.c_int
+    L.lb_set_wall_velocity.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32, _D]
     L.rb_add_raspberry.restype = ctypes.c_int
     L.rb_add_raspberry.argtypes = [_VP, ctypes.c_int32, _D, ctypes.c_int32, ctypes.c_double, _D,
                                    _D, _D, _D, _D, ctypes.c_double, ctypes.c_int32,
@@ -142,7 +145,7 @@ def _dp(a):
 
 def make_params(precision="f32", rho0=1.0, u0=(0.0, 0.0, 0.0), tau_shear=1.0, tau_bulk=None,
                 tau_odd=1.0, tau_even=1.0, kT=0.0, g_ext=(0.0, 0.0, 0.0), max_bodies=0,
-                max_beads=0):
+                max_beads=0, max_wall_links=0):
     p = lb_params()
     p.precision = LB_PRECISION_F32 if precision in ("f32", LB_PRECISION_F32) else LB_PRECISION_F64
     p.rho0 = rho0
@@ -155,6 +158,7 @@ def make_params(precision="f32", rho0=1.0, u0=(0.0, 0.0, 0.0), tau_shear=1.0, ta
     p.g_ext[:] = list(g_ext)
     p.max_bodies = max_bodies
     p.max_beads = max_beads
+    p.max_wall_links = max_wall_links
     return p
 
 
@@ -189,6 +193,11 @@ def lb_set_boundary_mask(ctx, replica, mask):
     _check(ctx, library().lb_set_boundary_mask(ctx, replica,
                                                m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))),
            "lb_set_boundary_mask")
+
+
+def lb_set_wall_velocity(ctx, replica, wall, u):
+    _check(ctx, library().lb_set_wall_velocity(ctx, int(replica), int(wall), _dp(_arr(u, 3))),
+           "lb_set_wall_velocity")
 
 
 def rb_add_raspberry(ctx, replica, offsets, mass, inertia, pos, quat=(1, 0, 0, 0),
@@ -281,6 +290,9 @@ class Simulation:
 
     def set_mask(self, replica, mask):
         lb_set_boundary_mask(self.ctx, replica, mask)
+
+    def set_wall_velocity(self, replica, wall, u):
+        lb_set_wall_velocity(self.ctx, replica, wall, u)
 
     def add_body(self, replica, offsets, mass, inertia, pos, quat=(1, 0, 0, 0), vel=(0, 0, 0),
                  omega=(0, 0, 0), gamma=0.0, fixed=False):
@@ -382,6 +394,14 @@ class Simulation:
                "lb_load_state")
 
 
+def wall_link_bound(mask, walls):
+    """Upper bound of the moving-wall links of one replica: 18 per boundary node of a wall
+    given a velocity (a boundary node faces at most 18 fluid neighbours)."""
+    if mask is None or not walls:
+        return 0
+    return 18 * int(np.isin(np.asarray(mask), [int(w) for w in walls]).sum())
+
+
 def simulation_from_workload(wl, precision=None, device="cuda:0", replicas=None,
                              max_extra_bodies=0, max_extra_beads=0):
     """Build a Simulation from a record of ``paper_1604_01829_amd.workloads.workload``."""
@@ -391,12 +411,15 @@ def simulation_from_workload(wl, precision=None, device="cuda:0", replicas=None,
     n_beads = sum(b["offsets"].shape[0] for r in reps for b in r["bodies"]) + max_extra_beads
     pp = dict(wl["params"])
     params = make_params(precision=prec, max_bodies=max(1, n_bodies), max_beads=max(1, n_beads),
-                         **pp)
+                         max_wall_links=sum(wall_link_bound(r["mask"], r.get("walls"))
+                                            for r in reps), **pp)
     rr = make_replicas([(r["shape"], r["seed"]) for r in reps])
     sim = Simulation(params, rr, device=device)
     for k, r in enumerate(reps):
         if r["mask"] is not None:
             sim.set_mask(k, r["mask"])
+        for wall, u in (r.get("walls") or {}).items():
+            sim.set_wall_velocity(k, wall, u)
         for b in r["bodies"]:
             sim.add_body(k, b["offsets"], b["mass"], b["inertia"], b["pos"], b["quat"], b["vel"],
                          b["omega"], b["gamma"], b["fixed"])
@@ -468,3 +491,25 @@ def calibrate_gamma(builder, n_steps, weights, target, gamma0, checkpoint_every=
         # stay positive: halve towards zero instead of stepping through it
         g = g_new if g_new > 0 else 0.5 * g
     raise LBError(LB_ERR_UNSTABLE, "calibration did not converge")
+
+
+# ------------------------------------------------------------------ Stokes-flow resistance
+
+def stokes_flow_resistance(sim, replica, body, u_wall, n_develop, n_samples=100, every=10):
+    """Colloid resistance from Stokes flow past a fixed raspberry (Sec. 2.3, eq.
+    (stokesflow)): run n_develop steps for the flow to develop, then take n_samples
+    measurements, `every` steps apart, of the summed bead force on the body; their mean F
+    balances the resistance times the imposed boundary velocity, so
+    xi_col = (F . u) / |u|^2 (the force on a fixed colloid points along the flow).
+    Returns (mean force (3,), xi_col)."""
+    u = np.asarray(u_wall, dtype=np.float64)
+    if not float(u @ u) > 0.0:
+        raise ValueError("the imposed velocity must be nonzero")
+    sim.step(n_develop)
+    acc = np.zeros(3)
+    for _ in range(n_samples):
+        sim.step(every)
+        _, bodies, _, _ = sim.observables(replica)
+        acc += bodies[body]["force"]
+    F = acc / n_samples
+    return F, float(F @ u / (u @ u))

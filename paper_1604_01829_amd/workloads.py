@@ -8,7 +8,7 @@ The paper's own raspberries come from an MD relaxation of beads on a surface (Se
 its coordinate files are not available.  The stand-ins here keep the same structure: a shell
 of beads spread evenly over a sphere or an ellipsoid of revolution (Sec. 1.2, Fig. "rasp")
 plus one centre bead, at one to two beads per unit area, in cubic periodic boxes or in boxes
-holding a cylindrical pore along z whose boundary nodes sit outside the wall (Sec. 2.2).
+holding a cylindrical pore along z whose boundary nodes sit outside the wall (Sec. 2.3).
 """
 import math
 
@@ -272,3 +272,34 @@ def workload(k, scale=1.0, gamma=None):
                     params=default_params(u0=(0.01, 0.0, 0.0)),
                     replicas=[dict(shape=shape, seed=seed, mask=None, bodies=bodies)])
     raise ValueError(k)
+
+
+# ------------------------------------------------------------------ Stokes-flow resistance
+
+# The paper's Stokes-flow set-up (Sec. 2.3, eq. (stokesflow)) in lattice units: grid
+# spacing 1 nm, fluid step 0.02 t0 with t0 = 6.352 ps, simulated kinematic viscosity
+# 0.8 sigma^2/t0, boundary velocity 2.20 m/s along z on the +-y faces of a 50 nm box.
+STOKES_DT_SECONDS = 0.02 * 6.352e-12
+STOKES_U_PAPER = 2.20 * STOKES_DT_SECONDS / 1e-9          # 2.79e-4 lattice units per step
+STOKES_TAU_PAPER = 0.5 + 3.0 * (0.8 * 0.02)                # nu = 0.016 -> tau = 0.548
+STOKES_BOX_PAPER = 50
+
+
+def stokes_flow_workload(L=STOKES_BOX_PAPER, radius=5.25, U=STOKES_U_PAPER,
+                         tau_shear=STOKES_TAU_PAPER, gamma=GAMMA_FIXED, precision="f64",
+                         per_area=2.2, seed=0):
+    """A fixed spherical raspberry at the centre of a cubic box whose -y and +y faces are
+    boundary nodes of one wall (id 1) moving with (0, 0, U); thermostat off.  The fluid
+    starts at the wall velocity, so only the disturbance of the particle has to develop.
+    The record has the layout of ``workload`` plus walls={id: velocity}."""
+    offs = sphere_beads(radius, sphere_bead_count(radius, per_area))
+    m, I = solid_body_mass_inertia(1.0, radius, radius, radius)
+    pos = np.array([L / 2.0, L / 2.0, L / 2.0]) + np.array([0.013, -0.021, 0.017])
+    mask = slab_mask(L, L, L, axis=1)
+    bodies = [body_record(offs, m, I, pos, gamma=gamma, fixed=True)]
+    return dict(name=f"Stokes flow past a fixed sphere R={radius} in a {L}^3 channel",
+                precision=precision, steps=0,
+                params=default_params(u0=(0.0, 0.0, U), tau_shear=tau_shear,
+                                      tau_bulk=tau_shear),
+                replicas=[dict(shape=(L, L, L), seed=PHILOX_SEED_BASE + 60 + seed, mask=mask,
+                               bodies=bodies, walls={1: (0.0, 0.0, U)})])

@@ -23,6 +23,8 @@ def oracle_from_workload(wl, r=0):
     sim._offsets = [np.asarray(bd["offsets"]) for bd in rep["bodies"]]
     if rep["mask"] is not None:
         sim.set_mask(rep["mask"])
+    for wall, u in (rep.get("walls") or {}).items():
+        sim.set_wall_velocity(wall, u)
     for b in rep["bodies"]:
         sim.add_body(b["offsets"], b["mass"], b["inertia"], b["pos"], b["quat"], b["vel"],
                      b["omega"], b["gamma"], b["fixed"])
@@ -134,3 +136,16 @@ def first_step_expected(shape, mask, params, seed, kT, nodes):
         u = (c.T @ f + 0.5 * gext) / rho
         out.append((rho, u))
     return out
+
+
+def oracle_stokes_resistance(orc, body, u_wall, n_develop, n_samples=100, every=10):
+    """The Stokes-flow protocol of the library's stokes_flow_resistance, driven on the
+    oracle: develop, then the mean of n_samples body forces `every` steps apart."""
+    u = np.asarray(u_wall, dtype=np.float64)
+    orc.step(n_develop)
+    acc = np.zeros(3)
+    for _ in range(n_samples):
+        orc.step(every)
+        acc += orc.body_state(body)["force"]
+    F = acc / n_samples
+    return F, float(F @ u / (u @ u))

@@ -44,12 +44,16 @@ def test_workspace_bytes_and_argument_checks():
     n64 = lbrb.lb_workspace_bytes(_params(precision="f64", max_bodies=1, max_beads=10), reps)
     # two population buffers dominate: 2 x 19 x 4 (8) bytes per node
     assert n32 >= 2 * 19 * 4 * 32 ** 3 and n64 >= 2 * 19 * 8 * 32 ** 3 and n64 > n32
+    # 24 bytes per moving-wall link
+    nl = lbrb.lb_workspace_bytes(_params(precision="f32", max_bodies=1, max_beads=10,
+                                         max_wall_links=100000), reps)
+    assert abs((nl - n32) - 24 * 100000) <= 256
     big = lbrb.lb_workspace_bytes(_params(precision="f32"),
                                   lbrb.make_replicas([((32, 32, 32), 1), ((40, 40, 40), 2)]))
     assert big > lbrb.lb_workspace_bytes(_params(precision="f32"), reps)
     # invalid parameters or boxes: 0 bytes
     for bad in (dict(tau_shear=0.5), dict(tau_bulk=0.4), dict(rho0=0.0), dict(kT=-1.0),
-                dict(max_beads=-1), dict(u0=(float("nan"), 0, 0))):
+                dict(max_beads=-1), dict(max_wall_links=-1), dict(u0=(float("nan"), 0, 0))):
         assert lbrb.lb_workspace_bytes(_params(**bad), reps) == 0, bad
     for shape in ((0, 4, 4), (4, -1, 4), (40000, 4, 4), (2048, 2048, 1024)):
         assert lbrb.lb_workspace_bytes(_params(), lbrb.make_replicas([(shape, 1)])) == 0, shape
@@ -65,6 +69,8 @@ def test_workspace_bytes_and_argument_checks():
     assert L.lb_init(ctypes.byref(p), reps, 1, None, need, None, None) == lbrb.LB_ERR_ARG
     # null contexts
     assert L.lb_rb_step(None, 1) == lbrb.LB_ERR_ARG
+    u = (ctypes.c_double * 3)(0.0, 0.0, 0.01)
+    assert L.lb_set_wall_velocity(None, 0, 1, u) == lbrb.LB_ERR_ARG
     assert L.lb_adjoint_workspace_bytes(None, 10, 2) == 0
     assert L.lb_last_error(None) == b"null context"
 
