@@ -17,7 +17,10 @@
  *     obeying fluctuation-dissipation;
  *   - raspberry rigid bodies whose beads are virtual sites of a centre (Sec. 1.2), with
  *     forces/torques summed onto the centre in the body frame and a velocity-Verlet /
- *     quaternion update of the centre (Sec. 2.3, "Simulation parameters").
+ *     quaternion update of the centre (Sec. 2.3, "Simulation parameters");
+ *   - several MD steps per fluid step (Sec. 2.3: the fluid step is twice the MD step) and the
+ *     WCA excluded volume between a body's inner-layer sites and the pore beads or the inner
+ *     sites of other bodies (Sec. 2.1 two-layer raspberries; Sec. 2.3 pore beads).
  * The paper names these steps but gives no formulas for the lattice scheme, forcing,
  * noise or integrator; every such choice made here is listed, with its reason, in the
  * design document of the repository ("readings").  All quantities are in lattice units
@@ -47,6 +50,9 @@ typedef struct {
     double kT;            /* thermal energy; 0 = deterministic fluid and beads        */
     double g_ext[3];      /* body-force density acting on every fluid node            */
     uint64_t seed;        /* Philox key of this box                                   */
+    int32_t md_substeps;  /* MD steps per fluid step (0 or 1: one)                    */
+    int32_t pad;
+    double wca_epsilon;   /* WCA energy scale (0: no excluded volume)                 */
 } orc_params;
 
 /* ---- lattice and mode tables (exposed so the tests can pin them) ---- */
@@ -88,6 +94,26 @@ int      orc_add_body(orc_sim* s, const double* offsets, int n_beads, double mas
                       const double inertia[3], const double pos[3], const double quat[4],
                       const double vel[3], const double omega_body[3], double gamma,
                       int fixed);
+/* Excluded-volume sites of a body (the inner layer of a two-layer raspberry, Sec. 2.1:
+ * sites that are not coupled to the fluid and only repel other sites): n body-frame
+ * offsets (n*3) and their Lennard-Jones radius.  Replaces earlier sites of the body.  Only
+ * before the first step.  0 ok, -1 error.                                                 */
+int      orc_set_excluded_volume(orc_sim* s, int body, const double* offsets, int n,
+                                 double radius);
+/* Static sites (the pore beads of Sec. 2.3): n lab positions (n*3) of one Lennard-Jones
+ * radius, appended to the box's sites.  Only before the first step.  0 ok, -1 error.      */
+int      orc_add_wall_sites(orc_sim* s, const double* pos, int n, double radius);
+/* WCA forces and torques (lab frame, torque about each centre) on every body at the
+ * current poses, 6 per body; and the total WCA energy (each pair once).  A pair of sites
+ * with radii r_a, r_b (sigma = r_a + r_b) at minimum-image distance r < 2^(1/6) sigma has
+ * energy 4 eps ((sigma/r)^12 - (sigma/r)^6) + eps.                                         */
+int      orc_wca_forces(const orc_sim* s, double* out);
+double   orc_wca_energy(const orc_sim* s);
+/* Advance by n_steps fluid steps.  With md_substeps = m > 1 every fluid step holds m MD
+ * steps of length h = 1/m on the frozen fluid: each does the first half kick and drift,
+ * the coupling (bead noise of its own, variance 2 kT gamma / h per component) plus the WCA
+ * forces, and the second half kick; the fluid receives -h times each MD step's coupling
+ * force, then collides and streams once.                                                  */
 int      orc_step(orc_sim* s, int n_steps);
 int64_t  orc_step_count(const orc_sim* s);
 /* rho and u = (j + g_ext/2)/rho of the current pre-collision state, 4*N, node-major
@@ -101,7 +127,8 @@ void     orc_set_populations(orc_sim* s, const double* f);
 /* out[0] = sum rho, out[1..3] = sum j, out[4..6] = sum of M V over free bodies,
  * out[7] = 1 if every population is finite else 0                                        */
 void     orc_totals(const orc_sim* s, double out[8]);
-/* pos3 quat4 vel3 omega_body3 force3 (lab, last step) torque3 (body frame, last step)    */
+/* pos3 quat4 vel3 omega_body3 force3 (lab, last MD step: coupling + WCA) torque3 (body
+ * frame, last MD step)                                                                     */
 int      orc_body_state(const orc_sim* s, int body, double out[19]);
 /* per-bead force of the last step, lab frame, n_beads*3 for the body                     */
 int      orc_bead_forces(const orc_sim* s, int body, double* out);
@@ -115,7 +142,8 @@ void     orc_collide_vjp(const orc_params* p, const double f_in[19], const doubl
 /* Advance the box by n_steps while computing J = sum_n sum_b dJ_dF[n][b] . F_b(n)
  * (dJ_dF: n_steps * n_bodies * 3) and its derivatives with respect to each body's gamma
  * (dJ_dgamma[n_bodies]) and every bead offset (dJ_doffsets: total beads * 3, bodies in
- * order).  Requires kT = 0 and all bodies fixed; p must be the box's parameters.
+ * order).  Requires kT = 0, all bodies fixed, one MD step per fluid step and no
+ * excluded-volume or wall sites; p must be the box's parameters.
  * Returns 0, or -1 on a violated requirement.                                              */
 int      orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies,
                      const double* dJ_dF, double* J_out, double* dJ_dgamma, double* dJ_doffsets);

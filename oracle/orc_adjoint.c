@@ -36,6 +36,7 @@ const uint8_t* orc_box_mask(const orc_sim* s);
 int orc_box_body(const orc_sim* s, int b, const double** offsets, int* n_beads, double pos[3],
                  double quat[4], double* gamma, int* fixed);
 double orc_box_kT(const orc_sim* s);
+int orc_box_plain_md(const orc_sim* s);
 
 static double E_(int k, int i) { return orc_basis(k, i); }
 
@@ -167,7 +168,7 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
     const int nx = dims[0], ny = dims[1], nz = dims[2];
     const int64_t N = (int64_t)nx * ny * nz;
     const uint8_t* mask = orc_box_mask(s);
-    if (orc_box_kT(s) != 0.0 || n_steps < 0) return -1;
+    if (orc_box_kT(s) != 0.0 || !orc_box_plain_md(s) || n_steps < 0) return -1;
 
     /* bodies: fixed, constant bead positions */
     int total_beads = 0;

@@ -11,17 +11,20 @@
  *               force F and body-frame torque T of the previous step) and the body-frame
  *               offsets b_k of their beads.
  *
- * One step n -> n+1, in this order (the paper's description of each part is cited inline):
- *   1  free bodies: half kick with last step's force/torque, drift, quaternion rotation
+ * One step n -> n+1, in this order (the paper's description of each part is cited inline);
+ * steps 1-7 and 10 form one MD step of length h, repeated m = md_substeps times (h = 1/m)
+ * on the frozen fluid before 8 and 9:
+ *   1  free bodies: half kick with last MD step's force/torque, drift, quaternion rotation
  *   2  bead positions r_k = R + R(q) b_k and velocities v_k = V + R(q)(w x b_k)
  *   3  node velocities u = (j + g_ext/2)/rho from the current populations
  *   4  trilinear interpolation of u at each bead
  *   5  friction + bead noise F_k = -gamma (v_k - u_k) + f_s
- *   6  the opposite force -F_k spread onto the same 8 nodes with the same weights
- *   7  body force F = sum F_k and torque T = sum (r_k - R) x F_k, torque into the body frame
+ *   6  the opposite force -h F_k spread onto the same 8 nodes with the same weights
+ *   7  body force F = sum F_k + WCA forces of its excluded-volume sites, torque
+ *      T = sum (r_k - R) x F_k (+ the same for the sites), torque into the body frame
  *   8  collision of every fluid node in mode space with the force g_ext + spread force
  *   9  streaming with halfway bounce-back at boundary nodes
- *  10  free bodies: second half kick with this step's force/torque
+ *  10  free bodies: second half kick with this MD step's force/torque
  */
 #include "oracle.h"
 
@@ -41,6 +44,9 @@ typedef struct {
     int64_t first_bead;                /* index of the first bead in the box's bead numbering */
     double* offsets;                   /* n_beads*3, body frame                               */
     double* bead_force;                /* n_beads*3, lab frame, last step                     */
+    int n_ev;                          /* excluded-volume sites (not coupled to the fluid)    */
+    double* ev_offsets;                /* n_ev*3, body frame                                  */
+    double ev_radius;
 } orc_body;
 
 struct orc_sim {
@@ -56,6 +62,9 @@ struct orc_sim {
     int n_bodies, cap_bodies;
     orc_body* bodies;
     int64_t n_beads_total;
+    int n_sites;          /* static WCA sites (pore beads) */
+    double* site_pos;     /* n_sites*3, lab */
+    double* site_radius;  /* n_sites */
 };
 
 /* ------------------------------------------------------------------------- helpers */
@@ -322,8 +331,11 @@ void orc_destroy(orc_sim* s)
     for (int b = 0; b < s->n_bodies; ++b) {
         free(s->bodies[b].offsets);
         free(s->bodies[b].bead_force);
+        free(s->bodies[b].ev_offsets);
     }
     free(s->bodies);
+    free(s->site_pos);
+    free(s->site_radius);
     free(s->f); free(s->fpost); free(s->g); free(s->mask);
     free(s);
 }
@@ -382,23 +394,23 @@ int orc_add_body(orc_sim* s, const double* offsets, int n_beads, double mass,
 
 /* step 1: first half kick (previous force/torque), drift, rotation by the exponential of
  * the body-frame angular velocity (Sec. 2.3: velocity Verlet for the centre, quaternion
- * update from the angular velocity).                                                       */
-static void body_first_half(orc_body* b)
+ * update from the angular velocity), over an MD step of length h.                          */
+static void body_first_half(orc_body* b, double h)
 {
     if (b->fixed) return;
     double Iw[3], wxIw[3];
-    for (int a = 0; a < 3; ++a) b->vel[a] += 0.5 * b->force[a] / b->mass;
+    for (int a = 0; a < 3; ++a) b->vel[a] += 0.5 * h * b->force[a] / b->mass;
     for (int a = 0; a < 3; ++a) Iw[a] = b->inertia[a] * b->omega[a];
     cross(b->omega, Iw, wxIw);
     for (int a = 0; a < 3; ++a)
-        b->omega[a] += 0.5 * (b->torque_body[a] - wxIw[a]) / b->inertia[a];
-    for (int a = 0; a < 3; ++a) b->pos[a] += b->vel[a];
+        b->omega[a] += 0.5 * h * (b->torque_body[a] - wxIw[a]) / b->inertia[a];
+    for (int a = 0; a < 3; ++a) b->pos[a] += h * b->vel[a];
     const double wn = sqrt(b->omega[0] * b->omega[0] + b->omega[1] * b->omega[1] +
                            b->omega[2] * b->omega[2]);
     if (wn > 0.0) {
-        const double h = 0.5 * wn;
-        const double dq[4] = {cos(h), sin(h) * b->omega[0] / wn, sin(h) * b->omega[1] / wn,
-                              sin(h) * b->omega[2] / wn};
+        const double ang = 0.5 * h * wn;   /* half the rotation angle */
+        const double dq[4] = {cos(ang), sin(ang) * b->omega[0] / wn,
+                              sin(ang) * b->omega[1] / wn, sin(ang) * b->omega[2] / wn};
         double qn[4];
         quat_mul(b->quat, dq, qn);
         const double nrm = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
@@ -406,16 +418,16 @@ static void body_first_half(orc_body* b)
     }
 }
 
-/* step 10: second half kick with this step's force and body-frame torque                  */
-static void body_second_half(orc_body* b)
+/* step 10: second half kick with this MD step's force and body-frame torque               */
+static void body_second_half(orc_body* b, double h)
 {
     if (b->fixed) return;
     double Iw[3], wxIw[3];
-    for (int a = 0; a < 3; ++a) b->vel[a] += 0.5 * b->force[a] / b->mass;
+    for (int a = 0; a < 3; ++a) b->vel[a] += 0.5 * h * b->force[a] / b->mass;
     for (int a = 0; a < 3; ++a) Iw[a] = b->inertia[a] * b->omega[a];
     cross(b->omega, Iw, wxIw);
     for (int a = 0; a < 3; ++a)
-        b->omega[a] += 0.5 * (b->torque_body[a] - wxIw[a]) / b->inertia[a];
+        b->omega[a] += 0.5 * h * (b->torque_body[a] - wxIw[a]) / b->inertia[a];
 }
 
 /* step 3: fluid velocity of a node from the current pre-collision populations             */
@@ -431,13 +443,16 @@ static void node_velocity(const orc_sim* s, int64_t x, double u[3])
     for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * s->p.g_ext[a]) / rho;
 }
 
-/* steps 2-7 for one body: returns force (lab) and torque (lab) sums                        */
-static void couple_body(orc_sim* s, orc_body* b, double Fsum[3], double Tsum[3])
+/* steps 2-7 for one body in MD step k (length h) of the fluid step: returns the coupling
+ * force (lab) and torque (lab) sums                                                         */
+static void couple_body(orc_sim* s, orc_body* b, int k_md, double h, double Fsum[3],
+                        double Tsum[3])
 {
     double R[3][3];
     quat_matrix(b->quat, R);
     for (int a = 0; a < 3; ++a) Fsum[a] = Tsum[a] = 0.0;
-    const double amp = sqrt(2.0 * s->p.kT * b->gamma) * sqrt(12.0);
+    /* a force held over h carries the momentum variance 2 kT gamma h */
+    const double amp = sqrt(2.0 * s->p.kT * b->gamma / h) * sqrt(12.0);
     for (int k = 0; k < b->n_beads; ++k) {
         const double* off = b->offsets + 3 * k;
         double d[3], r[3], v[3], wxb[3], rw[3];
@@ -463,15 +478,16 @@ static void couple_body(orc_sim* s, orc_body* b, double Fsum[3], double Tsum[3])
         double F[3];
         uint32_t words[4] = {0, 0, 0, 0};
         if (s->p.kT > 0.0)
-            draw(s, s->step, (uint32_t)(b->first_bead + k), 1u, 0u, words);
+            draw(s, s->step, (uint32_t)(b->first_bead + k), 1u, (uint32_t)k_md, words);
         for (int a = 0; a < 3; ++a) {
             F[a] = -b->gamma * (v[a] - uk[a]);
             if (s->p.kT > 0.0) F[a] += amp * orc_uniform16(half_of(words, a));
         }
-        /* the fluid receives the opposite force, on the same nodes with the same weights */
+        /* the fluid receives the opposite momentum h F, on the same nodes with the same
+         * weights (a force density over the unit fluid step)                               */
         for (int c = 0; c < 8; ++c) {
             if (s->mask[idx[c]]) continue;
-            for (int a = 0; a < 3; ++a) s->g[3 * idx[c] + a] -= w[c] * F[a];
+            for (int a = 0; a < 3; ++a) s->g[3 * idx[c] + a] -= w[c] * (h * F[a]);
         }
         double dxF[3];
         cross(d, F, dxF);
@@ -481,6 +497,138 @@ static void couple_body(orc_sim* s, orc_body* b, double Fsum[3], double Tsum[3])
             Tsum[a] += dxF[a];
         }
     }
+}
+
+/* ---- WCA excluded volume (Sec. 2.1 inner layer, Sec. 2.3 pore beads) ---- */
+
+/* separation a - b with each component taken to its nearest periodic image               */
+static void min_image(const orc_sim* s, const double a[3], const double b[3], double d[3])
+{
+    const double L[3] = {(double)s->nx, (double)s->ny, (double)s->nz};
+    for (int k = 0; k < 3; ++k) {
+        d[k] = a[k] - b[k];
+        d[k] -= L[k] * round(d[k] / L[k]);
+    }
+}
+
+/* WCA pair at separation d (first site minus second) with sigma = r_a + r_b: adds the
+ * force on the first site to F and returns the pair energy (0 beyond 2^(1/6) sigma).      */
+static double wca_pair(double eps, double sigma, const double d[3], double F[3])
+{
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const double rc2 = pow(2.0, 1.0 / 3.0) * sigma * sigma;
+    if (!(r2 < rc2)) return 0.0;
+    const double s2 = sigma * sigma / r2, s6 = s2 * s2 * s2, s12 = s6 * s6;
+    /* U = 4 eps (s12 - s6) + eps;  -dU/dr * (d / r) = 24 eps (2 s12 - s6) d / r^2          */
+    const double coef = 24.0 * eps * (2.0 * s12 - s6) / r2;
+    for (int k = 0; k < 3; ++k) F[k] += coef * d[k];
+    return 4.0 * eps * (s12 - s6) + eps;
+}
+
+/* lab positions of a body's excluded-volume sites and their offsets from the centre      */
+static void ev_sites(const orc_body* b, double* x, double* dv)
+{
+    double R[3][3];
+    quat_matrix(b->quat, R);
+    for (int k = 0; k < b->n_ev; ++k) {
+        mat_vec(R, b->ev_offsets + 3 * k, dv + 3 * k);
+        for (int a = 0; a < 3; ++a) x[3 * k + a] = b->pos[a] + dv[3 * k + a];
+    }
+}
+
+/* WCA force and torque (lab, about the centre) on every body, 6 per body, and the total
+ * energy with each pair counted once                                                      */
+static double wca_all(const orc_sim* s, double* out)
+{
+    const double eps = s->p.wca_epsilon;
+    double energy = 0.0;
+    for (int b = 0; b < 6 * s->n_bodies; ++b) out[b] = 0.0;
+    if (!(eps > 0.0)) return 0.0;
+    for (int b = 0; b < s->n_bodies; ++b) {
+        const orc_body* B = &s->bodies[b];
+        if (B->n_ev == 0) continue;
+        double* xb = (double*)malloc(sizeof(double) * 6 * (size_t)B->n_ev);
+        double* db = xb + 3 * B->n_ev;
+        ev_sites(B, xb, db);
+        for (int k = 0; k < B->n_ev; ++k) {
+            double F[3] = {0.0, 0.0, 0.0}, d[3];
+            for (int w = 0; w < s->n_sites; ++w) {
+                min_image(s, xb + 3 * k, s->site_pos + 3 * w, d);
+                energy += wca_pair(eps, B->ev_radius + s->site_radius[w], d, F);
+            }
+            for (int o = 0; o < s->n_bodies; ++o) {
+                const orc_body* O = &s->bodies[o];
+                if (o == b || O->n_ev == 0) continue;
+                double* xo = (double*)malloc(sizeof(double) * 6 * (size_t)O->n_ev);
+                ev_sites(O, xo, xo + 3 * O->n_ev);
+                for (int m = 0; m < O->n_ev; ++m) {
+                    min_image(s, xb + 3 * k, xo + 3 * m, d);
+                    energy += 0.5 * wca_pair(eps, B->ev_radius + O->ev_radius, d, F);
+                }
+                free(xo);
+            }
+            double T[3];
+            cross(db + 3 * k, F, T);
+            for (int a = 0; a < 3; ++a) {
+                out[6 * b + a] += F[a];
+                out[6 * b + 3 + a] += T[a];
+            }
+        }
+        free(xb);
+    }
+    return energy;
+}
+
+int orc_wca_forces(const orc_sim* s, double* out)
+{
+    if (!s || !out) return -1;
+    wca_all(s, out);
+    return 0;
+}
+
+double orc_wca_energy(const orc_sim* s)
+{
+    if (!s) return 0.0;
+    double* tmp = (double*)malloc(sizeof(double) * 6 * (size_t)(s->n_bodies > 0 ? s->n_bodies : 1));
+    const double e = wca_all(s, tmp);
+    free(tmp);
+    return e;
+}
+
+int orc_set_excluded_volume(orc_sim* s, int body, const double* offsets, int n, double radius)
+{
+    if (!s || body < 0 || body >= s->n_bodies || n < 0 || (n > 0 && !offsets) ||
+        !(radius >= 0.0) || s->step != 0)
+        return -1;
+    orc_body* b = &s->bodies[body];
+    free(b->ev_offsets);
+    b->ev_offsets = NULL;
+    b->n_ev = 0;
+    if (n > 0) {
+        b->ev_offsets = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+        if (!b->ev_offsets) return -1;
+        memcpy(b->ev_offsets, offsets, sizeof(double) * 3 * (size_t)n);
+    }
+    b->n_ev = n;
+    b->ev_radius = radius;
+    return 0;
+}
+
+int orc_add_wall_sites(orc_sim* s, const double* pos, int n, double radius)
+{
+    if (!s || n < 0 || (n > 0 && !pos) || !(radius >= 0.0) || s->step != 0) return -1;
+    double* p = (double*)realloc(s->site_pos, sizeof(double) * 3 * (size_t)(s->n_sites + n + 1));
+    if (!p) return -1;
+    s->site_pos = p;
+    double* r = (double*)realloc(s->site_radius, sizeof(double) * (size_t)(s->n_sites + n + 1));
+    if (!r) return -1;
+    s->site_radius = r;
+    for (int k = 0; k < n; ++k) {
+        for (int a = 0; a < 3; ++a) s->site_pos[3 * (s->n_sites + k) + a] = pos[3 * k + a];
+        s->site_radius[s->n_sites + k] = radius;
+    }
+    s->n_sites += n;
+    return 0;
 }
 
 static void collide_all(orc_sim* s)
@@ -517,25 +665,37 @@ static void collide_all(orc_sim* s)
 int orc_step(orc_sim* s, int n_steps)
 {
     if (!s || n_steps < 0) return -1;
+    const int m = s->p.md_substeps > 1 ? s->p.md_substeps : 1;
+    const double h = 1.0 / m;
+    double* wca = (double*)malloc(sizeof(double) * 6 * (size_t)(s->n_bodies > 0 ? s->n_bodies : 1));
+    if (!wca) return -1;
     for (int it = 0; it < n_steps; ++it) {
-        for (int b = 0; b < s->n_bodies; ++b) body_first_half(&s->bodies[b]);
         memset(s->g, 0, (size_t)(3 * s->n) * sizeof(double));
-        for (int b = 0; b < s->n_bodies; ++b) {
-            orc_body* body = &s->bodies[b];
-            double F[3], T[3], R[3][3], Tb[3];
-            couple_body(s, body, F, T);
-            quat_matrix(body->quat, R);
-            mat_t_vec(R, T, Tb);
-            for (int a = 0; a < 3; ++a) {
-                body->force[a] = F[a];
-                body->torque_body[a] = Tb[a];
+        for (int k = 0; k < m; ++k) {
+            for (int b = 0; b < s->n_bodies; ++b) body_first_half(&s->bodies[b], h);
+            wca_all(s, wca);   /* at the poses of this MD step, before any body moves on */
+            for (int b = 0; b < s->n_bodies; ++b) {
+                orc_body* body = &s->bodies[b];
+                double F[3], T[3], R[3][3], Tb[3];
+                couple_body(s, body, k, h, F, T);
+                for (int a = 0; a < 3; ++a) {
+                    F[a] += wca[6 * b + a];
+                    T[a] += wca[6 * b + 3 + a];
+                }
+                quat_matrix(body->quat, R);
+                mat_t_vec(R, T, Tb);
+                for (int a = 0; a < 3; ++a) {
+                    body->force[a] = F[a];
+                    body->torque_body[a] = Tb[a];
+                }
             }
+            for (int b = 0; b < s->n_bodies; ++b) body_second_half(&s->bodies[b], h);
         }
         collide_all(s);
         stream(s);
-        for (int b = 0; b < s->n_bodies; ++b) body_second_half(&s->bodies[b]);
         s->step += 1;
     }
+    free(wca);
     return 0;
 }
 
@@ -624,6 +784,14 @@ const double* orc_box_f(const orc_sim* s) { return s->f; }
 void orc_box_set_f(orc_sim* s, const double* f) { memcpy(s->f, f, sizeof(double) * 19 * (size_t)s->n); }
 const uint8_t* orc_box_mask(const orc_sim* s) { return s->mask; }
 double orc_box_kT(const orc_sim* s) { return s->p.kT; }
+/* 1 if every fluid step is one MD step without excluded volume                            */
+int orc_box_plain_md(const orc_sim* s)
+{
+    if (s->p.md_substeps > 1 || s->n_sites > 0) return 0;
+    for (int b = 0; b < s->n_bodies; ++b)
+        if (s->bodies[b].n_ev > 0) return 0;
+    return 1;
+}
 int orc_box_body(const orc_sim* s, int b, const double** offsets, int* n_beads, double pos[3],
                  double quat[4], double* gamma, int* fixed)
 {

@@ -26,6 +26,9 @@ class OrcParams(ctypes.Structure):
         ("kT", ctypes.c_double),
         ("g_ext", ctypes.c_double * 3),
         ("seed", ctypes.c_uint64),
+        ("md_substeps", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("wca_epsilon", ctypes.c_double),
     ]
 
 
@@ -69,6 +72,15 @@ def lib():
         L.orc_add_body.restype = ctypes.c_int
         L.orc_add_body.argtypes = [ctypes.c_void_p, _D, ctypes.c_int, ctypes.c_double, _D, _D,
                                    _D, _D, _D, ctypes.c_double, ctypes.c_int]
+        L.orc_set_excluded_volume.restype = ctypes.c_int
+        L.orc_set_excluded_volume.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, ctypes.c_int,
+                                              ctypes.c_double]
+        L.orc_add_wall_sites.restype = ctypes.c_int
+        L.orc_add_wall_sites.argtypes = [ctypes.c_void_p, _D, ctypes.c_int, ctypes.c_double]
+        L.orc_wca_forces.restype = ctypes.c_int
+        L.orc_wca_forces.argtypes = [ctypes.c_void_p, _D]
+        L.orc_wca_energy.restype = ctypes.c_double
+        L.orc_wca_energy.argtypes = [ctypes.c_void_p]
         L.orc_step.restype = ctypes.c_int
         L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_step_count.restype = ctypes.c_int64
@@ -106,7 +118,8 @@ def _vec(x, n):
 
 
 def make_params(rho0=1.0, u0=(0.0, 0.0, 0.0), tau_shear=1.0, tau_bulk=None, tau_odd=1.0,
-                tau_even=1.0, kT=0.0, g_ext=(0.0, 0.0, 0.0), seed=0):
+                tau_even=1.0, kT=0.0, g_ext=(0.0, 0.0, 0.0), seed=0, md_substeps=0,
+                wca_epsilon=0.0):
     p = OrcParams()
     p.rho0 = rho0
     p.u0[:] = list(u0)
@@ -117,6 +130,8 @@ def make_params(rho0=1.0, u0=(0.0, 0.0, 0.0), tau_shear=1.0, tau_bulk=None, tau_
     p.kT = kT
     p.g_ext[:] = list(g_ext)
     p.seed = seed
+    p.md_substeps = md_substeps
+    p.wca_epsilon = wca_epsilon
     return p
 
 
@@ -243,6 +258,26 @@ class OracleSim:
         self.beads_per_body.append(off.shape[0])
         return bid
 
+    def set_excluded_volume(self, body, offsets, radius):
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.float64).reshape(-1, 3))
+        if lib().orc_set_excluded_volume(self._h, int(body), _dp(off), off.shape[0],
+                                         float(radius)) != 0:
+            raise RuntimeError("orc_set_excluded_volume failed")
+
+    def add_wall_sites(self, positions, radius):
+        pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 3))
+        if lib().orc_add_wall_sites(self._h, _dp(pos), pos.shape[0], float(radius)) != 0:
+            raise RuntimeError("orc_add_wall_sites failed")
+
+    def wca_forces(self):
+        """(n_bodies, 6): WCA force and torque (lab, about the centre) at the current poses."""
+        out = np.zeros(6 * max(self.n_bodies, 1))
+        lib().orc_wca_forces(self._h, _dp(out))
+        return out[:6 * self.n_bodies].reshape(-1, 6)
+
+    def wca_energy(self):
+        return lib().orc_wca_energy(self._h)
+
     def step(self, n=1):
         if lib().orc_step(self._h, int(n)) != 0:
             raise RuntimeError("orc_step failed")
@@ -292,7 +327,8 @@ class OracleSim:
         rc = lib().orc_adjoint(self._h, ctypes.byref(self.params), int(n_steps), self.n_bodies,
                                _dp(a), _dp(J), _dp(dg), _dp(do))
         if rc != 0:
-            raise RuntimeError("orc_adjoint: needs kT = 0 and fixed bodies")
+            raise RuntimeError("orc_adjoint: needs kT = 0, fixed bodies, one MD step per fluid "
+                               "step and no excluded-volume sites")
         return float(J[0]), dg, do.reshape(-1, 3)
 
     def bead_forces(self, b):

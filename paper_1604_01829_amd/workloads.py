@@ -303,3 +303,63 @@ def stokes_flow_workload(L=STOKES_BOX_PAPER, radius=5.25, U=STOKES_U_PAPER,
                                       tau_bulk=tau_shear),
                 replicas=[dict(shape=(L, L, L), seed=PHILOX_SEED_BASE + 60 + seed, mask=mask,
                                bodies=bodies, walls={1: (0.0, 0.0, U)})])
+
+
+# ------------------------------------------------------------------ excluded volume
+
+# Sec. 2.1 and 2.3: the colloid's inner (excluded-volume) layer sits 0.5 inside the outer
+# hydrodynamic shell with Lennard-Jones radius 0.5; pore beads of radius 6.25 are spaced 5
+# apart around the pore; sigma_WCA = r_r + r_p and eps = kT.
+INNER_LAYER_DEPTH = 0.5
+INNER_LAYER_RADIUS = 0.5
+PORE_SITE_RADIUS = 6.25
+PORE_SITE_SPACING = 5.0
+
+
+def inner_layer_sphere(radius, per_area=2.2):
+    """Excluded-volume sites of a spherical raspberry: a shell INNER_LAYER_DEPTH inside the
+    outer radius at the outer shell's areal density (no centre site)."""
+    r = radius - INNER_LAYER_DEPTH
+    return sphere_beads(r, max(4, sphere_bead_count(r, per_area)), centre_bead=False)
+
+
+def pore_wall_sites(nx, ny, nz, pore_radius, site_radius=PORE_SITE_RADIUS,
+                    spacing=PORE_SITE_SPACING):
+    """Rings of pore beads around the z axis through the middle of the x-y cross-section,
+    centres one site radius outside the pore wall, about `spacing` apart along each ring and
+    between rings (the ring count divides nz, so the lattice is periodic along z).  The
+    rings must fit in the box with room for the interaction range."""
+    ring = pore_radius + site_radius
+    reach = ring + 2.0 ** (1.0 / 6.0) * (site_radius + INNER_LAYER_RADIUS)
+    if 2.0 * reach > min(nx, ny):
+        raise ValueError("the pore beads and their range do not fit in the box")
+    n_rings = max(1, int(round(nz / spacing)))
+    n_ang = max(3, int(round(2.0 * math.pi * ring / spacing)))
+    th = 2.0 * math.pi * np.arange(n_ang) / n_ang
+    pts = []
+    for j in range(n_rings):
+        z = (j + 0.5) * nz / n_rings
+        pts.append(np.stack([nx / 2.0 + ring * np.cos(th), ny / 2.0 + ring * np.sin(th),
+                             np.full(n_ang, z)], axis=1))
+    return np.concatenate(pts, axis=0)
+
+
+def confined_md_workload(scale=1.0, substeps=2, eps=None):
+    """Workload 2 with the paper's integration scheme: `substeps` MD steps per fluid step,
+    inner excluded-volume layers on every sphere, pore beads around the pore, and WCA
+    repulsion of energy eps (default kT) between inner layers and pore beads and between
+    the inner layers of different spheres.  Records carry params md_substeps/wca_epsilon,
+    per replica wall_sites=(positions, radius) and per body ev=(offsets, radius)."""
+    wl = workload(2, scale=scale)
+    p = wl["params"]
+    p["md_substeps"] = int(substeps)
+    p["wca_epsilon"] = p["kT"] if eps is None else float(eps)
+    rep = wl["replicas"][0]
+    nx, ny, nz = rep["shape"]
+    rep["wall_sites"] = (pore_wall_sites(nx, ny, nz, 40.0 * scale), PORE_SITE_RADIUS)
+    for b in rep["bodies"]:
+        R = float(np.linalg.norm(b["offsets"], axis=1).max())
+        b["ev"] = (inner_layer_sphere(R), INNER_LAYER_RADIUS)
+    wl["name"] = (f"{wl['name']}; {substeps} MD steps per fluid step, WCA inner layers and "
+                  "pore beads")
+    return wl
