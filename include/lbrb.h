@@ -71,6 +71,13 @@ typedef struct {
     int32_t max_wall_links;   /* capacity for moving walls (lb_set_wall_velocity): links
                                  between a fluid node and a moving boundary node, over all
                                  replicas (0 = walls at rest only)                           */
+    int32_t md_substeps;      /* MD steps per fluid step (0 or 1: one; the paper uses 2,
+                                 Sec. 2.3): each is a velocity-Verlet step of the bodies of
+                                 length 1/md_substeps on the frozen fluid, with bead noise of
+                                 its own; the fluid receives the MD steps' mean coupling force */
+    double wca_epsilon;       /* WCA energy of the excluded volume (Sec. 2.3: kT); 0 = none  */
+    int32_t max_ev_sites;     /* capacity: excluded-volume sites over all bodies             */
+    int32_t max_wall_sites;   /* capacity: static WCA sites (pore beads) over all replicas   */
 } lb_params;
 
 /* Device bytes needed for these parameters and boxes (upper bound, all nodes fluid).
@@ -150,6 +157,26 @@ typedef struct {
 int lb_observables(lb_ctx* ctx, int32_t replica, lb_totals* out, rb_state* bodies,
                    void* dev_rho_u);
 
+/* Excluded volume of a body (the inner layer of a two-layer raspberry, Sec. 2.1): n_sites
+ * body-frame offsets (n_sites*3, host) of sites that take no part in the fluid coupling and
+ * repel the static sites of the replica and the sites of its other bodies with the WCA pair
+ * potential 4 eps ((s/r)^12 - (s/r)^6) + eps below r = 2^(1/6) s, s = sum of the two radii,
+ * eps = wca_epsilon (Sec. 2.3), minimum image in every direction; their forces and torques
+ * join the body's.  radius: the sites' Lennard-Jones radius (Sec. 2.1: 0.5).  Replaces
+ * earlier sites of the body; n_sites = 0 removes them.  Only before the first step
+ * (LB_ERR_STATE); LB_ERR_ARG for bad ids or values, LB_ERR_CAPACITY beyond max_ev_sites.
+ * The first lb_rb_step returns LB_ERR_ARG if a box side is shorter than twice the largest
+ * interaction range of its replica.                                                        */
+int rb_set_excluded_volume(lb_ctx* ctx, int32_t replica, int32_t body_id,
+                           const double* offsets_body, int32_t n_sites, double radius);
+
+/* Static WCA sites of one replica (the pore beads of Sec. 2.3): n lab positions (n*3, host)
+ * with one Lennard-Jones radius (the paper: 6.25), appended to the replica's sites.  Only
+ * before the first step (LB_ERR_STATE); LB_ERR_ARG for bad values, LB_ERR_CAPACITY beyond
+ * max_wall_sites.                                                                          */
+int lb_add_wall_sites(lb_ctx* ctx, int32_t replica, const double* positions, int32_t n,
+                      double radius);
+
 /* Number of bodies in a replica, and the per-bead forces (lab frame, FP64, n_beads*3, in
  * the order the beads were given) of the last step of one body, copied to host memory.   */
 int lb_body_count(const lb_ctx* ctx, int32_t replica);
@@ -198,7 +225,8 @@ int lb_kernel_times(lb_ctx* ctx, double* node_ms, int64_t* node_launches, double
  *   dJ_dgamma   [n_bodies];
  *   dJ_doffsets [n_beads][3], body frame.
  * Synchronises the stream.  Errors: LB_ERR_ARG (window, workspace, missing arrays),
- * LB_ERR_STATE (kT > 0 or a free body).  The adjoint runs in the context precision; its
+ * LB_ERR_STATE (kT > 0, a free body, more than one MD step per fluid step, or excluded-
+ * volume or static sites).  The adjoint runs in the context precision; its
  * atomic accumulation of sampled-velocity adjoints is not order-deterministic.          */
 size_t lb_adjoint_workspace_bytes(const lb_ctx* ctx, int32_t n_steps, int32_t checkpoint_every);
 int lb_rb_adjoint(lb_ctx* ctx, int32_t n_steps, int32_t checkpoint_every, void* dev_ws,

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <string>
@@ -34,11 +35,16 @@ struct Plan {
     int64_t tiles_cap = 0;    // sum of ceil(nodes / 256)
     int64_t bead_cap = 0, body_cap = 0;
     int64_t link_cap = 0;     // moving-wall links
+    int64_t ev_cap = 0, site_cap = 0, cells_cap = 0;   // excluded volume
     int gforce_words = 3;     // fixed-point words per node: 3 axes x (1 in FP32, 2 in FP64)
     size_t off_hdr, off_reps, off_rows, off_rowinfo, off_tiles_d, off_tiles_m, off_fa, off_fb,
         off_gforce, off_flags, off_bodies, off_bead_off, off_bead_rec, off_bead_force,
-        off_bead_torque, off_partials, off_links, total;
+        off_bead_torque, off_partials, off_links, off_ev, off_sites, off_wrep, off_rep_bodies,
+        off_cell_start, off_cell_near, off_wca_ft, total;
 };
+
+constexpr int kMaxCellsPerAxis = 32;   // WCA cell grid: cells per axis at most
+int cells_per_axis_cap(int n) { return std::min(n, kMaxCellsPerAxis); }
 
 bool valid_params(const lb_params* p)
 {
@@ -52,6 +58,9 @@ bool valid_params(const lb_params* p)
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(p->u0[a]) || !std::isfinite(p->g_ext[a])) return false;
     if (p->max_bodies < 0 || p->max_beads < 0 || p->max_wall_links < 0) return false;
+    if (p->md_substeps < 0 || p->md_substeps > 64) return false;
+    if (!(p->wca_epsilon >= 0) || !std::isfinite(p->wca_epsilon)) return false;
+    if (p->max_ev_sites < 0 || p->max_wall_sites < 0) return false;
     return true;
 }
 
@@ -68,11 +77,16 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
         pl.N += pad_nodes(nodes);
         pl.rows_cap += (int64_t)R.ny * R.nz;
         pl.tiles_cap += pad_nodes(nodes) / kNodeBlock;
+        if (p->max_wall_sites > 0)
+            pl.cells_cap += (int64_t)cells_per_axis_cap(R.nx) * cells_per_axis_cap(R.ny) *
+                            cells_per_axis_cap(R.nz) + 1;
     }
     const size_t real = p->precision == LB_PRECISION_F32 ? sizeof(float) : sizeof(double);
     pl.body_cap = p->max_bodies;
     pl.bead_cap = p->max_beads;
     pl.link_cap = p->max_wall_links;
+    pl.ev_cap = p->max_ev_sites;
+    pl.site_cap = p->max_wall_sites;
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes, kAlign); return at; };
     pl.off_hdr = take(sizeof(DeviceHeader));
@@ -93,6 +107,13 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
     pl.off_bead_torque = take(sizeof(double) * 3 * std::max<int64_t>(pl.bead_cap, 1));
     pl.off_partials = take(sizeof(double) * 5 * pl.tiles_cap);
     pl.off_links = take(sizeof(WallLink) * std::max<int64_t>(pl.link_cap, 1));
+    pl.off_ev = take(sizeof(EvSite) * std::max<int64_t>(pl.ev_cap, 1));
+    pl.off_sites = take(sizeof(WallSite) * std::max<int64_t>(pl.site_cap, 1));
+    pl.off_wrep = take(sizeof(WcaRep) * n);
+    pl.off_rep_bodies = take(sizeof(int32_t) * std::max<int64_t>(pl.body_cap, 1));
+    pl.off_cell_start = take(sizeof(int32_t) * std::max<int64_t>(pl.cells_cap, 1));
+    pl.off_cell_near = take(std::max<int64_t>(pl.cells_cap, 1));
+    pl.off_wca_ft = take(sizeof(double) * 6 * std::max<int64_t>(pl.body_cap, 1));
     pl.total = o;
     return true;
 }
@@ -105,6 +126,12 @@ struct ReplicaHost {
     std::vector<double> uwall;      // 3 per wall id 0..255 once a wall velocity was set
     std::vector<WallLink> links;    // moving-wall links of this replica
     int64_t link0 = 0;              // their first entry in the device list
+    std::vector<WallSite> sites;    // static WCA sites
+};
+
+struct EvHost {
+    std::vector<double> off;        // body-frame offsets of the excluded-volume sites
+    double radius = 0.0;
 };
 
 struct EventPair { hipEvent_t a, b; };
@@ -135,6 +162,16 @@ struct lb_ctx {
     double* d_partials = nullptr;
     WallLink* d_links = nullptr;
     int64_t n_links = 0;
+    EvSite* d_ev = nullptr;
+    WallSite* d_sites = nullptr;
+    WcaRep* d_wrep = nullptr;
+    int32_t* d_rep_bodies = nullptr;
+    int32_t* d_cell_start = nullptr;
+    uint8_t* d_cell_near = nullptr;
+    double* d_wca_ft = nullptr;
+    std::vector<EvHost> ev;         // per body
+    int64_t n_ev = 0, n_sites = 0;
+    bool wca_dirty = false;         // site tables to rebuild before the next step
     // host mirrors
     std::vector<ReplicaDesc> reps;
     std::vector<RowDesc> rows;
@@ -230,6 +267,8 @@ StepArgs<Real> step_args(const lb_ctx* c, int group, int src_buf)
     return step_args_on<Real>(c, group, c->f[src_buf], c->f[src_buf ^ 1]);
 }
 
+int md_steps(const lb_ctx* c) { return std::max(1, (int)c->p.md_substeps); }
+
 CoupleArgs couple_args(const lb_ctx* c)
 {
     CoupleArgs ca{};
@@ -237,7 +276,9 @@ CoupleArgs couple_args(const lb_ctx* c)
     ca.bead_force = c->d_bead_force;
     ca.bead_torque = c->d_bead_torque;
     ca.n_beads = c->n_beads;
+    ca.md_step = 0;
     ca.kT = c->p.kT;
+    ca.spread_h = 1.0 / md_steps(c);
     ca.hdr = c->hdr;
     return ca;
 }
@@ -251,6 +292,15 @@ BodyArgs body_args(const lb_ctx* c)
     ba.bead_force = c->d_bead_force;
     ba.bead_torque = c->d_bead_torque;
     ba.n_bodies = c->n_bodies;
+    ba.substeps = md_steps(c);
+    ba.wca_eps = c->p.wca_epsilon;
+    ba.wca_ft = (c->n_ev > 0 && c->p.wca_epsilon > 0.0) ? c->d_wca_ft : nullptr;
+    ba.ev = c->d_ev;
+    ba.wrep = c->d_wrep;
+    ba.rep_bodies = c->d_rep_bodies;
+    ba.cell_start = c->d_cell_start;
+    ba.cell_near = c->d_cell_near;
+    ba.sites = c->d_sites;
     return ba;
 }
 
@@ -283,13 +333,24 @@ hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* st
     for (auto& a : ag) { a.step_ptr = step_ptr; a.step_arg = step_arg; }
     // timed launches carry their own start/stop events (recorded by the dispatch)
     const bool timed = c->timing && !capture;
-    if (c->n_beads > 0) {
+    const int m = md_steps(c);
+    for (int k = 0; k < m && c->n_beads > 0; ++k) {
+        // MD step k: coupling (its own noise block, the fluid gets 1/m of the force); every
+        // MD step but the last also finishes the bodies here
         EventPair e{};
         if (timed) e = get_pair(c);
-        launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], couple_args(c), s,
-                            LaunchEvents{e.a, e.b});
+        CoupleArgs ca = couple_args(c);
+        ca.md_step = (uint32_t)k;
+        launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], ca, s, LaunchEvents{e.a, e.b});
         note(hipGetLastError());
         if (timed && e.a && e.b) c->ev_couple_t.push_back(e);
+        const BodyArgs ba = body_args(c);
+        launch_wca(ba, step_ptr, step_arg, k, s);
+        note(hipGetLastError());
+        if (k + 1 < m) {
+            launch_body_substep(ba, step_ptr, step_arg, k, s);
+            note(hipGetLastError());
+        }
     }
     bool finished = c->n_bodies == 0;
     for (int g = 0; g < 2; ++g) {
@@ -547,6 +608,145 @@ bool check_replica(lb_ctx* c, int32_t r)
     return true;
 }
 
+// ------------------------------------------------------------------ excluded volume
+
+// WCA tables of every replica from the host records: the bodies of each replica, the
+// excluded-volume sites of every body (packed in body order), and the static sites sorted
+// into a per-replica cell grid whose cells are at least one interaction range wide (with a
+// margin, so a site within range of a point always lies in the point's cell or a
+// neighbouring one) and a flag per cell telling whether any site lies in its neighbourhood.
+int build_wca(lb_ctx* c)
+{
+    const double cut = std::pow(2.0, 1.0 / 6.0);
+    // bodies: excluded-volume ranges
+    std::vector<EvSite> ev;
+    for (int32_t b = 0; b < c->n_bodies; ++b) {
+        Body& B = c->bodies0[b];
+        const EvHost& E = c->ev[b];
+        B.first_ev = (int32_t)ev.size();
+        B.n_ev = (int32_t)(E.off.size() / 3);
+        B.ev_radius = E.radius;
+        B.ev_reach = 0.0;
+        for (int32_t k = 0; k < B.n_ev; ++k) {
+            EvSite e{};
+            for (int a = 0; a < 3; ++a) e.off[a] = E.off[3 * (size_t)k + a];
+            B.ev_reach = std::max(B.ev_reach, std::sqrt(e.off[0] * e.off[0] + e.off[1] * e.off[1] +
+                                                        e.off[2] * e.off[2]));
+            ev.push_back(e);
+        }
+    }
+    // replicas: body lists and site grids
+    std::vector<WcaRep> wr(c->n_rep);
+    std::vector<int32_t> rep_bodies;
+    std::vector<WallSite> sites;
+    std::vector<int32_t> cstart;
+    std::vector<uint8_t> cnear;
+    for (int r = 0; r < c->n_rep; ++r) {
+        const ReplicaDesc& R = c->reps[r];
+        const ReplicaHost& H = c->rh[r];
+        WcaRep& W = wr[r];
+        W = WcaRep{};
+        W.first_body = (int32_t)rep_bodies.size();
+        W.n_bodies = (int32_t)H.bodies.size();
+        double ev_r = -1.0;
+        for (int32_t b : H.bodies) {
+            rep_bodies.push_back(b);
+            if (c->bodies0[b].n_ev > 0) ev_r = std::max(ev_r, c->bodies0[b].ev_radius);
+        }
+        const int dims[3] = {R.nx, R.ny, R.nz};
+        // the largest range of a pair in this replica: body-body and body-site
+        double range = ev_r >= 0.0 ? cut * 2.0 * ev_r : 0.0;
+        double site_r = -1.0;
+        for (const WallSite& w : H.sites) site_r = std::max(site_r, w.radius);
+        if (ev_r >= 0.0 && site_r >= 0.0) range = std::max(range, cut * (ev_r + site_r));
+        for (int a = 0; a < 3; ++a)
+            if (ev_r >= 0.0 && 2.0 * range > dims[a])
+                return fail(c, LB_ERR_ARG, "a box side is shorter than twice the WCA range");
+        if (H.sites.empty() || ev_r < 0.0) continue;   // no grid needed
+        int nc[3];
+        for (int a = 0; a < 3; ++a) {
+            const int fit = (int)std::floor(dims[a] / (range * (1.0 + 1e-6)));
+            nc[a] = std::max(1, std::min(fit, cells_per_axis_cap(dims[a])));
+            W.cw[a] = (double)dims[a] / nc[a];
+        }
+        W.cx = nc[0]; W.cy = nc[1]; W.cz = nc[2];
+        W.cell0 = (int32_t)cstart.size();
+        const int ncell = nc[0] * nc[1] * nc[2];
+        // the cell of a site, computed as the kernel computes the cell of a point
+        auto cell_of = [&](const double p[3]) {
+            int ci[3];
+            for (int a = 0; a < 3; ++a) {
+                const double L = dims[a];
+                const double xw = p[a] - L * std::floor(p[a] / L);
+                int q = (int)(xw / W.cw[a]);
+                ci[a] = q < 0 ? 0 : (q >= nc[a] ? nc[a] - 1 : q);
+            }
+            return ci[0] + nc[0] * (ci[1] + nc[1] * ci[2]);
+        };
+        std::vector<std::vector<WallSite>> bins(ncell);
+        for (const WallSite& w : H.sites) bins[cell_of(w.p)].push_back(w);
+        std::vector<uint8_t> occ(ncell, 0);
+        for (int k = 0; k < ncell; ++k) {
+            cstart.push_back((int32_t)sites.size());
+            occ[k] = bins[k].empty() ? 0 : 1;
+            sites.insert(sites.end(), bins[k].begin(), bins[k].end());
+        }
+        cstart.push_back((int32_t)sites.size());
+        // neighbourhood flags (same neighbour rule as the kernel)
+        auto span = [](int ci, int n, int& first, int& count) {
+            if (n >= 3) { first = ci == 0 ? n - 1 : ci - 1; count = 3; }
+            else { first = 0; count = n; }
+        };
+        for (int z = 0; z < nc[2]; ++z)
+            for (int y = 0; y < nc[1]; ++y)
+                for (int x = 0; x < nc[0]; ++x) {
+                    int f0, n0, f1, n1, f2, n2;
+                    span(x, nc[0], f0, n0);
+                    span(y, nc[1], f1, n1);
+                    span(z, nc[2], f2, n2);
+                    uint8_t any = 0;
+                    for (int iz = 0; iz < n2; ++iz)
+                        for (int iy = 0; iy < n1; ++iy)
+                            for (int ix = 0; ix < n0; ++ix)
+                                any |= occ[(f0 + ix) % nc[0] +
+                                           nc[0] * ((f1 + iy) % nc[1] + nc[1] * ((f2 + iz) % nc[2]))];
+                    cnear.push_back(any);
+                }
+        cnear.push_back(0);   // keeps cell_near aligned with cell_start (one extra entry)
+    }
+    if ((int64_t)cstart.size() > std::max<int64_t>(c->plan.cells_cap, 0))
+        return fail(c, LB_ERR_CAPACITY, "WCA cell grid exceeds its workspace");
+    c->n_ev = (int64_t)ev.size();
+    if (!ev.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_ev, ev.data(), sizeof(EvSite) * ev.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+    if (!sites.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_sites, sites.data(), sizeof(WallSite) * sites.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+    if (!cstart.empty()) {
+        HIP_TRY(c, hipMemcpyAsync(c->d_cell_start, cstart.data(), sizeof(int32_t) * cstart.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->d_cell_near, cnear.data(), cnear.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+    }
+    if (!rep_bodies.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_rep_bodies, rep_bodies.data(),
+                                  sizeof(int32_t) * rep_bodies.size(), hipMemcpyHostToDevice,
+                                  c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_wrep, wr.data(), sizeof(WcaRep) * wr.size(),
+                              hipMemcpyHostToDevice, c->stream));
+    // the bodies' site ranges (set before the first step, so the host records are current
+    // apart from what a loaded state changed: copy only these fields)
+    const size_t f0 = offsetof(Body, ev_radius), f1 = offsetof(Body, n_ev) + sizeof(int32_t);
+    for (int32_t b = 0; b < c->n_bodies; ++b)
+        HIP_TRY(c, hipMemcpyAsync((char*)(c->d_bodies + b) + f0, (const char*)&c->bodies0[b] + f0,
+                                  f1 - f0, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->wca_dirty = false;
+    destroy_graphs(c);
+    return LB_OK;
+}
+
 // ------------------------------------------------------------------ reverse pass
 // Layout of the caller's reverse-pass workspace: checkpoints of the post-collision state
 // every K steps, K-1 slots for the states recomputed inside one segment, two adjoint
@@ -724,6 +924,13 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     c->d_bead_torque = (double*)(c->ws + pl.off_bead_torque);
     c->d_partials = (double*)(c->ws + pl.off_partials);
     c->d_links = (WallLink*)(c->ws + pl.off_links);
+    c->d_ev = (EvSite*)(c->ws + pl.off_ev);
+    c->d_sites = (WallSite*)(c->ws + pl.off_sites);
+    c->d_wrep = (WcaRep*)(c->ws + pl.off_wrep);
+    c->d_rep_bodies = (int32_t*)(c->ws + pl.off_rep_bodies);
+    c->d_cell_start = (int32_t*)(c->ws + pl.off_cell_start);
+    c->d_cell_near = (uint8_t*)(c->ws + pl.off_cell_near);
+    c->d_wca_ft = (double*)(c->ws + pl.off_wca_ft);
 
     c->reps.resize(n_replicas);
     c->rh.resize(n_replicas);
@@ -894,7 +1101,13 @@ int rb_add_raspberry(lb_ctx* c, int32_t replica, const double* offs, int32_t n_b
     for (int a = 0; a < 4; ++a) B.quat[a] = quat[a] / qn;
     B.mass = mass;
     B.gamma = gamma;
-    B.noise_amp = std::sqrt(2.0 * c->p.kT * gamma) * std::sqrt(12.0);
+    B.dt = 1.0 / md_steps(c);
+    // a force held over an MD step dt carries the momentum variance 2 kT gamma dt
+    B.noise_amp = std::sqrt(2.0 * c->p.kT * gamma / B.dt) * std::sqrt(12.0);
+    B.first_ev = 0;
+    B.n_ev = 0;
+    B.ev_radius = 0.0;
+    B.ev_reach = 0.0;
     B.fixed = fixed ? 1 : 0;
     B.replica = replica;
     B.first_bead = c->n_beads;
@@ -924,8 +1137,61 @@ int rb_add_raspberry(lb_ctx* c, int32_t replica, const double* offs, int32_t n_b
     c->n_bodies += 1;
     c->n_beads += n_beads;
     c->bead_user.insert(c->bead_user.end(), order.begin(), order.end());
+    c->ev.push_back(EvHost{});
+    c->wca_dirty = true;
     c->pose_stale = true;
     destroy_graphs(c);
+    return LB_OK;
+}
+
+int rb_set_excluded_volume(lb_ctx* c, int32_t replica, int32_t body_id, const double* offs,
+                           int32_t n_sites, double radius)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!check_replica(c, replica)) return LB_ERR_ARG;
+    const ReplicaHost& H = c->rh[replica];
+    if (body_id < 0 || body_id >= (int32_t)H.bodies.size())
+        return fail(c, LB_ERR_ARG, "bad body id");
+    if (n_sites < 0 || (n_sites > 0 && !offs) || !(radius >= 0.0) || !std::isfinite(radius))
+        return fail(c, LB_ERR_ARG, "bad excluded-volume sites");
+    for (int64_t k = 0; k < 3 * (int64_t)n_sites; ++k)
+        if (!std::isfinite(offs[k])) return fail(c, LB_ERR_ARG, "non-finite site offset");
+    if (c->step != 0)
+        return fail(c, LB_ERR_STATE, "excluded volume can only be set before the first step");
+    const int32_t g = H.bodies[body_id];
+    int64_t total = 0;
+    for (int32_t b = 0; b < c->n_bodies; ++b)
+        if (b != g) total += (int64_t)(c->ev[b].off.size() / 3);
+    if (total + n_sites > c->plan.ev_cap)
+        return fail(c, LB_ERR_CAPACITY, "excluded-volume sites exceed max_ev_sites");
+    c->ev[g].off.assign(offs, offs + 3 * (size_t)n_sites);
+    c->ev[g].radius = radius;
+    c->wca_dirty = true;
+    return LB_OK;
+}
+
+int lb_add_wall_sites(lb_ctx* c, int32_t replica, const double* pos, int32_t n, double radius)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!check_replica(c, replica)) return LB_ERR_ARG;
+    if (n < 0 || (n > 0 && !pos) || !(radius >= 0.0) || !std::isfinite(radius))
+        return fail(c, LB_ERR_ARG, "bad wall sites");
+    for (int64_t k = 0; k < 3 * (int64_t)n; ++k)
+        if (!std::isfinite(pos[k])) return fail(c, LB_ERR_ARG, "non-finite site position");
+    if (c->step != 0)
+        return fail(c, LB_ERR_STATE, "wall sites can only be added before the first step");
+    int64_t total = 0;
+    for (int r = 0; r < c->n_rep; ++r) total += (int64_t)c->rh[r].sites.size();
+    if (total + n > c->plan.site_cap)
+        return fail(c, LB_ERR_CAPACITY, "wall sites exceed max_wall_sites");
+    for (int32_t k = 0; k < n; ++k) {
+        WallSite w{};
+        for (int a = 0; a < 3; ++a) w.p[a] = pos[3 * (size_t)k + a];
+        w.radius = radius;
+        c->rh[replica].sites.push_back(w);
+    }
+    c->n_sites = total + n;
+    c->wca_dirty = true;
     return LB_OK;
 }
 
@@ -934,8 +1200,12 @@ int lb_rb_step(lb_ctx* c, int32_t n_steps)
     if (!c) return LB_ERR_ARG;
     if (n_steps < 0) return fail(c, LB_ERR_ARG, "negative step count");
     if (n_steps == 0) return LB_OK;
+    if (c->wca_dirty) {
+        const int rc = build_wca(c);
+        if (rc != LB_OK) return rc;
+    }
     if (c->pose_stale) {
-        launch_body_predict(body_args(c), (int)(c->step & 1), c->stream);
+        launch_body_predict(body_args(c), (int)((c->step * md_steps(c)) & 1), c->stream);
         HIP_TRY(c, hipGetLastError());
         c->pose_stale = false;
     }
@@ -1194,6 +1464,11 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     if (!dev_ws || ((uintptr_t)dev_ws % kAlign) != 0 || ws_bytes < ap.total)
         return fail(c, LB_ERR_ARG, "reverse-pass workspace missing, misaligned or too small");
     if (c->p.kT != 0.0) return fail(c, LB_ERR_STATE, "the reverse pass needs kT = 0");
+    bool any_ev = false;
+    for (const EvHost& E : c->ev) any_ev = any_ev || !E.off.empty();
+    if (md_steps(c) > 1 || any_ev || c->n_sites > 0)
+        return fail(c, LB_ERR_STATE,
+                    "the reverse pass needs one MD step per fluid step and no excluded volume");
     for (const Body& B : c->bodies0)
         if (!B.fixed) return fail(c, LB_ERR_STATE, "the reverse pass needs fixed bodies");
     if (c->n_bodies > 0 && (!dJ_dF || !dJ_dgamma || !dJ_doffsets))
@@ -1214,7 +1489,7 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_dg, 0, sizeof(double) * nb, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_J, 0, sizeof(double) * nb, s));
     if (c->pose_stale) {
-        launch_body_predict(body_args(c), (int)(c->step & 1), s);
+        launch_body_predict(body_args(c), (int)((c->step * md_steps(c)) & 1), s);
         HIP_TRY(c, hipGetLastError());
         c->pose_stale = false;
     }

@@ -391,15 +391,20 @@ struct BodyBox {
 
 struct Body {
     double pos[3], quat[4], vel[3], omega[3];
-    double force[3], torque[3];      // last step's sum (lab) and body-frame torque
+    double force[3], torque[3];      // last MD step's sum (lab) and body-frame torque
     double mass, inertia[3], gamma;
-    double noise_amp;                // sqrt(2 kT gamma) sqrt(12): bead noise per uniform variate
+    double noise_amp;                // sqrt(2 kT gamma / dt) sqrt(12): bead noise per uniform
+    double dt;                       // MD step in fluid steps (1 / MD steps per fluid step)
+    double ev_radius;                // Lennard-Jones radius of the excluded-volume sites
+    double ev_reach;                 // largest |offset| of those sites
+    int32_t first_ev, n_ev;          // excluded-volume site range
     int32_t fixed, replica;
     int32_t first_bead, n_beads;     // global bead range
     int32_t first_bead_in_replica;   // index of the first bead within its replica
     int32_t pad;
     BodyBox box;
-    Pose pose[2];                    // the pose used by step n is pose[n & 1]
+    Pose pose[2];                    // the pose used by MD step S (counted over the run) is
+                                     // pose[S & 1]
 };
 
 LBRB_HD void quat_to_matrix(const double q[4], double m[3][3])
@@ -416,32 +421,36 @@ LBRB_HD void quat_to_matrix(const double q[4], double m[3][3])
     m[2][2] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-// half kick of the angular velocity with a body-frame torque: Euler's equations, explicit
-LBRB_HD void half_kick(double omega[3], const double inertia[3], const double torque_b[3])
+// half kick of the angular velocity with a body-frame torque over an MD step dt: Euler's
+// equations, explicit
+LBRB_HD void half_kick(double omega[3], const double inertia[3], const double torque_b[3],
+                       double dt)
 {
     const double Lx = inertia[0] * omega[0], Ly = inertia[1] * omega[1], Lz = inertia[2] * omega[2];
     const double cxw = omega[1] * Lz - omega[2] * Ly;
     const double cyw = omega[2] * Lx - omega[0] * Lz;
     const double czw = omega[0] * Ly - omega[1] * Lx;
-    omega[0] += 0.5 * (torque_b[0] - cxw) / inertia[0];
-    omega[1] += 0.5 * (torque_b[1] - cyw) / inertia[1];
-    omega[2] += 0.5 * (torque_b[2] - czw) / inertia[2];
+    const double hh = 0.5 * dt;
+    omega[0] += hh * (torque_b[0] - cxw) / inertia[0];
+    omega[1] += hh * (torque_b[1] - cyw) / inertia[1];
+    omega[2] += hh * (torque_b[2] - czw) / inertia[2];
 }
 
-// First half of a step for a free body: V += F/(2M), omega half kick, R += V,
-// q <- q (x) (cos(|w|/2), sin(|w|/2) w/|w|), renormalised.  Pure function of b.
+// First half of an MD step dt for a free body: V += dt F/(2M), omega half kick,
+// R += dt V, q <- q (x) (cos(dt|w|/2), sin(dt|w|/2) w/|w|), renormalised.  Pure function of b.
 LBRB_HD void first_half(const Body& b, double pos[3], double quat[4], double vel[3],
                         double omega[3])
 {
     for (int a = 0; a < 3; ++a) { pos[a] = b.pos[a]; vel[a] = b.vel[a]; omega[a] = b.omega[a]; }
     for (int a = 0; a < 4; ++a) quat[a] = b.quat[a];
     if (b.fixed) return;
-    for (int a = 0; a < 3; ++a) vel[a] += 0.5 * b.force[a] / b.mass;
-    half_kick(omega, b.inertia, b.torque);
-    for (int a = 0; a < 3; ++a) pos[a] += vel[a];
+    const double hh = 0.5 * b.dt;
+    for (int a = 0; a < 3; ++a) vel[a] += hh * b.force[a] / b.mass;
+    half_kick(omega, b.inertia, b.torque, b.dt);
+    for (int a = 0; a < 3; ++a) pos[a] += b.dt * vel[a];
     const double wn = sqrt(omega[0] * omega[0] + omega[1] * omega[1] + omega[2] * omega[2]);
     if (wn > 0.0) {
-        const double h = 0.5 * wn, s = sin(h) / wn, c = cos(h);
+        const double h = hh * wn, s = sin(h) / wn, c = cos(h);
         const double p[4] = {c, s * omega[0], s * omega[1], s * omega[2]};
         const double* q = quat;
         double n[4];

@@ -115,9 +115,165 @@ __device__ __forceinline__ void write_bead_records(const Body& B, const Pose& P,
     }
 }
 
+// ------------------------------------------------------------------ excluded volume (WCA)
+
+// separation a - b with each component taken to its nearest periodic image
+__device__ __forceinline__ void min_image(const double a[3], const double b[3],
+                                          const double L[3], double d[3])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        d[k] = a[k] - b[k];
+        d[k] -= L[k] * round(d[k] / L[k]);
+    }
+}
+
+// WCA pair at separation d (first site minus second), sigma = r_a + r_b: adds the force on
+// the first site to F; nothing at or beyond 2^(1/6) sigma
+__device__ __forceinline__ void wca_add(double eps, double sigma, const double d[3], double F[3])
+{
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (!(r2 < 1.2599210498948732 * sigma * sigma)) return;   // 2^(1/3) sigma^2
+    const double s2 = sigma * sigma / r2, s6 = s2 * s2 * s2, s12 = s6 * s6;
+    const double coef = 24.0 * eps * (2.0 * s12 - s6) / r2;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) F[k] += coef * d[k];
+}
+
+// cell range along one axis around cell c: c-1, c, c+1 (periodic), or every cell when the
+// axis has fewer than three
+__device__ __forceinline__ void cell_span(int c, int n, int& first, int& count)
+{
+    if (n >= 3) { first = c == 0 ? n - 1 : c - 1; count = 3; }
+    else { first = 0; count = n; }
+}
+
+__device__ __forceinline__ int cell_of(double x, double L, double w, int n)
+{
+    const double xw = x - L * floor(x / L);
+    int c = (int)(xw / w);
+    return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
+// WCA force and torque (lab, about the centre) on the excluded-volume sites of body B at
+// pose P of the current MD step, from the static sites of its replica and the sites of the
+// replica's other bodies (at their poses of the same MD step), summed into acc[0..5]
+__device__ __forceinline__ void wca_body(const BodyArgs& ba, const Body& B, int b, int parity,
+                                         double acc[6])
+{
+    const Pose& P = B.pose[parity];
+    const WcaRep W = ba.wrep[B.replica];
+    const double L[3] = {(double)B.box.nx, (double)B.box.ny, (double)B.box.nz};
+    const double eps = ba.wca_eps;
+    for (int k = threadIdx.x; k < B.n_ev; k += blockDim.x) {
+        const EvSite e = ba.ev[B.first_ev + k];
+        double d[3], x[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            d[ax] = P.rot[3 * ax] * e.off[0] + P.rot[3 * ax + 1] * e.off[1] +
+                    P.rot[3 * ax + 2] * e.off[2];
+            x[ax] = P.pos[ax] + d[ax];
+        }
+        double F[3] = {0.0, 0.0, 0.0};
+        if (W.cx > 0) {
+            const int c0 = cell_of(x[0], L[0], W.cw[0], W.cx);
+            const int c1 = cell_of(x[1], L[1], W.cw[1], W.cy);
+            const int c2 = cell_of(x[2], L[2], W.cw[2], W.cz);
+            if (ba.cell_near[W.cell0 + c0 + W.cx * (c1 + W.cy * c2)]) {
+                int f0, n0, f1, n1, f2, n2;
+                cell_span(c0, W.cx, f0, n0);
+                cell_span(c1, W.cy, f1, n1);
+                cell_span(c2, W.cz, f2, n2);
+                for (int iz = 0; iz < n2; ++iz) {
+                    const int zc = (f2 + iz) % W.cz;
+                    for (int iy = 0; iy < n1; ++iy) {
+                        const int yc = (f1 + iy) % W.cy;
+                        for (int ix = 0; ix < n0; ++ix) {
+                            const int cell = W.cell0 + (f0 + ix) % W.cx + W.cx * (yc + W.cy * zc);
+                            const int s1 = ba.cell_start[cell + 1];
+                            for (int si = ba.cell_start[cell]; si < s1; ++si) {
+                                const WallSite ws = ba.sites[si];
+                                double dd[3];
+                                min_image(x, ws.p, L, dd);
+                                wca_add(eps, B.ev_radius + ws.radius, dd, F);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        for (int j = 0; j < W.n_bodies; ++j) {
+            const int o = ba.rep_bodies[W.first_body + j];
+            if (o == b) continue;
+            const Body& O = ba.bodies[o];
+            if (O.n_ev == 0) continue;
+            const Pose& Q = O.pose[parity];
+            const double sigma = B.ev_radius + O.ev_radius;
+            double dc[3];
+            min_image(P.pos, Q.pos, L, dc);
+            const double reach = B.ev_reach + O.ev_reach + 1.1224620483093730 * sigma;
+            if (dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2] >= reach * reach) continue;
+            for (int m = 0; m < O.n_ev; ++m) {
+                const EvSite eo = ba.ev[O.first_ev + m];
+                double xo[3], dd[3];
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax)
+                    xo[ax] = Q.pos[ax] + (Q.rot[3 * ax] * eo.off[0] + Q.rot[3 * ax + 1] * eo.off[1] +
+                                          Q.rot[3 * ax + 2] * eo.off[2]);
+                min_image(x, xo, L, dd);
+                wca_add(eps, sigma, dd, F);
+            }
+        }
+        acc[0] += F[0]; acc[1] += F[1]; acc[2] += F[2];
+        acc[3] += d[1] * F[2] - d[2] * F[1];
+        acc[4] += d[2] * F[0] - d[0] * F[2];
+        acc[5] += d[0] * F[1] - d[1] * F[0];
+    }
+}
+
+// per-body sums of a workgroup's acc[6] (shuffle + LDS tree, fixed order), valid in thread 0
+__device__ __forceinline__ void block_sum6(double acc[6], double (*part)[6], double out[6])
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        for (int k = 0; k < 6; ++k) acc[k] += __shfl_down(acc[k], m, 64);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 6; ++k) part[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; ++k) out[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
+}
+
+// WCA forces and torques of every body at the poses of MD step k of the fluid step (one
+// workgroup per body), 6 doubles per body into ba.wca_ft, read by the body finishing
+__global__ __launch_bounds__(256) void wca_kernel(const BodyArgs ba, const int64_t* step_ptr,
+                                                  int64_t step_arg, int k)
+{
+    __shared__ double part[4][6];
+    const int64_t step = current_step(step_ptr, step_arg);
+    const int parity = (int)((step * ba.substeps + k) & 1);
+    const int b = blockIdx.x;
+    const Body& B = ba.bodies[b];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (B.n_ev > 0) wca_body(ba, B, b, parity, acc);
+    double out[6];
+    block_sum6(acc, part, out);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q) ba.wca_ft[6 * b + q] = out[q];
+}
+
+void launch_wca(const BodyArgs& b, const int64_t* step_ptr, int64_t step_arg, int k,
+                hipStream_t s)
+{
+    if (b.n_bodies <= 0 || !b.wca_ft) return;
+    hipLaunchKernelGGL(wca_kernel, dim3(b.n_bodies), dim3(256), 0, s, b, step_ptr, step_arg, k);
+}
+
 // one workgroup per body: sum the bead forces and torques (shuffle + LDS tree, fixed order),
-// turn the torque into the body frame, second half kick, pose and bead records of the next
-// step
+// add the excluded-volume force and torque of the MD step, turn the torque into the body
+// frame, second half kick, pose and bead records of the next MD step.  parity: of the MD
+// step being finished.
 __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parity)
 {
     __shared__ double part[4][6];
@@ -145,6 +301,12 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
             F[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
             T[k] = (part[0][3 + k] + part[1][3 + k]) + (part[2][3 + k] + part[3][3 + k]);
         }
+        if (ba.wca_ft) {
+            for (int k = 0; k < 3; ++k) {
+                F[k] += ba.wca_ft[6 * b + k];
+                T[k] += ba.wca_ft[6 * b + 3 + k];
+            }
+        }
         // second half kick with this step's force and body-frame torque, from the step's pose
         const Pose& P = B.pose[parity];
         double vel[3], om[3], Tb[3];
@@ -154,8 +316,9 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
             Tb[ax] = P.rot[ax] * T[0] + P.rot[3 + ax] * T[1] + P.rot[6 + ax] * T[2];
         }
         if (!B.fixed) {
-            for (int ax = 0; ax < 3; ++ax) vel[ax] += 0.5 * F[ax] / B.mass;
-            half_kick(om, B.inertia, Tb);
+            const double hh = 0.5 * B.dt;
+            for (int ax = 0; ax < 3; ++ax) vel[ax] += hh * F[ax] / B.mass;
+            half_kick(om, B.inertia, Tb, B.dt);
         }
         Body& o = bodies[b];
         for (int ax = 0; ax < 3; ++ax) {
@@ -187,7 +350,8 @@ void node_step_kernel(const StepArgs<Real> a,
     const int64_t step = current_step(a.step_ptr, a.step_arg);
     int b = blockIdx.x;
     if (b < n_lead) {
-        if (b < ba.n_bodies) body_finish(ba, b, (int)(step & 1));
+        // the last MD step of this fluid step
+        if (b < ba.n_bodies) body_finish(ba, b, (int)((step * ba.substeps + ba.substeps - 1) & 1));
         return;
     }
     b -= n_lead;
@@ -353,7 +517,8 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
     double F[3];
     for (int ax = 0; ax < 3; ++ax) F[ax] = -B.gamma * (B.v[ax] - wu[ax]);
     if (c.kT > 0.0) {
-        const U4 blk = noise_block((uint64_t)step, (uint32_t)B.noise_idx, 1u, 0u, B.key0, B.key1);
+        const U4 blk = noise_block((uint64_t)step, (uint32_t)B.noise_idx, 1u, c.md_step, B.key0,
+                                   B.key1);
         const double amp = B.noise_amp;
         F[0] += amp * uniform16<double>(blk.x);
         F[1] += amp * uniform16<double>(blk.x >> 16);
@@ -363,7 +528,7 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
     if (local >= 0) {
         bool overflow = false;
         for (int ax = 0; ax < 3; ++ax) {
-            const double val = -(w * F[ax]);
+            const double val = -(w * (c.spread_h * F[ax]));
             const bool bad = !(fabs(val) < 16.0);
             overflow |= bad;
             long long hi, lo;
@@ -418,6 +583,23 @@ void launch_body_predict(const BodyArgs& b, int parity, hipStream_t s)
 {
     if (b.n_bodies <= 0) return;
     hipLaunchKernelGGL(body_predict_kernel, dim3(b.n_bodies), dim3(256), 0, s, b, parity);
+}
+
+// finish every body after MD step k of the fluid step (one workgroup per body)
+__global__ __launch_bounds__(256) void body_substep_kernel(const BodyArgs ba,
+                                                           const int64_t* step_ptr,
+                                                           int64_t step_arg, int k)
+{
+    const int64_t step = current_step(step_ptr, step_arg);
+    body_finish(ba, blockIdx.x, (int)((step * ba.substeps + k) & 1));
+}
+
+void launch_body_substep(const BodyArgs& b, const int64_t* step_ptr, int64_t step_arg, int k,
+                         hipStream_t s)
+{
+    if (b.n_bodies <= 0) return;
+    hipLaunchKernelGGL(body_substep_kernel, dim3(b.n_bodies), dim3(256), 0, s, b, step_ptr,
+                       step_arg, k);
 }
 
 __global__ void set_step_kernel(int64_t* p, int64_t v) { *p = v; }

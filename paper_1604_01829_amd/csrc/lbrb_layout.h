@@ -37,8 +37,10 @@ __host__ __device__ __forceinline__ int64_t pop_at(int i, int64_t g)
     const int64_t blk = g >> kPopBlockLog;
     return ((blk * Q + i) << kPopBlockLog) + (g & ((1 << kPopBlockLog) - 1));
 }
-// A step is two launches on one stream: the bead coupling, then the node update whose
-// leading workgroups finish the bodies (force/torque sums, second half kick).
+// A fluid step is two launches on one stream: the bead coupling, then the node update whose
+// leading workgroups finish the bodies (force/torque sums, second half kick).  With m MD
+// steps per fluid step, each of the first m - 1 MD steps adds a coupling launch and a body
+// launch before them.
 
 struct ReplicaDesc {
     int32_t nx, ny, nz, masked;
@@ -120,7 +122,9 @@ struct CoupleArgs {
     double* bead_force;         // 3 per bead, lab frame
     double* bead_torque;        // 3 per bead, lab frame
     int32_t n_beads;
+    uint32_t md_step;           // MD step within the fluid step (noise counter block)
     double kT;
+    double spread_h;            // the fluid receives -spread_h times the bead force
     DeviceHeader* hdr;
 };
 
@@ -133,8 +137,26 @@ struct LaunchEvents {
 template <typename Real>
 void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s,
                    const LaunchEvents& ev = LaunchEvents{});
-// Bodies to finish in a node launch: per-bead forces/torques of the coupling in, body records
-// and the bead records of the next step out.
+// Excluded volume (WCA).  A body's sites are body-frame offsets sharing one radius; static
+// sites (pore beads) are lab positions with a radius each, sorted into a uniform cell grid
+// per replica whose cells are at least one interaction range wide.
+struct EvSite {
+    double off[3];
+    double pad;
+};
+struct WallSite {
+    double p[3];
+    double radius;
+};
+struct WcaRep {
+    int32_t first_body, n_bodies;   // the replica's bodies: rep_bodies[first_body ...]
+    int32_t cx, cy, cz;             // cells per axis (0: no static sites)
+    int32_t cell0;                  // first entry of the replica in cell_start / cell_near
+    double cw[3];                   // cell widths (>= the largest interaction range)
+};
+
+// Bodies to finish: per-bead forces/torques of the coupling in, the excluded-volume forces of
+// the MD step computed here, body records and the bead records of the next MD step out.
 struct BodyArgs {
     Body* bodies;
     const Bead* beads;
@@ -142,14 +164,32 @@ struct BodyArgs {
     const double* bead_force;
     const double* bead_torque;
     int32_t n_bodies;
+    int32_t substeps;               // MD steps per fluid step
+    double wca_eps;
+    double* wca_ft;                 // excluded-volume force and torque of the MD step, 6 per
+                                    // body (null: no excluded volume)
+    const EvSite* ev;
+    const WcaRep* wrep;
+    const int32_t* rep_bodies;
+    const int32_t* cell_start;      // per replica cx*cy*cz + 1 entries into sites
+    const uint8_t* cell_near;       // 1 if a site lies in the cell or one of its neighbours
+    const WallSite* sites;
 };
 // the node update of one tile group; with forces the nodes consume the spread force, with
 // bodies != null its leading workgroups finish the bodies
 template <typename Real>
 void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const BodyArgs* bodies,
                       hipStream_t s, const LaunchEvents& ev = LaunchEvents{});
-// pose of the coming step (parity = step & 1) and bead records of every body
+// pose of the coming MD step (parity = MD step count & 1) and bead records of every body
 void launch_body_predict(const BodyArgs& b, int parity, hipStream_t s);
+// excluded-volume forces and torques of every body at the poses of MD step k of the fluid
+// step read from step_ptr + step_arg, into b.wca_ft (nothing when it is null)
+void launch_wca(const BodyArgs& b, const int64_t* step_ptr, int64_t step_arg, int k,
+                hipStream_t s);
+// finish the bodies after MD step k (< substeps - 1) of the fluid step read from
+// step_ptr + step_arg (or step_arg alone when step_ptr is null)
+void launch_body_substep(const BodyArgs& b, const int64_t* step_ptr, int64_t step_arg, int k,
+                         hipStream_t s);
 void launch_set_step(int64_t* step_ptr, int64_t value, hipStream_t s);
 template <typename Real>
 void launch_init_equilibrium(Real* f, int64_t N, const ReplicaDesc* reps, const NodeTile* tiles,

@@ -28,7 +28,7 @@ LB_PRECISION_F32 = 1
 
 # every symbol declared in include/lbrb.h
 EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wall_velocity",
-            "rb_add_raspberry",
+            "rb_add_raspberry", "rb_set_excluded_volume", "lb_add_wall_sites",
             "lb_rb_step", "lb_observables", "lb_body_count", "rb_bead_forces",
             "lb_export_populations", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
             "lb_set_timing", "lb_kernel_times", "lb_adjoint_workspace_bytes", "lb_rb_adjoint",
@@ -46,7 +46,9 @@ class lb_params(ctypes.Structure):
                 ("tau_bulk", ctypes.c_double), ("tau_odd", ctypes.c_double),
                 ("tau_even", ctypes.c_double), ("kT", ctypes.c_double),
                 ("g_ext", ctypes.c_double * 3), ("max_bodies", ctypes.c_int32),
-                ("max_beads", ctypes.c_int32), ("max_wall_links", ctypes.c_int32)]
+                ("max_beads", ctypes.c_int32), ("max_wall_links", ctypes.c_int32),
+                ("md_substeps", ctypes.c_int32), ("wca_epsilon", ctypes.c_double),
+                ("max_ev_sites", ctypes.c_int32), ("max_wall_sites", ctypes.c_int32)]
 
 
 class lb_totals(ctypes.Structure):
@@ -84,6 +86,11 @@ def library():
     L.lb_set_boundary_mask.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8)]
     L.lb_set_wall_velocity.restype = ctypes.c_int
     L.lb_set_wall_velocity.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32, _D]
+    L.rb_set_excluded_volume.restype = ctypes.c_int
+    L.rb_set_excluded_volume.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32, _D, ctypes.c_int32,
+                                         ctypes.c_double]
+    L.lb_add_wall_sites.restype = ctypes.c_int
+    L.lb_add_wall_sites.argtypes = [_VP, ctypes.c_int32, _D, ctypes.c_int32, ctypes.c_double]
     L.rb_add_raspberry.restype = ctypes.c_int
     L.rb_add_raspberry.argtypes = [_VP, ctypes.c_int32, _D, ctypes.c_int32, ctypes.c_double, _D,
                                    _D, _D, _D, _D, ctypes.c_double, ctypes.c_int32,
@@ -145,7 +152,8 @@ def _dp(a):
 
 def make_params(precision="f32", rho0=1.0, u0=(0.0, 0.0, 0.0), tau_shear=1.0, tau_bulk=None,
                 tau_odd=1.0, tau_even=1.0, kT=0.0, g_ext=(0.0, 0.0, 0.0), max_bodies=0,
-                max_beads=0, max_wall_links=0):
+                max_beads=0, max_wall_links=0, md_substeps=0, wca_epsilon=0.0, max_ev_sites=0,
+                max_wall_sites=0):
     p = lb_params()
     p.precision = LB_PRECISION_F32 if precision in ("f32", LB_PRECISION_F32) else LB_PRECISION_F64
     p.rho0 = rho0
@@ -159,6 +167,10 @@ def make_params(precision="f32", rho0=1.0, u0=(0.0, 0.0, 0.0), tau_shear=1.0, ta
     p.max_bodies = max_bodies
     p.max_beads = max_beads
     p.max_wall_links = max_wall_links
+    p.md_substeps = md_substeps
+    p.wca_epsilon = wca_epsilon
+    p.max_ev_sites = max_ev_sites
+    p.max_wall_sites = max_wall_sites
     return p
 
 
@@ -198,6 +210,19 @@ def lb_set_boundary_mask(ctx, replica, mask):
 def lb_set_wall_velocity(ctx, replica, wall, u):
     _check(ctx, library().lb_set_wall_velocity(ctx, int(replica), int(wall), _dp(_arr(u, 3))),
            "lb_set_wall_velocity")
+
+
+def rb_set_excluded_volume(ctx, replica, body_id, offsets, radius):
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.float64).reshape(-1, 3))
+    _check(ctx, library().rb_set_excluded_volume(ctx, int(replica), int(body_id), _dp(off),
+                                                 off.shape[0], float(radius)),
+           "rb_set_excluded_volume")
+
+
+def lb_add_wall_sites(ctx, replica, positions, radius):
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 3))
+    _check(ctx, library().lb_add_wall_sites(ctx, int(replica), _dp(pos), pos.shape[0],
+                                            float(radius)), "lb_add_wall_sites")
 
 
 def rb_add_raspberry(ctx, replica, offsets, mass, inertia, pos, quat=(1, 0, 0, 0),
@@ -293,6 +318,12 @@ class Simulation:
 
     def set_wall_velocity(self, replica, wall, u):
         lb_set_wall_velocity(self.ctx, replica, wall, u)
+
+    def set_excluded_volume(self, replica, body_id, offsets, radius):
+        rb_set_excluded_volume(self.ctx, replica, body_id, offsets, radius)
+
+    def add_wall_sites(self, replica, positions, radius):
+        lb_add_wall_sites(self.ctx, replica, positions, radius)
 
     def add_body(self, replica, offsets, mass, inertia, pos, quat=(1, 0, 0, 0), vel=(0, 0, 0),
                  omega=(0, 0, 0), gamma=0.0, fixed=False):
@@ -410,9 +441,14 @@ def simulation_from_workload(wl, precision=None, device="cuda:0", replicas=None,
     n_bodies = sum(len(r["bodies"]) for r in reps) + max_extra_bodies
     n_beads = sum(b["offsets"].shape[0] for r in reps for b in r["bodies"]) + max_extra_beads
     pp = dict(wl["params"])
+    n_ev = sum(np.asarray(b["ev"][0]).reshape(-1, 3).shape[0] for r in reps for b in r["bodies"]
+               if b.get("ev") is not None)
+    n_sites = sum(np.asarray(r["wall_sites"][0]).reshape(-1, 3).shape[0] for r in reps
+                  if r.get("wall_sites") is not None)
     params = make_params(precision=prec, max_bodies=max(1, n_bodies), max_beads=max(1, n_beads),
                          max_wall_links=sum(wall_link_bound(r["mask"], r.get("walls"))
-                                            for r in reps), **pp)
+                                            for r in reps),
+                         max_ev_sites=n_ev, max_wall_sites=n_sites, **pp)
     rr = make_replicas([(r["shape"], r["seed"]) for r in reps])
     sim = Simulation(params, rr, device=device)
     for k, r in enumerate(reps):
@@ -420,9 +456,13 @@ def simulation_from_workload(wl, precision=None, device="cuda:0", replicas=None,
             sim.set_mask(k, r["mask"])
         for wall, u in (r.get("walls") or {}).items():
             sim.set_wall_velocity(k, wall, u)
-        for b in r["bodies"]:
+        for j, b in enumerate(r["bodies"]):
             sim.add_body(k, b["offsets"], b["mass"], b["inertia"], b["pos"], b["quat"], b["vel"],
                          b["omega"], b["gamma"], b["fixed"])
+            if b.get("ev") is not None:
+                sim.set_excluded_volume(k, j, *b["ev"])
+        if r.get("wall_sites") is not None:
+            sim.add_wall_sites(k, *r["wall_sites"])
     return sim
 
 

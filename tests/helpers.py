@@ -10,7 +10,9 @@ def oracle_params(wl, rep):
     p = wl["params"]
     return po.make_params(rho0=p["rho0"], u0=p["u0"], tau_shear=p["tau_shear"],
                           tau_bulk=p["tau_bulk"], tau_odd=p["tau_odd"], tau_even=p["tau_even"],
-                          kT=p["kT"], g_ext=p["g_ext"], seed=rep["seed"])
+                          kT=p["kT"], g_ext=p["g_ext"], seed=rep["seed"],
+                          md_substeps=p.get("md_substeps", 0),
+                          wca_epsilon=p.get("wca_epsilon", 0.0))
 
 
 def orc_offsets(orc, b):
@@ -25,9 +27,13 @@ def oracle_from_workload(wl, r=0):
         sim.set_mask(rep["mask"])
     for wall, u in (rep.get("walls") or {}).items():
         sim.set_wall_velocity(wall, u)
-    for b in rep["bodies"]:
+    for j, b in enumerate(rep["bodies"]):
         sim.add_body(b["offsets"], b["mass"], b["inertia"], b["pos"], b["quat"], b["vel"],
                      b["omega"], b["gamma"], b["fixed"])
+        if b.get("ev") is not None:
+            sim.set_excluded_volume(j, *b["ev"])
+    if rep.get("wall_sites") is not None:
+        sim.add_wall_sites(*rep["wall_sites"])
     return sim
 
 
