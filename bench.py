@@ -201,6 +201,19 @@ def compare_runs(args):
                                  "node_step_gbs": round(m["node_gbs"], 1),
                                  "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
                                  "traffic": traffic_from_profiles(f"node_step_{prec}_box256")}
+    # the paper's integration scheme on the same pore: 2 MD steps per fluid step, inner
+    # excluded-volume layers on the spheres and WCA pore beads (eps = kT)
+    wlm = W.confined_md_workload(substeps=2)
+    sim = lbrb.simulation_from_workload(wlm, precision="f32")
+    m = measure(sim, 1000, 100, 100, 100, "f32")
+    sim.close()
+    out["confined_md_fp32"] = {
+        "md_steps_per_fluid_step": 2,
+        "pore_sites": int(wlm["replicas"][0]["wall_sites"][0].shape[0]),
+        "ev_sites": int(sum(b["ev"][0].shape[0] for b in wlm["replicas"][0]["bodies"])),
+        "mlups": round(m["mlups"], 1), "ms_per_step": round(m["ms_per_step"], 5),
+        "node_step_us": round(m["node_us"], 2), "couple_us": round(m["couple_us"], 2),
+        "finite": m["finite"]}
     # reverse pass on the fixed sphere in uniform flow
     wl5 = W.workload(5)
     wl5["params"]["kT"] = 0.0

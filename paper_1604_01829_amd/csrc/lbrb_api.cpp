@@ -35,16 +35,18 @@ struct Plan {
     int64_t tiles_cap = 0;    // sum of ceil(nodes / 256)
     int64_t bead_cap = 0, body_cap = 0;
     int64_t link_cap = 0;     // moving-wall links
-    int64_t ev_cap = 0, site_cap = 0, cells_cap = 0;   // excluded volume
+    int64_t ev_cap = 0, site_cap = 0, cells_cap = 0, fine_cap = 0;   // excluded volume
     int gforce_words = 3;     // fixed-point words per node: 3 axes x (1 in FP32, 2 in FP64)
     size_t off_hdr, off_reps, off_rows, off_rowinfo, off_tiles_d, off_tiles_m, off_fa, off_fb,
         off_gforce, off_flags, off_bodies, off_bead_off, off_bead_rec, off_bead_force,
         off_bead_torque, off_partials, off_links, off_ev, off_sites, off_wrep, off_rep_bodies,
-        off_cell_start, off_cell_near, off_wca_ft, total;
+        off_nb_start, off_nb_idx, off_near, off_wca_ft, total;
 };
 
-constexpr int kMaxCellsPerAxis = 32;   // WCA cell grid: cells per axis at most
+constexpr int kMaxCellsPerAxis = 32;   // WCA coarse grid: cells per axis at most
+constexpr double kFineCell = 2.0;      // WCA fine flag grid: cell width at most
 int cells_per_axis_cap(int n) { return std::min(n, kMaxCellsPerAxis); }
+int fine_per_axis(int n) { return (int)std::ceil(n / kFineCell); }
 
 bool valid_params(const lb_params* p)
 {
@@ -77,9 +79,11 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
         pl.N += pad_nodes(nodes);
         pl.rows_cap += (int64_t)R.ny * R.nz;
         pl.tiles_cap += pad_nodes(nodes) / kNodeBlock;
-        if (p->max_wall_sites > 0)
+        if (p->max_wall_sites > 0) {
             pl.cells_cap += (int64_t)cells_per_axis_cap(R.nx) * cells_per_axis_cap(R.ny) *
                             cells_per_axis_cap(R.nz) + 1;
+            pl.fine_cap += (int64_t)fine_per_axis(R.nx) * fine_per_axis(R.ny) * fine_per_axis(R.nz);
+        }
     }
     const size_t real = p->precision == LB_PRECISION_F32 ? sizeof(float) : sizeof(double);
     pl.body_cap = p->max_bodies;
@@ -111,8 +115,10 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
     pl.off_sites = take(sizeof(WallSite) * std::max<int64_t>(pl.site_cap, 1));
     pl.off_wrep = take(sizeof(WcaRep) * n);
     pl.off_rep_bodies = take(sizeof(int32_t) * std::max<int64_t>(pl.body_cap, 1));
-    pl.off_cell_start = take(sizeof(int32_t) * std::max<int64_t>(pl.cells_cap, 1));
-    pl.off_cell_near = take(std::max<int64_t>(pl.cells_cap, 1));
+    pl.off_nb_start = take(sizeof(int32_t) * std::max<int64_t>(pl.cells_cap, 1));
+    // a site appears in the neighbourhood lists of at most 27 coarse cells
+    pl.off_nb_idx = take(sizeof(int32_t) * 27 * std::max<int64_t>(pl.site_cap, 1));
+    pl.off_near = take(std::max<int64_t>(pl.fine_cap, 1));
     pl.off_wca_ft = take(sizeof(double) * 6 * std::max<int64_t>(pl.body_cap, 1));
     pl.total = o;
     return true;
@@ -166,8 +172,9 @@ struct lb_ctx {
     WallSite* d_sites = nullptr;
     WcaRep* d_wrep = nullptr;
     int32_t* d_rep_bodies = nullptr;
-    int32_t* d_cell_start = nullptr;
-    uint8_t* d_cell_near = nullptr;
+    int32_t* d_nb_start = nullptr;
+    int32_t* d_nb_idx = nullptr;
+    uint8_t* d_near = nullptr;
     double* d_wca_ft = nullptr;
     std::vector<EvHost> ev;         // per body
     int64_t n_ev = 0, n_sites = 0;
@@ -298,8 +305,9 @@ BodyArgs body_args(const lb_ctx* c)
     ba.ev = c->d_ev;
     ba.wrep = c->d_wrep;
     ba.rep_bodies = c->d_rep_bodies;
-    ba.cell_start = c->d_cell_start;
-    ba.cell_near = c->d_cell_near;
+    ba.nb_start = c->d_nb_start;
+    ba.nb_idx = c->d_nb_idx;
+    ba.near = c->d_near;
     ba.sites = c->d_sites;
     return ba;
 }
@@ -341,12 +349,10 @@ hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* st
         if (timed) e = get_pair(c);
         CoupleArgs ca = couple_args(c);
         ca.md_step = (uint32_t)k;
-        launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], ca, s, LaunchEvents{e.a, e.b});
+        const BodyArgs ba = body_args(c);
+        launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], ca, s, LaunchEvents{e.a, e.b}, &ba);
         note(hipGetLastError());
         if (timed && e.a && e.b) c->ev_couple_t.push_back(e);
-        const BodyArgs ba = body_args(c);
-        launch_wca(ba, step_ptr, step_arg, k, s);
-        note(hipGetLastError());
         if (k + 1 < m) {
             launch_body_substep(ba, step_ptr, step_arg, k, s);
             note(hipGetLastError());
@@ -611,10 +617,11 @@ bool check_replica(lb_ctx* c, int32_t r)
 // ------------------------------------------------------------------ excluded volume
 
 // WCA tables of every replica from the host records: the bodies of each replica, the
-// excluded-volume sites of every body (packed in body order), and the static sites sorted
-// into a per-replica cell grid whose cells are at least one interaction range wide (with a
-// margin, so a site within range of a point always lies in the point's cell or a
-// neighbouring one) and a flag per cell telling whether any site lies in its neighbourhood.
+// excluded-volume sites of every body (packed in body order), and for the static sites a
+// coarse grid whose cells are at least one interaction range wide (with a margin, so a site
+// within range of a point always lies in the point's cell or an adjacent one), one list per
+// coarse cell of the sites in that neighbourhood, and a fine grid of flags marking the cells
+// whose centre has a site within the range plus half the cell diagonal.
 int build_wca(lb_ctx* c)
 {
     const double cut = std::pow(2.0, 1.0 / 6.0);
@@ -637,10 +644,9 @@ int build_wca(lb_ctx* c)
     }
     // replicas: body lists and site grids
     std::vector<WcaRep> wr(c->n_rep);
-    std::vector<int32_t> rep_bodies;
+    std::vector<int32_t> rep_bodies, nb_start, nb_idx;
     std::vector<WallSite> sites;
-    std::vector<int32_t> cstart;
-    std::vector<uint8_t> cnear;
+    std::vector<uint8_t> near;
     for (int r = 0; r < c->n_rep; ++r) {
         const ReplicaDesc& R = c->reps[r];
         const ReplicaHost& H = c->rh[r];
@@ -663,36 +669,43 @@ int build_wca(lb_ctx* c)
             if (ev_r >= 0.0 && 2.0 * range > dims[a])
                 return fail(c, LB_ERR_ARG, "a box side is shorter than twice the WCA range");
         if (H.sites.empty() || ev_r < 0.0) continue;   // no grid needed
-        int nc[3];
+        // coarse grid, sites binned by cell (the kernel's cell rule)
+        int nc[3], ng[3];
         for (int a = 0; a < 3; ++a) {
             const int fit = (int)std::floor(dims[a] / (range * (1.0 + 1e-6)));
             nc[a] = std::max(1, std::min(fit, cells_per_axis_cap(dims[a])));
             W.cw[a] = (double)dims[a] / nc[a];
+            ng[a] = fine_per_axis(dims[a]);
+            W.fw[a] = (double)dims[a] / ng[a];
         }
         W.cx = nc[0]; W.cy = nc[1]; W.cz = nc[2];
-        W.cell0 = (int32_t)cstart.size();
-        const int ncell = nc[0] * nc[1] * nc[2];
-        // the cell of a site, computed as the kernel computes the cell of a point
-        auto cell_of = [&](const double p[3]) {
-            int ci[3];
-            for (int a = 0; a < 3; ++a) {
-                const double L = dims[a];
-                const double xw = p[a] - L * std::floor(p[a] / L);
-                int q = (int)(xw / W.cw[a]);
-                ci[a] = q < 0 ? 0 : (q >= nc[a] ? nc[a] - 1 : q);
-            }
-            return ci[0] + nc[0] * (ci[1] + nc[1] * ci[2]);
+        W.gx = ng[0]; W.gy = ng[1]; W.gz = ng[2];
+        W.cell0 = (int32_t)nb_start.size();
+        W.fine0 = (int32_t)near.size();
+        auto cell_idx = [](double x, double L, double w, int n) {
+            const double xw = x - L * std::floor(x / L);
+            const int q = (int)(xw / w);
+            return q < 0 ? 0 : (q >= n ? n - 1 : q);
         };
-        std::vector<std::vector<WallSite>> bins(ncell);
-        for (const WallSite& w : H.sites) bins[cell_of(w.p)].push_back(w);
-        std::vector<uint8_t> occ(ncell, 0);
-        for (int k = 0; k < ncell; ++k) {
-            cstart.push_back((int32_t)sites.size());
-            occ[k] = bins[k].empty() ? 0 : 1;
-            sites.insert(sites.end(), bins[k].begin(), bins[k].end());
+        const int ncell = nc[0] * nc[1] * nc[2];
+        const int32_t site0 = (int32_t)sites.size();
+        std::vector<std::vector<int32_t>> bins(ncell);
+        {
+            std::vector<std::vector<WallSite>> sb(ncell);
+            for (const WallSite& w : H.sites) {
+                const int k = cell_idx(w.p[0], dims[0], W.cw[0], nc[0]) +
+                              nc[0] * (cell_idx(w.p[1], dims[1], W.cw[1], nc[1]) +
+                                       nc[1] * cell_idx(w.p[2], dims[2], W.cw[2], nc[2]));
+                sb[k].push_back(w);
+            }
+            for (int k = 0; k < ncell; ++k)
+                for (const WallSite& w : sb[k]) {
+                    bins[k].push_back((int32_t)sites.size());
+                    sites.push_back(w);
+                }
         }
-        cstart.push_back((int32_t)sites.size());
-        // neighbourhood flags (same neighbour rule as the kernel)
+        // neighbourhood lists: the distinct cells c-1, c, c+1 along each axis (all cells of an
+        // axis with fewer than three)
         auto span = [](int ci, int n, int& first, int& count) {
             if (n >= 3) { first = ci == 0 ? n - 1 : ci - 1; count = 3; }
             else { first = 0; count = n; }
@@ -700,22 +713,53 @@ int build_wca(lb_ctx* c)
         for (int z = 0; z < nc[2]; ++z)
             for (int y = 0; y < nc[1]; ++y)
                 for (int x = 0; x < nc[0]; ++x) {
+                    nb_start.push_back((int32_t)nb_idx.size());
                     int f0, n0, f1, n1, f2, n2;
                     span(x, nc[0], f0, n0);
                     span(y, nc[1], f1, n1);
                     span(z, nc[2], f2, n2);
-                    uint8_t any = 0;
                     for (int iz = 0; iz < n2; ++iz)
                         for (int iy = 0; iy < n1; ++iy)
-                            for (int ix = 0; ix < n0; ++ix)
-                                any |= occ[(f0 + ix) % nc[0] +
-                                           nc[0] * ((f1 + iy) % nc[1] + nc[1] * ((f2 + iz) % nc[2]))];
-                    cnear.push_back(any);
+                            for (int ix = 0; ix < n0; ++ix) {
+                                const auto& bin = bins[(f0 + ix) % nc[0] +
+                                                       nc[0] * ((f1 + iy) % nc[1] +
+                                                                nc[1] * ((f2 + iz) % nc[2]))];
+                                nb_idx.insert(nb_idx.end(), bin.begin(), bin.end());
+                            }
                 }
-        cnear.push_back(0);   // keeps cell_near aligned with cell_start (one extra entry)
+        nb_start.push_back((int32_t)nb_idx.size());
+        // fine flags: cells whose centre lies within range + half diagonal of a site
+        const size_t nfine = (size_t)ng[0] * ng[1] * ng[2];
+        std::vector<uint8_t> fl(nfine, 0);
+        const double hd = 0.5 * std::sqrt(W.fw[0] * W.fw[0] + W.fw[1] * W.fw[1] + W.fw[2] * W.fw[2]);
+        for (size_t k = (size_t)site0; k < sites.size(); ++k) {
+            const WallSite& w = sites[k];
+            const double reach = cut * (ev_r + w.radius) + hd + 1e-6;
+            int lo[3], cnt[3];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = (int)std::floor((w.p[a] - reach) / W.fw[a]) - 1;
+                cnt[a] = std::min(ng[a], (int)std::ceil(2.0 * reach / W.fw[a]) + 4);
+            }
+            for (int iz = 0; iz < cnt[2]; ++iz)
+                for (int iy = 0; iy < cnt[1]; ++iy)
+                    for (int ix = 0; ix < cnt[0]; ++ix) {
+                        const int g[3] = {lo[0] + ix, lo[1] + iy, lo[2] + iz};
+                        double d2 = 0.0;
+                        int gi[3];
+                        for (int a = 0; a < 3; ++a) {
+                            gi[a] = ((g[a] % ng[a]) + ng[a]) % ng[a];
+                            double dd = (gi[a] + 0.5) * W.fw[a] - w.p[a];
+                            dd -= dims[a] * std::round(dd / dims[a]);
+                            d2 += dd * dd;
+                        }
+                        if (d2 <= reach * reach) fl[gi[0] + (size_t)ng[0] * (gi[1] + (size_t)ng[1] * gi[2])] = 1;
+                    }
+        }
+        near.insert(near.end(), fl.begin(), fl.end());
     }
-    if ((int64_t)cstart.size() > std::max<int64_t>(c->plan.cells_cap, 0))
-        return fail(c, LB_ERR_CAPACITY, "WCA cell grid exceeds its workspace");
+    if ((int64_t)nb_start.size() > c->plan.cells_cap || (int64_t)near.size() > c->plan.fine_cap ||
+        (int64_t)nb_idx.size() > 27 * c->plan.site_cap)
+        return fail(c, LB_ERR_CAPACITY, "WCA site grids exceed their workspace");
     c->n_ev = (int64_t)ev.size();
     if (!ev.empty())
         HIP_TRY(c, hipMemcpyAsync(c->d_ev, ev.data(), sizeof(EvSite) * ev.size(),
@@ -723,12 +767,15 @@ int build_wca(lb_ctx* c)
     if (!sites.empty())
         HIP_TRY(c, hipMemcpyAsync(c->d_sites, sites.data(), sizeof(WallSite) * sites.size(),
                                   hipMemcpyHostToDevice, c->stream));
-    if (!cstart.empty()) {
-        HIP_TRY(c, hipMemcpyAsync(c->d_cell_start, cstart.data(), sizeof(int32_t) * cstart.size(),
+    if (!nb_start.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_nb_start, nb_start.data(), sizeof(int32_t) * nb_start.size(),
                                   hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(c, hipMemcpyAsync(c->d_cell_near, cnear.data(), cnear.size(),
+    if (!nb_idx.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_nb_idx, nb_idx.data(), sizeof(int32_t) * nb_idx.size(),
                                   hipMemcpyHostToDevice, c->stream));
-    }
+    if (!near.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_near, near.data(), near.size(), hipMemcpyHostToDevice,
+                                  c->stream));
     if (!rep_bodies.empty())
         HIP_TRY(c, hipMemcpyAsync(c->d_rep_bodies, rep_bodies.data(),
                                   sizeof(int32_t) * rep_bodies.size(), hipMemcpyHostToDevice,
@@ -928,8 +975,9 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     c->d_sites = (WallSite*)(c->ws + pl.off_sites);
     c->d_wrep = (WcaRep*)(c->ws + pl.off_wrep);
     c->d_rep_bodies = (int32_t*)(c->ws + pl.off_rep_bodies);
-    c->d_cell_start = (int32_t*)(c->ws + pl.off_cell_start);
-    c->d_cell_near = (uint8_t*)(c->ws + pl.off_cell_near);
+    c->d_nb_start = (int32_t*)(c->ws + pl.off_nb_start);
+    c->d_nb_idx = (int32_t*)(c->ws + pl.off_nb_idx);
+    c->d_near = (uint8_t*)(c->ws + pl.off_near);
     c->d_wca_ft = (double*)(c->ws + pl.off_wca_ft);
 
     c->reps.resize(n_replicas);

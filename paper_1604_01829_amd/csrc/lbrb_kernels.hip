@@ -140,95 +140,11 @@ __device__ __forceinline__ void wca_add(double eps, double sigma, const double d
     for (int k = 0; k < 3; ++k) F[k] += coef * d[k];
 }
 
-// cell range along one axis around cell c: c-1, c, c+1 (periodic), or every cell when the
-// axis has fewer than three
-__device__ __forceinline__ void cell_span(int c, int n, int& first, int& count)
-{
-    if (n >= 3) { first = c == 0 ? n - 1 : c - 1; count = 3; }
-    else { first = 0; count = n; }
-}
-
 __device__ __forceinline__ int cell_of(double x, double L, double w, int n)
 {
     const double xw = x - L * floor(x / L);
     int c = (int)(xw / w);
     return c < 0 ? 0 : (c >= n ? n - 1 : c);
-}
-
-// WCA force and torque (lab, about the centre) on the excluded-volume sites of body B at
-// pose P of the current MD step, from the static sites of its replica and the sites of the
-// replica's other bodies (at their poses of the same MD step), summed into acc[0..5]
-__device__ __forceinline__ void wca_body(const BodyArgs& ba, const Body& B, int b, int parity,
-                                         double acc[6])
-{
-    const Pose& P = B.pose[parity];
-    const WcaRep W = ba.wrep[B.replica];
-    const double L[3] = {(double)B.box.nx, (double)B.box.ny, (double)B.box.nz};
-    const double eps = ba.wca_eps;
-    for (int k = threadIdx.x; k < B.n_ev; k += blockDim.x) {
-        const EvSite e = ba.ev[B.first_ev + k];
-        double d[3], x[3];
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            d[ax] = P.rot[3 * ax] * e.off[0] + P.rot[3 * ax + 1] * e.off[1] +
-                    P.rot[3 * ax + 2] * e.off[2];
-            x[ax] = P.pos[ax] + d[ax];
-        }
-        double F[3] = {0.0, 0.0, 0.0};
-        if (W.cx > 0) {
-            const int c0 = cell_of(x[0], L[0], W.cw[0], W.cx);
-            const int c1 = cell_of(x[1], L[1], W.cw[1], W.cy);
-            const int c2 = cell_of(x[2], L[2], W.cw[2], W.cz);
-            if (ba.cell_near[W.cell0 + c0 + W.cx * (c1 + W.cy * c2)]) {
-                int f0, n0, f1, n1, f2, n2;
-                cell_span(c0, W.cx, f0, n0);
-                cell_span(c1, W.cy, f1, n1);
-                cell_span(c2, W.cz, f2, n2);
-                for (int iz = 0; iz < n2; ++iz) {
-                    const int zc = (f2 + iz) % W.cz;
-                    for (int iy = 0; iy < n1; ++iy) {
-                        const int yc = (f1 + iy) % W.cy;
-                        for (int ix = 0; ix < n0; ++ix) {
-                            const int cell = W.cell0 + (f0 + ix) % W.cx + W.cx * (yc + W.cy * zc);
-                            const int s1 = ba.cell_start[cell + 1];
-                            for (int si = ba.cell_start[cell]; si < s1; ++si) {
-                                const WallSite ws = ba.sites[si];
-                                double dd[3];
-                                min_image(x, ws.p, L, dd);
-                                wca_add(eps, B.ev_radius + ws.radius, dd, F);
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        for (int j = 0; j < W.n_bodies; ++j) {
-            const int o = ba.rep_bodies[W.first_body + j];
-            if (o == b) continue;
-            const Body& O = ba.bodies[o];
-            if (O.n_ev == 0) continue;
-            const Pose& Q = O.pose[parity];
-            const double sigma = B.ev_radius + O.ev_radius;
-            double dc[3];
-            min_image(P.pos, Q.pos, L, dc);
-            const double reach = B.ev_reach + O.ev_reach + 1.1224620483093730 * sigma;
-            if (dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2] >= reach * reach) continue;
-            for (int m = 0; m < O.n_ev; ++m) {
-                const EvSite eo = ba.ev[O.first_ev + m];
-                double xo[3], dd[3];
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax)
-                    xo[ax] = Q.pos[ax] + (Q.rot[3 * ax] * eo.off[0] + Q.rot[3 * ax + 1] * eo.off[1] +
-                                          Q.rot[3 * ax + 2] * eo.off[2]);
-                min_image(x, xo, L, dd);
-                wca_add(eps, sigma, dd, F);
-            }
-        }
-        acc[0] += F[0]; acc[1] += F[1]; acc[2] += F[2];
-        acc[3] += d[1] * F[2] - d[2] * F[1];
-        acc[4] += d[2] * F[0] - d[0] * F[2];
-        acc[5] += d[0] * F[1] - d[1] * F[0];
-    }
 }
 
 // per-body sums of a workgroup's acc[6] (shuffle + LDS tree, fixed order), valid in thread 0
@@ -245,29 +161,123 @@ __device__ __forceinline__ void block_sum6(double acc[6], double (*part)[6], dou
         for (int k = 0; k < 6; ++k) out[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
 }
 
-// WCA forces and torques of every body at the poses of MD step k of the fluid step (one
-// workgroup per body), 6 doubles per body into ba.wca_ft, read by the body finishing
-__global__ __launch_bounds__(256) void wca_kernel(const BodyArgs ba, const int64_t* step_ptr,
-                                                  int64_t step_arg, int k)
+// LDS of one excluded-volume workgroup: the other bodies in range, 64 at a time
+struct WcaLds {
+    double pose[64][13];         // centre, rotation matrix, site radius
+    int32_t site0[64], nsite[64];
+    int32_t n;
+    double part[4][6];
+};
+
+// lab position of a body-frame offset at a pose given as centre + row-major rotation
+__device__ __forceinline__ void site_at(const double* pos, const double* rot, const double off[3],
+                                        double d[3], double x[3])
 {
-    __shared__ double part[4][6];
-    const int64_t step = current_step(step_ptr, step_arg);
-    const int parity = (int)((step * ba.substeps + k) & 1);
-    const int b = blockIdx.x;
-    const Body& B = ba.bodies[b];
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    if (B.n_ev > 0) wca_body(ba, B, b, parity, acc);
-    double out[6];
-    block_sum6(acc, part, out);
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 6; ++q) ba.wca_ft[6 * b + q] = out[q];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        d[ax] = rot[3 * ax] * off[0] + rot[3 * ax + 1] * off[1] + rot[3 * ax + 2] * off[2];
+        x[ax] = pos[ax] + d[ax];
+    }
 }
 
-void launch_wca(const BodyArgs& b, const int64_t* step_ptr, int64_t step_arg, int k,
-                hipStream_t s)
+// One workgroup: the WCA force and torque (lab, about the centre) on the excluded-volume
+// sites of body b at its pose of MD step S (parity = S & 1), from the static sites of its
+// replica (through the cell grid) and from the sites of the replica's other bodies at their
+// poses of the same MD step; 6 doubles into ba.wca_ft.  The other bodies are screened 64 at
+// a time by their centre distance; the ones in range are compacted in body order (ballot),
+// so the sums do not depend on timing.
+__device__ __forceinline__ void wca_block(const BodyArgs& ba, int b, int parity, WcaLds& S)
 {
-    if (b.n_bodies <= 0 || !b.wca_ft) return;
-    hipLaunchKernelGGL(wca_kernel, dim3(b.n_bodies), dim3(256), 0, s, b, step_ptr, step_arg, k);
+    const Body& B = ba.bodies[b];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (B.n_ev > 0) {
+        const Pose& P = B.pose[parity];
+        const WcaRep W = ba.wrep[B.replica];
+        const double L[3] = {(double)B.box.nx, (double)B.box.ny, (double)B.box.nz};
+        const double eps = ba.wca_eps;
+        // static sites: the fine flag, then one contiguous list of the coarse cell's
+        // neighbourhood
+        if (W.cx > 0) {
+            for (int k = threadIdx.x; k < B.n_ev; k += blockDim.x) {
+                double d[3], x[3], F[3] = {0.0, 0.0, 0.0};
+                site_at(P.pos, P.rot, ba.ev[B.first_ev + k].off, d, x);
+                const int g0 = cell_of(x[0], L[0], W.fw[0], W.gx);
+                const int g1 = cell_of(x[1], L[1], W.fw[1], W.gy);
+                const int g2 = cell_of(x[2], L[2], W.fw[2], W.gz);
+                if (!ba.near[W.fine0 + g0 + W.gx * (g1 + W.gy * g2)]) continue;
+                const int c0 = cell_of(x[0], L[0], W.cw[0], W.cx);
+                const int c1 = cell_of(x[1], L[1], W.cw[1], W.cy);
+                const int c2 = cell_of(x[2], L[2], W.cw[2], W.cz);
+                const int cell = W.cell0 + c0 + W.cx * (c1 + W.cy * c2);
+                const int i1 = ba.nb_start[cell + 1];
+                for (int i = ba.nb_start[cell]; i < i1; ++i) {
+                    const WallSite ws = ba.sites[ba.nb_idx[i]];
+                    double dd[3];
+                    min_image(x, ws.p, L, dd);
+                    wca_add(eps, B.ev_radius + ws.radius, dd, F);
+                }
+                acc[0] += F[0]; acc[1] += F[1]; acc[2] += F[2];
+                acc[3] += d[1] * F[2] - d[2] * F[1];
+                acc[4] += d[2] * F[0] - d[0] * F[2];
+                acc[5] += d[0] * F[1] - d[1] * F[0];
+            }
+        }
+        // other bodies, 64 candidates at a time
+        for (int j0 = 0; j0 < W.n_bodies; j0 += 64) {
+            if (threadIdx.x < 64) {
+                const int lane = threadIdx.x, j = j0 + lane;
+                bool close = false;
+                int o = -1;
+                if (j < W.n_bodies) {
+                    o = ba.rep_bodies[W.first_body + j];
+                    if (o != b && ba.bodies[o].n_ev > 0) {
+                        const Body& O = ba.bodies[o];
+                        double dc[3];
+                        min_image(P.pos, O.pose[parity].pos, L, dc);
+                        const double reach = B.ev_reach + O.ev_reach +
+                                             1.1224620483093730 * (B.ev_radius + O.ev_radius);
+                        close = dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2] < reach * reach;
+                    }
+                }
+                const unsigned long long mask = __ballot(close);
+                if (close) {
+                    const int q = __popcll(mask & ((1ull << lane) - 1ull));
+                    const Body& O = ba.bodies[o];
+                    const Pose& Q = O.pose[parity];
+                    for (int t = 0; t < 3; ++t) S.pose[q][t] = Q.pos[t];
+                    for (int t = 0; t < 9; ++t) S.pose[q][3 + t] = Q.rot[t];
+                    S.pose[q][12] = O.ev_radius;
+                    S.site0[q] = O.first_ev;
+                    S.nsite[q] = O.n_ev;
+                }
+                if (lane == 0) S.n = __popcll(mask);
+            }
+            __syncthreads();
+            const int nc = S.n;
+            for (int k = threadIdx.x; k < B.n_ev && nc > 0; k += blockDim.x) {
+                double d[3], x[3], F[3] = {0.0, 0.0, 0.0};
+                site_at(P.pos, P.rot, ba.ev[B.first_ev + k].off, d, x);
+                for (int q = 0; q < nc; ++q) {
+                    const double sigma = B.ev_radius + S.pose[q][12];
+                    for (int m = 0; m < S.nsite[q]; ++m) {
+                        double dq[3], xo[3], dd[3];
+                        site_at(&S.pose[q][0], &S.pose[q][3], ba.ev[S.site0[q] + m].off, dq, xo);
+                        min_image(x, xo, L, dd);
+                        wca_add(eps, sigma, dd, F);
+                    }
+                }
+                acc[0] += F[0]; acc[1] += F[1]; acc[2] += F[2];
+                acc[3] += d[1] * F[2] - d[2] * F[1];
+                acc[4] += d[2] * F[0] - d[0] * F[2];
+                acc[5] += d[0] * F[1] - d[1] * F[0];
+            }
+            __syncthreads();
+        }
+    }
+    double out[6];
+    block_sum6(acc, S.part, out);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q) ba.wca_ft[6 * b + q] = out[q];
 }
 
 // one workgroup per body: sum the bead forces and torques (shuffle + LDS tree, fixed order),
@@ -419,9 +429,15 @@ void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const B
 // lanes' force contributions are summed as fixed-point words in LDS and the node's owner
 // adds each sum to the node with one device atomic per word.  Integer sums do not depend on
 // their order, so the result is the same as one atomic per lane.
-template <typename Real>
+//
+// With excluded volume (WCA), the first n_wca workgroups (a multiple of 8, so that the bead
+// workgroups keep their XCD pattern) compute each body's WCA force and torque for the same
+// MD step instead (wca_block); they use the LDS of the force sums.  Without it the kernel is
+// compiled without that code (its registers stay those of the coupling alone).
+template <typename Real, bool WCA>
 __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Real> a,
-                                                              const CoupleArgs c)
+                                                              const CoupleArgs c,
+                                                              const BodyArgs ba, int n_wca)
 {
     constexpr int TS = 2 * kCoupleBlock;                 // hash slots (power of two)
     constexpr int NW = sizeof(Real) == 8 ? 6 : 3;       // fixed-point words per node
@@ -429,6 +445,15 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
     __shared__ unsigned long long key[TS];
     __shared__ Real mom[4][TS];
     __shared__ unsigned long long acc[NW][TS];
+    static_assert(sizeof(acc) >= sizeof(WcaLds), "excluded-volume LDS fits in the force sums");
+    if (WCA && (int)blockIdx.x < n_wca) {
+        if ((int)blockIdx.x < ba.n_bodies) {
+            const int64_t step = current_step(a.step_ptr, a.step_arg);
+            wca_block(ba, blockIdx.x, (int)((step * ba.substeps + c.md_step) & 1),
+                      *reinterpret_cast<WcaLds*>(&acc[0][0]));
+        }
+        return;
+    }
     for (int k = threadIdx.x; k < TS; k += kCoupleBlock) {
         key[k] = EMPTY;
         for (int w = 0; w < NW; ++w) acc[w][k] = 0;
@@ -436,7 +461,7 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
 
     // consecutive bead blocks (neighbouring beads of one body, sharing stencil rows) stay on
     // one XCD and its L2
-    const int tid = xcd_tile(blockIdx.x, gridDim.x) * kCoupleBlock + threadIdx.x;
+    const int tid = xcd_tile(blockIdx.x - n_wca, gridDim.x - n_wca) * kCoupleBlock + threadIdx.x;
     const int bead = tid >> 3, corner = tid & 7;
     const bool active = bead < c.n_beads;   // the 8 lanes of a bead share this
     const int64_t step = current_step(a.step_ptr, a.step_arg);
@@ -558,12 +583,21 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
 
 template <typename Real>
 void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s,
-                   const LaunchEvents& ev)
+                   const LaunchEvents& ev, const BodyArgs* wca)
 {
     if (c.n_beads <= 0) return;
+    BodyArgs ba{};
+    int n_wca = 0;
+    if (wca && wca->wca_ft && wca->n_bodies > 0) {
+        ba = *wca;
+        n_wca = (ba.n_bodies + 7) & ~7;
+    }
     const int threads = c.n_beads * kBeadLanes;
-    launch_timed(couple_kernel<Real>, dim3((threads + kCoupleBlock - 1) / kCoupleBlock),
-                 dim3(kCoupleBlock), s, ev, a, c);
+    const dim3 grid((threads + kCoupleBlock - 1) / kCoupleBlock + n_wca);
+    if (n_wca > 0)
+        launch_timed(couple_kernel<Real, true>, grid, dim3(kCoupleBlock), s, ev, a, c, ba, n_wca);
+    else
+        launch_timed(couple_kernel<Real, false>, grid, dim3(kCoupleBlock), s, ev, a, c, ba, 0);
 }
 
 // pose of the coming step and its bead records, one workgroup per body
@@ -703,9 +737,9 @@ void launch_observe(const StepArgs<Real>& a, bool masked, int32_t tile0, int32_t
 
 // explicit instantiations
 template void launch_couple<float>(const StepArgs<float>&, const CoupleArgs&, hipStream_t,
-                                   const LaunchEvents&);
+                                   const LaunchEvents&, const BodyArgs*);
 template void launch_couple<double>(const StepArgs<double>&, const CoupleArgs&, hipStream_t,
-                                    const LaunchEvents&);
+                                    const LaunchEvents&, const BodyArgs*);
 template void launch_node_step<float>(const StepArgs<float>&, bool, bool, const BodyArgs*,
                                       hipStream_t, const LaunchEvents&);
 template void launch_node_step<double>(const StepArgs<double>&, bool, bool, const BodyArgs*,

@@ -134,12 +134,17 @@ struct LaunchEvents {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 
+struct BodyArgs;
+// the bead coupling of one MD step; with wca (bodies with excluded volume and wca_ft set) the
+// same launch also writes every body's WCA force and torque for that MD step
 template <typename Real>
 void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s,
-                   const LaunchEvents& ev = LaunchEvents{});
+                   const LaunchEvents& ev = LaunchEvents{}, const BodyArgs* wca = nullptr);
 // Excluded volume (WCA).  A body's sites are body-frame offsets sharing one radius; static
-// sites (pore beads) are lab positions with a radius each, sorted into a uniform cell grid
-// per replica whose cells are at least one interaction range wide.
+// sites (pore beads) are lab positions with a radius each.  Per replica, a coarse cell grid
+// (cells at least one interaction range wide) gives each cell one contiguous list of the
+// sites in its neighbourhood (itself and the adjacent cells), and a fine flag grid (cells at
+// most 2 wide) marks the cells from which some site may be within range.
 struct EvSite {
     double off[3];
     double pad;
@@ -150,9 +155,12 @@ struct WallSite {
 };
 struct WcaRep {
     int32_t first_body, n_bodies;   // the replica's bodies: rep_bodies[first_body ...]
-    int32_t cx, cy, cz;             // cells per axis (0: no static sites)
-    int32_t cell0;                  // first entry of the replica in cell_start / cell_near
-    double cw[3];                   // cell widths (>= the largest interaction range)
+    int32_t cx, cy, cz;             // coarse cells per axis (0: no static sites)
+    int32_t cell0;                  // first entry of the replica in nb_start
+    int32_t gx, gy, gz;             // fine cells per axis
+    int32_t fine0;                  // first entry of the replica in near
+    double cw[3];                   // coarse cell widths (>= the largest interaction range)
+    double fw[3];                   // fine cell widths (<= 2)
 };
 
 // Bodies to finish: per-bead forces/torques of the coupling in, the excluded-volume forces of
@@ -171,8 +179,9 @@ struct BodyArgs {
     const EvSite* ev;
     const WcaRep* wrep;
     const int32_t* rep_bodies;
-    const int32_t* cell_start;      // per replica cx*cy*cz + 1 entries into sites
-    const uint8_t* cell_near;       // 1 if a site lies in the cell or one of its neighbours
+    const int32_t* nb_start;        // per replica cx*cy*cz + 1 entries into nb_idx
+    const int32_t* nb_idx;          // site indices of each coarse cell's neighbourhood
+    const uint8_t* near;            // fine cells: 1 if a site may be within range
     const WallSite* sites;
 };
 // the node update of one tile group; with forces the nodes consume the spread force, with
@@ -182,10 +191,6 @@ void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const B
                       hipStream_t s, const LaunchEvents& ev = LaunchEvents{});
 // pose of the coming MD step (parity = MD step count & 1) and bead records of every body
 void launch_body_predict(const BodyArgs& b, int parity, hipStream_t s);
-// excluded-volume forces and torques of every body at the poses of MD step k of the fluid
-// step read from step_ptr + step_arg, into b.wca_ft (nothing when it is null)
-void launch_wca(const BodyArgs& b, const int64_t* step_ptr, int64_t step_arg, int k,
-                hipStream_t s);
 // finish the bodies after MD step k (< substeps - 1) of the fluid step read from
 // step_ptr + step_arg (or step_arg alone when step_ptr is null)
 void launch_body_substep(const BodyArgs& b, const int64_t* step_ptr, int64_t step_arg, int k,

@@ -87,6 +87,38 @@ def test_substeps_and_wca_parity(precision, kT, substeps):
         assert np.abs(fb_g - fb_o).max() <= tol * np.abs(fb_o).max() + 1e-17
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tight_pore_contacts_all_around(precision):
+    """A sphere on the axis of a pore barely wider than itself: inner sites all around it are
+    in range of pore beads at many angles and heights (every path of the site grids)."""
+    nx, ny, nz = 24, 24, 18
+    mask = W.pore_mask(nx, ny, nz, 2.8)
+    sites = W.pore_wall_sites(nx, ny, nz, 2.8, site_radius=1.5, spacing=1.2)
+    R = 2.5
+    shell = W.sphere_beads(R, W.sphere_bead_count(R))
+    m, I = W.solid_body_mass_inertia(1.0, R, R, R)
+    b = W.body_record(shell, m, I, (12.1, 11.8, 7.3), quat=(0.8, 0.2, 0.5, -0.1),
+                      vel=(2e-3, -1e-3, 1e-3), gamma=W.GAMMA_FREE)
+    b["ev"] = (W.inner_layer_sphere(R), W.INNER_LAYER_RADIUS)
+    wl = dict(name="tight", precision=precision, steps=20,
+              params=W.default_params(kT=4e-5, md_substeps=2, wca_epsilon=2e-3),
+              replicas=[dict(shape=(nx, ny, nz), seed=5, mask=mask, bodies=[b],
+                             wall_sites=(sites, 1.5))])
+    orc = oracle_from_workload(wl)
+    F = orc.wca_forces()[0]
+    assert np.linalg.norm(F[:3]) > 0
+    gpu = gpu_from_workload(wl)
+    gpu.set_graph_steps(0)
+    done = 0
+    for st in (1, 5, 20):
+        gpu.step(st - done)
+        orc.step(st - done)
+        done = st
+        e = compare(gpu, orc)
+        _print(f"tight {precision} step {st}", e)
+        _assert_close(e, *_tol(precision))
+
+
 def test_batched_replicas_with_different_sites():
     a = md_case("f64", 4e-5, seed=31)
     b = md_case("f64", 4e-5, seed=32, site_radius=1.2, shift=0.15)
