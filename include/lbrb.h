@@ -177,6 +177,54 @@ int rb_set_excluded_volume(lb_ctx* ctx, int32_t replica, int32_t body_id,
 int lb_add_wall_sites(lb_ctx* ctx, int32_t replica, const double* positions, int32_t n,
                       double radius);
 
+/* ---- trajectory analysis (Sec. 2.4-2.8) ----
+ * A trajectory is a device array traj[n_frames][n_bodies][7]: the centre (x, y, z; lab frame,
+ * unwrapped) and unit quaternion (w, x, y, z) of every body at every recording.  Series are
+ * device arrays stored body-major, series[n_bodies][n_frames][k].  These functions take no
+ * context: they launch on `stream` (a hipStream_t; NULL = the default stream) and return
+ * LB_OK, LB_ERR_ARG (null pointers, sizes out of range) or LB_ERR_HIP (launch failure)
+ * without synchronising.
+ *
+ * rb_record_poses: every body's centre and quaternion after the last completed step into
+ * dev_frame (n_bodies*7 doubles; bodies in the order they were added over all replicas),
+ * asynchronously on the context's stream.                                                  */
+int rb_record_poses(lb_ctx* ctx, double* dev_frame);
+
+/* Cumulative series, 0 at frame 0.  lab (k = 3): the centre minus its first position.
+ * body frame (k = 6): the body-frame displacement (Sec. 2.6: each interval's lab
+ * displacement turned into the body frame with the orientation at the start of the
+ * interval, summed) and the body-frame rotation angles about x^b, y^b, z^b (Sec. 2.7 and its
+ * SI: the body axes at t projected onto the planes normal to the axes at t-1, angles by
+ * arctan, summed).  pore frame (k = 3): the displacement rotated by minus the polar angle of
+ * the centre about the axis through (cx, cy) parallel to z at the start of each interval
+ * (x^p radial, y^p tangential, z^p axial; Sec. 2.8 and its SI), summed; radial[n_bodies]
+ * [n_frames] receives each frame's distance from that axis.                                */
+int lb_traj_lab_frame(const double* traj, int32_t n_frames, int32_t n_bodies, double* out,
+                        void* stream);
+int lb_traj_body_frame(const double* traj, int32_t n_frames, int32_t n_bodies, double* out,
+                         void* stream);
+int lb_traj_pore_frame(const double* traj, int32_t n_frames, int32_t n_bodies, double cx,
+                         double cy, double* out, double* radial, void* stream);
+
+/* Mean squared displacement over all time origins for lags 1..n_lags (< n_frames), per body
+ * and component: out[n_bodies][n_lags][k], k = 1..6 (eqs. (dt_lab), (dt_body), (dr_body)). */
+int lb_traj_msd(const double* series, int32_t n_frames, int32_t n_bodies, int32_t k,
+                  int32_t n_lags, double* out, void* stream);
+
+/* Lab-frame rotational MSD (eqs. (dr_lab), (delta_theta)): the mean over origins of
+ * arccos(p^(t) . p^(t+tau))^2 for p = R(q) ref, ref_body[n_bodies][3] (device) the body-frame
+ * vector from the centre to each body's reference bead: out[n_bodies][n_lags].             */
+int lb_traj_rotation_msd(const double* traj, int32_t n_frames, int32_t n_bodies,
+                           const double* ref_body, int32_t n_lags, double* out, void* stream);
+
+/* Radially binned MSD (Sec. 2.8): every origin frame t of every body whose radial[b][t]
+ * lies in [edges[j], edges[j+1]) (edges: device, n_bins+1 ascending) adds its squared
+ * increments over lags 1..n_lags of series (k = 1..3) to sums[n_bins][n_lags][k] and 1 to
+ * counts[n_bins][n_lags] (both overwritten).                                               */
+int lb_traj_binned_msd(const double* series, const double* radial, int32_t n_frames,
+                         int32_t n_bodies, int32_t k, const double* edges, int32_t n_bins,
+                         int32_t n_lags, double* sums, double* counts, void* stream);
+
 /* Number of bodies in a replica, and the per-bead forces (lab frame, FP64, n_beads*3, in
  * the order the beads were given) of the last step of one body, copied to host memory.   */
 int lb_body_count(const lb_ctx* ctx, int32_t replica);

@@ -18,6 +18,7 @@
 #include "../../include/lbrb.h"
 #include "lbrb_layout.h"
 #include "lbrb_walls.h"
+#include "lbrb_analysis.h"
 
 using namespace lbrb;
 
@@ -1337,6 +1338,15 @@ int lb_observables(lb_ctx* c, int32_t replica, lb_totals* out, rb_state* bodies,
     }
     if (!T.finite) return fail(c, LB_ERR_UNSTABLE, "non-finite populations");
     if (hdr.err_flags & 1u) return fail(c, LB_ERR_UNSTABLE, "spread force out of range");
+    return LB_OK;
+}
+
+int rb_record_poses(lb_ctx* c, double* dev_frame)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!dev_frame) return fail(c, LB_ERR_ARG, "missing frame buffer");
+    launch_record_poses(c->d_bodies, c->n_bodies, dev_frame, c->stream);
+    HIP_TRY(c, hipGetLastError());
     return LB_OK;
 }
 

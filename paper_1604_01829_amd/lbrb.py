@@ -28,7 +28,9 @@ LB_PRECISION_F32 = 1
 
 # every symbol declared in include/lbrb.h
 EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wall_velocity",
-            "rb_add_raspberry", "rb_set_excluded_volume", "lb_add_wall_sites",
+            "rb_add_raspberry", "rb_set_excluded_volume", "lb_add_wall_sites", "rb_record_poses",
+            "lb_traj_lab_frame", "lb_traj_body_frame", "lb_traj_pore_frame",
+            "lb_traj_msd", "lb_traj_rotation_msd", "lb_traj_binned_msd",
             "lb_rb_step", "lb_observables", "lb_body_count", "rb_bead_forces",
             "lb_export_populations", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
             "lb_set_timing", "lb_kernel_times", "lb_adjoint_workspace_bytes", "lb_rb_adjoint",
@@ -91,6 +93,21 @@ def library():
                                          ctypes.c_double]
     L.lb_add_wall_sites.restype = ctypes.c_int
     L.lb_add_wall_sites.argtypes = [_VP, ctypes.c_int32, _D, ctypes.c_int32, ctypes.c_double]
+    L.rb_record_poses.restype = ctypes.c_int
+    L.rb_record_poses.argtypes = [_VP, _VP]
+    i32 = ctypes.c_int32
+    for name in ("lb_traj_lab_frame", "lb_traj_body_frame"):
+        getattr(L, name).restype = ctypes.c_int
+        getattr(L, name).argtypes = [_VP, i32, i32, _VP, _VP]
+    L.lb_traj_pore_frame.restype = ctypes.c_int
+    L.lb_traj_pore_frame.argtypes = [_VP, i32, i32, ctypes.c_double, ctypes.c_double, _VP, _VP,
+                                       _VP]
+    L.lb_traj_msd.restype = ctypes.c_int
+    L.lb_traj_msd.argtypes = [_VP, i32, i32, i32, i32, _VP, _VP]
+    L.lb_traj_rotation_msd.restype = ctypes.c_int
+    L.lb_traj_rotation_msd.argtypes = [_VP, i32, i32, _VP, i32, _VP, _VP]
+    L.lb_traj_binned_msd.restype = ctypes.c_int
+    L.lb_traj_binned_msd.argtypes = [_VP, _VP, i32, i32, i32, _VP, i32, i32, _VP, _VP, _VP]
     L.rb_add_raspberry.restype = ctypes.c_int
     L.rb_add_raspberry.argtypes = [_VP, ctypes.c_int32, _D, ctypes.c_int32, ctypes.c_double, _D,
                                    _D, _D, _D, _D, ctypes.c_double, ctypes.c_int32,

@@ -363,3 +363,33 @@ def confined_md_workload(scale=1.0, substeps=2, eps=None):
     wl["name"] = (f"{wl['name']}; {substeps} MD steps per fluid step, WCA inner layers and "
                   "pore beads")
     return wl
+
+
+# ------------------------------------------------------------------ trajectories
+
+def synthetic_trajectory(n_frames, n_bodies, seed, step=0.05, rot_step=0.03, centre=None,
+                         radius=(2.0, 8.0), z0=0.0):
+    """Seeded poses [n_frames, n_bodies, 7] (centre x, y, z; quaternion w, x, y, z) for the
+    trajectory analysis: centres take Gaussian steps of standard deviation `step` per axis,
+    starting at random radii in `radius` around `centre` (x, y) when given; orientations start
+    random and are turned each frame by a rotation about a Gaussian body-frame vector of
+    standard deviation `rot_step` per component."""
+    from scipy.spatial.transform import Rotation as Rot
+    rng = np.random.default_rng(seed)
+    traj = np.zeros((n_frames, n_bodies, 7))
+    for b in range(n_bodies):
+        if centre is None:
+            p = rng.uniform(0.0, 20.0, size=3)
+        else:
+            r, th = rng.uniform(*radius), rng.uniform(0.0, 2.0 * math.pi)
+            p = np.array([centre[0] + r * math.cos(th), centre[1] + r * math.sin(th), z0])
+        steps = rng.normal(0.0, step, size=(n_frames, 3))
+        steps[0] = 0.0
+        traj[:, b, :3] = p + np.cumsum(steps, axis=0)
+        rot = Rot.from_quat(rng.normal(size=4))
+        incs = Rot.from_rotvec(rng.normal(0.0, rot_step, size=(n_frames, 3)))
+        for f in range(n_frames):
+            q = rot.as_quat()
+            traj[f, b, 3:] = (q[3], q[0], q[1], q[2])
+            rot = rot * incs[f]
+    return traj

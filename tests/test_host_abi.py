@@ -71,6 +71,13 @@ def test_workspace_bytes_and_argument_checks():
     assert L.lb_rb_step(None, 1) == lbrb.LB_ERR_ARG
     u = (ctypes.c_double * 3)(0.0, 0.0, 0.01)
     assert L.lb_set_wall_velocity(None, 0, 1, u) == lbrb.LB_ERR_ARG
+    assert L.rb_record_poses(None, None) == lbrb.LB_ERR_ARG
+    # the trajectory analysis checks its arguments before any launch
+    assert L.lb_traj_msd(None, 10, 1, 3, 2, None, None) == lbrb.LB_ERR_ARG
+    assert L.lb_traj_body_frame(None, 10, 1, None, None) == lbrb.LB_ERR_ARG
+    assert L.lb_traj_pore_frame(None, 10, 1, 0.0, 0.0, None, None, None) == lbrb.LB_ERR_ARG
+    assert L.lb_traj_rotation_msd(None, 10, 1, None, 2, None, None) == lbrb.LB_ERR_ARG
+    assert L.lb_traj_binned_msd(None, None, 10, 1, 3, None, 1, 2, None, None, None) == lbrb.LB_ERR_ARG
     assert L.lb_adjoint_workspace_bytes(None, 10, 2) == 0
     assert L.lb_last_error(None) == b"null context"
 
@@ -144,3 +151,17 @@ def test_workloads_are_seeded(k):
         assert ra["seed"] == rb["seed"]
         for ba, bb in zip(ra["bodies"], rb["bodies"]):
             assert np.array_equal(ba["offsets"], bb["offsets"]) and np.array_equal(ba["pos"], bb["pos"])
+
+
+def test_analysis_fits_match_the_oracle():
+    from oracle import analysis as OA
+    from paper_1604_01829_amd import analysis as GA
+    rng = np.random.default_rng(5)
+    t = np.arange(1, 26) * 200.0
+    m = 6 * 3e-4 * t + rng.normal(0, 1e-3, t.size)
+    assert abs(GA.diffusivity(t, m, 6) - OA.diffusivity(t, m, 6)) < 1e-15
+    L = np.array([27.0, 32, 38, 48, 55, 64, 76, 94])
+    d = 0.02 - 0.3 / L + rng.normal(0, 1e-5, L.size)
+    g, o = GA.hasimoto_intercept(L, d), OA.hasimoto_d0(L, d)
+    assert abs(g[0] - o[0]) < 1e-15 and abs(g[1] - o[1]) < 1e-12
+    assert GA.einstein(4e-5, g[0]) == OA.einstein_resistance(4e-5, g[0])
