@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["orc_lattice.c", "orc_philox.c", "orc_lbrb.c", "orc_adjoint.c"]
+SOURCES = ["orc_lattice.c", "orc_philox.c", "orc_lbrb.c", "orc_adjoint.c", "orc_relax.c"]
 LIB = os.path.join(HERE, "liborc.so")
 
 

@@ -134,6 +134,28 @@ int      orc_body_state(const orc_sim* s, int body, double out[19]);
 int      orc_bead_forces(const orc_sim* s, int body, double* out);
 int      orc_num_threads(void);
 
+/* ---- raspberry construction (orc_relax.c; Sec. 2.1 and its SI) ---- */
+typedef struct {
+    double k_surface;     /* harmonic restraint U = k |r - r_s|^2 to the closest surface point */
+    double sigma;         /* WCA size between beads (the paper: 1.4)                          */
+    double epsilon;       /* WCA energy (the paper: 0.1)                                      */
+    double damping;       /* friction rate eta (the paper: 1000)                              */
+    double dt;            /* time step (the paper: 0.001)                                     */
+    double mass;          /* bead mass                                                        */
+} orc_relax_params;
+/* Closest point rs on the ellipsoid with semi-axes axes[3] (along x, y, z) to the point x:
+ * the root t of F(t) = sum (x a / (t + a^2))^2 - 1 on (-min a^2, inf) by bisection to the
+ * last representable midpoint, rs = x a^2 / (t + a^2).  Returns t.                          */
+double   orc_closest_point(const double axes[3], const double x[3], double rs[3]);
+/* n_steps damped leapfrog steps of n beads (pos, vel: n*3, in/out; vel is the velocity at
+ * the half step before): forces = WCA between all pairs + the surface restraint.
+ * 0 ok, -1 error.                                                                           */
+int      orc_relax_shell(const double axes[3], int n, double* pos, double* vel,
+                         const orc_relax_params* p, int n_steps);
+/* WCA energy of all pairs plus the restraint energy of every bead                           */
+double   orc_shell_energy(const double axes[3], int n, const double* pos,
+                          const orc_relax_params* p);
+
 /* ---- reverse-mode derivative (orc_adjoint.c) ---- */
 /* vector-Jacobian product of orc_collide_node (deterministic): given the adjoint lam_out of
  * the post-collision populations, the adjoints of f_in and of the force density F.        */

@@ -32,6 +32,38 @@ class OrcParams(ctypes.Structure):
     ]
 
 
+class RelaxParams(ctypes.Structure):
+    _fields_ = [("k_surface", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("epsilon", ctypes.c_double), ("damping", ctypes.c_double),
+                ("dt", ctypes.c_double), ("mass", ctypes.c_double)]
+
+
+def relax_params(k_surface=10.0, sigma=1.4, epsilon=0.1, damping=1000.0, dt=0.001, mass=1.0):
+    return RelaxParams(k_surface, sigma, epsilon, damping, dt, mass)
+
+
+def closest_point(axes, x):
+    """(rs, t): closest point on the ellipsoid with semi-axes `axes` to the point x."""
+    rs = np.zeros(3)
+    t = lib().orc_closest_point(_dp(_vec(axes, 3)), _dp(_vec(x, 3)), _dp(rs))
+    return rs, t
+
+
+def relax_shell(axes, pos, vel, params, n_steps):
+    """Advance a bead shell n_steps (copies in, returns (pos, vel))."""
+    p = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3)).copy()
+    v = np.ascontiguousarray(np.asarray(vel, dtype=np.float64).reshape(-1, 3)).copy()
+    if lib().orc_relax_shell(_dp(_vec(axes, 3)), p.shape[0], _dp(p), _dp(v),
+                             ctypes.byref(params), int(n_steps)) != 0:
+        raise RuntimeError("orc_relax_shell failed")
+    return p, v
+
+
+def shell_energy(axes, pos, params):
+    p = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+    return lib().orc_shell_energy(_dp(_vec(axes, 3)), p.shape[0], _dp(p), ctypes.byref(params))
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -99,6 +131,13 @@ def lib():
         L.orc_bead_forces.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_closest_point.restype = ctypes.c_double
+        L.orc_closest_point.argtypes = [_D, _D, _D]
+        L.orc_relax_shell.restype = ctypes.c_int
+        L.orc_relax_shell.argtypes = [_D, ctypes.c_int, _D, _D, ctypes.POINTER(RelaxParams),
+                                      ctypes.c_int]
+        L.orc_shell_energy.restype = ctypes.c_double
+        L.orc_shell_energy.argtypes = [_D, ctypes.c_int, _D, ctypes.POINTER(RelaxParams)]
         L.orc_collide_vjp.restype = None
         L.orc_collide_vjp.argtypes = [ctypes.POINTER(OrcParams), _D, _D, _D, _D, _D]
         L.orc_adjoint.restype = ctypes.c_int
