@@ -225,6 +225,31 @@ int lb_traj_binned_msd(const double* series, const double* radial, int32_t n_fra
                          int32_t n_bodies, int32_t k, const double* edges, int32_t n_bins,
                          int32_t n_lags, double* sums, double* counts, void* stream);
 
+/* ---- raspberry construction (Sec. 2.1 and its SI "Details for ellipsoidal raspberry
+ * construction") ----
+ * rb_relax_shells: n_steps of damped MD for n_shells bead shells at once.  Within a shell the
+ * beads repel with the WCA pair potential (sigma, epsilon; cut at 2^(1/6) sigma) and each is
+ * held to the closest point r_s of its shell's ellipsoid (semi-axes axes[s][0..2] along the
+ * body x, y, z) by U = k_surface |r - r_s|^2; r_s = x a^2 / (t + a^2) per axis with t the
+ * root of F(t) = sum (x a / (t + a^2))^2 - 1 on (-min a^2, inf), found by bisection.
+ * Integration: v <- ((1 - g) v + dt F / mass) / (1 + g), g = damping dt / 2, then
+ * r <- r + dt v (the paper's script: leapfrog, damping 1000, dt 0.001, sigma 1.4,
+ * epsilon 0.1).  axes (n_shells*3) and counts (n_shells, each 1..2048) are host arrays; the
+ * shells' beads are packed one after another in the device arrays dev_pos and dev_vel
+ * ([total beads][3], body frame, in/out; dev_vel holds the velocities of the half step
+ * before, zeros to start).  Asynchronous on `stream`; LB_ERR_ARG for bad arguments.        */
+typedef struct {
+    double k_surface;   /* restraint stiffness k                                           */
+    double sigma;       /* WCA size                                                         */
+    double epsilon;     /* WCA energy                                                       */
+    double damping;     /* friction rate                                                    */
+    double dt;          /* time step                                                        */
+    double mass;        /* bead mass                                                        */
+} rb_relax_params;
+int rb_relax_shells(int32_t n_shells, const double* axes, const int32_t* counts,
+                    double* dev_pos, double* dev_vel, const rb_relax_params* params,
+                    int32_t n_steps, void* stream);
+
 /* Number of bodies in a replica, and the per-bead forces (lab frame, FP64, n_beads*3, in
  * the order the beads were given) of the last step of one body, copied to host memory.   */
 int lb_body_count(const lb_ctx* ctx, int32_t replica);

@@ -1,0 +1,182 @@
+// lbrb_construct.hip -- raspberry construction by constrained relaxation (rb_relax_shells).
+//
+// Sec. 2.1 and its SI: the beads of a shell are spread evenly over an ellipsoid
+// x^2/a^2 + y^2/b^2 + z^2/c^2 = 1 by damped MD under a WCA repulsion between beads and a
+// harmonic restraint U = k |r - r_s|^2 towards the closest surface point r_s.  From the
+// normal condition r - r_s = (t/2) grad S(r_s), x_s = x a^2 / (t + a^2) per axis, and the
+// surface equation becomes F(t) = sum (x a / (t + a^2))^2 - 1 = 0, decreasing in t on
+// (-min a^2, inf), solved by bisection.
+//
+// One workgroup per shell: the shell's positions live in LDS for the whole launch, each thread
+// owns up to kPer beads (their velocities in registers), and a step is "forces from the LDS
+// positions, barrier, kick and drift, barrier" -- no grid-wide synchronisation.  Up to
+// kShellsPerLaunch shells go in one launch as a by-value argument.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "../../include/lbrb.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxBeads = 2048;                 // per shell (48 KB of LDS)
+constexpr int kPer = kMaxBeads / kBlock;        // beads per thread
+constexpr int kShellsPerLaunch = 64;
+
+struct Shell {
+    double axes[3];
+    int32_t first, count;
+};
+struct ShellBatch {
+    Shell s[kShellsPerLaunch];
+};
+struct RelaxArgs {
+    double k2;          // 2 k
+    double s2, rc2;     // sigma^2, (2^(1/6) sigma)^2
+    double eps24;       // 24 eps
+    double dt, m;
+    double g;           // eta dt / 2
+};
+
+// closest point of the ellipsoid (semi-axes a, squares a2) to x: bisection of F(t) on
+// (-min a^2, max a |x| + 1] down to the last representable midpoint
+__device__ void closest(const double a[3], const double a2[3], double amin2, double amax,
+                        const double x[3], double rs[3])
+{
+    double lo = -amin2;
+    double hi = amax * sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) + 1.0;
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double f = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double v = x[k] * a[k] / (mid + a2[k]);
+            f += v * v;
+        }
+        if (f - 1.0 > 0.0) lo = mid;
+        else hi = mid;
+    }
+    const double t = 0.5 * (lo + hi);
+    for (int k = 0; k < 3; ++k) rs[k] = x[k] * a2[k] / (t + a2[k]);
+}
+
+__global__ __launch_bounds__(kBlock) void relax_kernel(const ShellBatch B, double* pos,
+                                                       double* vel, const RelaxArgs p,
+                                                       int n_steps)
+{
+    __shared__ double X[kMaxBeads][3];
+    const Shell S = B.s[blockIdx.x];
+    const int n = S.count;
+    double a[3], a2[3], amin2 = INFINITY, amax = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        a[k] = S.axes[k];
+        a2[k] = a[k] * a[k];
+        amin2 = fmin(amin2, a2[k]);
+        amax = fmax(amax, a[k]);
+    }
+    double* P = pos + 3 * (int64_t)S.first;
+    double* V = vel + 3 * (int64_t)S.first;
+    double v[kPer][3];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + q * kBlock;
+        for (int k = 0; k < 3; ++k) {
+            v[q][k] = i < n ? V[3 * i + k] : 0.0;
+            if (i < n) X[i][k] = P[3 * i + k];
+        }
+    }
+    __syncthreads();
+    for (int step = 0; step < n_steps; ++step) {
+        double f[kPer][3];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int i = threadIdx.x + q * kBlock;
+            f[q][0] = f[q][1] = f[q][2] = 0.0;
+            if (i >= n) continue;
+            const double xi[3] = {X[i][0], X[i][1], X[i][2]};
+            for (int j = 0; j < n; ++j) {
+                if (j == i) continue;
+                const double d[3] = {xi[0] - X[j][0], xi[1] - X[j][1], xi[2] - X[j][2]};
+                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (!(r2 < p.rc2)) continue;
+                const double u = p.s2 / r2, u6 = u * u * u;
+                const double coef = p.eps24 * (2.0 * u6 * u6 - u6) / r2;
+                for (int k = 0; k < 3; ++k) f[q][k] += coef * d[k];
+            }
+            double rs[3];
+            closest(a, a2, amin2, amax, xi, rs);
+            for (int k = 0; k < 3; ++k) f[q][k] -= p.k2 * (xi[k] - rs[k]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int i = threadIdx.x + q * kBlock;
+            if (i >= n) continue;
+            for (int k = 0; k < 3; ++k) {
+                v[q][k] = ((1.0 - p.g) * v[q][k] + p.dt * f[q][k] / p.m) / (1.0 + p.g);
+                X[i][k] += p.dt * v[q][k];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + q * kBlock;
+        if (i >= n) continue;
+        for (int k = 0; k < 3; ++k) {
+            P[3 * i + k] = X[i][k];
+            V[3 * i + k] = v[q][k];
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int rb_relax_shells(int32_t n_shells, const double* axes, const int32_t* counts,
+                               double* dev_pos, double* dev_vel, const rb_relax_params* prm,
+                               int32_t n_steps, void* stream)
+{
+    if (n_shells < 1 || !axes || !counts || !dev_pos || !dev_vel || !prm || n_steps < 0)
+        return LB_ERR_ARG;
+    const rb_relax_params& q = *prm;
+    if (!(q.dt > 0.0) || !(q.mass > 0.0) || !(q.sigma > 0.0) || !(q.epsilon >= 0.0) ||
+        !(q.k_surface >= 0.0) || !(q.damping >= 0.0) || !std::isfinite(q.dt) ||
+        !std::isfinite(q.mass) || !std::isfinite(q.sigma) || !std::isfinite(q.epsilon) ||
+        !std::isfinite(q.k_surface) || !std::isfinite(q.damping))
+        return LB_ERR_ARG;
+    for (int32_t s = 0; s < n_shells; ++s) {
+        if (counts[s] < 1 || counts[s] > kMaxBeads) return LB_ERR_ARG;
+        for (int k = 0; k < 3; ++k)
+            if (!(axes[3 * s + k] > 0.0) || !std::isfinite(axes[3 * s + k])) return LB_ERR_ARG;
+    }
+    RelaxArgs p{};
+    p.k2 = 2.0 * q.k_surface;
+    p.s2 = q.sigma * q.sigma;
+    p.rc2 = std::pow(2.0, 1.0 / 3.0) * q.sigma * q.sigma;
+    p.eps24 = 24.0 * q.epsilon;
+    p.dt = q.dt;
+    p.m = q.mass;
+    p.g = 0.5 * q.damping * q.dt;
+    int64_t first = 0;
+    for (int32_t s0 = 0; s0 < n_shells; s0 += kShellsPerLaunch) {
+        ShellBatch B{};
+        const int nb = std::min<int32_t>(kShellsPerLaunch, n_shells - s0);
+        for (int k = 0; k < nb; ++k) {
+            Shell& S = B.s[k];
+            for (int a = 0; a < 3; ++a) S.axes[a] = axes[3 * (s0 + k) + a];
+            S.first = (int32_t)first;
+            S.count = counts[s0 + k];
+            first += counts[s0 + k];
+        }
+        if (first > INT32_MAX) return LB_ERR_ARG;
+        if (n_steps > 0)
+            hipLaunchKernelGGL(relax_kernel, dim3(nb), dim3(kBlock), 0, (hipStream_t)stream, B,
+                               dev_pos, dev_vel, p, n_steps);
+        if (hipGetLastError() != hipSuccess) return LB_ERR_HIP;
+    }
+    return LB_OK;
+}

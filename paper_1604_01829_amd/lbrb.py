@@ -30,7 +30,7 @@ LB_PRECISION_F32 = 1
 EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wall_velocity",
             "rb_add_raspberry", "rb_set_excluded_volume", "lb_add_wall_sites", "rb_record_poses",
             "lb_traj_lab_frame", "lb_traj_body_frame", "lb_traj_pore_frame",
-            "lb_traj_msd", "lb_traj_rotation_msd", "lb_traj_binned_msd",
+            "lb_traj_msd", "lb_traj_rotation_msd", "lb_traj_binned_msd", "rb_relax_shells",
             "lb_rb_step", "lb_observables", "lb_body_count", "rb_bead_forces",
             "lb_export_populations", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
             "lb_set_timing", "lb_kernel_times", "lb_adjoint_workspace_bytes", "lb_rb_adjoint",
@@ -51,6 +51,12 @@ class lb_params(ctypes.Structure):
                 ("max_beads", ctypes.c_int32), ("max_wall_links", ctypes.c_int32),
                 ("md_substeps", ctypes.c_int32), ("wca_epsilon", ctypes.c_double),
                 ("max_ev_sites", ctypes.c_int32), ("max_wall_sites", ctypes.c_int32)]
+
+
+class rb_relax_params(ctypes.Structure):
+    _fields_ = [("k_surface", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("epsilon", ctypes.c_double), ("damping", ctypes.c_double),
+                ("dt", ctypes.c_double), ("mass", ctypes.c_double)]
 
 
 class lb_totals(ctypes.Structure):
@@ -108,6 +114,9 @@ def library():
     L.lb_traj_rotation_msd.argtypes = [_VP, i32, i32, _VP, i32, _VP, _VP]
     L.lb_traj_binned_msd.restype = ctypes.c_int
     L.lb_traj_binned_msd.argtypes = [_VP, _VP, i32, i32, i32, _VP, i32, i32, _VP, _VP, _VP]
+    L.rb_relax_shells.restype = ctypes.c_int
+    L.rb_relax_shells.argtypes = [ctypes.c_int32, _D, ctypes.POINTER(ctypes.c_int32), _VP, _VP,
+                                  ctypes.POINTER(rb_relax_params), ctypes.c_int32, _VP]
     L.rb_add_raspberry.restype = ctypes.c_int
     L.rb_add_raspberry.argtypes = [_VP, ctypes.c_int32, _D, ctypes.c_int32, ctypes.c_double, _D,
                                    _D, _D, _D, _D, ctypes.c_double, ctypes.c_int32,

@@ -72,6 +72,15 @@ def test_workspace_bytes_and_argument_checks():
     u = (ctypes.c_double * 3)(0.0, 0.0, 0.01)
     assert L.lb_set_wall_velocity(None, 0, 1, u) == lbrb.LB_ERR_ARG
     assert L.rb_record_poses(None, None) == lbrb.LB_ERR_ARG
+    # construction: host arrays are checked before any launch
+    prm = lbrb.rb_relax_params(10.0, 1.4, 0.1, 10.0, 0.01, 1.0)
+    axes = np.array([3.0, 2.0, 1.0])
+    dummy = ctypes.c_void_p(256)
+    for cnt, ax, p in ((0, axes, prm), (2049, axes, prm), (10, np.array([3.0, 0.0, 1.0]), prm),
+                       (10, axes, lbrb.rb_relax_params(10.0, 1.4, 0.1, 10.0, 0.0, 1.0))):
+        c = (ctypes.c_int32 * 1)(cnt)
+        assert L.rb_relax_shells(1, ax.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), c,
+                                 dummy, dummy, ctypes.byref(p), 10, None) == lbrb.LB_ERR_ARG
     # the trajectory analysis checks its arguments before any launch
     assert L.lb_traj_msd(None, 10, 1, 3, 2, None, None) == lbrb.LB_ERR_ARG
     assert L.lb_traj_body_frame(None, 10, 1, None, None) == lbrb.LB_ERR_ARG
