@@ -214,6 +214,26 @@ def compare_runs(args):
         "mlups": round(m["mlups"], 1), "ms_per_step": round(m["ms_per_step"], 5),
         "node_step_us": round(m["node_us"], 2), "couple_us": round(m["couple_us"], 2),
         "finite": m["finite"]}
+    # raspberry construction: the paper's 15 ellipsoids of revolution (volume of a radius-4.25
+    # sphere, aspect ratios 1/10 .. 10), outer and inner shells relaxed together, 20,000 steps
+    from paper_1604_01829_amd import construction as CN
+    phis = [1 / 10, 1 / 5, 1 / 4, 1 / 3, 1 / 2, 2 / 3, 4 / 5, 9 / 10, 10 / 9, 5 / 4, 3 / 2, 2, 4, 5, 10]
+    axes, init = [], []
+    for k, phi in enumerate(phis):
+        bb = (4.25 ** 3 / phi) ** (1 / 3)
+        for d in (0.0, 0.5):
+            ax = (phi * bb - d, bb - d, bb - d)
+            axes.append(ax)
+            init.append(CN.separated_shell(*ax, CN.shell_count(*ax), seed=k))
+    CN.relax_shells(axes, init, n_steps=10)              # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    CN.relax_shells(axes, init, n_steps=20000)
+    torch.cuda.synchronize()
+    t_c = time.perf_counter() - t0
+    out["construction"] = {"shells": len(axes), "beads": int(sum(len(p) for p in init)),
+                           "steps": 20000, "seconds": round(t_c, 3),
+                           "us_per_step": round(t_c / 20000 * 1e6, 2)}
     # reverse pass on the fixed sphere in uniform flow
     wl5 = W.workload(5)
     wl5["params"]["kT"] = 0.0

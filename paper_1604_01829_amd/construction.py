@@ -67,29 +67,36 @@ def initial_shell(a, b, c, n, seed=0, jitter=0.1):
     return pts + rng.uniform(-jitter, jitter, size=pts.shape)
 
 
-def separated_shell(a, b, c, n, seed=0, min_frac=0.75, max_tries=200000):
+def separated_shell(a, b, c, n, seed=0, min_frac=0.75, tries=50000):
     """n points on the ellipsoid placed one by one at area-uniform random positions, each kept
     only if it is at least min_frac times the mean spacing sqrt(area / n) from every point
-    already placed (random sequential addition): a start without close pairs."""
+    already placed (random sequential addition): a start without close pairs.  When a pass
+    cannot place them all (thin shells: the faces of a flat ellipsoid are close), the next
+    pass asks for 10 % less separation."""
     rng = np.random.default_rng(seed)
     ax = np.array([a, b, c], dtype=np.float64)
-    dmin = min_frac * math.sqrt(W.ellipsoid_area(a, b, c) / n)
-    # area element of the map u -> ax * u from the unit sphere, and its largest value
-    amax = max(a * b, b * c, a * c)
-    pts = []
-    for _ in range(max_tries):
-        u = rng.normal(size=3)
-        u /= np.linalg.norm(u)
-        dA = math.sqrt((b * c * u[0]) ** 2 + (a * c * u[1]) ** 2 + (a * b * u[2]) ** 2)
-        if rng.uniform() * amax > dA:
-            continue
-        p = ax * u
-        if pts and np.min(np.linalg.norm(np.asarray(pts) - p, axis=1)) < dmin:
-            continue
-        pts.append(p)
-        if len(pts) == n:
-            return np.asarray(pts)
-    raise RuntimeError("could not place the beads apart; lower min_frac")
+    spacing = math.sqrt(W.ellipsoid_area(a, b, c) / n)
+    amax = max(a * b, b * c, a * c)      # largest area element of the map from the unit sphere
+    frac = min_frac
+    for _ in range(20):
+        dmin = frac * spacing
+        pts = np.zeros((n, 3))
+        m = 0
+        for _ in range(tries):
+            u = rng.normal(size=3)
+            u /= np.linalg.norm(u)
+            dA = math.sqrt((b * c * u[0]) ** 2 + (a * c * u[1]) ** 2 + (a * b * u[2]) ** 2)
+            if rng.uniform() * amax > dA:
+                continue
+            p = ax * u
+            if m and np.min(np.linalg.norm(pts[:m] - p, axis=1)) < dmin:
+                continue
+            pts[m] = p
+            m += 1
+            if m == n:
+                return pts
+        frac *= 0.9
+    raise RuntimeError("could not place the beads")
 
 
 def shell_count(a, b, c, density=1.0):

@@ -7,10 +7,11 @@
 // surface equation becomes F(t) = sum (x a / (t + a^2))^2 - 1 = 0, decreasing in t on
 // (-min a^2, inf), solved by bisection.
 //
-// One workgroup per shell: the shell's positions live in LDS for the whole launch, each thread
-// owns up to kPer beads (their velocities in registers), and a step is "forces from the LDS
-// positions, barrier, kick and drift, barrier" -- no grid-wide synchronisation.  Up to
-// kShellsPerLaunch shells go in one launch as a by-value argument.
+// One workgroup of 1024 threads per shell: the shell's positions live in LDS for the whole
+// launch, each thread owns up to kPer beads (their velocities in registers), and a step is
+// "forces from the LDS positions, barrier, kick and drift, barrier" -- no grid-wide
+// synchronisation.  Sixteen wavefronts per shell keep the LDS reads of the pair loop in
+// flight.  Up to kShellsPerLaunch shells go in one launch as a by-value argument.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -22,7 +23,7 @@
 
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 1024;
 constexpr int kMaxBeads = 2048;                 // per shell (48 KB of LDS)
 constexpr int kPer = kMaxBeads / kBlock;        // beads per thread
 constexpr int kShellsPerLaunch = 64;
@@ -103,8 +104,9 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const ShellBatch B, doubl
                 const double d[3] = {xi[0] - X[j][0], xi[1] - X[j][1], xi[2] - X[j][2]};
                 const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
                 if (!(r2 < p.rc2)) continue;
-                const double u = p.s2 / r2, u6 = u * u * u;
-                const double coef = p.eps24 * (2.0 * u6 * u6 - u6) / r2;
+                const double ir2 = 1.0 / r2;
+                const double u = p.s2 * ir2, u6 = u * u * u;
+                const double coef = p.eps24 * (2.0 * u6 * u6 - u6) * ir2;
                 for (int k = 0; k < 3; ++k) f[q][k] += coef * d[k];
             }
             double rs[3];
