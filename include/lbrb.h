@@ -278,6 +278,16 @@ int lb_set_timing(lb_ctx* ctx, int32_t enable);
 int lb_kernel_times(lb_ctx* ctx, double* node_ms, int64_t* node_launches, double* couple_ms,
                     int64_t* couple_launches);
 
+/* How the node update stores the populations.  LB_STORES_STREAMING: non-temporal stores,
+ * which bypass the caches -- faster (3-5 % on MI355X) once the two population buffers are far
+ * larger than the 256 MB Infinity Cache, much slower (about 25 %) when they fit in it.
+ * LB_STORES_CACHED: ordinary stores.  LB_STORES_AUTO (default): streaming when the two
+ * buffers together exceed 256 MiB.                                                         */
+#define LB_STORES_AUTO 0
+#define LB_STORES_CACHED 1
+#define LB_STORES_STREAMING 2
+int lb_set_store_policy(lb_ctx* ctx, int32_t policy);
+
 /* Reverse-mode derivative of a window of steps (not in the paper: the hand adjoint of the
  * coupled update of Sec. 1.1-1.2 -- streaming with bounce-back, the mode-space collision
  * with its force source, the frictional coupling of eq. (latticeboltzmannfriction) with its

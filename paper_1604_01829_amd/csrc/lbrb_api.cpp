@@ -25,6 +25,8 @@ using namespace lbrb;
 namespace {
 
 constexpr size_t kAlign = 256;
+// MI355X's Infinity Cache: population buffers beyond it are stored with non-temporal stores
+constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
 constexpr uint64_t kStateMagic = 0x4C42524253544154ull;  // "LBRBSTAT"
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -199,6 +201,7 @@ struct lb_ctx {
     hipStream_t cap_stream = nullptr;
     // timing
     bool timing = false;
+    int32_t store_policy = LB_STORES_AUTO;
     std::vector<EventPair> ev_node, ev_couple_t, ev_pool;
 };
 
@@ -245,6 +248,16 @@ CollideParams<Real> collide_params(const lb_params& p)
     return cp;
 }
 
+// non-temporal population stores: forced by the policy, or (automatic) once the two
+// population buffers together exceed the Infinity Cache
+bool streaming_stores(const lb_ctx* c)
+{
+    if (c->store_policy == LB_STORES_CACHED) return false;
+    if (c->store_policy == LB_STORES_STREAMING) return true;
+    const double real = c->p.precision == LB_PRECISION_F32 ? 4.0 : 8.0;
+    return 2.0 * Q * real * (double)c->plan.N > kInfinityCacheBytes;
+}
+
 // launch arguments of one tile group pulling from src and writing dst
 template <typename Real>
 StepArgs<Real> step_args_on(const lb_ctx* c, int group, const void* src, void* dst)
@@ -260,6 +273,7 @@ StepArgs<Real> step_args_on(const lb_ctx* c, int group, const void* src, void* d
     a.n_tiles = (int32_t)c->tiles[group].size();
     a.thermal = c->p.kT > 0.0 ? 1 : 0;
     a.narrow = c->narrow[group] ? 1 : 0;
+    a.stream_stores = streaming_stores(c) ? 1 : 0;
     a.gforce = c->gforce;
     a.flags = c->flags;
     a.cp = collide_params<Real>(c->p);
@@ -1442,6 +1456,16 @@ int lb_load_state(lb_ctx* c, const void* dev_buf, size_t bytes)
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->step = (int64_t)h[1];
     c->pose_stale = true;
+    return LB_OK;
+}
+
+int lb_set_store_policy(lb_ctx* c, int32_t policy)
+{
+    if (!c) return LB_ERR_ARG;
+    if (policy != LB_STORES_AUTO && policy != LB_STORES_CACHED && policy != LB_STORES_STREAMING)
+        return fail(c, LB_ERR_ARG, "unknown store policy");
+    destroy_graphs(c);
+    c->store_policy = policy;
     return LB_OK;
 }
 

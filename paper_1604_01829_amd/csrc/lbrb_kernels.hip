@@ -36,8 +36,10 @@ void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t s, const LaunchEv
 // ------------------------------------------------------------------ node update
 
 // One fluid node: pull, add the force density (external, plus the spread force when the
-// node's flag is set and FORCES), collide with the node's noise, store.
-template <typename Real, bool MASKED, bool THERMAL, bool FORCES, bool NARROW>
+// node's flag is set and FORCES), collide with the node's noise, store (non-temporal stores
+// with NT: they bypass the caches, which pays once the population buffers are far larger than
+// the Infinity Cache and costs when they fit in it).
+template <typename Real, bool MASKED, bool THERMAL, bool FORCES, bool NARROW, bool NT>
 __device__ __forceinline__ void update_node(const StepArgs<Real>& a, const ReplicaDesc& R,
                                             int64_t local, int x, int y, int z,
                                             const RowDesc& self, int64_t step)
@@ -71,12 +73,18 @@ __device__ __forceinline__ void update_node(const StepArgs<Real>& a, const Repli
     if constexpr (NARROW) {
         char* __restrict__ rb = (char*)(a.dst + (int64_t)Q * R.base);
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            *(Real*)(rb + pop_byte32<Real>((uint32_t)i, (uint32_t)local)) = d[i];
+        for (int i = 0; i < Q; ++i) {
+            Real* p = (Real*)(rb + pop_byte32<Real>((uint32_t)i, (uint32_t)local));
+            if constexpr (NT) __builtin_nontemporal_store(d[i], p);
+            else *p = d[i];
+        }
     } else {
         Real* __restrict__ dst = a.dst;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) dst[pop_at(i, g)] = d[i];
+        for (int i = 0; i < Q; ++i) {
+            if constexpr (NT) __builtin_nontemporal_store(d[i], &dst[pop_at(i, g)]);
+            else dst[pop_at(i, g)] = d[i];
+        }
     }
 }
 
@@ -352,7 +360,7 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
 // the coupling and write only body records, which no node thread touches.
 // FP32: 72 registers give 7 wavefronts per SIMD (the FP32 paths fit without spills; FP64 is
 // left to the compiler)
-template <typename Real, bool MASKED, bool THERMAL, bool FORCES, bool NARROW>
+template <typename Real, bool MASKED, bool THERMAL, bool FORCES, bool NARROW, bool NT>
 __global__ __launch_bounds__(kNodeBlock) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 7 : 1)))
 void node_step_kernel(const StepArgs<Real> a,
                                                                const BodyArgs ba, int n_lead)
@@ -372,7 +380,7 @@ void node_step_kernel(const StepArgs<Real> a,
     int x, y, z;
     RowDesc self;
     locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
-    update_node<Real, MASKED, THERMAL, FORCES, NARROW>(a, R, local, x, y, z, self, step);
+    update_node<Real, MASKED, THERMAL, FORCES, NARROW, NT>(a, R, local, x, y, z, self, step);
 }
 
 template <typename Real, bool MASKED, bool THERMAL, bool NARROW>
@@ -383,12 +391,21 @@ void launch_node_t(const StepArgs<Real>& a, bool forces, const BodyArgs* bodies,
     if (bodies) ba = *bodies;
     const int n_lead = ba.n_bodies > 0 ? (ba.n_bodies + 7) & ~7 : 0;
     const dim3 grid(a.n_tiles + n_lead), block(kNodeBlock);
-    if (forces)
-        launch_timed(node_step_kernel<Real, MASKED, THERMAL, true, NARROW>, grid, block, s, ev, a,
-                     ba, n_lead);
-    else
-        launch_timed(node_step_kernel<Real, MASKED, THERMAL, false, NARROW>, grid, block, s, ev, a,
-                     ba, n_lead);
+    if (a.stream_stores) {
+        if (forces)
+            launch_timed(node_step_kernel<Real, MASKED, THERMAL, true, NARROW, true>, grid, block,
+                         s, ev, a, ba, n_lead);
+        else
+            launch_timed(node_step_kernel<Real, MASKED, THERMAL, false, NARROW, true>, grid, block,
+                         s, ev, a, ba, n_lead);
+    } else {
+        if (forces)
+            launch_timed(node_step_kernel<Real, MASKED, THERMAL, true, NARROW, false>, grid, block,
+                         s, ev, a, ba, n_lead);
+        else
+            launch_timed(node_step_kernel<Real, MASKED, THERMAL, false, NARROW, false>, grid, block,
+                         s, ev, a, ba, n_lead);
+    }
 }
 
 // 32-bit offsets pay in FP32 (+2 % on a pore, +1 % on a batch); FP64 keeps 64-bit indices

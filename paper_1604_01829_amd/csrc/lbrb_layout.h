@@ -85,6 +85,7 @@ struct StepArgs {
     int32_t thermal;
     int32_t narrow;         // every replica of the group spans at most 4 GiB of populations:
                             // 32-bit byte offsets from a per-replica base
+    int32_t stream_stores;  // non-temporal population stores (buffers beyond the caches)
     long long* gforce;      // fixed-point spread force, [word][axis][node] (1 or 2 words)
     uint8_t* flags;         // 1 byte per node: spread force present
     CollideParams<Real> cp;

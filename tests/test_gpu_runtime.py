@@ -206,3 +206,21 @@ def test_degenerate_boxes_with_a_body(shape, precision):
     for k in ("vel", "omega", "force", "torque"):
         assert e["body_" + k] <= tol_u * max(e["scale_" + k], 1e-14) + 1e-15, k
     assert e["body_pos"] <= tol_r * 100 and e["body_quat"] <= tol_r * 100
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_store_policy_does_not_change_results(precision):
+    """Non-temporal and ordinary population stores write the same values."""
+    wl = W.workload(1)
+    wl["params"]["kT"] = 4e-5
+    out = []
+    for policy in (lbrb.LB_STORES_CACHED, lbrb.LB_STORES_STREAMING, lbrb.LB_STORES_AUTO):
+        gpu = gpu_from_workload(wl, precision=precision)
+        gpu.set_store_policy(policy)
+        gpu.step(30)
+        out.append(gpu.populations(0))
+        gpu.close()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    with pytest.raises(lbrb.LBError):
+        gpu = gpu_from_workload(wl, precision=precision)
+        gpu.set_store_policy(7)
