@@ -281,8 +281,8 @@ int lb_kernel_times(lb_ctx* ctx, double* node_ms, int64_t* node_launches, double
 /* How the node update stores the populations.  LB_STORES_STREAMING: non-temporal stores,
  * which bypass the caches -- faster (3-5 % on MI355X) once the two population buffers are far
  * larger than the 256 MB Infinity Cache, much slower (about 25 %) when they fit in it.
- * LB_STORES_CACHED: ordinary stores.  LB_STORES_AUTO (default): streaming when the two
- * buffers together exceed 256 MiB.                                                         */
+ * LB_STORES_CACHED: ordinary stores.  LB_STORES_AUTO (default): streaming when the
+ * populations of the fluid nodes, in both buffers, exceed 256 MiB.                         */
 #define LB_STORES_AUTO 0
 #define LB_STORES_CACHED 1
 #define LB_STORES_STREAMING 2

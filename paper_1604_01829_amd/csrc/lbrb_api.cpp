@@ -248,14 +248,17 @@ CollideParams<Real> collide_params(const lb_params& p)
     return cp;
 }
 
-// non-temporal population stores: forced by the policy, or (automatic) once the two
-// population buffers together exceed the Infinity Cache
+// non-temporal population stores: forced by the policy, or (automatic) once the populations
+// the steps touch -- the fluid nodes of every replica, in both buffers -- exceed the Infinity
+// Cache
 bool streaming_stores(const lb_ctx* c)
 {
     if (c->store_policy == LB_STORES_CACHED) return false;
     if (c->store_policy == LB_STORES_STREAMING) return true;
     const double real = c->p.precision == LB_PRECISION_F32 ? 4.0 : 8.0;
-    return 2.0 * Q * real * (double)c->plan.N > kInfinityCacheBytes;
+    double nodes = 0.0;
+    for (int r = 0; r < c->n_rep; ++r) nodes += (double)pad_nodes(c->reps[r].n_fluid);
+    return 2.0 * Q * real * nodes > kInfinityCacheBytes;
 }
 
 // launch arguments of one tile group pulling from src and writing dst
