@@ -108,9 +108,14 @@ def cpu_baseline(wl, seconds):
             "sample": f"{k} steps (after 1 sizing step) of the same box, FP64, {dt:.1f} s"}
 
 
-def measure(sim, steps, warmup, timing_steps, graph_steps, precision):
-    """Timed graph-replayed steps, then an eager window with per-launch HIP events."""
+def measure(sim, steps, warmup, timing_steps, graph_steps, precision, policy=None):
+    """Timed graph-replayed steps, then an eager window with per-launch HIP events.  In the
+    overlapped step both launches update nodes (the coupling runs inside the first, the body
+    finishing inside the second); node_us is then their sum per step and couple_us is 0."""
     import torch
+    if policy is not None:
+        sim.set_step_policy(policy)
+    overlapped = sim.step_overlapped()
     n_nodes = n_fluid = 0
     for r in range(len(sim.shapes)):
         a, b = sim.node_counts(r)
@@ -131,14 +136,18 @@ def measure(sim, steps, warmup, timing_steps, graph_steps, precision):
     sim.step(timing_steps)
     kt = sim.kernel_times()
     sim.set_timing(False)
-    node_s = kt["node_ms"] / max(1, kt["node_launches"]) / 1e3
-    couple_s = kt["couple_ms"] / max(1, kt["couple_launches"]) / 1e3
+    if overlapped:
+        node_s = kt["node_ms"] / timing_steps / 1e3
+        couple_s = 0.0
+    else:
+        node_s = kt["node_ms"] / max(1, kt["node_launches"]) / 1e3
+        couple_s = kt["couple_ms"] / max(1, kt["couple_launches"]) / 1e3
     bpn = algorithmic_bytes_per_node(precision)
     achieved = bpn * n_fluid / node_s / 1e9
     return {"mlups": n_fluid * steps / dt / 1e6, "all_node_mlups": n_nodes * steps / dt / 1e6,
             "ms_per_step": dt / steps * 1e3, "n_fluid": n_fluid, "n_nodes": n_nodes,
             "finite": finite, "node_us": node_s * 1e6, "couple_us": couple_s * 1e6,
-            "node_gbs": achieved, "bytes_per_launch": bpn * n_fluid}
+            "node_gbs": achieved, "bytes_per_launch": bpn * n_fluid, "overlapped": overlapped}
 
 
 def compare_runs(args):
@@ -148,6 +157,16 @@ def compare_runs(args):
     from paper_1604_01829_amd import workloads as W
 
     out = {}
+    # same pore workload, FP32, with the serial step (coupling launch, then the node update)
+    wl2 = W.workload(2)
+    sim = lbrb.simulation_from_workload(wl2, precision="f32")
+    m = measure(sim, 2000, 200, 100, 100, "f32", policy=lbrb.LB_STEP_SERIAL)
+    sim.close()
+    out["serial_step_fp32"] = {"mlups": round(m["mlups"], 1),
+                               "ms_per_step": round(m["ms_per_step"], 5),
+                               "node_step_us": round(m["node_us"], 2),
+                               "couple_us": round(m["couple_us"], 2),
+                               "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4)}
     # same pore workload, FP64 populations
     wl2 = W.workload(2)
     sim = lbrb.simulation_from_workload(wl2, precision="f64")
@@ -155,7 +174,8 @@ def compare_runs(args):
     sim.close()
     out["fp64"] = {"mlups": round(m["mlups"], 1), "ms_per_step": round(m["ms_per_step"], 5),
                    "node_step_us": round(m["node_us"], 2),
-                   "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4)}
+                   "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
+                   "overlapped": m["overlapped"]}
     # 512 uneven pore replicas in one batch, FP32
     wl4 = W.workload(4)
     sim = lbrb.simulation_from_workload(wl4, precision="f32")
@@ -166,7 +186,8 @@ def compare_runs(args):
         "mlups": round(m["mlups"], 1), "all_node_mlups": round(m["all_node_mlups"], 1),
         "ms_per_step": round(m["ms_per_step"], 5), "node_step_us": round(m["node_us"], 2),
         "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
-        "couple_us": round(m["couple_us"], 2), "finite": m["finite"]}
+        "couple_us": round(m["couple_us"], 2), "finite": m["finite"],
+        "overlapped": m["overlapped"]}
     del sim
     torch.cuda.empty_cache()
     # the plain path: a sample of the same replicas, one FP64 context at a time
@@ -200,6 +221,7 @@ def compare_runs(args):
                                  "node_step_us": round(m["node_us"], 2),
                                  "node_step_gbs": round(m["node_gbs"], 1),
                                  "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
+                                 "overlapped": m["overlapped"],
                                  "traffic": traffic_from_profiles(f"node_step_{prec}_box256")}
     # the paper's integration scheme on the same pore: 2 MD steps per fluid step, inner
     # excluded-volume layers on the spheres and WCA pore beads (eps = kT)
@@ -319,7 +341,9 @@ def main():
                    "finite_after_run": m["finite"]},
         "roofline": {"bound": "hbm", "achieved": round(m["node_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profiles(tag), "kernel": "node_step",
+                     "traffic": traffic_from_profiles(tag),
+                     "kernel": ("node update of the overlapped step (overlap_free + "
+                                "overlap_forced, per step)" if m["overlapped"] else "node_step"),
                      "algorithmic_bytes_per_launch": m["bytes_per_launch"],
                      "mean_launch_us": round(m["node_us"], 3),
                      "couple_mean_launch_us": round(m["couple_us"], 3)},

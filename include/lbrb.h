@@ -288,6 +288,23 @@ int lb_kernel_times(lb_ctx* ctx, double* node_ms, int64_t* node_launches, double
 #define LB_STORES_STREAMING 2
 int lb_set_store_policy(lb_ctx* ctx, int32_t policy);
 
+/* How a fluid step is launched.  LB_STEP_SERIAL: the bead coupling, then the node update of
+ * every tile (whose leading workgroups finish the bodies).  LB_STEP_OVERLAP: two launches
+ * that hide the coupling -- (1) the coupling together with the node update of the tiles
+ * that receive no spread force in this step, (2) the body finishing together with the node
+ * update of the remaining tiles; the body finishing marks the tiles under the next step's
+ * bead stencils.  It applies to contexts whose replicas are all masked or all unmasked, with
+ * bodies, one MD step per fluid step and no excluded volume; elsewhere the serial step runs.
+ * Both give the same results bit for bit.  LB_STEP_AUTO (default): overlapped where it
+ * applies.  lb_step_overlapped sets *out to 1 if the next step will be overlapped.  With
+ * timing on, both launches of an overlapped step count as node launches and no coupling
+ * launch is counted (the coupling runs inside the first).                                 */
+#define LB_STEP_AUTO 0
+#define LB_STEP_SERIAL 1
+#define LB_STEP_OVERLAP 2
+int lb_set_step_policy(lb_ctx* ctx, int32_t policy);
+int lb_step_overlapped(lb_ctx* ctx, int32_t* out);
+
 /* Reverse-mode derivative of a window of steps (not in the paper: the hand adjoint of the
  * coupled update of Sec. 1.1-1.2 -- streaming with bounce-back, the mode-space collision
  * with its force source, the frictional coupling of eq. (latticeboltzmannfriction) with its

@@ -2,7 +2,10 @@
 
 The library holds the HIP kernels and the C-ABI of ``include/lbrb.h``.  Packed FP32
 instructions are disabled for the device code (-packed-fp32-ops); the host pass of hipcc
-warns that it does not know that feature, which is harmless.
+warns that it does not know that feature, which is harmless.  Multiply-adds are fused only
+within one source expression (-ffp-contract=on): fusion across statements, which the backend
+decides per kernel, would let the same collision code round differently in different kernels
+(the serial and the overlapped step must agree bit for bit).
 """
 import os
 import shutil
@@ -25,7 +28,7 @@ def hipcc():
 def build(verbose: bool = False, extra=()) -> str:
     out = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"),
            "-o", out] + list(extra) + SOURCES
     if verbose:

@@ -43,7 +43,8 @@ struct Plan {
     size_t off_hdr, off_reps, off_rows, off_rowinfo, off_tiles_d, off_tiles_m, off_fa, off_fb,
         off_gforce, off_flags, off_bodies, off_bead_off, off_bead_rec, off_bead_force,
         off_bead_torque, off_partials, off_links, off_ev, off_sites, off_wrep, off_rep_bodies,
-        off_nb_start, off_nb_idx, off_near, off_wca_ft, total;
+        off_nb_start, off_nb_idx, off_near, off_wca_ft, off_tmark, off_tlist, off_tcount,
+        off_tile_of, total;
 };
 
 constexpr int kMaxCellsPerAxis = 32;   // WCA coarse grid: cells per axis at most
@@ -123,6 +124,11 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
     pl.off_nb_idx = take(sizeof(int32_t) * 27 * std::max<int64_t>(pl.site_cap, 1));
     pl.off_near = take(std::max<int64_t>(pl.fine_cap, 1));
     pl.off_wca_ft = take(sizeof(double) * 6 * std::max<int64_t>(pl.body_cap, 1));
+    // overlapped step: tile marks and lists of both parities, global tile -> tile index
+    pl.off_tmark = take(sizeof(uint32_t) * 2 * pl.tiles_cap);
+    pl.off_tlist = take(sizeof(int32_t) * 2 * pl.tiles_cap);
+    pl.off_tcount = take(sizeof(int32_t) * 2);
+    pl.off_tile_of = take(sizeof(int32_t) * pl.tiles_cap);
     pl.total = o;
     return true;
 }
@@ -179,6 +185,7 @@ struct lb_ctx {
     int32_t* d_nb_idx = nullptr;
     uint8_t* d_near = nullptr;
     double* d_wca_ft = nullptr;
+    TileMarks marks{};              // overlapped step
     std::vector<EvHost> ev;         // per body
     int64_t n_ev = 0, n_sites = 0;
     bool wca_dirty = false;         // site tables to rebuild before the next step
@@ -202,6 +209,8 @@ struct lb_ctx {
     // timing
     bool timing = false;
     int32_t store_policy = LB_STORES_AUTO;
+    int32_t step_policy = LB_STEP_AUTO;
+    bool marks_valid = false;       // the tile marks describe the coming step's stencils
     std::vector<EventPair> ev_node, ev_couple_t, ev_pool;
 };
 
@@ -327,10 +336,26 @@ BodyArgs body_args(const lb_ctx* c)
     ba.nb_idx = c->d_nb_idx;
     ba.near = c->d_near;
     ba.sites = c->d_sites;
+    ba.rowinfo = c->d_rowinfo;
     return ba;
 }
 
 bool any_masked(const lb_ctx* c) { return !c->tiles[1].empty(); }
+
+// The overlapped step (coupling alongside the node update of the tiles without spread force)
+// covers one tile group, one MD step per fluid step and no excluded volume; LB_STEP_SERIAL
+// turns it off.
+bool overlap_possible(const lb_ctx* c)
+{
+    const bool one_group = c->tiles[0].empty() != c->tiles[1].empty();
+    const bool wca = c->n_ev > 0 && c->p.wca_epsilon > 0.0;
+    return c->n_beads > 0 && one_group && md_steps(c) == 1 && !wca;
+}
+
+bool use_overlap(const lb_ctx* c)
+{
+    return c->step_policy != LB_STEP_SERIAL && overlap_possible(c);
+}
 
 EventPair get_pair(lb_ctx* c)
 {
@@ -359,6 +384,31 @@ hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* st
     for (auto& a : ag) { a.step_ptr = step_ptr; a.step_arg = step_arg; }
     // timed launches carry their own start/stop events (recorded by the dispatch)
     const bool timed = c->timing && !capture;
+    if (use_overlap(c)) {
+        // launch A: the coupling and the tiles without spread force; launch B: the bodies
+        // (claiming the next step's tiles) and the marked tiles.  Both count as node launches
+        // for the timing.
+        const int g = c->tiles[1].empty() ? 0 : 1;
+        BodyArgs ba = body_args(c);
+        ba.marks = c->marks;
+        for (int part = 0; part < 2; ++part) {
+            EventPair e{};
+            if (timed) e = get_pair(c);
+            if (part == 0)
+                launch_overlap_free<Real>(ag[g], g == 1, couple_args(c), c->marks, s,
+                                          LaunchEvents{e.a, e.b});
+            else
+                launch_overlap_forced<Real>(ag[g], g == 1, ba, s, LaunchEvents{e.a, e.b});
+            note(hipGetLastError());
+            if (timed && e.a && e.b) c->ev_node.push_back(e);
+        }
+        if (c->n_links > 0) {
+            launch_wall_links<Real>(ag[0].dst, c->d_links, c->n_links, s);
+            note(hipGetLastError());
+        }
+        return err;
+    }
+    c->marks_valid = false;   // the serial step does not keep the tile marks
     const int m = md_steps(c);
     for (int k = 0; k < m && c->n_beads > 0; ++k) {
         // MD step k: coupling (its own noise block, the fluid gets 1/m of the force); every
@@ -472,6 +522,7 @@ void rebuild_tiles(lb_ctx* c)
                 t.row_lo = row;
                 t.row_hi = rh;
             }
+            t.gt = (int32_t)((R.base + b) >> kPopBlockLog);
             T.push_back(t);
         }
         H.n_tiles = (int32_t)T.size() - H.tile0;
@@ -493,7 +544,14 @@ int upload_tables(lb_ctx* c)
             HIP_TRY(c, hipMemcpyAsync(c->d_tiles[g], c->tiles[g].data(),
                                       sizeof(NodeTile) * c->tiles[g].size(), hipMemcpyHostToDevice,
                                       c->stream));
+    // global tile -> index in its group's tile array (-1: a tile of padding nodes only)
+    std::vector<int32_t> tile_of((size_t)c->marks.n_gt, -1);
+    for (int g = 0; g < 2; ++g)
+        for (size_t k = 0; k < c->tiles[g].size(); ++k) tile_of[c->tiles[g][k].gt] = (int32_t)k;
+    HIP_TRY(c, hipMemcpyAsync((void*)c->marks.tile_of, tile_of.data(),
+                              sizeof(int32_t) * tile_of.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->marks_valid = false;
     return LB_OK;
 }
 
@@ -997,6 +1055,11 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     c->d_nb_idx = (int32_t*)(c->ws + pl.off_nb_idx);
     c->d_near = (uint8_t*)(c->ws + pl.off_near);
     c->d_wca_ft = (double*)(c->ws + pl.off_wca_ft);
+    c->marks.mark = (uint32_t*)(c->ws + pl.off_tmark);
+    c->marks.list = (int32_t*)(c->ws + pl.off_tlist);
+    c->marks.count = (int32_t*)(c->ws + pl.off_tcount);
+    c->marks.tile_of = (const int32_t*)(c->ws + pl.off_tile_of);
+    c->marks.n_gt = (int32_t)pl.tiles_cap;
 
     c->reps.resize(n_replicas);
     c->rh.resize(n_replicas);
@@ -1261,6 +1324,26 @@ int lb_add_wall_sites(lb_ctx* c, int32_t replica, const double* pos, int32_t n, 
     return LB_OK;
 }
 
+// Before a run of steps: recompute stale body poses and bead records; for the overlapped
+// step, also rebuild the tile marks of the coming step (after a state change, or after serial
+// steps, which do not keep them).  Predicting a current pose again reproduces it bit for bit.
+int prepare_bodies(lb_ctx* c, hipStream_t s)
+{
+    const bool ov = use_overlap(c);
+    if (!c->pose_stale && !(ov && !c->marks_valid)) return LB_OK;
+    BodyArgs ba = body_args(c);
+    if (ov) {
+        ba.marks = c->marks;
+        launch_clear_marks(c->marks, s);
+        HIP_TRY(c, hipGetLastError());
+    }
+    launch_body_predict(ba, (int)((c->step * md_steps(c)) & 1), (int)(c->step & 1), s);
+    HIP_TRY(c, hipGetLastError());
+    c->pose_stale = false;
+    c->marks_valid = ov;
+    return LB_OK;
+}
+
 int lb_rb_step(lb_ctx* c, int32_t n_steps)
 {
     if (!c) return LB_ERR_ARG;
@@ -1270,11 +1353,8 @@ int lb_rb_step(lb_ctx* c, int32_t n_steps)
         const int rc = build_wca(c);
         if (rc != LB_OK) return rc;
     }
-    if (c->pose_stale) {
-        launch_body_predict(body_args(c), (int)((c->step * md_steps(c)) & 1), c->stream);
-        HIP_TRY(c, hipGetLastError());
-        c->pose_stale = false;
-    }
+    const int rc = prepare_bodies(c, c->stream);
+    if (rc != LB_OK) return rc;
     int32_t left = n_steps;
     const bool use_graph = c->graph_steps > 0 && !c->timing;
     while (use_graph && left >= c->graph_steps) {
@@ -1423,13 +1503,17 @@ int lb_save_state(lb_ctx* c, void* dev_buf, size_t* bytes)
     const size_t need = head + bod + pops;
     if (!dev_buf) { *bytes = need; return LB_OK; }
     if (*bytes < need) return fail(c, LB_ERR_ARG, "state buffer too small");
-    uint64_t h[6] = {kStateMagic, (uint64_t)c->step, (uint64_t)c->n_bodies,
-                     (uint64_t)c->p.precision, (uint64_t)c->plan.N, (uint64_t)c->n_beads};
+    // every byte of the state is written (the header and the padding after the bodies as
+    // zeros), so that a saved state is a function of the run alone
+    uint64_t h[head / sizeof(uint64_t)] = {kStateMagic, (uint64_t)c->step, (uint64_t)c->n_bodies,
+                                           (uint64_t)c->p.precision, (uint64_t)c->plan.N,
+                                           (uint64_t)c->n_beads};
     char* d = (char*)dev_buf;
-    HIP_TRY(c, hipMemcpyAsync(d, h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(d, h, head, hipMemcpyHostToDevice, c->stream));
+    const size_t used = sizeof(Body) * c->n_bodies;
     if (c->n_bodies > 0)
-        HIP_TRY(c, hipMemcpyAsync(d + head, c->d_bodies, sizeof(Body) * c->n_bodies,
-                                  hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(d + head, c->d_bodies, used, hipMemcpyDeviceToDevice, c->stream));
+    if (bod > used) HIP_TRY(c, hipMemsetAsync(d + head + used, 0, bod - used, c->stream));
     HIP_TRY(c, hipMemcpyAsync(d + head + bod, c->f[c->cur], pops, hipMemcpyDeviceToDevice,
                               c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1469,6 +1553,24 @@ int lb_set_store_policy(lb_ctx* c, int32_t policy)
         return fail(c, LB_ERR_ARG, "unknown store policy");
     destroy_graphs(c);
     c->store_policy = policy;
+    return LB_OK;
+}
+
+int lb_set_step_policy(lb_ctx* c, int32_t policy)
+{
+    if (!c) return LB_ERR_ARG;
+    if (policy != LB_STEP_AUTO && policy != LB_STEP_SERIAL && policy != LB_STEP_OVERLAP)
+        return fail(c, LB_ERR_ARG, "unknown step policy");
+    destroy_graphs(c);
+    c->step_policy = policy;
+    c->marks_valid = false;
+    return LB_OK;
+}
+
+int lb_step_overlapped(lb_ctx* c, int32_t* out)
+{
+    if (!c || !out) return LB_ERR_ARG;
+    *out = use_overlap(c) ? 1 : 0;
     return LB_OK;
 }
 
@@ -1573,15 +1675,15 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_dr, 0, sizeof(double) * 3 * nb, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_dg, 0, sizeof(double) * nb, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_J, 0, sizeof(double) * nb, s));
-    if (c->pose_stale) {
-        launch_body_predict(body_args(c), (int)((c->step * md_steps(c)) & 1), s);
-        HIP_TRY(c, hipGetLastError());
-        c->pose_stale = false;
+    {
+        const int rc = prepare_bodies(c, s);
+        if (rc != LB_OK) return rc;
     }
     const int parity = (int)(c->step & 1);
     const int rc = is_f32(c) ? run_adjoint<float>(c, n_steps, checkpoint_every, ws, ap)
                              : run_adjoint<double>(c, n_steps, checkpoint_every, ws, ap);
     if (rc != LB_OK) return rc;
+    c->marks_valid = false;
     std::vector<double> dr(3 * nb), dg(nb), jp(nb);
     std::vector<Body> bs(c->n_bodies);
     HIP_TRY(c, hipMemcpyAsync(dr.data(), ws + ap.off_dr, sizeof(double) * dr.size(), hipMemcpyDeviceToHost, s));

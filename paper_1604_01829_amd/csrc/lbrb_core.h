@@ -437,17 +437,21 @@ LBRB_HD void half_kick(double omega[3], const double inertia[3], const double to
 }
 
 // First half of an MD step dt for a free body: V += dt F/(2M), omega half kick,
-// R += dt V, q <- q (x) (cos(dt|w|/2), sin(dt|w|/2) w/|w|), renormalised.  Pure function of b.
-LBRB_HD void first_half(const Body& b, double pos[3], double quat[4], double vel[3],
-                        double omega[3])
+// R += dt V, q <- q (x) (cos(dt|w|/2), sin(dt|w|/2) w/|w|), renormalised.  Inputs: the state
+// after the previous step (pos0, quat0, vel0, omega0) and that step's force and body-frame
+// torque; outputs may not alias them.
+LBRB_HD void first_half(const double pos0[3], const double quat0[4], const double vel0[3],
+                        const double omega0[3], const double force[3], const double torque[3],
+                        double mass, const double inertia[3], double dt, bool fixed,
+                        double pos[3], double quat[4], double vel[3], double omega[3])
 {
-    for (int a = 0; a < 3; ++a) { pos[a] = b.pos[a]; vel[a] = b.vel[a]; omega[a] = b.omega[a]; }
-    for (int a = 0; a < 4; ++a) quat[a] = b.quat[a];
-    if (b.fixed) return;
-    const double hh = 0.5 * b.dt;
-    for (int a = 0; a < 3; ++a) vel[a] += hh * b.force[a] / b.mass;
-    half_kick(omega, b.inertia, b.torque, b.dt);
-    for (int a = 0; a < 3; ++a) pos[a] += b.dt * vel[a];
+    for (int a = 0; a < 3; ++a) { pos[a] = pos0[a]; vel[a] = vel0[a]; omega[a] = omega0[a]; }
+    for (int a = 0; a < 4; ++a) quat[a] = quat0[a];
+    if (fixed) return;
+    const double hh = 0.5 * dt;
+    for (int a = 0; a < 3; ++a) vel[a] += hh * force[a] / mass;
+    half_kick(omega, inertia, torque, dt);
+    for (int a = 0; a < 3; ++a) pos[a] += dt * vel[a];
     const double wn = sqrt(omega[0] * omega[0] + omega[1] * omega[1] + omega[2] * omega[2]);
     if (wn > 0.0) {
         const double h = hh * wn, s = sin(h) / wn, c = cos(h);
@@ -463,16 +467,24 @@ LBRB_HD void first_half(const Body& b, double pos[3], double quat[4], double vel
     }
 }
 
-// Fill a pose from the state of a body (the first half of a step).
-LBRB_HD void predict_pose(const Body& b, Pose& p)
+// rotation matrix and lab-frame angular velocity of a pose whose quaternion and body-frame
+// angular velocity are set
+LBRB_HD void complete_pose(Pose& p)
 {
-    first_half(b, p.pos, p.quat, p.vel, p.omega);
     double m[3][3];
     quat_to_matrix(p.quat, m);
     for (int r = 0; r < 3; ++r) {
         for (int k = 0; k < 3; ++k) p.rot[3 * r + k] = m[r][k];
         p.omega_lab[r] = m[r][0] * p.omega[0] + m[r][1] * p.omega[1] + m[r][2] * p.omega[2];
     }
+}
+
+// Fill a pose from the state of a body (the first half of a step).
+LBRB_HD void predict_pose(const Body& b, Pose& p)
+{
+    first_half(b.pos, b.quat, b.vel, b.omega, b.force, b.torque, b.mass, b.inertia, b.dt,
+               b.fixed != 0, p.pos, p.quat, p.vel, p.omega);
+    complete_pose(p);
 }
 
 }  // namespace lbrb

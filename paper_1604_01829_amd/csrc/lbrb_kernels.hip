@@ -18,6 +18,9 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstddef>
+
 #include "lbrb_device.h"
 
 namespace lbrb {
@@ -88,38 +91,164 @@ __device__ __forceinline__ void update_node(const StepArgs<Real>& a, const Repli
     }
 }
 
-// bead records of body b for the step whose pose is P (all threads of the workgroup)
-__device__ __forceinline__ void write_bead_records(const Body& B, const Pose& P,
-                                                   const Bead* __restrict__ beads,
-                                                   BeadRec* __restrict__ recs)
+// What a bead record takes from its body besides the pose (uniform over the workgroup, read
+// once into registers).
+struct RecConst {
+    double gamma, noise_amp;
+    int32_t first_in_replica, fixed;
+    BodyBox box;
+};
+
+__device__ __forceinline__ RecConst rec_const(const Body& B)
 {
-    const BodyBox& X = B.box;
-    for (int k = threadIdx.x; k < B.n_beads; k += blockDim.x) {
-        const int e = B.first_bead + k;
-        const Bead bd = beads[e];
-        BeadRec& o = recs[e];   // written field by field: few live registers in the node kernel
-        double dv[3];
-        for (int ax = 0; ax < 3; ++ax) {
-            dv[ax] = P.rot[3 * ax] * bd.off[0] + P.rot[3 * ax + 1] * bd.off[1] +
-                     P.rot[3 * ax + 2] * bd.off[2];
-            o.dv[ax] = dv[ax];
-            o.r[ax] = P.pos[ax] + dv[ax];
+    return RecConst{B.gamma, B.noise_amp, B.first_bead_in_replica, B.fixed, B.box};
+}
+
+// the pose terms a bead record takes, held in scalar registers
+struct RecPose {
+    double rot[9], pos[3], vel[3], omega_lab[3];
+};
+
+__device__ __forceinline__ double uniform_value(double x)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ int32_t uniform_int(int32_t x)
+{
+    return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+}
+
+__device__ __forceinline__ RecConst uniform_rec_const(const RecConst& c)
+{
+    RecConst r;
+    r.gamma = uniform_value(c.gamma);
+    r.noise_amp = uniform_value(c.noise_amp);
+    r.first_in_replica = uniform_int(c.first_in_replica);
+    r.fixed = uniform_int(c.fixed);
+    r.box.nx = uniform_int(c.box.nx);
+    r.box.ny = uniform_int(c.box.ny);
+    r.box.nz = uniform_int(c.box.nz);
+    r.box.masked = uniform_int(c.box.masked);
+    r.box.base = (int64_t)(((uint64_t)(uint32_t)uniform_int((int32_t)(c.box.base >> 32)) << 32) |
+                           (uint32_t)uniform_int((int32_t)c.box.base));
+    r.box.row_base = uniform_int(c.box.row_base);
+    r.box.key0 = (uint32_t)uniform_int((int32_t)c.box.key0);
+    r.box.key1 = (uint32_t)uniform_int((int32_t)c.box.key1);
+    r.box.pad = 0;
+    return r;
+}
+
+__device__ __forceinline__ RecPose uniform_rec_pose(const Pose& P)
+{
+    RecPose r;
+    for (int k = 0; k < 9; ++k) r.rot[k] = uniform_value(P.rot[k]);
+    for (int k = 0; k < 3; ++k) {
+        r.pos[k] = uniform_value(P.pos[k]);
+        r.vel[k] = uniform_value(P.vel[k]);
+        r.omega_lab[k] = uniform_value(P.omega_lab[k]);
+    }
+    return r;
+}
+
+// record of bead bd for the step whose pose is P
+template <typename PoseT>
+__device__ __forceinline__ void write_bead_record(const RecConst& C, const PoseT& P,
+                                                  const Bead& bd, BeadRec& o, double r[3])
+{
+    // written field by field: few live registers in the node kernel
+    double dv[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        dv[ax] = P.rot[3 * ax] * bd.off[0] + P.rot[3 * ax + 1] * bd.off[1] +
+                 P.rot[3 * ax + 2] * bd.off[2];
+        o.dv[ax] = dv[ax];
+        r[ax] = P.pos[ax] + dv[ax];
+        o.r[ax] = r[ax];
+    }
+    if (C.fixed) {
+        o.v[0] = o.v[1] = o.v[2] = 0.0;
+    } else {
+        const double* w = P.omega_lab;
+        o.v[0] = P.vel[0] + (w[1] * dv[2] - w[2] * dv[1]);
+        o.v[1] = P.vel[1] + (w[2] * dv[0] - w[0] * dv[2]);
+        o.v[2] = P.vel[2] + (w[0] * dv[1] - w[1] * dv[0]);
+    }
+    const BodyBox& X = C.box;
+    o.gamma = C.gamma;
+    o.noise_amp = C.noise_amp;
+    o.noise_idx = C.first_in_replica + bd.user;   // noise follows the caller's order
+    o.row_base = X.row_base;
+    o.nx = X.nx; o.ny = X.ny; o.nz = X.nz; o.masked = X.masked;
+    o.base = X.base;
+    o.key0 = X.key0; o.key1 = X.key1;
+}
+
+// ------------------------------------------------------------------ tiles under the stencils
+
+// The first claim of global tile gt for the fluid step of parity p appends it to that
+// parity's list.
+__device__ __forceinline__ void claim_tile(const TileMarks& tm, int p, int32_t gt)
+{
+    const int64_t o = (int64_t)p * tm.n_gt;
+    if (atomicExch(&tm.mark[o + gt], 1u) == 0u) {
+        const int32_t i = atomicAdd(&tm.count[p], 1);
+        tm.list[o + i] = gt;
+    }
+}
+
+// LDS set of the tiles one workgroup has claimed (open addressing): a bead stencil's tiles
+// are claimed once per workgroup rather than once per corner.  A full table passes the claim
+// on to the device atomic, which deduplicates as well.
+constexpr int kTileSet = 1024;
+
+__device__ __forceinline__ void set_claim(uint32_t* set, const TileMarks& tm, int p, int32_t gt)
+{
+    const uint32_t key = (uint32_t)gt + 1u;
+    int slot = (int)((key * 2654435761u) >> 22) & (kTileSet - 1);
+    for (int probe = 0; probe < kTileSet; ++probe) {
+        const uint32_t prev = atomicCAS(&set[slot], 0u, key);
+        if (prev == 0u) {
+            claim_tile(tm, p, gt);
+            return;
         }
-        if (B.fixed) {
-            o.v[0] = o.v[1] = o.v[2] = 0.0;
-        } else {
-            const double* w = P.omega_lab;
-            o.v[0] = P.vel[0] + (w[1] * dv[2] - w[2] * dv[1]);
-            o.v[1] = P.vel[1] + (w[2] * dv[0] - w[0] * dv[2]);
-            o.v[2] = P.vel[2] + (w[0] * dv[1] - w[1] * dv[0]);
+        if (prev == key) return;
+        slot = (slot + 1) & (kTileSet - 1);
+    }
+    claim_tile(tm, p, gt);
+}
+
+// claim the tiles of the fluid nodes of the trilinear stencil around bead position r: the
+// corners the coupling computes from the same r (fluid nodes only)
+__device__ __forceinline__ void claim_stencil(const BodyBox& X, const RowDesc* __restrict__ rowinfo,
+                                              const double r[3], uint32_t* set,
+                                              const TileMarks& tm, int p)
+{
+    double fr[3];
+    int i0[3];
+    i0[0] = wrap_floor(r[0] - 0.5, X.nx, fr[0]);
+    i0[1] = wrap_floor(r[1] - 0.5, X.ny, fr[1]);
+    i0[2] = wrap_floor(r[2] - 0.5, X.nz, fr[2]);
+    for (int oz = 0; oz < 2; ++oz) {
+        const int pz = i0[2] + oz == X.nz ? 0 : i0[2] + oz;
+        for (int oy = 0; oy < 2; ++oy) {
+            const int py = i0[1] + oy == X.ny ? 0 : i0[1] + oy;
+            RowDesc rd{0, 0, 0, 0};
+            if (X.masked) rd = rowinfo[X.row_base + py + X.ny * pz];
+            for (int ox = 0; ox < 2; ++ox) {
+                const int px = i0[0] + ox == X.nx ? 0 : i0[0] + ox;
+                int64_t local;
+                if (X.masked) {
+                    const int off = px - rd.xlo;
+                    local = (unsigned)off < (unsigned)rd.len ? rd.start + off : -1;
+                } else {
+                    local = px + (int64_t)X.nx * (py + (int64_t)X.ny * pz);
+                }
+                if (local >= 0) set_claim(set, tm, p, (int32_t)((X.base + local) >> kPopBlockLog));
+            }
         }
-        o.gamma = B.gamma;
-        o.noise_amp = B.noise_amp;
-        o.noise_idx = B.first_bead_in_replica + bd.user;   // noise follows the caller's order
-        o.row_base = X.row_base;
-        o.nx = X.nx; o.ny = X.ny; o.nz = X.nz; o.masked = X.masked;
-        o.base = X.base;
-        o.key0 = X.key0; o.key1 = X.key1;
     }
 }
 
@@ -291,67 +420,135 @@ __device__ __forceinline__ void wca_block(const BodyArgs& ba, int b, int parity,
 // one workgroup per body: sum the bead forces and torques (shuffle + LDS tree, fixed order),
 // add the excluded-volume force and torque of the MD step, turn the torque into the body
 // frame, second half kick, pose and bead records of the next MD step.  parity: of the MD
-// step being finished.
-__device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parity)
+// step being finished.  Two dependent rounds of loads: the body's bead range, then together
+// the bead forces, each thread's first two bead offsets (parked in LDS), and the step's pose,
+// mass, inertia, dt and excluded-volume sums (one word per lane into LDS).  The next pose is
+// built in LDS, stored by 25 lanes, and read back into scalar registers for the records, so
+// that this code needs fewer registers than the node update it shares a kernel with.
+// With MARK, the tiles under the new bead stencils are claimed for the fluid step of parity
+// mark_parity (the overlapped step).
+template <bool MARK>
+__device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parity,
+                                            int mark_parity = 0)
 {
+    constexpr int kPre = 2;                       // bead offsets fetched with the forces
+    constexpr int kPoseWords = sizeof(Pose) / sizeof(double);
+    static_assert(sizeof(Pose) == 25 * sizeof(double), "a pose is 25 doubles");
+    static_assert(offsetof(Body, dt) == offsetof(Body, mass) + 6 * sizeof(double),
+                  "mass, inertia, gamma, noise_amp, dt are consecutive");
     __shared__ double part[4][6];
-    __shared__ Pose next;
-    Body* __restrict__ bodies = ba.bodies;
+    __shared__ Pose cur, next;
+    __shared__ double st[12];                     // vel, omega, force, body torque after the step
+    __shared__ double cst[13];                    // mass, inertia[3], gamma, noise, dt, wca F, T
+    const Body& B = ba.bodies[b];
+    const int first = B.first_bead, n = B.n_beads;
+    const int tid = threadIdx.x;
+    __shared__ RecConst rcs;
+    const int fixed = B.fixed;
+    if (tid == 64) rcs = rec_const(B);
+    __shared__ uint32_t tile_set[MARK ? kTileSet : 1];
+    if constexpr (MARK)
+        for (int k = tid; k < kTileSet; k += 256) tile_set[k] = 0u;
+    const bool has_wca = ba.wca_ft != nullptr;
+    if (tid < kPoseWords) {
+        reinterpret_cast<double*>(&cur)[tid] = reinterpret_cast<const double*>(&B.pose[parity])[tid];
+    } else if (tid < kPoseWords + 7) {
+        cst[tid - kPoseWords] = reinterpret_cast<const double*>(&B.mass)[tid - kPoseWords];
+    } else if (tid < kPoseWords + 13) {
+        cst[tid - kPoseWords] = has_wca ? ba.wca_ft[6 * b + tid - kPoseWords - 7] : 0.0;
+    }
+    __shared__ double pre_off[kPre][3][256];     // body-frame offsets of each thread's first beads
+    __shared__ int32_t pre_user[kPre][256];
     const double* __restrict__ bf = ba.bead_force;
     const double* __restrict__ bt = ba.bead_torque;
-    const Body& B = bodies[b];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = threadIdx.x; k < B.n_beads; k += 256) {
-        const int64_t e = 3 * (int64_t)(B.first_bead + k);
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+        const int k = tid + q * 256;
+        if (k < n) {
+            const int64_t e = 3 * (int64_t)(first + k);
+            const Bead& bd = ba.beads[first + k];
+            const double o0 = bd.off[0], o1 = bd.off[1], o2 = bd.off[2];
+            const int32_t us = bd.user;
+            const double f0 = bf[e], f1 = bf[e + 1], f2 = bf[e + 2];
+            const double t0 = bt[e], t1 = bt[e + 1], t2 = bt[e + 2];
+            acc[0] += f0; acc[1] += f1; acc[2] += f2;
+            acc[3] += t0; acc[4] += t1; acc[5] += t2;
+            pre_off[q][0][tid] = o0; pre_off[q][1][tid] = o1; pre_off[q][2][tid] = o2;
+            pre_user[q][tid] = us;
+        }
+    }
+    for (int k = tid + kPre * 256; k < n; k += 256) {
+        const int64_t e = 3 * (int64_t)(first + k);
         acc[0] += bf[e]; acc[1] += bf[e + 1]; acc[2] += bf[e + 2];
         acc[3] += bt[e]; acc[4] += bt[e + 1]; acc[5] += bt[e + 2];
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1)
         for (int k = 0; k < 6; ++k) acc[k] += __shfl_down(acc[k], m, 64);
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0)
         for (int k = 0; k < 6; ++k) part[wave][k] = acc[k];
     __syncthreads();
-    if (threadIdx.x == 0) {
+    Body& o = ba.bodies[b];
+    if (tid == 0) {
         double F[3], T[3];
         for (int k = 0; k < 3; ++k) {
             F[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
             T[k] = (part[0][3 + k] + part[1][3 + k]) + (part[2][3 + k] + part[3][3 + k]);
         }
-        if (ba.wca_ft) {
+        if (has_wca) {
             for (int k = 0; k < 3; ++k) {
-                F[k] += ba.wca_ft[6 * b + k];
-                T[k] += ba.wca_ft[6 * b + 3 + k];
+                F[k] += cst[7 + k];
+                T[k] += cst[10 + k];
             }
         }
+        const double mass = cst[0], dt = cst[6];
+        const double inertia[3] = {cst[1], cst[2], cst[3]};
         // second half kick with this step's force and body-frame torque, from the step's pose
-        const Pose& P = B.pose[parity];
+        const Pose& P = cur;
         double vel[3], om[3], Tb[3];
         for (int ax = 0; ax < 3; ++ax) {
             vel[ax] = P.vel[ax];
             om[ax] = P.omega[ax];
             Tb[ax] = P.rot[ax] * T[0] + P.rot[3 + ax] * T[1] + P.rot[6 + ax] * T[2];
         }
-        if (!B.fixed) {
-            const double hh = 0.5 * B.dt;
-            for (int ax = 0; ax < 3; ++ax) vel[ax] += hh * F[ax] / B.mass;
-            half_kick(om, B.inertia, Tb, B.dt);
+        if (!fixed) {
+            const double hh = 0.5 * dt;
+            for (int ax = 0; ax < 3; ++ax) vel[ax] += hh * F[ax] / mass;
+            half_kick(om, inertia, Tb, dt);
         }
-        Body& o = bodies[b];
         for (int ax = 0; ax < 3; ++ax) {
             o.pos[ax] = P.pos[ax];
-            o.vel[ax] = vel[ax];
-            o.omega[ax] = om[ax];
-            o.force[ax] = F[ax];
-            o.torque[ax] = Tb[ax];
+            o.vel[ax] = st[ax] = vel[ax];
+            o.omega[ax] = st[3 + ax] = om[ax];
+            o.force[ax] = st[6 + ax] = F[ax];
+            o.torque[ax] = st[9 + ax] = Tb[ax];
         }
         for (int k = 0; k < 4; ++k) o.quat[k] = P.quat[k];
-        predict_pose(o, o.pose[parity ^ 1]);
-        next = o.pose[parity ^ 1];
+        // the prediction reads the state back from LDS (fewer live registers)
+        asm volatile("" ::: "memory");
+        first_half(cur.pos, cur.quat, st, st + 3, st + 6, st + 9, cst[0], cst + 1, cst[6],
+                   fixed != 0, next.pos, next.quat, next.vel, next.omega);
+        complete_pose(next);
     }
     __syncthreads();
-    write_bead_records(B, next, ba.beads, ba.recs);
+    if (tid < kPoseWords)
+        reinterpret_cast<double*>(&o.pose[parity ^ 1])[tid] = reinterpret_cast<const double*>(&next)[tid];
+    const RecPose RP = uniform_rec_pose(next);
+    const RecConst C = uniform_rec_const(rcs);
+    for (int q = 0, k = tid; k < n; ++q, k += 256) {
+        Bead bd;
+        if (q < kPre) {
+            for (int ax = 0; ax < 3; ++ax) bd.off[ax] = pre_off[q][ax][tid];
+            bd.user = pre_user[q][tid];
+        } else {
+            bd = ba.beads[first + k];
+        }
+        double r[3];
+        write_bead_record(C, RP, bd, ba.recs[first + k], r);
+        if constexpr (MARK) claim_stencil(C.box, ba.rowinfo, r, tile_set, ba.marks, mark_parity);
+    }
 }
 
 // The node update of one tile group.  With FORCES the nodes consume the spread force of the
@@ -369,7 +566,8 @@ void node_step_kernel(const StepArgs<Real> a,
     int b = blockIdx.x;
     if (b < n_lead) {
         // the last MD step of this fluid step
-        if (b < ba.n_bodies) body_finish(ba, b, (int)((step * ba.substeps + ba.substeps - 1) & 1));
+        if (b < ba.n_bodies)
+            body_finish<false>(ba, b, (int)((step * ba.substeps + ba.substeps - 1) & 1));
         return;
     }
     b -= n_lead;
@@ -446,31 +644,28 @@ void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const B
 // lanes' force contributions are summed as fixed-point words in LDS and the node's owner
 // adds each sum to the node with one device atomic per word.  Integer sums do not depend on
 // their order, so the result is the same as one atomic per lane.
-//
-// With excluded volume (WCA), the first n_wca workgroups (a multiple of 8, so that the bead
-// workgroups keep their XCD pattern) compute each body's WCA force and torque for the same
-// MD step instead (wca_block); they use the LDS of the force sums.  Without it the kernel is
-// compiled without that code (its registers stay those of the coupling alone).
-template <typename Real, bool WCA>
-__global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Real> a,
-                                                              const CoupleArgs c,
-                                                              const BodyArgs ba, int n_wca)
+
+// LDS of one coupling workgroup: the node hash table, the nodes' moments and the force sums
+template <typename Real>
+struct CoupleLds {
+    static constexpr int TS = 2 * kCoupleBlock;          // hash slots (power of two)
+    static constexpr int NW = sizeof(Real) == 8 ? 6 : 3; // fixed-point words per node
+    unsigned long long key[TS];
+    Real mom[4][TS];
+    unsigned long long acc[NW][TS];
+};
+
+// the coupling of bead block cb of ncb (32 beads)
+template <typename Real>
+__device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const CoupleArgs& c, int cb,
+                                             int ncb, CoupleLds<Real>& L)
 {
-    constexpr int TS = 2 * kCoupleBlock;                 // hash slots (power of two)
-    constexpr int NW = sizeof(Real) == 8 ? 6 : 3;       // fixed-point words per node
+    constexpr int TS = CoupleLds<Real>::TS;
+    constexpr int NW = CoupleLds<Real>::NW;
     constexpr unsigned long long EMPTY = ~0ull;
-    __shared__ unsigned long long key[TS];
-    __shared__ Real mom[4][TS];
-    __shared__ unsigned long long acc[NW][TS];
-    static_assert(sizeof(acc) >= sizeof(WcaLds), "excluded-volume LDS fits in the force sums");
-    if (WCA && (int)blockIdx.x < n_wca) {
-        if ((int)blockIdx.x < ba.n_bodies) {
-            const int64_t step = current_step(a.step_ptr, a.step_arg);
-            wca_block(ba, blockIdx.x, (int)((step * ba.substeps + c.md_step) & 1),
-                      *reinterpret_cast<WcaLds*>(&acc[0][0]));
-        }
-        return;
-    }
+    unsigned long long* key = L.key;
+    Real (*mom)[TS] = L.mom;
+    unsigned long long (*acc)[TS] = L.acc;
     for (int k = threadIdx.x; k < TS; k += kCoupleBlock) {
         key[k] = EMPTY;
         for (int w = 0; w < NW; ++w) acc[w][k] = 0;
@@ -478,7 +673,7 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
 
     // consecutive bead blocks (neighbouring beads of one body, sharing stencil rows) stay on
     // one XCD and its L2
-    const int tid = xcd_tile(blockIdx.x - n_wca, gridDim.x - n_wca) * kCoupleBlock + threadIdx.x;
+    const int tid = xcd_tile(cb, ncb) * kCoupleBlock + threadIdx.x;
     const int bead = tid >> 3, corner = tid & 7;
     const bool active = bead < c.n_beads;   // the 8 lanes of a bead share this
     const int64_t step = current_step(a.step_ptr, a.step_arg);
@@ -598,6 +793,29 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
     }
 }
 
+// The coupling launch.  With excluded volume (WCA), the first n_wca workgroups (a multiple of
+// 8, so that the bead workgroups keep their XCD pattern) compute each body's WCA force and
+// torque for the same MD step instead (wca_block); they use the LDS of the force sums.
+// Without it the kernel is compiled without that code (its registers stay those of the
+// coupling alone).
+template <typename Real, bool WCA>
+__global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Real> a,
+                                                              const CoupleArgs c,
+                                                              const BodyArgs ba, int n_wca)
+{
+    __shared__ CoupleLds<Real> L;
+    static_assert(sizeof(L.acc) >= sizeof(WcaLds), "excluded-volume LDS fits in the force sums");
+    if (WCA && (int)blockIdx.x < n_wca) {
+        if ((int)blockIdx.x < ba.n_bodies) {
+            const int64_t step = current_step(a.step_ptr, a.step_arg);
+            wca_block(ba, blockIdx.x, (int)((step * ba.substeps + c.md_step) & 1),
+                      *reinterpret_cast<WcaLds*>(&L.acc[0][0]));
+        }
+        return;
+    }
+    couple_beads<Real>(a, c, blockIdx.x - n_wca, gridDim.x - n_wca, L);
+}
+
 template <typename Real>
 void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s,
                    const LaunchEvents& ev, const BodyArgs* wca)
@@ -617,23 +835,182 @@ void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s,
         launch_timed(couple_kernel<Real, false>, grid, dim3(kCoupleBlock), s, ev, a, c, ba, 0);
 }
 
-// pose of the coming step and its bead records, one workgroup per body
-__global__ __launch_bounds__(256) void body_predict_kernel(const BodyArgs ba, int parity)
+// ------------------------------------------------------------------ overlapped step
+
+// Launch A of the overlapped step: the first n_cb workgroups couple the beads (n_cb a
+// multiple of 8, so that the tile workgroups keep their XCD pattern); every other workgroup
+// owns one node tile, clears the tile's mark of the other parity, and updates its nodes
+// without force unless the tile is marked for this step.
+template <typename Real, bool MASKED, bool THERMAL, bool NARROW, bool NT>
+__global__ __launch_bounds__(kNodeBlock) void overlap_free_kernel(const StepArgs<Real> a,
+                                                                  const CoupleArgs c,
+                                                                  const TileMarks tm, int n_cb)
+{
+    static_assert(kNodeBlock == kCoupleBlock, "one workgroup size for both roles");
+    int b = blockIdx.x;
+    if (b < n_cb) {
+        __shared__ CoupleLds<Real> L;
+        couple_beads<Real>(a, c, b, n_cb, L);
+        return;
+    }
+    b -= n_cb;
+    const int64_t step = current_step(a.step_ptr, a.step_arg);
+    const int p = (int)(step & 1);
+    const NodeTile t = a.tiles[xcd_tile(b, gridDim.x - n_cb)];
+    if (threadIdx.x == 0) {
+        tm.mark[(int64_t)(p ^ 1) * tm.n_gt + t.gt] = 0u;
+        if (b == 0) tm.count[p ^ 1] = 0;
+    }
+    if (tm.mark[(int64_t)p * tm.n_gt + t.gt] != 0u) return;
+    if ((int)threadIdx.x >= t.count) return;
+    const ReplicaDesc R = a.reps[t.replica];
+    const int64_t local = t.begin + threadIdx.x;
+    int x, y, z;
+    RowDesc self;
+    locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
+    update_node<Real, MASKED, THERMAL, false, NARROW, NT>(a, R, local, x, y, z, self, step);
+}
+
+// Launch B: the first n_lead workgroups finish the bodies and claim the tiles of the next
+// step; the others walk the tiles marked for this step (workgroup w takes list entries w,
+// w + G, ...) and update their nodes with the spread force.
+template <typename Real, bool MASKED, bool THERMAL, bool NARROW, bool NT>
+__global__ __launch_bounds__(kNodeBlock) void overlap_forced_kernel(const StepArgs<Real> a,
+                                                                    const BodyArgs ba,
+                                                                    int n_lead)
+{
+    const int64_t step = current_step(a.step_ptr, a.step_arg);
+    int b = blockIdx.x;
+    if (b < n_lead) {
+        if (b < ba.n_bodies) body_finish<true>(ba, b, (int)(step & 1), (int)((step + 1) & 1));
+        return;
+    }
+    b -= n_lead;
+    const int G = gridDim.x - n_lead;
+    const TileMarks& tm = ba.marks;
+    const int p = (int)(step & 1);
+    const int n = min(tm.count[p], tm.n_gt);
+    for (int i = b; i < n; i += G) {
+        const int32_t gt = tm.list[(int64_t)p * tm.n_gt + i];
+        const int32_t ti = (unsigned)gt < (unsigned)tm.n_gt ? tm.tile_of[gt] : -1;
+        if (ti < 0 || ti >= a.n_tiles) continue;   // (never: a claimed tile holds fluid nodes)
+        const NodeTile t = a.tiles[ti];
+        if ((int)threadIdx.x >= t.count) continue;
+        const ReplicaDesc R = a.reps[t.replica];
+        const int64_t local = t.begin + threadIdx.x;
+        int x, y, z;
+        RowDesc self;
+        locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
+        update_node<Real, MASKED, THERMAL, true, NARROW, NT>(a, R, local, x, y, z, self, step);
+    }
+}
+
+template <typename Real, bool MASKED, bool THERMAL, bool NARROW, bool NT>
+void launch_overlap_t(const StepArgs<Real>& a, const CoupleArgs* c, const TileMarks& tm,
+                      const BodyArgs* ba, hipStream_t s, const LaunchEvents& ev)
+{
+    const dim3 block(kNodeBlock);
+    if (c) {
+        const int n_cb = c->n_beads > 0 ? ((c->n_beads * kBeadLanes + kCoupleBlock - 1) /
+                                           kCoupleBlock + 7) & ~7 : 0;
+        launch_timed(overlap_free_kernel<Real, MASKED, THERMAL, NARROW, NT>,
+                     dim3(n_cb + a.n_tiles), block, s, ev, a, *c, tm, n_cb);
+    } else {
+        const int n_lead = ba->n_bodies > 0 ? (ba->n_bodies + 7) & ~7 : 0;
+        const int G = std::max(1, std::min(a.n_tiles, kForcedTileWorkgroups));
+        launch_timed(overlap_forced_kernel<Real, MASKED, THERMAL, NARROW, NT>,
+                     dim3(n_lead + G), block, s, ev, a, *ba, n_lead);
+    }
+}
+
+template <typename Real, bool MASKED, bool THERMAL>
+void launch_overlap_w(const StepArgs<Real>& a, const CoupleArgs* c, const TileMarks& tm,
+                      const BodyArgs* ba, hipStream_t s, const LaunchEvents& ev)
+{
+    const bool narrow = sizeof(Real) == 4 && a.narrow;
+    if (narrow) {
+        if (a.stream_stores) launch_overlap_t<Real, MASKED, THERMAL, true, true>(a, c, tm, ba, s, ev);
+        else launch_overlap_t<Real, MASKED, THERMAL, true, false>(a, c, tm, ba, s, ev);
+    } else {
+        if (a.stream_stores) launch_overlap_t<Real, MASKED, THERMAL, false, true>(a, c, tm, ba, s, ev);
+        else launch_overlap_t<Real, MASKED, THERMAL, false, false>(a, c, tm, ba, s, ev);
+    }
+}
+
+template <typename Real>
+void launch_overlap(const StepArgs<Real>& a, bool masked, const CoupleArgs* c,
+                    const TileMarks& tm, const BodyArgs* ba, hipStream_t s, const LaunchEvents& ev)
+{
+    if (masked) {
+        if (a.thermal) launch_overlap_w<Real, true, true>(a, c, tm, ba, s, ev);
+        else launch_overlap_w<Real, true, false>(a, c, tm, ba, s, ev);
+    } else {
+        if (a.thermal) launch_overlap_w<Real, false, true>(a, c, tm, ba, s, ev);
+        else launch_overlap_w<Real, false, false>(a, c, tm, ba, s, ev);
+    }
+}
+
+template <typename Real>
+void launch_overlap_free(const StepArgs<Real>& a, bool masked, const CoupleArgs& c,
+                         const TileMarks& tm, hipStream_t s, const LaunchEvents& ev)
+{
+    launch_overlap<Real>(a, masked, &c, tm, nullptr, s, ev);
+}
+
+template <typename Real>
+void launch_overlap_forced(const StepArgs<Real>& a, bool masked, const BodyArgs& ba,
+                           hipStream_t s, const LaunchEvents& ev)
+{
+    launch_overlap<Real>(a, masked, nullptr, ba.marks, &ba, s, ev);
+}
+
+__global__ void clear_marks_kernel(TileMarks tm)
+{
+    const int64_t n = 2 * (int64_t)tm.n_gt;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        tm.mark[i] = 0u;
+        tm.list[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 2) tm.count[threadIdx.x] = 0;
+}
+
+void launch_clear_marks(const TileMarks& tm, hipStream_t s)
+{
+    if (!tm.mark || tm.n_gt <= 0) return;
+    const int blocks = (int)std::min<int64_t>(1024, (2 * (int64_t)tm.n_gt + 255) / 256);
+    hipLaunchKernelGGL(clear_marks_kernel, dim3(blocks), dim3(256), 0, s, tm);
+}
+
+// pose of the coming step and its bead records, one workgroup per body; with marks, the tiles
+// under the bead stencils are claimed for the fluid step of parity mark_parity
+__global__ __launch_bounds__(256) void body_predict_kernel(const BodyArgs ba, int parity,
+                                                           int mark_parity)
 {
     __shared__ Pose next;
+    __shared__ uint32_t tile_set[kTileSet];
     Body& B = ba.bodies[blockIdx.x];
+    const bool mark = ba.marks.mark != nullptr;
+    for (int k = threadIdx.x; k < kTileSet; k += blockDim.x) tile_set[k] = 0u;
     if (threadIdx.x == 0) {
         predict_pose(B, B.pose[parity]);
         next = B.pose[parity];
     }
     __syncthreads();
-    write_bead_records(B, next, ba.beads, ba.recs);
+    const RecConst C = rec_const(B);
+    const int first = B.first_bead, n = B.n_beads;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        double r[3];
+        write_bead_record(C, next, ba.beads[first + k], ba.recs[first + k], r);
+        if (mark) claim_stencil(C.box, ba.rowinfo, r, tile_set, ba.marks, mark_parity);
+    }
 }
 
-void launch_body_predict(const BodyArgs& b, int parity, hipStream_t s)
+void launch_body_predict(const BodyArgs& b, int parity, int mark_parity, hipStream_t s)
 {
     if (b.n_bodies <= 0) return;
-    hipLaunchKernelGGL(body_predict_kernel, dim3(b.n_bodies), dim3(256), 0, s, b, parity);
+    hipLaunchKernelGGL(body_predict_kernel, dim3(b.n_bodies), dim3(256), 0, s, b, parity,
+                       mark_parity);
 }
 
 // finish every body after MD step k of the fluid step (one workgroup per body)
@@ -642,7 +1019,7 @@ __global__ __launch_bounds__(256) void body_substep_kernel(const BodyArgs ba,
                                                            int64_t step_arg, int k)
 {
     const int64_t step = current_step(step_ptr, step_arg);
-    body_finish(ba, blockIdx.x, (int)((step * ba.substeps + k) & 1));
+    body_finish<false>(ba, blockIdx.x, (int)((step * ba.substeps + k) & 1));
 }
 
 void launch_body_substep(const BodyArgs& b, const int64_t* step_ptr, int64_t step_arg, int k,
@@ -753,6 +1130,14 @@ void launch_observe(const StepArgs<Real>& a, bool masked, int32_t tile0, int32_t
 }
 
 // explicit instantiations
+template void launch_overlap_free<float>(const StepArgs<float>&, bool, const CoupleArgs&,
+                                         const TileMarks&, hipStream_t, const LaunchEvents&);
+template void launch_overlap_free<double>(const StepArgs<double>&, bool, const CoupleArgs&,
+                                          const TileMarks&, hipStream_t, const LaunchEvents&);
+template void launch_overlap_forced<float>(const StepArgs<float>&, bool, const BodyArgs&,
+                                           hipStream_t, const LaunchEvents&);
+template void launch_overlap_forced<double>(const StepArgs<double>&, bool, const BodyArgs&,
+                                            hipStream_t, const LaunchEvents&);
 template void launch_couple<float>(const StepArgs<float>&, const CoupleArgs&, hipStream_t,
                                    const LaunchEvents&, const BodyArgs*);
 template void launch_couple<double>(const StepArgs<double>&, const CoupleArgs&, hipStream_t,

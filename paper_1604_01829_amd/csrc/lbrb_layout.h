@@ -30,6 +30,7 @@ constexpr int kNodeBlock = 256;   // threads (= nodes) per node-update workgroup
 constexpr int kBeadLanes = 8;     // threads per bead in the coupling kernel (one per corner)
 constexpr int kCoupleBlock = 256;
 constexpr int kPopBlockLog = 8;   // populations are blocked per 256 nodes
+constexpr int kForcedTileWorkgroups = 2048;   // tile workgroups of the overlapped step's launch B
 
 // index of population i of global node g in a population buffer
 __host__ __device__ __forceinline__ int64_t pop_at(int i, int64_t g)
@@ -64,6 +65,19 @@ struct NodeTile {
     int32_t count;          // nodes in this tile (<= kNodeBlock)
     int64_t begin;          // local index of the first node
     int32_t row_lo, row_hi; // rows[] range that covers the tile (masked replicas)
+    int32_t gt;             // global tile: (replica base + begin) / 256
+    int32_t pad;
+};
+
+// Tiles that receive spread force, per fluid step parity (the overlapped step, see
+// launch_overlap_free).  A global tile gt holds global nodes [256 gt, 256 gt + 256).
+struct TileMarks {
+    uint32_t* mark;         // [2][n_gt]: 1 if the tile receives spread force in that step
+    int32_t* list;          // [2][n_gt]: the marked tiles in the order they were claimed
+    int32_t* count;         // [2]: entries in list
+    const int32_t* tile_of; // [n_gt]: index of the global tile in its group's tile array
+    int32_t n_gt;
+    int32_t pad;
 };
 
 struct DeviceHeader {
@@ -184,14 +198,37 @@ struct BodyArgs {
     const int32_t* nb_idx;          // site indices of each coarse cell's neighbourhood
     const uint8_t* near;            // fine cells: 1 if a site may be within range
     const WallSite* sites;
+    TileMarks marks;                // with the overlapped step: tiles of the next step's
+                                    // bead stencils are claimed here (mark null: not used)
+    const RowDesc* rowinfo;         // row table, for the stencil tiles of masked replicas
 };
 // the node update of one tile group; with forces the nodes consume the spread force, with
 // bodies != null its leading workgroups finish the bodies
 template <typename Real>
 void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const BodyArgs* bodies,
                       hipStream_t s, const LaunchEvents& ev = LaunchEvents{});
-// pose of the coming MD step (parity = MD step count & 1) and bead records of every body
-void launch_body_predict(const BodyArgs& b, int parity, hipStream_t s);
+// The overlapped fluid step (one tile group, one MD step per fluid step, no excluded volume):
+// two launches instead of coupling -> node update.
+//  launch_overlap_free: the coupling workgroups, and the node update (without force) of every
+//    tile not marked for this step; each tile workgroup also clears its tile's mark of the
+//    other parity (and the first one that parity's count).
+//  launch_overlap_forced: the body finishing, which also claims the tiles under the bead
+//    stencils of the next step, and the node update (with force) of the tiles marked for this
+//    step, walked from the list.
+// The results are those of the serial step bit for bit: a node's update reads only its own
+// spread force, and every node that receives one lies in a marked tile.
+template <typename Real>
+void launch_overlap_free(const StepArgs<Real>& a, bool masked, const CoupleArgs& c,
+                         const TileMarks& tm, hipStream_t s, const LaunchEvents& ev = LaunchEvents{});
+template <typename Real>
+void launch_overlap_forced(const StepArgs<Real>& a, bool masked, const BodyArgs& ba,
+                           hipStream_t s, const LaunchEvents& ev = LaunchEvents{});
+// clear the marks, lists and counts of both parities
+void launch_clear_marks(const TileMarks& tm, hipStream_t s);
+// pose of the coming MD step (parity = MD step count & 1) and bead records of every body;
+// with b.marks set, the tiles under the bead stencils are claimed for the fluid step of parity
+// mark_parity
+void launch_body_predict(const BodyArgs& b, int parity, int mark_parity, hipStream_t s);
 // finish the bodies after MD step k (< substeps - 1) of the fluid step read from
 // step_ptr + step_arg (or step_arg alone when step_ptr is null)
 void launch_body_substep(const BodyArgs& b, const int64_t* step_ptr, int64_t step_arg, int k,

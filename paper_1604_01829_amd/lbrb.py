@@ -26,6 +26,7 @@ LB_ERR_CAPACITY = -5
 LB_PRECISION_F64 = 0
 LB_PRECISION_F32 = 1
 LB_STORES_AUTO, LB_STORES_CACHED, LB_STORES_STREAMING = 0, 1, 2
+LB_STEP_AUTO, LB_STEP_SERIAL, LB_STEP_OVERLAP = 0, 1, 2
 
 # every symbol declared in include/lbrb.h
 EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wall_velocity",
@@ -35,6 +36,7 @@ EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wal
             "lb_rb_step", "lb_observables", "lb_body_count", "rb_bead_forces",
             "lb_export_populations", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
             "lb_set_timing", "lb_kernel_times", "lb_set_store_policy",
+            "lb_set_step_policy", "lb_step_overlapped",
             "lb_adjoint_workspace_bytes", "lb_rb_adjoint",
             "lb_node_counts", "lb_destroy", "lb_last_error"]
 
@@ -144,6 +146,10 @@ def library():
     L.lb_set_timing.argtypes = [_VP, ctypes.c_int32]
     L.lb_set_store_policy.restype = ctypes.c_int
     L.lb_set_store_policy.argtypes = [_VP, ctypes.c_int32]
+    L.lb_set_step_policy.restype = ctypes.c_int
+    L.lb_set_step_policy.argtypes = [_VP, ctypes.c_int32]
+    L.lb_step_overlapped.restype = ctypes.c_int
+    L.lb_step_overlapped.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
     L.lb_kernel_times.restype = ctypes.c_int
     L.lb_kernel_times.argtypes = [_VP, _D, ctypes.POINTER(ctypes.c_int64), _D,
                                   ctypes.POINTER(ctypes.c_int64)]
@@ -388,6 +394,16 @@ class Simulation:
     def set_store_policy(self, policy):
         _check(self.ctx, library().lb_set_store_policy(self.ctx, int(policy)),
                "lb_set_store_policy")
+
+    def set_step_policy(self, policy):
+        _check(self.ctx, library().lb_set_step_policy(self.ctx, int(policy)),
+               "lb_set_step_policy")
+
+    def step_overlapped(self):
+        out = ctypes.c_int32(0)
+        _check(self.ctx, library().lb_step_overlapped(self.ctx, ctypes.byref(out)),
+               "lb_step_overlapped")
+        return bool(out.value)
 
     def set_timing(self, on):
         _check(self.ctx, library().lb_set_timing(self.ctx, 1 if on else 0), "lb_set_timing")

@@ -224,3 +224,22 @@ def test_store_policy_does_not_change_results(precision):
     with pytest.raises(lbrb.LBError):
         gpu = gpu_from_workload(wl, precision=precision)
         gpu.set_store_policy(7)
+
+
+def test_saved_state_does_not_depend_on_the_buffer():
+    """Every byte of a saved state is written: buffers prefilled differently end up equal."""
+    import ctypes
+    import torch
+    wl = _thermal_sphere("f64")
+    sim = gpu_from_workload(wl)
+    sim.step(5)
+    L = lbrb.library()
+    n = ctypes.c_size_t(0)
+    assert L.lb_save_state(sim.ctx, None, ctypes.byref(n)) == lbrb.LB_OK
+    out = []
+    for fill in (0x00, 0xA5):
+        buf = torch.full((n.value,), fill, dtype=torch.uint8, device=sim.device)
+        assert L.lb_save_state(sim.ctx, ctypes.c_void_p(buf.data_ptr()), ctypes.byref(n)) == lbrb.LB_OK
+        out.append(buf.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+    sim.close()
