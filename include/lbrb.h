@@ -290,15 +290,17 @@ int lb_set_store_policy(lb_ctx* ctx, int32_t policy);
 
 /* How a fluid step is launched.  LB_STEP_SERIAL: the bead coupling, then the node update of
  * every tile (whose leading workgroups finish the bodies).  LB_STEP_OVERLAP: two launches
- * that hide the coupling -- (1) the coupling together with the node update of the tiles
- * that receive no spread force in this step, (2) the body finishing together with the node
- * update of the remaining tiles; the body finishing marks the tiles under the next step's
- * bead stencils.  It applies to contexts whose replicas are all masked or all unmasked, with
- * bodies, one MD step per fluid step and no excluded volume; elsewhere the serial step runs.
- * Both give the same results bit for bit.  LB_STEP_AUTO (default): overlapped where it
- * applies.  lb_step_overlapped sets *out to 1 if the next step will be overlapped.  With
- * timing on, both launches of an overlapped step count as node launches and no coupling
- * launch is counted (the coupling runs inside the first).                                 */
+ * that run the coupling concurrently with node updates -- (1) the coupling together with the
+ * node update of the tiles that receive no spread force in this step, (2) the body
+ * finishing together with the node update of the remaining tiles; the body finishing marks
+ * the tiles under the next step's bead stencils.  It applies to contexts whose replicas are
+ * all masked or all unmasked, with bodies, one MD step per fluid step and no excluded
+ * volume; elsewhere the serial step runs.  Both give the same results bit for bit.  On
+ * MI355X the overlapped step is the slower one (launch (1) needs the coupling's registers
+ * for every workgroup, launch (2) waits for the body finishing), so LB_STEP_AUTO (default)
+ * is the serial step.  lb_step_overlapped sets *out to 1 if the next step will be
+ * overlapped.  With timing on, both launches of an overlapped step count as node launches
+ * and no coupling launch is counted (the coupling runs inside the first).                  */
 #define LB_STEP_AUTO 0
 #define LB_STEP_SERIAL 1
 #define LB_STEP_OVERLAP 2

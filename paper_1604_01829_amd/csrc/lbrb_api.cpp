@@ -343,18 +343,20 @@ BodyArgs body_args(const lb_ctx* c)
 bool any_masked(const lb_ctx* c) { return !c->tiles[1].empty(); }
 
 // The overlapped step (coupling alongside the node update of the tiles without spread force)
-// covers one tile group, one MD step per fluid step and no excluded volume; LB_STEP_SERIAL
-// turns it off.
+// covers one tile group, one MD step per fluid step and no excluded volume; it runs only when
+// asked for (LB_STEP_OVERLAP): on the measured workloads it is slower than the serial step.
 bool overlap_possible(const lb_ctx* c)
 {
     const bool one_group = c->tiles[0].empty() != c->tiles[1].empty();
-    const bool wca = c->n_ev > 0 && c->p.wca_epsilon > 0.0;
+    bool wca = false;   // from the host records: the device site tables follow at the next step
+    if (c->p.wca_epsilon > 0.0)
+        for (const EvHost& e : c->ev) wca = wca || !e.off.empty();
     return c->n_beads > 0 && one_group && md_steps(c) == 1 && !wca;
 }
 
 bool use_overlap(const lb_ctx* c)
 {
-    return c->step_policy != LB_STEP_SERIAL && overlap_possible(c);
+    return c->step_policy == LB_STEP_OVERLAP && overlap_possible(c);
 }
 
 EventPair get_pair(lb_ctx* c)

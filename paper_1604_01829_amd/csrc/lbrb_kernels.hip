@@ -189,7 +189,7 @@ __device__ __forceinline__ void write_bead_record(const RecConst& C, const PoseT
 // ------------------------------------------------------------------ tiles under the stencils
 
 // The first claim of global tile gt for the fluid step of parity p appends it to that
-// parity's list.
+// parity's list (used when a workgroup's tile set overflows).
 __device__ __forceinline__ void claim_tile(const TileMarks& tm, int p, int32_t gt)
 {
     const int64_t o = (int64_t)p * tm.n_gt;
@@ -199,9 +199,10 @@ __device__ __forceinline__ void claim_tile(const TileMarks& tm, int p, int32_t g
     }
 }
 
-// LDS set of the tiles one workgroup has claimed (open addressing): a bead stencil's tiles
-// are claimed once per workgroup rather than once per corner.  A full table passes the claim
-// on to the device atomic, which deduplicates as well.
+// LDS set of the tiles one workgroup claims (open addressing, key gt + 1, 0 = empty).  The
+// stencils are first collected here; claim_set then marks the distinct tiles with device
+// atomics issued in parallel and reserves the workgroup's list entries with one atomic.  A
+// full table passes the claim on to claim_tile directly.
 constexpr int kTileSet = 1024;
 
 __device__ __forceinline__ void set_claim(uint32_t* set, const TileMarks& tm, int p, int32_t gt)
@@ -210,14 +211,30 @@ __device__ __forceinline__ void set_claim(uint32_t* set, const TileMarks& tm, in
     int slot = (int)((key * 2654435761u) >> 22) & (kTileSet - 1);
     for (int probe = 0; probe < kTileSet; ++probe) {
         const uint32_t prev = atomicCAS(&set[slot], 0u, key);
-        if (prev == 0u) {
-            claim_tile(tm, p, gt);
-            return;
-        }
-        if (prev == key) return;
+        if (prev == 0u || prev == key) return;
         slot = (slot + 1) & (kTileSet - 1);
     }
     claim_tile(tm, p, gt);
+}
+
+// all threads of the workgroup, after a barrier that follows the last set_claim: mark the
+// set's tiles, append the newly marked ones to the list (fresh: LDS scratch of kTileSet ints,
+// n_fresh: an LDS counter that starts at 0) and clear the set
+__device__ __forceinline__ void claim_set(uint32_t* set, int32_t* fresh, int32_t* n_fresh,
+                                          int32_t* base, const TileMarks& tm, int p)
+{
+    const int64_t o = (int64_t)p * tm.n_gt;
+    for (int k = threadIdx.x; k < kTileSet; k += blockDim.x) {
+        const uint32_t key = set[k];
+        if (key == 0u) continue;
+        set[k] = 0u;
+        const int32_t gt = (int32_t)(key - 1u);
+        if (atomicExch(&tm.mark[o + gt], 1u) == 0u) fresh[atomicAdd(n_fresh, 1)] = gt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && *n_fresh > 0) *base = atomicAdd(&tm.count[p], *n_fresh);
+    __syncthreads();
+    for (int k = threadIdx.x; k < *n_fresh; k += blockDim.x) tm.list[o + *base + k] = fresh[k];
 }
 
 // claim the tiles of the fluid nodes of the trilinear stencil around bead position r: the
@@ -548,6 +565,14 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
         double r[3];
         write_bead_record(C, RP, bd, ba.recs[first + k], r);
         if constexpr (MARK) claim_stencil(C.box, ba.rowinfo, r, tile_set, ba.marks, mark_parity);
+    }
+    if constexpr (MARK) {
+        __shared__ int32_t n_fresh, fresh_base;
+        static_assert(sizeof(pre_off) >= kTileSet * sizeof(int32_t), "scratch for new tiles");
+        if (tid == 0) n_fresh = 0;
+        __syncthreads();   // every claim is in the set, the offsets are no longer needed
+        claim_set(tile_set, reinterpret_cast<int32_t*>(&pre_off[0][0][0]), &n_fresh, &fresh_base,
+                  ba.marks, mark_parity);
     }
 }
 
@@ -989,10 +1014,13 @@ __global__ __launch_bounds__(256) void body_predict_kernel(const BodyArgs ba, in
 {
     __shared__ Pose next;
     __shared__ uint32_t tile_set[kTileSet];
+    __shared__ int32_t fresh[kTileSet];
+    __shared__ int32_t n_fresh, fresh_base;
     Body& B = ba.bodies[blockIdx.x];
     const bool mark = ba.marks.mark != nullptr;
     for (int k = threadIdx.x; k < kTileSet; k += blockDim.x) tile_set[k] = 0u;
     if (threadIdx.x == 0) {
+        n_fresh = 0;
         predict_pose(B, B.pose[parity]);
         next = B.pose[parity];
     }
@@ -1003,6 +1031,10 @@ __global__ __launch_bounds__(256) void body_predict_kernel(const BodyArgs ba, in
         double r[3];
         write_bead_record(C, next, ba.beads[first + k], ba.recs[first + k], r);
         if (mark) claim_stencil(C.box, ba.rowinfo, r, tile_set, ba.marks, mark_parity);
+    }
+    if (mark) {
+        __syncthreads();
+        claim_set(tile_set, fresh, &n_fresh, &fresh_base, ba.marks, mark_parity);
     }
 }
 

@@ -23,6 +23,9 @@ def oracle_from_workload(wl, r=0):
     rep = wl["replicas"][r]
     sim = po.OracleSim(rep["shape"], oracle_params(wl, rep))
     sim._offsets = [np.asarray(bd["offsets"]) for bd in rep["bodies"]]
+    sim._mass_inertia = [(0.0, np.zeros(3)) if bd["fixed"] else
+                         (float(bd["mass"]), np.asarray(bd["inertia"], dtype=float))
+                         for bd in rep["bodies"]]
     if rep["mask"] is not None:
         sim.set_mask(rep["mask"])
     for wall, u in (rep.get("walls") or {}).items():
@@ -91,6 +94,14 @@ def compare(gpu, orc, r=0, n_bodies=None):
         scale["torque"] = max(scale["torque"], gross_t)
         for k in ("vel", "omega"):
             scale[k] = max(scale[k], float(np.abs(so[k]).max()))
+        # velocities integrate the force and torque over the run (V += F/M, omega += T/I per
+        # step): an error of a given fraction of the gross force or torque in every step
+        # bounds their error by that fraction of step * gross / M (or I)
+        mi = getattr(orc, "_mass_inertia", None)
+        if mi is not None and b < len(mi) and mi[b][0] > 0.0:
+            m, inertia = mi[b]
+            scale["vel"] = max(scale["vel"], tg["step"] * gross_f / m)
+            scale["omega"] = max(scale["omega"], tg["step"] * gross_t / float(inertia.min()))
     out.update({"body_" + k: v for k, v in errs.items()})
     out.update({"scale_" + k: v for k, v in scale.items()})
     return out

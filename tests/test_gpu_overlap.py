@@ -122,19 +122,36 @@ def test_body_added_mid_run():
     assert np.array_equal(out[0], out[1])
 
 
+def _overlap_requested(sim):
+    sim.set_step_policy(lbrb.LB_STEP_OVERLAP)
+    return sim.step_overlapped()
+
+
 def test_uncovered_contexts_fall_back_to_the_serial_step():
     from tests.test_gpu_runtime import pore_batch
+    plain = gpu_from_workload(W.workload(1))       # the default is the serial step
+    assert not plain.step_overlapped() and _overlap_requested(plain)
+    plain.close()
     mixed = gpu_from_workload(pore_batch())        # masked and dense replicas
-    assert not mixed.step_overlapped()
+    assert not _overlap_requested(mixed)
     mixed.close()
-    md = gpu_from_workload(W.confined_md_workload(scale=0.25))   # sub-steps and WCA
-    assert not md.step_overlapped()
+    wl = W.workload(1)
+    wl["params"]["md_substeps"] = 2                # MD sub-steps
+    md = gpu_from_workload(wl)
+    assert not _overlap_requested(md)
     md.close()
+    wl = W.workload(1)                             # excluded volume
+    wl["params"]["wca_epsilon"] = 1e-4
+    wl["replicas"][0]["bodies"][0]["ev"] = (W.inner_layer_sphere(3.0), 0.5)
+    ev = gpu_from_workload(wl)
+    assert not _overlap_requested(ev)
+    ev.step(3)
+    ev.close()
     empty = lbrb.simulation_from_workload(dict(name="empty", precision="f32", steps=0,
                                                params=W.default_params(),
                                                replicas=[dict(shape=(8, 8, 8), seed=1,
                                                               mask=None, bodies=[])]))
-    assert not empty.step_overlapped()             # no bodies: nothing to overlap
+    assert not _overlap_requested(empty)           # no bodies: nothing to overlap
     with pytest.raises(lbrb.LBError):
         empty.set_step_policy(9)
     empty.close()
