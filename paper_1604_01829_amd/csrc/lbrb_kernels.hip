@@ -154,32 +154,44 @@ __device__ __forceinline__ RecPose uniform_rec_pose(const Pose& P)
     return r;
 }
 
-// record of bead bd for the step whose pose is P
+// The part of a bead record that follows its body's pose: position, arm r - R and velocity
+// (72 bytes, written as four 16-byte stores and one 8-byte store).  r receives the position.
 template <typename PoseT>
-__device__ __forceinline__ void write_bead_record(const RecConst& C, const PoseT& P,
-                                                  const Bead& bd, BeadRec& o, double r[3])
+__device__ __forceinline__ void write_bead_pose(const PoseT& P, bool fixed, const double off[3],
+                                                BeadRec& o, double r[3])
 {
-    // written field by field: few live registers in the node kernel
-    double dv[3];
+    static_assert(offsetof(BeadRec, r) == 0 && offsetof(BeadRec, dv) == 24 &&
+                  offsetof(BeadRec, v) == 48, "position, arm and velocity lead the record");
+    double dv[3], v[3];
     for (int ax = 0; ax < 3; ++ax) {
-        dv[ax] = P.rot[3 * ax] * bd.off[0] + P.rot[3 * ax + 1] * bd.off[1] +
-                 P.rot[3 * ax + 2] * bd.off[2];
-        o.dv[ax] = dv[ax];
+        dv[ax] = P.rot[3 * ax] * off[0] + P.rot[3 * ax + 1] * off[1] + P.rot[3 * ax + 2] * off[2];
         r[ax] = P.pos[ax] + dv[ax];
-        o.r[ax] = r[ax];
     }
-    if (C.fixed) {
-        o.v[0] = o.v[1] = o.v[2] = 0.0;
+    if (fixed) {
+        v[0] = v[1] = v[2] = 0.0;
     } else {
         const double* w = P.omega_lab;
-        o.v[0] = P.vel[0] + (w[1] * dv[2] - w[2] * dv[1]);
-        o.v[1] = P.vel[1] + (w[2] * dv[0] - w[0] * dv[2]);
-        o.v[2] = P.vel[2] + (w[0] * dv[1] - w[1] * dv[0]);
+        v[0] = P.vel[0] + (w[1] * dv[2] - w[2] * dv[1]);
+        v[1] = P.vel[1] + (w[2] * dv[0] - w[0] * dv[2]);
+        v[2] = P.vel[2] + (w[0] * dv[1] - w[1] * dv[0]);
     }
+    double2* q = reinterpret_cast<double2*>(&o);   // records are 128-byte aligned
+    q[0] = make_double2(r[0], r[1]);
+    q[1] = make_double2(r[2], dv[0]);
+    q[2] = make_double2(dv[1], dv[2]);
+    q[3] = make_double2(v[0], v[1]);
+    o.v[2] = v[2];
+}
+
+// The part of a bead record that stays fixed for the body's lifetime: friction, noise
+// amplitude and stream, replica geometry (written when the pose is predicted from the body
+// state: after the body was added, a mask was set or a state loaded).
+__device__ __forceinline__ void write_bead_const(const RecConst& C, int32_t user, BeadRec& o)
+{
     const BodyBox& X = C.box;
     o.gamma = C.gamma;
     o.noise_amp = C.noise_amp;
-    o.noise_idx = C.first_in_replica + bd.user;   // noise follows the caller's order
+    o.noise_idx = C.first_in_replica + user;   // noise follows the caller's order
     o.row_base = X.row_base;
     o.nx = X.nx; o.ny = X.ny; o.nz = X.nz; o.masked = X.masked;
     o.base = X.base;
@@ -436,8 +448,8 @@ __device__ __forceinline__ void wca_block(const BodyArgs& ba, int b, int parity,
 
 // one workgroup per body: sum the bead forces and torques (shuffle + LDS tree, fixed order),
 // add the excluded-volume force and torque of the MD step, turn the torque into the body
-// frame, second half kick, pose and bead records of the next MD step.  parity: of the MD
-// step being finished.  Two dependent rounds of loads: the body's bead range, then together
+// frame, second half kick, pose of the next MD step and the pose part of its bead records
+// (write_bead_pose).  parity: of the MD step being finished.  Two dependent rounds of loads: the body's bead range, then together
 // the bead forces, each thread's first two bead offsets (parked in LDS), and the step's pose,
 // mass, inertia, dt and excluded-volume sums (one word per lane into LDS).  The next pose is
 // built in LDS, stored by 25 lanes, and read back into scalar registers for the records, so
@@ -475,7 +487,6 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
         cst[tid - kPoseWords] = has_wca ? ba.wca_ft[6 * b + tid - kPoseWords - 7] : 0.0;
     }
     __shared__ double pre_off[kPre][3][256];     // body-frame offsets of each thread's first beads
-    __shared__ int32_t pre_user[kPre][256];
     const double* __restrict__ bf = ba.bead_force;
     const double* __restrict__ bt = ba.bead_torque;
     double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -486,13 +497,11 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
             const int64_t e = 3 * (int64_t)(first + k);
             const Bead& bd = ba.beads[first + k];
             const double o0 = bd.off[0], o1 = bd.off[1], o2 = bd.off[2];
-            const int32_t us = bd.user;
             const double f0 = bf[e], f1 = bf[e + 1], f2 = bf[e + 2];
             const double t0 = bt[e], t1 = bt[e + 1], t2 = bt[e + 2];
             acc[0] += f0; acc[1] += f1; acc[2] += f2;
             acc[3] += t0; acc[4] += t1; acc[5] += t2;
             pre_off[q][0][tid] = o0; pre_off[q][1][tid] = o1; pre_off[q][2][tid] = o2;
-            pre_user[q][tid] = us;
         }
     }
     for (int k = tid + kPre * 256; k < n; k += 256) {
@@ -555,15 +564,15 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
     const RecPose RP = uniform_rec_pose(next);
     const RecConst C = uniform_rec_const(rcs);
     for (int q = 0, k = tid; k < n; ++q, k += 256) {
-        Bead bd;
+        double off[3];
         if (q < kPre) {
-            for (int ax = 0; ax < 3; ++ax) bd.off[ax] = pre_off[q][ax][tid];
-            bd.user = pre_user[q][tid];
+            for (int ax = 0; ax < 3; ++ax) off[ax] = pre_off[q][ax][tid];
         } else {
-            bd = ba.beads[first + k];
+            const Bead& bd = ba.beads[first + k];
+            for (int ax = 0; ax < 3; ++ax) off[ax] = bd.off[ax];
         }
         double r[3];
-        write_bead_record(C, RP, bd, ba.recs[first + k], r);
+        write_bead_pose(RP, C.fixed != 0, off, ba.recs[first + k], r);
         if constexpr (MARK) claim_stencil(C.box, ba.rowinfo, r, tile_set, ba.marks, mark_parity);
     }
     if constexpr (MARK) {
@@ -1028,8 +1037,10 @@ __global__ __launch_bounds__(256) void body_predict_kernel(const BodyArgs ba, in
     const RecConst C = rec_const(B);
     const int first = B.first_bead, n = B.n_beads;
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const Bead bd = ba.beads[first + k];
         double r[3];
-        write_bead_record(C, next, ba.beads[first + k], ba.recs[first + k], r);
+        write_bead_const(C, bd.user, ba.recs[first + k]);
+        write_bead_pose(next, C.fixed != 0, bd.off, ba.recs[first + k], r);
         if (mark) claim_stencil(C.box, ba.rowinfo, r, tile_set, ba.marks, mark_parity);
     }
     if (mark) {
