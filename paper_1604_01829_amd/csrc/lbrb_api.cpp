@@ -42,8 +42,8 @@ struct Plan {
     int gforce_words = 3;     // fixed-point words per node: 3 axes x (1 in FP32, 2 in FP64)
     size_t off_hdr, off_reps, off_rows, off_rowinfo, off_tiles_d, off_tiles_m, off_fa, off_fb,
         off_gforce, off_flags, off_bodies, off_bead_off, off_bead_rec, off_bead_force,
-        off_bead_torque, off_partials, off_links, off_ev, off_sites, off_wrep, off_rep_bodies,
-        off_nb_start, off_nb_idx, off_near, off_wca_ft, off_tmark, off_tlist, off_tcount,
+        off_bead_torque, off_partials, off_links, off_ev, off_wrep, off_rep_bodies,
+        off_nb_start, off_nb_sites, off_near, off_wca_ft, off_tmark, off_tlist, off_tcount,
         off_tile_of, total;
 };
 
@@ -116,12 +116,11 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
     pl.off_partials = take(sizeof(double) * 5 * pl.tiles_cap);
     pl.off_links = take(sizeof(WallLink) * std::max<int64_t>(pl.link_cap, 1));
     pl.off_ev = take(sizeof(EvSite) * std::max<int64_t>(pl.ev_cap, 1));
-    pl.off_sites = take(sizeof(WallSite) * std::max<int64_t>(pl.site_cap, 1));
     pl.off_wrep = take(sizeof(WcaRep) * n);
     pl.off_rep_bodies = take(sizeof(int32_t) * std::max<int64_t>(pl.body_cap, 1));
     pl.off_nb_start = take(sizeof(int32_t) * std::max<int64_t>(pl.cells_cap, 1));
     // a site appears in the neighbourhood lists of at most 27 coarse cells
-    pl.off_nb_idx = take(sizeof(int32_t) * 27 * std::max<int64_t>(pl.site_cap, 1));
+    pl.off_nb_sites = take(sizeof(WallSite) * 27 * std::max<int64_t>(pl.site_cap, 1));
     pl.off_near = take(std::max<int64_t>(pl.fine_cap, 1));
     pl.off_wca_ft = take(sizeof(double) * 6 * std::max<int64_t>(pl.body_cap, 1));
     // overlapped step: tile marks and lists of both parities, global tile -> tile index
@@ -178,11 +177,10 @@ struct lb_ctx {
     WallLink* d_links = nullptr;
     int64_t n_links = 0;
     EvSite* d_ev = nullptr;
-    WallSite* d_sites = nullptr;
     WcaRep* d_wrep = nullptr;
     int32_t* d_rep_bodies = nullptr;
     int32_t* d_nb_start = nullptr;
-    int32_t* d_nb_idx = nullptr;
+    WallSite* d_nb_sites = nullptr;
     uint8_t* d_near = nullptr;
     double* d_wca_ft = nullptr;
     TileMarks marks{};              // overlapped step
@@ -333,9 +331,8 @@ BodyArgs body_args(const lb_ctx* c)
     ba.wrep = c->d_wrep;
     ba.rep_bodies = c->d_rep_bodies;
     ba.nb_start = c->d_nb_start;
-    ba.nb_idx = c->d_nb_idx;
+    ba.nb_sites = c->d_nb_sites;
     ba.near = c->d_near;
-    ba.sites = c->d_sites;
     ba.rowinfo = c->d_rowinfo;
     return ba;
 }
@@ -722,7 +719,8 @@ int build_wca(lb_ctx* c)
     }
     // replicas: body lists and site grids
     std::vector<WcaRep> wr(c->n_rep);
-    std::vector<int32_t> rep_bodies, nb_start, nb_idx;
+    std::vector<int32_t> rep_bodies, nb_start;
+    std::vector<WallSite> nb_sites;   // each coarse cell's neighbourhood, the records in place
     std::vector<WallSite> sites;
     std::vector<uint8_t> near;
     for (int r = 0; r < c->n_rep; ++r) {
@@ -791,7 +789,7 @@ int build_wca(lb_ctx* c)
         for (int z = 0; z < nc[2]; ++z)
             for (int y = 0; y < nc[1]; ++y)
                 for (int x = 0; x < nc[0]; ++x) {
-                    nb_start.push_back((int32_t)nb_idx.size());
+                    nb_start.push_back((int32_t)nb_sites.size());
                     int f0, n0, f1, n1, f2, n2;
                     span(x, nc[0], f0, n0);
                     span(y, nc[1], f1, n1);
@@ -802,10 +800,10 @@ int build_wca(lb_ctx* c)
                                 const auto& bin = bins[(f0 + ix) % nc[0] +
                                                        nc[0] * ((f1 + iy) % nc[1] +
                                                                 nc[1] * ((f2 + iz) % nc[2]))];
-                                nb_idx.insert(nb_idx.end(), bin.begin(), bin.end());
+                                for (int32_t i : bin) nb_sites.push_back(sites[i]);
                             }
                 }
-        nb_start.push_back((int32_t)nb_idx.size());
+        nb_start.push_back((int32_t)nb_sites.size());
         // fine flags: cells whose centre lies within range + half diagonal of a site
         const size_t nfine = (size_t)ng[0] * ng[1] * ng[2];
         std::vector<uint8_t> fl(nfine, 0);
@@ -836,20 +834,17 @@ int build_wca(lb_ctx* c)
         near.insert(near.end(), fl.begin(), fl.end());
     }
     if ((int64_t)nb_start.size() > c->plan.cells_cap || (int64_t)near.size() > c->plan.fine_cap ||
-        (int64_t)nb_idx.size() > 27 * c->plan.site_cap)
+        (int64_t)nb_sites.size() > 27 * c->plan.site_cap)
         return fail(c, LB_ERR_CAPACITY, "WCA site grids exceed their workspace");
     c->n_ev = (int64_t)ev.size();
     if (!ev.empty())
         HIP_TRY(c, hipMemcpyAsync(c->d_ev, ev.data(), sizeof(EvSite) * ev.size(),
                                   hipMemcpyHostToDevice, c->stream));
-    if (!sites.empty())
-        HIP_TRY(c, hipMemcpyAsync(c->d_sites, sites.data(), sizeof(WallSite) * sites.size(),
-                                  hipMemcpyHostToDevice, c->stream));
     if (!nb_start.empty())
         HIP_TRY(c, hipMemcpyAsync(c->d_nb_start, nb_start.data(), sizeof(int32_t) * nb_start.size(),
                                   hipMemcpyHostToDevice, c->stream));
-    if (!nb_idx.empty())
-        HIP_TRY(c, hipMemcpyAsync(c->d_nb_idx, nb_idx.data(), sizeof(int32_t) * nb_idx.size(),
+    if (!nb_sites.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_nb_sites, nb_sites.data(), sizeof(WallSite) * nb_sites.size(),
                                   hipMemcpyHostToDevice, c->stream));
     if (!near.empty())
         HIP_TRY(c, hipMemcpyAsync(c->d_near, near.data(), near.size(), hipMemcpyHostToDevice,
@@ -1050,11 +1045,10 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     c->d_partials = (double*)(c->ws + pl.off_partials);
     c->d_links = (WallLink*)(c->ws + pl.off_links);
     c->d_ev = (EvSite*)(c->ws + pl.off_ev);
-    c->d_sites = (WallSite*)(c->ws + pl.off_sites);
     c->d_wrep = (WcaRep*)(c->ws + pl.off_wrep);
     c->d_rep_bodies = (int32_t*)(c->ws + pl.off_rep_bodies);
     c->d_nb_start = (int32_t*)(c->ws + pl.off_nb_start);
-    c->d_nb_idx = (int32_t*)(c->ws + pl.off_nb_idx);
+    c->d_nb_sites = (WallSite*)(c->ws + pl.off_nb_sites);
     c->d_near = (uint8_t*)(c->ws + pl.off_near);
     c->d_wca_ft = (double*)(c->ws + pl.off_wca_ft);
     c->marks.mark = (uint32_t*)(c->ws + pl.off_tmark);

@@ -375,9 +375,22 @@ __device__ __forceinline__ void wca_block(const BodyArgs& ba, int b, int parity,
                 const int c1 = cell_of(x[1], L[1], W.cw[1], W.cy);
                 const int c2 = cell_of(x[2], L[2], W.cw[2], W.cz);
                 const int cell = W.cell0 + c0 + W.cx * (c1 + W.cy * c2);
+                // the list's records are contiguous: four loads go out together
                 const int i1 = ba.nb_start[cell + 1];
-                for (int i = ba.nb_start[cell]; i < i1; ++i) {
-                    const WallSite ws = ba.sites[ba.nb_idx[i]];
+                int i = ba.nb_start[cell];
+                for (; i + 4 <= i1; i += 4) {
+                    WallSite ws[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) ws[u] = ba.nb_sites[i + u];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        double dd[3];
+                        min_image(x, ws[u].p, L, dd);
+                        wca_add(eps, B.ev_radius + ws[u].radius, dd, F);
+                    }
+                }
+                for (; i < i1; ++i) {
+                    const WallSite ws = ba.nb_sites[i];
                     double dd[3];
                     min_image(x, ws.p, L, dd);
                     wca_add(eps, B.ev_radius + ws.radius, dd, F);
@@ -449,11 +462,12 @@ __device__ __forceinline__ void wca_block(const BodyArgs& ba, int b, int parity,
 // one workgroup per body: sum the bead forces and torques (shuffle + LDS tree, fixed order),
 // add the excluded-volume force and torque of the MD step, turn the torque into the body
 // frame, second half kick, pose of the next MD step and the pose part of its bead records
-// (write_bead_pose).  parity: of the MD step being finished.  Two dependent rounds of loads: the body's bead range, then together
-// the bead forces, each thread's first two bead offsets (parked in LDS), and the step's pose,
-// mass, inertia, dt and excluded-volume sums (one word per lane into LDS).  The next pose is
-// built in LDS, stored by 25 lanes, and read back into scalar registers for the records, so
-// that this code needs fewer registers than the node update it shares a kernel with.
+// (write_bead_pose).  parity: of the MD step being finished.  Two dependent rounds of loads:
+// the body's bead range, then together the bead forces, each thread's first two bead
+// offsets (parked in LDS), and the step's pose, mass, inertia, dt and excluded-volume sums
+// (one word per lane into LDS).  The next pose is built in LDS, stored by 25 lanes, and read
+// back into scalar registers for the records, so that this code needs fewer registers than
+// the node update it shares a kernel with.
 // With MARK, the tiles under the new bead stencils are claimed for the fluid step of parity
 // mark_parity (the overlapped step).
 template <bool MARK>

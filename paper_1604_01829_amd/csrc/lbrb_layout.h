@@ -194,10 +194,9 @@ struct BodyArgs {
     const EvSite* ev;
     const WcaRep* wrep;
     const int32_t* rep_bodies;
-    const int32_t* nb_start;        // per replica cx*cy*cz + 1 entries into nb_idx
-    const int32_t* nb_idx;          // site indices of each coarse cell's neighbourhood
+    const int32_t* nb_start;        // per replica cx*cy*cz + 1 entries into nb_sites
+    const WallSite* nb_sites;       // the static sites of each coarse cell's neighbourhood
     const uint8_t* near;            // fine cells: 1 if a site may be within range
-    const WallSite* sites;
     TileMarks marks;                // with the overlapped step: tiles of the next step's
                                     // bead stencils are claimed here (mark null: not used)
     const RowDesc* rowinfo;         // row table, for the stencil tiles of masked replicas
