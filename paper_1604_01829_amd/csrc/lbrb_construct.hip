@@ -12,11 +12,22 @@
 // "forces from the LDS positions, barrier, kick and drift, barrier" -- no grid-wide
 // synchronisation.  Sixteen wavefronts per shell keep the LDS reads of the pair loop in
 // flight.  Up to kShellsPerLaunch shells go in one launch as a by-value argument.
+//
+// Pairs: a Verlet list per bead (the beads within the cut plus a skin, in ascending index
+// order, in LDS), rebuilt once any bead has moved more than half the skin since the last
+// build.  Walking the list in order adds exactly the nonzero pair terms of the all-pairs loop
+// in the same order, so the WCA sums are the all-pairs sums bit for bit.  The list capacity
+// per bead is the shell's share of kNbSlots (24 for 2048 beads, 90 for 543: thin oblate
+// shells have beads of both faces within the list radius); a bead with more candidates walks
+// all pairs.  Closest point: Newton on a nearly linear transform of
+// F(t) inside the shrinking bisection bracket, started from the bead's parameter of the
+// previous step (one to three iterations where the bisection took about sixty).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 
 #include "../../include/lbrb.h"
@@ -27,6 +38,9 @@ constexpr int kBlock = 1024;
 constexpr int kMaxBeads = 2048;                 // per shell (48 KB of LDS)
 constexpr int kPer = kMaxBeads / kBlock;        // beads per thread
 constexpr int kShellsPerLaunch = 64;
+constexpr int kNbSlots = kMaxBeads * 24;        // list entries per shell (96 KB of LDS)
+constexpr int kNbMax = 128;                     // list capacity per bead at most
+constexpr double kSkin = 0.4;                   // list radius: the WCA cut plus kSkin
 
 struct Shell {
     double axes[3];
@@ -43,26 +57,55 @@ struct RelaxArgs {
     double g;           // eta dt / 2
 };
 
-// closest point of the ellipsoid (semi-axes a, squares a2) to x: bisection of F(t) on
-// (-min a^2, max a |x| + 1] down to the last representable midpoint
+// closest point of the ellipsoid (semi-axes a, squares a2) to x: the root of F(t) on
+// (-min a^2, max a |x| + 1], F decreasing there.  S = F + 1 is a sum of c_k / (t + a_k^2)^2,
+// so G = 1/sqrt(S) - 1 is nearly linear in t (linear on a sphere): Newton on G from t (the
+// previous step's root), inside the bracket that every evaluation shrinks; a step that leaves
+// the bracket becomes the midpoint.  It stops once a step is within the rounding noise of
+// S (64 ulp of max a^2 in t; S itself carries a relative error near 1e-16).  t returns the
+// root.
 __device__ void closest(const double a[3], const double a2[3], double amin2, double amax,
-                        const double x[3], double rs[3])
+                        const double x[3], double& t, double rs[3])
 {
     double lo = -amin2;
     double hi = amax * sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) + 1.0;
-    for (int it = 0; it < 400; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (mid <= lo || mid >= hi) break;
-        double f = 0.0;
+    const double tol = 64.0 * DBL_EPSILON * (amax * amax);
+    if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
+    for (int it = 0; it < 100; ++it) {
+        double S = 0.0, dS = 0.0;
         for (int k = 0; k < 3; ++k) {
-            const double v = x[k] * a[k] / (mid + a2[k]);
-            f += v * v;
+            const double ir = 1.0 / (t + a2[k]);
+            const double v = x[k] * a[k] * ir;
+            S += v * v;
+            dS -= 2.0 * v * v * ir;
         }
-        if (f - 1.0 > 0.0) lo = mid;
-        else hi = mid;
+        if (S == 1.0) break;
+        if (S > 1.0) lo = t;
+        else hi = t;
+        const double rsq = 1.0 / sqrt(S);
+        double tn = t + 2.0 * (rsq - 1.0) * S / (rsq * dS);
+        if (!(fabs(tn - t) > tol)) {
+            if (tn > lo && tn < hi) t = tn;
+            break;
+        }
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        if (!(tn > lo && tn < hi)) break;
+        t = tn;
     }
-    const double t = 0.5 * (lo + hi);
     for (int k = 0; k < 3; ++k) rs[k] = x[k] * a2[k] / (t + a2[k]);
+}
+
+// WCA force of the pair (i, j) on i, added to f (nothing at or beyond the cut)
+__device__ __forceinline__ void pair_force(const double xi[3], const double (*X)[3], int j,
+                                           const RelaxArgs& p, double f[3])
+{
+    const double d[3] = {xi[0] - X[j][0], xi[1] - X[j][1], xi[2] - X[j][2]};
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (!(r2 < p.rc2)) return;
+    const double ir2 = 1.0 / r2;
+    const double u = p.s2 * ir2, u6 = u * u * u;
+    const double coef = p.eps24 * (2.0 * u6 * u6 - u6) * ir2;
+    for (int k = 0; k < 3; ++k) f[k] += coef * d[k];
 }
 
 __global__ __launch_bounds__(kBlock) void relax_kernel(const ShellBatch B, double* pos,
@@ -70,6 +113,7 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const ShellBatch B, doubl
                                                        int n_steps)
 {
     __shared__ double X[kMaxBeads][3];
+    __shared__ uint16_t nb[kNbSlots];
     const Shell S = B.s[blockIdx.x];
     const int n = S.count;
     double a[3], a2[3], amin2 = INFINITY, amax = 0.0;
@@ -79,19 +123,45 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const ShellBatch B, doubl
         amin2 = fmin(amin2, a2[k]);
         amax = fmax(amax, a[k]);
     }
+    const int cap = min(kNbMax, kNbSlots / max(n, 1));   // list entries per bead
+    const double rl = sqrt(p.rc2) + kSkin, rl2 = rl * rl;
+    const double move2 = 0.25 * kSkin * kSkin;       // (skin / 2)^2
     double* P = pos + 3 * (int64_t)S.first;
     double* V = vel + 3 * (int64_t)S.first;
-    double v[kPer][3];
+    double v[kPer][3], xb[kPer][3], t[kPer];
+    int cnt[kPer];                                   // list length; cap + 1: walk all pairs
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int i = threadIdx.x + q * kBlock;
+        t[q] = 0.0;
+        cnt[q] = 0;
         for (int k = 0; k < 3; ++k) {
             v[q][k] = i < n ? V[3 * i + k] : 0.0;
+            xb[q][k] = 0.0;
             if (i < n) X[i][k] = P[3 * i + k];
         }
     }
     __syncthreads();
+    bool rebuild = true;
     for (int step = 0; step < n_steps; ++step) {
+        if (rebuild) {
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int i = threadIdx.x + q * kBlock;
+                if (i >= n) continue;
+                const double xi[3] = {X[i][0], X[i][1], X[i][2]};
+                int c = 0;
+                for (int j = 0; j < n; ++j) {
+                    if (j == i) continue;
+                    const double d0 = xi[0] - X[j][0], d1 = xi[1] - X[j][1], d2 = xi[2] - X[j][2];
+                    if (!(d0 * d0 + d1 * d1 + d2 * d2 < rl2)) continue;
+                    if (c < cap) nb[i * cap + c] = (uint16_t)j;
+                    ++c;
+                }
+                cnt[q] = c <= cap ? c : cap + 1;
+                for (int k = 0; k < 3; ++k) xb[q][k] = xi[k];
+            }
+        }
         double f[kPer][3];
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
@@ -99,31 +169,32 @@ __global__ __launch_bounds__(kBlock) void relax_kernel(const ShellBatch B, doubl
             f[q][0] = f[q][1] = f[q][2] = 0.0;
             if (i >= n) continue;
             const double xi[3] = {X[i][0], X[i][1], X[i][2]};
-            for (int j = 0; j < n; ++j) {
-                if (j == i) continue;
-                const double d[3] = {xi[0] - X[j][0], xi[1] - X[j][1], xi[2] - X[j][2]};
-                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                if (!(r2 < p.rc2)) continue;
-                const double ir2 = 1.0 / r2;
-                const double u = p.s2 * ir2, u6 = u * u * u;
-                const double coef = p.eps24 * (2.0 * u6 * u6 - u6) * ir2;
-                for (int k = 0; k < 3; ++k) f[q][k] += coef * d[k];
+            if (cnt[q] <= cap) {
+                for (int m = 0; m < cnt[q]; ++m) pair_force(xi, X, nb[i * cap + m], p, f[q]);
+            } else {
+                for (int j = 0; j < n; ++j)
+                    if (j != i) pair_force(xi, X, j, p, f[q]);
             }
             double rs[3];
-            closest(a, a2, amin2, amax, xi, rs);
+            closest(a, a2, amin2, amax, xi, t[q], rs);
             for (int k = 0; k < 3; ++k) f[q][k] -= p.k2 * (xi[k] - rs[k]);
         }
         __syncthreads();
+        bool moved = false;
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int i = threadIdx.x + q * kBlock;
             if (i >= n) continue;
+            double dd = 0.0;
             for (int k = 0; k < 3; ++k) {
                 v[q][k] = ((1.0 - p.g) * v[q][k] + p.dt * f[q][k] / p.m) / (1.0 + p.g);
                 X[i][k] += p.dt * v[q][k];
+                const double e = X[i][k] - xb[q][k];
+                dd += e * e;
             }
+            moved = moved || !(dd <= move2);
         }
-        __syncthreads();
+        rebuild = __syncthreads_or(moved) != 0;
     }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {

@@ -3,7 +3,9 @@
 - a shell on an ellipsoid from a jittered start, 400 steps: every position against the oracle;
 - several shells of different sizes in one call, and 70 tiny shells (two launches of 64 and 6
   workgroups): each against its own oracle run;
-- the largest shell (2048 beads), a few steps;
+- the largest shell (2048 beads), a few steps; a crowded 2048-bead shell whose beads have more
+  pair candidates than their list holds (they walk all pairs); a thin oblate shell whose two
+  faces are within the list radius of each other;
 - the tetrahedron end state of four beads on a small sphere;
 - a two-layer filled raspberry (prolate 8,4,4 at one bead per unit area): both shells on their
   surfaces with nearly even spacing, interior points inside the inner shell.
@@ -80,6 +82,26 @@ def test_largest_shell():
     init = C.initial_shell(R, R, R, 2048, seed=2, jitter=0.05)
     (g,) = _gpu([(R, R, R)], [init], 20)
     _close(g, _oracle((R, R, R), init, 20), 1e-12, "2048 beads")
+
+
+def test_crowded_shell_walks_all_pairs():
+    """2048 beads on a radius-7 sphere (0.3 units of area each): a bead has about 30 others
+    within the pair list's radius, more than the 24 entries a 2048-bead shell gets, so the
+    beads walk all pairs; a weak repulsion keeps the start's overlaps tame."""
+    R = 7.0
+    prm = dict(FAST, epsilon=1e-6)
+    init = C.initial_shell(R, R, R, 2048, seed=5, jitter=0.02)
+    (g,), _ = C.relax_shells([(R, R, R)], [init], prm, 30)
+    _close(g, _oracle((R, R, R), init, 30, prm), 1e-12, "crowded 2048 beads")
+
+
+def test_thin_oblate_shell():
+    """Beads of both faces of a thin oblate shell are within the list radius of each other
+    (up to 30 candidates; a 475-bead shell gets lists of 103)."""
+    axes = (0.42, 8.66, 8.66)
+    init = C.separated_shell(*axes, C.shell_count(*axes), seed=1)
+    (g,), _ = C.relax_shells([axes], [init], n_steps=600)
+    _close(g, _oracle(axes, init, 600, C.DEFAULT_PARAMS), 1e-9, "thin oblate shell")
 
 
 def test_tetrahedron():
