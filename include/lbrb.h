@@ -231,8 +231,9 @@ int lb_traj_binned_msd(const double* series, const double* radial, int32_t n_fra
  * beads repel with the WCA pair potential (sigma, epsilon; cut at 2^(1/6) sigma) and each is
  * held to the closest point r_s of its shell's ellipsoid (semi-axes axes[s][0..2] along the
  * body x, y, z) by U = k_surface |r - r_s|^2; r_s = x a^2 / (t + a^2) per axis with t the
- * root of F(t) = sum (x a / (t + a^2))^2 - 1 on (-min a^2, inf), found by bisection.
- * Integration: v <- ((1 - g) v + dt F / mass) / (1 + g), g = damping dt / 2, then
+ * root of F(t) = sum (x a / (t + a^2))^2 - 1 on (-min a^2, inf) (bracketed Newton, to the
+ * rounding noise of F).  Each bead's pair forces are summed over a pair list in index order,
+ * the same terms in the same order as over all beads.  Integration: v <- ((1 - g) v + dt F / mass) / (1 + g), g = damping dt / 2, then
  * r <- r + dt v (the paper's script: leapfrog, damping 1000, dt 0.001, sigma 1.4,
  * epsilon 0.1).  axes (n_shells*3) and counts (n_shells, each 1..2048) are host arrays; the
  * shells' beads are packed one after another in the device arrays dev_pos and dev_vel
