@@ -327,12 +327,15 @@ __device__ __forceinline__ void block_sum6(double acc[6], double (*part)[6], dou
         for (int k = 0; k < 6; ++k) out[k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
 }
 
-// LDS of one excluded-volume workgroup: the other bodies in range, 64 at a time
+// LDS of one excluded-volume workgroup: the other bodies in range, 64 at a time; the sites
+// near static sites of one pass of 256, compacted in site order
 struct WcaLds {
     double pose[64][13];         // centre, rotation matrix, site radius
     int32_t site0[64], nsite[64];
     int32_t n;
     double part[4][6];
+    double flagged[256][6];      // lab position and arm of each flagged site
+    int32_t wave_count[4];
 };
 
 // lab position of a body-frame offset at a pose given as centre + row-major rotation
@@ -361,44 +364,69 @@ __device__ __forceinline__ void wca_block(const BodyArgs& ba, int b, int parity,
         const WcaRep W = ba.wrep[B.replica];
         const double L[3] = {(double)B.box.nx, (double)B.box.ny, (double)B.box.nz};
         const double eps = ba.wca_eps;
-        // static sites: the fine flag, then one contiguous list of the coarse cell's
-        // neighbourhood
+        // static sites, 256 per pass: the fine flag of each; the flagged ones are compacted
+        // in site order (wave ballots, then the waves' offsets) and each is walked by eight
+        // lanes over the coarse cell's neighbourhood list (entries l, l + 8, ...; the eight
+        // partial forces combined in a fixed butterfly), the group's first lane adding the
+        // site's force and torque
         if (W.cx > 0) {
-            for (int k = threadIdx.x; k < B.n_ev; k += blockDim.x) {
-                double d[3], x[3], F[3] = {0.0, 0.0, 0.0};
-                site_at(P.pos, P.rot, ba.ev[B.first_ev + k].off, d, x);
-                const int g0 = cell_of(x[0], L[0], W.fw[0], W.gx);
-                const int g1 = cell_of(x[1], L[1], W.fw[1], W.gy);
-                const int g2 = cell_of(x[2], L[2], W.fw[2], W.gz);
-                if (!ba.near[W.fine0 + g0 + W.gx * (g1 + W.gy * g2)]) continue;
-                const int c0 = cell_of(x[0], L[0], W.cw[0], W.cx);
-                const int c1 = cell_of(x[1], L[1], W.cw[1], W.cy);
-                const int c2 = cell_of(x[2], L[2], W.cw[2], W.cz);
-                const int cell = W.cell0 + c0 + W.cx * (c1 + W.cy * c2);
-                // the list's records are contiguous: four loads go out together
-                const int i1 = ba.nb_start[cell + 1];
-                int i = ba.nb_start[cell];
-                for (; i + 4 <= i1; i += 4) {
-                    WallSite ws[4];
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            const int grp = threadIdx.x >> 3, sub = threadIdx.x & 7;
+            for (int k0 = 0; k0 < B.n_ev; k0 += blockDim.x) {
+                const int k = k0 + threadIdx.x;
+                double d[3] = {0.0, 0.0, 0.0}, x[3] = {0.0, 0.0, 0.0};
+                bool flag = false;
+                if (k < B.n_ev) {
+                    site_at(P.pos, P.rot, ba.ev[B.first_ev + k].off, d, x);
+                    const int g0 = cell_of(x[0], L[0], W.fw[0], W.gx);
+                    const int g1 = cell_of(x[1], L[1], W.fw[1], W.gy);
+                    const int g2 = cell_of(x[2], L[2], W.fw[2], W.gz);
+                    flag = ba.near[W.fine0 + g0 + W.gx * (g1 + W.gy * g2)] != 0;
+                }
+                const unsigned long long mask = __ballot(flag);
+                if (lane == 0) S.wave_count[wave] = __popcll(mask);
+                __syncthreads();
+                int pos = __popcll(mask & ((1ull << lane) - 1ull)), nflag = 0;
+                for (int w = 0; w < 4; ++w) {
+                    if (w < wave) pos += S.wave_count[w];
+                    nflag += S.wave_count[w];
+                }
+                if (flag)
+                    for (int t = 0; t < 3; ++t) {
+                        S.flagged[pos][t] = x[t];
+                        S.flagged[pos][3 + t] = d[t];
+                    }
+                __syncthreads();
+                for (int c0 = 0; c0 < nflag; c0 += 32) {
+                    const int f = c0 + grp;
+                    double F[3] = {0.0, 0.0, 0.0};
+                    double xs[3] = {0.0, 0.0, 0.0};
+                    if (f < nflag) {
+                        for (int t = 0; t < 3; ++t) xs[t] = S.flagged[f][t];
+                        const int c0c = cell_of(xs[0], L[0], W.cw[0], W.cx);
+                        const int c1c = cell_of(xs[1], L[1], W.cw[1], W.cy);
+                        const int c2c = cell_of(xs[2], L[2], W.cw[2], W.cz);
+                        const int cell = W.cell0 + c0c + W.cx * (c1c + W.cy * c2c);
+                        const int i1 = ba.nb_start[cell + 1];
+                        for (int i = ba.nb_start[cell] + sub; i < i1; i += 8) {
+                            const WallSite ws = ba.nb_sites[i];
+                            double dd[3];
+                            min_image(xs, ws.p, L, dd);
+                            wca_add(eps, B.ev_radius + ws.radius, dd, F);
+                        }
+                    }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) ws[u] = ba.nb_sites[i + u];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        double dd[3];
-                        min_image(x, ws[u].p, L, dd);
-                        wca_add(eps, B.ev_radius + ws[u].radius, dd, F);
+                    for (int m = 1; m < 8; m <<= 1)
+                        for (int t = 0; t < 3; ++t) F[t] += __shfl_xor(F[t], m, 8);
+                    if (f < nflag && sub == 0) {
+                        const double* ds = &S.flagged[f][3];
+                        acc[0] += F[0]; acc[1] += F[1]; acc[2] += F[2];
+                        acc[3] += ds[1] * F[2] - ds[2] * F[1];
+                        acc[4] += ds[2] * F[0] - ds[0] * F[2];
+                        acc[5] += ds[0] * F[1] - ds[1] * F[0];
                     }
                 }
-                for (; i < i1; ++i) {
-                    const WallSite ws = ba.nb_sites[i];
-                    double dd[3];
-                    min_image(x, ws.p, L, dd);
-                    wca_add(eps, B.ev_radius + ws.radius, dd, F);
-                }
-                acc[0] += F[0]; acc[1] += F[1]; acc[2] += F[2];
-                acc[3] += d[1] * F[2] - d[2] * F[1];
-                acc[4] += d[2] * F[0] - d[0] * F[2];
-                acc[5] += d[0] * F[1] - d[1] * F[0];
+                __syncthreads();
             }
         }
         // other bodies, 64 candidates at a time
@@ -843,7 +871,7 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
 
 // The coupling launch.  With excluded volume (WCA), the first n_wca workgroups (a multiple of
 // 8, so that the bead workgroups keep their XCD pattern) compute each body's WCA force and
-// torque for the same MD step instead (wca_block); they use the LDS of the force sums.
+// torque for the same MD step instead (wca_block); they use the coupling's LDS.
 // Without it the kernel is compiled without that code (its registers stay those of the
 // coupling alone).
 template <typename Real, bool WCA>
@@ -852,12 +880,12 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Rea
                                                               const BodyArgs ba, int n_wca)
 {
     __shared__ CoupleLds<Real> L;
-    static_assert(sizeof(L.acc) >= sizeof(WcaLds), "excluded-volume LDS fits in the force sums");
+    static_assert(sizeof(L) >= sizeof(WcaLds), "excluded-volume LDS fits in the coupling's");
     if (WCA && (int)blockIdx.x < n_wca) {
         if ((int)blockIdx.x < ba.n_bodies) {
             const int64_t step = current_step(a.step_ptr, a.step_arg);
             wca_block(ba, blockIdx.x, (int)((step * ba.substeps + c.md_step) & 1),
-                      *reinterpret_cast<WcaLds*>(&L.acc[0][0]));
+                      *reinterpret_cast<WcaLds*>(&L));
         }
         return;
     }
