@@ -122,23 +122,19 @@ __device__ __forceinline__ int32_t uniform_int(int32_t x)
     return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
 }
 
-__device__ __forceinline__ RecConst uniform_rec_const(const RecConst& c)
+__device__ __forceinline__ BodyBox uniform_box(const BodyBox& c)
 {
-    RecConst r;
-    r.gamma = uniform_value(c.gamma);
-    r.noise_amp = uniform_value(c.noise_amp);
-    r.first_in_replica = uniform_int(c.first_in_replica);
-    r.fixed = uniform_int(c.fixed);
-    r.box.nx = uniform_int(c.box.nx);
-    r.box.ny = uniform_int(c.box.ny);
-    r.box.nz = uniform_int(c.box.nz);
-    r.box.masked = uniform_int(c.box.masked);
-    r.box.base = (int64_t)(((uint64_t)(uint32_t)uniform_int((int32_t)(c.box.base >> 32)) << 32) |
-                           (uint32_t)uniform_int((int32_t)c.box.base));
-    r.box.row_base = uniform_int(c.box.row_base);
-    r.box.key0 = (uint32_t)uniform_int((int32_t)c.box.key0);
-    r.box.key1 = (uint32_t)uniform_int((int32_t)c.box.key1);
-    r.box.pad = 0;
+    BodyBox r;
+    r.nx = uniform_int(c.nx);
+    r.ny = uniform_int(c.ny);
+    r.nz = uniform_int(c.nz);
+    r.masked = uniform_int(c.masked);
+    r.base = (int64_t)(((uint64_t)(uint32_t)uniform_int((int32_t)(c.base >> 32)) << 32) |
+                       (uint32_t)uniform_int((int32_t)c.base));
+    r.row_base = uniform_int(c.row_base);
+    r.key0 = (uint32_t)uniform_int((int32_t)c.key0);
+    r.key1 = (uint32_t)uniform_int((int32_t)c.key1);
+    r.pad = 0;
     return r;
 }
 
@@ -514,9 +510,9 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
     const Body& B = ba.bodies[b];
     const int first = B.first_bead, n = B.n_beads;
     const int tid = threadIdx.x;
-    __shared__ RecConst rcs;
+    __shared__ BodyBox box;                       // the replica's geometry, for the claims
     const int fixed = B.fixed;
-    if (tid == 64) rcs = rec_const(B);
+    if (MARK && tid == 64) box = B.box;
     __shared__ uint32_t tile_set[MARK ? kTileSet : 1];
     if constexpr (MARK)
         for (int k = tid; k < kTileSet; k += 256) tile_set[k] = 0u;
@@ -604,7 +600,8 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
     if (tid < kPoseWords)
         reinterpret_cast<double*>(&o.pose[parity ^ 1])[tid] = reinterpret_cast<const double*>(&next)[tid];
     const RecPose RP = uniform_rec_pose(next);
-    const RecConst C = uniform_rec_const(rcs);
+    BodyBox X{};
+    if constexpr (MARK) X = uniform_box(box);
     for (int q = 0, k = tid; k < n; ++q, k += 256) {
         double off[3];
         if (q < kPre) {
@@ -614,8 +611,8 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
             for (int ax = 0; ax < 3; ++ax) off[ax] = bd.off[ax];
         }
         double r[3];
-        write_bead_pose(RP, C.fixed != 0, off, ba.recs[first + k], r);
-        if constexpr (MARK) claim_stencil(C.box, ba.rowinfo, r, tile_set, ba.marks, mark_parity);
+        write_bead_pose(RP, fixed != 0, off, ba.recs[first + k], r);
+        if constexpr (MARK) claim_stencil(X, ba.rowinfo, r, tile_set, ba.marks, mark_parity);
     }
     if constexpr (MARK) {
         __shared__ int32_t n_fresh, fresh_base;
