@@ -6,6 +6,10 @@
 - 512 uneven pore replicas with one ellipsoid each, FP32 thermal, all in one batch: sampled
   replicas against independent oracle boxes, and graph replay of 100 steps against eager
   launches, bit for bit.
+- the benchmark's pore (128 x 128 x 256, radius 40, 32 spheres, FP32 thermal) in its timed
+  launch configuration (one graph replay of 100 steps): whole fields and every body against
+  the oracle; the same pore with the paper's integration scheme (2 MD steps per fluid step,
+  inner excluded-volume layers, pore beads) over 4 steps in graph replays of 2.
 """
 import numpy as np
 import pytest
@@ -196,3 +200,31 @@ def test_512_cubed_first_step_sampled(precision, masked):
         assert err_rho < 1e-6 and err_u < 1e-5 * scale_u
     if masked:
         assert np.all(f[mask.astype(bool)] == 0.0)
+
+
+def test_pore_128_in_the_benchmark_configuration():
+    wl = W.workload(2)
+    gpu = gpu_from_workload(wl)
+    gpu.set_graph_steps(100)
+    gpu.step(100)
+    orc = oracle_from_workload(wl)
+    orc.step(100)
+    e = _field_errors(gpu, orc)
+    print("  pore 128x128x256 FP32, 100 steps:",
+          {k: f"{v:.3g}" for k, v in e.items() if isinstance(v, float)}, flush=True)
+    _check(e, 1e-5, 1e-6, 1e-6)
+    gpu.close()
+
+
+def test_confined_md_full_size():
+    wl = W.confined_md_workload(substeps=2)
+    gpu = gpu_from_workload(wl)
+    gpu.set_graph_steps(2)
+    gpu.step(4)
+    orc = oracle_from_workload(wl)
+    orc.step(4)
+    e = _field_errors(gpu, orc)
+    print("  confined MD 128x128x256 FP32, 4 steps:",
+          {k: f"{v:.3g}" for k, v in e.items() if isinstance(v, float)}, flush=True)
+    _check(e, 1e-5, 1e-6, 1e-6)
+    gpu.close()
