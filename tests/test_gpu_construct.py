@@ -127,3 +127,22 @@ def test_two_layer_filled_raspberry():
         assert max(off) < 0.05 and nn.std() < 0.1 * nn.mean()
     f = rb["fill"]
     assert len(f) > 0 and np.all((f[:, 0] / 7.5) ** 2 + (f[:, 1] / 3.5) ** 2 + (f[:, 2] / 3.5) ** 2 < 1)
+
+
+def test_the_papers_thirty_shells():
+    """The construction benchmark's configuration: the paper's 15 ellipsoids of revolution of
+    equal volume (aspect ratios 1/10 to 10), outer and inner shells at one bead per unit area,
+    relaxed together in one launch at the default parameters; every shell against its own
+    oracle run over 200 steps."""
+    phis = [1 / 10, 1 / 5, 1 / 4, 1 / 3, 1 / 2, 2 / 3, 4 / 5, 9 / 10, 10 / 9, 5 / 4, 3 / 2, 2, 4,
+            5, 10]
+    axes, init = [], []
+    for k, phi in enumerate(phis):
+        bb = (4.25 ** 3 / phi) ** (1 / 3)
+        for d in (0.0, 0.5):
+            ax = (phi * bb - d, bb - d, bb - d)
+            axes.append(ax)
+            init.append(C.separated_shell(*ax, C.shell_count(*ax), seed=k))
+    got, _ = C.relax_shells(axes, init, n_steps=200)
+    for k, (ax, x0, g) in enumerate(zip(axes, init, got)):
+        _close(g, _oracle(ax, x0, 200, C.DEFAULT_PARAMS), 1e-9, f"shell {k} {len(x0)} beads")
