@@ -258,6 +258,39 @@ def compare_runs(args):
     out["construction"] = {"shells": len(axes), "beads": int(sum(len(p) for p in init)),
                            "steps": 20000, "seconds": round(t_c, 3),
                            "us_per_step": round(t_c / 20000 * 1e6, 2)}
+    # trajectory analysis: 32 bodies, 20,000 frames (seeded synthetic poses around the pore
+    # axis), 1000 lags of every MSD
+    from paper_1604_01829_amd import analysis as AN
+    F, NB, LAGS = 20000, 32, 1000
+    traj = torch.as_tensor(W.synthetic_trajectory(F, NB, seed=5, centre=(64.0, 64.0),
+                                                  radius=(2.0, 30.0)), device="cuda:0").contiguous()
+    ref = np.tile([1.0, 0.0, 0.0], (NB, 1))
+    edges = np.linspace(0.0, 32.0, 9)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3
+
+    lab, t_lab = timed(lambda: AN.lab_frame(traj))
+    _, t_msd3 = timed(lambda: AN.msd(lab, LAGS))
+    bod, t_body = timed(lambda: AN.body_frame(traj))
+    _, t_msd6 = timed(lambda: AN.msd(bod, LAGS))
+    _, t_rot = timed(lambda: AN.rotation_msd(traj, ref, LAGS))
+    (pf, rad), t_pore = timed(lambda: AN.pore_frame(traj, (64.0, 64.0)))
+    _, t_bin = timed(lambda: AN.binned_msd(pf, rad, edges, LAGS))
+    terms = NB * sum(F - k for k in range(1, LAGS + 1))      # (origin, lag) pairs per body set
+    out["analysis"] = {"bodies": NB, "frames": F, "lags": LAGS,
+                       "lab_frame_ms": round(t_lab, 3), "msd_lab_ms": round(t_msd3, 3),
+                       "body_frame_ms": round(t_body, 3), "msd_body_ms": round(t_msd6, 3),
+                       "rotation_msd_ms": round(t_rot, 3), "pore_frame_ms": round(t_pore, 3),
+                       "binned_msd_ms": round(t_bin, 3),
+                       "msd_lab_gterms_per_s": round(terms * 3 / (t_msd3 * 1e-3) / 1e9, 1)}
+    del traj, lab, bod, pf, rad
+    torch.cuda.empty_cache()
     # reverse pass on the fixed sphere in uniform flow
     wl5 = W.workload(5)
     wl5["params"]["kT"] = 0.0
