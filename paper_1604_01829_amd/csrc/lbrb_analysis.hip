@@ -177,59 +177,111 @@ __global__ __launch_bounds__(kBlock) void cumulate_kernel(const double* __restri
 
 // ------------------------------------------------------------------ MSDs
 
-// grid (lag, body): mean over origins of the squared increment of each component
+// The MSD and rotational MSD kernels: one workgroup per block of kLagBlock consecutive lags
+// and per body.  The origins are staged kChunk at a time in LDS together with the frames
+// the block's lags reach from them, so each frame is read from memory about twice per block
+// instead of twice per (origin, lag).  Thread (l, ph) accumulates lag lag0 + l + 1 over the
+// origins t = ph mod 4 in increasing order; the four phases are then added in a fixed order.
+constexpr int kLagBlock = 64;
+constexpr int kChunk = 256;
+constexpr int kPhases = kBlock / kLagBlock;
+static_assert(kPhases == 4, "four origin phases per lag");
+
+// stage frames f0 .. f0 + n - 1 of a body-major series (K values per frame) into T; frames
+// at or beyond n_frames read as zero
+template <int K>
+__device__ __forceinline__ void stage(const double* __restrict__ sb, int64_t f0, int n,
+                                      int n_frames, double (*T)[K])
+{
+    for (int e = threadIdx.x; e < n * K; e += kBlock) {
+        const int64_t f = f0 + e / K;
+        T[e / K][e % K] = f < n_frames ? sb[f * K + e % K] : 0.0;
+    }
+}
+
+// grid (lag block, body): mean over origins of the squared increment of each component
 template <int K>
 __global__ __launch_bounds__(kBlock) void msd_kernel(const double* __restrict__ s, int n_frames,
                                                      int n_lags, double* __restrict__ out)
 {
-    __shared__ double part[4][K];
-    const int tau = blockIdx.x + 1, b = blockIdx.y;
+    __shared__ double A[kChunk][K];                       // origins t0 ..
+    __shared__ double Bt[kChunk + kLagBlock - 1][K];      // frames t0 + lag0 + 1 ..
+    __shared__ double part[kPhases][kLagBlock][K];
+    const int lag0 = blockIdx.x * kLagBlock, b = blockIdx.y;
+    const int l = threadIdx.x % kLagBlock, ph = threadIdx.x / kLagBlock;
+    const int tau = lag0 + l + 1;
     const double* sb = s + (int64_t)b * n_frames * K;
     double acc[K];
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
-    for (int64_t t = threadIdx.x; t + tau < n_frames; t += kBlock)
+    for (int64_t t0 = 0; t0 + lag0 + 1 < n_frames; t0 += kChunk) {
+        __syncthreads();
+        stage<K>(sb, t0, kChunk, n_frames, A);
+        stage<K>(sb, t0 + lag0 + 1, kChunk + kLagBlock - 1, n_frames, Bt);
+        __syncthreads();
+        for (int o = ph; o < kChunk && t0 + o + tau < n_frames; o += kPhases)
+            for (int k = 0; k < K; ++k) {
+                const double d = Bt[o + l][k] - A[o][k];
+                acc[k] += d * d;
+            }
+    }
+    for (int k = 0; k < K; ++k) part[ph][l][k] = acc[k];
+    __syncthreads();
+    if (ph == 0 && tau <= n_lags)
         for (int k = 0; k < K; ++k) {
-            const double d = sb[(t + tau) * K + k] - sb[t * K + k];
-            acc[k] += d * d;
+            const double v = (part[0][l][k] + part[1][l][k]) + (part[2][l][k] + part[3][l][k]);
+            out[((int64_t)b * n_lags + tau - 1) * K + k] = v / (double)(n_frames - tau);
         }
-    block_sum<K>(acc, part);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < K; ++k)
-            out[((int64_t)b * n_lags + blockIdx.x) * K + k] = acc[k] / (double)(n_frames - tau);
 }
 
-// grid (lag, body): mean over origins of the squared angle between the reference vectors
+// grid (lag block, body): mean over origins of the squared angle between the reference
+// vectors; the unit vectors R(q) r / |R(q) r| are computed once per staged frame
 __global__ __launch_bounds__(kBlock) void rotation_msd_kernel(const double* __restrict__ traj,
                                                               int n_frames, int n_bodies,
                                                               const double* __restrict__ ref,
                                                               int n_lags, double* __restrict__ out)
 {
-    __shared__ double part[4][1];
-    const int tau = blockIdx.x + 1, b = blockIdx.y;
+    __shared__ double A[kChunk][3];
+    __shared__ double Bt[kChunk + kLagBlock - 1][3];
+    __shared__ double part[kPhases][kLagBlock];
+    const int lag0 = blockIdx.x * kLagBlock, b = blockIdx.y;
+    const int l = threadIdx.x % kLagBlock, ph = threadIdx.x / kLagBlock;
+    const int tau = lag0 + l + 1;
     const double r[3] = {ref[3 * b], ref[3 * b + 1], ref[3 * b + 2]};
-    auto unit = [&](int64_t f, double p[3]) {
+    auto unit = [&](int64_t f, double* p) {
+        if (f >= n_frames) { p[0] = p[1] = p[2] = 0.0; return; }
         double R[9];
         rot_of(traj + 7 * (f * n_bodies + b) + 3, R);
         for (int a = 0; a < 3; ++a) p[a] = R[3 * a] * r[0] + R[3 * a + 1] * r[1] + R[3 * a + 2] * r[2];
         const double n = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
         for (int a = 0; a < 3; ++a) p[a] /= n;
     };
-    double acc[1] = {0.0};
-    for (int64_t t = threadIdx.x; t + tau < n_frames; t += kBlock) {
-        double p0[3], p1[3];
-        unit(t, p0);
-        unit(t + tau, p1);
-        double c = p0[0] * p1[0] + p0[1] * p1[1] + p0[2] * p1[2];
-        c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
-        const double th = acos(c);
-        acc[0] += th * th;
+    double acc = 0.0;
+    for (int64_t t0 = 0; t0 + lag0 + 1 < n_frames; t0 += kChunk) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kChunk; e += kBlock) unit(t0 + e, A[e]);
+        for (int e = threadIdx.x; e < kChunk + kLagBlock - 1; e += kBlock)
+            unit(t0 + lag0 + 1 + e, Bt[e]);
+        __syncthreads();
+        for (int o = ph; o < kChunk && t0 + o + tau < n_frames; o += kPhases) {
+            const double* p0 = A[o];
+            const double* p1 = Bt[o + l];
+            double c = p0[0] * p1[0] + p0[1] * p1[1] + p0[2] * p1[2];
+            c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+            const double th = acos(c);
+            acc += th * th;
+        }
     }
-    block_sum<1>(acc, part);
-    if (threadIdx.x == 0) out[(int64_t)b * n_lags + blockIdx.x] = acc[0] / (double)(n_frames - tau);
+    part[ph][l] = acc;
+    __syncthreads();
+    if (ph == 0 && tau <= n_lags)
+        out[(int64_t)b * n_lags + tau - 1] =
+            ((part[0][l] + part[1][l]) + (part[2][l] + part[3][l])) / (double)(n_frames - tau);
 }
 
 // grid (lag, bin): sums of the squared increments from the origins whose radial coordinate
-// lies in [edges[bin], edges[bin+1]), over all bodies, and their count
+// lies in [edges[bin], edges[bin+1]), over all bodies, and their count (one workgroup per lag:
+// staging all frames for a block of lags would repeat for every bin, and the grid of lag
+// blocks times bins is too small to fill the GPU)
 template <int K>
 __global__ __launch_bounds__(kBlock) void binned_msd_kernel(const double* __restrict__ s,
                                                             const double* __restrict__ radial,
@@ -321,7 +373,7 @@ int lb_traj_msd(const double* series, int32_t n_frames, int32_t n_bodies, int32_
     if (!frames_ok(series, n_frames, n_bodies) || !out || k < 1 || k > 6 || n_lags < 1 ||
         n_lags >= n_frames || n_bodies > 65535)
         return LB_ERR_ARG;
-    const dim3 grid(n_lags, n_bodies);
+    const dim3 grid((n_lags + kLagBlock - 1) / kLagBlock, n_bodies);
     hipStream_t s = (hipStream_t)stream;
     switch (k) {
     case 1: hipLaunchKernelGGL((msd_kernel<1>), grid, dim3(kBlock), 0, s, series, n_frames, n_lags, out); break;
@@ -340,7 +392,8 @@ int lb_traj_rotation_msd(const double* traj, int32_t n_frames, int32_t n_bodies,
     if (!frames_ok(traj, n_frames, n_bodies) || !ref_body || !out || n_lags < 1 ||
         n_lags >= n_frames || n_bodies > 65535)
         return LB_ERR_ARG;
-    hipLaunchKernelGGL(rotation_msd_kernel, dim3(n_lags, n_bodies), dim3(kBlock), 0,
+    hipLaunchKernelGGL(rotation_msd_kernel, dim3((n_lags + kLagBlock - 1) / kLagBlock, n_bodies),
+                       dim3(kBlock), 0,
                        (hipStream_t)stream, traj, n_frames, n_bodies, ref_body, n_lags, out);
     return launched();
 }
