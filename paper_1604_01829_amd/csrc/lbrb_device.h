@@ -58,6 +58,29 @@ __device__ __forceinline__ void locate(const ReplicaDesc& R, const RowDesc* __re
     }
 }
 
+// locate for a whole workgroup of a node tile (every thread calls it; a barrier inside for
+// masked replicas): the descriptors of the rows the tile overlaps are loaded once into LDS
+// (tile_rows, kNodeBlock entries: a tile of at most kNodeBlock nodes overlaps at most that many
+// non-empty rows) and searched there instead of in global memory
+template <bool MASKED>
+__device__ __forceinline__ void locate_tile(const ReplicaDesc& R, const RowDesc* __restrict__ rows,
+                                            const NodeTile& t, int64_t local, RowDesc* tile_rows,
+                                            int& x, int& y, int& z, RowDesc& self)
+{
+    if constexpr (MASKED) {
+        const int nr = t.row_hi - t.row_lo + 1;
+        if (nr <= kNodeBlock) {
+            if ((int)threadIdx.x < nr) tile_rows[threadIdx.x] = rows[t.row_lo + threadIdx.x];
+            __syncthreads();
+            locate<true>(R, tile_rows, 0, nr - 1, local, x, y, z, self);
+        } else {
+            locate<true>(R, rows, t.row_lo, t.row_hi, local, x, y, z, self);
+        }
+    } else {
+        locate<false>(R, rows, t.row_lo, t.row_hi, local, x, y, z, self);
+    }
+}
+
 // Fluid runs of the 9 rows (y - cy, z - cz), cy, cz in {-1, 0, 1}, at index (cy+1) + 3 (cz+1).
 struct Rows9 {
     int32_t st[9], lo[9], ln[9];

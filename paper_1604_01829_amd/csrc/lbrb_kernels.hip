@@ -644,13 +644,14 @@ void node_step_kernel(const StepArgs<Real> a,
         return;
     }
     b -= n_lead;
+    __shared__ RowDesc tile_rows[MASKED ? kNodeBlock : 1];
     const NodeTile t = a.tiles[xcd_tile(b, gridDim.x - n_lead)];
-    if ((int)threadIdx.x >= t.count) return;
     const ReplicaDesc R = a.reps[t.replica];
     const int64_t local = t.begin + threadIdx.x;
     int x, y, z;
     RowDesc self;
-    locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
+    locate_tile<MASKED>(R, a.rows, t, local, tile_rows, x, y, z, self);
+    if ((int)threadIdx.x >= t.count) return;
     update_node<Real, MASKED, THERMAL, FORCES, NARROW, NT>(a, R, local, x, y, z, self, step);
 }
 
