@@ -76,6 +76,16 @@ def test_synthetic_trajectories(n_frames, n_bodies):
     _compare_all(traj, centre, min(60, n_frames - 1), [0.0, 3.0, 5.0, 7.0, 100.0], ref)
 
 
+@pytest.mark.parametrize("n_frames,n_bodies,n_lags", [(1000, 2, 150), (300, 1, 299)])
+def test_lags_over_several_blocks(n_frames, n_bodies, n_lags):
+    """More lags than one workgroup's block of 64 (and not a multiple of it), up to the
+    largest, n_frames - 1."""
+    centre = (32.0, 30.0)
+    traj = W.synthetic_trajectory(n_frames, n_bodies, seed=5 + n_lags, centre=centre)
+    ref = np.random.default_rng(8).normal(size=(n_bodies, 3))
+    _compare_all(traj, centre, n_lags, [0.0, 4.0, 100.0], ref)
+
+
 def test_long_trajectory():
     traj = W.synthetic_trajectory(200000, 1, seed=99, step=0.02, rot_step=0.02,
                                   centre=(64.0, 64.0), radius=(10.0, 20.0))
