@@ -330,7 +330,8 @@ int lb_step_overlapped(lb_ctx* ctx, int32_t* out);
  * Synchronises the stream.  Errors: LB_ERR_ARG (window, workspace, missing arrays),
  * LB_ERR_STATE (kT > 0, a free body, more than one MD step per fluid step, or excluded-
  * volume or static sites).  The adjoint runs in the context precision; its
- * atomic accumulation of sampled-velocity adjoints is not order-deterministic.          */
+ * atomic accumulation of sampled-velocity adjoints into the population adjoint is not
+ * order-deterministic.                                                                    */
 size_t lb_adjoint_workspace_bytes(const lb_ctx* ctx, int32_t n_steps, int32_t checkpoint_every);
 int lb_rb_adjoint(lb_ctx* ctx, int32_t n_steps, int32_t checkpoint_every, void* dev_ws,
                   size_t ws_bytes, const double* dJ_dF, double* J, double* dJ_dgamma,

@@ -11,9 +11,11 @@
 //   adj_bead : per bead corner (8 lanes per bead, as the forward coupling), the transpose of
 //              spreading, friction and interpolation: adjoint of the bead force, d/dgamma,
 //              d/dposition through the trilinear weights, and the adjoint of the sampled node
-//              velocities (atomic adds where beads share a node).
-//   adj_vel  : per node that was sampled, the node velocity u = (j + g_ext/2)/rho depends on
-//              the populations: lambda^n_i += (c_i - u) . lambda_u / rho.
+//              velocity.  That velocity u = (j + g_ext/2)/rho depends on the node's
+//              populations, so lambda^n_i(x_c) += (c_i - u) . (w_c lambda_uk) / rho; the term is
+//              linear in each bead's lambda_uk, so every corner adds its own share straight
+//              into lambda^n (atomic adds where beads share a node) and no pass over the
+//              sampled nodes follows.
 // The forward state f^n is re-pulled from the stored post-collision populations of step n-1.
 #include <hip/hip_runtime.h>
 
@@ -50,22 +52,21 @@ __global__ __launch_bounds__(kNodeBlock) void adj_node_kernel(const AdjArgs<Real
     for (int ax = 0; ax < 3; ++ax) A.lamF[(int64_t)ax * a.N + g] = lF[ax];
 }
 
+// one wave per workgroup: the atomics of a bead pass this short spread over every XCD
+constexpr int kAdjBeadBlock = 64;
+
 template <typename Real>
-__global__ __launch_bounds__(kCoupleBlock) void adj_bead_kernel(const AdjArgs<Real> A)
+__global__ __launch_bounds__(kAdjBeadBlock) void adj_bead_kernel(const AdjArgs<Real> A)
 {
     const StepArgs<Real>& a = A.a;
-    const int tid = xcd_tile(blockIdx.x, gridDim.x) * kCoupleBlock + threadIdx.x;
+    const int tid = blockIdx.x * kAdjBeadBlock + threadIdx.x;
     const int bead = tid >> 3, corner = tid & 7;
     if (bead >= A.n_beads) return;   // the 8 lanes of a bead leave together
-    const int64_t step = current_step(a.step_ptr, a.step_arg);
-    const Bead bd = A.beads[bead];
-    const Body& B = A.bodies[bd.body];
-    const Pose& P = B.pose[step & 1];
-    const BodyBox& X = B.box;
-    double r[3];
-    for (int ax = 0; ax < 3; ++ax)
-        r[ax] = P.pos[ax] + (P.rot[3 * ax] * bd.off[0] + P.rot[3 * ax + 1] * bd.off[1] +
-                             P.rot[3 * ax + 2] * bd.off[2]);
+    // the bead record the forward coupling read: lab position, friction, replica geometry
+    // (the bodies are fixed, so one record serves every step of the window)
+    const BeadRec& X = A.recs[bead];
+    const int32_t body = A.beads[bead].body;
+    const double r[3] = {X.r[0], X.r[1], X.r[2]};
     double fr[3];
     int i0[3];
     i0[0] = wrap_floor(r[0] - 0.5, X.nx, fr[0]);
@@ -99,11 +100,11 @@ __global__ __launch_bounds__(kCoupleBlock) void adj_bead_kernel(const AdjArgs<Re
         pull<Real, false, 1>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
     }
     const int64_t g = X.base + local;
-    double uc[3] = {0.0, 0.0, 0.0}, lFc[3] = {0.0, 0.0, 0.0};
+    double uc[3] = {0.0, 0.0, 0.0}, lFc[3] = {0.0, 0.0, 0.0}, ir = 0.0;
     if (local >= 0) {
         Real drho, j[3];
         density_momentum<Real>(d, drho, j);
-        const double ir = 1.0 / ((double)a.cp.rho0 + (double)drho);
+        ir = 1.0 / ((double)a.cp.rho0 + (double)drho);
         for (int ax = 0; ax < 3; ++ax) {
             uc[ax] = ((double)j[ax] + 0.5 * (double)a.gext[ax]) * ir;
             lFc[ax] = (double)A.lamF[(int64_t)ax * a.N + g];
@@ -115,11 +116,11 @@ __global__ __launch_bounds__(kCoupleBlock) void adj_bead_kernel(const AdjArgs<Re
     for (int m = 1; m < 8; m <<= 1)
         for (int k = 0; k < 6; ++k) s6[k] += __shfl_xor(s6[k], m, 8);
     const double* Fk = A.bead_force + 3 * (int64_t)bead;
-    const double* an = A.weights + 3 * (int64_t)bd.body;
+    const double* an = A.weights + 3 * (int64_t)body;
     double lFk[3], luk[3];
     for (int ax = 0; ax < 3; ++ax) {
         lFk[ax] = an[ax] - s6[3 + ax];
-        luk[ax] = B.gamma * lFk[ax];
+        luk[ax] = X.gamma * lFk[ax];
     }
     // position derivative through the interpolation and the spreading weights of this corner
     double dr[3] = {0.0, 0.0, 0.0};
@@ -127,9 +128,13 @@ __global__ __launch_bounds__(kCoupleBlock) void adj_bead_kernel(const AdjArgs<Re
         double su = 0.0, sF = 0.0;
         for (int ax = 0; ax < 3; ++ax) { su += uc[ax] * luk[ax]; sF += Fk[ax] * lFc[ax]; }
         for (int ax = 0; ax < 3; ++ax) dr[ax] = gw[ax] * (su - sF);
-        for (int ax = 0; ax < 3; ++ax)
-            atomicAdd(A.lamU + (int64_t)ax * a.N + g, (Real)(w * luk[ax]));
-        A.uflag[g] = 1;
+        // this corner's share of the sampled velocity's adjoint, through u to the populations
+        const double l0 = w * luk[0] * ir, l1 = w * luk[1] * ir, l2 = w * luk[2] * ir;
+        const double cu = uc[0] * l0 + uc[1] * l1 + uc[2] * l2;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            atomicAdd(A.lam_cur + pop_at(i, g),
+                      (Real)(cx_of(i) * l0 + cy_of(i) * l1 + cz_of(i) * l2 - cu));
     }
 #pragma unroll
     for (int m = 1; m < 8; m <<= 1)
@@ -144,39 +149,6 @@ __global__ __launch_bounds__(kCoupleBlock) void adj_bead_kernel(const AdjArgs<Re
         A.Jpart[bead] += jp;
         A.dgam[bead] += dg;
     }
-}
-
-template <typename Real, bool MASKED>
-__global__ __launch_bounds__(kNodeBlock) void adj_vel_kernel(const AdjArgs<Real> A)
-{
-    const StepArgs<Real>& a = A.a;
-    const NodeTile t = a.tiles[blockIdx.x];
-    if ((int)threadIdx.x >= t.count) return;
-    const ReplicaDesc R = a.reps[t.replica];
-    const int64_t local = t.begin + threadIdx.x;
-    const int64_t g = R.base + local;
-    if (!A.uflag[g]) return;
-    int x, y, z;
-    RowDesc self;
-    locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
-    Real d[Q];
-    pull<Real, MASKED, 1>(a.src, a.N, R, a.rowinfo, x, y, z, local, self, d);
-    Real drho, j[3];
-    density_momentum<Real>(d, drho, j);
-    const Real ir = (Real)1 / (a.cp.rho0 + drho);
-    Real u[3], lu[3];
-    for (int ax = 0; ax < 3; ++ax) {
-        u[ax] = (j[ax] + (Real)0.5 * a.gext[ax]) * ir;
-        lu[ax] = A.lamU[(int64_t)ax * a.N + g];
-        A.lamU[(int64_t)ax * a.N + g] = (Real)0;
-    }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const Real acc = ((Real)cx_of(i) - u[0]) * lu[0] + ((Real)cy_of(i) - u[1]) * lu[1] +
-                         ((Real)cz_of(i) - u[2]) * lu[2];
-        A.lam_cur[pop_at(i, g)] += acc * ir;
-    }
-    A.uflag[g] = 0;
 }
 
 template <typename Real>
@@ -194,25 +166,13 @@ void launch_adjoint_beads(const AdjArgs<Real>& A, hipStream_t s)
 {
     if (A.n_beads <= 0) return;
     const int threads = A.n_beads * kBeadLanes;
-    hipLaunchKernelGGL((adj_bead_kernel<Real>), dim3((threads + kCoupleBlock - 1) / kCoupleBlock),
-                       dim3(kCoupleBlock), 0, s, A);
-}
-
-template <typename Real>
-void launch_adjoint_vel(const AdjArgs<Real>& A, bool masked, hipStream_t s)
-{
-    const dim3 block(kNodeBlock);
-    if (A.a.n_tiles > 0) {
-        if (masked) hipLaunchKernelGGL((adj_vel_kernel<Real, true>), dim3(A.a.n_tiles), block, 0, s, A);
-        else hipLaunchKernelGGL((adj_vel_kernel<Real, false>), dim3(A.a.n_tiles), block, 0, s, A);
-    }
+    hipLaunchKernelGGL((adj_bead_kernel<Real>), dim3((threads + kAdjBeadBlock - 1) / kAdjBeadBlock),
+                       dim3(kAdjBeadBlock), 0, s, A);
 }
 
 template void launch_adjoint_step<float>(const AdjArgs<float>&, bool, hipStream_t);
 template void launch_adjoint_step<double>(const AdjArgs<double>&, bool, hipStream_t);
 template void launch_adjoint_beads<float>(const AdjArgs<float>&, hipStream_t);
 template void launch_adjoint_beads<double>(const AdjArgs<double>&, hipStream_t);
-template void launch_adjoint_vel<float>(const AdjArgs<float>&, bool, hipStream_t);
-template void launch_adjoint_vel<double>(const AdjArgs<double>&, bool, hipStream_t);
 
 }  // namespace lbrb

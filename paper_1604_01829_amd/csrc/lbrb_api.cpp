@@ -875,8 +875,8 @@ int build_wca(lb_ctx* c)
 struct AdjPlan {
     int32_t n_ck = 0, n_seg = 0;
     size_t state = 0;
-    size_t off_ck, off_seg, off_lam0, off_lam1, off_lamF, off_lamU, off_uflag, off_w, off_dr,
-        off_dg, off_J, off_save, total;
+    size_t off_ck, off_seg, off_lam0, off_lam1, off_lamF, off_w, off_dr, off_dg, off_J,
+        off_save, total;
 };
 
 bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
@@ -897,8 +897,6 @@ bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
     ap.off_lam0 = take(ap.state);
     ap.off_lam1 = take(ap.state);
     ap.off_lamF = take(real * 3 * N);
-    ap.off_lamU = take(real * 3 * N);
-    ap.off_uflag = take(N);
     ap.off_w = take(sizeof(double) * 3 * nbod * (size_t)T);
     ap.off_dr = take(sizeof(double) * 3 * nb);
     ap.off_dg = take(sizeof(double) * nb);
@@ -935,10 +933,8 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
         X.lam_next = lam_next;
         X.lam_cur = lam_cur;
         X.lamF = (Real*)(ws + ap.off_lamF);
-        X.lamU = (Real*)(ws + ap.off_lamU);
-        X.uflag = (uint8_t*)(ws + ap.off_uflag);
-        X.bodies = c->d_bodies;
         X.beads = c->d_beads;
+        X.recs = c->d_recs;
         X.bead_force = c->d_bead_force;
         X.weights = (const double*)(ws + ap.off_w) + 3 * (int64_t)c->n_bodies * n;
         X.dr = (double*)(ws + ap.off_dr);
@@ -949,10 +945,7 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
     const int cg = any_masked(c) ? 1 : 0;
     if (c->n_beads > 0) launch_couple<Real>(A[cg].a, couple_args(c), s);
     for (int g = 0; g < 2; ++g) launch_adjoint_step<Real>(A[g], g == 1, s);
-    if (c->n_beads > 0) {
-        launch_adjoint_beads<Real>(A[cg], s);
-        for (int g = 0; g < 2; ++g) launch_adjoint_vel<Real>(A[g], g == 1, s);
-    }
+    if (c->n_beads > 0) launch_adjoint_beads<Real>(A[cg], s);
 }
 
 template <typename Real>
@@ -1658,16 +1651,12 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
         return fail(c, LB_ERR_ARG, "missing objective weights or gradient outputs");
     char* ws = (char*)dev_ws;
     hipStream_t s = c->stream;
-    const size_t real = is_f32(c) ? sizeof(float) : sizeof(double);
-    const int64_t N = c->plan.N;
     const size_t nb = (size_t)std::max<int32_t>(c->n_beads, 1);
     if (c->n_bodies > 0)
         HIP_TRY(c, hipMemcpyAsync(ws + ap.off_w, dJ_dF, sizeof(double) * 3 * c->n_bodies * (size_t)n_steps,
                                   hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_lam0, 0, ap.state, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_lam1, 0, ap.state, s));
-    HIP_TRY(c, hipMemsetAsync(ws + ap.off_lamU, 0, real * 3 * N, s));
-    HIP_TRY(c, hipMemsetAsync(ws + ap.off_uflag, 0, N, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_dr, 0, sizeof(double) * 3 * nb, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_dg, 0, sizeof(double) * nb, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_J, 0, sizeof(double) * nb, s));

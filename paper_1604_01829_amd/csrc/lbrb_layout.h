@@ -252,10 +252,8 @@ struct AdjArgs {
     const Real* lam_next;       // adjoint of the pre-collision populations of the next step
     Real* lam_cur;              // adjoint of the pre-collision populations of this step
     Real* lamF;                 // adjoint of the node force density, [axis][node]
-    Real* lamU;                 // adjoint of the sampled node velocities, [axis][node], zeroed
-    uint8_t* uflag;             // 1 byte per node: velocity sampled by a bead, zeroed
-    const Body* bodies;
     const Bead* beads;
+    const BeadRec* recs;        // bead records (fixed bodies: the same for every step)
     const double* bead_force;   // bead forces of this step (lab frame)
     const double* weights;      // dJ/dF_b of this step, 3 per body (global body order)
     double* dr;                 // accumulated dJ/d(bead lab position), 3 per bead
@@ -267,12 +265,10 @@ struct AdjArgs {
 // node pass: transposed streaming + collision VJP (writes lam_cur, lamF, consumes the force)
 template <typename Real>
 void launch_adjoint_step(const AdjArgs<Real>& A, bool masked, hipStream_t s);
-// bead pass: transpose of spreading, friction and interpolation
+// bead pass: transpose of spreading, friction and interpolation, and of the velocity
+// sampling (adds into lam_cur)
 template <typename Real>
 void launch_adjoint_beads(const AdjArgs<Real>& A, hipStream_t s);
-// velocity-sampling pass: adds (c_i - u).lamU/rho to lam_cur at sampled nodes, clears lamU
-template <typename Real>
-void launch_adjoint_vel(const AdjArgs<Real>& A, bool masked, hipStream_t s);
 
 }  // namespace lbrb
 
