@@ -1,0 +1,110 @@
+// lbrb_adjoint_device.h -- the bead pass of the reverse step as a device function, shared by
+// its own kernel and by the launch that also runs the next reverse step's coupling.
+#pragma once
+
+#include "lbrb_device.h"
+
+namespace lbrb {
+
+// Lanes per workgroup of the bead pass: one wave, so that its atomics issue from every XCD.
+constexpr int kAdjBeadBlock = 64;
+
+// Bead pass for lane `tid` (8 lanes per bead, one per stencil corner): the transpose of
+// spreading, friction and interpolation, and of the velocity sampling.  Lanes past the last
+// bead return at once (the 8 lanes of a bead leave together).
+template <typename Real>
+__device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
+{
+    const StepArgs<Real>& a = A.a;
+    const int bead = tid >> 3, corner = tid & 7;
+    if (bead >= A.n_beads) return;   // the 8 lanes of a bead leave together
+    // the bead record the forward coupling read: lab position, friction, replica geometry
+    // (the bodies are fixed, so one record serves every step of the window)
+    const BeadRec& X = A.recs[bead];
+    const int32_t body = A.beads[bead].body;
+    const double r[3] = {X.r[0], X.r[1], X.r[2]};
+    double fr[3];
+    int i0[3];
+    i0[0] = wrap_floor(r[0] - 0.5, X.nx, fr[0]);
+    i0[1] = wrap_floor(r[1] - 0.5, X.ny, fr[1]);
+    i0[2] = wrap_floor(r[2] - 0.5, X.nz, fr[2]);
+    const int o[3] = {corner & 1, (corner >> 1) & 1, corner >> 2};
+    const int px = i0[0] + o[0] == X.nx ? 0 : i0[0] + o[0];
+    const int py = i0[1] + o[1] == X.ny ? 0 : i0[1] + o[1];
+    const int pz = i0[2] + o[2] == X.nz ? 0 : i0[2] + o[2];
+    double t[3];
+    for (int ax = 0; ax < 3; ++ax) t[ax] = o[ax] ? fr[ax] : 1.0 - fr[ax];
+    const double w = t[0] * t[1] * t[2];
+    double gw[3];   // gradient of the weight with respect to the bead position
+    gw[0] = (o[0] ? 1.0 : -1.0) * t[1] * t[2];
+    gw[1] = (o[1] ? 1.0 : -1.0) * t[0] * t[2];
+    gw[2] = (o[2] ? 1.0 : -1.0) * t[0] * t[1];
+
+    ReplicaDesc R{};
+    R.nx = X.nx; R.ny = X.ny; R.nz = X.nz; R.masked = X.masked;
+    R.base = X.base; R.row_base = X.row_base;
+    int64_t local;
+    Real d[Q];
+    if (X.masked) {
+        const RowDesc self = a.rowinfo[X.row_base + py + X.ny * pz];
+        const int off = px - self.xlo;
+        local = (unsigned)off < (unsigned)self.len ? self.start + off : -1;
+        if (local >= 0) pull<Real, true, 1>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
+    } else {
+        local = px + (int64_t)X.nx * (py + (int64_t)X.ny * pz);
+        const RowDesc self{0, 0, X.nx, 0};
+        pull<Real, false, 1>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
+    }
+    const int64_t g = X.base + local;
+    double uc[3] = {0.0, 0.0, 0.0}, lFc[3] = {0.0, 0.0, 0.0}, ir = 0.0;
+    if (local >= 0) {
+        Real drho, j[3];
+        density_momentum<Real>(d, drho, j);
+        ir = 1.0 / ((double)a.cp.rho0 + (double)drho);
+        for (int ax = 0; ax < 3; ++ax) {
+            uc[ax] = ((double)j[ax] + 0.5 * (double)a.gext[ax]) * ir;
+            lFc[ax] = (double)A.lamF[(int64_t)ax * a.N + g];
+        }
+    }
+    // uk = sum_c w u(x_c), sF = sum_c w lamF(x_c) over the 8 corner lanes
+    double s6[6] = {w * uc[0], w * uc[1], w * uc[2], w * lFc[0], w * lFc[1], w * lFc[2]};
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1)
+        for (int k = 0; k < 6; ++k) s6[k] += __shfl_xor(s6[k], m, 8);
+    const double* Fk = A.bead_force + 3 * (int64_t)bead;
+    const double* an = A.weights + 3 * (int64_t)body;
+    double lFk[3], luk[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        lFk[ax] = an[ax] - s6[3 + ax];
+        luk[ax] = X.gamma * lFk[ax];
+    }
+    // position derivative through the interpolation and the spreading weights of this corner
+    double dr[3] = {0.0, 0.0, 0.0};
+    if (local >= 0) {
+        double su = 0.0, sF = 0.0;
+        for (int ax = 0; ax < 3; ++ax) { su += uc[ax] * luk[ax]; sF += Fk[ax] * lFc[ax]; }
+        for (int ax = 0; ax < 3; ++ax) dr[ax] = gw[ax] * (su - sF);
+        // this corner's share of the sampled velocity's adjoint, through u to the populations
+        const double l0 = w * luk[0] * ir, l1 = w * luk[1] * ir, l2 = w * luk[2] * ir;
+        const double cu = uc[0] * l0 + uc[1] * l1 + uc[2] * l2;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            atomicAdd(A.lam_cur + pop_at(i, g),
+                      (Real)(cx_of(i) * l0 + cy_of(i) * l1 + cz_of(i) * l2 - cu));
+    }
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1)
+        for (int ax = 0; ax < 3; ++ax) dr[ax] += __shfl_xor(dr[ax], m, 8);
+    if (corner == 0) {
+        double jp = 0.0, dg = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            jp += an[ax] * Fk[ax];
+            dg += lFk[ax] * s6[ax];
+            A.dr[3 * (int64_t)bead + ax] += dr[ax];
+        }
+        A.Jpart[bead] += jp;
+        A.dgam[bead] += dg;
+    }
+}
+
+}  // namespace lbrb

@@ -876,7 +876,7 @@ struct AdjPlan {
     int32_t n_ck = 0, n_seg = 0;
     size_t state = 0;
     size_t off_ck, off_seg, off_lam0, off_lam1, off_lamF, off_w, off_dr, off_dg, off_J,
-        off_save, total;
+        off_bf, off_save, total;
 };
 
 bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
@@ -901,6 +901,7 @@ bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
     ap.off_dr = take(sizeof(double) * 3 * nb);
     ap.off_dg = take(sizeof(double) * nb);
     ap.off_J = take(sizeof(double) * nb);
+    ap.off_bf = take(sizeof(double) * 6 * nb);
     ap.off_save = take(sizeof(double) * 6 * nb);
     ap.total = o;
     return true;
@@ -919,11 +920,23 @@ void enqueue_replay(lb_ctx* c, hipStream_t s, const void* src, void* dst, int64_
     if (c->n_links > 0) launch_wall_links<Real>(ag[0].dst, c->d_links, c->n_links, s);
 }
 
-// one reverse step at forward step `step` (index n of the window), forward state pulled from src
+// one reverse step at forward step `step` (index n of the window), forward state pulled from
+// src.  coupled: the coupling of this step already ran (in the previous reverse step's bead
+// launch); prev_src: the state of step - 1, whose coupling then runs in this step's bead launch
+// (nullptr: none, as at the start of a segment, whose states the replay rewrites first).
+// The bead forces of a reverse step go to one of two buffers by the parity of n.
 template <typename Real>
 void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, const Real* lam_next,
-                     Real* lam_cur, char* ws, const AdjPlan& ap, int64_t n)
+                     Real* lam_cur, char* ws, const AdjPlan& ap, int64_t n, bool coupled,
+                     const void* prev_src)
 {
+    double* bf = (double*)(ws + ap.off_bf);
+    const size_t nbf = 3 * (size_t)std::max<int32_t>(c->n_beads, 1);
+    auto coupling = [&](int64_t k) {
+        CoupleArgs ca = couple_args(c);
+        ca.bead_force = bf + nbf * (size_t)(k & 1);
+        return ca;
+    };
     AdjArgs<Real> A[2];
     for (int g = 0; g < 2; ++g) {
         AdjArgs<Real>& X = A[g];
@@ -935,7 +948,7 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
         X.lamF = (Real*)(ws + ap.off_lamF);
         X.beads = c->d_beads;
         X.recs = c->d_recs;
-        X.bead_force = c->d_bead_force;
+        X.bead_force = bf + nbf * (size_t)(n & 1);
         X.weights = (const double*)(ws + ap.off_w) + 3 * (int64_t)c->n_bodies * n;
         X.dr = (double*)(ws + ap.off_dr);
         X.dgam = (double*)(ws + ap.off_dg);
@@ -943,9 +956,16 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
         X.n_beads = c->n_beads;
     }
     const int cg = any_masked(c) ? 1 : 0;
-    if (c->n_beads > 0) launch_couple<Real>(A[cg].a, couple_args(c), s);
+    if (c->n_beads > 0 && !coupled) launch_couple<Real>(A[cg].a, coupling(n), s);
     for (int g = 0; g < 2; ++g) launch_adjoint_step<Real>(A[g], g == 1, s);
-    if (c->n_beads > 0) launch_adjoint_beads<Real>(A[cg], s);
+    if (c->n_beads <= 0) return;
+    if (prev_src) {
+        StepArgs<Real> pa = step_args_on<Real>(c, cg, prev_src, nullptr);
+        pa.step_arg = step - 1;
+        launch_couple_adj_bead<Real>(pa, coupling(n - 1), A[cg], s);
+    } else {
+        launch_adjoint_beads<Real>(A[cg], s);
+    }
 }
 
 template <typename Real>
@@ -979,7 +999,8 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
             enqueue_replay<Real>(c, s, state(j), state(j + 1), step0 + n0 + j);
         HIP_TRY(c, hipGetLastError());
         for (int32_t n = n1 - 1; n >= n0; --n) {
-            enqueue_adjoint<Real>(c, s, state(n - n0), step0 + n, lam[nxt], lam[nxt ^ 1], ws, ap, n);
+            enqueue_adjoint<Real>(c, s, state(n - n0), step0 + n, lam[nxt], lam[nxt ^ 1], ws, ap, n,
+                                  n < n1 - 1, n > n0 ? state(n - 1 - n0) : nullptr);
             nxt ^= 1;
         }
         HIP_TRY(c, hipGetLastError());

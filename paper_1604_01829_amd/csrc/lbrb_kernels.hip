@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cstddef>
 
+#include "lbrb_adjoint_device.h"
 #include "lbrb_device.h"
 
 namespace lbrb {
@@ -909,6 +910,39 @@ void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s,
         launch_timed(couple_kernel<Real, false>, grid, dim3(kCoupleBlock), s, ev, a, c, ba, 0);
 }
 
+// Reverse pass: the coupling recompute of the next reverse step (forward step n-1, from its
+// own state) in the same launch as the bead pass of reverse step n.  The two touch disjoint
+// data: the coupling writes the spread force and flags of step n-1 (the node pass of step n
+// has consumed those of step n) and its bead forces into the other of two buffers; the bead
+// pass reads step n's bead forces, the force adjoints and adds into the population adjoint.
+// The first n_cb workgroups couple (with the coupling's XCD pattern); each later workgroup
+// runs the bead pass on its first wave.
+template <typename Real>
+__global__ __launch_bounds__(kCoupleBlock) void couple_adj_bead_kernel(const StepArgs<Real> a,
+                                                                      const CoupleArgs c,
+                                                                      const AdjArgs<Real> A,
+                                                                      int n_cb)
+{
+    __shared__ CoupleLds<Real> L;
+    if ((int)blockIdx.x < n_cb) {
+        couple_beads<Real>(a, c, blockIdx.x, n_cb, L);
+        return;
+    }
+    if ((int)threadIdx.x < kAdjBeadBlock)
+        adj_bead_lanes<Real>(A, ((int)blockIdx.x - n_cb) * kAdjBeadBlock + (int)threadIdx.x);
+}
+
+template <typename Real>
+void launch_couple_adj_bead(const StepArgs<Real>& a, const CoupleArgs& c, const AdjArgs<Real>& A,
+                            hipStream_t s)
+{
+    if (c.n_beads <= 0) return;
+    const int n_cb = (c.n_beads * kBeadLanes + kCoupleBlock - 1) / kCoupleBlock;
+    const int n_ab = (A.n_beads * kBeadLanes + kAdjBeadBlock - 1) / kAdjBeadBlock;
+    hipLaunchKernelGGL((couple_adj_bead_kernel<Real>), dim3(n_cb + n_ab), dim3(kCoupleBlock), 0,
+                       s, a, c, A, n_cb);
+}
+
 // ------------------------------------------------------------------ overlapped step
 
 // Launch A of the overlapped step: the first n_cb workgroups couple the beads (n_cb a
@@ -1221,6 +1255,10 @@ template void launch_overlap_forced<float>(const StepArgs<float>&, bool, const B
                                            hipStream_t, const LaunchEvents&);
 template void launch_overlap_forced<double>(const StepArgs<double>&, bool, const BodyArgs&,
                                             hipStream_t, const LaunchEvents&);
+template void launch_couple_adj_bead<float>(const StepArgs<float>&, const CoupleArgs&,
+                                           const AdjArgs<float>&, hipStream_t);
+template void launch_couple_adj_bead<double>(const StepArgs<double>&, const CoupleArgs&,
+                                            const AdjArgs<double>&, hipStream_t);
 template void launch_couple<float>(const StepArgs<float>&, const CoupleArgs&, hipStream_t,
                                    const LaunchEvents&, const BodyArgs*);
 template void launch_couple<double>(const StepArgs<double>&, const CoupleArgs&, hipStream_t,

@@ -269,6 +269,10 @@ void launch_adjoint_step(const AdjArgs<Real>& A, bool masked, hipStream_t s);
 // sampling (adds into lam_cur)
 template <typename Real>
 void launch_adjoint_beads(const AdjArgs<Real>& A, hipStream_t s);
+// the bead pass of A in one launch with the coupling (a, c) of the previous forward step
+template <typename Real>
+void launch_couple_adj_bead(const StepArgs<Real>& a, const CoupleArgs& c, const AdjArgs<Real>& A,
+                            hipStream_t s);
 
 }  // namespace lbrb
 
