@@ -3,6 +3,7 @@
 - small periodic and pore boxes with two fixed bodies, FP64 and FP32, against the oracle's
   reverse-mode derivative (itself pinned against central differences of the oracle's forward
   run), with a window that does not divide into whole checkpoint segments;
+- a batch of a periodic and a pore replica against each replica's own oracle adjoint;
 - the checkpoint interval does not change the result; the call leaves the state that the same
   number of forward steps leaves;
 - the fixed R = 4 sphere in uniform flow on 64^3 over 200 steps, checkpoints every 20 steps:
@@ -99,6 +100,44 @@ def test_adjoint_matches_oracle(masked, precision):
     assert abs(Jg - Jo) <= tJ * abs(Jo), (Jg, Jo)
     assert np.abs(dgg - dgo).max() <= tg * np.abs(dgo).max(), (dgg, dgo)
     assert np.abs(dog - doo).max() <= to * np.abs(doo).max(), np.abs(dog - doo).max()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_of_a_periodic_and_a_pore_replica(precision):
+    """Replicas are independent, so the reverse pass over one context holding a periodic and a
+    pore replica (dense and masked tile groups, one bead launch over both) returns the sum of
+    the two objectives and each replica's own gradients, in global body and bead order."""
+    from paper_1604_01829_amd import lbrb
+    sp, _, _, bp = _case(False)
+    sm, mask, pp, bm = _case(True)
+    T, K = 11, 4                                 # segments of 4, 4 and 3 steps
+    a = _weights(T, len(bp) + len(bm), seed=21)
+    print(f"batch adjoint vs oracle: {precision} T={T} K={K}", flush=True)
+    nb = sum(len(b[0]) for b in bp + bm)
+    params = lbrb.make_params(precision=precision, kT=0.0, max_bodies=len(bp) + len(bm),
+                              max_beads=nb, **pp)
+    sim = lbrb.Simulation(params, lbrb.make_replicas([(sp, 7), (sm, 8)]))
+    sim.set_mask(1, mask)
+    for r, bodies in ((0, bp), (1, bm)):
+        for offs, c, q, g in bodies:
+            sim.add_body(r, offs, 1.0, (1, 1, 1), c, quat=q, gamma=g, fixed=True)
+    Jg, dgg, dog = sim.adjoint(T, a, checkpoint_every=K)
+    sim.close()
+    Jp, dgp, dop = _oracle(sp, None, pp, bp).adjoint(T, a[:, :len(bp)])
+    Jm, dgm, dom = _oracle(sm, mask, pp, bm).adjoint(T, a[:, len(bp):])
+    Jo = Jp + Jm
+    dgo = np.concatenate([dgp, dgm])
+    doo = np.concatenate([dop, dom])
+    tJ, tg, to = (1e-12, 1e-10, 1e-10) if precision == "f64" else (2e-6, 5e-6, 5e-6)
+    print(f"  J rel {abs(Jg - Jo) / abs(Jo):.2e}  dgamma rel "
+          f"{np.abs(dgg - dgo).max() / np.abs(dgo).max():.2e}  doffsets rel "
+          f"{np.abs(dog - doo).max() / np.abs(doo).max():.2e}", flush=True)
+    assert abs(Jg - Jo) <= tJ * abs(Jo), (Jg, Jo)
+    for got, want in ((dgg[:len(bp)], dgp), (dgg[len(bp):], dgm)):
+        assert np.abs(got - want).max() <= tg * np.abs(want).max(), (got, want)
+    npb = sum(len(b[0]) for b in bp)
+    for got, want in ((dog[:npb], dop), (dog[npb:], dom)):
+        assert np.abs(got - want).max() <= to * np.abs(want).max(), np.abs(got - want).max()
 
 
 def test_checkpoint_interval_does_not_change_the_gradient():
