@@ -992,6 +992,7 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
     // reverse, one segment at a time: recompute the segment's states, then walk it backwards
     Real* lam[2] = {(Real*)(ws + ap.off_lam0), (Real*)(ws + ap.off_lam1)};
     int nxt = 0;
+    bool coupled = false;   // the coupling of the next reverse step already ran
     for (int32_t sg = ap.n_ck - 1; sg >= 0; --sg) {
         const int32_t n0 = sg * K, n1 = std::min(T, n0 + K);
         auto state = [&](int32_t j) { return j == 0 ? ck(sg) : seg(j - 1); };
@@ -999,8 +1000,13 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
             enqueue_replay<Real>(c, s, state(j), state(j + 1), step0 + n0 + j);
         HIP_TRY(c, hipGetLastError());
         for (int32_t n = n1 - 1; n >= n0; --n) {
+            // the coupling of step n - 1 joins this step's bead launch when its state is at
+            // hand and nothing in between rewrites the force accumulators: inside a segment,
+            // and across segments of one step each (no replays)
+            const void* prev = n > n0 ? state(n - 1 - n0) : (K == 1 && n > 0 ? ck(n - 1) : nullptr);
             enqueue_adjoint<Real>(c, s, state(n - n0), step0 + n, lam[nxt], lam[nxt ^ 1], ws, ap, n,
-                                  n < n1 - 1, n > n0 ? state(n - 1 - n0) : nullptr);
+                                  coupled, prev);
+            coupled = prev != nullptr;
             nxt ^= 1;
         }
         HIP_TRY(c, hipGetLastError());
