@@ -220,7 +220,10 @@ int lb_traj_rotation_msd(const double* traj, int32_t n_frames, int32_t n_bodies,
 /* Radially binned MSD (Sec. 2.8): every origin frame t of every body whose radial[b][t]
  * lies in [edges[j], edges[j+1]) (edges: device, n_bins+1 ascending) adds its squared
  * increments over lags 1..n_lags of series (k = 1..3) to sums[n_bins][n_lags][k] and 1 to
- * counts[n_bins][n_lags] (both overwritten).                                               */
+ * counts[n_bins][n_lags] (both overwritten).  With at most 8 bins each body's sums are added
+ * to the outputs by device atomics, so the order of the bodies in the sums (their last bits)
+ * may differ between calls; the counts are exact.  With more bins the bodies are added in
+ * order.                                                                                  */
 int lb_traj_binned_msd(const double* series, const double* radial, int32_t n_frames,
                          int32_t n_bodies, int32_t k, const double* edges, int32_t n_bins,
                          int32_t n_lags, double* sums, double* counts, void* stream);

@@ -278,10 +278,9 @@ __global__ __launch_bounds__(kBlock) void rotation_msd_kernel(const double* __re
             ((part[0][l] + part[1][l]) + (part[2][l] + part[3][l])) / (double)(n_frames - tau);
 }
 
-// grid (lag, bin): sums of the squared increments from the origins whose radial coordinate
-// lies in [edges[bin], edges[bin+1]), over all bodies, and their count (one workgroup per lag:
-// staging all frames for a block of lags would repeat for every bin, and the grid of lag
-// blocks times bins is too small to fill the GPU)
+// grid (lag, bin), for more than kTileBins bins: sums of the squared increments from the
+// origins whose radial coordinate lies in [edges[bin], edges[bin+1]), over all bodies, and
+// their count (one workgroup per lag and bin, the bodies added in order)
 template <int K>
 __global__ __launch_bounds__(kBlock) void binned_msd_kernel(const double* __restrict__ s,
                                                             const double* __restrict__ radial,
@@ -313,6 +312,81 @@ __global__ __launch_bounds__(kBlock) void binned_msd_kernel(const double* __rest
         const int64_t o = (int64_t)bin * n_lags + blockIdx.x;
         for (int k = 0; k < K; ++k) sums[o * K + k] = acc[k];
         counts[o] = acc[K];
+    }
+}
+
+// grid (lag block, body), for at most kTileBins bins: the MSD kernel's staging, with each
+// staged origin's bin found once.  The lanes of a wave share their origin (they differ in the
+// lag), so the bin is uniform across the wave and only its own sums are updated.  Thread
+// (l, ph) keeps every bin's sums for lag lag0 + l + 1 in registers; the four phases are added
+// in a fixed order and each body's sums are added to the outputs with device atomics, so the
+// order in which bodies are added (and the last bits of the sums) is not fixed; the counts
+// are whole numbers and exact.
+constexpr int kTileBins = 8;
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void binned_msd_tiled_kernel(
+    const double* __restrict__ s, const double* __restrict__ radial, int n_frames,
+    const double* __restrict__ edges, int n_bins, int n_lags, double* __restrict__ sums,
+    double* __restrict__ counts)
+{
+    __shared__ double A[kChunk][K];
+    __shared__ double Bt[kChunk + kLagBlock - 1][K];
+    __shared__ int bin_of[kChunk];
+    __shared__ double part[kPhases][kLagBlock];
+    const int lag0 = blockIdx.x * kLagBlock, b = blockIdx.y;
+    const int l = threadIdx.x % kLagBlock, ph = threadIdx.x / kLagBlock;
+    const int tau = lag0 + l + 1;
+    const double* sb = s + (int64_t)b * n_frames * K;
+    const double* rb = radial + (int64_t)b * n_frames;
+    double acc[kTileBins][K + 1];
+#pragma unroll
+    for (int q = 0; q < kTileBins; ++q)
+        for (int k = 0; k <= K; ++k) acc[q][k] = 0.0;
+    for (int64_t t0 = 0; t0 + lag0 + 1 < n_frames; t0 += kChunk) {
+        __syncthreads();
+        stage<K>(sb, t0, kChunk, n_frames, A);
+        stage<K>(sb, t0 + lag0 + 1, kChunk + kLagBlock - 1, n_frames, Bt);
+        for (int e = threadIdx.x; e < kChunk; e += kBlock) {
+            int j = -1;
+            if (t0 + e < n_frames) {
+                const double r = rb[t0 + e];
+                for (int q = 0; q < n_bins; ++q)
+                    if (r >= edges[q] && r < edges[q + 1]) j = q;
+            }
+            bin_of[e] = j;
+        }
+        __syncthreads();
+        for (int o = ph; o < kChunk && t0 + o + tau < n_frames; o += kPhases) {
+            const int j = __builtin_amdgcn_readfirstlane(bin_of[o]);   // uniform in the wave
+            if (j < 0) continue;
+            double d2[K];
+            for (int k = 0; k < K; ++k) {
+                const double d = Bt[o + l][k] - A[o][k];
+                d2[k] = d * d;
+            }
+#pragma unroll
+            for (int q = 0; q < kTileBins; ++q)
+                if (q == j) {
+                    for (int k = 0; k < K; ++k) acc[q][k] += d2[k];
+                    acc[q][K] += 1.0;
+                }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kTileBins; ++q) {
+        if (q >= n_bins) break;
+        for (int k = 0; k <= K; ++k) {
+            __syncthreads();
+            part[ph][l] = acc[q][k];
+            __syncthreads();
+            if (ph == 0 && tau <= n_lags) {
+                const double v = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
+                const int64_t o = (int64_t)q * n_lags + tau - 1;
+                if (k < K) atomicAdd(sums + o * K + k, v);
+                else atomicAdd(counts + o, v);
+            }
+        }
     }
 }
 
@@ -405,8 +479,20 @@ int lb_traj_binned_msd(const double* series, const double* radial, int32_t n_fra
     if (!frames_ok(series, n_frames, n_bodies) || !radial || !edges || !sums || !counts ||
         k < 1 || k > 3 || n_bins < 1 || n_bins > 65535 || n_lags < 1 || n_lags >= n_frames)
         return LB_ERR_ARG;
-    const dim3 grid(n_lags, n_bins);
     hipStream_t s = (hipStream_t)stream;
+    if (n_bins <= kTileBins && n_bodies <= 65535) {
+        if (hipMemsetAsync(sums, 0, sizeof(double) * k * n_bins * (size_t)n_lags, s) != hipSuccess ||
+            hipMemsetAsync(counts, 0, sizeof(double) * n_bins * (size_t)n_lags, s) != hipSuccess)
+            return LB_ERR_HIP;
+        const dim3 tiles((n_lags + kLagBlock - 1) / kLagBlock, n_bodies);
+        switch (k) {
+        case 1: hipLaunchKernelGGL((binned_msd_tiled_kernel<1>), tiles, dim3(kBlock), 0, s, series, radial, n_frames, edges, n_bins, n_lags, sums, counts); break;
+        case 2: hipLaunchKernelGGL((binned_msd_tiled_kernel<2>), tiles, dim3(kBlock), 0, s, series, radial, n_frames, edges, n_bins, n_lags, sums, counts); break;
+        default: hipLaunchKernelGGL((binned_msd_tiled_kernel<3>), tiles, dim3(kBlock), 0, s, series, radial, n_frames, edges, n_bins, n_lags, sums, counts); break;
+        }
+        return launched();
+    }
+    const dim3 grid(n_lags, n_bins);
     switch (k) {
     case 1: hipLaunchKernelGGL((binned_msd_kernel<1>), grid, dim3(kBlock), 0, s, series, radial, n_frames, n_bodies, edges, n_lags, sums, counts); break;
     case 2: hipLaunchKernelGGL((binned_msd_kernel<2>), grid, dim3(kBlock), 0, s, series, radial, n_frames, n_bodies, edges, n_lags, sums, counts); break;

@@ -86,6 +86,24 @@ def test_lags_over_several_blocks(n_frames, n_bodies, n_lags):
     _compare_all(traj, centre, n_lags, [0.0, 4.0, 100.0], ref)
 
 
+@pytest.mark.parametrize("edges", [np.linspace(2.0, 9.0, 9),          # 8 bins, the tiled kernel
+                                   np.linspace(0.0, 12.0, 13)],       # 12 bins, one workgroup per bin
+                         ids=["8_bins", "12_bins"])
+def test_binned_msd_bin_counts(edges):
+    """Binned MSD with the most bins the tiled kernel takes and with more (the per-bin
+    kernel); origins outside every bin (radius below 2) are left out."""
+    centre = (32.0, 30.0)
+    traj = W.synthetic_trajectory(1500, 3, seed=44, centre=centre)
+    t = _dev(traj)
+    pore_o, rad_o = OA.pore_frame(traj, centre)
+    pore_g, rad_g = GA.pore_frame(t, centre)
+    sg, cg = GA.binned_msd(pore_g, rad_g, list(edges), 100)
+    so, co = OA.binned_msd(pore_o, rad_o, list(edges), 100)
+    assert np.array_equal(_host(cg), co), "bin counts"
+    scale = max(1.0, np.abs(so).max())
+    _close(_host(sg) / scale, so / scale, 1e-10, "binned msd")
+
+
 def test_long_trajectory():
     traj = W.synthetic_trajectory(200000, 1, seed=99, step=0.02, rot_step=0.02,
                                   centre=(64.0, 64.0), radius=(10.0, 20.0))
