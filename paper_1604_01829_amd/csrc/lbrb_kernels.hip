@@ -48,13 +48,27 @@ __device__ __forceinline__ void update_node(const StepArgs<Real>& a, const Repli
                                             int64_t local, int x, int y, int z,
                                             const RowDesc& self, int64_t step)
 {
+    // the force flag is loaded before the populations: loads complete in order, so a flag
+    // loaded after them would make its branch wait for all of them, and the noise rounds
+    // (which need no loaded value) could not run while they are in flight
+    const int64_t g = R.base + local;
+    uint8_t flag = 0;
+    if constexpr (FORCES) flag = a.flags[g];
     Real d[Q];
     pull<Real, MASKED, 1, NARROW>(a.src, a.N, R, a.rowinfo, x, y, z, local, self, d);
 
-    const int64_t g = R.base + local;
+    uint32_t w[8];
+    if constexpr (THERMAL) {
+        const uint32_t dense = (uint32_t)(x + (int64_t)R.nx * (y + (int64_t)R.ny * z));
+        const U4 b0 = noise_block((uint64_t)step, dense, 0u, 0u, R.key0, R.key1);
+        const U4 b1 = noise_block((uint64_t)step, dense, 0u, 1u, R.key0, R.key1);
+        w[0] = b0.x; w[1] = b0.y; w[2] = b0.z; w[3] = b0.w;
+        w[4] = b1.x; w[5] = b1.y; w[6] = b1.z; w[7] = b1.w;
+    }
+
     Real F[3] = {a.gext[0], a.gext[1], a.gext[2]};
     if constexpr (FORCES) {
-        if (a.flags[g]) {
+        if (flag) {
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) F[ax] += take_spread_force<Real>(a.gforce, a.N, ax, g);
             a.flags[g] = 0;
@@ -62,10 +76,6 @@ __device__ __forceinline__ void update_node(const StepArgs<Real>& a, const Repli
     }
 
     if constexpr (THERMAL) {
-        const uint32_t dense = (uint32_t)(x + (int64_t)R.nx * (y + (int64_t)R.ny * z));
-        const U4 b0 = noise_block((uint64_t)step, dense, 0u, 0u, R.key0, R.key1);
-        const U4 b1 = noise_block((uint64_t)step, dense, 0u, 1u, R.key0, R.key1);
-        const uint32_t w[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
         Real U[15];
 #pragma unroll
         for (int h = 0; h < 15; ++h) U[h] = uniform16<Real>((h & 1) ? (w[h >> 1] >> 16) : w[h >> 1]);
