@@ -20,7 +20,7 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
     if (bead >= A.n_beads) return;   // the 8 lanes of a bead leave together
     // the bead record the forward coupling read: lab position, friction, replica geometry
     // (the bodies are fixed, so one record serves every step of the window)
-    const BeadRec& X = A.recs[bead];
+    const BeadRec X = load_record(A.recs + bead);
     const int32_t body = A.beads[bead].body;
     const double r[3] = {X.r[0], X.r[1], X.r[2]};
     double fr[3];

@@ -16,6 +16,24 @@ __device__ __forceinline__ int wrap1(int v, int n)
     return v < 0 ? v + n : (v >= n ? v - n : v);
 }
 
+// A bead record read whole, as eight 16-byte loads in one round.  Read field by field, the
+// compiler issues a field's load where it is first used; for fields first used after a
+// branch or a barrier that is a dependent round trip of its own.  The empty asm takes every
+// loaded word as an operand, so all eight loads are issued before it.
+__device__ __forceinline__ BeadRec load_record(const BeadRec* p)
+{
+    constexpr int kWords = (int)(sizeof(BeadRec) / sizeof(uint4));
+    const uint4* src = reinterpret_cast<const uint4*>(p);
+    uint4 q[kWords];
+#pragma unroll
+    for (int k = 0; k < kWords; ++k) q[k] = src[k];
+#pragma unroll
+    for (int k = 0; k < kWords; ++k) asm volatile("" ::"v"(q[k].x), "v"(q[k].y), "v"(q[k].z), "v"(q[k].w));
+    BeadRec B;
+    __builtin_memcpy(&B, q, sizeof(BeadRec));
+    return B;
+}
+
 __device__ __forceinline__ int64_t current_step(const int64_t* p, int64_t arg)
 {
     return (p ? *p : 0) + arg;

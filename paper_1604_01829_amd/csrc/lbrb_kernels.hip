@@ -721,6 +721,7 @@ void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const B
 
 // ------------------------------------------------------------------ bead coupling
 
+
 // Thread t handles corner t & 7 of bead t >> 3.  The dependent loads are kept to three
 // rounds: the bead's record of the step (position, velocity, friction, replica geometry) ->
 // the 9 row descriptors around the corner node -> its 19 populations.  Within a workgroup
@@ -762,7 +763,7 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
     const int bead = tid >> 3, corner = tid & 7;
     const bool active = bead < c.n_beads;   // the 8 lanes of a bead share this
     const int64_t step = current_step(a.step_ptr, a.step_arg);
-    const BeadRec& B = c.recs[active ? bead : 0];
+    const BeadRec B = load_record(c.recs + (active ? bead : 0));
     const double r[3] = {B.r[0], B.r[1], B.r[2]};
     const int nx = B.nx, ny = B.ny, nz = B.nz;
 
