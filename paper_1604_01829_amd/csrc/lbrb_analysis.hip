@@ -218,7 +218,11 @@ __global__ __launch_bounds__(kBlock) void msd_kernel(const double* __restrict__ 
         stage<K>(sb, t0, kChunk, n_frames, A);
         stage<K>(sb, t0 + lag0 + 1, kChunk + kLagBlock - 1, n_frames, Bt);
         __syncthreads();
-        for (int o = ph; o < kChunk && t0 + o + tau < n_frames; o += kPhases)
+        // origins t0 + o with t0 + o + tau < n_frames; a counted loop, unrolled, lets the
+        // LDS reads of several origins be in flight together
+        const int o_end = (int)min<int64_t>(kChunk, n_frames - tau - t0);
+#pragma unroll 8
+        for (int o = ph; o < o_end; o += kPhases)
             for (int k = 0; k < K; ++k) {
                 const double d = Bt[o + l][k] - A[o][k];
                 acc[k] += d * d;
@@ -262,7 +266,9 @@ __global__ __launch_bounds__(kBlock) void rotation_msd_kernel(const double* __re
         for (int e = threadIdx.x; e < kChunk + kLagBlock - 1; e += kBlock)
             unit(t0 + lag0 + 1 + e, Bt[e]);
         __syncthreads();
-        for (int o = ph; o < kChunk && t0 + o + tau < n_frames; o += kPhases) {
+        const int o_end = (int)min<int64_t>(kChunk, n_frames - tau - t0);
+#pragma unroll 8
+        for (int o = ph; o < o_end; o += kPhases) {
             const double* p0 = A[o];
             const double* p1 = Bt[o + l];
             double c = p0[0] * p1[0] + p0[1] * p1[1] + p0[2] * p1[2];
@@ -357,7 +363,9 @@ __global__ __launch_bounds__(kBlock) void binned_msd_tiled_kernel(
             bin_of[e] = j;
         }
         __syncthreads();
-        for (int o = ph; o < kChunk && t0 + o + tau < n_frames; o += kPhases) {
+        const int o_end = (int)min<int64_t>(kChunk, n_frames - tau - t0);
+#pragma unroll 2
+        for (int o = ph; o < o_end; o += kPhases) {
             const int j = __builtin_amdgcn_readfirstlane(bin_of[o]);   // uniform in the wave
             if (j < 0) continue;
             double d2[K];
