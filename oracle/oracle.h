@@ -133,6 +133,7 @@ int      orc_body_state(const orc_sim* s, int body, double out[19]);
 /* per-bead force of the last step, lab frame, n_beads*3 for the body                     */
 int      orc_bead_forces(const orc_sim* s, int body, double* out);
 int      orc_num_threads(void);
+void     orc_set_num_threads(int n);
 
 /* ---- raspberry construction (orc_relax.c; Sec. 2.1 and its SI) ---- */
 typedef struct {

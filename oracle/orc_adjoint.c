@@ -38,19 +38,34 @@ int orc_box_body(const orc_sim* s, int b, const double** offsets, int* n_beads, 
 double orc_box_kT(const orc_sim* s);
 int orc_box_plain_md(const orc_sim* s);
 
-static double E_(int k, int i) { return orc_basis(k, i); }
+/* the basis, its norms and the weights, read once into tables (the same values) */
+static double AE[19][19], AB[19], AW[19];
+static int tables_ready = 0;
+static void adj_tables(void)
+{
+    if (tables_ready) return;
+    for (int k = 0; k < 19; ++k) {
+        AB[k] = orc_basis_norm(k);
+        AW[k] = orc_weight(k);
+        for (int i = 0; i < 19; ++i) AE[k][i] = orc_basis(k, i);
+    }
+    tables_ready = 1;
+}
+
+static double E_(int k, int i) { return AE[k][i]; }
 
 void orc_collide_vjp(const orc_params* p, const double f_in[19], const double F[3],
                      const double lam_out[19], double lam_in[19], double lam_F[3])
 {
     double m[19], b[19], w[19], lam_ms[19], lam_m[19];
+    adj_tables();
     for (int k = 0; k < 19; ++k) {
-        b[k] = orc_basis_norm(k);
+        b[k] = AB[k];
         double acc = 0.0;
         for (int i = 0; i < 19; ++i) acc += E_(k, i) * f_in[i];
         m[k] = acc;
     }
-    for (int i = 0; i < 19; ++i) w[i] = orc_weight(i);
+    for (int i = 0; i < 19; ++i) w[i] = AW[i];
     const double rho = m[0];
     double u[3];
     for (int a = 0; a < 3; ++a) u[a] = (m[1 + a] + 0.5 * F[a]) / rho;
@@ -169,6 +184,7 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
     const int64_t N = (int64_t)nx * ny * nz;
     const uint8_t* mask = orc_box_mask(s);
     if (orc_box_kT(s) != 0.0 || !orc_box_plain_md(s) || n_steps < 0) return -1;
+    adj_tables();   /* before the parallel node loop */
 
     /* bodies: fixed, constant bead positions */
     int total_beads = 0;
@@ -235,7 +251,8 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
                 }
             }
         }
-        /* streaming transpose and collision VJP */
+        /* streaming transpose and collision VJP (each node writes only its own entries) */
+#pragma omp parallel for schedule(static)
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {

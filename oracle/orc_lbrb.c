@@ -814,3 +814,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* threads of the parallel loops from here on (the baseline is timed at 1 and at all) */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

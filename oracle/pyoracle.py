@@ -131,6 +131,8 @@ def lib():
         L.orc_bead_forces.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_closest_point.restype = ctypes.c_double
         L.orc_closest_point.argtypes = [_D, _D, _D]
         L.orc_relax_shell.restype = ctypes.c_int
@@ -248,6 +250,10 @@ def trilinear(shape, r):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------- a box

@@ -201,18 +201,22 @@ __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
 
 // ------------------------------------------------------------------ spread force
 // Bead forces are spread as sums of 64-bit integers, so the total on a node does not depend
-// on the order of the atomic additions.  Word 0 counts units of 2^-56; in FP64 a second
-// word carries the remainder in units of 2^-112, which makes the spread exact to far below
-// FP64 rounding.  Layout: word w of axis ax of node g at gforce[(w*3 + ax) * N + g].
+// on the order of the atomic additions.  Word 0 counts units of 2^-56 (signed; a node's
+// total must stay below 128 in magnitude); in FP64 a second word carries the remainder of
+// each contribution in units of 2^-104, which makes the spread exact to far below FP64
+// rounding.  A remainder lies in [0, 2^48) and the second word is read back as unsigned, so
+// it holds the sum of up to 65535 contributions (beads whose stencil holds the node, times
+// MD steps per fluid step) without wrapping.  Layout: word w of axis ax of node g at
+// gforce[(w*3 + ax) * N + g].
 // the fixed-point words of one contribution: hi in units of 2^-56, lo (FP64 only) the
-// remainder in units of 2^-112
+// remainder in units of 2^-104
 template <typename Real>
 __device__ __forceinline__ void spread_words(double val, long long& hi, long long& lo)
 {
     const double x = val * 0x1p56;
     const double h = floor(x);
     hi = (long long)h;
-    lo = sizeof(Real) == 8 ? (long long)((x - h) * 0x1p56) : 0;
+    lo = sizeof(Real) == 8 ? (long long)((x - h) * 0x1p48) : 0;
 }
 
 template <typename Real>
@@ -223,7 +227,7 @@ __device__ __forceinline__ Real take_spread_force(long long* gforce, int64_t N, 
     *p = 0;
     if constexpr (sizeof(Real) == 8) {
         long long* q = gforce + (int64_t)(3 + ax) * N + g;
-        v += (double)(*q) * 0x1p-112;
+        v += (double)(unsigned long long)(*q) * 0x1p-104;
         *q = 0;
     }
     return (Real)v;

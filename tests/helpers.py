@@ -56,13 +56,39 @@ def exact_totals(orc):
     return t
 
 
-def compare(gpu, orc, r=0, n_bodies=None):
-    """Max errors between a GPU replica and its oracle box: dict of scalars."""
+def population_errors(gpu, orc, r=0):
+    """Max error of all 19 pre-collision populations of a GPU replica against its oracle box,
+    and the population scale max |f_i - w_i rho0| over the oracle's fluid nodes (the shifted
+    values that FP32 stores; the ghost moments are linear combinations of them, so an error in
+    any of the 19 moments shows here at the population scale).  Also the largest error of each
+    moment m_k = sum_i e_ki f_i, for the record."""
+    fg = gpu.populations(r)
+    fo = orc.populations()
+    w = po.weights()
+    rho0 = float(orc.params.rho0)
+    fluid = np.any(fo != 0.0, axis=0)
+    dg = fg[:, fluid]
+    do = fo[:, fluid]
+    out = {"pop_abs": float(np.abs(dg - do).max()) if do.size else 0.0,
+           "pop_scale": float(np.abs(do - w[:, None] * rho0).max()) if do.size else 0.0,
+           "pop_max": float(np.abs(do).max()) if do.size else 0.0,
+           "pop_solid_zero": bool(np.all(fg[:, ~fluid] == 0.0))}
+    E = po.basis()
+    dm = np.abs(E @ (dg - do)).max(axis=1) if do.size else np.zeros(19)
+    out["mode_abs"] = [float(v) for v in dm]
+    return out
+
+
+def compare(gpu, orc, r=0, n_bodies=None, pops=True):
+    """Max errors between a GPU replica and its oracle box: dict of scalars.  Body velocity
+    error scales: |V| itself ("scale_vel") and the per-step gross force integrated over the
+    run, step * sum_k |F_k| / M ("scale_vel_int"); angular velocity: the larger of |omega|
+    and step * sum_k |r_k - R| |F_k| / I_min ("scale_omega")."""
     tg, bg, fg, rc = gpu.observables(r, fields=True, check=False)
     fo = orc.fields()
     to = exact_totals(orc)
     fluid = fo[..., 0] != 0.0
-    out = {"rc": rc}
+    out = {"rc": rc, "step": int(tg["step"])}
     rho_o, rho_g = fo[..., 0][fluid], fg[..., 0][fluid]
     out["rho"] = float(np.abs(rho_g - rho_o).max()) if rho_o.size else 0.0
     uo, ug = fo[..., 1:][fluid], fg[..., 1:][fluid]
@@ -78,7 +104,7 @@ def compare(gpu, orc, r=0, n_bodies=None):
     out["finite"] = tg["finite"] == to["finite"]
     nb = orc.n_bodies if n_bodies is None else n_bodies
     errs = {"pos": 0.0, "quat": 0.0, "vel": 0.0, "omega": 0.0, "force": 0.0, "torque": 0.0}
-    scale = {"vel": 0.0, "omega": 0.0, "force": 0.0, "torque": 0.0}
+    scale = {"vel": 0.0, "vel_int": 0.0, "omega": 0.0, "force": 0.0, "torque": 0.0}
     for b in range(nb):
         so = orc.body_state(b)
         sg = bg[b]
@@ -96,14 +122,19 @@ def compare(gpu, orc, r=0, n_bodies=None):
             scale[k] = max(scale[k], float(np.abs(so[k]).max()))
         # velocities integrate the force and torque over the run (V += F/M, omega += T/I per
         # step): an error of a given fraction of the gross force or torque in every step
-        # bounds their error by that fraction of step * gross / M (or I)
+        # bounds their error by that fraction of step * gross / M (or I).  The net angular
+        # velocity of a symmetric body is itself a cancelling sum, so omega keeps that scale
+        # as its only one; V is bounded by a fraction of |V| plus a much smaller fraction of
+        # the integrated gross force (see the parity tests)
         mi = getattr(orc, "_mass_inertia", None)
         if mi is not None and b < len(mi) and mi[b][0] > 0.0:
             m, inertia = mi[b]
-            scale["vel"] = max(scale["vel"], tg["step"] * gross_f / m)
+            scale["vel_int"] = max(scale["vel_int"], tg["step"] * gross_f / m)
             scale["omega"] = max(scale["omega"], tg["step"] * gross_t / float(inertia.min()))
     out.update({"body_" + k: v for k, v in errs.items()})
     out.update({"scale_" + k: v for k, v in scale.items()})
+    if pops:
+        out.update(population_errors(gpu, orc, r))
     return out
 
 

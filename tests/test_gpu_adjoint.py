@@ -9,6 +9,8 @@
 - the fixed R = 4 sphere in uniform flow on 64^3 over 200 steps, checkpoints every 20 steps:
   FP64 gradients against central differences of FP64 forward runs of the library, FP32
   gradients against the FP64 ones;
+- the same sphere over the first 40 steps (a window whose 41 states of 40 MB the oracle
+  holds), FP64 and FP32 against the oracle's FP64 reverse pass;
 - the torch.autograd.Function wrapper; error codes.
 """
 import numpy as np
@@ -236,6 +238,36 @@ def test_full_size_sphere_window_gradient():
     assert abs(J32 - J) <= 1e-5 * abs(J)
     assert abs(dg32[0] - dg[0]) <= 1e-5 * abs(dg[0])
     assert np.abs(do32 - do).max() <= 1e-5 * np.abs(do).max()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_full_size_sphere_against_the_oracle_adjoint(precision):
+    """64^3, R = 4 fixed sphere (401 beads), u0 = (0.01, 0, 0): J = drag along x averaged over
+    a 40-step window, checkpoints every 20 steps on the GPU, every state kept by the oracle.
+    Tolerances: those of the small boxes (FP64: 1e-12 on J, 1e-10 of the largest gradient;
+    FP32: 5e-6), relative."""
+    import copy
+    T, K = 40, 20
+    wl = W.workload(5)
+    w = copy.deepcopy(wl)
+    w["params"]["kT"] = 0.0
+    a = np.zeros((T, 1, 3))
+    a[:, 0, 0] = 1.0 / T
+    print(f"64^3 sphere, {T}-step window, {precision}: oracle reverse pass", flush=True)
+    from tests.helpers import oracle_from_workload
+    orc = oracle_from_workload(w)
+    Jo, dgo, doo = orc.adjoint(T, a)
+    print(f"  oracle J {Jo:.9e} dJ/dgamma {dgo[0]:.9e}", flush=True)
+    sim = _config5_sim(wl, precision, None, None)
+    J, dg, do = sim.adjoint(T, a, checkpoint_every=K)
+    sim.close()
+    eJ = abs(J - Jo) / abs(Jo)
+    eg = abs(dg[0] - dgo[0]) / abs(dgo[0])
+    eo = float(np.abs(do - doo).max() / np.abs(doo).max())
+    print(f"  GPU {precision}: J rel {eJ:.2e}  dgamma rel {eg:.2e}  doffsets rel {eo:.2e}",
+          flush=True)
+    tJ, tg = (1e-12, 1e-10) if precision == "f64" else (5e-6, 5e-6)
+    assert eJ <= tJ and eg <= tg and eo <= tg
 
 
 def test_autograd_function_returns_the_library_gradient():

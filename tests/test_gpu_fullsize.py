@@ -5,7 +5,10 @@
   library over all 5000 steps (same noise streams): body positions, orientations, drag.
 - 512 uneven pore replicas with one ellipsoid each, FP32 thermal, all in one batch: sampled
   replicas against independent oracle boxes, and graph replay of 100 steps against eager
-  launches, bit for bit.
+  launches, bit for bit; the batch's full 10,000 steps in its timed launch configuration
+  (graph replays of 100 steps): finite, every replica's mass conserved to the FP32 rounding
+  bound, and its two smallest replicas against their oracle boxes run over the same 10,000
+  steps.
 - the benchmark's pore (128 x 128 x 256, radius 40, 32 spheres, FP32 thermal) in its timed
   launch configuration (one graph replay of 100 steps): whole fields and every body against
   the oracle; the same pore with the paper's integration scheme (2 MD steps per fluid step,
@@ -14,14 +17,17 @@
 import numpy as np
 import pytest
 
+from oracle import pyoracle as po
 from paper_1604_01829_amd import workloads as W
-from tests.helpers import first_step_expected, gpu_from_workload, oracle_from_workload
+from tests.helpers import (first_step_expected, gpu_from_workload, oracle_from_workload,
+                           population_errors)
 
 pytestmark = pytest.mark.gpu
 
 
-def _field_errors(gpu, orc, r=0):
-    """Max errors of rho and u over fluid nodes, and of every body's state."""
+def _field_errors(gpu, orc, r=0, pops=True):
+    """Max errors of rho and u over fluid nodes, of all 19 populations (against the scale
+    max |f_i - w_i rho0|), and of every body's state."""
     _, bg, fg, rc = gpu.observables(r, fields=True, check=False)
     fo = orc.fields()
     fluid = fo[..., 0] != 0.0
@@ -30,6 +36,11 @@ def _field_errors(gpu, orc, r=0):
            "u": float(np.abs(fg[..., 1:][fluid] - fo[..., 1:][fluid]).max()),
            "u_scale": float(np.abs(fo[..., 1:][fluid]).max()),
            "solid_zero": bool(np.all(fg[~fluid] == 0.0))}
+    del fg, fo
+    if pops:
+        pe = population_errors(gpu, orc, r)
+        out["pop"], out["pop_scale"] = pe["pop_abs"], pe["pop_scale"]
+        out["pop_solid_zero"] = pe["pop_solid_zero"]
     for k in ("pos", "quat", "vel", "omega", "force", "torque"):
         out[k] = 0.0
     out["vel_scale"] = out["omega_scale"] = out["force_scale"] = out["torque_scale"] = 0.0
@@ -51,6 +62,9 @@ def _check(e, tol_u, tol_rho, tol_body):
     assert e["rc"] == 0 and e["solid_zero"]
     assert e["rho"] <= tol_rho
     assert e["u"] <= tol_u * e["u_scale"]
+    if "pop" in e:
+        assert e["pop_solid_zero"]
+        assert e["pop"] <= tol_u * e["pop_scale"], "populations"
     assert e["pos"] <= tol_body and e["quat"] <= tol_body
     for k in ("vel", "omega", "force", "torque"):
         assert e[k] <= tol_u * max(e[k + "_scale"], 1e-14) + 1e-15, k
@@ -133,6 +147,78 @@ def test_512_replicas_sampled_against_oracle():
         print(f"  replica {r} side {sides[r]}:",
               {k: f"{v:.3g}" for k, v in e.items() if isinstance(v, float)}, flush=True)
         _check(e, 1e-5, 1e-6, 1e-6)
+    gpu.close()
+
+
+def test_512_replicas_full_run():
+    """The batch's specified 10,000 steps, replayed as graphs of 100 steps (the timed
+    configuration).  Mass: the node update conserves sum_i f_i exactly in exact arithmetic, so
+    each replica's FP64 total may drift only by the FP32 rounding of the stored shifted
+    populations, at most 2^-24 |f_i - w_i rho0| per stored value and step (a worst-case sum;
+    the actual drift is a random walk far below it).  The two smallest replicas run in their
+    own oracle boxes over the same steps, on host threads while the GPU runs (same seeds and
+    noise streams: the comparison is pathwise)."""
+    import threading
+    wl = _batch()
+    reps = wl["replicas"]
+    T = wl["steps"]
+    sides = np.array([r["shape"][0] for r in reps])
+    small = [int(v) for v in np.argsort(sides, kind="stable")[:2]]
+    print(f"512 replicas, {T} steps; oracle boxes for replicas {small} (side "
+          f"{[int(sides[r]) for r in small]})", flush=True)
+    orcs = {r: oracle_from_workload(wl, r) for r in small}
+    errors = []
+
+    def run(r):
+        try:
+            for k in range(10):
+                orcs[r].step(T // 10)
+                print(f"  oracle replica {r}: step {(k + 1) * (T // 10)}", flush=True)
+        except Exception as exc:   # reported in the main thread
+            errors.append(exc)
+
+    threads = [threading.Thread(target=run, args=(r,)) for r in small]
+    for t in threads:
+        t.start()
+    gpu = gpu_from_workload(wl)
+    gpu.set_graph_steps(100)
+    m0 = np.array([gpu.observables(r)[0]["mass"] for r in range(len(reps))])
+    for k in range(10):
+        gpu.step(T // 10)
+        tot, _, _, rc = gpu.observables(0, check=False)
+        assert rc == 0 and tot["finite"]
+        print(f"  GPU step {tot['step']}", flush=True)
+    m1, finite, bound = np.zeros(len(reps)), True, np.zeros(len(reps))
+    for r in range(len(reps)):
+        tot, _, _, rc = gpu.observables(r, check=False)
+        m1[r] = tot["mass"]
+        finite &= rc == 0 and tot["finite"]
+    w = po.weights()
+    for r in range(0, len(reps), 64):
+        f = gpu.populations(r)
+        fl = np.any(f != 0.0, axis=0)
+        dev = np.abs(f[:, fl] - w[:, None] * wl["params"]["rho0"]).max()
+        bound[r] = T * 19 * fl.sum() * 2.0 ** -24 * dev
+    drift = np.abs(m1 - m0)
+    print(f"  finite {finite}; largest relative mass drift {float((drift / m0).max()):.3g}; "
+          f"sampled drift / worst-case bound {float((drift / np.maximum(bound, 1e-300))[bound > 0].max()):.3g}",
+          flush=True)
+    assert finite
+    assert np.all(drift[bound > 0] <= bound[bound > 0])
+    # every replica: 1e-6 relative, below the worst-case bound of the sampled replicas
+    # (~2e-5 relative: shifted populations of ~1.5e-3 at kT = 4e-5) and far above the
+    # random-walk size of unbiased rounding (~1e-10)
+    assert float((drift / m0).max()) <= 1e-6
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for r in small:
+        e = _field_errors(gpu, orcs[r], r)
+        print(f"  replica {r} after {T} steps:",
+              {k: f"{v:.3g}" for k, v in e.items() if isinstance(v, float)}, flush=True)
+        # the precision study's pathwise bounds for long FP32 runs (positions 2e-5,
+        # quaternions 5e-7) with the first-step field bounds widened 10x for 10,000 steps
+        _check(e, 1e-4, 1e-5, 2e-5)
     gpu.close()
 
 

@@ -241,3 +241,28 @@ def test_sphere_bounces_off_the_pore_beads():
     assert r_on.max() + 3.5 < ring - 0.8 * sigma
     assert r_on[-1] < r_on.max() - 1.0                 # it came back
     assert r_off.max() > r_on.max() + 1.0              # without the repulsion it goes on
+
+
+def test_many_contributions_per_node_fp64_spread_stays_exact():
+    """The FP64 spread keeps each contribution's remainder below 2^-56 in a second fixed-point
+    word; 200 beads at one point of a fixed body with 64 MD steps per fluid step put 12,800
+    contributions on each stencil node in one fluid step.  The remainders must sum without
+    wrapping (a wrapped word shifts the node force by 2^-48, far above the FP64 tolerance)."""
+    shape = (12, 12, 12)
+    offs = np.zeros((200, 3))
+    wl = dict(name="pile", precision="f64", steps=3,
+              params=W.default_params(kT=0.0, u0=(0.01, -0.004, 0.002), md_substeps=64),
+              replicas=[dict(shape=shape, seed=99, mask=None,
+                             bodies=[W.body_record(offs, 1.0, (1.0, 1.0, 1.0),
+                                                   np.array([5.37, 6.21, 4.83]),
+                                                   gamma=1e-4, fixed=True)])])
+    gpu = gpu_from_workload(wl)
+    gpu.set_graph_steps(0)
+    orc = oracle_from_workload(wl)
+    for s in range(1, 4):
+        gpu.step(1)
+        orc.step(1)
+        e = compare(gpu, orc)
+        _print(f"200-bead pile, 64 MD steps, step {s}", e)
+        _assert_close(e, *_tol("f64"))
+    gpu.close()

@@ -3,10 +3,25 @@
 Tolerances (derivation in the design notes):
 - FP64 populations: the GPU stores f - w rho0 and sums in another order, and spreads bead
   forces as 2^-56 fixed point; errors stay at round-off, ~1e-15 per step relative to the
-  field scale, so 1e-12 of the scale is allowed over <= 100 steps.
+  field scale, so 1e-12 of the scale is allowed over <= 100 steps.  The oracle stores the
+  unshifted populations (|f| <= rho0/3 at rest), so its own rounding is ~2^-53 of |f| per
+  operation and accumulates with the steps (measured ~2.7e-16 per step on rho at rho0 = 1,
+  the same sign every step): density, mass and populations are also allowed
+  step * 2^-49 * max|f| (2^-49 rho0 per step for density), 6x the measured drift.
 - FP32 shifted populations: one FP32 rounding of the shifted populations per step (~6e-8
   relative to |f - w rho0| ~ |u|) accumulates over the run; the workload target is 1e-5 of
   the field scale for velocities and 1e-5 relative for density.
+- all 19 populations are compared at every checked step, against the population scale
+  max |f_i - w_i rho0| (FP32 stores exactly these shifted values), with the velocity
+  tolerance; so every moment, the ghost moments included, is checked.
+- body velocity: tol * |V| plus tol / 100 times the gross bead force integrated over the run,
+  step * sum_k |F_k| / M.  The coupling takes the fluid velocity from the rounded
+  populations, so each step's bead forces carry an error of about gamma * 6e-8 |u| per bead
+  (FP32), far below 1e-7 of |F_k|, whose thermal part is identical on both sides; V sums
+  those errors over the steps.  Angular velocity: tol times the larger of |omega| and the
+  integrated gross torque, step * sum_k |r_k - R| |F_k| / I_min (the net omega of a symmetric
+  body is itself a cancelling sum: 3.6e-8 for the sphere of workload 1 after 40 steps).
+- body position: the position tolerance plus step times the velocity bound (R integrates V).
 """
 import numpy as np
 import pytest
@@ -18,27 +33,41 @@ pytestmark = pytest.mark.gpu
 
 
 def _print(tag, e):
-    keys = ["rho", "u_abs", "u_scale", "mass", "momentum", "momentum_scale", "body_pos",
-            "body_quat", "body_vel",
-            "body_force", "scale_force", "body_torque", "scale_torque"]
+    keys = ["rho", "u_abs", "u_scale", "pop_abs", "pop_scale", "mass", "momentum",
+            "momentum_scale", "body_pos", "body_quat", "body_vel", "scale_vel", "scale_vel_int",
+            "body_omega", "scale_omega", "body_force", "scale_force", "body_torque",
+            "scale_torque"]
     print(tag, " ".join(f"{k}={e[k]:.3g}" for k in keys if k in e), flush=True)
+    if "mode_abs" in e:
+        print("   moment errors", " ".join(f"{v:.2g}" for v in e["mode_abs"]), flush=True)
+
+
+ORACLE_ROUNDING_PER_STEP = 2.0 ** -49   # of max|f| (of rho0 for density): see above
 
 
 def _assert_close(e, tol_rel_u, tol_rho, tol_body):
+    steps = e.get("step", 0)
+    drift = steps * ORACLE_ROUNDING_PER_STEP
     assert e["rc"] == 0
     assert e["solid_zero"]
     assert e["finite"]
-    assert e["rho"] <= tol_rho
+    assert e["rho"] <= max(tol_rho, drift), "rho"
     assert e["u_abs"] <= tol_rel_u * max(e["u_scale"], 1e-12)
-    assert e["mass"] <= tol_rho
+    if "pop_abs" in e:
+        assert e["pop_solid_zero"]
+        assert e["pop_abs"] <= (tol_rel_u * max(e["pop_scale"], 1e-12)
+                                + drift * e["pop_max"]), "populations"
+    assert e["mass"] <= max(tol_rho, drift), "mass"
     assert e["momentum"] <= tol_rel_u * e["momentum_scale"] + 1e-15
-    for k in ("pos", "quat"):
-        assert e["body_" + k] <= tol_body
-    for k in ("vel", "omega", "force", "torque"):
-        assert e["body_" + k] <= tol_rel_u * max(e["scale_" + k], 1e-14) + 1e-15
+    vel_bound = (tol_rel_u * e["scale_vel"] + 1e-2 * tol_rel_u * e["scale_vel_int"] + 1e-15)
+    assert e["body_vel"] <= vel_bound, "vel"
+    assert e["body_pos"] <= tol_body + steps * vel_bound, "pos"
+    assert e["body_quat"] <= tol_body, "quat"
+    for k in ("omega", "force", "torque"):
+        assert e["body_" + k] <= tol_rel_u * max(e["scale_" + k], 1e-14) + 1e-15, k
 
 
-def small_sphere_case(precision, kT=0.0, steps=(1, 2, 7, 40)):
+def small_sphere_case(precision, kT=0.0, steps=(1, 2, 7, 40, 500)):
     wl = W.workload(1)
     wl["params"]["kT"] = kT
     wl["precision"] = precision

@@ -174,3 +174,31 @@ def test_analysis_fits_match_the_oracle():
     g, o = GA.hasimoto_intercept(L, d), OA.hasimoto_d0(L, d)
     assert abs(g[0] - o[0]) < 1e-15 and abs(g[1] - o[1]) < 1e-12
     assert GA.einstein(4e-5, g[0]) == OA.einstein_resistance(4e-5, g[0])
+
+
+def test_spread_fixed_point_words_hold_the_worst_case():
+    """The FP64 spread splits each contribution v into hi = floor(v 2^56) and a remainder
+    lo = floor((v 2^56 - hi) 2^48) in units of 2^-104, summed as 64-bit integers on each node
+    and read back unsigned.  lo < 2^48 for every v, so 65,535 worst-case remainders sum below
+    2^64 (no wrap), and hi 2^-56 + lo 2^-104 recovers v to 2^-104."""
+    import math
+    assert (2 ** 48 - 1) * 65535 < 2 ** 64
+    assert (2 ** 56 - 1) * 256 >= 2 ** 63      # a 56-bit remainder would wrap at 128 terms
+    rng = np.random.default_rng(2)
+    vals = np.concatenate([rng.normal(0, 1e-4, 2000), rng.uniform(-15.9, 15.9, 2000),
+                           [0.0, -0.0, 2.0 ** -60, -2.0 ** -60, 1 - 2.0 ** -53, -15.999]])
+    total_hi = total_lo = 0
+    for v in vals:
+        x = float(v) * 2.0 ** 56
+        h = math.floor(x)
+        lo = int((x - h) * 2.0 ** 48)
+        assert 0 <= lo < 2 ** 48
+        rec = h * 2.0 ** -56 + lo * 2.0 ** -104
+        assert abs(rec - v) <= 2.0 ** -104 + abs(v) * 2.0 ** -52
+        total_hi += h
+        total_lo += lo
+    # the exact integer sums recover the exact sum of the values to 2^-104 per term
+    from fractions import Fraction
+    exact = sum(Fraction(float(v)) for v in vals)
+    got = Fraction(total_hi, 2 ** 56) + Fraction(total_lo, 2 ** 104)
+    assert abs(float(got - exact)) <= len(vals) * 2.0 ** -104
