@@ -1,30 +1,36 @@
 #!/usr/bin/env python3
 """Throughput of the fused lattice-Boltzmann + raspberry-coupling step on one MI355X.
 
-Default workload: a 128x128x256 box holding a cylindrical pore of radius 40 along z
-(1,286,144 fluid nodes), thermal fluid (kT = 4e-5) with counter-based noise, 32 raspberry
-spheres of radius 2-6 (about 15k beads), FP32 populations stored shifted by w_i rho0.
-One step = body half kick/drift, bead coupling + force spreading, body force/torque sums
-and second half kick, fused collide-and-stream of every fluid node.  Inputs are synthetic
-and resident in HBM before timing; the steps run as HIP-graph replays.
+Default workload: a batch of 512 independent replica boxes of uneven size (cubic sides drawn
+from {32, 40, 48, 56, 64}; about 66M nodes, 33M of them fluid), each holding a cylindrical
+pore of radius 0.4 side along z and one raspberry ellipsoid (prolate, aspect ratio 1-4,
+equal-volume radius 0.1 side, about 400 beads), thermal fluid (kT = 4e-5) with independent
+counter-based noise per replica, bead friction gamma = 1/6 (the paper's low bead friction in
+lattice units), FP32 populations stored shifted by w_i rho0, all replicas in one flat tile
+list, HIP-graph replays of 100 steps.  One step = body half kick/drift, bead coupling + force
+spreading, body force/torque sums and second half kick, fused collide-and-stream of every
+fluid node.  Inputs are synthetic and resident in HBM before timing.
 
 Prints one JSON line.  `value` = fluid-node updates per second / 1e6 (MLUPS) over the timed
 steps.  `roofline` is for the dominant kernel, node_step (the update of every fluid node; its
-few leading workgroups finish the bodies): algorithmic bytes 152 B (FP32) or 304 B (FP64) per
+leading workgroups finish the bodies): algorithmic bytes 152 B (FP32) or 304 B (FP64) per
 fluid node (19 populations read + written) divided by its mean duration from HIP events
-recorded by the dispatch of each launch on the library's stream, in a separate eager window of the same
-run.  `cpu_baseline` times the FP64 CPU oracle on a few steps of the same box.
+recorded by the dispatch of each launch on the library's stream, in a separate eager window
+of the same run; `step_frac` is the same bytes over the whole timed step (coupling, body
+finishing, node update and the gaps between launches).  `cpu_baseline` times the FP64 CPU
+oracle on 16 sampled replicas of the same batch: a 50-step window on every host thread, and a
+shorter window on one thread.
 
-`compare` (default workload only) measures, on the same GPU in the same process:
-  fp64            the same workload with FP64 populations;
-  batched_fp32    512 uneven pore replicas (sides 32-64, one ellipsoid each, thermal) in one
-                  batch, 100-step graph replays, with its node_step roofline;
-  plain_fp64      a sample of those replicas run one context at a time in FP64;
-  box256_fp32/64  the 256^3 periodic box with 16 ellipsoids (larger than the on-package
-                  cache, so its node_step bandwidth is HBM bandwidth);
-  adjoint         64^3 box, fixed sphere of 401 beads, 200-step window with checkpoints every
-                  20 steps: the reverse pass (forward + recompute + reverse) against 200
-                  forward steps; and the same window with every state kept (no recompute).
+`compare` (unless --no-compare) measures, on the same GPU in the same process:
+  batched_fp64    the same 512 replicas in one batch with FP64 populations (precision alone);
+  plain_fp64      16 sampled replicas run one FP64 context at a time (neither batching nor
+                  the FP32 storage);
+  pore128_f32/64  one 128x128x256 box holding a radius-40 pore with 32 spheres (its population
+                  buffers fit in the 256 MB on-package cache, so node_step bandwidth there is
+                  partly cache bandwidth);
+  box256_f32/64   the 256^3 periodic box with 16 ellipsoids (HBM-resident);
+  confined_md     the paper's integration scheme on the pore: 2 MD steps per fluid step, WCA;
+  construction, analysis, adjoint   raspberry relaxation, trajectory analysis, reverse pass.
 """
 import argparse
 import hashlib
@@ -36,6 +42,13 @@ import time
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 WORKLOAD_TAGS = {2: "pore128x128x256", 3: "box256", 4: "batch512"}
+METRIC = "MLUPS (D3Q19 LB + raspberry coupling) and % HBM roofline, batched FP32 vs FP64"
+NAMES = {2: "pore 128x128x256 (radius 40, 1,286,144 fluid nodes), 32 raspberry spheres R~U[2,6] "
+            "(gamma 1/6), thermal kT=4e-5",
+         3: "256^3 periodic box, 16 raspberry ellipsoids (gamma 1/6), thermal kT=4e-5",
+         4: "batch of 512 uneven pore replicas (cubic sides from {32,40,48,56,64}, pore radius "
+            "0.4 side along z), one raspberry ellipsoid each (aspect 1-4, gamma 1/6), thermal "
+            "kT=4e-5, independent Philox seeds, one flat tile list, 100-step HIP-graph replays"}
 
 
 def parse():
@@ -44,17 +57,18 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4],
-                    help="2 = pore with 32 spheres (default), 3 = 256^3 box with 16 "
-                         "ellipsoids, 4 = 512 pore replicas")
+    ap.add_argument("--workload", type=int, default=4, choices=[2, 3, 4],
+                    help="4 = 512 pore replicas in one batch (default), 2 = one pore with 32 "
+                         "spheres, 3 = 256^3 box with 16 ellipsoids")
     ap.add_argument("--timing-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target length of each CPU-baseline leg")
     ap.add_argument("--graph-steps", type=int, default=100,
                     help="steps per HIP-graph replay (0 = eager launches, for profilers)")
-    ap.add_argument("--step-policy", default="auto", choices=["auto", "serial", "overlap"],
-                    help="how the main workload's fluid step is launched (lb_set_step_policy)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the untuned node-update launch settings (no lb_autotune)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before the run, copy a buffer of this many MiB three times with a "
                          "plain device copy (reference for hardware byte counters)")
@@ -88,36 +102,68 @@ def traffic_from_profiles(kernel_tag):
         return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def replica_sample(n_replicas, k=16, seed=1):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return sorted(rng.choice(n_replicas, min(k, n_replicas), replace=False).tolist())
+
+
 def cpu_baseline(wl, seconds):
-    """The FP64 oracle on the same box: one step to size the sample, then as many steps as
-    fit in about `seconds`."""
+    """The FP64 oracle on a bounded sample of the same batch: 16 sampled replicas, each built
+    as its own oracle box.  Leg 1: every host thread, one sizing step per replica, then a
+    window of up to 50 steps per replica sized to about `seconds`.  Leg 2: one thread, a
+    window sized the same way from leg 1's rate.  Set-up is not timed."""
     sys.path.insert(0, ROOT)
+    import numpy as np
     from oracle import pyoracle as po
     from tests.helpers import oracle_from_workload
-    orc = oracle_from_workload(wl)
-    rep = wl["replicas"][0]
-    n_fluid = int((rep["mask"] == 0).sum()) if rep["mask"] is not None else \
-        rep["shape"][0] * rep["shape"][1] * rep["shape"][2]
-    t0 = time.perf_counter()
-    orc.step(1)
-    t1 = time.perf_counter() - t0
-    k = max(1, int(seconds / max(t1, 1e-3)) - 1)
-    t0 = time.perf_counter()
-    orc.step(k)
-    dt = time.perf_counter() - t0
-    return {"value": round(n_fluid * k / dt / 1e6, 3), "unit": "MLUPS", "cores": po.num_threads(),
-            "kind": "oracle",
-            "sample": f"{k} steps (after 1 sizing step) of the same box, FP64, {dt:.1f} s"}
+    reps = wl["replicas"]
+    sample = replica_sample(len(reps))
+    fluid = [int((reps[r]["mask"] == 0).sum()) if reps[r]["mask"] is not None
+             else int(np.prod(reps[r]["shape"])) for r in sample]
+    threads = po.num_threads()
+
+    def window(n_steps):
+        upd, dt = 0, 0.0
+        for r, nf in zip(sample, fluid):
+            orc = oracle_from_workload(wl, r)
+            t0 = time.perf_counter()
+            orc.step(n_steps)
+            dt += time.perf_counter() - t0
+            upd += nf * n_steps
+            del orc
+        return upd / dt / 1e6, dt
+
+    rate1, _ = window(1)                                   # sizing
+    k_all = int(max(1, min(50, seconds * rate1 * 1e6 / max(1, sum(fluid)))))
+    rate_all, t_all = window(k_all)
+    po.set_num_threads(1)
+    try:
+        k_one = int(max(1, min(50, seconds * rate_all / threads * 1e6 / max(1, sum(fluid)))))
+        rate_one, t_one = window(k_one)
+    finally:
+        po.set_num_threads(threads)
+    return {"value": round(rate_all, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sample)} sampled replicas of the same batch ({sum(fluid)} fluid "
+                      f"nodes), {k_all} steps each on {threads} threads ({t_all:.1f} s), FP64",
+            "single_thread": {"value": round(rate_one, 3), "unit": "MLUPS", "cores": 1,
+                              "sample": f"the same replicas, {k_one} steps each ({t_one:.1f} s)"},
+            "cpu_model": cpu_model()}
 
 
-def measure(sim, steps, warmup, timing_steps, graph_steps, precision, policy=None):
-    """Timed graph-replayed steps, then an eager window with per-launch HIP events.  In the
-    overlapped step both launches update nodes (the coupling runs inside the first, the body
-    finishing inside the second); node_us is then their sum per step and couple_us is 0."""
+def measure(sim, steps, warmup, timing_steps, graph_steps, precision):
+    """Timed graph-replayed steps, then an eager window with per-launch HIP events."""
     import torch
-    if policy is not None:
-        sim.set_step_policy(policy)
-    overlapped = sim.step_overlapped()
     n_nodes = n_fluid = 0
     for r in range(len(sim.shapes)):
         a, b = sim.node_counts(r)
@@ -138,64 +184,53 @@ def measure(sim, steps, warmup, timing_steps, graph_steps, precision, policy=Non
     sim.step(timing_steps)
     kt = sim.kernel_times()
     sim.set_timing(False)
-    if overlapped:
-        node_s = kt["node_ms"] / timing_steps / 1e3
-        couple_s = 0.0
-    else:
-        node_s = kt["node_ms"] / max(1, kt["node_launches"]) / 1e3
-        couple_s = kt["couple_ms"] / max(1, kt["couple_launches"]) / 1e3
+    # per step: every node-update launch of the step (one per tile group)
+    node_s = kt["node_ms"] / timing_steps / 1e3
+    couple_s = kt["couple_ms"] / timing_steps / 1e3
     bpn = algorithmic_bytes_per_node(precision)
     achieved = bpn * n_fluid / node_s / 1e9
+    step_s = dt / steps
     return {"mlups": n_fluid * steps / dt / 1e6, "all_node_mlups": n_nodes * steps / dt / 1e6,
-            "ms_per_step": dt / steps * 1e3, "n_fluid": n_fluid, "n_nodes": n_nodes,
+            "ms_per_step": step_s * 1e3, "n_fluid": n_fluid, "n_nodes": n_nodes,
             "finite": finite, "node_us": node_s * 1e6, "couple_us": couple_s * 1e6,
-            "node_gbs": achieved, "bytes_per_launch": bpn * n_fluid, "overlapped": overlapped}
+            "node_gbs": achieved, "step_gbs": bpn * n_fluid / step_s / 1e9,
+            "bytes_per_launch": bpn * n_fluid,
+            "node_launches_per_step": kt["node_launches"] / timing_steps}
 
 
-def compare_runs(args):
+def _short(m, prec):
+    return {"mlups": round(m["mlups"], 1), "ms_per_step": round(m["ms_per_step"], 5),
+            "node_step_us": round(m["node_us"], 2),
+            "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
+            "step_frac": round(m["step_gbs"] / HBM_PEAK_GBS, 4),
+            "couple_us": round(m["couple_us"], 2), "finite": m["finite"]}
+
+
+def compare_runs(args, wl4):
     import numpy as np
     import torch
     from paper_1604_01829_amd import lbrb
     from paper_1604_01829_amd import workloads as W
 
     out = {}
-    # same pore workload, FP32, with the overlapped step (coupling alongside the node update
-    # of the tiles without spread force; body finishing alongside the remaining tiles)
-    wl2 = W.workload(2)
-    sim = lbrb.simulation_from_workload(wl2, precision="f32")
-    m = measure(sim, 2000, 200, 100, 100, "f32", policy=lbrb.LB_STEP_OVERLAP)
-    sim.close()
-    out["overlapped_step_fp32"] = {"mlups": round(m["mlups"], 1),
-                                   "ms_per_step": round(m["ms_per_step"], 5),
-                                   "node_update_us_per_step": round(m["node_us"], 2),
-                                   "overlapped": m["overlapped"]}
-    # same pore workload, FP64 populations
-    wl2 = W.workload(2)
-    sim = lbrb.simulation_from_workload(wl2, precision="f64")
-    m = measure(sim, 1000, 100, 100, 100, "f64")
-    sim.close()
-    out["fp64"] = {"mlups": round(m["mlups"], 1), "ms_per_step": round(m["ms_per_step"], 5),
-                   "node_step_us": round(m["node_us"], 2),
-                   "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
-                   "overlapped": m["overlapped"]}
-    # 512 uneven pore replicas in one batch, FP32
-    wl4 = W.workload(4)
+    # the same batch with the untuned launch settings
     sim = lbrb.simulation_from_workload(wl4, precision="f32")
-    m = measure(sim, 400, 100, 100, 100, "f32")
+    m = measure(sim, 400, 100, 50, 100, "f32")
     sim.close()
-    out["batched_fp32"] = {
-        "replicas": len(wl4["replicas"]), "fluid_nodes": m["n_fluid"], "all_nodes": m["n_nodes"],
-        "mlups": round(m["mlups"], 1), "all_node_mlups": round(m["all_node_mlups"], 1),
-        "ms_per_step": round(m["ms_per_step"], 5), "node_step_us": round(m["node_us"], 2),
-        "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
-        "couple_us": round(m["couple_us"], 2), "finite": m["finite"],
-        "overlapped": m["overlapped"]}
     del sim
     torch.cuda.empty_cache()
+    out["batched_fp32_untuned"] = _short(m, "f32")
+    # the same 512 replicas in one batch, FP64 populations: precision alone
+    sim = lbrb.simulation_from_workload(wl4, precision="f64")
+    sim.autotune()
+    m = measure(sim, 200, 50, 50, 100, "f64")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    out["batched_fp64"] = _short(m, "f64")
     # the plain path: a sample of the same replicas, one FP64 context at a time
-    rng = np.random.default_rng(1)
-    sample = sorted(rng.choice(len(wl4["replicas"]), 16, replace=False).tolist())
     upd, tsum = 0, 0.0
+    sample = replica_sample(len(wl4["replicas"]))
     for r in sample:
         sim = lbrb.simulation_from_workload(wl4, precision="f64", replicas=[r])
         sim.set_graph_steps(100)
@@ -208,23 +243,34 @@ def compare_runs(args):
         upd += sim.node_counts(0)[1] * 200
         sim.close()
     out["plain_fp64"] = {"replicas_sampled": len(sample), "mlups": round(upd / tsum / 1e6, 1)}
-    out["batched_fp32_over_plain_fp64"] = round(out["batched_fp32"]["mlups"] /
-                                                out["plain_fp64"]["mlups"], 2)
+    # one pore with 32 spheres (buffers inside the on-package cache)
+    wl2 = W.workload(2)
+    for prec, steps in (("f32", 2000), ("f64", 1000)):
+        for tuned in (False, True):
+            sim = lbrb.simulation_from_workload(wl2, precision=prec)
+            tune = sim.autotune() if tuned else None
+            m = measure(sim, steps, 200, 100, 100, prec)
+            sim.close()
+            key = "pore128_" + prec + ("" if tuned else "_untuned")
+            out[key] = _short(m, prec)
+            if tuned:
+                out[key]["tuned"] = tune
+                out[key]["traffic"] = traffic_from_profiles(f"node_step_{prec}_pore128x128x256")
     # 256^3 box, 16 ellipsoids: HBM-resident
     wl3 = W.workload(3)
-    for prec in ("f32", "f64"):
+    for prec, tuned in (("f32", False), ("f32", True), ("f64", True)):
         sim = lbrb.simulation_from_workload(wl3, precision=prec)
+        tune = sim.autotune() if tuned else None
         m = measure(sim, 400, 100, 100, 100, prec)
         sim.close()
         del sim
         torch.cuda.empty_cache()
-        out["box256_" + prec] = {"mlups": round(m["mlups"], 1),
-                                 "ms_per_step": round(m["ms_per_step"], 5),
-                                 "node_step_us": round(m["node_us"], 2),
-                                 "node_step_gbs": round(m["node_gbs"], 1),
-                                 "node_step_frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
-                                 "overlapped": m["overlapped"],
-                                 "traffic": traffic_from_profiles(f"node_step_{prec}_box256")}
+        key = "box256_" + prec + ("" if tuned else "_untuned")
+        out[key] = _short(m, prec)
+        out[key]["node_step_gbs"] = round(m["node_gbs"], 1)
+        if tuned:
+            out[key]["tuned"] = tune
+            out[key]["traffic"] = traffic_from_profiles(f"node_step_{prec}_box256")
     # the paper's integration scheme on the same pore: 2 MD steps per fluid step, inner
     # excluded-volume layers on the spheres and WCA pore beads (eps = kT)
     wlm = W.confined_md_workload(substeps=2)
@@ -271,9 +317,9 @@ def compare_runs(args):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = fn()
+        res = fn()
         torch.cuda.synchronize()
-        return out, (time.perf_counter() - t0) * 1e3
+        return res, (time.perf_counter() - t0) * 1e3
 
     lab, t_lab = timed(lambda: AN.lab_frame(traj))
     _, t_msd3 = timed(lambda: AN.msd(lab, LAGS))
@@ -324,7 +370,8 @@ def compare_runs(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this library runs on one GPU: every figure is a one-GPU "
+                                   "figure, and --gpus must be 1"}), flush=True)
         sys.exit(2)
     sys.path.insert(0, ROOT)
     import torch
@@ -342,23 +389,16 @@ def main():
         del a, b
     wl = W.workload(args.workload)
     sim = lbrb.simulation_from_workload(wl, precision=args.precision)
+    tune = sim.tuned_settings() if args.no_tune else sim.autotune()
     n_beads = sum(b["offsets"].shape[0] for r in wl["replicas"] for b in r["bodies"])
     n_bodies = sum(len(r["bodies"]) for r in wl["replicas"])
-    policy = {"auto": lbrb.LB_STEP_AUTO, "serial": lbrb.LB_STEP_SERIAL,
-              "overlap": lbrb.LB_STEP_OVERLAP}[args.step_policy]
-    m = measure(sim, args.steps, args.warmup, args.timing_steps, args.graph_steps, args.precision,
-                policy=policy)
+    m = measure(sim, args.steps, args.warmup, args.timing_steps, args.graph_steps, args.precision)
     sim.close()
     del sim
     torch.cuda.empty_cache()
     tag = f"node_step_{args.precision}_{WORKLOAD_TAGS[args.workload]}"
-    names = {2: "pore 128x128x256 (radius 40, 1,286,144 fluid nodes), 32 raspberry spheres "
-                "R~U[2,6], thermal kT=4e-5",
-             3: "256^3 periodic box, 16 raspberry ellipsoids, thermal kT=4e-5",
-             4: "512 uneven pore replicas (sides 32-64, pore radius 0.4 side), one ellipsoid "
-                "each, thermal kT=4e-5"}
     out = {
-        "metric": "MLUPS (D3Q19 LB + raspberry coupling) and % HBM roofline",
+        "metric": METRIC,
         "value": round(m["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -370,25 +410,33 @@ def main():
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": names[args.workload] + (", FP32 shifted populations"
+        "config": {"workload": NAMES[args.workload] + (", FP32 shifted populations"
                                                        if args.precision == "f32"
                                                        else ", FP64 populations"),
+                   "replicas": len(wl["replicas"]),
                    "fluid_nodes": m["n_fluid"], "all_nodes": m["n_nodes"],
                    "all_node_mlups": round(m["all_node_mlups"], 1), "beads": n_beads,
                    "bodies": n_bodies, "graph_steps": args.graph_steps,
-                   "finite_after_run": m["finite"]},
+                   "tuned": tune, "finite_after_run": m["finite"]},
         "roofline": {"bound": "hbm", "achieved": round(m["node_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(m["node_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profiles(tag),
-                     "kernel": ("node update of the overlapped step (overlap_free + "
-                                "overlap_forced, per step)" if m["overlapped"] else "node_step"),
+                     "kernel": "node_step",
                      "algorithmic_bytes_per_launch": m["bytes_per_launch"],
-                     "mean_launch_us": round(m["node_us"], 3),
-                     "couple_mean_launch_us": round(m["couple_us"], 3)},
+                     "node_step_us_per_step": round(m["node_us"], 3),
+                     "node_launches_per_step": m["node_launches_per_step"],
+                     "couple_us_per_step": round(m["couple_us"], 3),
+                     "step_achieved": round(m["step_gbs"], 1),
+                     "step_frac": round(m["step_gbs"] / HBM_PEAK_GBS, 4)},
     }
-    if args.workload == 2 and not args.no_compare:
-        out["compare"] = compare_runs(args)
-    if not args.no_cpu_baseline and args.workload == 2:
+    if not args.no_compare and args.workload == 4:
+        cmp = compare_runs(args, wl)
+        cmp["batched_fp32_over_batched_fp64"] = round(m["mlups"] / cmp["batched_fp64"]["mlups"], 3)
+        cmp["batched_fp32_over_plain_fp64"] = round(m["mlups"] / cmp["plain_fp64"]["mlups"], 2)
+        cmp["batched_fp64_over_plain_fp64"] = round(cmp["batched_fp64"]["mlups"] /
+                                                    cmp["plain_fp64"]["mlups"], 2)
+        out["compare"] = cmp
+    if not args.no_cpu_baseline and args.workload == 4:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

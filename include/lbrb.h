@@ -285,31 +285,42 @@ int lb_kernel_times(lb_ctx* ctx, double* node_ms, int64_t* node_launches, double
 /* How the node update stores the populations.  LB_STORES_STREAMING: non-temporal stores,
  * which bypass the caches -- faster (3-5 % on MI355X) once the two population buffers are far
  * larger than the 256 MB Infinity Cache, much slower (about 25 %) when they fit in it.
- * LB_STORES_CACHED: ordinary stores.  LB_STORES_AUTO (default): streaming when the
- * populations of the fluid nodes, in both buffers, exceed 256 MiB.                         */
+ * LB_STORES_CACHED: ordinary stores.  LB_STORES_AUTO (default): the choice of lb_autotune
+ * once it has run on this context, else streaming when the populations of the fluid nodes, in
+ * both buffers, exceed 256 MiB.                                                            */
 #define LB_STORES_AUTO 0
 #define LB_STORES_CACHED 1
 #define LB_STORES_STREAMING 2
 int lb_set_store_policy(lb_ctx* ctx, int32_t policy);
 
-/* How a fluid step is launched.  LB_STEP_SERIAL: the bead coupling, then the node update of
- * every tile (whose leading workgroups finish the bodies).  LB_STEP_OVERLAP: two launches
- * that run the coupling concurrently with node updates -- (1) the coupling together with the
- * node update of the tiles that receive no spread force in this step, (2) the body
- * finishing together with the node update of the remaining tiles; the body finishing marks
- * the tiles under the next step's bead stencils.  It applies to contexts whose replicas are
- * all masked or all unmasked, with bodies, one MD step per fluid step and no excluded
- * volume; elsewhere the serial step runs.  Both give the same results bit for bit.  On
- * MI355X the overlapped step is the slower one (launch (1) needs the coupling's registers
- * for every workgroup, launch (2) waits for the body finishing), so LB_STEP_AUTO (default)
- * is the serial step.  lb_step_overlapped sets *out to 1 if the next step will be
- * overlapped.  With timing on, both launches of an overlapped step count as node launches
- * and no coupling launch is counted (the coupling runs inside the first).                  */
-#define LB_STEP_AUTO 0
-#define LB_STEP_SERIAL 1
-#define LB_STEP_OVERLAP 2
-int lb_set_step_policy(lb_ctx* ctx, int32_t policy);
-int lb_step_overlapped(lb_ctx* ctx, int32_t* out);
+/* Launch settings of the node update, chosen by timing (not in the paper: a property of the
+ * GPU).  lb_autotune times the context's own node kernel over its own tiles for every
+ * combination of node tiles per workgroup (1 or 4; 256 nodes each), a cap on the node
+ * workgroups resident per compute unit (none, 6, 5, 4; by dynamic LDS) and the store kind
+ * (ordinary or non-temporal; only the forced kind under LB_STORES_CACHED/STREAMING), and
+ * keeps the fastest for the following steps if it beats the untuned settings by at least
+ * 1 % (else the untuned ones).  The timed launches leave the simulation state
+ * unchanged (no spread force is consumed, no body is finished; they write the buffer the next
+ * step overwrites).  Results are kept for the process per (GPU architecture, precision,
+ * thermal, tile counts, fluid nodes, store policy): repeats = 0 takes a kept result when there
+ * is one and otherwise times 3 launches per setting; repeats > 0 always times that many and
+ * replaces the kept result.  Synchronises the stream.  LB_ERR_ARG for repeats outside
+ * 0..1000.  The choice changes no result, only speed.                                       */
+typedef struct {
+    int32_t tuned;            /* 1 once lb_autotune has run on this context                 */
+    int32_t tiles_per_wg;     /* node tiles (256 nodes) per node-update workgroup           */
+    int32_t wg_per_cu;        /* cap on node-update workgroups per compute unit (0: none)   */
+    int32_t streaming;        /* 1: non-temporal population stores in use                   */
+    int32_t candidates;       /* settings timed                                             */
+    double node_us_default;   /* one node update of every tile with the untuned settings, us */
+    double node_us_tuned;     /* the same with the chosen settings, us                      */
+} lb_tuning;
+int lb_autotune(lb_ctx* ctx, int32_t repeats);
+int lb_get_tuning(const lb_ctx* ctx, lb_tuning* out);
+/* Apply settings directly (for instance ones kept from an earlier process): tiles_per_wg
+ * 1 or 4, wg_per_cu 0..32, streaming 0/1 (used while the store policy is LB_STORES_AUTO); the
+ * other fields are ignored.  LB_ERR_ARG outside those ranges.                               */
+int lb_set_tuning(lb_ctx* ctx, const lb_tuning* settings);
 
 /* Reverse-mode derivative of a window of steps (not in the paper: the hand adjoint of the
  * coupled update of Sec. 1.1-1.2 -- streaming with bounce-back, the mode-space collision

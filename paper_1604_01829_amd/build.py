@@ -5,7 +5,7 @@ instructions are disabled for the device code (-packed-fp32-ops); the host pass 
 warns that it does not know that feature, which is harmless.  Multiply-adds are fused only
 within one source expression (-ffp-contract=on): fusion across statements, which the backend
 decides per kernel, would let the same collision code round differently in different kernels
-(the serial and the overlapped step must agree bit for bit).
+(the forward step and the reverse pass's replays of it must agree bit for bit).
 """
 import os
 import shutil

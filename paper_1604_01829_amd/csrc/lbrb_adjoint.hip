@@ -40,8 +40,7 @@ __global__ __launch_bounds__(kNodeBlock) void adj_node_kernel(const AdjArgs<Real
     const int64_t g = R.base + local;
     Real F[3] = {a.gext[0], a.gext[1], a.gext[2]};
     if (a.flags[g]) {
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) F[ax] += take_spread_force<Real>(a.gforce, a.N, ax, g);
+        take_spread_force<Real>(a.gforce, g, F);
         a.flags[g] = 0;
     }
     Real lF[3];

@@ -11,6 +11,8 @@
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -39,12 +41,12 @@ struct Plan {
     int64_t bead_cap = 0, body_cap = 0;
     int64_t link_cap = 0;     // moving-wall links
     int64_t ev_cap = 0, site_cap = 0, cells_cap = 0, fine_cap = 0;   // excluded volume
-    int gforce_words = 3;     // fixed-point words per node: 3 axes x (1 in FP32, 2 in FP64)
+    int gforce_words = 4;     // fixed-point words per node: 3 axes x (1 in FP32, 2 in FP64),
+                              // padded to 4 (32 bytes) or 8 (64 bytes)
     size_t off_hdr, off_reps, off_rows, off_rowinfo, off_tiles_d, off_tiles_m, off_fa, off_fb,
         off_gforce, off_flags, off_bodies, off_bead_off, off_bead_rec, off_bead_force,
         off_bead_torque, off_partials, off_links, off_ev, off_wrep, off_rep_bodies,
-        off_nb_start, off_nb_sites, off_near, off_wca_ft, off_tmark, off_tlist, off_tcount,
-        off_tile_of, total;
+        off_nb_start, off_nb_sites, off_near, off_wca_ft, total;
 };
 
 constexpr int kMaxCellsPerAxis = 32;   // WCA coarse grid: cells per axis at most
@@ -105,7 +107,8 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
     pl.off_tiles_m = take(sizeof(NodeTile) * pl.tiles_cap);
     pl.off_fa = take(real * Q * pl.N);
     pl.off_fb = take(real * Q * pl.N);
-    pl.gforce_words = p->precision == LB_PRECISION_F32 ? 3 : 6;
+    pl.gforce_words = p->precision == LB_PRECISION_F32 ? spread_stride<float>()
+                                                       : spread_stride<double>();
     pl.off_gforce = take(sizeof(long long) * pl.gforce_words * pl.N);
     pl.off_flags = take(pl.N);
     pl.off_bodies = take(sizeof(Body) * std::max<int64_t>(pl.body_cap, 1));
@@ -123,11 +126,6 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
     pl.off_nb_sites = take(sizeof(WallSite) * 27 * std::max<int64_t>(pl.site_cap, 1));
     pl.off_near = take(std::max<int64_t>(pl.fine_cap, 1));
     pl.off_wca_ft = take(sizeof(double) * 6 * std::max<int64_t>(pl.body_cap, 1));
-    // overlapped step: tile marks and lists of both parities, global tile -> tile index
-    pl.off_tmark = take(sizeof(uint32_t) * 2 * pl.tiles_cap);
-    pl.off_tlist = take(sizeof(int32_t) * 2 * pl.tiles_cap);
-    pl.off_tcount = take(sizeof(int32_t) * 2);
-    pl.off_tile_of = take(sizeof(int32_t) * pl.tiles_cap);
     pl.total = o;
     return true;
 }
@@ -149,6 +147,16 @@ struct EvHost {
 };
 
 struct EventPair { hipEvent_t a, b; };
+
+// Node-update launch settings chosen by lb_autotune (defaults until then)
+struct Tuning {
+    bool tuned = false;
+    int32_t tiles_per_wg = 1;
+    int32_t wg_per_cu = 0;
+    int32_t streaming = 0;          // non-temporal population stores
+    double us_default = 0.0, us_best = 0.0;
+    int32_t candidates = 0;
+};
 
 }  // namespace
 
@@ -183,7 +191,6 @@ struct lb_ctx {
     WallSite* d_nb_sites = nullptr;
     uint8_t* d_near = nullptr;
     double* d_wca_ft = nullptr;
-    TileMarks marks{};              // overlapped step
     std::vector<EvHost> ev;         // per body
     int64_t n_ev = 0, n_sites = 0;
     bool wca_dirty = false;         // site tables to rebuild before the next step
@@ -207,8 +214,7 @@ struct lb_ctx {
     // timing
     bool timing = false;
     int32_t store_policy = LB_STORES_AUTO;
-    int32_t step_policy = LB_STEP_AUTO;
-    bool marks_valid = false;       // the tile marks describe the coming step's stencils
+    Tuning tune;
     std::vector<EventPair> ev_node, ev_couple_t, ev_pool;
 };
 
@@ -255,13 +261,14 @@ CollideParams<Real> collide_params(const lb_params& p)
     return cp;
 }
 
-// non-temporal population stores: forced by the policy, or (automatic) once the populations
-// the steps touch -- the fluid nodes of every replica, in both buffers -- exceed the Infinity
-// Cache
+// non-temporal population stores: forced by the policy, else the tuned choice (lb_autotune),
+// else once the populations the steps touch -- the fluid nodes of every replica, in both
+// buffers -- exceed the Infinity Cache
 bool streaming_stores(const lb_ctx* c)
 {
     if (c->store_policy == LB_STORES_CACHED) return false;
     if (c->store_policy == LB_STORES_STREAMING) return true;
+    if (c->tune.tuned) return c->tune.streaming != 0;
     const double real = c->p.precision == LB_PRECISION_F32 ? 4.0 : 8.0;
     double nodes = 0.0;
     for (int r = 0; r < c->n_rep; ++r) nodes += (double)pad_nodes(c->reps[r].n_fluid);
@@ -281,6 +288,8 @@ StepArgs<Real> step_args_on(const lb_ctx* c, int group, const void* src, void* d
     a.rowinfo = c->d_rowinfo;
     a.tiles = c->d_tiles[group];
     a.n_tiles = (int32_t)c->tiles[group].size();
+    a.tiles_per_wg = std::max(1, (int)c->tune.tiles_per_wg);
+    a.wg_per_cu = c->tune.wg_per_cu;
     a.thermal = c->p.kT > 0.0 ? 1 : 0;
     a.narrow = c->narrow[group] ? 1 : 0;
     a.stream_stores = streaming_stores(c) ? 1 : 0;
@@ -333,28 +342,10 @@ BodyArgs body_args(const lb_ctx* c)
     ba.nb_start = c->d_nb_start;
     ba.nb_sites = c->d_nb_sites;
     ba.near = c->d_near;
-    ba.rowinfo = c->d_rowinfo;
     return ba;
 }
 
 bool any_masked(const lb_ctx* c) { return !c->tiles[1].empty(); }
-
-// The overlapped step (coupling alongside the node update of the tiles without spread force)
-// covers one tile group, one MD step per fluid step and no excluded volume; it runs only when
-// asked for (LB_STEP_OVERLAP): on the measured workloads it is slower than the serial step.
-bool overlap_possible(const lb_ctx* c)
-{
-    const bool one_group = c->tiles[0].empty() != c->tiles[1].empty();
-    bool wca = false;   // from the host records: the device site tables follow at the next step
-    if (c->p.wca_epsilon > 0.0)
-        for (const EvHost& e : c->ev) wca = wca || !e.off.empty();
-    return c->n_beads > 0 && one_group && md_steps(c) == 1 && !wca;
-}
-
-bool use_overlap(const lb_ctx* c)
-{
-    return c->step_policy == LB_STEP_OVERLAP && overlap_possible(c);
-}
 
 EventPair get_pair(lb_ctx* c)
 {
@@ -369,55 +360,28 @@ EventPair get_pair(lb_ctx* c)
     return e;
 }
 
-// Enqueue one step on stream s: the coupling (with bodies), then the node update of each
-// tile group; the first node launch also finishes the bodies.  In capture mode the kernels
-// read the step counter from device memory (step_ptr + step_arg).  Returns the first HIP
-// error of the enqueued calls.
+// The couplings of one fluid step on stream s, pulling from buffer src_buf; every MD step but
+// the last also finishes the bodies.  In capture mode the kernels read the step counter from
+// device memory (step_ptr + step_arg).
 template <typename Real>
-hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* step_ptr,
-                        int64_t step_arg, bool capture)
+hipError_t enqueue_couple(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* step_ptr,
+                          int64_t step_arg, bool timed)
 {
     hipError_t err = hipSuccess;
     auto note = [&](hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; };
-    StepArgs<Real> ag[2] = {step_args<Real>(c, 0, src_buf), step_args<Real>(c, 1, src_buf)};
-    for (auto& a : ag) { a.step_ptr = step_ptr; a.step_arg = step_arg; }
-    // timed launches carry their own start/stop events (recorded by the dispatch)
-    const bool timed = c->timing && !capture;
-    if (use_overlap(c)) {
-        // launch A: the coupling and the tiles without spread force; launch B: the bodies
-        // (claiming the next step's tiles) and the marked tiles.  Both count as node launches
-        // for the timing.
-        const int g = c->tiles[1].empty() ? 0 : 1;
-        BodyArgs ba = body_args(c);
-        ba.marks = c->marks;
-        for (int part = 0; part < 2; ++part) {
-            EventPair e{};
-            if (timed) e = get_pair(c);
-            if (part == 0)
-                launch_overlap_free<Real>(ag[g], g == 1, couple_args(c), c->marks, s,
-                                          LaunchEvents{e.a, e.b});
-            else
-                launch_overlap_forced<Real>(ag[g], g == 1, ba, s, LaunchEvents{e.a, e.b});
-            note(hipGetLastError());
-            if (timed && e.a && e.b) c->ev_node.push_back(e);
-        }
-        if (c->n_links > 0) {
-            launch_wall_links<Real>(ag[0].dst, c->d_links, c->n_links, s);
-            note(hipGetLastError());
-        }
-        return err;
-    }
-    c->marks_valid = false;   // the serial step does not keep the tile marks
+    StepArgs<Real> a = step_args<Real>(c, any_masked(c) ? 1 : 0, src_buf);
+    a.step_ptr = step_ptr;
+    a.step_arg = step_arg;
+    CoupleArgs ca = couple_args(c);
+    const BodyArgs ba = body_args(c);
+    if (ca.n_beads <= 0) return err;
     const int m = md_steps(c);
-    for (int k = 0; k < m && c->n_beads > 0; ++k) {
-        // MD step k: coupling (its own noise block, the fluid gets 1/m of the force); every
-        // MD step but the last also finishes the bodies here
+    for (int k = 0; k < m; ++k) {
+        // MD step k: its own noise block, the fluid gets 1/m of the force
         EventPair e{};
         if (timed) e = get_pair(c);
-        CoupleArgs ca = couple_args(c);
         ca.md_step = (uint32_t)k;
-        const BodyArgs ba = body_args(c);
-        launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], ca, s, LaunchEvents{e.a, e.b}, &ba);
+        launch_couple<Real>(a, ca, s, LaunchEvents{e.a, e.b}, &ba);
         note(hipGetLastError());
         if (timed && e.a && e.b) c->ev_couple_t.push_back(e);
         if (k + 1 < m) {
@@ -425,22 +389,52 @@ hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* st
             note(hipGetLastError());
         }
     }
-    bool finished = c->n_bodies == 0;
+    return err;
+}
+
+// The node update of one fluid step on stream s, src_buf -> src_buf ^ 1, one launch per tile
+// group; the first launch also finishes the bodies.
+template <typename Real>
+hipError_t enqueue_node(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* step_ptr,
+                        int64_t step_arg, bool timed)
+{
+    hipError_t err = hipSuccess;
+    auto note = [&](hipError_t e) { if (err == hipSuccess && e != hipSuccess) err = e; };
+    StepArgs<Real> ag[2] = {step_args<Real>(c, 0, src_buf), step_args<Real>(c, 1, src_buf)};
+    const BodyArgs ba = body_args(c);
+    for (int g = 0; g < 2; ++g) {
+        ag[g].step_ptr = step_ptr;
+        ag[g].step_arg = step_arg;
+    }
+    bool finished = ba.n_bodies == 0;
     for (int g = 0; g < 2; ++g) {
         const bool last = g == 1 || ag[1].n_tiles == 0;
         if (ag[g].n_tiles == 0 && !(last && !finished)) continue;
         EventPair e{};
         if (timed) e = get_pair(c);
-        const BodyArgs ba = body_args(c);
         launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, finished ? nullptr : &ba, s,
                                LaunchEvents{e.a, e.b});
         note(hipGetLastError());
         if (timed && e.a && e.b) c->ev_node.push_back(e);
         finished = true;
     }
-    if (c->n_links > 0) {
-        launch_wall_links<Real>(ag[0].dst, c->d_links, c->n_links, s);
-        note(hipGetLastError());
+    return err;
+}
+
+// One serial fluid step on stream s: the couplings, then the node update of each tile group
+// (the first node launch also finishes the bodies), then the moving-wall links.  Returns the
+// first HIP error of the enqueued calls.
+template <typename Real>
+hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* step_ptr,
+                        int64_t step_arg, bool capture)
+{
+    const bool timed = c->timing && !capture;   // timed launches carry their own events
+    hipError_t err = enqueue_couple<Real>(c, s, src_buf, step_ptr, step_arg, timed);
+    const hipError_t e2 = enqueue_node<Real>(c, s, src_buf, step_ptr, step_arg, timed);
+    if (err == hipSuccess) err = e2;
+    if (c->n_links > 0 && err == hipSuccess) {
+        launch_wall_links<Real>((Real*)c->f[src_buf ^ 1], c->d_links, c->n_links, s);
+        err = hipGetLastError();
     }
     return err;
 }
@@ -455,6 +449,7 @@ int build_graph(lb_ctx* c, int parity)
 {
     if (!c->cap_stream)
         HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+
     hipGraph_t graph = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t cap_err = hipSuccess;
@@ -479,7 +474,7 @@ int build_graph(lb_ctx* c, int parity)
     return LB_OK;
 }
 
-// Build the fluid-row tables and tiles of every replica from the host masks.
+// Build the tiles of every replica from the fluid-row tables, replicas in index order.
 void rebuild_tiles(lb_ctx* c)
 {
     c->tiles[0].clear();
@@ -543,14 +538,7 @@ int upload_tables(lb_ctx* c)
             HIP_TRY(c, hipMemcpyAsync(c->d_tiles[g], c->tiles[g].data(),
                                       sizeof(NodeTile) * c->tiles[g].size(), hipMemcpyHostToDevice,
                                       c->stream));
-    // global tile -> index in its group's tile array (-1: a tile of padding nodes only)
-    std::vector<int32_t> tile_of((size_t)c->marks.n_gt, -1);
-    for (int g = 0; g < 2; ++g)
-        for (size_t k = 0; k < c->tiles[g].size(); ++k) tile_of[c->tiles[g][k].gt] = (int32_t)k;
-    HIP_TRY(c, hipMemcpyAsync((void*)c->marks.tile_of, tile_of.data(),
-                              sizeof(int32_t) * tile_of.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    c->marks_valid = false;
     return LB_OK;
 }
 
@@ -1017,6 +1005,117 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
     return LB_OK;
 }
 
+// ------------------------------------------------------------------ autotuner
+// The node update's launch settings -- node tiles per workgroup, a cap on the workgroups
+// resident per CU (by dynamic LDS), ordinary or non-temporal population stores -- are timed on
+// the context's own node kernel over its own tiles: every tile group, the kernel the steps
+// launch (with the force path when the context has beads) but without body finishing, pulling
+// from the current buffer and writing the other one, which the next step overwrites whole.
+// Between steps every spread force has been consumed (flags and words are zero), so the timed
+// launches take none and the simulation state is unchanged.  Results are kept per
+// (device architecture, precision, thermal, tile counts, fluid nodes) for the process.
+
+struct TuneCand { int32_t per, cap, streaming; };
+constexpr double kTuneMargin = 0.01;   // a setting must beat the untuned one by this fraction
+
+std::mutex& tune_mutex() { static std::mutex m; return m; }
+std::map<std::string, Tuning>& tune_cache() { static std::map<std::string, Tuning> m; return m; }
+
+std::string tune_key(const lb_ctx* c)
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    int64_t fluid = 0;
+    for (int r = 0; r < c->n_rep; ++r) fluid += c->reps[r].n_fluid;
+    return arch + "|" + std::to_string(c->p.precision) + "|" + std::to_string(c->p.kT > 0.0) + "|" +
+           std::to_string(c->tiles[0].size()) + "|" + std::to_string(c->tiles[1].size()) + "|" +
+           std::to_string(fluid) + "|" + std::to_string(c->store_policy);
+}
+
+// mean duration (us) of one node update of every tile group with the context's current settings
+template <typename Real>
+int time_node_update(lb_ctx* c, hipEvent_t e0, hipEvent_t e1, int reps, double& us)
+{
+    StepArgs<Real> ag[2] = {step_args<Real>(c, 0, c->cur), step_args<Real>(c, 1, c->cur)};
+    auto once = [&]() {
+        for (int g = 0; g < 2; ++g)
+            if (ag[g].n_tiles > 0)
+                launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, nullptr, c->stream);
+    };
+    once();   // warm-up
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    for (int k = 0; k < reps; ++k) once();
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    HIP_TRY(c, hipGetLastError());
+    float ms = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+    us = 1e3 * (double)ms / reps;
+    return LB_OK;
+}
+
+template <typename Real>
+int autotune_t(lb_ctx* c, int reps, Tuning& best)
+{
+    std::vector<TuneCand> cands;
+    const bool fixed_stores = c->store_policy != LB_STORES_AUTO;
+    Tuning saved = c->tune;
+    c->tune = Tuning{};
+    const int32_t default_streaming = streaming_stores(c) ? 1 : 0;   // the untuned rule
+    for (int st = 0; st < 2; ++st) {
+        if (fixed_stores && st != default_streaming) continue;
+        for (int per : {1, kWideTiles})
+            for (int cap : {0, 6, 5, 4}) cands.push_back(TuneCand{per, cap, st});
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, LB_ERR_HIP, "hipEventCreate");
+    }
+    int rc = LB_OK;
+    best = Tuning{};
+    bool have = false;
+    double t_default = -1.0;
+    for (const TuneCand& k : cands) {
+        c->tune = Tuning{};
+        c->tune.tuned = true;
+        c->tune.tiles_per_wg = k.per;
+        c->tune.wg_per_cu = k.cap;
+        c->tune.streaming = k.streaming;
+        double us = 0.0;
+        rc = time_node_update<Real>(c, e0, e1, reps, us);
+        if (rc != LB_OK) break;
+        if (k.per == 1 && k.cap == 0 && k.streaming == default_streaming) t_default = us;
+        if (!have || us < best.us_best) {
+            best = c->tune;
+            best.us_best = us;
+            have = true;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LB_OK) {
+        c->tune = saved;
+        return rc;
+    }
+    // the untuned settings stay unless another setting is at least 1 % faster
+    if (t_default > 0.0 && best.us_best > (1.0 - kTuneMargin) * t_default) {
+        best = Tuning{};
+        best.streaming = default_streaming;
+        best.us_best = t_default;
+    }
+    best.candidates = (int32_t)cands.size();
+    best.us_default = t_default;
+    best.tuned = true;
+    c->tune = best;
+    return LB_OK;
+}
+
 }  // namespace
 
 // ============================================================================ C-ABI
@@ -1071,11 +1170,6 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     c->d_nb_sites = (WallSite*)(c->ws + pl.off_nb_sites);
     c->d_near = (uint8_t*)(c->ws + pl.off_near);
     c->d_wca_ft = (double*)(c->ws + pl.off_wca_ft);
-    c->marks.mark = (uint32_t*)(c->ws + pl.off_tmark);
-    c->marks.list = (int32_t*)(c->ws + pl.off_tlist);
-    c->marks.count = (int32_t*)(c->ws + pl.off_tcount);
-    c->marks.tile_of = (const int32_t*)(c->ws + pl.off_tile_of);
-    c->marks.n_gt = (int32_t)pl.tiles_cap;
 
     c->reps.resize(n_replicas);
     c->rh.resize(n_replicas);
@@ -1340,23 +1434,14 @@ int lb_add_wall_sites(lb_ctx* c, int32_t replica, const double* pos, int32_t n, 
     return LB_OK;
 }
 
-// Before a run of steps: recompute stale body poses and bead records; for the overlapped
-// step, also rebuild the tile marks of the coming step (after a state change, or after serial
-// steps, which do not keep them).  Predicting a current pose again reproduces it bit for bit.
+// Before a run of steps: stale body poses and bead records (predicting a current pose again
+// reproduces it bit for bit).
 int prepare_bodies(lb_ctx* c, hipStream_t s)
 {
-    const bool ov = use_overlap(c);
-    if (!c->pose_stale && !(ov && !c->marks_valid)) return LB_OK;
-    BodyArgs ba = body_args(c);
-    if (ov) {
-        ba.marks = c->marks;
-        launch_clear_marks(c->marks, s);
-        HIP_TRY(c, hipGetLastError());
-    }
-    launch_body_predict(ba, (int)((c->step * md_steps(c)) & 1), (int)(c->step & 1), s);
+    if (!c->pose_stale) return LB_OK;
+    launch_body_predict(body_args(c), (int)((c->step * md_steps(c)) & 1), s);
     HIP_TRY(c, hipGetLastError());
     c->pose_stale = false;
-    c->marks_valid = ov;
     return LB_OK;
 }
 
@@ -1369,13 +1454,13 @@ int lb_rb_step(lb_ctx* c, int32_t n_steps)
         const int rc = build_wca(c);
         if (rc != LB_OK) return rc;
     }
-    const int rc = prepare_bodies(c, c->stream);
+    int rc = prepare_bodies(c, c->stream);
     if (rc != LB_OK) return rc;
     int32_t left = n_steps;
     const bool use_graph = c->graph_steps > 0 && !c->timing;
     while (use_graph && left >= c->graph_steps) {
         if (!c->gexec[c->cur]) {
-            int rc = build_graph(c, c->cur);
+            rc = build_graph(c, c->cur);
             if (rc != LB_OK) return rc;
         }
         launch_set_step(&c->hdr->step, c->step, c->stream);
@@ -1572,21 +1657,63 @@ int lb_set_store_policy(lb_ctx* c, int32_t policy)
     return LB_OK;
 }
 
-int lb_set_step_policy(lb_ctx* c, int32_t policy)
+int lb_autotune(lb_ctx* c, int32_t repeats)
 {
     if (!c) return LB_ERR_ARG;
-    if (policy != LB_STEP_AUTO && policy != LB_STEP_SERIAL && policy != LB_STEP_OVERLAP)
-        return fail(c, LB_ERR_ARG, "unknown step policy");
+    if (repeats < 0 || repeats > 1000) return fail(c, LB_ERR_ARG, "repeats must be 0..1000");
+    if (c->wca_dirty) {
+        const int rc = build_wca(c);
+        if (rc != LB_OK) return rc;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const std::string key = tune_key(c);
+    if (repeats == 0) {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        auto it = tune_cache().find(key);
+        if (it != tune_cache().end()) {
+            destroy_graphs(c);
+            c->tune = it->second;
+            return LB_OK;
+        }
+    }
+    Tuning t;
+    const int rc = is_f32(c) ? autotune_t<float>(c, repeats > 0 ? repeats : 3, t)
+                             : autotune_t<double>(c, repeats > 0 ? repeats : 3, t);
     destroy_graphs(c);
-    c->step_policy = policy;
-    c->marks_valid = false;
+    if (rc != LB_OK) return rc;
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    tune_cache()[key] = t;
     return LB_OK;
 }
 
-int lb_step_overlapped(lb_ctx* c, int32_t* out)
+int lb_get_tuning(const lb_ctx* c, lb_tuning* out)
 {
     if (!c || !out) return LB_ERR_ARG;
-    *out = use_overlap(c) ? 1 : 0;
+    lb_tuning t{};
+    t.tuned = c->tune.tuned ? 1 : 0;
+    t.tiles_per_wg = std::max(1, (int)c->tune.tiles_per_wg);
+    t.wg_per_cu = c->tune.wg_per_cu;
+    t.streaming = streaming_stores(c) ? 1 : 0;
+    t.candidates = c->tune.candidates;
+    t.node_us_default = c->tune.us_default;
+    t.node_us_tuned = c->tune.us_best;
+    *out = t;
+    return LB_OK;
+}
+
+int lb_set_tuning(lb_ctx* c, const lb_tuning* t)
+{
+    if (!c || !t) return LB_ERR_ARG;
+    if ((t->tiles_per_wg != 1 && t->tiles_per_wg != kWideTiles) || t->wg_per_cu < 0 ||
+        t->wg_per_cu > 32 || (t->streaming != 0 && t->streaming != 1))
+        return fail(c, LB_ERR_ARG, "tiles_per_wg 1 or 4, wg_per_cu 0..32, streaming 0 or 1");
+    destroy_graphs(c);
+    Tuning x{};
+    x.tuned = true;
+    x.tiles_per_wg = t->tiles_per_wg;
+    x.wg_per_cu = t->wg_per_cu;
+    x.streaming = t->streaming;
+    c->tune = x;
     return LB_OK;
 }
 
@@ -1695,7 +1822,6 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     const int rc = is_f32(c) ? run_adjoint<float>(c, n_steps, checkpoint_every, ws, ap)
                              : run_adjoint<double>(c, n_steps, checkpoint_every, ws, ap);
     if (rc != LB_OK) return rc;
-    c->marks_valid = false;
     std::vector<double> dr(3 * nb), dg(nb), jp(nb);
     std::vector<Body> bs(c->n_bodies);
     HIP_TRY(c, hipMemcpyAsync(dr.data(), ws + ap.off_dr, sizeof(double) * dr.size(), hipMemcpyDeviceToHost, s));

@@ -206,8 +206,10 @@ __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
 // each contribution in units of 2^-104, which makes the spread exact to far below FP64
 // rounding.  A remainder lies in [0, 2^48) and the second word is read back as unsigned, so
 // it holds the sum of up to 65535 contributions (beads whose stencil holds the node, times
-// MD steps per fluid step) without wrapping.  Layout: word w of axis ax of node g at
-// gforce[(w*3 + ax) * N + g].
+// MD steps per fluid step) without wrapping.  Layout: the words of a node are contiguous,
+// word w of axis ax of node g at gforce[g * spread_stride + 3 w + ax], padded to 32 bytes
+// (FP32: 3 words) or 64 bytes (FP64: 6 words), so the atomics on a node and the node
+// update's read-and-clear touch one cache line.
 // the fixed-point words of one contribution: hi in units of 2^-56, lo (FP64 only) the
 // remainder in units of 2^-104
 template <typename Real>
@@ -219,18 +221,27 @@ __device__ __forceinline__ void spread_words(double val, long long& hi, long lon
     lo = sizeof(Real) == 8 ? (long long)((x - h) * 0x1p48) : 0;
 }
 
+// add the spread force of node g to F and clear its words (16-byte loads and stores)
 template <typename Real>
-__device__ __forceinline__ Real take_spread_force(long long* gforce, int64_t N, int ax, int64_t g)
+__device__ __forceinline__ void take_spread_force(long long* gforce, int64_t g, Real F[3])
 {
-    long long* p = gforce + (int64_t)ax * N + g;
-    double v = (double)(*p) * 0x1p-56;
-    *p = 0;
-    if constexpr (sizeof(Real) == 8) {
-        long long* q = gforce + (int64_t)(3 + ax) * N + g;
-        v += (double)(unsigned long long)(*q) * 0x1p-104;
-        *q = 0;
+    constexpr int S = spread_stride<Real>();
+    long long* p = gforce + g * S;
+    long long w[S];
+#pragma unroll
+    for (int k = 0; k < S; k += 2) {
+        const longlong2 v = *reinterpret_cast<const longlong2*>(p + k);
+        w[k] = v.x;
+        w[k + 1] = v.y;
     }
-    return (Real)v;
+#pragma unroll
+    for (int k = 0; k < S; k += 2) *reinterpret_cast<longlong2*>(p + k) = make_longlong2(0, 0);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        double v = (double)w[ax] * 0x1p-56;
+        if constexpr (sizeof(Real) == 8) v += (double)(unsigned long long)w[3 + ax] * 0x1p-104;
+        F[ax] += (Real)v;
+    }
 }
 
 // Workgroups are dealt round-robin to the 8 XCDs (separate L2 caches).  Give each XCD a

@@ -69,8 +69,7 @@ __device__ __forceinline__ void update_node(const StepArgs<Real>& a, const Repli
     Real F[3] = {a.gext[0], a.gext[1], a.gext[2]};
     if constexpr (FORCES) {
         if (flag) {
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) F[ax] += take_spread_force<Real>(a.gforce, a.N, ax, g);
+            take_spread_force<Real>(a.gforce, g, F);
             a.flags[g] = 0;
         }
     }
@@ -133,22 +132,6 @@ __device__ __forceinline__ int32_t uniform_int(int32_t x)
     return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
 }
 
-__device__ __forceinline__ BodyBox uniform_box(const BodyBox& c)
-{
-    BodyBox r;
-    r.nx = uniform_int(c.nx);
-    r.ny = uniform_int(c.ny);
-    r.nz = uniform_int(c.nz);
-    r.masked = uniform_int(c.masked);
-    r.base = (int64_t)(((uint64_t)(uint32_t)uniform_int((int32_t)(c.base >> 32)) << 32) |
-                       (uint32_t)uniform_int((int32_t)c.base));
-    r.row_base = uniform_int(c.row_base);
-    r.key0 = (uint32_t)uniform_int((int32_t)c.key0);
-    r.key1 = (uint32_t)uniform_int((int32_t)c.key1);
-    r.pad = 0;
-    return r;
-}
-
 __device__ __forceinline__ RecPose uniform_rec_pose(const Pose& P)
 {
     RecPose r;
@@ -203,89 +186,6 @@ __device__ __forceinline__ void write_bead_const(const RecConst& C, int32_t user
     o.nx = X.nx; o.ny = X.ny; o.nz = X.nz; o.masked = X.masked;
     o.base = X.base;
     o.key0 = X.key0; o.key1 = X.key1;
-}
-
-// ------------------------------------------------------------------ tiles under the stencils
-
-// The first claim of global tile gt for the fluid step of parity p appends it to that
-// parity's list (used when a workgroup's tile set overflows).
-__device__ __forceinline__ void claim_tile(const TileMarks& tm, int p, int32_t gt)
-{
-    const int64_t o = (int64_t)p * tm.n_gt;
-    if (atomicExch(&tm.mark[o + gt], 1u) == 0u) {
-        const int32_t i = atomicAdd(&tm.count[p], 1);
-        tm.list[o + i] = gt;
-    }
-}
-
-// LDS set of the tiles one workgroup claims (open addressing, key gt + 1, 0 = empty).  The
-// stencils are first collected here; claim_set then marks the distinct tiles with device
-// atomics issued in parallel and reserves the workgroup's list entries with one atomic.  A
-// full table passes the claim on to claim_tile directly.
-constexpr int kTileSet = 1024;
-
-__device__ __forceinline__ void set_claim(uint32_t* set, const TileMarks& tm, int p, int32_t gt)
-{
-    const uint32_t key = (uint32_t)gt + 1u;
-    int slot = (int)((key * 2654435761u) >> 22) & (kTileSet - 1);
-    for (int probe = 0; probe < kTileSet; ++probe) {
-        const uint32_t prev = atomicCAS(&set[slot], 0u, key);
-        if (prev == 0u || prev == key) return;
-        slot = (slot + 1) & (kTileSet - 1);
-    }
-    claim_tile(tm, p, gt);
-}
-
-// all threads of the workgroup, after a barrier that follows the last set_claim: mark the
-// set's tiles, append the newly marked ones to the list (fresh: LDS scratch of kTileSet ints,
-// n_fresh: an LDS counter that starts at 0) and clear the set
-__device__ __forceinline__ void claim_set(uint32_t* set, int32_t* fresh, int32_t* n_fresh,
-                                          int32_t* base, const TileMarks& tm, int p)
-{
-    const int64_t o = (int64_t)p * tm.n_gt;
-    for (int k = threadIdx.x; k < kTileSet; k += blockDim.x) {
-        const uint32_t key = set[k];
-        if (key == 0u) continue;
-        set[k] = 0u;
-        const int32_t gt = (int32_t)(key - 1u);
-        if (atomicExch(&tm.mark[o + gt], 1u) == 0u) fresh[atomicAdd(n_fresh, 1)] = gt;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && *n_fresh > 0) *base = atomicAdd(&tm.count[p], *n_fresh);
-    __syncthreads();
-    for (int k = threadIdx.x; k < *n_fresh; k += blockDim.x) tm.list[o + *base + k] = fresh[k];
-}
-
-// claim the tiles of the fluid nodes of the trilinear stencil around bead position r: the
-// corners the coupling computes from the same r (fluid nodes only)
-__device__ __forceinline__ void claim_stencil(const BodyBox& X, const RowDesc* __restrict__ rowinfo,
-                                              const double r[3], uint32_t* set,
-                                              const TileMarks& tm, int p)
-{
-    double fr[3];
-    int i0[3];
-    i0[0] = wrap_floor(r[0] - 0.5, X.nx, fr[0]);
-    i0[1] = wrap_floor(r[1] - 0.5, X.ny, fr[1]);
-    i0[2] = wrap_floor(r[2] - 0.5, X.nz, fr[2]);
-    for (int oz = 0; oz < 2; ++oz) {
-        const int pz = i0[2] + oz == X.nz ? 0 : i0[2] + oz;
-        for (int oy = 0; oy < 2; ++oy) {
-            const int py = i0[1] + oy == X.ny ? 0 : i0[1] + oy;
-            RowDesc rd{0, 0, 0, 0};
-            if (X.masked) rd = rowinfo[X.row_base + py + X.ny * pz];
-            for (int ox = 0; ox < 2; ++ox) {
-                const int px = i0[0] + ox == X.nx ? 0 : i0[0] + ox;
-                int64_t local;
-                if (X.masked) {
-                    const int off = px - rd.xlo;
-                    local = (unsigned)off < (unsigned)rd.len ? rd.start + off : -1;
-                } else {
-                    local = px + (int64_t)X.nx * (py + (int64_t)X.ny * pz);
-                }
-                if (local >= 0) set_claim(set, tm, p, (int32_t)((X.base + local) >> kPopBlockLog));
-            }
-        }
-    }
 }
 
 // ------------------------------------------------------------------ excluded volume (WCA)
@@ -503,11 +403,7 @@ __device__ __forceinline__ void wca_block(const BodyArgs& ba, int b, int parity,
 // (one word per lane into LDS).  The next pose is built in LDS, stored by 25 lanes, and read
 // back into scalar registers for the records, so that this code needs fewer registers than
 // the node update it shares a kernel with.
-// With MARK, the tiles under the new bead stencils are claimed for the fluid step of parity
-// mark_parity (the overlapped step).
-template <bool MARK>
-__device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parity,
-                                            int mark_parity = 0)
+__device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parity)
 {
     constexpr int kPre = 2;                       // bead offsets fetched with the forces
     constexpr int kPoseWords = sizeof(Pose) / sizeof(double);
@@ -521,12 +417,7 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
     const Body& B = ba.bodies[b];
     const int first = B.first_bead, n = B.n_beads;
     const int tid = threadIdx.x;
-    __shared__ BodyBox box;                       // the replica's geometry, for the claims
     const int fixed = B.fixed;
-    if (MARK && tid == 64) box = B.box;
-    __shared__ uint32_t tile_set[MARK ? kTileSet : 1];
-    if constexpr (MARK)
-        for (int k = tid; k < kTileSet; k += 256) tile_set[k] = 0u;
     const bool has_wca = ba.wca_ft != nullptr;
     if (tid < kPoseWords) {
         reinterpret_cast<double*>(&cur)[tid] = reinterpret_cast<const double*>(&B.pose[parity])[tid];
@@ -611,8 +502,6 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
     if (tid < kPoseWords)
         reinterpret_cast<double*>(&o.pose[parity ^ 1])[tid] = reinterpret_cast<const double*>(&next)[tid];
     const RecPose RP = uniform_rec_pose(next);
-    BodyBox X{};
-    if constexpr (MARK) X = uniform_box(box);
     for (int q = 0, k = tid; k < n; ++q, k += 256) {
         double off[3];
         if (q < kPre) {
@@ -623,47 +512,116 @@ __device__ __forceinline__ void body_finish(const BodyArgs& ba, int b, int parit
         }
         double r[3];
         write_bead_pose(RP, fixed != 0, off, ba.recs[first + k], r);
-        if constexpr (MARK) claim_stencil(X, ba.rowinfo, r, tile_set, ba.marks, mark_parity);
-    }
-    if constexpr (MARK) {
-        __shared__ int32_t n_fresh, fresh_base;
-        static_assert(sizeof(pre_off) >= kTileSet * sizeof(int32_t), "scratch for new tiles");
-        if (tid == 0) n_fresh = 0;
-        __syncthreads();   // every claim is in the set, the offsets are no longer needed
-        claim_set(tile_set, reinterpret_cast<int32_t*>(&pre_off[0][0][0]), &n_fresh, &fresh_base,
-                  ba.marks, mark_parity);
     }
 }
 
 // The node update of one tile group.  With FORCES the nodes consume the spread force of the
 // coupling.  The first n_lead workgroups (0, or a multiple of 8 so that blockIdx % 8 still
 // picks the XCD of the node tiles) finish the bodies: they read only the per-bead forces of
-// the coupling and write only body records, which no node thread touches.
+// the coupling and write only body records, which no node thread touches.  Every other workgroup updates PER consecutive tiles (a
+// tuning choice; the XCD-aware order deals runs of them to each XCD).
 // FP32: 72 registers give 7 wavefronts per SIMD (the FP32 paths fit without spills; FP64 is
 // left to the compiler)
-template <typename Real, bool MASKED, bool THERMAL, bool FORCES, bool NARROW, bool NT>
+template <typename Real, bool MASKED, bool THERMAL, bool FORCES, bool NARROW, bool NT, int PER>
 __global__ __launch_bounds__(kNodeBlock) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 7 : 1)))
-void node_step_kernel(const StepArgs<Real> a,
-                                                               const BodyArgs ba, int n_lead)
+void node_step_kernel(const StepArgs<Real> a, const BodyArgs ba, int n_lead)
 {
     const int64_t step = current_step(a.step_ptr, a.step_arg);
     int b = blockIdx.x;
     if (b < n_lead) {
         // the last MD step of this fluid step
         if (b < ba.n_bodies)
-            body_finish<false>(ba, b, (int)((step * ba.substeps + ba.substeps - 1) & 1));
+            body_finish(ba, b, (int)((step * ba.substeps + ba.substeps - 1) & 1));
         return;
     }
     b -= n_lead;
     __shared__ RowDesc tile_rows[MASKED ? kNodeBlock : 1];
-    const NodeTile t = a.tiles[xcd_tile(b, gridDim.x - n_lead)];
-    const ReplicaDesc R = a.reps[t.replica];
-    const int64_t local = t.begin + threadIdx.x;
-    int x, y, z;
-    RowDesc self;
-    locate_tile<MASKED>(R, a.rows, t, local, tile_rows, x, y, z, self);
-    if ((int)threadIdx.x >= t.count) return;
-    update_node<Real, MASKED, THERMAL, FORCES, NARROW, NT>(a, R, local, x, y, z, self, step);
+    if constexpr (PER == 1) {
+        const NodeTile t = a.tiles[xcd_tile(b, gridDim.x - n_lead)];
+        const ReplicaDesc R = a.reps[t.replica];
+        const int64_t local = t.begin + threadIdx.x;
+        int x, y, z;
+        RowDesc self;
+        locate_tile<MASKED>(R, a.rows, t, local, tile_rows, x, y, z, self);
+        if ((int)threadIdx.x >= t.count) return;
+        update_node<Real, MASKED, THERMAL, FORCES, NARROW, NT>(a, R, local, x, y, z, self, step);
+    } else {
+        const int first = xcd_tile(b, gridDim.x - n_lead) * PER;
+        for (int q = 0; q < PER; ++q) {
+            const int ti = first + q;
+            if (ti >= a.n_tiles) break;               // uniform over the workgroup
+            if (MASKED && q > 0) __syncthreads();     // the previous tile's rows are no longer read
+            const NodeTile t = a.tiles[ti];
+            const ReplicaDesc R = a.reps[t.replica];
+            const int64_t local = t.begin + threadIdx.x;
+            int x, y, z;
+            RowDesc self;
+            locate_tile<MASKED>(R, a.rows, t, local, tile_rows, x, y, z, self);
+            if ((int)threadIdx.x < t.count)
+                update_node<Real, MASKED, THERMAL, FORCES, NARROW, NT>(a, R, local, x, y, z, self,
+                                                                     step);
+        }
+    }
+}
+
+template <typename K>
+int node_wg_lds(K kernel)
+{
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel)) != hipSuccess) return 0;
+    return (int)fa.sharedSizeBytes;
+}
+
+// LDS bytes one workgroup may allocate on the current device
+inline int max_wg_lds()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 64 * 1024;
+    return v;
+}
+
+// launch with dynamic LDS that caps the workgroups resident per CU at wg_per_cu (0: no cap;
+// the request is clamped to what one workgroup may allocate)
+template <typename K, typename... Args>
+void launch_node_capped(K kernel, dim3 grid, hipStream_t s, const LaunchEvents& ev, int wg_per_cu,
+                        Args... args)
+{
+    size_t dyn = 0;
+    if (wg_per_cu > 0) {
+        static const int limit = max_wg_lds();
+        const int stat = node_wg_lds(kernel);
+        const int want = std::min(kLdsPerCu / wg_per_cu, limit) - stat;
+        dyn = want > 0 ? (size_t)want : 0;
+    }
+    if (ev.start)
+        hipExtLaunchKernelGGL(kernel, grid, dim3(kNodeBlock), dyn, s, ev.start, ev.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, dim3(kNodeBlock), dyn, s, args...);
+}
+
+template <typename Real, bool MASKED, bool THERMAL, bool NARROW, int PER>
+void launch_node_p(const StepArgs<Real>& a, bool forces, const BodyArgs& ba, int n_lead,
+                   hipStream_t s, const LaunchEvents& ev)
+{
+    const dim3 grid((a.n_tiles + PER - 1) / PER + n_lead);
+    const int cap = a.wg_per_cu;
+    if (a.stream_stores) {
+        if (forces)
+            launch_node_capped(node_step_kernel<Real, MASKED, THERMAL, true, NARROW, true, PER>,
+                               grid, s, ev, cap, a, ba, n_lead);
+        else
+            launch_node_capped(node_step_kernel<Real, MASKED, THERMAL, false, NARROW, true, PER>,
+                               grid, s, ev, cap, a, ba, n_lead);
+    } else {
+        if (forces)
+            launch_node_capped(node_step_kernel<Real, MASKED, THERMAL, true, NARROW, false, PER>,
+                               grid, s, ev, cap, a, ba, n_lead);
+        else
+            launch_node_capped(node_step_kernel<Real, MASKED, THERMAL, false, NARROW, false, PER>,
+                               grid, s, ev, cap, a, ba, n_lead);
+    }
 }
 
 template <typename Real, bool MASKED, bool THERMAL, bool NARROW>
@@ -673,22 +631,10 @@ void launch_node_t(const StepArgs<Real>& a, bool forces, const BodyArgs* bodies,
     BodyArgs ba{};
     if (bodies) ba = *bodies;
     const int n_lead = ba.n_bodies > 0 ? (ba.n_bodies + 7) & ~7 : 0;
-    const dim3 grid(a.n_tiles + n_lead), block(kNodeBlock);
-    if (a.stream_stores) {
-        if (forces)
-            launch_timed(node_step_kernel<Real, MASKED, THERMAL, true, NARROW, true>, grid, block,
-                         s, ev, a, ba, n_lead);
-        else
-            launch_timed(node_step_kernel<Real, MASKED, THERMAL, false, NARROW, true>, grid, block,
-                         s, ev, a, ba, n_lead);
-    } else {
-        if (forces)
-            launch_timed(node_step_kernel<Real, MASKED, THERMAL, true, NARROW, false>, grid, block,
-                         s, ev, a, ba, n_lead);
-        else
-            launch_timed(node_step_kernel<Real, MASKED, THERMAL, false, NARROW, false>, grid, block,
-                         s, ev, a, ba, n_lead);
-    }
+    if (a.tiles_per_wg == kWideTiles)
+        launch_node_p<Real, MASKED, THERMAL, NARROW, kWideTiles>(a, forces, ba, n_lead, s, ev);
+    else
+        launch_node_p<Real, MASKED, THERMAL, NARROW, 1>(a, forces, ba, n_lead, s, ev);
 }
 
 // 32-bit offsets pay in FP32 (+2 % on a pore, +1 % on a batch); FP64 keeps 64-bit indices
@@ -871,9 +817,10 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
     __syncthreads();
     // one device atomic per node and word
     if (owner) {
+        unsigned long long* gw = (unsigned long long*)(a.gforce + g * spread_stride<Real>());
         for (int wd = 0; wd < NW; ++wd) {
             const unsigned long long v = acc[wd][slot];
-            if (v != 0) atomicAdd((unsigned long long*)(a.gforce + (int64_t)wd * a.N + g), v);
+            if (v != 0) atomicAdd(gw + wd, v);
         }
         a.flags[g] = 1;
     }
@@ -954,167 +901,12 @@ void launch_couple_adj_bead(const StepArgs<Real>& a, const CoupleArgs& c, const 
                        s, a, c, A, n_cb);
 }
 
-// ------------------------------------------------------------------ overlapped step
-
-// Launch A of the overlapped step: the first n_cb workgroups couple the beads (n_cb a
-// multiple of 8, so that the tile workgroups keep their XCD pattern); every other workgroup
-// owns one node tile, clears the tile's mark of the other parity, and updates its nodes
-// without force unless the tile is marked for this step.
-template <typename Real, bool MASKED, bool THERMAL, bool NARROW, bool NT>
-__global__ __launch_bounds__(kNodeBlock) void overlap_free_kernel(const StepArgs<Real> a,
-                                                                  const CoupleArgs c,
-                                                                  const TileMarks tm, int n_cb)
-{
-    static_assert(kNodeBlock == kCoupleBlock, "one workgroup size for both roles");
-    int b = blockIdx.x;
-    if (b < n_cb) {
-        __shared__ CoupleLds<Real> L;
-        couple_beads<Real>(a, c, b, n_cb, L);
-        return;
-    }
-    b -= n_cb;
-    const int64_t step = current_step(a.step_ptr, a.step_arg);
-    const int p = (int)(step & 1);
-    const NodeTile t = a.tiles[xcd_tile(b, gridDim.x - n_cb)];
-    if (threadIdx.x == 0) {
-        tm.mark[(int64_t)(p ^ 1) * tm.n_gt + t.gt] = 0u;
-        if (b == 0) tm.count[p ^ 1] = 0;
-    }
-    if (tm.mark[(int64_t)p * tm.n_gt + t.gt] != 0u) return;
-    if ((int)threadIdx.x >= t.count) return;
-    const ReplicaDesc R = a.reps[t.replica];
-    const int64_t local = t.begin + threadIdx.x;
-    int x, y, z;
-    RowDesc self;
-    locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
-    update_node<Real, MASKED, THERMAL, false, NARROW, NT>(a, R, local, x, y, z, self, step);
-}
-
-// Launch B: the first n_lead workgroups finish the bodies and claim the tiles of the next
-// step; the others walk the tiles marked for this step (workgroup w takes list entries w,
-// w + G, ...) and update their nodes with the spread force.
-template <typename Real, bool MASKED, bool THERMAL, bool NARROW, bool NT>
-__global__ __launch_bounds__(kNodeBlock) void overlap_forced_kernel(const StepArgs<Real> a,
-                                                                    const BodyArgs ba,
-                                                                    int n_lead)
-{
-    const int64_t step = current_step(a.step_ptr, a.step_arg);
-    int b = blockIdx.x;
-    if (b < n_lead) {
-        if (b < ba.n_bodies) body_finish<true>(ba, b, (int)(step & 1), (int)((step + 1) & 1));
-        return;
-    }
-    b -= n_lead;
-    const int G = gridDim.x - n_lead;
-    const TileMarks& tm = ba.marks;
-    const int p = (int)(step & 1);
-    const int n = min(tm.count[p], tm.n_gt);
-    for (int i = b; i < n; i += G) {
-        const int32_t gt = tm.list[(int64_t)p * tm.n_gt + i];
-        const int32_t ti = (unsigned)gt < (unsigned)tm.n_gt ? tm.tile_of[gt] : -1;
-        if (ti < 0 || ti >= a.n_tiles) continue;   // (never: a claimed tile holds fluid nodes)
-        const NodeTile t = a.tiles[ti];
-        if ((int)threadIdx.x >= t.count) continue;
-        const ReplicaDesc R = a.reps[t.replica];
-        const int64_t local = t.begin + threadIdx.x;
-        int x, y, z;
-        RowDesc self;
-        locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
-        update_node<Real, MASKED, THERMAL, true, NARROW, NT>(a, R, local, x, y, z, self, step);
-    }
-}
-
-template <typename Real, bool MASKED, bool THERMAL, bool NARROW, bool NT>
-void launch_overlap_t(const StepArgs<Real>& a, const CoupleArgs* c, const TileMarks& tm,
-                      const BodyArgs* ba, hipStream_t s, const LaunchEvents& ev)
-{
-    const dim3 block(kNodeBlock);
-    if (c) {
-        const int n_cb = c->n_beads > 0 ? ((c->n_beads * kBeadLanes + kCoupleBlock - 1) /
-                                           kCoupleBlock + 7) & ~7 : 0;
-        launch_timed(overlap_free_kernel<Real, MASKED, THERMAL, NARROW, NT>,
-                     dim3(n_cb + a.n_tiles), block, s, ev, a, *c, tm, n_cb);
-    } else {
-        const int n_lead = ba->n_bodies > 0 ? (ba->n_bodies + 7) & ~7 : 0;
-        const int G = std::max(1, std::min(a.n_tiles, kForcedTileWorkgroups));
-        launch_timed(overlap_forced_kernel<Real, MASKED, THERMAL, NARROW, NT>,
-                     dim3(n_lead + G), block, s, ev, a, *ba, n_lead);
-    }
-}
-
-template <typename Real, bool MASKED, bool THERMAL>
-void launch_overlap_w(const StepArgs<Real>& a, const CoupleArgs* c, const TileMarks& tm,
-                      const BodyArgs* ba, hipStream_t s, const LaunchEvents& ev)
-{
-    const bool narrow = sizeof(Real) == 4 && a.narrow;
-    if (narrow) {
-        if (a.stream_stores) launch_overlap_t<Real, MASKED, THERMAL, true, true>(a, c, tm, ba, s, ev);
-        else launch_overlap_t<Real, MASKED, THERMAL, true, false>(a, c, tm, ba, s, ev);
-    } else {
-        if (a.stream_stores) launch_overlap_t<Real, MASKED, THERMAL, false, true>(a, c, tm, ba, s, ev);
-        else launch_overlap_t<Real, MASKED, THERMAL, false, false>(a, c, tm, ba, s, ev);
-    }
-}
-
-template <typename Real>
-void launch_overlap(const StepArgs<Real>& a, bool masked, const CoupleArgs* c,
-                    const TileMarks& tm, const BodyArgs* ba, hipStream_t s, const LaunchEvents& ev)
-{
-    if (masked) {
-        if (a.thermal) launch_overlap_w<Real, true, true>(a, c, tm, ba, s, ev);
-        else launch_overlap_w<Real, true, false>(a, c, tm, ba, s, ev);
-    } else {
-        if (a.thermal) launch_overlap_w<Real, false, true>(a, c, tm, ba, s, ev);
-        else launch_overlap_w<Real, false, false>(a, c, tm, ba, s, ev);
-    }
-}
-
-template <typename Real>
-void launch_overlap_free(const StepArgs<Real>& a, bool masked, const CoupleArgs& c,
-                         const TileMarks& tm, hipStream_t s, const LaunchEvents& ev)
-{
-    launch_overlap<Real>(a, masked, &c, tm, nullptr, s, ev);
-}
-
-template <typename Real>
-void launch_overlap_forced(const StepArgs<Real>& a, bool masked, const BodyArgs& ba,
-                           hipStream_t s, const LaunchEvents& ev)
-{
-    launch_overlap<Real>(a, masked, nullptr, ba.marks, &ba, s, ev);
-}
-
-__global__ void clear_marks_kernel(TileMarks tm)
-{
-    const int64_t n = 2 * (int64_t)tm.n_gt;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        tm.mark[i] = 0u;
-        tm.list[i] = 0;
-    }
-    if (blockIdx.x == 0 && threadIdx.x < 2) tm.count[threadIdx.x] = 0;
-}
-
-void launch_clear_marks(const TileMarks& tm, hipStream_t s)
-{
-    if (!tm.mark || tm.n_gt <= 0) return;
-    const int blocks = (int)std::min<int64_t>(1024, (2 * (int64_t)tm.n_gt + 255) / 256);
-    hipLaunchKernelGGL(clear_marks_kernel, dim3(blocks), dim3(256), 0, s, tm);
-}
-
-// pose of the coming step and its bead records, one workgroup per body; with marks, the tiles
-// under the bead stencils are claimed for the fluid step of parity mark_parity
-__global__ __launch_bounds__(256) void body_predict_kernel(const BodyArgs ba, int parity,
-                                                           int mark_parity)
+// pose of the coming step and its bead records, one workgroup per body
+__global__ __launch_bounds__(256) void body_predict_kernel(const BodyArgs ba, int parity)
 {
     __shared__ Pose next;
-    __shared__ uint32_t tile_set[kTileSet];
-    __shared__ int32_t fresh[kTileSet];
-    __shared__ int32_t n_fresh, fresh_base;
     Body& B = ba.bodies[blockIdx.x];
-    const bool mark = ba.marks.mark != nullptr;
-    for (int k = threadIdx.x; k < kTileSet; k += blockDim.x) tile_set[k] = 0u;
     if (threadIdx.x == 0) {
-        n_fresh = 0;
         predict_pose(B, B.pose[parity]);
         next = B.pose[parity];
     }
@@ -1126,19 +918,13 @@ __global__ __launch_bounds__(256) void body_predict_kernel(const BodyArgs ba, in
         double r[3];
         write_bead_const(C, bd.user, ba.recs[first + k]);
         write_bead_pose(next, C.fixed != 0, bd.off, ba.recs[first + k], r);
-        if (mark) claim_stencil(C.box, ba.rowinfo, r, tile_set, ba.marks, mark_parity);
-    }
-    if (mark) {
-        __syncthreads();
-        claim_set(tile_set, fresh, &n_fresh, &fresh_base, ba.marks, mark_parity);
     }
 }
 
-void launch_body_predict(const BodyArgs& b, int parity, int mark_parity, hipStream_t s)
+void launch_body_predict(const BodyArgs& b, int parity, hipStream_t s)
 {
     if (b.n_bodies <= 0) return;
-    hipLaunchKernelGGL(body_predict_kernel, dim3(b.n_bodies), dim3(256), 0, s, b, parity,
-                       mark_parity);
+    hipLaunchKernelGGL(body_predict_kernel, dim3(b.n_bodies), dim3(256), 0, s, b, parity);
 }
 
 // finish every body after MD step k of the fluid step (one workgroup per body)
@@ -1147,7 +933,7 @@ __global__ __launch_bounds__(256) void body_substep_kernel(const BodyArgs ba,
                                                            int64_t step_arg, int k)
 {
     const int64_t step = current_step(step_ptr, step_arg);
-    body_finish<false>(ba, blockIdx.x, (int)((step * ba.substeps + k) & 1));
+    body_finish(ba, blockIdx.x, (int)((step * ba.substeps + k) & 1));
 }
 
 void launch_body_substep(const BodyArgs& b, const int64_t* step_ptr, int64_t step_arg, int k,
@@ -1258,14 +1044,6 @@ void launch_observe(const StepArgs<Real>& a, bool masked, int32_t tile0, int32_t
 }
 
 // explicit instantiations
-template void launch_overlap_free<float>(const StepArgs<float>&, bool, const CoupleArgs&,
-                                         const TileMarks&, hipStream_t, const LaunchEvents&);
-template void launch_overlap_free<double>(const StepArgs<double>&, bool, const CoupleArgs&,
-                                          const TileMarks&, hipStream_t, const LaunchEvents&);
-template void launch_overlap_forced<float>(const StepArgs<float>&, bool, const BodyArgs&,
-                                           hipStream_t, const LaunchEvents&);
-template void launch_overlap_forced<double>(const StepArgs<double>&, bool, const BodyArgs&,
-                                            hipStream_t, const LaunchEvents&);
 template void launch_couple_adj_bead<float>(const StepArgs<float>&, const CoupleArgs&,
                                            const AdjArgs<float>&, hipStream_t);
 template void launch_couple_adj_bead<double>(const StepArgs<double>&, const CoupleArgs&,

@@ -30,7 +30,13 @@ constexpr int kNodeBlock = 256;   // threads (= nodes) per node-update workgroup
 constexpr int kBeadLanes = 8;     // threads per bead in the coupling kernel (one per corner)
 constexpr int kCoupleBlock = 256;
 constexpr int kPopBlockLog = 8;   // populations are blocked per 256 nodes
-constexpr int kForcedTileWorkgroups = 2048;   // tile workgroups of the overlapped step's launch B
+constexpr int kLdsPerCu = 160 * 1024;   // LDS bytes of one gfx950 compute unit
+constexpr int kWideTiles = 4;     // node tiles per workgroup of the wide node-update launch
+
+// 64-bit fixed-point words of the spread force per node: 3 (FP32) or 6 (FP64) used, padded to
+// 32 or 64 bytes so that a node's words share one cache line
+template <typename Real>
+constexpr int spread_stride() { return sizeof(Real) == 8 ? 8 : 4; }
 
 // index of population i of global node g in a population buffer
 __host__ __device__ __forceinline__ int64_t pop_at(int i, int64_t g)
@@ -69,17 +75,6 @@ struct NodeTile {
     int32_t pad;
 };
 
-// Tiles that receive spread force, per fluid step parity (the overlapped step, see
-// launch_overlap_free).  A global tile gt holds global nodes [256 gt, 256 gt + 256).
-struct TileMarks {
-    uint32_t* mark;         // [2][n_gt]: 1 if the tile receives spread force in that step
-    int32_t* list;          // [2][n_gt]: the marked tiles in the order they were claimed
-    int32_t* count;         // [2]: entries in list
-    const int32_t* tile_of; // [n_gt]: index of the global tile in its group's tile array
-    int32_t n_gt;
-    int32_t pad;
-};
-
 struct DeviceHeader {
     int64_t step;           // completed steps (read by graph-replayed kernels)
     uint32_t err_flags;     // bit 0: spread force out of the fixed-point range
@@ -96,11 +91,13 @@ struct StepArgs {
     const RowDesc* rowinfo;   // every row, indexed by row_base + y + ny z
     const NodeTile* tiles;
     int32_t n_tiles;
+    int32_t tiles_per_wg;   // node tiles per node-update workgroup (1 or kWideTiles)
+    int32_t wg_per_cu;      // node-update workgroups resident per CU at most (0: no cap)
     int32_t thermal;
     int32_t narrow;         // every replica of the group spans at most 4 GiB of populations:
                             // 32-bit byte offsets from a per-replica base
     int32_t stream_stores;  // non-temporal population stores (buffers beyond the caches)
-    long long* gforce;      // fixed-point spread force, [word][axis][node] (1 or 2 words)
+    long long* gforce;      // fixed-point spread force, node-major (spread_stride words)
     uint8_t* flags;         // 1 byte per node: spread force present
     CollideParams<Real> cp;
     Real gext[3];
@@ -197,37 +194,14 @@ struct BodyArgs {
     const int32_t* nb_start;        // per replica cx*cy*cz + 1 entries into nb_sites
     const WallSite* nb_sites;       // the static sites of each coarse cell's neighbourhood
     const uint8_t* near;            // fine cells: 1 if a site may be within range
-    TileMarks marks;                // with the overlapped step: tiles of the next step's
-                                    // bead stencils are claimed here (mark null: not used)
-    const RowDesc* rowinfo;         // row table, for the stencil tiles of masked replicas
 };
 // the node update of one tile group; with forces the nodes consume the spread force, with
 // bodies != null its leading workgroups finish the bodies
 template <typename Real>
 void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const BodyArgs* bodies,
                       hipStream_t s, const LaunchEvents& ev = LaunchEvents{});
-// The overlapped fluid step (one tile group, one MD step per fluid step, no excluded volume):
-// two launches instead of coupling -> node update.
-//  launch_overlap_free: the coupling workgroups, and the node update (without force) of every
-//    tile not marked for this step; each tile workgroup also clears its tile's mark of the
-//    other parity (and the first one that parity's count).
-//  launch_overlap_forced: the body finishing, which also claims the tiles under the bead
-//    stencils of the next step, and the node update (with force) of the tiles marked for this
-//    step, walked from the list.
-// The results are those of the serial step bit for bit: a node's update reads only its own
-// spread force, and every node that receives one lies in a marked tile.
-template <typename Real>
-void launch_overlap_free(const StepArgs<Real>& a, bool masked, const CoupleArgs& c,
-                         const TileMarks& tm, hipStream_t s, const LaunchEvents& ev = LaunchEvents{});
-template <typename Real>
-void launch_overlap_forced(const StepArgs<Real>& a, bool masked, const BodyArgs& ba,
-                           hipStream_t s, const LaunchEvents& ev = LaunchEvents{});
-// clear the marks, lists and counts of both parities
-void launch_clear_marks(const TileMarks& tm, hipStream_t s);
-// pose of the coming MD step (parity = MD step count & 1) and bead records of every body;
-// with b.marks set, the tiles under the bead stencils are claimed for the fluid step of parity
-// mark_parity
-void launch_body_predict(const BodyArgs& b, int parity, int mark_parity, hipStream_t s);
+// pose of the coming MD step (parity = MD step count & 1) and bead records of every body
+void launch_body_predict(const BodyArgs& b, int parity, hipStream_t s);
 // finish the bodies after MD step k (< substeps - 1) of the fluid step read from
 // step_ptr + step_arg (or step_arg alone when step_ptr is null)
 void launch_body_substep(const BodyArgs& b, const int64_t* step_ptr, int64_t step_arg, int k,

@@ -26,7 +26,6 @@ LB_ERR_CAPACITY = -5
 LB_PRECISION_F64 = 0
 LB_PRECISION_F32 = 1
 LB_STORES_AUTO, LB_STORES_CACHED, LB_STORES_STREAMING = 0, 1, 2
-LB_STEP_AUTO, LB_STEP_SERIAL, LB_STEP_OVERLAP = 0, 1, 2
 
 # every symbol declared in include/lbrb.h
 EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wall_velocity",
@@ -36,7 +35,7 @@ EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wal
             "lb_rb_step", "lb_observables", "lb_body_count", "rb_bead_forces",
             "lb_export_populations", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
             "lb_set_timing", "lb_kernel_times", "lb_set_store_policy",
-            "lb_set_step_policy", "lb_step_overlapped",
+            "lb_autotune", "lb_get_tuning", "lb_set_tuning",
             "lb_adjoint_workspace_bytes", "lb_rb_adjoint",
             "lb_node_counts", "lb_destroy", "lb_last_error"]
 
@@ -61,6 +60,13 @@ class rb_relax_params(ctypes.Structure):
     _fields_ = [("k_surface", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("epsilon", ctypes.c_double), ("damping", ctypes.c_double),
                 ("dt", ctypes.c_double), ("mass", ctypes.c_double)]
+
+
+class lb_tuning(ctypes.Structure):
+    _fields_ = [("tuned", ctypes.c_int32), ("tiles_per_wg", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32), ("streaming", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("node_us_default", ctypes.c_double),
+                ("node_us_tuned", ctypes.c_double)]
 
 
 class lb_totals(ctypes.Structure):
@@ -146,10 +152,12 @@ def library():
     L.lb_set_timing.argtypes = [_VP, ctypes.c_int32]
     L.lb_set_store_policy.restype = ctypes.c_int
     L.lb_set_store_policy.argtypes = [_VP, ctypes.c_int32]
-    L.lb_set_step_policy.restype = ctypes.c_int
-    L.lb_set_step_policy.argtypes = [_VP, ctypes.c_int32]
-    L.lb_step_overlapped.restype = ctypes.c_int
-    L.lb_step_overlapped.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
+    L.lb_autotune.restype = ctypes.c_int
+    L.lb_autotune.argtypes = [_VP, ctypes.c_int32]
+    L.lb_get_tuning.restype = ctypes.c_int
+    L.lb_get_tuning.argtypes = [_VP, ctypes.POINTER(lb_tuning)]
+    L.lb_set_tuning.restype = ctypes.c_int
+    L.lb_set_tuning.argtypes = [_VP, ctypes.POINTER(lb_tuning)]
     L.lb_kernel_times.restype = ctypes.c_int
     L.lb_kernel_times.argtypes = [_VP, _D, ctypes.POINTER(ctypes.c_int64), _D,
                                   ctypes.POINTER(ctypes.c_int64)]
@@ -395,15 +403,23 @@ class Simulation:
         _check(self.ctx, library().lb_set_store_policy(self.ctx, int(policy)),
                "lb_set_store_policy")
 
-    def set_step_policy(self, policy):
-        _check(self.ctx, library().lb_set_step_policy(self.ctx, int(policy)),
-               "lb_set_step_policy")
+    def autotune(self, repeats=0):
+        """Time the node update's launch settings on this context and keep the fastest."""
+        _check(self.ctx, library().lb_autotune(self.ctx, int(repeats)), "lb_autotune")
+        return self.tuned_settings()
 
-    def step_overlapped(self):
-        out = ctypes.c_int32(0)
-        _check(self.ctx, library().lb_step_overlapped(self.ctx, ctypes.byref(out)),
-               "lb_step_overlapped")
-        return bool(out.value)
+    def set_tuning(self, tiles_per_wg=1, wg_per_cu=0, streaming=False):
+        t = lb_tuning(tuned=1, tiles_per_wg=tiles_per_wg, wg_per_cu=wg_per_cu,
+                      streaming=1 if streaming else 0)
+        _check(self.ctx, library().lb_set_tuning(self.ctx, ctypes.byref(t)), "lb_set_tuning")
+
+    def tuned_settings(self):
+        t = lb_tuning()
+        _check(self.ctx, library().lb_get_tuning(self.ctx, ctypes.byref(t)), "lb_get_tuning")
+        return {"tuned": bool(t.tuned), "tiles_per_wg": t.tiles_per_wg, "wg_per_cu": t.wg_per_cu,
+                "streaming_stores": bool(t.streaming), "candidates": t.candidates,
+                "node_us_default": round(t.node_us_default, 3),
+                "node_us_tuned": round(t.node_us_tuned, 3)}
 
     def set_timing(self, on):
         _check(self.ctx, library().lb_set_timing(self.ctx, 1 if on else 0), "lb_set_timing")

@@ -26,6 +26,7 @@ def oracle_from_workload(wl, r=0):
     sim._mass_inertia = [(0.0, np.zeros(3)) if bd["fixed"] else
                          (float(bd["mass"]), np.asarray(bd["inertia"], dtype=float))
                          for bd in rep["bodies"]]
+    sim._gammas = [float(bd["gamma"]) for bd in rep["bodies"]]
     if rep["mask"] is not None:
         sim.set_mask(rep["mask"])
     for wall, u in (rep.get("walls") or {}).items():
@@ -104,12 +105,23 @@ def compare(gpu, orc, r=0, n_bodies=None, pops=True):
     out["finite"] = tg["finite"] == to["finite"]
     nb = orc.n_bodies if n_bodies is None else n_bodies
     errs = {"pos": 0.0, "quat": 0.0, "vel": 0.0, "omega": 0.0, "force": 0.0, "torque": 0.0}
-    scale = {"vel": 0.0, "vel_int": 0.0, "omega": 0.0, "force": 0.0, "torque": 0.0}
+    scale = {"vel": 0.0, "vel_int": 0.0, "omega": 0.0, "force": 0.0, "torque": 0.0,
+             "force_prop": 0.0, "torque_prop": 0.0}
+    gammas = getattr(orc, "_gammas", None)
     for b in range(nb):
         so = orc.body_state(b)
         sg = bg[b]
+        berr = {k: float(np.abs(sg[k] - so[k]).max()) for k in errs}
         for k in errs:
-            errs[k] = max(errs[k], float(np.abs(sg[k] - so[k]).max()))
+            errs[k] = max(errs[k], berr[k])
+        # what the measured errors of the sampled fluid velocity (at most u_abs at any node,
+        # so at any bead) and of the body's velocities propagate through the friction
+        # -gamma (v_k - u_k) into the net force and torque
+        if gammas is not None and b < len(gammas):
+            arm = np.linalg.norm(orc_offsets(orc, b), axis=1)
+            dv = out["u_abs"] + berr["vel"] + arm * berr["omega"]
+            scale["force_prop"] = max(scale["force_prop"], gammas[b] * float(dv.sum()))
+            scale["torque_prop"] = max(scale["torque_prop"], gammas[b] * float((arm * dv).sum()))
         # force and torque are sums of per-bead terms that largely cancel; their error scale
         # is the gross sum of the terms, sum_k |F_k| and sum_k |r_k - R| |F_k|
         fb = orc.bead_forces(b)

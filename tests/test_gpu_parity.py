@@ -22,6 +22,11 @@ Tolerances (derivation in the design notes):
   integrated gross torque, step * sum_k |r_k - R| |F_k| / I_min (the net omega of a symmetric
   body is itself a cancelling sum: 3.6e-8 for the sphere of workload 1 after 40 steps).
 - body position: the position tolerance plus step times the velocity bound (R integrates V).
+- body force and torque: tol times the gross bead sums, plus what the measured errors of the
+  fluid velocity and of the body's velocities propagate to through the friction,
+  gamma sum_k (|du| + |dV| + |r_k - R| |dw|) (and |r_k - R| times that for the torque).  A body
+  that moves with the fluid has a net force far below its gross bead force (workload 1
+  without noise, 500 steps: 1.1e-3 gross), so this second term is the one that scales there.
 """
 import numpy as np
 import pytest
@@ -63,8 +68,10 @@ def _assert_close(e, tol_rel_u, tol_rho, tol_body):
     assert e["body_vel"] <= vel_bound, "vel"
     assert e["body_pos"] <= tol_body + steps * vel_bound, "pos"
     assert e["body_quat"] <= tol_body, "quat"
-    for k in ("omega", "force", "torque"):
-        assert e["body_" + k] <= tol_rel_u * max(e["scale_" + k], 1e-14) + 1e-15, k
+    assert e["body_omega"] <= tol_rel_u * max(e["scale_omega"], 1e-14) + 1e-15, "omega"
+    for k in ("force", "torque"):
+        assert e["body_" + k] <= (tol_rel_u * max(e["scale_" + k], 1e-14)
+                                  + e.get("scale_" + k + "_prop", 0.0) + 1e-15), k
 
 
 def small_sphere_case(precision, kT=0.0, steps=(1, 2, 7, 40, 500)):

@@ -1,0 +1,110 @@
+"""The oracle's whole step against the physics it must reproduce (CPU, slow): small boxes the
+oracle finishes in seconds, with the bounds of the GPU physics tests.
+
+- Stokes drag on a fixed raspberry sphere (R = 1.5, 63 beads) in a periodic box, flow driven
+  by a body force on the fluid: at steady state the drag equals the total driving force; the
+  friction xi(L) = F / <u> follows Hasimoto's result for a periodic array of spheres (eq.
+  hasimoto, read as 2.837 kT / (6 pi eta L); here in its resistance form with the higher-order
+  terms of the same series), so the hydrodynamic radius solved from each box size must not
+  depend on L while the friction itself drops by a quarter from L = 10 to 16.
+- Equipartition (eq. einstein_trans and the fluctuation-dissipation statement of Sec. 1.1) in
+  a 12^3 thermal box with a free R = 1.5 sphere: the fluid's velocity variance is kT per
+  degree of freedom; the body's <V_a^2> = kT/M (1 - M/M_total) with the total momentum fixed,
+  and <w_a^2> = kT/I_a, up to the bias of the explicit bead coupling (the sampled fluid
+  velocity does not yet contain the bead's own reaction force of the step), which shrinks
+  with the bead friction.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import pyoracle as po
+from paper_1604_01829_amd import workloads as W
+
+pytestmark = pytest.mark.slow
+
+ETA = 1.0 / 6.0      # rho0 nu with tau_shear = 1
+
+
+def _steady_drag(L, offs, gamma, axis, u_target=2e-3, xi_guess=9.0, chunk=200):
+    g = u_target * xi_guess / L ** 3          # keeps the mean flow near u_target
+    ge = [0.0, 0.0, 0.0]
+    ge[axis] = g
+    sim = po.OracleSim((L, L, L), po.make_params(tau_shear=1.0, g_ext=tuple(ge), seed=1))
+    sim.add_body(offs, 1.0, (1, 1, 1), (L / 2 + 0.13, L / 2 - 0.21, L / 2 + 0.07), gamma=gamma,
+                 fixed=True)
+    gN = g * L ** 3
+    F = 0.0
+    for _ in range(200):
+        sim.step(chunk)
+        F = sim.body_state(0)["force"][axis]
+        if abs(F - gN) < 1e-5 * gN:
+            break
+    assert abs(F - gN) < 1e-5 * gN, "no steady state"
+    U = float(sim.fields()[..., 1 + axis].mean())
+    return F / U
+
+
+def _hasimoto_radius(xi, L):
+    """R with 6 pi eta R / xi = 1 - 2.837 x + 4.19 x^3 - 27.4 x^6, x = R / L (bisection)."""
+    lo, hi = 1e-3, L / 3.0
+    for _ in range(200):
+        R = 0.5 * (lo + hi)
+        x = R / L
+        if 6 * math.pi * ETA * R / xi > 1 - 2.837 * x + 4.19 * x ** 3 - 27.4 * x ** 6:
+            hi = R
+        else:
+            lo = R
+    return 0.5 * (lo + hi)
+
+
+def test_oracle_hasimoto_box_size_series():
+    R = 1.5
+    offs = W.sphere_beads(R, W.sphere_bead_count(R))
+    xi, rh = {}, {}
+    for L in (10, 12, 16):
+        xi[L] = _steady_drag(L, offs, W.GAMMA_FIXED, 0)
+        rh[L] = _hasimoto_radius(xi[L], L)
+        print(f"  L={L}: xi={xi[L]:.5f} R_h={rh[L]:.5f}", flush=True)
+    v = np.array(list(rh.values()))
+    assert xi[16] < 0.8 * xi[10]                 # the images matter at these sizes
+    assert (v.max() - v.min()) / v.mean() < 5e-3
+    assert R < v.mean() < R + 0.5                # beyond the bead radius, by a bead shell
+
+
+def _temperatures(gamma, samples, seed, L=12, R=1.5, kT=4e-5, every=2):
+    offs = W.sphere_beads(R, W.sphere_bead_count(R))
+    m, I = W.solid_body_mass_inertia(1.0, R, R, R)
+    sim = po.OracleSim((L, L, L), po.make_params(tau_shear=1.0, kT=kT, seed=seed))
+    sim.add_body(offs, m, I, (L / 2, L / 2, L / 2), gamma=gamma)
+    sim.step(300)
+    V, Om, fluid = [], [], []
+    for k in range(samples):
+        sim.step(every)
+        b = sim.body_state(0)
+        V.append(b["vel"])
+        Om.append(b["omega"])
+        if k % 50 == 0:
+            f = sim.fields()
+            fluid.append(float((f[..., 0] * (f[..., 1:] ** 2).sum(-1)).mean() / (3 * kT)))
+    V, Om = np.array(V), np.array(Om)
+    m_total = m + L ** 3                          # rho0 = 1: fluid mass = node count
+    tt = float((V ** 2).mean() / (kT / m * (1 - m / m_total)))
+    tr = float(((Om ** 2).mean(0) / (kT / np.asarray(I))).mean())
+    blk = (V ** 2).sum(1).reshape(20, -1).mean(1)
+    err = float(blk.std() / blk.mean() / math.sqrt(20))
+    return tt, tr, err, float(np.mean(fluid))
+
+
+def test_oracle_equipartition_of_a_free_raspberry():
+    g = W.GAMMA_FREE
+    runs = {"gamma": _temperatures(g, 20000, 123), "gamma/4": _temperatures(g / 4, 20000, 123)}
+    for k, (tt, tr, e, tf) in runs.items():
+        print(f"  {k}: T_trans/kT={tt:.4f} T_rot/kT={tr:.4f} (+-{e:.4f}), fluid {tf:.4f}",
+              flush=True)
+        assert abs(tf - 1.0) < 5e-3                  # the fluid is at kT
+        assert 0.99 < tt < 1.08 and 0.99 < tr < 1.08
+    (t1, r1, _, _), (tq, rq, _, _) = runs.values()
+    # smaller with a smaller bead friction
+    assert tq < t1 and rq < r1 and tq < 1.04 and rq < 1.04
