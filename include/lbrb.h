@@ -351,6 +351,20 @@ int lb_rb_adjoint(lb_ctx* ctx, int32_t n_steps, int32_t checkpoint_every, void* 
                   size_t ws_bytes, const double* dJ_dF, double* J, double* dJ_dgamma,
                   double* dJ_doffsets);
 
+/* The reverse pass of lb_rb_adjoint without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  It runs on a scratch array of LB_NOALLOC_SCRATCH_BYTES (64 MiB) that
+ * the library holds on every GPU it runs on until the process ends, and calls no allocating
+ * routine; arguments and results as for lb_rb_adjoint.  LB_ERR_ARG when the window needs more
+ * than LB_NOALLOC_SCRATCH_BYTES (lb_adjoint_workspace_bytes tells; a longer checkpoint
+ * interval needs less), LB_ERR_HIP when the scratch array's address cannot be taken.  Every
+ * call on one GPU uses that GPU's array (the parts that must start at zero are cleared by
+ * each call), so calls that overlap on one GPU race.                                       */
+#define LB_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+int lb_rb_adjoint_noalloc(lb_ctx* ctx, int32_t n_steps, int32_t checkpoint_every,
+                          const double* dJ_dF, double* J, double* dJ_dgamma,
+                          double* dJ_doffsets);
+
 /* Node counts of one replica: all nodes and fluid nodes.                                  */
 int lb_node_counts(const lb_ctx* ctx, int32_t replica, int64_t* n_nodes, int64_t* n_fluid);
 

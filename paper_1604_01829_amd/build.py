@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbrb.so")
 SOURCES = [os.path.join(HERE, "csrc", n)
            for n in ("lbrb_kernels.hip", "lbrb_adjoint.hip", "lbrb_walls.hip", "lbrb_analysis.hip",
-                     "lbrb_construct.hip", "lbrb_api.cpp")]
+                     "lbrb_construct.hip", "lbrb_noalloc.hip", "lbrb_api.cpp")]
 ARCH = os.environ.get("LBRB_ARCH", "gfx950")
 
 

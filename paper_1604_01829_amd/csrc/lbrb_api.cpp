@@ -24,6 +24,10 @@
 
 using namespace lbrb;
 
+namespace lbrb {
+void noalloc_prepare();   // lbrb_noalloc.hip: the scratch array's address on this device
+}
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -1118,6 +1122,11 @@ int autotune_t(lb_ctx* c, int reps, Tuning& best)
 
 }  // namespace
 
+namespace lbrb {
+// error reporting for the entry points of other source files
+int set_error(lb_ctx* c, int code, const char* msg) { return fail(c, code, msg); }
+}
+
 // ============================================================================ C-ABI
 
 extern "C" {
@@ -1209,6 +1218,7 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     int rc = upload_tables(c);
     if (rc == LB_OK) rc = init_fluid(c, -1);
     if (rc != LB_OK) { lb_destroy(c); return rc; }
+    noalloc_prepare();
     *out = c;
     return LB_OK;
 }

@@ -26,6 +26,7 @@ LB_ERR_CAPACITY = -5
 LB_PRECISION_F64 = 0
 LB_PRECISION_F32 = 1
 LB_STORES_AUTO, LB_STORES_CACHED, LB_STORES_STREAMING = 0, 1, 2
+LB_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 # every symbol declared in include/lbrb.h
 EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wall_velocity",
@@ -36,7 +37,7 @@ EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wal
             "lb_export_populations", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
             "lb_set_timing", "lb_kernel_times", "lb_set_store_policy",
             "lb_autotune", "lb_get_tuning", "lb_set_tuning",
-            "lb_adjoint_workspace_bytes", "lb_rb_adjoint",
+            "lb_adjoint_workspace_bytes", "lb_rb_adjoint", "lb_rb_adjoint_noalloc",
             "lb_node_counts", "lb_destroy", "lb_last_error"]
 
 
@@ -166,6 +167,8 @@ def library():
     L.lb_rb_adjoint.restype = ctypes.c_int
     L.lb_rb_adjoint.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_size_t, _D, _D,
                                 _D, _D]
+    L.lb_rb_adjoint_noalloc.restype = ctypes.c_int
+    L.lb_rb_adjoint_noalloc.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32, _D, _D, _D, _D]
     L.lb_node_counts.restype = ctypes.c_int
     L.lb_node_counts.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64)]
@@ -313,6 +316,20 @@ def lb_rb_adjoint(ctx, n_steps, checkpoint_every, dev_ws, ws_bytes, dJ_dF, n_bod
     return J.value, dg[:n_bodies], do[:n_beads]
 
 
+def lb_rb_adjoint_noalloc(ctx, n_steps, checkpoint_every, dJ_dF, n_bodies, n_beads):
+    """lb_rb_adjoint on the library's own scratch array (no workspace): same results."""
+    w = np.ascontiguousarray(np.asarray(dJ_dF, dtype=np.float64).reshape(-1))
+    if w.size != 3 * n_bodies * int(n_steps):
+        raise ValueError("dJ_dF must hold n_steps * n_bodies * 3 values")
+    J = ctypes.c_double(0.0)
+    dg = np.zeros(max(1, n_bodies))
+    do = np.zeros((max(1, n_beads), 3))
+    rc = library().lb_rb_adjoint_noalloc(ctx, int(n_steps), int(checkpoint_every), _dp(w),
+                                         ctypes.byref(J), _dp(dg), _dp(do))
+    _check(ctx, rc, "lb_rb_adjoint_noalloc")
+    return J.value, dg[:n_bodies], do[:n_beads]
+
+
 def lb_destroy(ctx):
     library().lb_destroy(ctx)
 
@@ -392,6 +409,12 @@ class Simulation:
                             len(self.body_order), n_beads)
         del ws
         return out
+
+    def adjoint_noalloc(self, n_steps, dJ_dF, checkpoint_every=20):
+        """As adjoint(), on the library's scratch array instead of a torch workspace."""
+        n_beads = sum(self.n_beads[k] for k in self.body_order)
+        return lb_rb_adjoint_noalloc(self.ctx, n_steps, checkpoint_every, dJ_dF,
+                                     len(self.body_order), n_beads)
 
     def step(self, n=1):
         lb_rb_step(self.ctx, n)
