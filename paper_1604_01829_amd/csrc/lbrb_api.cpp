@@ -48,7 +48,7 @@ struct Plan {
     int gforce_words = 4;     // fixed-point words per node: 3 axes x (1 in FP32, 2 in FP64),
                               // padded to 4 (32 bytes) or 8 (64 bytes)
     size_t off_hdr, off_reps, off_rows, off_rowinfo, off_tiles_d, off_tiles_m, off_fa, off_fb,
-        off_gforce, off_flags, off_bodies, off_bead_off, off_bead_rec, off_bead_force,
+        off_gforce, off_flags, off_hole, off_hole_tiles, off_bodies, off_bead_off, off_bead_rec, off_bead_force,
         off_bead_torque, off_partials, off_links, off_ev, off_wrep, off_rep_bodies,
         off_nb_start, off_nb_sites, off_near, off_wca_ft, total;
 };
@@ -115,6 +115,8 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
                                                        : spread_stride<double>();
     pl.off_gforce = take(sizeof(long long) * pl.gforce_words * pl.N);
     pl.off_flags = take(pl.N);
+    pl.off_hole = take(pl.N);
+    pl.off_hole_tiles = take(sizeof(NodeTile) * pl.tiles_cap);
     pl.off_bodies = take(sizeof(Body) * std::max<int64_t>(pl.body_cap, 1));
     pl.off_bead_off = take(sizeof(Bead) * std::max<int64_t>(pl.bead_cap, 1));
     pl.off_bead_rec = take(sizeof(BeadRec) * std::max<int64_t>(pl.bead_cap, 1));
@@ -136,6 +138,7 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
 
 struct ReplicaHost {
     int group = 0;            // 0 = dense tiles, 1 = masked tiles
+    int64_t n_holes = 0;      // boundary nodes stored inside row spans (lbrb_walls.h)
     int32_t tile0 = 0, n_tiles = 0;
     std::vector<int32_t> bodies;
     std::vector<uint8_t> mask;      // boundary mask as set (wall ids), empty = all fluid
@@ -180,6 +183,9 @@ struct lb_ctx {
     int cur = 0;
     long long* gforce = nullptr;
     uint8_t* flags = nullptr;
+    uint8_t* hole = nullptr;          // per node: wall id of a hole, else 0
+    NodeTile* d_hole_tiles = nullptr;  // the tiles of replicas with holes
+    std::vector<NodeTile> hole_tiles;
     Body* d_bodies = nullptr;
     Bead* d_beads = nullptr;
     BeadRec* d_recs = nullptr;
@@ -299,6 +305,7 @@ StepArgs<Real> step_args_on(const lb_ctx* c, int group, const void* src, void* d
     a.stream_stores = streaming_stores(c) ? 1 : 0;
     a.gforce = c->gforce;
     a.flags = c->flags;
+    a.hole = c->hole;
     a.cp = collide_params<Real>(c->p);
     for (int ax = 0; ax < 3; ++ax) a.gext[ax] = (Real)c->p.g_ext[ax];
     a.step_ptr = nullptr;
@@ -440,6 +447,11 @@ hipError_t enqueue_step(lb_ctx* c, hipStream_t s, int src_buf, const int64_t* st
         launch_wall_links<Real>((Real*)c->f[src_buf ^ 1], c->d_links, c->n_links, s);
         err = hipGetLastError();
     }
+    if (!c->hole_tiles.empty() && err == hipSuccess) {
+        launch_mirror_holes<Real>((Real*)c->f[src_buf ^ 1], c->d_reps, c->d_rows, c->d_rowinfo,
+                                  c->d_hole_tiles, (int32_t)c->hole_tiles.size(), c->hole, s);
+        err = hipGetLastError();
+    }
     return err;
 }
 
@@ -529,6 +541,16 @@ void rebuild_tiles(lb_ctx* c)
 
 int upload_tables(lb_ctx* c)
 {
+    // the tiles of replicas with holes, for the mirror launch
+    c->hole_tiles.clear();
+    for (int r = 0; r < c->n_rep; ++r)
+        if (c->reps[r].masked == 2)
+            c->hole_tiles.insert(c->hole_tiles.end(), c->tiles[1].begin() + c->rh[r].tile0,
+                                 c->tiles[1].begin() + c->rh[r].tile0 + c->rh[r].n_tiles);
+    if (!c->hole_tiles.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->d_hole_tiles, c->hole_tiles.data(),
+                                  sizeof(NodeTile) * c->hole_tiles.size(), hipMemcpyHostToDevice,
+                                  c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->d_reps, c->reps.data(), sizeof(ReplicaDesc) * c->n_rep,
                               hipMemcpyHostToDevice, c->stream));
     if (!c->rows.empty())
@@ -577,6 +599,17 @@ int init_fluid(lb_ctx* c, int replica)
             launch_wall_links<double>((double*)c->f[c->cur], c->d_links + H.link0,
                                       (int64_t)H.links.size(), c->stream);
     }
+    // and the holes reflect what their fluid neighbours hold
+    if (!c->hole_tiles.empty()) {
+        if (is_f32(c))
+            launch_mirror_holes<float>((float*)c->f[c->cur], c->d_reps, c->d_rows, c->d_rowinfo,
+                                       c->d_hole_tiles, (int32_t)c->hole_tiles.size(), c->hole,
+                                       c->stream);
+        else
+            launch_mirror_holes<double>((double*)c->f[c->cur], c->d_reps, c->d_rows,
+                                        c->d_rowinfo, c->d_hole_tiles,
+                                        (int32_t)c->hole_tiles.size(), c->hole, c->stream);
+    }
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return LB_OK;
@@ -596,7 +629,8 @@ std::vector<WallLink> build_links(const ReplicaDesc& R, const uint8_t* mask,
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y) {
             const RowDesc& row = info[(size_t)y + (size_t)ny * z];
-            for (int x = row.xlo; x < row.xlo + row.len; ++x)
+            for (int x = row.xlo; x < row.xlo + row.len; ++x) {
+                if (mask[x + (size_t)nx * (y + (size_t)ny * z)]) continue;   // a hole
                 for (int i = 1; i < Q; ++i) {
                     const int bx = wrapi(x - cx_of(i), nx), by = wrapi(y - cy_of(i), ny),
                               bz = wrapi(z - cz_of(i), nz);
@@ -611,6 +645,7 @@ std::vector<WallLink> build_links(const ReplicaDesc& R, const uint8_t* mask,
                     L.delta = 6.0 * weight_of(i) * rho0 * cu;
                     out.push_back(L);
                 }
+            }
         }
     // in storage order of the slots they update
     std::sort(out.begin(), out.end(), [](const WallLink& a, const WallLink& b) {
@@ -1165,6 +1200,8 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     c->f[1] = c->ws + pl.off_fb;
     c->gforce = (long long*)(c->ws + pl.off_gforce);
     c->flags = (uint8_t*)(c->ws + pl.off_flags);
+    c->hole = (uint8_t*)(c->ws + pl.off_hole);
+    c->d_hole_tiles = (NodeTile*)(c->ws + pl.off_hole_tiles);
     c->d_bodies = (Body*)(c->ws + pl.off_bodies);
     c->d_beads = (Bead*)(c->ws + pl.off_bead_off);
     c->d_recs = (BeadRec*)(c->ws + pl.off_bead_rec);
@@ -1214,6 +1251,7 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
     for (int k = 0; k < 2 && e == hipSuccess; ++k)
         e = hipMemsetAsync(c->f[k], 0, real * Q * pl.N, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->flags, 0, pl.N, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->hole, 0, pl.N, c->stream);
     if (e != hipSuccess) { lb_destroy(c); return LB_ERR_HIP; }
     int rc = upload_tables(c);
     if (rc == LB_OK) rc = init_fluid(c, -1);
@@ -1233,18 +1271,19 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
     bool any_solid = false;
     std::vector<RowDesc> rows;
     std::vector<RowDesc> info((size_t)ny * nz, RowDesc{0, 0, 0, 0});
-    int64_t start = 0;
+    std::vector<uint8_t> holes;   // per stored node: the wall id of a hole, else 0
+    int64_t start = 0, n_holes = 0;
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y) {
             const uint8_t* m = mask + (size_t)nx * (y + (size_t)ny * z);
-            int xlo = -1, xhi = -1, runs = 0;
+            int xlo = -1, xhi = -1;
             for (int x = 0; x < nx; ++x) {
                 if (m[x]) { any_solid = true; continue; }
-                if (x == 0 || m[x - 1]) { ++runs; if (xlo < 0) xlo = x; }
+                if (xlo < 0) xlo = x;
                 xhi = x;
             }
-            if (runs == 0) continue;
-            if (runs > 1) return fail(c, LB_ERR_ARG, "a mask row holds more than one fluid run");
+            if (xlo < 0) continue;
+            // the span from the first to the last fluid node; boundary nodes inside it are holes
             RowDesc d{};
             d.start = (int32_t)start;
             d.xlo = xlo;
@@ -1252,6 +1291,10 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
             d.yz = y | (z << 16);
             info[(size_t)y + (size_t)ny * z] = d;
             rows.push_back(d);
+            for (int x = xlo; x <= xhi; ++x) {
+                holes.push_back(m[x]);
+                if (m[x]) ++n_holes;
+            }
             start += d.len;
         }
     // links of the replica's moving walls under the new mask, checked before anything changes
@@ -1265,17 +1308,22 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
         c->rowinfo[R.row_base + k] = RowDesc{0, 0, 0, 0};
         c->rows[R.row_base + k] = RowDesc{0, 0, 0, 0};
     }
+    HIP_TRY(c, hipMemsetAsync(c->hole + R.base, 0, (size_t)pad_nodes(R.n_nodes), c->stream));
     if (any_solid) {
         for (size_t k = 0; k < rows.size(); ++k) c->rows[R.row_base + k] = rows[k];
         for (int64_t k = 0; k < (int64_t)ny * nz; ++k) c->rowinfo[R.row_base + k] = info[k];
-        R.masked = 1;
-        R.n_fluid = start;
+        R.masked = n_holes > 0 ? 2 : 1;
+        R.n_fluid = start;                       // stored nodes: fluid nodes and holes
         H.mask.assign(mask, mask + (size_t)nx * ny * nz);
+        if (n_holes > 0)
+            HIP_TRY(c, hipMemcpyAsync(c->hole + R.base, holes.data(), holes.size(),
+                                      hipMemcpyHostToDevice, c->stream));
     } else {
         R.masked = 0;
         R.n_fluid = R.n_nodes;
         H.mask.clear();
     }
+    H.n_holes = n_holes;
     H.links.swap(links);
     destroy_graphs(c);
     rebuild_tiles(c);
@@ -1524,7 +1572,7 @@ int lb_observables(lb_ctx* c, int32_t replica, lb_totals* out, rb_state* bodies,
     for (int32_t t = 0; t < H.n_tiles; ++t)
         for (int k = 0; k < 5; ++k) s[k] += part[5 * (size_t)t + k];
     lb_totals T{};
-    T.mass = (double)R.n_fluid * c->p.rho0 + s[0];
+    T.mass = (double)(R.n_fluid - H.n_holes) * c->p.rho0 + s[0];
     for (int a = 0; a < 3; ++a) T.momentum[a] = s[1 + a];
     for (int32_t b : H.bodies) {
         if (bs[b].fixed) continue;
@@ -1767,7 +1815,7 @@ int lb_node_counts(const lb_ctx* c, int32_t replica, int64_t* n_nodes, int64_t* 
 {
     if (!c || replica < 0 || replica >= c->n_rep) return LB_ERR_ARG;
     if (n_nodes) *n_nodes = c->reps[replica].n_nodes;
-    if (n_fluid) *n_fluid = c->reps[replica].n_fluid;
+    if (n_fluid) *n_fluid = c->reps[replica].n_fluid - c->rh[replica].n_holes;
     return LB_OK;
 }
 
@@ -1811,6 +1859,9 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
                     "the reverse pass needs one MD step per fluid step and no excluded volume");
     for (const Body& B : c->bodies0)
         if (!B.fixed) return fail(c, LB_ERR_STATE, "the reverse pass needs fixed bodies");
+    for (int r = 0; r < c->n_rep; ++r)
+        if (c->reps[r].masked == 2)
+            return fail(c, LB_ERR_STATE, "the reverse pass needs masks of one fluid run per row");
     if (c->n_bodies > 0 && (!dJ_dF || !dJ_dgamma || !dJ_doffsets))
         return fail(c, LB_ERR_ARG, "missing objective weights or gradient outputs");
     char* ws = (char*)dev_ws;

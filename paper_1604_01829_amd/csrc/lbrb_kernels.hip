@@ -734,6 +734,8 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
             load_rows9(a.rowinfo, B.row_base, ny, nz, py, pz, rw);
             const int off = px - rw.lo[4];
             local = (unsigned)off < (unsigned)rw.ln[4] ? rw.st[4] + off : -1;
+            // a hole is a boundary node: no velocity sampled, no force spread
+            if (B.masked == 2 && local >= 0 && a.hole[B.base + local] != 0) local = -1;
         } else {
             local = px + (int64_t)nx * (py + (int64_t)ny * pz);
         }
@@ -990,7 +992,10 @@ __global__ __launch_bounds__(kNodeBlock) void observe_kernel(const StepArgs<Real
     const NodeTile t = tiles[blockIdx.x];
     const ReplicaDesc R = a.reps[t.replica];
     double acc[5] = {0, 0, 0, 0, 0};
-    if ((int)threadIdx.x < t.count) {
+    // holes are boundary nodes: zero fields and populations, not in the sums
+    const bool node = (int)threadIdx.x < t.count &&
+                      !(MASKED && R.masked == 2 && a.hole[R.base + t.begin + threadIdx.x] != 0);
+    if (node) {
         const int64_t local = t.begin + threadIdx.x;
         int x, y, z;
         RowDesc self;

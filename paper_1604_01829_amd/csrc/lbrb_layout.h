@@ -1,9 +1,10 @@
 // lbrb_layout.h -- device data structures of the library and the kernel launchers.
 //
 // Fluid storage ("compact rows").  Each replica keeps only its fluid nodes.  A (y,z) row of a
-// replica holds at most one contiguous run of fluid nodes [xlo, xlo+len); the runs of all
-// non-empty rows are stored back to back in (z, y) order, so node (x,y,z) of the run of row
-// (y,z) lives at local index start + x - xlo.  rowinfo[row_base + y + ny z] holds
+// replica stores the span [xlo, xlo+len) from its first to its last fluid node (one run in
+// the common case; with several runs the boundary nodes between them are stored as "holes",
+// see lbrb_walls.h); the spans of all non-empty rows are stored back to back in (z, y) order,
+// so node (x,y,z) of the span of row (y,z) lives at local index start + x - xlo.  rowinfo[row_base + y + ny z] holds
 // (start, xlo, len) of every row (len = 0 for a row without fluid), so a neighbour lookup is
 // one load; rows[] lists the non-empty rows in storage order for the thread -> node map.  A replica without boundary nodes is
 // "dense": every row is full and the local index is x + nx (y + ny z), computed without
@@ -50,7 +51,7 @@ __host__ __device__ __forceinline__ int64_t pop_at(int i, int64_t g)
 // launch before them.
 
 struct ReplicaDesc {
-    int32_t nx, ny, nz, masked;
+    int32_t nx, ny, nz, masked;   // 0: no boundary nodes; 1: masked; 2: masked, with holes
     int64_t base;           // global index of local node 0
     int64_t n_nodes;        // nx*ny*nz
     int64_t n_fluid;
@@ -99,6 +100,7 @@ struct StepArgs {
     int32_t stream_stores;  // non-temporal population stores (buffers beyond the caches)
     long long* gforce;      // fixed-point spread force, node-major (spread_stride words)
     uint8_t* flags;         // 1 byte per node: spread force present
+    const uint8_t* hole;    // 1 byte per node: the wall id of a hole, 0 otherwise
     CollideParams<Real> cp;
     Real gext[3];
     const int64_t* step_ptr;  // if set, step = *step_ptr + step_arg

@@ -28,6 +28,24 @@ struct WallLink {
 template <typename Real>
 void launch_wall_links(Real* f, const WallLink* links, int64_t n_links, hipStream_t s);
 
+// Holes.  A (y,z) row with several fluid runs stores the span from its first to its last fluid
+// node, the boundary nodes between the runs ("holes", hole[g] = their wall id) included, so
+// the row keeps one descriptor and the pull looks its neighbours up as before.  A fluid node x
+// pulls population i from a hole h = x - c_i as if h were fluid; halfway bounce-back needs the
+// opposite post-collision population of x itself there, and the slot i of h is read by x and
+// by nothing else.  So after each node update (and the moving-wall links, whose term the
+// reflected value carries) every hole copies f*_opp(i)(x) into its slot i for each fluid
+// neighbour x = h + c_i.  Holes are updated like fluid nodes by the node kernel (their values
+// are never read), and every other consumer -- coupling, observables, export -- treats them as
+// boundary nodes.
+struct ReplicaDesc;
+struct RowDesc;
+struct NodeTile;
+template <typename Real>
+void launch_mirror_holes(Real* f, const ReplicaDesc* reps, const RowDesc* rows,
+                         const RowDesc* rowinfo, const NodeTile* tiles, int32_t n_tiles,
+                         const uint8_t* hole, hipStream_t s);
+
 }  // namespace lbrb
 
 #endif

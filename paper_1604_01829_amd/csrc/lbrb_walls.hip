@@ -1,4 +1,5 @@
-// lbrb_walls.hip -- the moving-wall link kernel (see lbrb_walls.h).
+// lbrb_walls.hip -- the moving-wall link kernel and the hole mirrors (see lbrb_walls.h).
+#include "lbrb_device.h"
 #include "lbrb_layout.h"
 #include "lbrb_walls.h"
 
@@ -24,6 +25,51 @@ void launch_wall_links(Real* f, const WallLink* links, int64_t n_links, hipStrea
                        links, n_links);
 }
 
+// one thread per stored node of the tiles of replicas with holes
+template <typename Real>
+__global__ __launch_bounds__(kNodeBlock) void mirror_holes_kernel(Real* f, const ReplicaDesc* reps,
+                                                                  const RowDesc* rows,
+                                                                  const RowDesc* rowinfo,
+                                                                  const NodeTile* tiles,
+                                                                  const uint8_t* hole)
+{
+    const NodeTile t = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= t.count) return;
+    const ReplicaDesc R = reps[t.replica];
+    const int64_t local = t.begin + threadIdx.x;
+    const int64_t g = R.base + local;
+    if (hole[g] == 0) return;
+    int x, y, z;
+    RowDesc self;
+    locate<true>(R, rows, t.row_lo, t.row_hi, local, x, y, z, self);
+    for (int i = 1; i < Q; ++i) {
+        const int xs = wrap1(x + cx_of(i), R.nx), ys = wrap1(y + cy_of(i), R.ny),
+                  zs = wrap1(z + cz_of(i), R.nz);
+        const RowDesc rd = rowinfo[R.row_base + ys + R.ny * zs];
+        const int off = xs - rd.xlo;
+        if ((unsigned)off >= (unsigned)rd.len) continue;       // not stored: boundary node
+        const int64_t gx = R.base + rd.start + off;
+        if (hole[gx] != 0) continue;                             // another hole
+        f[pop_at(i, g)] = f[pop_at(opposite_of(i), gx)];
+    }
+}
+
+template <typename Real>
+void launch_mirror_holes(Real* f, const ReplicaDesc* reps, const RowDesc* rows,
+                         const RowDesc* rowinfo, const NodeTile* tiles, int32_t n_tiles,
+                         const uint8_t* hole, hipStream_t s)
+{
+    if (n_tiles <= 0) return;
+    hipLaunchKernelGGL((mirror_holes_kernel<Real>), dim3(n_tiles), dim3(kNodeBlock), 0, s, f, reps,
+                       rows, rowinfo, tiles, hole);
+}
+
+template void launch_mirror_holes<float>(float*, const ReplicaDesc*, const RowDesc*,
+                                         const RowDesc*, const NodeTile*, int32_t,
+                                         const uint8_t*, hipStream_t);
+template void launch_mirror_holes<double>(double*, const ReplicaDesc*, const RowDesc*,
+                                          const RowDesc*, const NodeTile*, int32_t,
+                                          const uint8_t*, hipStream_t);
 template void launch_wall_links<float>(float*, const WallLink*, int64_t, hipStream_t);
 template void launch_wall_links<double>(double*, const WallLink*, int64_t, hipStream_t);
 

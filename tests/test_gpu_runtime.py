@@ -143,12 +143,11 @@ def test_error_codes():
     p = lbrb.make_params("f32", max_bodies=1, max_beads=4)
     reps = lbrb.make_replicas([((8, 8, 8), 1)])
     sim = lbrb.Simulation(p, reps)
-    # a row with two fluid runs
+    # rows with two fluid runs are accepted; the wall between them is no fluid node
     m = np.zeros((8, 8, 8), dtype=np.uint8)
     m[:, :, 3] = 1
-    with pytest.raises(lbrb.LBError) as e:
-        sim.set_mask(0, m)
-    assert e.value.code == lbrb.LB_ERR_ARG
+    sim.set_mask(0, m)
+    assert sim.node_counts(0) == (512, 448)
     with pytest.raises(lbrb.LBError) as e:
         sim.add_body(0, np.zeros((5, 3)), 1.0, (1, 1, 1), (4, 4, 4))
     assert e.value.code == lbrb.LB_ERR_CAPACITY
