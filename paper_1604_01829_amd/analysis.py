@@ -136,5 +136,48 @@ def hasimoto_intercept(box_lengths, diffusivities):
     return float(d.mean() - slope * x.mean()), -slope
 
 
+def hasimoto_radius(xi, L, eta):
+    """Hydrodynamic radius of a sphere whose friction in a periodic cubic box of side L is xi
+    (Hasimoto's series for a periodic array, eq. (hasimoto), in its resistance form:
+    6 pi eta R / xi = 1 - 2.837 x + 4.19 x^3 - 27.4 x^6, x = R / L), by bisection."""
+    lo, hi = 1e-6, L / 3.0
+    for _ in range(200):
+        R = 0.5 * (lo + hi)
+        x = R / L
+        if 6 * np.pi * eta * R / xi > 1 - 2.837 * x + 4.19 * x ** 3 - 27.4 * x ** 6:
+            hi = R
+        else:
+            lo = R
+    return 0.5 * (lo + hi)
+
+
+def hasimoto_friction(R, L, eta):
+    """The friction in a periodic box of side L of a sphere of hydrodynamic radius R."""
+    x = R / L
+    return 6 * np.pi * eta * R / (1 - 2.837 * x + 4.19 * x ** 3 - 27.4 * x ** 6)
+
+
+def decay_friction(drag, u0, rho0, n_nodes, window):
+    """Friction of a fixed body in a periodic box whose fluid started at the uniform velocity
+    u0 (along the drag axis) and is not driven: the fluid loses the body's drag F(m) every step,
+    so its mean velocity after step n is U(n) = u0 - sum_{m<=n} F(m) / (rho0 n_nodes), and over a
+    window of steps (1-based, inclusive) the friction is sum F / sum U.  drag[m-1] = F(m)."""
+    F = np.asarray(drag, dtype=np.float64)
+    U = u0 - np.cumsum(F) / (rho0 * n_nodes)
+    a, b = window
+    return float(F[a - 1:b].sum() / U[a - 1:b].sum())
+
+
+def decay_friction_weights(xi, u0, rho0, n_nodes, window, n_steps):
+    """Weights c[m-1] and target t of the linear condition sum_m c_m F(m) = t that holds when
+    decay_friction(...) equals xi: sum_W F - xi sum_W U = 0 with U as in decay_friction."""
+    a, b = window
+    c = np.zeros(n_steps)
+    c[a - 1:b] = 1.0
+    for m in range(1, b + 1):
+        c[m - 1] += xi / (rho0 * n_nodes) * (b - max(a, m) + 1)
+    return c, xi * (b - a + 1) * u0
+
+
 def einstein(kT, d0):
     return kT / d0

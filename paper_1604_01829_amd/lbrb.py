@@ -622,6 +622,26 @@ def calibrate_gamma(builder, n_steps, weights, target, gamma0, checkpoint_every=
     raise LBError(LB_ERR_UNSTABLE, "calibration did not converge")
 
 
+def calibrate_gamma_to_radius(builder, box, target_radius, u0, rho0, eta, window, gamma0,
+                              axis=0, checkpoint_every=40, tol=1e-10, max_iter=20):
+    """Bead friction gamma of a fixed raspberry (every body of the builder's simulation) whose
+    Hasimoto-corrected hydrodynamic radius is `target_radius`: the simulation is a periodic
+    cubic box of side `box` whose fluid starts at the uniform velocity u0 along `axis` and is
+    not driven; the friction over `window` (steps, 1-based, inclusive) is measured as in
+    analysis.decay_friction and must equal Hasimoto's friction at the target radius.  That
+    condition is linear in the per-step drags, so calibrate_gamma (Newton with the reverse
+    pass's exact slope) solves it.  Returns (gamma, iterations, friction)."""
+    from . import analysis as AN
+    n_nodes = box ** 3
+    xi = AN.hasimoto_friction(target_radius, box, eta)
+    c, target = AN.decay_friction_weights(xi, u0, rho0, n_nodes, window, window[1])
+    weights = np.zeros((window[1], 1, 3))
+    weights[:, 0, axis] = c
+    g, _, it = calibrate_gamma(builder, window[1], weights, target, gamma0,
+                               checkpoint_every=checkpoint_every, tol=tol, max_iter=max_iter)
+    return g, it, xi
+
+
 # ------------------------------------------------------------------ Stokes-flow resistance
 
 def stokes_flow_resistance(sim, replica, body, u_wall, n_develop, n_samples=100, every=10):

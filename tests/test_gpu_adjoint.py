@@ -362,3 +362,49 @@ def test_gamma_calibration_recovers_a_known_friction():
     print(f"  calibrated gamma {g:.12f} in {it} iterations (J {J:.9e}, target {target:.9e})",
           flush=True)
     assert abs(g - 0.5) < 1e-9 and it <= 8
+
+
+def test_gamma_calibrated_to_a_hydrodynamic_radius():
+    """The workload-5 sphere (R = 4, 401 beads, fixed) in a 64^3 box whose fluid starts at
+    u0 = 0.01 and decays: gamma such that the friction over steps 800-1000, measured from the
+    drag history with the fluid's momentum bookkeeping, is Hasimoto's friction of a sphere of
+    hydrodynamic radius R + 0.2 (Newton with the reverse pass's slope).  Then forward runs with
+    that gamma in boxes of 48 and 80 (windows scaled with L^2, the flow's development time):
+    the Hasimoto-corrected radius is the target there too, to 2 %: the calibration fixed a
+    property of the raspberry, not of the box."""
+    from paper_1604_01829_amd import analysis as AN
+    from paper_1604_01829_amd import lbrb
+    wl5 = W.workload(5)
+    body = wl5["replicas"][0]["bodies"][0]
+    R, u0, eta, rho0 = 4.0, 0.01, 1.0 / 6.0, 1.0
+    window = (800, 1000)
+    target = R + 0.2
+
+    def builder(g):
+        return _config5_sim(wl5, "f64", g, None)
+
+    g, it, xi = lbrb.calibrate_gamma_to_radius(builder, 64, target, u0, rho0, eta, window,
+                                               gamma0=body["gamma"], tol=1e-12)
+    print(f"  calibrated gamma {g:.9f} in {it} Newton steps (friction {xi:.6f})", flush=True)
+    assert g > 0 and it <= 10
+    delta = body["pos"] - 32.0
+    radii = {}
+    for L in (48, 64, 80):
+        a, b = (window if L == 64 else
+                (round(window[0] * L * L / 64 ** 2), round(window[1] * L * L / 64 ** 2)))
+        params = lbrb.make_params("f64", u0=(u0, 0.0, 0.0), max_bodies=1,
+                                  max_beads=len(body["offsets"]))
+        sim = lbrb.Simulation(params, lbrb.make_replicas([((L, L, L), 1)]))
+        sim.add_body(0, body["offsets"], 1.0, (1, 1, 1), L / 2 + delta, gamma=g, fixed=True)
+        sim.set_graph_steps(0)
+        drag = []
+        for _ in range(b):
+            sim.step(1)
+            drag.append(sim.observables(0)[1][0]["force"][0])
+        sim.close()
+        xi_L = AN.decay_friction(drag, u0, rho0, L ** 3, (a, b))
+        radii[L] = AN.hasimoto_radius(xi_L, L, eta)
+        print(f"  L={L}: window {a}-{b}, friction {xi_L:.6f}, R_h {radii[L]:.6f}", flush=True)
+    assert abs(radii[64] - target) <= 1e-8 * target
+    for L in (48, 80):
+        assert abs(radii[L] - target) <= 0.02 * target

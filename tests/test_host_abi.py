@@ -202,3 +202,21 @@ def test_spread_fixed_point_words_hold_the_worst_case():
     exact = sum(Fraction(float(v)) for v in vals)
     got = Fraction(total_hi, 2 ** 56) + Fraction(total_lo, 2 ** 104)
     assert abs(float(got - exact)) <= len(vals) * 2.0 ** -104
+
+
+def test_decay_friction_condition_is_linear_in_the_drags():
+    """sum_m c_m F(m) - t equals sum_W F - xi sum_W U for any drag history (U from the fluid's
+    momentum bookkeeping), so a zero of the one is a zero of the other; Hasimoto's friction and
+    radius invert each other."""
+    from paper_1604_01829_amd import analysis as AN
+    rng = np.random.default_rng(3)
+    N, u0, rho0, window, T = 4096, 0.01, 1.0, (30, 50), 50
+    F = rng.uniform(0.0, 0.02, T)
+    xi = 7.3
+    c, t = AN.decay_friction_weights(xi, u0, rho0, N, window, T)
+    U = u0 - np.cumsum(F) / (rho0 * N)
+    direct = F[29:50].sum() - xi * U[29:50].sum()
+    assert abs((c @ F - t) - direct) <= 1e-12 * (abs(direct) + F.sum())
+    assert abs(AN.decay_friction(F, u0, rho0, N, window) - F[29:50].sum() / U[29:50].sum()) < 1e-12
+    for R, L in ((2.0, 16), (4.2, 64), (1.5, 10)):
+        assert abs(AN.hasimoto_radius(AN.hasimoto_friction(R, L, 1 / 6), L, 1 / 6) - R) < 1e-9
