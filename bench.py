@@ -48,7 +48,7 @@ NAMES = {2: "pore 128x128x256 (radius 40, 1,286,144 fluid nodes), 32 raspberry s
          3: "256^3 periodic box, 16 raspberry ellipsoids (gamma 1/6), thermal kT=4e-5",
          4: "batch of 512 uneven pore replicas (cubic sides from {32,40,48,56,64}, pore radius "
             "0.4 side along z), one raspberry ellipsoid each (aspect 1-4, gamma 1/6), thermal "
-            "kT=4e-5, independent Philox seeds, one flat tile list, 100-step HIP-graph replays"}
+            "kT=4e-5, independent Philox seeds, one flat tile list"}
 
 
 def parse():

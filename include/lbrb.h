@@ -267,10 +267,19 @@ int rb_bead_forces(lb_ctx* ctx, int32_t replica, int32_t body_id, double* host_o
  * (19*nx*ny*nz values, zeros on boundary nodes), into a device array.                    */
 int lb_export_populations(lb_ctx* ctx, int32_t replica, double* dev_out);
 
+/* Fault injection, for tests of the failure detection (an aid of the library, not a step of
+ * the method): population i (0..18) of the fluid node (x, y, z) of one replica, in the current
+ * state, becomes a quiet NaN.  The NaN spreads with the next steps, lb_observables then
+ * returns LB_ERR_UNSTABLE, and lb_load_state of an earlier checkpoint recovers the run.
+ * Synchronises the stream.  LB_ERR_ARG for a node outside the box, a boundary node or i out
+ * of range.                                                                                */
+int lb_inject_nan(lb_ctx* ctx, int32_t replica, int32_t x, int32_t y, int32_t z, int32_t i);
+
 /* Checkpointing: the complete dynamic state (populations, bodies, step) in bytes that a
  * later lb_load_state of a context with the same parameters, boxes, masks, wall velocities
- * and bodies restores bit for bit.  dev_buf may be NULL to query the size: *bytes
- * receives it.                                                                            */
+ * and bodies restores bit for bit (and clears a spread-force overflow reported since, which
+ * belongs to the run it replaces).  dev_buf may be NULL to query the size: *bytes receives
+ * it.                                                                                      */
 int lb_save_state(lb_ctx* ctx, void* dev_buf, size_t* bytes);
 int lb_load_state(lb_ctx* ctx, const void* dev_buf, size_t bytes);
 

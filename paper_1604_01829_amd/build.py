@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbrb.so")
 SOURCES = [os.path.join(HERE, "csrc", n)
            for n in ("lbrb_kernels.hip", "lbrb_adjoint.hip", "lbrb_walls.hip", "lbrb_analysis.hip",
-                     "lbrb_construct.hip", "lbrb_noalloc.hip", "lbrb_api.cpp")]
+                     "lbrb_construct.hip", "lbrb_noalloc.hip", "lbrb_plan.cpp", "lbrb_api.cpp")]
 ARCH = os.environ.get("LBRB_ARCH", "gfx950")
 
 
@@ -30,7 +30,8 @@ def build(verbose: bool = False, extra=()) -> str:
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
            "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"),
-           "-o", out] + list(extra) + SOURCES
+           "-o", out] + list(extra) + SOURCES + [
+               "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

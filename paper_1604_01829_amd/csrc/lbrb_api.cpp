@@ -5,12 +5,14 @@
 // of many steps and the per-kernel event timing.  Every step runs on the caller's stream;
 // graphs are captured on a private stream (default priority) and replayed on the caller's.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <new>
@@ -19,6 +21,7 @@
 
 #include "../../include/lbrb.h"
 #include "lbrb_layout.h"
+#include "lbrb_plan.h"
 #include "lbrb_walls.h"
 #include "lbrb_analysis.h"
 
@@ -36,7 +39,15 @@ constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;
 constexpr uint64_t kStateMagic = 0x4C42524253544154ull;  // "LBRBSTAT"
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-int64_t pad_nodes(int64_t n) { return (n + kNodeBlock - 1) / kNodeBlock * kNodeBlock; }
+
+// roctx range on the calling thread for the lifetime of the object (seen by rocprofv3
+// --marker-trace; a no-op without a profiler)
+struct Marker {
+    explicit Marker(const char* msg) { roctxRangePushA(msg); }
+    ~Marker() { roctxRangePop(); }
+    Marker(const Marker&) = delete;
+    Marker& operator=(const Marker&) = delete;
+};
 
 struct Plan {
     int64_t N = 0;            // padded total node count (stride between populations)
@@ -52,11 +63,6 @@ struct Plan {
         off_bead_torque, off_partials, off_links, off_ev, off_wrep, off_rep_bodies,
         off_nb_start, off_nb_sites, off_near, off_wca_ft, total;
 };
-
-constexpr int kMaxCellsPerAxis = 32;   // WCA coarse grid: cells per axis at most
-constexpr double kFineCell = 2.0;      // WCA fine flag grid: cell width at most
-int cells_per_axis_cap(int n) { return std::min(n, kMaxCellsPerAxis); }
-int fine_per_axis(int n) { return (int)std::ceil(n / kFineCell); }
 
 bool valid_params(const lb_params* p)
 {
@@ -509,32 +515,7 @@ void rebuild_tiles(lb_ctx* c)
         H.group = R.masked ? 1 : 0;
         std::vector<NodeTile>& T = c->tiles[H.group];
         H.tile0 = (int32_t)T.size();
-        const int64_t n = R.n_fluid;
-        int row = R.row_base;  // first row of the replica (masked)
-        int last_row = row;
-        if (R.masked) {
-            // rows of this replica are rows[row_base .. row_base + n_rows)
-            int64_t nr = 0;
-            for (int64_t k = 0; k < (int64_t)R.ny * R.nz; ++k)
-                if (c->rowinfo[R.row_base + k].len > 0) ++nr;
-            last_row = R.row_base + (int)nr - 1;
-        }
-        for (int64_t b = 0; b < n; b += kNodeBlock) {
-            NodeTile t{};
-            t.replica = r;
-            t.begin = b;
-            t.count = (int32_t)std::min<int64_t>(kNodeBlock, n - b);
-            const int64_t e = b + t.count - 1;   // last local index of the tile
-            if (R.masked) {
-                while (row < last_row && c->rows[row + 1].start <= b) ++row;
-                int rh = row;
-                while (rh < last_row && c->rows[rh + 1].start <= e) ++rh;
-                t.row_lo = row;
-                t.row_hi = rh;
-            }
-            t.gt = (int32_t)((R.base + b) >> kPopBlockLog);
-            T.push_back(t);
-        }
+        append_tiles(R, r, c->rows.data(), c->rowinfo.data(), T);
         H.n_tiles = (int32_t)T.size() - H.tile0;
     }
 }
@@ -615,45 +596,6 @@ int init_fluid(lb_ctx* c, int replica)
     return LB_OK;
 }
 
-// Moving-wall links of one replica: every fluid node x and direction i whose neighbour
-// x - c_i (periodic) is a boundary node of a wall k with c_i . u_k != 0.  info holds the
-// replica's (start, xlo, len) per (y,z) row, mask its wall ids, uwall 3 velocities per id.
-std::vector<WallLink> build_links(const ReplicaDesc& R, const uint8_t* mask,
-                                  const RowDesc* info, const std::vector<double>& uwall,
-                                  double rho0)
-{
-    std::vector<WallLink> out;
-    if (!mask || uwall.empty()) return out;
-    const int nx = R.nx, ny = R.ny, nz = R.nz;
-    auto wrapi = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
-    for (int z = 0; z < nz; ++z)
-        for (int y = 0; y < ny; ++y) {
-            const RowDesc& row = info[(size_t)y + (size_t)ny * z];
-            for (int x = row.xlo; x < row.xlo + row.len; ++x) {
-                if (mask[x + (size_t)nx * (y + (size_t)ny * z)]) continue;   // a hole
-                for (int i = 1; i < Q; ++i) {
-                    const int bx = wrapi(x - cx_of(i), nx), by = wrapi(y - cy_of(i), ny),
-                              bz = wrapi(z - cz_of(i), nz);
-                    const uint8_t k = mask[bx + (size_t)nx * (by + (size_t)ny * bz)];
-                    if (!k) continue;
-                    const double* u = &uwall[3 * (size_t)k];
-                    const double cu = cx_of(i) * u[0] + cy_of(i) * u[1] + cz_of(i) * u[2];
-                    if (cu == 0.0) continue;
-                    WallLink L{};
-                    L.g = R.base + row.start + (x - row.xlo);
-                    L.pop = opposite_of(i);
-                    L.delta = 6.0 * weight_of(i) * rho0 * cu;
-                    out.push_back(L);
-                }
-            }
-        }
-    // in storage order of the slots they update
-    std::sort(out.begin(), out.end(), [](const WallLink& a, const WallLink& b) {
-        return pop_at(a.pop, a.g) < pop_at(b.pop, b.g);
-    });
-    return out;
-}
-
 int64_t links_without(const lb_ctx* c, int32_t replica)
 {
     int64_t n = 0;
@@ -677,27 +619,6 @@ int upload_links(lb_ctx* c)
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     return LB_OK;
-}
-
-// Morton (Z-order) ranking of body-frame offsets on a half-lattice-unit grid
-std::vector<int32_t> spatial_order(const double* offs, int32_t n)
-{
-    double lo[3] = {offs[0], offs[1], offs[2]};
-    for (int32_t k = 1; k < n; ++k)
-        for (int a = 0; a < 3; ++a) lo[a] = std::min(lo[a], offs[3 * k + a]);
-    std::vector<uint64_t> key(n);
-    for (int32_t k = 0; k < n; ++k) {
-        uint64_t m = 0;
-        for (int a = 0; a < 3; ++a) {
-            const uint64_t q = (uint64_t)std::min(2097151.0, std::floor((offs[3 * k + a] - lo[a]) * 2.0));
-            for (int bit = 0; bit < 21; ++bit) m |= ((q >> bit) & 1ull) << (3 * bit + a);
-        }
-        key[k] = m;
-    }
-    std::vector<int32_t> order(n);
-    for (int32_t k = 0; k < n; ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return key[x] < key[y]; });
-    return order;
 }
 
 BodyBox body_box(const ReplicaDesc& R)
@@ -726,7 +647,6 @@ bool check_replica(lb_ctx* c, int32_t r)
 // whose centre has a site within the range plus half the cell diagonal.
 int build_wca(lb_ctx* c)
 {
-    const double cut = std::pow(2.0, 1.0 / 6.0);
     // bodies: excluded-volume ranges
     std::vector<EvSite> ev;
     for (int32_t b = 0; b < c->n_bodies; ++b) {
@@ -746,10 +666,11 @@ int build_wca(lb_ctx* c)
     }
     // replicas: body lists and site grids
     std::vector<WcaRep> wr(c->n_rep);
-    std::vector<int32_t> rep_bodies, nb_start;
-    std::vector<WallSite> nb_sites;   // each coarse cell's neighbourhood, the records in place
-    std::vector<WallSite> sites;
-    std::vector<uint8_t> near;
+    std::vector<int32_t> rep_bodies;
+    WcaTables wt;
+    const std::vector<int32_t>& nb_start = wt.nb_start;
+    const std::vector<WallSite>& nb_sites = wt.nb_sites;
+    const std::vector<uint8_t>& near = wt.near;
     for (int r = 0; r < c->n_rep; ++r) {
         const ReplicaDesc& R = c->reps[r];
         const ReplicaHost& H = c->rh[r];
@@ -763,102 +684,8 @@ int build_wca(lb_ctx* c)
             if (c->bodies0[b].n_ev > 0) ev_r = std::max(ev_r, c->bodies0[b].ev_radius);
         }
         const int dims[3] = {R.nx, R.ny, R.nz};
-        // the largest range of a pair in this replica: body-body and body-site
-        double range = ev_r >= 0.0 ? cut * 2.0 * ev_r : 0.0;
-        double site_r = -1.0;
-        for (const WallSite& w : H.sites) site_r = std::max(site_r, w.radius);
-        if (ev_r >= 0.0 && site_r >= 0.0) range = std::max(range, cut * (ev_r + site_r));
-        for (int a = 0; a < 3; ++a)
-            if (ev_r >= 0.0 && 2.0 * range > dims[a])
-                return fail(c, LB_ERR_ARG, "a box side is shorter than twice the WCA range");
-        if (H.sites.empty() || ev_r < 0.0) continue;   // no grid needed
-        // coarse grid, sites binned by cell (the kernel's cell rule)
-        int nc[3], ng[3];
-        for (int a = 0; a < 3; ++a) {
-            const int fit = (int)std::floor(dims[a] / (range * (1.0 + 1e-6)));
-            nc[a] = std::max(1, std::min(fit, cells_per_axis_cap(dims[a])));
-            W.cw[a] = (double)dims[a] / nc[a];
-            ng[a] = fine_per_axis(dims[a]);
-            W.fw[a] = (double)dims[a] / ng[a];
-        }
-        W.cx = nc[0]; W.cy = nc[1]; W.cz = nc[2];
-        W.gx = ng[0]; W.gy = ng[1]; W.gz = ng[2];
-        W.cell0 = (int32_t)nb_start.size();
-        W.fine0 = (int32_t)near.size();
-        auto cell_idx = [](double x, double L, double w, int n) {
-            const double xw = x - L * std::floor(x / L);
-            const int q = (int)(xw / w);
-            return q < 0 ? 0 : (q >= n ? n - 1 : q);
-        };
-        const int ncell = nc[0] * nc[1] * nc[2];
-        const int32_t site0 = (int32_t)sites.size();
-        std::vector<std::vector<int32_t>> bins(ncell);
-        {
-            std::vector<std::vector<WallSite>> sb(ncell);
-            for (const WallSite& w : H.sites) {
-                const int k = cell_idx(w.p[0], dims[0], W.cw[0], nc[0]) +
-                              nc[0] * (cell_idx(w.p[1], dims[1], W.cw[1], nc[1]) +
-                                       nc[1] * cell_idx(w.p[2], dims[2], W.cw[2], nc[2]));
-                sb[k].push_back(w);
-            }
-            for (int k = 0; k < ncell; ++k)
-                for (const WallSite& w : sb[k]) {
-                    bins[k].push_back((int32_t)sites.size());
-                    sites.push_back(w);
-                }
-        }
-        // neighbourhood lists: the distinct cells c-1, c, c+1 along each axis (all cells of an
-        // axis with fewer than three)
-        auto span = [](int ci, int n, int& first, int& count) {
-            if (n >= 3) { first = ci == 0 ? n - 1 : ci - 1; count = 3; }
-            else { first = 0; count = n; }
-        };
-        for (int z = 0; z < nc[2]; ++z)
-            for (int y = 0; y < nc[1]; ++y)
-                for (int x = 0; x < nc[0]; ++x) {
-                    nb_start.push_back((int32_t)nb_sites.size());
-                    int f0, n0, f1, n1, f2, n2;
-                    span(x, nc[0], f0, n0);
-                    span(y, nc[1], f1, n1);
-                    span(z, nc[2], f2, n2);
-                    for (int iz = 0; iz < n2; ++iz)
-                        for (int iy = 0; iy < n1; ++iy)
-                            for (int ix = 0; ix < n0; ++ix) {
-                                const auto& bin = bins[(f0 + ix) % nc[0] +
-                                                       nc[0] * ((f1 + iy) % nc[1] +
-                                                                nc[1] * ((f2 + iz) % nc[2]))];
-                                for (int32_t i : bin) nb_sites.push_back(sites[i]);
-                            }
-                }
-        nb_start.push_back((int32_t)nb_sites.size());
-        // fine flags: cells whose centre lies within range + half diagonal of a site
-        const size_t nfine = (size_t)ng[0] * ng[1] * ng[2];
-        std::vector<uint8_t> fl(nfine, 0);
-        const double hd = 0.5 * std::sqrt(W.fw[0] * W.fw[0] + W.fw[1] * W.fw[1] + W.fw[2] * W.fw[2]);
-        for (size_t k = (size_t)site0; k < sites.size(); ++k) {
-            const WallSite& w = sites[k];
-            const double reach = cut * (ev_r + w.radius) + hd + 1e-6;
-            int lo[3], cnt[3];
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = (int)std::floor((w.p[a] - reach) / W.fw[a]) - 1;
-                cnt[a] = std::min(ng[a], (int)std::ceil(2.0 * reach / W.fw[a]) + 4);
-            }
-            for (int iz = 0; iz < cnt[2]; ++iz)
-                for (int iy = 0; iy < cnt[1]; ++iy)
-                    for (int ix = 0; ix < cnt[0]; ++ix) {
-                        const int g[3] = {lo[0] + ix, lo[1] + iy, lo[2] + iz};
-                        double d2 = 0.0;
-                        int gi[3];
-                        for (int a = 0; a < 3; ++a) {
-                            gi[a] = ((g[a] % ng[a]) + ng[a]) % ng[a];
-                            double dd = (gi[a] + 0.5) * W.fw[a] - w.p[a];
-                            dd -= dims[a] * std::round(dd / dims[a]);
-                            d2 += dd * dd;
-                        }
-                        if (d2 <= reach * reach) fl[gi[0] + (size_t)ng[0] * (gi[1] + (size_t)ng[1] * gi[2])] = 1;
-                    }
-        }
-        near.insert(near.end(), fl.begin(), fl.end());
+        if (!wca_grid(dims, ev_r, H.sites, W, wt))
+            return fail(c, LB_ERR_ARG, "a box side is shorter than twice the WCA range");
     }
     if ((int64_t)nb_start.size() > c->plan.cells_cap || (int64_t)near.size() > c->plan.fine_cap ||
         (int64_t)nb_sites.size() > 27 * c->plan.site_cap)
@@ -1268,39 +1095,13 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
     if (c->step != 0) return fail(c, LB_ERR_STATE, "masks can only be set before the first step");
     ReplicaDesc& R = c->reps[replica];
     const int nx = R.nx, ny = R.ny, nz = R.nz;
-    bool any_solid = false;
-    std::vector<RowDesc> rows;
-    std::vector<RowDesc> info((size_t)ny * nz, RowDesc{0, 0, 0, 0});
-    std::vector<uint8_t> holes;   // per stored node: the wall id of a hole, else 0
-    int64_t start = 0, n_holes = 0;
-    for (int z = 0; z < nz; ++z)
-        for (int y = 0; y < ny; ++y) {
-            const uint8_t* m = mask + (size_t)nx * (y + (size_t)ny * z);
-            int xlo = -1, xhi = -1;
-            for (int x = 0; x < nx; ++x) {
-                if (m[x]) { any_solid = true; continue; }
-                if (xlo < 0) xlo = x;
-                xhi = x;
-            }
-            if (xlo < 0) continue;
-            // the span from the first to the last fluid node; boundary nodes inside it are holes
-            RowDesc d{};
-            d.start = (int32_t)start;
-            d.xlo = xlo;
-            d.len = xhi - xlo + 1;
-            d.yz = y | (z << 16);
-            info[(size_t)y + (size_t)ny * z] = d;
-            rows.push_back(d);
-            for (int x = xlo; x <= xhi; ++x) {
-                holes.push_back(m[x]);
-                if (m[x]) ++n_holes;
-            }
-            start += d.len;
-        }
+    MaskRows m = compress_mask(nx, ny, nz, mask);
+    const bool any_solid = m.any_solid;
+    const int64_t n_holes = m.n_holes;
     // links of the replica's moving walls under the new mask, checked before anything changes
     ReplicaHost& H = c->rh[replica];
     std::vector<WallLink> links;
-    if (any_solid) links = build_links(R, mask, info.data(), H.uwall, c->p.rho0);
+    if (any_solid) links = build_links(R, mask, m.info.data(), H.uwall, c->p.rho0);
     if (links_without(c, replica) + (int64_t)links.size() > c->plan.link_cap)
         return fail(c, LB_ERR_CAPACITY, "moving-wall links exceed max_wall_links");
     // rows of this replica go to rows[row_base ...]; clear the old ones first
@@ -1310,13 +1111,13 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
     }
     HIP_TRY(c, hipMemsetAsync(c->hole + R.base, 0, (size_t)pad_nodes(R.n_nodes), c->stream));
     if (any_solid) {
-        for (size_t k = 0; k < rows.size(); ++k) c->rows[R.row_base + k] = rows[k];
-        for (int64_t k = 0; k < (int64_t)ny * nz; ++k) c->rowinfo[R.row_base + k] = info[k];
+        for (size_t k = 0; k < m.rows.size(); ++k) c->rows[R.row_base + k] = m.rows[k];
+        for (int64_t k = 0; k < (int64_t)ny * nz; ++k) c->rowinfo[R.row_base + k] = m.info[k];
         R.masked = n_holes > 0 ? 2 : 1;
-        R.n_fluid = start;                       // stored nodes: fluid nodes and holes
+        R.n_fluid = m.stored;                    // stored nodes: fluid nodes and holes
         H.mask.assign(mask, mask + (size_t)nx * ny * nz);
         if (n_holes > 0)
-            HIP_TRY(c, hipMemcpyAsync(c->hole + R.base, holes.data(), holes.size(),
+            HIP_TRY(c, hipMemcpyAsync(c->hole + R.base, m.holes.data(), m.holes.size(),
                                       hipMemcpyHostToDevice, c->stream));
     } else {
         R.masked = 0;
@@ -1516,11 +1317,16 @@ int lb_rb_step(lb_ctx* c, int32_t n_steps)
     if (rc != LB_OK) return rc;
     int32_t left = n_steps;
     const bool use_graph = c->graph_steps > 0 && !c->timing;
+    char name[64];
     while (use_graph && left >= c->graph_steps) {
         if (!c->gexec[c->cur]) {
             rc = build_graph(c, c->cur);
             if (rc != LB_OK) return rc;
         }
+        // one range per replay: the steps it enqueues
+        std::snprintf(name, sizeof name, "lb_rb_step %lld-%lld", (long long)c->step,
+                      (long long)(c->step + c->graph_steps - 1));
+        Marker m(name);
         launch_set_step(&c->hdr->step, c->step, c->stream);
         HIP_TRY(c, hipGraphLaunch(c->gexec[c->cur], c->stream));
         c->step += c->graph_steps;
@@ -1528,6 +1334,8 @@ int lb_rb_step(lb_ctx* c, int32_t n_steps)
         left -= c->graph_steps;
     }
     for (; left > 0; --left) {
+        std::snprintf(name, sizeof name, "lb_rb_step %lld", (long long)c->step);
+        Marker m(name);
         HIP_TRY(c, is_f32(c) ? enqueue_step<float>(c, c->stream, c->cur, nullptr, c->step, false)
                              : enqueue_step<double>(c, c->stream, c->cur, nullptr, c->step, false));
         c->cur ^= 1;
@@ -1653,6 +1461,34 @@ int lb_export_populations(lb_ctx* c, int32_t replica, double* dev_out)
     return LB_OK;
 }
 
+int lb_inject_nan(lb_ctx* c, int32_t replica, int32_t x, int32_t y, int32_t z, int32_t i)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!check_replica(c, replica)) return fail(c, LB_ERR_ARG, "bad replica");
+    const ReplicaDesc& R = c->reps[replica];
+    if (x < 0 || x >= R.nx || y < 0 || y >= R.ny || z < 0 || z >= R.nz || i < 0 || i >= Q)
+        return fail(c, LB_ERR_ARG, "node or population out of range");
+    int64_t local = x + (int64_t)R.nx * (y + (int64_t)R.ny * z);
+    if (R.masked) {
+        const RowDesc& d = c->rowinfo[R.row_base + y + (int64_t)R.ny * z];
+        const ReplicaHost& H = c->rh[replica];
+        if (x < d.xlo || x >= d.xlo + d.len || H.mask[local] != 0)
+            return fail(c, LB_ERR_ARG, "not a fluid node");
+        local = d.start + (x - d.xlo);
+    }
+    const int64_t slot = pop_at(i, R.base + local);
+    static const float nan32 = std::numeric_limits<float>::quiet_NaN();
+    static const double nan64 = std::numeric_limits<double>::quiet_NaN();
+    if (is_f32(c))
+        HIP_TRY(c, hipMemcpyAsync((float*)c->f[c->cur] + slot, &nan32, sizeof(float),
+                                  hipMemcpyHostToDevice, c->stream));
+    else
+        HIP_TRY(c, hipMemcpyAsync((double*)c->f[c->cur] + slot, &nan64, sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
 int lb_save_state(lb_ctx* c, void* dev_buf, size_t* bytes)
 {
     if (!c || !bytes) return LB_ERR_ARG;
@@ -1699,6 +1535,8 @@ int lb_load_state(lb_ctx* c, const void* dev_buf, size_t bytes)
                                   hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->f[c->cur], d + head + bod, pops, hipMemcpyDeviceToDevice,
                               c->stream));
+    // a spread-force overflow flagged since belongs to the run being replaced
+    HIP_TRY(c, hipMemsetAsync(&c->hdr->err_flags, 0, sizeof(uint32_t), c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->step = (int64_t)h[1];
     c->pose_stale = true;
@@ -1735,6 +1573,7 @@ int lb_autotune(lb_ctx* c, int32_t repeats)
         }
     }
     Tuning t;
+    Marker m("lb_autotune");
     const int rc = is_f32(c) ? autotune_t<float>(c, repeats > 0 ? repeats : 3, t)
                              : autotune_t<double>(c, repeats > 0 ? repeats : 3, t);
     destroy_graphs(c);
@@ -1880,6 +1719,7 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
         if (rc != LB_OK) return rc;
     }
     const int parity = (int)(c->step & 1);
+    Marker m("lb_rb_adjoint");
     const int rc = is_f32(c) ? run_adjoint<float>(c, n_steps, checkpoint_every, ws, ap)
                              : run_adjoint<double>(c, n_steps, checkpoint_every, ws, ap);
     if (rc != LB_OK) return rc;

@@ -31,14 +31,13 @@ LB_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 # every symbol declared in include/lbrb.h
 EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wall_velocity",
             "rb_add_raspberry", "rb_set_excluded_volume", "lb_add_wall_sites", "rb_record_poses",
-            "lb_traj_lab_frame", "lb_traj_body_frame", "lb_traj_pore_frame",
-            "lb_traj_msd", "lb_traj_rotation_msd", "lb_traj_binned_msd", "rb_relax_shells",
-            "lb_rb_step", "lb_observables", "lb_body_count", "rb_bead_forces",
-            "lb_export_populations", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
-            "lb_set_timing", "lb_kernel_times", "lb_set_store_policy",
-            "lb_autotune", "lb_get_tuning", "lb_set_tuning",
-            "lb_adjoint_workspace_bytes", "lb_rb_adjoint", "lb_rb_adjoint_noalloc",
-            "lb_node_counts", "lb_destroy", "lb_last_error"]
+            "lb_traj_lab_frame", "lb_traj_body_frame", "lb_traj_pore_frame", "lb_traj_msd",
+            "lb_traj_rotation_msd", "lb_traj_binned_msd", "rb_relax_shells", "lb_rb_step",
+            "lb_observables", "lb_body_count", "rb_bead_forces", "lb_export_populations",
+            "lb_inject_nan", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
+            "lb_set_timing", "lb_kernel_times", "lb_set_store_policy", "lb_autotune",
+            "lb_get_tuning", "lb_set_tuning", "lb_adjoint_workspace_bytes", "lb_rb_adjoint",
+            "lb_rb_adjoint_noalloc", "lb_node_counts", "lb_destroy", "lb_last_error"]
 
 
 class lb_replica(ctypes.Structure):
@@ -143,6 +142,8 @@ def library():
     L.rb_bead_forces.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32, _D, ctypes.c_int32]
     L.lb_export_populations.restype = ctypes.c_int
     L.lb_export_populations.argtypes = [_VP, ctypes.c_int32, _VP]
+    L.lb_inject_nan.restype = ctypes.c_int
+    L.lb_inject_nan.argtypes = [_VP] + [ctypes.c_int32] * 5
     L.lb_save_state.restype = ctypes.c_int
     L.lb_save_state.argtypes = [_VP, _VP, ctypes.POINTER(ctypes.c_size_t)]
     L.lb_load_state.restype = ctypes.c_int
@@ -499,6 +500,11 @@ class Simulation:
         _check(self.ctx, library().rb_bead_forces(self.ctx, replica, body, _dp(out), n),
                "rb_bead_forces")
         return out.reshape(n, 3)
+
+    def inject_nan(self, replica, x, y, z, i):
+        """Fault injection for tests: population i of fluid node (x, y, z) becomes NaN."""
+        _check(self.ctx, library().lb_inject_nan(self.ctx, int(replica), int(x), int(y), int(z),
+                                                 int(i)), "lb_inject_nan")
 
     def save_state(self):
         torch = self.torch

@@ -242,3 +242,48 @@ def test_saved_state_does_not_depend_on_the_buffer():
         out.append(buf.cpu().numpy())
     assert np.array_equal(out[0], out[1])
     sim.close()
+
+
+@pytest.mark.parametrize("case", ["pore_f32", "pore_f64", "dense_f32"])
+def test_injected_nan_is_reported_and_a_checkpoint_restores_the_run_bitwise(case):
+    """Failure detection and recovery: a NaN written into one population (lb_inject_nan)
+    spreads, lb_observables reports LB_ERR_UNSTABLE, and loading the checkpoint taken before
+    it reruns the same steps bit for bit (graph replays and eager steps mixed)."""
+    from tests.test_gpu_parity import pore_case
+    precision = case[-3:]
+    if case.startswith("pore"):
+        wl = pore_case(precision, 4e-5)
+    else:
+        wl = dict(name="dense", precision=precision, steps=10,
+                  params=W.default_params(kT=4e-5, g_ext=(1e-6, 0.0, -2e-6)),
+                  replicas=[dict(shape=(20, 18, 16), seed=4, mask=None, bodies=[])])
+    sim = gpu_from_workload(wl)
+    sim.set_graph_steps(4)
+    sim.step(6)
+    ck = sim.save_state().clone()
+    sim.step(11)
+    want = sim.save_state().cpu().numpy()
+    assert sim.observables(0, check=False)[3] == lbrb.LB_OK
+    mask = wl["replicas"][0]["mask"]
+    nx, ny, nz = wl["replicas"][0]["shape"]
+    x, y, z = nx // 2, ny // 2, nz // 2
+    assert mask is None or mask[z, y, x] == 0
+    sim.load_state(ck)
+    sim.inject_nan(0, x, y, z, 7)
+    sim.step(3)
+    t, _, _, rc = sim.observables(0, check=False)
+    assert rc == lbrb.LB_ERR_UNSTABLE and not t["finite"]
+    sim.load_state(ck)
+    assert sim.observables(0, check=False)[3] == lbrb.LB_OK
+    sim.step(11)
+    assert np.array_equal(sim.save_state().cpu().numpy(), want)
+    # a boundary node, a node outside the box and a population out of range are refused
+    bad = [(nx, 0, 0, 0), (0, 0, 0, 19), (0, 0, -1, 0)]
+    if mask is not None:
+        zz, yy, xx = np.argwhere(mask != 0)[0]
+        bad.append((int(xx), int(yy), int(zz), 1))
+    for args in bad:
+        with pytest.raises(lbrb.LBError) as e:
+            sim.inject_nan(0, *args)
+        assert e.value.code == lbrb.LB_ERR_ARG
+    sim.close()
