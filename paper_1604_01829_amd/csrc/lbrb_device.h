@@ -34,6 +34,25 @@ __device__ __forceinline__ BeadRec load_record(const BeadRec* p)
     return B;
 }
 
+// A bead record spread over the 8 lanes of its bead: lane j of the group holds bytes
+// 16j .. 16j+15 (one coalesced 16-byte load per lane), and a field is gathered from its lane
+// by a shuffle where it is used, so no lane keeps the whole record in registers.  Every lane
+// of the group must take part in each gather (uniform control flow).
+template <int K>   // 32-bit word K (0..31) of the record
+__device__ __forceinline__ uint32_t rec_word(const uint4& q)
+{
+    static_assert(K >= 0 && K < 32, "a bead record has 32 words");
+    const uint32_t v = (K & 3) == 0 ? q.x : (K & 3) == 1 ? q.y : (K & 3) == 2 ? q.z : q.w;
+    return (uint32_t)__shfl((int)v, K >> 2, 8);
+}
+template <int K>   // the double at word K
+__device__ __forceinline__ double rec_f64(const uint4& q)
+{
+    const uint64_t lo = rec_word<K>(q), hi = rec_word<K + 1>(q);
+    return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+#define LBRB_REC_WORD(field) ((int)(offsetof(BeadRec, field) / 4))
+
 __device__ __forceinline__ int64_t current_step(const int64_t* p, int64_t arg)
 {
     return (p ? *p : 0) + arg;

@@ -709,9 +709,18 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
     const int bead = tid >> 3, corner = tid & 7;
     const bool active = bead < c.n_beads;   // the 8 lanes of a bead share this
     const int64_t step = current_step(a.step_ptr, a.step_arg);
-    const BeadRec B = load_record(c.recs + (active ? bead : 0));
-    const double r[3] = {B.r[0], B.r[1], B.r[2]};
-    const int nx = B.nx, ny = B.ny, nz = B.nz;
+    // the record spread over the bead's 8 lanes; the geometry is gathered now, the dynamics
+    // after the stencil's populations are in
+    const uint4 rq = reinterpret_cast<const uint4*>(c.recs + (active ? bead : 0))[corner];
+    const double r[3] = {rec_f64<LBRB_REC_WORD(r[0])>(rq), rec_f64<LBRB_REC_WORD(r[1])>(rq),
+                         rec_f64<LBRB_REC_WORD(r[2])>(rq)};
+    const int nx = (int)rec_word<LBRB_REC_WORD(nx)>(rq);
+    const int ny = (int)rec_word<LBRB_REC_WORD(ny)>(rq);
+    const int nz = (int)rec_word<LBRB_REC_WORD(nz)>(rq);
+    const int masked = (int)rec_word<LBRB_REC_WORD(masked)>(rq);
+    const int row_base = (int)rec_word<LBRB_REC_WORD(row_base)>(rq);
+    const int64_t base = (int64_t)(((uint64_t)rec_word<LBRB_REC_WORD(base) + 1>(rq) << 32) |
+                                   rec_word<LBRB_REC_WORD(base)>(rq));
 
     // corner of the trilinear stencil handled by this lane
     double fr[3];
@@ -730,17 +739,17 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
     int64_t local = -1;
     Rows9 rw;
     if (active) {
-        if (B.masked) {
-            load_rows9(a.rowinfo, B.row_base, ny, nz, py, pz, rw);
+        if (masked) {
+            load_rows9(a.rowinfo, row_base, ny, nz, py, pz, rw);
             const int off = px - rw.lo[4];
             local = (unsigned)off < (unsigned)rw.ln[4] ? rw.st[4] + off : -1;
             // a hole is a boundary node: no velocity sampled, no force spread
-            if (B.masked == 2 && local >= 0 && a.hole[B.base + local] != 0) local = -1;
+            if (masked == 2 && local >= 0 && a.hole[base + local] != 0) local = -1;
         } else {
             local = px + (int64_t)nx * (py + (int64_t)ny * pz);
         }
     }
-    const int64_t g = B.base + local;
+    const int64_t g = base + local;
     __syncthreads();   // the table is cleared
 
     // claim the node's slot
@@ -758,12 +767,12 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
     // the owner pulls the node's populations (pre-collision of this step)
     if (owner) {
         Real d[Q];
-        if (B.masked) {
-            pull_rows<Real, 1>(a.src, B.base, nx, rw, px, local, d);
+        if (masked) {
+            pull_rows<Real, 1>(a.src, base, nx, rw, px, local, d);
         } else {
             ReplicaDesc R{};
             R.nx = nx; R.ny = ny; R.nz = nz;
-            R.base = B.base;
+            R.base = base;
             const RowDesc self{0, 0, nx, 0};
             pull<Real, false>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
         }
@@ -785,12 +794,16 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
     for (int m = 1; m < 8; m <<= 1)
         for (int ax = 0; ax < 3; ++ax) wu[ax] += __shfl_xor(wu[ax], m, 8);
 
+    const double gamma = rec_f64<LBRB_REC_WORD(gamma)>(rq);
+    const double v[3] = {rec_f64<LBRB_REC_WORD(v[0])>(rq), rec_f64<LBRB_REC_WORD(v[1])>(rq),
+                         rec_f64<LBRB_REC_WORD(v[2])>(rq)};
     double F[3];
-    for (int ax = 0; ax < 3; ++ax) F[ax] = -B.gamma * (B.v[ax] - wu[ax]);
+    for (int ax = 0; ax < 3; ++ax) F[ax] = -gamma * (v[ax] - wu[ax]);
     if (c.kT > 0.0) {
-        const U4 blk = noise_block((uint64_t)step, (uint32_t)B.noise_idx, 1u, c.md_step, B.key0,
-                                   B.key1);
-        const double amp = B.noise_amp;
+        const U4 blk = noise_block((uint64_t)step, rec_word<LBRB_REC_WORD(noise_idx)>(rq), 1u,
+                                   c.md_step, rec_word<LBRB_REC_WORD(key0)>(rq),
+                                   rec_word<LBRB_REC_WORD(key1)>(rq));
+        const double amp = rec_f64<LBRB_REC_WORD(noise_amp)>(rq);
         F[0] += amp * uniform16<double>(blk.x);
         F[1] += amp * uniform16<double>(blk.x >> 16);
         F[2] += amp * uniform16<double>(blk.y);
@@ -809,8 +822,9 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
         }
         if (overflow) atomicOr(&c.hdr->err_flags, 1u);
     }
+    const double dv[3] = {rec_f64<LBRB_REC_WORD(dv[0])>(rq), rec_f64<LBRB_REC_WORD(dv[1])>(rq),
+                          rec_f64<LBRB_REC_WORD(dv[2])>(rq)};
     if (active && corner == 0) {
-        const double* dv = B.dv;
         for (int ax = 0; ax < 3; ++ax) c.bead_force[3 * bead + ax] = F[ax];
         c.bead_torque[3 * bead + 0] = dv[1] * F[2] - dv[2] * F[1];
         c.bead_torque[3 * bead + 1] = dv[2] * F[0] - dv[0] * F[2];
@@ -832,9 +846,12 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
 // 8, so that the bead workgroups keep their XCD pattern) compute each body's WCA force and
 // torque for the same MD step instead (wca_block); they use the coupling's LDS.
 // Without it the kernel is compiled without that code (its registers stay those of the
-// coupling alone).
+// coupling alone).  In FP32 the LDS admits 6 workgroups per CU; the coupling alone fits the
+// 80 registers of 6 waves per SIMD without spilling, so it is compiled for that occupancy.
 template <typename Real, bool WCA>
-__global__ __launch_bounds__(kCoupleBlock) void couple_kernel(const StepArgs<Real> a,
+__global__ __launch_bounds__(kCoupleBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 && !WCA ? 6 : 1)))
+void couple_kernel(const StepArgs<Real> a,
                                                               const CoupleArgs c,
                                                               const BodyArgs ba, int n_wca)
 {
