@@ -309,8 +309,11 @@ int lb_set_store_policy(lb_ctx* ctx, int32_t policy);
  * GPU).  lb_autotune times the context's own node kernel over its own tiles for every
  * combination of node tiles per workgroup (1 or 4; 256 nodes each), a cap on the node
  * workgroups resident per compute unit (none, 6, 5, 4; by dynamic LDS) and the store kind
- * (ordinary or non-temporal; only the forced kind under LB_STORES_CACHED/STREAMING), and
- * keeps the fastest for the following steps if it beats the untuned settings by at least
+ * (ordinary or non-temporal when both population buffers exceed the 256 MB Infinity Cache;
+ * ordinary stores only when they fit in it, where the timed launches, which re-read an
+ * unchanged buffer, cannot see what non-temporal stores cost the next step's reads; only the
+ * forced kind under LB_STORES_CACHED/STREAMING): 16 or 8 settings.  It keeps the fastest
+ * for the following steps if it beats the untuned settings by at least
  * 1 % (else the untuned ones).  The timed launches leave the simulation state
  * unchanged (no spread force is consumed, no body is finished; they write the buffer the next
  * step overwrites).  Results are kept for the process per (GPU architecture, precision,

@@ -277,18 +277,24 @@ CollideParams<Real> collide_params(const lb_params& p)
     return cp;
 }
 
-// non-temporal population stores: forced by the policy, else the tuned choice (lb_autotune),
-// else once the populations the steps touch -- the fluid nodes of every replica, in both
+// whether the populations the steps touch -- the fluid nodes of every replica, in both
 // buffers -- exceed the Infinity Cache
+bool populations_exceed_cache(const lb_ctx* c)
+{
+    const double real = c->p.precision == LB_PRECISION_F32 ? 4.0 : 8.0;
+    double nodes = 0.0;
+    for (int r = 0; r < c->n_rep; ++r) nodes += (double)pad_nodes(c->reps[r].n_fluid);
+    return 2.0 * Q * real * nodes > kInfinityCacheBytes;
+}
+
+// non-temporal population stores: forced by the policy, else the tuned choice (lb_autotune),
+// else once the populations exceed the Infinity Cache
 bool streaming_stores(const lb_ctx* c)
 {
     if (c->store_policy == LB_STORES_CACHED) return false;
     if (c->store_policy == LB_STORES_STREAMING) return true;
     if (c->tune.tuned) return c->tune.streaming != 0;
-    const double real = c->p.precision == LB_PRECISION_F32 ? 4.0 : 8.0;
-    double nodes = 0.0;
-    for (int r = 0; r < c->n_rep; ++r) nodes += (double)pad_nodes(c->reps[r].n_fluid);
-    return 2.0 * Q * real * nodes > kInfinityCacheBytes;
+    return populations_exceed_cache(c);
 }
 
 // launch arguments of one tile group pulling from src and writing dst
@@ -932,8 +938,13 @@ int autotune_t(lb_ctx* c, int reps, Tuning& best)
     Tuning saved = c->tune;
     c->tune = Tuning{};
     const int32_t default_streaming = streaming_stores(c) ? 1 : 0;   // the untuned rule
+    // The timed launches read a buffer that stays unchanged, while a step reads what the step
+    // before wrote: with buffers that fit in the Infinity Cache, non-temporal stores would time
+    // faster here and run slower in the steps (their data bypasses the cache the next step
+    // reads from), so they are a candidate only for buffers larger than the cache.
+    const bool both_kinds = !fixed_stores && populations_exceed_cache(c);
     for (int st = 0; st < 2; ++st) {
-        if (fixed_stores && st != default_streaming) continue;
+        if (!both_kinds && st != default_streaming) continue;
         for (int per : {1, kWideTiles})
             for (int cap : {0, 6, 5, 4}) cands.push_back(TuneCand{per, cap, st});
     }

@@ -24,7 +24,8 @@ def test_autotune_leaves_the_state_and_results_unchanged():
     a.step(10)
     b.step(10)
     t = b.autotune(repeats=2)
-    assert t["tuned"] and t["candidates"] == 16
+    # small boxes: the populations fit in the Infinity Cache, so ordinary stores only
+    assert t["tuned"] and t["candidates"] == 8 and not t["streaming_stores"]
     assert t["node_us_tuned"] <= t["node_us_default"]
     assert np.array_equal(_state(a), _state(b))     # timing the settings changed nothing
     a.step(30)
@@ -35,6 +36,21 @@ def test_autotune_leaves_the_state_and_results_unchanged():
     assert c.autotune(repeats=0) == t
     for s in (a, b, c):
         s.close()
+
+
+def test_autotune_times_both_store_kinds_beyond_the_cache():
+    """A box whose two FP32 population buffers (2 x 0.8 GB) exceed the 256 MB Infinity Cache:
+    ordinary and non-temporal stores are both timed; the state stays unchanged."""
+    wl = dict(name="large", precision="f32", steps=4,
+              params=W.default_params(kT=4e-5, g_ext=(1e-6, 0.0, 0.0)),
+              replicas=[dict(shape=(256, 256, 80), seed=8, mask=None, bodies=[])])
+    a = gpu_from_workload(wl)
+    a.step(2)
+    before = _state(a)
+    t = a.autotune(repeats=1)
+    assert t["tuned"] and t["candidates"] == 16
+    assert np.array_equal(before, _state(a))
+    a.close()
 
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
