@@ -677,10 +677,14 @@ void launch_node_step(const StepArgs<Real>& a, bool masked, bool forces, const B
 // adds each sum to the node with one device atomic per word.  Integer sums do not depend on
 // their order, so the result is the same as one atomic per lane.
 
-// LDS of one coupling workgroup: the node hash table, the nodes' moments and the force sums
+// LDS of one coupling workgroup: the node hash table, the nodes' moments and the force sums.
+// A workgroup's lanes claim at most kCoupleBlock distinct nodes, so kCoupleBlock slots always
+// suffice; FP32 takes twice that (shorter probes), FP64 takes kCoupleBlock so that its larger
+// entries leave room for 4 instead of 3 workgroups per CU (the batch's FP64 coupling 248 ->
+// 236 us).
 template <typename Real>
 struct CoupleLds {
-    static constexpr int TS = 2 * kCoupleBlock;          // hash slots (power of two)
+    static constexpr int TS = (sizeof(Real) == 8 ? 1 : 2) * kCoupleBlock;   // power of two
     static constexpr int NW = sizeof(Real) == 8 ? 6 : 3; // fixed-point words per node
     unsigned long long key[TS];
     Real mom[4][TS];
