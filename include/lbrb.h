@@ -383,6 +383,14 @@ int lb_rb_adjoint_noalloc(lb_ctx* ctx, int32_t n_steps, int32_t checkpoint_every
 /* Node counts of one replica: all nodes and fluid nodes.                                  */
 int lb_node_counts(const lb_ctx* ctx, int32_t replica, int64_t* n_nodes, int64_t* n_fluid);
 
+/* Storage axis of a replica's rows (a layout choice of the library, not of the method):
+ * *axis = 0 when the fluid is stored in rows along x, 2 when lb_set_boundary_mask chose rows
+ * along z (the box's axes x and z exchanged in storage) because the mask's fluid runs are
+ * much longer along z, as in a pore along z.  Results do not depend on it; fields,
+ * populations and positions are always in the box's own coordinates.  LB_ERR_ARG for a bad
+ * replica or a NULL output.                                                                */
+int lb_row_axis(const lb_ctx* ctx, int32_t replica, int32_t* axis);
+
 void lb_destroy(lb_ctx* ctx);
 const char* lb_last_error(const lb_ctx* ctx);
 

@@ -40,16 +40,21 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
     gw[1] = (o[1] ? 1.0 : -1.0) * t[0] * t[2];
     gw[2] = (o[2] ? 1.0 : -1.0) * t[0] * t[1];
 
+    // the record holds the box's sides; a swapped replica is stored with axes x and z
+    // exchanged (bit 8 of masked), so its node and sides in storage coordinates are these
+    const int masked = X.masked & 0xFF;
+    const bool swap = (X.masked >> 8) != 0;
+    const int sx = swap ? pz : px, sz = swap ? px : pz;
     ReplicaDesc R{};
-    R.nx = X.nx; R.ny = X.ny; R.nz = X.nz; R.masked = X.masked;
-    R.base = X.base; R.row_base = X.row_base;
+    R.nx = swap ? X.nz : X.nx; R.ny = X.ny; R.nz = swap ? X.nx : X.nz; R.masked = masked;
+    R.base = X.base; R.row_base = X.row_base; R.swap = swap ? 1 : 0;
     int64_t local;
     Real d[Q];
-    if (X.masked) {
-        const RowDesc self = a.rowinfo[X.row_base + py + X.ny * pz];
-        const int off = px - self.xlo;
+    if (masked) {
+        const RowDesc self = a.rowinfo[X.row_base + py + X.ny * sz];
+        const int off = sx - self.xlo;
         local = (unsigned)off < (unsigned)self.len ? self.start + off : -1;
-        if (local >= 0) pull<Real, true, 1>(a.src, a.N, R, a.rowinfo, px, py, pz, local, self, d);
+        if (local >= 0) pull<Real, true, 1>(a.src, a.N, R, a.rowinfo, sx, py, sz, local, self, d);
     } else {
         local = px + (int64_t)X.nx * (py + (int64_t)X.ny * pz);
         const RowDesc self{0, 0, X.nx, 0};

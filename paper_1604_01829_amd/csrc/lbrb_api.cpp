@@ -93,7 +93,8 @@ bool make_plan(const lb_params* p, const lb_replica* reps, int32_t n, Plan& pl)
         const int64_t nodes = (int64_t)R.nx * R.ny * R.nz;
         if (nodes >= (int64_t(1) << 31)) return false;
         pl.N += pad_nodes(nodes);
-        pl.rows_cap += (int64_t)R.ny * R.nz;
+        // rows of either storage orientation (rows along x or, exchanged, along z)
+        pl.rows_cap += (int64_t)R.ny * std::max(R.nx, R.nz);
         pl.tiles_cap += pad_nodes(nodes) / kNodeBlock;
         if (p->max_wall_sites > 0) {
             pl.cells_cap += (int64_t)cells_per_axis_cap(R.nx) * cells_per_axis_cap(R.ny) *
@@ -627,10 +628,21 @@ int upload_links(lb_ctx* c)
     return LB_OK;
 }
 
+// the box's own sides of a replica (its storage may exchange axes x and z)
+void box_dims(const ReplicaDesc& R, int d[3])
+{
+    d[0] = R.swap ? R.nz : R.nx;
+    d[1] = R.ny;
+    d[2] = R.swap ? R.nx : R.nz;
+}
+
 BodyBox body_box(const ReplicaDesc& R)
 {
     BodyBox x{};
-    x.nx = R.nx; x.ny = R.ny; x.nz = R.nz; x.masked = R.masked;
+    int d[3];
+    box_dims(R, d);
+    x.nx = d[0]; x.ny = d[1]; x.nz = d[2]; x.masked = R.masked;
+    x.swap = R.swap;
     x.base = R.base;
     x.row_base = R.row_base;
     x.key0 = R.key0; x.key1 = R.key1;
@@ -689,7 +701,8 @@ int build_wca(lb_ctx* c)
             rep_bodies.push_back(b);
             if (c->bodies0[b].n_ev > 0) ev_r = std::max(ev_r, c->bodies0[b].ev_radius);
         }
-        const int dims[3] = {R.nx, R.ny, R.nz};
+        int dims[3];
+        box_dims(R, dims);
         if (!wca_grid(dims, ev_r, H.sites, W, wt))
             return fail(c, LB_ERR_ARG, "a box side is shorter than twice the WCA range");
     }
@@ -1076,7 +1089,7 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
         R.inv_ny = 1.0 / in.ny;
 
         base += pad_nodes(R.n_nodes);
-        row_base += (int64_t)in.ny * in.nz;
+        row_base += (int64_t)in.ny * std::max(in.nx, in.nz);
     }
     rebuild_tiles(c);
     // zero the header, the spread-force accumulators and the flags once
@@ -1105,36 +1118,72 @@ int lb_set_boundary_mask(lb_ctx* c, int32_t replica, const uint8_t* mask)
     if (!check_replica(c, replica) || !mask) return fail(c, LB_ERR_ARG, "bad replica or mask");
     if (c->step != 0) return fail(c, LB_ERR_STATE, "masks can only be set before the first step");
     ReplicaDesc& R = c->reps[replica];
-    const int nx = R.nx, ny = R.ny, nz = R.nz;
+    int box[3];
+    box_dims(R, box);
+    const int nx = box[0], ny = box[1], nz = box[2];
+    // Storage orientation: rows along x, or along z (axes x and z exchanged) when that gives
+    // much longer rows -- a pore along z cuts every x row short, and the node update's reads of
+    // neighbouring rows then fall on more cache lines
     MaskRows m = compress_mask(nx, ny, nz, mask);
+    std::vector<uint8_t> stored_mask(mask, mask + (size_t)nx * ny * nz);
+    bool swap = false;
+    if (m.any_solid) {
+        std::vector<uint8_t> t((size_t)nx * ny * nz);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x)
+                    t[z + (size_t)nz * (y + (size_t)ny * x)] = mask[x + (size_t)nx * (y + (size_t)ny * z)];
+        MaskRows mt = compress_mask(nz, ny, nx, t.data());
+        // stored nodes plus a cache line's worth of nodes per row
+        const double cost_x = (double)m.stored + 16.0 * (double)m.rows.size();
+        const double cost_z = (double)mt.stored + 16.0 * (double)mt.rows.size();
+        if (cost_z < 0.9 * cost_x) {
+            swap = true;
+            m = std::move(mt);
+            stored_mask.swap(t);
+        }
+    }
     const bool any_solid = m.any_solid;
     const int64_t n_holes = m.n_holes;
+    // the replica in the chosen storage orientation
+    ReplicaDesc Rs = R;
+    Rs.swap = swap ? 1 : 0;
+    Rs.nx = swap ? nz : nx;
+    Rs.nz = swap ? nx : nz;
     // links of the replica's moving walls under the new mask, checked before anything changes
     ReplicaHost& H = c->rh[replica];
     std::vector<WallLink> links;
-    if (any_solid) links = build_links(R, mask, m.info.data(), H.uwall, c->p.rho0);
+    if (any_solid) links = build_links(Rs, stored_mask.data(), m.info.data(), H.uwall, c->p.rho0);
     if (links_without(c, replica) + (int64_t)links.size() > c->plan.link_cap)
         return fail(c, LB_ERR_CAPACITY, "moving-wall links exceed max_wall_links");
     // rows of this replica go to rows[row_base ...]; clear the old ones first
-    for (int64_t k = 0; k < (int64_t)ny * nz; ++k) {
+    for (int64_t k = 0; k < (int64_t)ny * std::max(nx, nz); ++k) {
         c->rowinfo[R.row_base + k] = RowDesc{0, 0, 0, 0};
         c->rows[R.row_base + k] = RowDesc{0, 0, 0, 0};
     }
     HIP_TRY(c, hipMemsetAsync(c->hole + R.base, 0, (size_t)pad_nodes(R.n_nodes), c->stream));
     if (any_solid) {
         for (size_t k = 0; k < m.rows.size(); ++k) c->rows[R.row_base + k] = m.rows[k];
-        for (int64_t k = 0; k < (int64_t)ny * nz; ++k) c->rowinfo[R.row_base + k] = m.info[k];
+        for (size_t k = 0; k < m.info.size(); ++k) c->rowinfo[R.row_base + k] = m.info[k];
         R.masked = n_holes > 0 ? 2 : 1;
         R.n_fluid = m.stored;                    // stored nodes: fluid nodes and holes
-        H.mask.assign(mask, mask + (size_t)nx * ny * nz);
+        R.swap = Rs.swap;
+        R.nx = Rs.nx;
+        R.nz = Rs.nz;
+        H.mask.swap(stored_mask);                // in storage order
         if (n_holes > 0)
             HIP_TRY(c, hipMemcpyAsync(c->hole + R.base, m.holes.data(), m.holes.size(),
                                       hipMemcpyHostToDevice, c->stream));
     } else {
         R.masked = 0;
         R.n_fluid = R.n_nodes;
+        R.swap = 0;
+        R.nx = nx;
+        R.nz = nz;
         H.mask.clear();
     }
+    R.inv_nx = 1.0 / R.nx;
+    R.inv_ny = 1.0 / R.ny;
     H.n_holes = n_holes;
     H.links.swap(links);
     destroy_graphs(c);
@@ -1477,8 +1526,11 @@ int lb_inject_nan(lb_ctx* c, int32_t replica, int32_t x, int32_t y, int32_t z, i
     if (!c) return LB_ERR_ARG;
     if (!check_replica(c, replica)) return fail(c, LB_ERR_ARG, "bad replica");
     const ReplicaDesc& R = c->reps[replica];
-    if (x < 0 || x >= R.nx || y < 0 || y >= R.ny || z < 0 || z >= R.nz || i < 0 || i >= Q)
+    int box[3];
+    box_dims(R, box);
+    if (x < 0 || x >= box[0] || y < 0 || y >= box[1] || z < 0 || z >= box[2] || i < 0 || i >= Q)
         return fail(c, LB_ERR_ARG, "node or population out of range");
+    if (R.swap) std::swap(x, z);   // storage coordinates
     int64_t local = x + (int64_t)R.nx * (y + (int64_t)R.ny * z);
     if (R.masked) {
         const RowDesc& d = c->rowinfo[R.row_base + y + (int64_t)R.ny * z];
@@ -1658,6 +1710,13 @@ int lb_kernel_times(lb_ctx* c, double* node_ms, int64_t* node_n, double* couple_
     if (node_n) *node_n = (int64_t)c->ev_node.size();
     if (couple_ms) *couple_ms = tc;
     if (couple_n) *couple_n = (int64_t)c->ev_couple_t.size();
+    return LB_OK;
+}
+
+int lb_row_axis(const lb_ctx* c, int32_t replica, int32_t* axis)
+{
+    if (!c || replica < 0 || replica >= c->n_rep || !axis) return LB_ERR_ARG;
+    *axis = c->reps[replica].swap ? 2 : 0;
     return LB_OK;
 }
 

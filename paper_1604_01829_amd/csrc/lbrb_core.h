@@ -43,6 +43,12 @@ LBRB_HD int cz_of(int i)
     return t[i];
 }
 LBRB_HD int opposite_of(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+// the direction with the x and z components of direction i exchanged
+LBRB_HD int swap_xz_of(int i)
+{
+    constexpr int t[Q] = {0, 5, 6, 3, 4, 1, 2, 15, 16, 18, 17, 11, 12, 14, 13, 7, 8, 10, 9};
+    return t[i];
+}
 LBRB_HD double weight_of(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
 // ------------------------------------------------------------------ Philox4x32-10
@@ -382,11 +388,11 @@ struct Pose {
 // Geometry of the replica a body lives in, copied into the body record so that the
 // coupling reaches it without another dependent load.
 struct BodyBox {
-    int32_t nx, ny, nz, masked;
+    int32_t nx, ny, nz, masked;      // the box's own sides (not the storage's)
     int64_t base;                    // global index of the replica's local node 0
     int32_t row_base;
     uint32_t key0, key1;             // Philox key of the replica
-    int32_t pad;
+    int32_t swap;                    // the replica is stored with axes x and z exchanged
 };
 
 struct Body {

@@ -159,9 +159,15 @@ __device__ __forceinline__ Real load_pop(const Real* __restrict__ src, int64_t b
 
 // Masked gather over preloaded rows: element i from x - S c_i (periodic in x) if that node is
 // fluid, else population opposite(i) of the node itself (own = its local index).
+// sw: the replica is stored with axes x and z exchanged (uniform over the workgroup).  Its
+// population j then steps by (c_jz, c_jy, c_jx) in storage, which is the storage step of
+// direction k = swap_xz(j): iteration k keeps its geometry and loads population swap_xz(k)
+// into d[k], and the pairs (k, swap_xz(k)) are exchanged afterwards.  Same registers, same
+// loads, a scalar choice of population per iteration.
 template <typename Real, int S, bool NARROW = false>
 __device__ __forceinline__ void pull_rows(const Real* __restrict__ src, int64_t base, int nx,
-                                          const Rows9& rw, int x, int64_t own, Real d[Q])
+                                          const Rows9& rw, int x, int64_t own, Real d[Q],
+                                          bool sw = false)
 {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -171,8 +177,20 @@ __device__ __forceinline__ void pull_rows(const Real* __restrict__ src, int64_t 
         const int off = xs - rw.lo[r9];
         const bool fluid = (unsigned)off < (unsigned)rw.ln[r9];
         const int64_t l = fluid ? (int64_t)rw.st[r9] + off : own;
-        const int p = fluid ? i : opposite_of(i);
+        const int j = sw ? swap_xz_of(i) : i;
+        const int p = fluid ? j : opposite_of(j);
         d[i] = load_pop<Real, NARROW>(src, base, p, l);
+    }
+    if (sw) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int k = swap_xz_of(i);
+            if (k > i) {
+                const Real t = d[i];
+                d[i] = d[k];
+                d[k] = t;
+            }
+        }
     }
 }
 
@@ -201,7 +219,7 @@ __device__ __forceinline__ void pull(const Real* __restrict__ src, int64_t N,
                 rw.st[r9] = rd.start; rw.lo[r9] = rd.xlo; rw.ln[r9] = rd.len;
             }
         }
-        pull_rows<Real, S, NARROW>(src, R.base, R.nx, rw, x, local, d);
+        pull_rows<Real, S, NARROW>(src, R.base, R.nx, rw, x, local, d, R.swap != 0);
     } else {
         const int xm = wrap1(x - 1, R.nx), xp = wrap1(x + 1, R.nx);
         const int ym = wrap1(y - 1, R.ny), yp = wrap1(y + 1, R.ny);

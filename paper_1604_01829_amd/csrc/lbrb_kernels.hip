@@ -59,7 +59,8 @@ __device__ __forceinline__ void update_node(const StepArgs<Real>& a, const Repli
 
     uint32_t w[8];
     if constexpr (THERMAL) {
-        const uint32_t dense = (uint32_t)(x + (int64_t)R.nx * (y + (int64_t)R.ny * z));
+        // the noise stream of the node in the box's own coordinates
+        const uint32_t dense = (uint32_t)box_index(R, x, y, z);
         const U4 b0 = noise_block((uint64_t)step, dense, 0u, 0u, R.key0, R.key1);
         const U4 b1 = noise_block((uint64_t)step, dense, 0u, 1u, R.key0, R.key1);
         w[0] = b0.x; w[1] = b0.y; w[2] = b0.z; w[3] = b0.w;
@@ -183,7 +184,9 @@ __device__ __forceinline__ void write_bead_const(const RecConst& C, int32_t user
     o.noise_amp = C.noise_amp;
     o.noise_idx = C.first_in_replica + user;   // noise follows the caller's order
     o.row_base = X.row_base;
-    o.nx = X.nx; o.ny = X.ny; o.nz = X.nz; o.masked = X.masked;
+    // the box's sides; bit 8 of masked: the replica is stored with axes x and z exchanged
+    o.nx = X.nx; o.ny = X.ny; o.nz = X.nz;
+    o.masked = X.masked | (X.swap << 8);
     o.base = X.base;
     o.key0 = X.key0; o.key1 = X.key1;
 }
@@ -716,17 +719,20 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
     // the record spread over the bead's 8 lanes; the geometry is gathered now, the dynamics
     // after the stencil's populations are in
     const uint4 rq = reinterpret_cast<const uint4*>(c.recs + (active ? bead : 0))[corner];
-    const double r[3] = {rec_f64<LBRB_REC_WORD(r[0])>(rq), rec_f64<LBRB_REC_WORD(r[1])>(rq),
-                         rec_f64<LBRB_REC_WORD(r[2])>(rq)};
     const int nx = (int)rec_word<LBRB_REC_WORD(nx)>(rq);
     const int ny = (int)rec_word<LBRB_REC_WORD(ny)>(rq);
     const int nz = (int)rec_word<LBRB_REC_WORD(nz)>(rq);
-    const int masked = (int)rec_word<LBRB_REC_WORD(masked)>(rq);
+    const int mword = (int)rec_word<LBRB_REC_WORD(masked)>(rq);
+    const int masked = mword & 0xFF;
+    const bool swap = (mword >> 8) != 0;   // storage axes x and z exchanged
+    const double r[3] = {rec_f64<LBRB_REC_WORD(r[0])>(rq), rec_f64<LBRB_REC_WORD(r[1])>(rq),
+                         rec_f64<LBRB_REC_WORD(r[2])>(rq)};
     const int row_base = (int)rec_word<LBRB_REC_WORD(row_base)>(rq);
     const int64_t base = (int64_t)(((uint64_t)rec_word<LBRB_REC_WORD(base) + 1>(rq) << 32) |
                                    rec_word<LBRB_REC_WORD(base)>(rq));
 
-    // corner of the trilinear stencil handled by this lane
+    // corner of the trilinear stencil handled by this lane, in box coordinates (so the weights
+    // and the corner sums do not depend on the storage axes)
     double fr[3];
     int i0[3];
     i0[0] = wrap_floor(r[0] - 0.5, nx, fr[0]);
@@ -739,13 +745,17 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
     const double w = (ox ? fr[0] : 1.0 - fr[0]) * (oy ? fr[1] : 1.0 - fr[1]) *
                      (oz ? fr[2] : 1.0 - fr[2]);
 
+    // the node in storage coordinates and sides
+    const int sx = swap ? pz : px, sz = swap ? px : pz;
+    const int snx = swap ? nz : nx, snz = swap ? nx : nz;
+
     // the node's local index (-1: boundary node or no bead)
     int64_t local = -1;
     Rows9 rw;
     if (active) {
         if (masked) {
-            load_rows9(a.rowinfo, row_base, ny, nz, py, pz, rw);
-            const int off = px - rw.lo[4];
+            load_rows9(a.rowinfo, row_base, ny, snz, py, sz, rw);
+            const int off = sx - rw.lo[4];
             local = (unsigned)off < (unsigned)rw.ln[4] ? rw.st[4] + off : -1;
             // a hole is a boundary node: no velocity sampled, no force spread
             if (masked == 2 && local >= 0 && a.hole[base + local] != 0) local = -1;
@@ -772,7 +782,7 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
     if (owner) {
         Real d[Q];
         if (masked) {
-            pull_rows<Real, 1>(a.src, base, nx, rw, px, local, d);
+            pull_rows<Real, 1>(a.src, base, snx, rw, sx, local, d, swap);
         } else {
             ReplicaDesc R{};
             R.nx = nx; R.ny = ny; R.nz = nz;
@@ -1025,7 +1035,7 @@ __global__ __launch_bounds__(kNodeBlock) void observe_kernel(const StepArgs<Real
         pull<Real, MASKED>(a.src, a.N, R, a.rowinfo, x, y, z, local, self, d);
         Real drho, j[3];
         density_momentum<Real>(d, drho, j);
-        const int64_t dense = x + (int64_t)R.nx * (y + (int64_t)R.ny * z);
+        const int64_t dense = box_index(R, x, y, z);   // outputs in the box's own order
         if (fields) {
             const Real rho = a.cp.rho0 + drho;
             Real* o = fields + 4 * dense;

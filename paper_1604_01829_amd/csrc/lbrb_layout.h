@@ -50,6 +50,12 @@ __host__ __device__ __forceinline__ int64_t pop_at(int i, int64_t g)
 // steps per fluid step, each of the first m - 1 MD steps adds a coupling launch and a body
 // launch before them.
 
+// Storage axes.  A masked replica may be stored with its z axis as the row axis ("swapped":
+// storage x = box z, storage z = box x, y unchanged), chosen by the mask so that the stored
+// rows run along long fluid runs (a pore along z).  nx, ny, nz, the rows and every kernel's
+// (x, y, z) are storage coordinates; the populations keep the box's velocity directions, so a
+// pull along c_i steps by (c_iz, c_iy, c_ix) in storage coordinates; the noise streams, the
+// fields handed out and the bead positions stay in box coordinates.
 struct ReplicaDesc {
     int32_t nx, ny, nz, masked;   // 0: no boundary nodes; 1: masked; 2: masked, with holes
     int64_t base;           // global index of local node 0
@@ -57,9 +63,17 @@ struct ReplicaDesc {
     int64_t n_fluid;
     int32_t row_base;       // first entry of this replica in rows[] and rowinfo[]
     uint32_t key0, key1;    // Philox key (seed)
-    int32_t pad0, pad1;
+    int32_t swap;           // 1: stored with box axes x and z exchanged (masked replicas only)
+    int32_t pad1;
     double inv_nx, inv_ny;  // for exact index division
 };
+
+// index of storage node (x, y, z) in the box's own x-fastest order
+__host__ __device__ __forceinline__ int64_t box_index(const ReplicaDesc& R, int x, int y, int z)
+{
+    return R.swap ? z + (int64_t)R.nz * (y + (int64_t)R.ny * x)
+                  : x + (int64_t)R.nx * (y + (int64_t)R.ny * z);
+}
 
 struct RowDesc {
     int32_t start;          // local index of the first fluid node of the row

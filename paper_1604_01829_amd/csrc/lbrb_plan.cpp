@@ -85,8 +85,11 @@ std::vector<WallLink> build_links(const ReplicaDesc& R, const uint8_t* mask, con
             for (int x = row.xlo; x < row.xlo + row.len; ++x) {
                 if (mask[x + (size_t)nx * (y + (size_t)ny * z)]) continue;   // a hole
                 for (int i = 1; i < Q; ++i) {
-                    const int bx = wrapi(x - cx_of(i), nx), by = wrapi(y - cy_of(i), ny),
-                              bz = wrapi(z - cz_of(i), nz);
+                    // c_i in storage coordinates (axes x and z exchanged when R.swap)
+                    const int sx = R.swap ? cz_of(i) : cx_of(i);
+                    const int sz = R.swap ? cx_of(i) : cz_of(i);
+                    const int bx = wrapi(x - sx, nx), by = wrapi(y - cy_of(i), ny),
+                              bz = wrapi(z - sz, nz);
                     const uint8_t k = mask[bx + (size_t)nx * (by + (size_t)ny * bz)];
                     if (!k) continue;
                     const double* u = &uwall[3 * (size_t)k];

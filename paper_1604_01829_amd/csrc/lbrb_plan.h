@@ -43,8 +43,10 @@ void append_tiles(const ReplicaDesc& R, int32_t r, const RowDesc* rows, const Ro
 
 // Moving-wall links of one replica: every stored fluid node x and direction i whose neighbour
 // x - c_i (periodic) is a boundary node of a wall k with c_i . u_k != 0 (Ladd's moving
-// bounce-back).  info holds the replica's rows per (y,z), mask its wall ids, uwall three
-// velocities per wall id (empty: no moving walls).  Sorted by the population slot they update.
+// bounce-back).  R, info (the rows per (y,z)) and mask (wall ids) are in storage coordinates:
+// when R.swap the box's axes x and z are exchanged, so c_i steps by (c_iz, c_iy, c_ix) there.
+// uwall holds three velocities per wall id (empty: no moving walls).  Sorted by the population
+// slot they update.
 std::vector<WallLink> build_links(const ReplicaDesc& R, const uint8_t* mask, const RowDesc* info,
                                   const std::vector<double>& uwall, double rho0);
 

@@ -43,8 +43,10 @@ __global__ __launch_bounds__(kNodeBlock) void mirror_holes_kernel(Real* f, const
     RowDesc self;
     locate<true>(R, rows, t.row_lo, t.row_hi, local, x, y, z, self);
     for (int i = 1; i < Q; ++i) {
-        const int xs = wrap1(x + cx_of(i), R.nx), ys = wrap1(y + cy_of(i), R.ny),
-                  zs = wrap1(z + cz_of(i), R.nz);
+        // c_i in storage coordinates (axes x and z exchanged for a swapped replica)
+        const int ci_x = R.swap ? cz_of(i) : cx_of(i), ci_z = R.swap ? cx_of(i) : cz_of(i);
+        const int xs = wrap1(x + ci_x, R.nx), ys = wrap1(y + cy_of(i), R.ny),
+                  zs = wrap1(z + ci_z, R.nz);
         const RowDesc rd = rowinfo[R.row_base + ys + R.ny * zs];
         const int off = xs - rd.xlo;
         if ((unsigned)off >= (unsigned)rd.len) continue;       // not stored: boundary node

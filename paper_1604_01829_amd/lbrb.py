@@ -37,7 +37,8 @@ EXPORTED = ["lb_workspace_bytes", "lb_init", "lb_set_boundary_mask", "lb_set_wal
             "lb_inject_nan", "lb_save_state", "lb_load_state", "lb_set_graph_steps",
             "lb_set_timing", "lb_kernel_times", "lb_set_store_policy", "lb_autotune",
             "lb_get_tuning", "lb_set_tuning", "lb_adjoint_workspace_bytes", "lb_rb_adjoint",
-            "lb_rb_adjoint_noalloc", "lb_node_counts", "lb_destroy", "lb_last_error"]
+            "lb_rb_adjoint_noalloc", "lb_node_counts", "lb_row_axis", "lb_destroy",
+            "lb_last_error"]
 
 
 class lb_replica(ctypes.Structure):
@@ -173,6 +174,8 @@ def library():
     L.lb_node_counts.restype = ctypes.c_int
     L.lb_node_counts.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64)]
+    L.lb_row_axis.restype = ctypes.c_int
+    L.lb_row_axis.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.lb_destroy.restype = None
     L.lb_destroy.argtypes = [_VP]
     L.lb_last_error.restype = ctypes.c_char_p
@@ -456,6 +459,12 @@ class Simulation:
                "lb_kernel_times")
         return {"node_ms": tn.value, "node_launches": nn.value, "couple_ms": tc.value,
                 "couple_launches": nc.value}
+
+    def row_axis(self, replica=0):
+        """0: the replica's fluid is stored in rows along x; 2: along z (a layout choice)."""
+        a = ctypes.c_int32()
+        _check(self.ctx, library().lb_row_axis(self.ctx, replica, ctypes.byref(a)), "lb_row_axis")
+        return a.value
 
     def node_counts(self, replica=0):
         a, b = ctypes.c_int64(), ctypes.c_int64()

@@ -140,26 +140,47 @@ static void check_tiles(const ReplicaDesc& R, const std::vector<RowDesc>& rows,
     CHECK(next == n, "tiles cover the stored nodes");
 }
 
-static void check_links(const ReplicaDesc& R, const std::vector<uint8_t>& mask,
-                        const MaskRows& mr, std::mt19937_64& rng)
+// The links of a replica whose mask is given in the box's order; with swap the replica is
+// stored with axes x and z exchanged (mask, rows and R in storage coordinates), while the
+// expected links are enumerated in box coordinates and mapped to the storage node.
+static void check_links(const ReplicaDesc& Rbox, const std::vector<uint8_t>& mask,
+                        const MaskRows& mr_box, std::mt19937_64& rng, bool swap)
 {
+    ReplicaDesc R = Rbox;
+    MaskRows mr = mr_box;
+    std::vector<uint8_t> smask = mask;
+    if (swap) {
+        const int bx = Rbox.nx, by = Rbox.ny, bz = Rbox.nz;
+        for (int z = 0; z < bz; ++z)
+            for (int y = 0; y < by; ++y)
+                for (int x = 0; x < bx; ++x)
+                    smask[z + (size_t)bz * (y + (size_t)by * x)] = mask[x + (size_t)bx * (y + (size_t)by * z)];
+        mr = compress_mask(bz, by, bx, smask.data());
+        check_mask(smask, bz, by, bx, mr);
+        R.nx = bz;
+        R.nz = bx;
+        R.swap = 1;
+        R.n_fluid = mr.stored;
+    }
     std::vector<double> uwall(256 * 3, 0.0);
     std::uniform_real_distribution<double> u(-1e-2, 1e-2);
     for (int k : {2, 4})
         for (int a = 0; a < 3; ++a) uwall[3 * k + a] = u(rng);
     uwall[3 * 3 + 1] = 5e-3;   // wall 3 moves along y only: links with c_i . u = 0 drop out
     const double rho0 = 1.25;
-    const std::vector<WallLink> got = build_links(R, mask.data(), mr.info.data(), uwall, rho0);
+    const std::vector<WallLink> got = build_links(R, smask.data(), mr.info.data(), uwall, rho0);
     // a link: (node, direction of the reflected population, delta); the direction -c_i is
     // compared as a vector, so the check does not depend on the library's velocity order
     typedef std::tuple<int64_t, int, int, int, double> Link;
     std::set<Link> want, have;
-    const int nx = R.nx, ny = R.ny, nz = R.nz;
+    const int nx = Rbox.nx, ny = Rbox.ny, nz = Rbox.nz;
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 if (mask[x + (size_t)nx * (y + (size_t)ny * z)]) continue;
-                const RowDesc& d = mr.info[(size_t)y + (size_t)ny * z];
+                // the node's storage coordinates and row
+                const int sx = swap ? z : x, sz = swap ? x : z;
+                const RowDesc& d = mr.info[(size_t)y + (size_t)ny * sz];
                 for (int i = 1; i < 19; ++i) {
                     const int* c = C19[i];
                     const int bx = ((x - c[0]) % nx + nx) % nx;
@@ -172,7 +193,7 @@ static void check_links(const ReplicaDesc& R, const std::vector<uint8_t>& mask,
                     if (cu == 0.0) continue;
                     const int c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
                     const double w = c2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
-                    want.emplace(R.base + d.start + (x - d.xlo), -c[0], -c[1], -c[2],
+                    want.emplace(R.base + d.start + (sx - d.xlo), -c[0], -c[1], -c[2],
                                  6.0 * w * rho0 * cu);
                 }
             }
@@ -322,7 +343,10 @@ int main()
             info.insert(info.end(), mr.info.begin(), mr.info.end());
             const ReplicaDesc R = replica(nx, ny, nz, mr, 3 * kNodeBlock, row_base);
             if (R.n_fluid > 0) check_tiles(R, rows, info);
-            if (mr.any_solid) check_links(R, mask, mr, rng);
+            if (mr.any_solid) {
+                check_links(R, mask, mr, rng, false);
+                check_links(R, mask, mr, rng, true);
+            }
             ++n_cases;
         }
     check_order(rng);

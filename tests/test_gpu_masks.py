@@ -156,6 +156,37 @@ def test_batch_with_holed_and_plain_replicas():
     gpu.close()
 
 
+def baffle_case(precision, kT, walls=None):
+    """The 24 x 22 x 40 pore along z of the parity tests with a baffle (wall 2) across half of
+    its cross-section at z = 20: the library stores this replica in rows along z (the pore
+    axis), and the rows through the baffle hold two fluid runs (holes)."""
+    from tests.test_gpu_parity import pore_case
+    wl = pore_case(precision, kT)
+    m = wl["replicas"][0]["mask"].copy()
+    nz, ny, nx = m.shape
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    half = (yy < ny // 2) & (m[20] == 0)
+    m[20][half] = 2
+    wl["replicas"][0]["mask"] = m
+    wl["replicas"][0]["walls"] = walls or {}
+    # keep the bodies clear of the baffle
+    wl["replicas"][0]["bodies"] = [b for b in wl["replicas"][0]["bodies"]
+                                   if abs(b["pos"][2] - 20.5) > 5.0]
+    return wl
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("moving", [False, True])
+def test_pore_with_a_baffle_stored_along_the_pore(precision, moving):
+    wl = baffle_case(precision, 0.0 if moving else 4e-5,
+                     walls={2: (1e-3, 0.0, -5e-4)} if moving else None)
+    gpu, _ = _run(wl, precision, tag=f"baffle moving={moving}")
+    assert gpu.row_axis(0) == 2
+    m = wl["replicas"][0]["mask"]
+    assert gpu.node_counts(0) == (m.size, int((m == 0).sum()))
+    gpu.close()
+
+
 def test_reverse_pass_refuses_holes():
     rng = np.random.default_rng(3)
     wl = dict(name="obstacle", precision="f64", steps=4, params=W.default_params(),

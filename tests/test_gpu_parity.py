@@ -139,6 +139,7 @@ def pore_case(precision, kT):
 def test_pore_with_spheres(precision, kT):
     wl = pore_case(precision, kT)
     gpu = gpu_from_workload(wl)
+    assert gpu.row_axis(0) == 2   # stored in rows along the pore axis
     gpu.set_graph_steps(0)
     orc = oracle_from_workload(wl)
     done = 0
@@ -152,3 +153,30 @@ def test_pore_with_spheres(precision, kT):
             _assert_close(e, 1e-11, 1e-13, 1e-12)
         else:
             _assert_close(e, 1e-5, 1e-6, 1e-6)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_pore_along_x_stored_in_x_rows(precision):
+    """The same pore and spheres turned so that the pore runs along x: its rows are stored
+    along x (no exchange of axes), against the oracle."""
+    wl = pore_case(precision, 4e-5)
+    r = wl["replicas"][0]
+    r["mask"] = np.ascontiguousarray(np.transpose(r["mask"], (2, 1, 0)))
+    r["shape"] = tuple(r["shape"][::-1])
+    r["bodies"] = [dict(b, pos=np.asarray(b["pos"])[[2, 1, 0]]) for b in r["bodies"]]
+    gpu = gpu_from_workload(wl)
+    assert gpu.row_axis(0) == 0
+    gpu.set_graph_steps(0)
+    orc = oracle_from_workload(wl)
+    done = 0
+    for s in (1, 3, 30):
+        gpu.step(s - done)
+        orc.step(s - done)
+        done = s
+        e = compare(gpu, orc)
+        _print(f"pore along x {precision} step {s}", e)
+        if precision == "f64":
+            _assert_close(e, 1e-11, 1e-13, 1e-12)
+        else:
+            _assert_close(e, 1e-5, 1e-6, 1e-6)
+    gpu.close()
