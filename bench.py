@@ -23,8 +23,8 @@ shorter window on one thread.
 
 `compare` (unless --no-compare) measures, on the same GPU in the same process:
   batched_fp64    the same 512 replicas in one batch with FP64 populations (precision alone);
-  batched_fp32_pore_along_x   the batch with every pore turned along x, the axis of the stored
-                  rows (what the pore along z costs the node update);
+  batched_fp32_pore_along_x   the batch with every pore turned along x (the library stores
+                  either orientation in rows along the pore axis);
   plain_fp64      16 sampled replicas run one FP64 context at a time (neither batching nor
                   the FP32 storage);
   pore128_f32/64  one 128x128x256 box holding a radius-40 pore with 32 spheres (its population
@@ -222,9 +222,8 @@ def compare_runs(args, wl4):
     del sim
     torch.cuda.empty_cache()
     out["batched_fp32_untuned"] = _short(m, "f32")
-    # the same batch with each replica's pore turned along x (rows along the pore axis): what
-    # the pore along z costs the node update, whose rows run along x and are cut short by the
-    # circular cross-section
+    # the same batch with each replica's pore turned along x: the library stores both
+    # orientations in rows along the pore axis (lb_row_axis), so the two should agree
     wlx = dict(wl4, replicas=[
         dict(r, mask=np.ascontiguousarray(np.transpose(r["mask"], (2, 1, 0))),
              bodies=[dict(b, pos=np.asarray(b["pos"])[[2, 1, 0]]) for b in r["bodies"]])

@@ -385,8 +385,9 @@ int lb_node_counts(const lb_ctx* ctx, int32_t replica, int64_t* n_nodes, int64_t
 
 /* Storage axis of a replica's rows (a layout choice of the library, not of the method):
  * *axis = 0 when the fluid is stored in rows along x, 2 when lb_set_boundary_mask chose rows
- * along z (the box's axes x and z exchanged in storage) because the mask's fluid runs are
- * much longer along z, as in a pore along z.  Results do not depend on it; fields,
+ * along z (the box's axes x and z exchanged in storage) because the mask's x rows are short
+ * (under 48 stored nodes on average) and its fluid runs much longer along z, as in a narrow
+ * pore along z.  Results do not depend on it; fields,
  * populations and positions are always in the box's own coordinates.  LB_ERR_ARG for a bad
  * replica or a NULL output.                                                                */
 int lb_row_axis(const lb_ctx* ctx, int32_t replica, int32_t* axis);
