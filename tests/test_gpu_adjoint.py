@@ -26,7 +26,13 @@ TAUS = dict(tau_shear=0.9, tau_bulk=1.2, tau_odd=1.05, tau_even=0.8)
 
 def _case(masked):
     rng = np.random.default_rng(15 if masked else 16)
-    if masked:
+    if masked == "long":
+        # a longer pore: stored in rows along z (its axis)
+        shape = (14, 14, 24)
+        mask = W.pore_mask(*shape, 6.0)
+        gext, u0 = (0.0, 0.0, 1e-4), (0.0, 0.0, 0.0)
+        centres = [np.array([7.1, 6.8, 11.9]), np.array([4.3, 9.6, 20.2])]
+    elif masked:
         shape = (14, 14, 10)
         mask = W.pore_mask(*shape, 6.0)
         gext, u0 = (0.0, 0.0, 1e-4), (0.0, 0.0, 0.0)
@@ -80,16 +86,16 @@ def _forward_J(sim, steps, a):
     return J
 
 
-@pytest.mark.parametrize("masked", [False, True], ids=["periodic", "pore"])
+@pytest.mark.parametrize("masked", [False, True, "long"], ids=["periodic", "pore", "long pore"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_adjoint_matches_oracle(masked, precision):
     shape, mask, pp, bodies = _case(masked)
     T, K = 13, 5                                 # segments of 5, 5 and 3 steps
     a = _weights(T, len(bodies))
-    print(f"adjoint vs oracle: {'pore' if masked else 'periodic'} {precision} T={T} K={K}",
-          flush=True)
+    print(f"adjoint vs oracle: {masked} {precision} T={T} K={K}", flush=True)
     Jo, dgo, doo = _oracle(shape, mask, pp, bodies).adjoint(T, a)
     sim = _gpu(shape, mask, pp, bodies, precision)
+    assert sim.row_axis(0) == (2 if masked == "long" else 0)
     Jg, dgg, dog = sim.adjoint(T, a, checkpoint_every=K)
     sim.close()
     if precision == "f64":
