@@ -302,6 +302,51 @@ def test_pore_128_in_the_benchmark_configuration():
     gpu.close()
 
 
+def test_pore_128_full_run():
+    """Workload 2 for its specified 2000 steps in the timed configuration (graph replays of 100
+    steps), pathwise against the oracle box over the same steps (run on host threads while
+    the GPU runs), with the long-run bounds of the batch's full run; FP64 mass within the
+    FP32 rounding bound of the stored shifted populations."""
+    import threading
+    wl = W.workload(2)
+    T = wl["steps"]
+    orc = oracle_from_workload(wl)
+    errors = []
+
+    def run():
+        try:
+            for k in range(10):
+                orc.step(T // 10)
+                print(f"  oracle: step {(k + 1) * (T // 10)}", flush=True)
+        except Exception as exc:   # reported in the main thread
+            errors.append(exc)
+
+    th = threading.Thread(target=run)
+    th.start()
+    gpu = gpu_from_workload(wl)
+    gpu.set_graph_steps(100)
+    m0 = gpu.observables(0)[0]["mass"]
+    for k in range(10):
+        gpu.step(T // 10)
+        tot, _, _, rc = gpu.observables(0, check=False)
+        assert rc == 0 and tot["finite"]
+        print(f"  GPU step {tot['step']}", flush=True)
+    tot, _, _, _ = gpu.observables(0)
+    f = gpu.populations(0)
+    fl = np.any(f != 0.0, axis=0)
+    dev = np.abs(f[:, fl] - po.weights()[:, None] * wl["params"]["rho0"]).max()
+    bound = T * 19 * fl.sum() * 2.0 ** -24 * dev
+    print(f"  mass drift {abs(tot['mass'] - m0):.3g}, worst-case FP32 bound {bound:.3g}", flush=True)
+    assert abs(tot["mass"] - m0) <= bound
+    th.join()
+    assert not errors, errors
+    e = _field_errors(gpu, orc)
+    print(f"  pore 128x128x256 after {T} steps:",
+          {k: f"{v:.3g}" for k, v in e.items() if isinstance(v, float)}, flush=True)
+    _check(e, 1e-4, 1e-5, 2e-5)
+    gpu.close()
+
+
 def test_confined_md_full_size():
     wl = W.confined_md_workload(substeps=2)
     gpu = gpu_from_workload(wl)
