@@ -7,6 +7,8 @@ oracle finishes in seconds, with the bounds of the GPU physics tests.
   hasimoto, read as 2.837 kT / (6 pi eta L); here in its resistance form with the higher-order
   terms of the same series), so the hydrodynamic radius solved from each box size must not
   depend on L while the friction itself drops by a quarter from L = 10 to 16.
+- Perrin's friction ratio of a prolate spheroid (eq. perrin_a) for a raspberry ellipsoid, grown
+  by the hydrodynamic shell the sphere test measures, corrected for periodic images.
 - Equipartition (eq. einstein_trans and the fluctuation-dissipation statement of Sec. 1.1) in
   a 12^3 thermal box with a free R = 1.5 sphere: the fluid's velocity variance is kT per
   degree of freedom; the body's <V_a^2> = kT/M (1 - M/M_total) with the total momentum fixed,
@@ -71,6 +73,31 @@ def test_oracle_hasimoto_box_size_series():
     assert xi[16] < 0.8 * xi[10]                 # the images matter at these sizes
     assert (v.max() - v.min()) / v.mean() < 5e-3
     assert R < v.mean() < R + 0.5                # beyond the bead radius, by a bead shell
+
+
+def test_oracle_perrin_friction_ratio_of_a_raspberry_ellipsoid():
+    """Eq. perrin_a: a fixed (3, 1.5, 1.5) raspberry ellipsoid's friction along its axis over
+    that across it, each mobility corrected by the isotropic periodic-image term, against
+    Perrin's ratio for the spheroid grown by the hydrodynamic shell of a raspberry sphere
+    (the R_h - R of the R = 1.5 sphere in the same lattice), at two box sizes."""
+    from tests.test_gpu_physics import _perrin
+    R = 1.5
+    sph = W.sphere_beads(R, W.sphere_bead_count(R))
+    delta = _hasimoto_radius(_steady_drag(16, sph, W.GAMMA_FIXED, 0), 16) - R
+    a, b = 3.0, 1.5
+    offs = W.ellipsoid_beads(a, b, b)
+    fa, fb = _perrin(a + delta, b + delta)
+    ratios = []
+    for L in (16, 20):
+        xa = _steady_drag(L, offs, W.GAMMA_FIXED, 0)     # long axis along x
+        xb = _steady_drag(L, offs, W.GAMMA_FIXED, 1)
+        corr = 2.837 / (6 * math.pi * ETA * L)
+        ratios.append((1 / xb + corr) / (1 / xa + corr))
+        print(f"  L={L}: xi_par={xa:.5f} xi_perp={xb:.5f} corrected ratio {ratios[-1]:.5f}; "
+              f"Perrin {fa / fb:.5f} (shell {delta:.3f})", flush=True)
+    assert abs(ratios[0] - ratios[1]) < 5e-3
+    for r in ratios:
+        assert r < 1.0 and abs(r / (fa / fb) - 1) < 1.5e-2
 
 
 def _temperatures(gamma, samples, seed, L=12, R=1.5, kT=4e-5, every=2):
