@@ -865,9 +865,7 @@ __device__ __forceinline__ void couple_beads(const StepArgs<Real>& a, const Coup
 template <typename Real, bool WCA>
 __global__ __launch_bounds__(kCoupleBlock)
 __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 && !WCA ? 6 : 1)))
-void couple_kernel(const StepArgs<Real> a,
-                                                              const CoupleArgs c,
-                                                              const BodyArgs ba, int n_wca)
+void couple_kernel(const StepArgs<Real> a, const CoupleArgs c, const BodyArgs ba, int n_wca)
 {
     __shared__ CoupleLds<Real> L;
     static_assert(sizeof(L) >= sizeof(WcaLds), "excluded-volume LDS fits in the coupling's");
