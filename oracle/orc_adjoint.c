@@ -8,9 +8,10 @@
  * (a = (1/T, 0, 0) for every step gives the time-averaged drag along x).  Derivatives are
  * taken with respect to each body's bead friction gamma_b and each bead's body-frame offset.
  *
- * Scope: every body fixed (bead velocities zero, positions constant over the window) and a
- * deterministic fluid (kT = 0); boundary masks allowed.  The adjoint of one step is the
- * transpose of each of its parts, taken in reverse order:
+ * Scope: a deterministic fluid (kT = 0), one MD step per fluid step, no excluded volume;
+ * boundary masks allowed; bodies fixed or free.  The window's initial state (populations and
+ * body states, including the force and torque of the step before the window) is held fixed.
+ * The adjoint of one step is the transpose of each of its parts, taken in reverse order:
  *   streaming with halfway bounce-back  ->  lambda*_i(y) = lambda_i(y + c_i) if y + c_i is a
  *                                           fluid node, else lambda_opp(i)(y);
  *   collision f* = C(f, F)               ->  vector-Jacobian product of the mode-space collision
@@ -19,8 +20,17 @@
  *   friction F_k = gamma u_k             ->  d gamma += lambda_Fk . u_k, lambda_uk = gamma lambda_Fk;
  *   interpolation u_k = sum w_c u(x_c)   ->  lambda_u(x_c) += w_c lambda_uk, and the position
  *                                           derivative of the weights;
- *   node velocity u = (j + g/2)/rho      ->  lambda_f_i += (c_i - u) . lambda_u / rho.
- * Every pre-collision state of the window is kept in memory (19 * N doubles per step).
+ *   node velocity u = (j + g/2)/rho      ->  lambda_f_i += (c_i - u) . lambda_u / rho;
+ * and for a free body (Sec. 1.2 virtual sites, Sec. 2.3 integrator) the transposes of
+ *   bead kinematics r_k = R + Q(q) b_k, v_k = V + Q(q)(omega x b_k);
+ *   force and torque sums F = sum F_k, tau = Q^T sum (r_k - R) x F_k;
+ *   the second half kick V += h F/2M, omega += h (tau - omega x I omega) / 2I;
+ *   the first half kick with the previous step's F and tau, the drift R += h V and the
+ *   rotation q <- (q (x) (cos(h|w|/2), sin(h|w|/2) w/|w|)) / norm;
+ * with the adjoint of the body state carried from step to step.  The rotation matrix is
+ * differentiated entry by entry in the quaternion's components.
+ * Every pre-collision state of the window is kept in memory (19 * N doubles per step), and
+ * every body state before each step.
  */
 #include "oracle.h"
 
@@ -37,6 +47,8 @@ int orc_box_body(const orc_sim* s, int b, const double** offsets, int* n_beads, 
                  double quat[4], double* gamma, int* fixed);
 double orc_box_kT(const orc_sim* s);
 int orc_box_plain_md(const orc_sim* s);
+int orc_box_body_mass(const orc_sim* s, int b, double* mass, double inertia[3]);
+int orc_box_first_half(const orc_sim* s, int b, const double state[19], double h, double out[13]);
 
 /* the basis, its norms and the weights, read once into tables (the same values) */
 static double AE[19][19], AB[19], AW[19];
@@ -175,6 +187,46 @@ static void node_u(const double* f, int64_t N, int64_t x, const double gext[3], 
     *rho_out = rho;
 }
 
+/* A(w) d = d x (I w) + w x (I d), the derivative of w x I w along d; out = A(w)^T m         */
+static void euler_vjp(const double w[3], const double I[3], const double m[3], double out[3])
+{
+    const double Iw[3] = {I[0] * w[0], I[1] * w[1], I[2] * w[2]};
+    double a[3], b[3];
+    /* m . (d x Iw) = d . (Iw x m) */
+    a[0] = Iw[1] * m[2] - Iw[2] * m[1];
+    a[1] = Iw[2] * m[0] - Iw[0] * m[2];
+    a[2] = Iw[0] * m[1] - Iw[1] * m[0];
+    /* m . (w x I d) = (I d) . (m x w) */
+    b[0] = m[1] * w[2] - m[2] * w[1];
+    b[1] = m[2] * w[0] - m[0] * w[2];
+    b[2] = m[0] * w[1] - m[1] * w[0];
+    for (int k = 0; k < 3; ++k) out[k] = a[k] + I[k] * b[k];
+}
+
+static void cross3(const double a[3], const double b[3], double o[3])
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* partial derivatives of the rotation matrix entries with respect to q = (w, x, y, z)      */
+static void rotmat_partials(const double q[4], double d[4][3][3])
+{
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    const double dw[3][3] = {{0, -2 * z, 2 * y}, {2 * z, 0, -2 * x}, {-2 * y, 2 * x, 0}};
+    const double dx[3][3] = {{0, 2 * y, 2 * z}, {2 * y, -4 * x, -2 * w}, {2 * z, 2 * w, -4 * x}};
+    const double dy[3][3] = {{-4 * y, 2 * x, 2 * w}, {2 * x, 0, 2 * z}, {-2 * w, 2 * z, -4 * y}};
+    const double dz[3][3] = {{-4 * z, -2 * w, 2 * x}, {2 * w, -4 * z, 2 * y}, {2 * x, 2 * y, 0}};
+    memcpy(d[0], dw, sizeof dw);
+    memcpy(d[1], dx, sizeof dx);
+    memcpy(d[2], dy, sizeof dy);
+    memcpy(d[3], dz, sizeof dz);
+}
+
+/* body layout of orc_body_state: pos 0, quat 3, vel 7, omega 10, force 13, torque 16       */
+enum { S_POS = 0, S_QUAT = 3, S_VEL = 7, S_OM = 10, S_F = 13, S_T = 16, S_N = 19 };
+
 int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, const double* dJ_dF,
                 double* J_out, double* dJ_dgamma, double* dJ_doffsets)
 {
@@ -183,33 +235,34 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
     const int nx = dims[0], ny = dims[1], nz = dims[2];
     const int64_t N = (int64_t)nx * ny * nz;
     const uint8_t* mask = orc_box_mask(s);
+    const double h = 1.0;   /* one MD step per fluid step */
     if (orc_box_kT(s) != 0.0 || !orc_box_plain_md(s) || n_steps < 0) return -1;
     adj_tables();   /* before the parallel node loop */
 
-    /* bodies: fixed, constant bead positions */
     int total_beads = 0;
     for (int b = 0; b < n_bodies; ++b) {
         const double* off; int nb; double pos[3], q[4], gamma; int fixed;
-        if (orc_box_body(s, b, &off, &nb, pos, q, &gamma, &fixed) != 0 || !fixed) return -1;
+        if (orc_box_body(s, b, &off, &nb, pos, q, &gamma, &fixed) != 0) return -1;
         total_beads += nb;
     }
 
-    /* forward pass, keeping every pre-collision state and the bead forces */
+    /* forward pass, keeping every pre-collision state and every body state before each step
+     * (and after the last) */
+    const size_t nbs = (size_t)(n_bodies > 0 ? n_bodies : 1);
     double* states = (double*)malloc(sizeof(double) * 19 * N * (size_t)(n_steps + 1));
-    double* bead_F = (double*)malloc(sizeof(double) * 3 * (size_t)total_beads * (n_steps + 1));
-    if (!states || !bead_F) { free(states); free(bead_F); return -1; }
+    double* bst = (double*)malloc(sizeof(double) * S_N * nbs * (size_t)(n_steps + 1));
+    double* bead_F = (double*)malloc(sizeof(double) * 3 * (size_t)(total_beads > 0 ? total_beads : 1));
+    if (!states || !bst || !bead_F) { free(states); free(bst); free(bead_F); return -1; }
     double J = 0.0;
-    for (int n = 0; n < n_steps; ++n) {
+    for (int n = 0; n <= n_steps; ++n) {
+        for (int b = 0; b < n_bodies; ++b) orc_body_state(s, b, bst + ((size_t)n * nbs + b) * S_N);
+        if (n == n_steps) break;
         memcpy(states + (size_t)n * 19 * N, orc_box_f(s), sizeof(double) * 19 * N);
         orc_step(s, 1);
-        int k0 = 0;
         for (int b = 0; b < n_bodies; ++b) {
             double st[19];
             orc_body_state(s, b, st);
-            const double* off; int nb; double pos[3], q[4], gamma; int fixed;
-            orc_box_body(s, b, &off, &nb, pos, q, &gamma, &fixed);
-            for (int a = 0; a < 3; ++a) J += dJ_dF[((size_t)n * n_bodies + b) * 3 + a] * st[13 + a];
-            k0 += nb;
+            for (int a = 0; a < 3; ++a) J += dJ_dF[((size_t)n * n_bodies + b) * 3 + a] * st[S_F + a];
         }
     }
     memcpy(states + (size_t)n_steps * 19 * N, orc_box_f(s), sizeof(double) * 19 * N);
@@ -221,21 +274,29 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
     double* lam_F = (double*)calloc((size_t)3 * N, sizeof(double));
     double* lam_u = (double*)calloc((size_t)3 * N, sizeof(double));
     double* g = (double*)calloc((size_t)3 * N, sizeof(double));
-    double* dr = (double*)calloc((size_t)3 * total_beads, sizeof(double));
+    double* bstate = (double*)calloc(S_N * nbs, sizeof(double));       /* adjoint of the body state after the step */
+    double* pose = (double*)calloc(13 * nbs, sizeof(double));          /* pose of the step per body */
     for (int b = 0; b < n_bodies; ++b) dJ_dgamma[b] = 0.0;
+    for (int k = 0; k < 3 * total_beads; ++k) dJ_doffsets[k] = 0.0;
     for (int n = n_steps - 1; n >= 0; --n) {
         const double* f = states + (size_t)n * 19 * N;
-        /* spread force of step n, recomputed from f^n */
+        /* the pose of every body in step n, and the spread force recomputed from f^n */
         memset(g, 0, sizeof(double) * 3 * N);
         for (int b = 0, kb = 0; b < n_bodies; ++b) {
-            const double* off; int nb; double pos[3], q[4], gamma; int fixed;
-            orc_box_body(s, b, &off, &nb, pos, q, &gamma, &fixed);
+            const double* off; int nb; double pos0[3], q0[4], gamma; int fixed;
+            orc_box_body(s, b, &off, &nb, pos0, q0, &gamma, &fixed);
+            double* P = pose + 13 * (size_t)b;
+            orc_box_first_half(s, b, bst + ((size_t)n * nbs + b) * S_N, h, P);
             double R[3][3];
-            rotmat(q, R);
+            rotmat(P + S_QUAT, R);
             for (int k = 0; k < nb; ++k, ++kb) {
-                double r[3];
-                for (int a = 0; a < 3; ++a)
-                    r[a] = pos[a] + R[a][0] * off[3 * k] + R[a][1] * off[3 * k + 1] + R[a][2] * off[3 * k + 2];
+                const double* bk = off + 3 * k;
+                double r[3], v[3] = {0, 0, 0}, e[3];
+                cross3(P + S_OM, bk, e);
+                for (int a = 0; a < 3; ++a) {
+                    r[a] = P[S_POS + a] + R[a][0] * bk[0] + R[a][1] * bk[1] + R[a][2] * bk[2];
+                    if (!fixed) v[a] = P[S_VEL + a] + R[a][0] * e[0] + R[a][1] * e[1] + R[a][2] * e[2];
+                }
                 int64_t idx[8]; double w[8], uk[3] = {0, 0, 0};
                 orc_trilinear(nx, ny, nz, r, idx, w);
                 for (int c = 0; c < 8; ++c) {
@@ -244,10 +305,10 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
                     node_u(f, N, idx[c], p->g_ext, &rho, u);
                     for (int a = 0; a < 3; ++a) uk[a] += w[c] * u[a];
                 }
-                for (int a = 0; a < 3; ++a) bead_F[3 * (size_t)kb + a] = gamma * uk[a];
+                for (int a = 0; a < 3; ++a) bead_F[3 * (size_t)kb + a] = -gamma * (v[a] - uk[a]);
                 for (int c = 0; c < 8; ++c) {
                     if (mask[idx[c]]) continue;
-                    for (int a = 0; a < 3; ++a) g[3 * idx[c] + a] -= w[c] * gamma * uk[a];
+                    for (int a = 0; a < 3; ++a) g[3 * idx[c] + a] -= w[c] * h * bead_F[3 * (size_t)kb + a];
                 }
             }
         }
@@ -276,24 +337,67 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
                     for (int i = 0; i < 19; ++i) lam_n[i * N + here] = lin[i];
                     for (int a = 0; a < 3; ++a) lam_F[3 * here + a] = lF[a];
                 }
-        /* coupling transpose */
+        /* coupling and body transpose */
         memset(lam_u, 0, sizeof(double) * 3 * N);
         for (int b = 0, kb = 0; b < n_bodies; ++b) {
-            const double* off; int nb; double pos[3], q[4], gamma; int fixed;
-            orc_box_body(s, b, &off, &nb, pos, q, &gamma, &fixed);
+            const double* off; int nb; double pos0[3], q0[4], gamma; int fixed;
+            orc_box_body(s, b, &off, &nb, pos0, q0, &gamma, &fixed);
+            double mass, I[3];
+            orc_box_body_mass(s, b, &mass, I);
+            const double* P = pose + 13 * (size_t)b;
+            const double* in = bst + ((size_t)n * nbs + b) * S_N;         /* before step n */
+            const double* out = bst + ((size_t)(n + 1) * nbs + b) * S_N;  /* after step n */
+            double* ab = bstate + S_N * (size_t)b;                        /* adjoint of `out` */
             double R[3][3];
-            rotmat(q, R);
-            for (int k = 0; k < nb; ++k, ++kb) {
-                double r[3];
+            rotmat(P + S_QUAT, R);
+            /* second half kick: V_out = V_m + h F/2M, w_out = w_m + h (tau - w_m x I w_m)/2I */
+            double Fbar[3], taubar[3], Vmbar[3], wmbar[3], mu[3], Tbar[3], T[3], Qbar[3][3];
+            double Rcbar[3], qcbar[4];
+            for (int a = 0; a < 3; ++a) {
+                Fbar[a] = dJ_dF[((size_t)n * n_bodies + b) * 3 + a];
+                Tbar[a] = 0.0;
+            }
+            memset(Qbar, 0, sizeof Qbar);
+            if (!fixed) {
+                for (int a = 0; a < 3; ++a) {
+                    Fbar[a] += ab[S_F + a] + 0.5 * h * ab[S_VEL + a] / mass;
+                    mu[a] = 0.5 * h * ab[S_OM + a] / I[a];
+                    taubar[a] = ab[S_T + a] + mu[a];
+                    Vmbar[a] = ab[S_VEL + a];
+                    Rcbar[a] = ab[S_POS + a];
+                }
+                for (int a = 0; a < 4; ++a) qcbar[a] = ab[S_QUAT + a];
+                double em[3];
+                euler_vjp(P + S_OM, I, mu, em);
+                for (int a = 0; a < 3; ++a) wmbar[a] = ab[S_OM + a] - em[a];
+                /* tau = Q^T T with T the lab torque: T = Q tau */
+                for (int a = 0; a < 3; ++a) {
+                    T[a] = R[a][0] * out[S_T] + R[a][1] * out[S_T + 1] + R[a][2] * out[S_T + 2];
+                    Tbar[a] = R[a][0] * taubar[0] + R[a][1] * taubar[1] + R[a][2] * taubar[2];
+                }
                 for (int a = 0; a < 3; ++a)
-                    r[a] = pos[a] + R[a][0] * off[3 * k] + R[a][1] * off[3 * k + 1] + R[a][2] * off[3 * k + 2];
+                    for (int c = 0; c < 3; ++c) Qbar[a][c] += T[a] * taubar[c];
+            }
+            for (int k = 0; k < nb; ++k, ++kb) {
+                const double* bk = off + 3 * k;
+                double d[3], r[3], e[3], v[3] = {0, 0, 0};
+                cross3(P + S_OM, bk, e);
+                for (int a = 0; a < 3; ++a) {
+                    d[a] = R[a][0] * bk[0] + R[a][1] * bk[1] + R[a][2] * bk[2];
+                    r[a] = P[S_POS + a] + d[a];
+                    if (!fixed) v[a] = P[S_VEL + a] + R[a][0] * e[0] + R[a][1] * e[1] + R[a][2] * e[2];
+                }
                 int64_t idx[8]; double w[8];
                 orc_trilinear(nx, ny, nz, r, idx, w);
                 /* fractional position inside the cell, for the weight gradients */
-                double d[3];
-                for (int a = 0; a < 3; ++a) { const double sa = r[a] - 0.5; d[a] = sa - floor(sa); }
-                double lFk[3], uc[8][3], uk[3] = {0, 0, 0};
-                for (int a = 0; a < 3; ++a) lFk[a] = dJ_dF[((size_t)n * n_bodies + b) * 3 + a];
+                double fr[3];
+                for (int a = 0; a < 3; ++a) { const double sa = r[a] - 0.5; fr[a] = sa - floor(sa); }
+                const double* Fk = bead_F + 3 * (size_t)kb;
+                /* adjoint of the bead force: the objective and the body sums, the torque sum
+                 * T = sum d x F, and the spreading g -= w h F */
+                double lFk[3], uc[8][3], uk[3] = {0, 0, 0}, TxD[3];
+                cross3(Tbar, d, TxD);
+                for (int a = 0; a < 3; ++a) lFk[a] = Fbar[a] + TxD[a];
                 for (int c = 0; c < 8; ++c) {
                     for (int a = 0; a < 3; ++a) uc[c][a] = 0.0;
                     if (mask[idx[c]]) continue;
@@ -301,32 +405,121 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
                     node_u(f, N, idx[c], p->g_ext, &rho, uc[c]);
                     for (int a = 0; a < 3; ++a) {
                         uk[a] += w[c] * uc[c][a];
-                        lFk[a] -= w[c] * lam_F[3 * idx[c] + a];
+                        lFk[a] -= w[c] * h * lam_F[3 * idx[c] + a];
                     }
                 }
-                const double* Fk = bead_F + 3 * (size_t)kb;
-                for (int a = 0; a < 3; ++a) dJ_dgamma[b] += lFk[a] * uk[a];
-                double luk[3];
-                for (int a = 0; a < 3; ++a) luk[a] = gamma * lFk[a];
+                /* F_k = -gamma (v_k - u_k) */
+                double luk[3], lv[3];
+                for (int a = 0; a < 3; ++a) {
+                    dJ_dgamma[b] += lFk[a] * (uk[a] - v[a]);
+                    luk[a] = gamma * lFk[a];
+                    lv[a] = -gamma * lFk[a];
+                }
+                /* interpolation and spreading weights at r */
+                double rbar[3] = {0, 0, 0};
                 for (int c = 0; c < 8; ++c) {
                     if (mask[idx[c]]) continue;
                     const int o[3] = {c & 1, (c >> 1) & 1, c >> 2};
                     double gw[3];
                     for (int a = 0; a < 3; ++a) {
                         double prod = o[a] ? 1.0 : -1.0;
-                        for (int e = 0; e < 3; ++e)
-                            if (e != a) prod *= o[e] ? d[e] : 1.0 - d[e];
+                        for (int e2 = 0; e2 < 3; ++e2)
+                            if (e2 != a) prod *= o[e2] ? fr[e2] : 1.0 - fr[e2];
                         gw[a] = prod;
                     }
                     double su = 0.0, sF = 0.0;
                     for (int a = 0; a < 3; ++a) {
                         su += uc[c][a] * luk[a];
-                        sF += Fk[a] * lam_F[3 * idx[c] + a];
+                        sF += h * Fk[a] * lam_F[3 * idx[c] + a];
                         lam_u[3 * idx[c] + a] += w[c] * luk[a];
                     }
-                    for (int a = 0; a < 3; ++a) dr[3 * (size_t)kb + a] += gw[a] * (su - sF);
+                    for (int a = 0; a < 3; ++a) rbar[a] += gw[a] * (su - sF);
                 }
+                /* r = R + d, d = Q b, and d enters T = sum d x F */
+                double dbar[3], FxT[3];
+                cross3(Fk, Tbar, FxT);
+                for (int a = 0; a < 3; ++a) dbar[a] = rbar[a] + (fixed ? 0.0 : FxT[a]);
+                double* ob = dJ_doffsets + 3 * (size_t)kb;
+                for (int a = 0; a < 3; ++a)
+                    ob[a] += R[0][a] * dbar[0] + R[1][a] * dbar[1] + R[2][a] * dbar[2];
+                if (fixed) continue;
+                for (int a = 0; a < 3; ++a) {
+                    Rcbar[a] += rbar[a];
+                    for (int c = 0; c < 3; ++c) Qbar[a][c] += dbar[a] * bk[c];
+                }
+                /* v = V_m + Q e, e = w_m x b */
+                double ebar[3], bxe[3], exw[3];
+                for (int a = 0; a < 3; ++a) {
+                    Vmbar[a] += lv[a];
+                    for (int c = 0; c < 3; ++c) Qbar[a][c] += lv[a] * e[c];
+                    ebar[a] = R[0][a] * lv[0] + R[1][a] * lv[1] + R[2][a] * lv[2];
+                }
+                cross3(bk, ebar, bxe);
+                cross3(ebar, P + S_OM, exw);
+                for (int a = 0; a < 3; ++a) { wmbar[a] += bxe[a]; ob[a] += exw[a]; }
             }
+            if (fixed) continue;
+            /* rotation matrix of the step's quaternion */
+            double dQ[4][3][3];
+            rotmat_partials(P + S_QUAT, dQ);
+            for (int j = 0; j < 4; ++j)
+                for (int a = 0; a < 3; ++a)
+                    for (int c = 0; c < 3; ++c) qcbar[j] += Qbar[a][c] * dQ[j][a][c];
+            /* first half: q_c = p/|p|, p = q_in (x) dq(w_m) (q_c = q_in when w_m = 0) */
+            const double* qi = in + S_QUAT;
+            const double* wm = P + S_OM;
+            double qibar[4];
+            const double wn = sqrt(wm[0] * wm[0] + wm[1] * wm[1] + wm[2] * wm[2]);
+            if (wn > 0.0) {
+                const double ang = 0.5 * h * wn;
+                const double dq[4] = {cos(ang), sin(ang) * wm[0] / wn, sin(ang) * wm[1] / wn,
+                                      sin(ang) * wm[2] / wn};
+                double pq[4];
+                pq[0] = qi[0] * dq[0] - qi[1] * dq[1] - qi[2] * dq[2] - qi[3] * dq[3];
+                pq[1] = qi[0] * dq[1] + qi[1] * dq[0] + qi[2] * dq[3] - qi[3] * dq[2];
+                pq[2] = qi[0] * dq[2] - qi[1] * dq[3] + qi[2] * dq[0] + qi[3] * dq[1];
+                pq[3] = qi[0] * dq[3] + qi[1] * dq[2] - qi[2] * dq[1] + qi[3] * dq[0];
+                const double np = sqrt(pq[0] * pq[0] + pq[1] * pq[1] + pq[2] * pq[2] + pq[3] * pq[3]);
+                const double* qc = P + S_QUAT;
+                const double qq = qc[0] * qcbar[0] + qc[1] * qcbar[1] + qc[2] * qcbar[2] + qc[3] * qcbar[3];
+                double pb[4];
+                for (int a = 0; a < 4; ++a) pb[a] = (qcbar[a] - qc[a] * qq) / np;
+                /* product rule of the quaternion product, component by component */
+                qibar[0] = pb[0] * dq[0] + pb[1] * dq[1] + pb[2] * dq[2] + pb[3] * dq[3];
+                qibar[1] = -pb[0] * dq[1] + pb[1] * dq[0] - pb[2] * dq[3] + pb[3] * dq[2];
+                qibar[2] = -pb[0] * dq[2] + pb[1] * dq[3] + pb[2] * dq[0] - pb[3] * dq[1];
+                qibar[3] = -pb[0] * dq[3] - pb[1] * dq[2] + pb[2] * dq[1] + pb[3] * dq[0];
+                double dqbar[4];
+                dqbar[0] = pb[0] * qi[0] + pb[1] * qi[1] + pb[2] * qi[2] + pb[3] * qi[3];
+                dqbar[1] = -pb[0] * qi[1] + pb[1] * qi[0] + pb[2] * qi[3] - pb[3] * qi[2];
+                dqbar[2] = -pb[0] * qi[2] - pb[1] * qi[3] + pb[2] * qi[0] + pb[3] * qi[1];
+                dqbar[3] = -pb[0] * qi[3] + pb[1] * qi[2] - pb[2] * qi[1] + pb[3] * qi[0];
+                /* dq = (cos(h n/2), s(n) w) with n = |w|, s(n) = sin(h n/2)/n */
+                const double sn = sin(ang) / wn;
+                const double dsn = (0.5 * h * cos(ang) / wn - sin(ang) / (wn * wn));
+                const double wdq = wm[0] * dqbar[1] + wm[1] * dqbar[2] + wm[2] * dqbar[3];
+                for (int a = 0; a < 3; ++a)
+                    wmbar[a] += -sin(ang) * 0.5 * h * (wm[a] / wn) * dqbar[0] + sn * dqbar[1 + a] +
+                                dsn * (wm[a] / wn) * wdq;
+            } else {
+                for (int a = 0; a < 4; ++a) qibar[a] = qcbar[a];
+            }
+            /* drift R_c = R_in + h V_m; kick V_m = V_in + h F_prev/2M;
+             * w_m = w_in + h (tau_prev - w_in x I w_in)/2I */
+            double mu2[3], em2[3];
+            for (int a = 0; a < 3; ++a) {
+                Vmbar[a] += h * Rcbar[a];
+                mu2[a] = 0.5 * h * wmbar[a] / I[a];
+            }
+            euler_vjp(in + S_OM, I, mu2, em2);
+            for (int a = 0; a < 3; ++a) {
+                ab[S_POS + a] = Rcbar[a];
+                ab[S_VEL + a] = Vmbar[a];
+                ab[S_OM + a] = wmbar[a] - em2[a];
+                ab[S_F + a] = 0.5 * h * Vmbar[a] / mass;
+                ab[S_T + a] = mu2[a];
+            }
+            for (int a = 0; a < 4; ++a) ab[S_QUAT + a] = qibar[a];
         }
         /* node velocities depend on f^n */
         for (int64_t x = 0; x < N; ++x) {
@@ -343,20 +536,9 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
         }
         double* t = lam; lam = lam_n; lam_n = t;
     }
-    /* offsets: r_k = R + Q b_k */
-    for (int b = 0, kb = 0; b < n_bodies; ++b) {
-        const double* off; int nb; double pos[3], q[4], gamma; int fixed;
-        orc_box_body(s, b, &off, &nb, pos, q, &gamma, &fixed);
-        double R[3][3];
-        rotmat(q, R);
-        for (int k = 0; k < nb; ++k, ++kb)
-            for (int a = 0; a < 3; ++a)
-                dJ_doffsets[3 * (size_t)kb + a] = R[0][a] * dr[3 * (size_t)kb] +
-                                                  R[1][a] * dr[3 * (size_t)kb + 1] +
-                                                  R[2][a] * dr[3 * (size_t)kb + 2];
-    }
     /* the box ends at the last state of the window */
     orc_box_set_f(s, states + (size_t)n_steps * 19 * N);
-    free(states); free(bead_F); free(lam); free(lam_n); free(lam_F); free(lam_u); free(g); free(dr);
+    free(states); free(bst); free(bead_F); free(lam); free(lam_n); free(lam_F); free(lam_u);
+    free(g); free(bstate); free(pose);
     return 0;
 }

@@ -792,6 +792,37 @@ int orc_box_plain_md(const orc_sim* s)
         if (s->bodies[b].n_ev > 0) return 0;
     return 1;
 }
+int orc_box_body_mass(const orc_sim* s, int b, double* mass, double inertia[3])
+{
+    if (b < 0 || b >= s->n_bodies) return -1;
+    *mass = s->bodies[b].mass;
+    for (int a = 0; a < 3; ++a) inertia[a] = s->bodies[b].inertia[a];
+    return 0;
+}
+/* the first half of an MD step of length h (body_first_half) applied to a state of body b
+ * in the layout of orc_body_state: out = position, quaternion, velocity and body-frame
+ * angular velocity that the step's coupling uses                                          */
+int orc_box_first_half(const orc_sim* s, int b, const double state[19], double h, double out[13])
+{
+    if (b < 0 || b >= s->n_bodies) return -1;
+    orc_body t = s->bodies[b];
+    for (int a = 0; a < 3; ++a) {
+        t.pos[a] = state[a];
+        t.vel[a] = state[7 + a];
+        t.omega[a] = state[10 + a];
+        t.force[a] = state[13 + a];
+        t.torque_body[a] = state[16 + a];
+    }
+    for (int a = 0; a < 4; ++a) t.quat[a] = state[3 + a];
+    body_first_half(&t, h);
+    for (int a = 0; a < 3; ++a) {
+        out[a] = t.pos[a];
+        out[7 + a] = t.vel[a];
+        out[10 + a] = t.omega[a];
+    }
+    for (int a = 0; a < 4; ++a) out[3 + a] = t.quat[a];
+    return 0;
+}
 int orc_box_body(const orc_sim* s, int b, const double** offsets, int* n_beads, double pos[3],
                  double quat[4], double* gamma, int* fixed)
 {

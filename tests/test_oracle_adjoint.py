@@ -101,3 +101,85 @@ def test_window_gradient_matches_finite_difference(masked):
             fd = (_run(shape, mask, params, op, centre, q, gamma, steps, weights)
                   - _run(shape, mask, params, om, centre, q, gamma, steps, weights)) / (2 * h)
             assert abs(fd - do[k, a]) < 1e-5 * np.abs(do).max() + 1e-13, (k, a, fd, do[k, a])
+
+
+def _free_case(masked):
+    """A free sphere (anisotropic inertia, moving and spinning at the start) and a fixed
+    smaller body in the same box."""
+    shape, mask, params, offs, centre, q = _case(masked)
+    rng = np.random.default_rng(31 if masked else 32)
+    # the start is shifted so that no bead of the free body passes within 1e-3 of a cell
+    # face during the window
+    free = dict(offs=offs, mass=40.0, inertia=(40.0, 45.0, 50.0), centre=centre + 0.047, quat=q,
+                vel=(0.004, -0.002, 0.003), omega=(0.01, -0.015, 0.02), gamma=W.GAMMA_FREE)
+    fixed_centre = np.array([2.3, 9.1, 8.2]) if not masked else np.array([4.3, 9.6, 1.7])
+    fixed = dict(offs=W.sphere_beads(1.0, 6), centre=fixed_centre,
+                 quat=W.random_quaternion(rng), gamma=0.5 * W.GAMMA_FIXED)
+    return shape, mask, params, free, fixed
+
+
+def _run_free(shape, mask, params, free, fixed, steps, weights, adjoint=False, poses=None):
+    sim = po.OracleSim(shape, params)
+    if mask is not None:
+        sim.set_mask(mask)
+    sim.add_body(free["offs"], free["mass"], free["inertia"], free["centre"], quat=free["quat"],
+                 vel=free["vel"], omega=free["omega"], gamma=free["gamma"])
+    sim.add_body(fixed["offs"], 1.0, (1, 1, 1), fixed["centre"], quat=fixed["quat"],
+                 gamma=fixed["gamma"], fixed=True)
+    if adjoint:
+        return sim.adjoint(steps, weights)
+    J = 0.0
+    for n in range(steps):
+        sim.step(1)
+        for b in range(2):
+            st = sim.body_state(b)
+            J += float(weights[n, b] @ st["force"])
+            if poses is not None and b == 0:
+                poses.append((st["pos"].copy(), st["quat"].copy()))
+    return J
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_free_body_window_gradient_matches_finite_difference(masked):
+    """The reverse pass through the rigid-body integrator (both half kicks, the drift, the
+    quaternion rotation and the moving bead positions and velocities) against central
+    differences of J re-run by the forward oracle, for a free body next to a fixed one."""
+    from scipy.spatial.transform import Rotation
+    shape, mask, params, free, fixed = _free_case(masked)
+    steps = 12
+    rng = np.random.default_rng(19)
+    weights = np.zeros((steps, 2, 3))
+    weights[:, 0, 0] = 1.0 / steps
+    weights += 0.02 * rng.standard_normal(weights.shape)
+    J, dg, do = _run_free(shape, mask, params, free, fixed, steps, weights, adjoint=True)
+    poses = []
+    assert abs(J - _run_free(shape, mask, params, free, fixed, steps, weights, poses=poses)) < 1e-15
+    # the free body really moves and turns over the window
+    assert np.linalg.norm(poses[-1][0] - free["centre"]) > 0.02
+    # no bead of the free body comes near a cell face in any step (kinks of the weights)
+    gap = 1.0
+    for pos, q in poses:
+        Rm = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        frac = np.mod(pos + free["offs"] @ Rm.T - 0.5, 1.0)
+        gap = min(gap, float(np.minimum(frac, 1 - frac).min()))
+    assert gap > 1e-4, gap
+    h = 1e-6
+    for b, body in ((0, free), (1, fixed)):
+        bp, bm = dict(body), dict(body)
+        bp["gamma"] += h
+        bm["gamma"] -= h
+        args = ((bp, fixed) if b == 0 else (free, bp)), ((bm, fixed) if b == 0 else (free, bm))
+        fd = (_run_free(shape, mask, params, *args[0], steps, weights)
+              - _run_free(shape, mask, params, *args[1], steps, weights)) / (2 * h)
+        assert abs(fd - dg[b]) < 1e-6 * abs(fd) + 1e-12, (b, fd, dg[b])
+    scale = np.abs(do[:len(free["offs"])]).max()
+    for k in (0, 5, 11, 17):
+        for a in range(3):
+            op, om = dict(free), dict(free)
+            op["offs"] = free["offs"].copy()
+            om["offs"] = free["offs"].copy()
+            op["offs"][k, a] += h
+            om["offs"][k, a] -= h
+            fd = (_run_free(shape, mask, params, op, fixed, steps, weights)
+                  - _run_free(shape, mask, params, om, fixed, steps, weights)) / (2 * h)
+            assert abs(fd - do[k, a]) < 1e-5 * scale + 1e-13, (k, a, fd, do[k, a])
