@@ -344,7 +344,11 @@ int lb_set_tuning(lb_ctx* ctx, const lb_tuning* settings);
  * Objective J = sum_n sum_b a(n,b) . F_b(n) over the next n_steps steps, F_b(n) the summed
  * bead force on body b in step n (a = (1/T,0,0) for every step: time-averaged drag along x).
  * Derivatives with respect to every body's friction gamma and every bead's body-frame
- * offset.  Requires kT = 0 and every body fixed.
+ * offset, holding the window's initial state fixed (populations, body states, and the force
+ * and torque of the step before the window).  Bodies may be fixed or free: for a free body
+ * the derivative runs through the rigid-body integrator of Sec. 2.3 as well (both half
+ * kicks, the drift, the quaternion rotation and the moving bead positions and velocities),
+ * which adds a few hundred bytes per body and step to the workspace.  Requires kT = 0.
  * The call advances the context by n_steps steps (its state afterwards is that of
  * lb_rb_step(n_steps)), keeping the post-collision state every checkpoint_every steps in the
  * caller's device workspace dev_ws (256-byte aligned, at least
@@ -357,7 +361,7 @@ int lb_set_tuning(lb_ctx* ctx, const lb_tuning* settings);
  *   dJ_dgamma   [n_bodies];
  *   dJ_doffsets [n_beads][3], body frame.
  * Synchronises the stream.  Errors: LB_ERR_ARG (window, workspace, missing arrays),
- * LB_ERR_STATE (kT > 0, a free body, more than one MD step per fluid step, excluded-volume
+ * LB_ERR_STATE (kT > 0, more than one MD step per fluid step, excluded-volume
  * or static sites, or a mask with a row of several fluid runs).  The adjoint runs in the context precision; its
  * atomic accumulation of sampled-velocity adjoints into the population adjoint is not
  * order-deterministic.                                                                    */

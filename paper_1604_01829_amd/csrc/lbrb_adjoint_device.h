@@ -10,16 +10,18 @@ namespace lbrb {
 constexpr int kAdjBeadBlock = 64;
 
 // Bead pass for lane `tid` (8 lanes per bead, one per stencil corner): the transpose of
-// spreading, friction and interpolation, and of the velocity sampling.  Lanes past the last
-// bead return at once (the 8 lanes of a bead leave together).
-template <typename Real>
+// spreading, friction and interpolation, and of the velocity sampling; with FREE also of the
+// torque sum and of the bead kinematics (the adjoint of the body force and torque comes from
+// A.body_adj).  Lanes past the last bead return at once (the 8 lanes of a bead leave
+// together).
+template <typename Real, bool FREE = false>
 __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
 {
     const StepArgs<Real>& a = A.a;
     const int bead = tid >> 3, corner = tid & 7;
     if (bead >= A.n_beads) return;   // the 8 lanes of a bead leave together
-    // the bead record the forward coupling read: lab position, friction, replica geometry
-    // (the bodies are fixed, so one record serves every step of the window)
+    // the bead record the forward coupling of this step read: lab position, arm, velocity,
+    // friction, replica geometry
     const BeadRec X = load_record(A.recs + bead);
     const int32_t body = A.beads[bead].body;
     const double r[3] = {X.r[0], X.r[1], X.r[2]};
@@ -79,10 +81,17 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
     const double* Fk = A.bead_force + 3 * (int64_t)bead;
     const double* an = A.weights + 3 * (int64_t)body;
     double lFk[3], luk[3];
-    for (int ax = 0; ax < 3; ++ax) {
-        lFk[ax] = an[ax] - s6[3 + ax];
-        luk[ax] = X.gamma * lFk[ax];
+    if constexpr (FREE) {
+        // the body force F = sum F_k and the lab torque T = sum d_k x F_k
+        const double* bj = A.body_adj + 6 * (int64_t)body;
+        const double* dv = X.dv;
+        lFk[0] = bj[0] + (bj[4] * dv[2] - bj[5] * dv[1]) - s6[3];
+        lFk[1] = bj[1] + (bj[5] * dv[0] - bj[3] * dv[2]) - s6[4];
+        lFk[2] = bj[2] + (bj[3] * dv[1] - bj[4] * dv[0]) - s6[5];
+    } else {
+        for (int ax = 0; ax < 3; ++ax) lFk[ax] = an[ax] - s6[3 + ax];
     }
+    for (int ax = 0; ax < 3; ++ax) luk[ax] = X.gamma * lFk[ax];
     // position derivative through the interpolation and the spreading weights of this corner
     double dr[3] = {0.0, 0.0, 0.0};
     if (local >= 0) {
@@ -100,16 +109,51 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
 #pragma unroll
     for (int m = 1; m < 8; m <<= 1)
         for (int ax = 0; ax < 3; ++ax) dr[ax] += __shfl_xor(dr[ax], m, 8);
-    if (corner == 0) {
-        double jp = 0.0, dg = 0.0;
+    if (corner != 0) return;
+    double jp = 0.0, dg = 0.0;
+    if constexpr (FREE) {
+        // F_k = -gamma (v_k - u_k); the arm d = Q b enters the torque, d and v = V + w x d the
+        // kinematics; dr is kept in the body frame of the step's pose
+        const double* bj = A.body_adj + 6 * (int64_t)body;
+        const Pose& P = A.snap[body].pose[A.pose_par];
+        const double* w = P.omega_lab;
+        const double* d = X.dv;
+        double lv[3], db[3], y[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            jp += an[ax] * Fk[ax];
+            dg += lFk[ax] * (s6[ax] - X.v[ax]);
+            lv[ax] = -X.gamma * lFk[ax];
+        }
+        db[0] = dr[0] + (Fk[1] * bj[5] - Fk[2] * bj[4]);
+        db[1] = dr[1] + (Fk[2] * bj[3] - Fk[0] * bj[5]);
+        db[2] = dr[2] + (Fk[0] * bj[4] - Fk[1] * bj[3]);
+        y[0] = db[0] + (lv[1] * w[2] - lv[2] * w[1]);
+        y[1] = db[1] + (lv[2] * w[0] - lv[0] * w[2]);
+        y[2] = db[2] + (lv[0] * w[1] - lv[1] * w[0]);
+        for (int ax = 0; ax < 3; ++ax)
+            A.dr[3 * (int64_t)bead + ax] += P.rot[ax] * y[0] + P.rot[3 + ax] * y[1] + P.rot[6 + ax] * y[2];
+        const double wd[3] = {w[1] * d[2] - w[2] * d[1], w[2] * d[0] - w[0] * d[2],
+                              w[0] * d[1] - w[1] * d[0]};
+        double* o = A.bead_sums + kBeadSumWords * (int64_t)bead;
+        for (int ax = 0; ax < 3; ++ax) {
+            o[ax] = dr[ax];
+            o[3 + ax] = lv[ax];
+        }
+        o[6] = (d[1] * db[2] - d[2] * db[1]) + (wd[1] * lv[2] - wd[2] * lv[1]);
+        o[7] = (d[2] * db[0] - d[0] * db[2]) + (wd[2] * lv[0] - wd[0] * lv[2]);
+        o[8] = (d[0] * db[1] - d[1] * db[0]) + (wd[0] * lv[1] - wd[1] * lv[0]);
+        o[9] = d[1] * lv[2] - d[2] * lv[1];
+        o[10] = d[2] * lv[0] - d[0] * lv[2];
+        o[11] = d[0] * lv[1] - d[1] * lv[0];
+    } else {
         for (int ax = 0; ax < 3; ++ax) {
             jp += an[ax] * Fk[ax];
             dg += lFk[ax] * s6[ax];
             A.dr[3 * (int64_t)bead + ax] += dr[ax];
         }
-        A.Jpart[bead] += jp;
-        A.dgam[bead] += dg;
     }
+    A.Jpart[bead] += jp;
+    A.dgam[bead] += dg;
 }
 
 }  // namespace lbrb

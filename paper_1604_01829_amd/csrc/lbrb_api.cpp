@@ -744,13 +744,23 @@ int build_wca(lb_ctx* c)
 // Layout of the caller's reverse-pass workspace: checkpoints of the post-collision state
 // every K steps, K-1 slots for the states recomputed inside one segment, two adjoint
 // population buffers, the adjoints of the node force and velocity, the per-step objective
-// weights, the per-bead accumulators, and room to restore the bead forces afterwards.
+// weights, the per-bead accumulators, and room to restore the bead forces afterwards; for
+// free bodies the body table before every step of the window (and after the last), the
+// adjoint of the body states, of each step's body force and torque, the bead pass's sums
+// and room to restore the bead records.
 struct AdjPlan {
     int32_t n_ck = 0, n_seg = 0;
     size_t state = 0;
     size_t off_ck, off_seg, off_lam0, off_lam1, off_lamF, off_w, off_dr, off_dg, off_J,
-        off_bf, off_save, total;
+        off_bf, off_save, off_snap, off_badj, off_bin, off_bsum, off_recs, total;
 };
+
+bool any_free(const lb_ctx* c)
+{
+    for (const Body& B : c->bodies0)
+        if (!B.fixed) return true;
+    return false;
+}
 
 bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
 {
@@ -776,16 +786,29 @@ bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
     ap.off_J = take(sizeof(double) * nb);
     ap.off_bf = take(sizeof(double) * 6 * nb);
     ap.off_save = take(sizeof(double) * 6 * nb);
+    if (any_free(c)) {
+        ap.off_snap = take(sizeof(Body) * nbod * ((size_t)T + 1));
+        ap.off_badj = take(sizeof(double) * kBodyAdjWords * nbod);
+        ap.off_bin = take(sizeof(double) * 6 * nbod);
+        ap.off_bsum = take(sizeof(double) * kBeadSumWords * nb);
+        ap.off_recs = take(sizeof(BeadRec) * nb);
+    } else {
+        ap.off_snap = ap.off_badj = ap.off_bin = ap.off_bsum = ap.off_recs = 0;
+    }
     ap.total = o;
     return true;
 }
 
-// forward step without finishing the bodies (fixed bodies: nothing to finish), src -> dst
+// forward step without finishing the bodies, src -> dst.  Fixed bodies: the records hold the
+// only pose; free bodies: the records are first written from the stored body table `bodies`
+// of the step.
 template <typename Real>
-void enqueue_replay(lb_ctx* c, hipStream_t s, const void* src, void* dst, int64_t step)
+void enqueue_replay(lb_ctx* c, hipStream_t s, const void* src, void* dst, int64_t step,
+                    const Body* bodies)
 {
     StepArgs<Real> ag[2] = {step_args_on<Real>(c, 0, src, dst), step_args_on<Real>(c, 1, src, dst)};
     for (auto& a : ag) a.step_arg = step;
+    if (bodies) launch_records_from_poses(bodies, (int)(step & 1), c->d_beads, c->d_recs, c->n_beads, s);
     if (c->n_beads > 0) launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], couple_args(c), s);
     for (int g = 0; g < 2; ++g)
         if (ag[g].n_tiles > 0)
@@ -798,10 +821,12 @@ void enqueue_replay(lb_ctx* c, hipStream_t s, const void* src, void* dst, int64_
 // launch); prev_src: the state of step - 1, whose coupling then runs in this step's bead launch
 // (nullptr: none, as at the start of a segment, whose states the replay rewrites first).
 // The bead forces of a reverse step go to one of two buffers by the parity of n.
+// snap: with free bodies, the stored body tables of the window (the step's records are
+// written from table n, the body pass reads tables n and n + 1); prev_src is then null.
 template <typename Real>
 void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, const Real* lam_next,
                      Real* lam_cur, char* ws, const AdjPlan& ap, int64_t n, bool coupled,
-                     const void* prev_src)
+                     const void* prev_src, const Body* snap)
 {
     double* bf = (double*)(ws + ap.off_bf);
     const size_t nbf = 3 * (size_t)std::max<int32_t>(c->n_beads, 1);
@@ -827,11 +852,30 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
         X.dgam = (double*)(ws + ap.off_dg);
         X.Jpart = (double*)(ws + ap.off_J);
         X.n_beads = c->n_beads;
+        if (snap) {
+            X.body_adj = (const double*)(ws + ap.off_bin);
+            X.snap = snap + (size_t)c->n_bodies * n;
+            X.pose_par = (int32_t)(step & 1);
+            X.bead_sums = (double*)(ws + ap.off_bsum);
+        }
     }
     const int cg = any_masked(c) ? 1 : 0;
+    if (snap && c->n_beads > 0)
+        launch_records_from_poses(snap + (size_t)c->n_bodies * n, (int)(step & 1), c->d_beads,
+                                  c->d_recs, c->n_beads, s);
     if (c->n_beads > 0 && !coupled) launch_couple<Real>(A[cg].a, coupling(n), s);
     for (int g = 0; g < 2; ++g) launch_adjoint_step<Real>(A[g], g == 1, s);
     if (c->n_beads <= 0) return;
+    if (snap) {
+        const Body* in = snap + (size_t)c->n_bodies * n;
+        double* badj = (double*)(ws + ap.off_badj);
+        launch_adjoint_body_pre(in, (int)(step & 1), A[cg].weights, badj, (double*)(ws + ap.off_bin),
+                                c->n_bodies, s);
+        launch_adjoint_beads<Real>(A[cg], s);
+        launch_adjoint_body_post(in, in + c->n_bodies, (int)(step & 1), (const double*)(ws + ap.off_bsum),
+                                 badj, c->n_bodies, s);
+        return;
+    }
     if (prev_src) {
         StepArgs<Real> pa = step_args_on<Real>(c, cg, prev_src, nullptr);
         pa.step_arg = step - 1;
@@ -849,6 +893,11 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
     auto ck = [&](int k) { return (void*)(ws + ap.off_ck + ap.state * k); };
     auto seg = [&](int k) { return (void*)(ws + ap.off_seg + ap.state * k); };
     const int64_t step0 = c->step;
+    // free bodies: the body table before every step of the window and after the last
+    const bool fb = any_free(c);
+    Body* snap = fb ? (Body*)(ws + ap.off_snap) : nullptr;
+    const size_t table = sizeof(Body) * (size_t)c->n_bodies;
+    if (fb) HIP_TRY(c, hipMemcpyAsync(snap, c->d_bodies, table, hipMemcpyDeviceToDevice, s));
     // forward window, keeping a checkpoint every K steps
     for (int32_t n = 0; n < T; ++n) {
         if (n % K == 0)
@@ -856,8 +905,14 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
         HIP_TRY(c, enqueue_step<Real>(c, s, c->cur, nullptr, c->step, false));
         c->cur ^= 1;
         c->step += 1;
+        if (fb)
+            HIP_TRY(c, hipMemcpyAsync(snap + (size_t)c->n_bodies * (n + 1), c->d_bodies, table,
+                                      hipMemcpyDeviceToDevice, s));
     }
     const size_t nb = (size_t)std::max<int32_t>(c->n_beads, 1);
+    if (fb)
+        HIP_TRY(c, hipMemcpyAsync(ws + ap.off_recs, c->d_recs, sizeof(BeadRec) * nb,
+                                  hipMemcpyDeviceToDevice, s));
     double* save = (double*)(ws + ap.off_save);
     HIP_TRY(c, hipMemcpyAsync(save, c->d_bead_force, sizeof(double) * 3 * nb, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(save + 3 * nb, c->d_bead_torque, sizeof(double) * 3 * nb,
@@ -870,15 +925,18 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
         const int32_t n0 = sg * K, n1 = std::min(T, n0 + K);
         auto state = [&](int32_t j) { return j == 0 ? ck(sg) : seg(j - 1); };
         for (int32_t j = 0; j + 1 < n1 - n0; ++j)
-            enqueue_replay<Real>(c, s, state(j), state(j + 1), step0 + n0 + j);
+            enqueue_replay<Real>(c, s, state(j), state(j + 1), step0 + n0 + j,
+                                 fb ? snap + (size_t)c->n_bodies * (n0 + j) : nullptr);
         HIP_TRY(c, hipGetLastError());
         for (int32_t n = n1 - 1; n >= n0; --n) {
             // the coupling of step n - 1 joins this step's bead launch when its state is at
             // hand and nothing in between rewrites the force accumulators: inside a segment,
-            // and across segments of one step each (no replays)
-            const void* prev = n > n0 ? state(n - 1 - n0) : (K == 1 && n > 0 ? ck(n - 1) : nullptr);
+            // and across segments of one step each (no replays); not with free bodies, whose
+            // records change from step to step
+            const void* prev = fb ? nullptr
+                                  : n > n0 ? state(n - 1 - n0) : (K == 1 && n > 0 ? ck(n - 1) : nullptr);
             enqueue_adjoint<Real>(c, s, state(n - n0), step0 + n, lam[nxt], lam[nxt ^ 1], ws, ap, n,
-                                  coupled, prev);
+                                  coupled, prev, snap);
             coupled = prev != nullptr;
             nxt ^= 1;
         }
@@ -887,6 +945,9 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
     HIP_TRY(c, hipMemcpyAsync(c->d_bead_force, save, sizeof(double) * 3 * nb, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->d_bead_torque, save + 3 * nb, sizeof(double) * 3 * nb,
                               hipMemcpyDeviceToDevice, s));
+    if (fb)
+        HIP_TRY(c, hipMemcpyAsync(c->d_recs, ws + ap.off_recs, sizeof(BeadRec) * nb,
+                                  hipMemcpyDeviceToDevice, s));
     return LB_OK;
 }
 
@@ -1770,8 +1831,6 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     if (md_steps(c) > 1 || any_ev || c->n_sites > 0)
         return fail(c, LB_ERR_STATE,
                     "the reverse pass needs one MD step per fluid step and no excluded volume");
-    for (const Body& B : c->bodies0)
-        if (!B.fixed) return fail(c, LB_ERR_STATE, "the reverse pass needs fixed bodies");
     for (int r = 0; r < c->n_rep; ++r)
         if (c->reps[r].masked == 2)
             return fail(c, LB_ERR_STATE, "the reverse pass needs masks of one fluid run per row");
@@ -1788,6 +1847,9 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_dr, 0, sizeof(double) * 3 * nb, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_dg, 0, sizeof(double) * nb, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_J, 0, sizeof(double) * nb, s));
+    if (any_free(c))
+        HIP_TRY(c, hipMemsetAsync(ws + ap.off_badj, 0,
+                                  sizeof(double) * kBodyAdjWords * std::max<int32_t>(c->n_bodies, 1), s));
     {
         const int rc = prepare_bodies(c, s);
         if (rc != LB_OK) return rc;
@@ -1809,6 +1871,7 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     double Jsum = 0.0;
     for (int32_t k = 0; k < c->n_beads; ++k) Jsum += jp[k];
     if (J) *J = Jsum;
+    const bool body_frame = any_free(c);   // the bead pass then accumulated body-frame values
     for (int32_t b = 0; b < c->n_bodies; ++b) {
         const Body& B = bs[b];
         const double* R = B.pose[parity].rot;   // body -> lab; a fixed body keeps one pose
@@ -1818,7 +1881,8 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
             const double* d = &dr[3 * (size_t)k];
             const size_t u = (size_t)B.first_bead + c->bead_user[k];   // caller's order
             for (int a = 0; a < 3; ++a)
-                dJ_doffsets[3 * u + a] = R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2];
+                dJ_doffsets[3 * u + a] =
+                    body_frame ? d[a] : R[a] * d[0] + R[3 + a] * d[1] + R[6 + a] * d[2];
         }
         dJ_dgamma[b] = g;
     }

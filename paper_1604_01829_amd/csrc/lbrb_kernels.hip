@@ -958,6 +958,27 @@ void launch_body_predict(const BodyArgs& b, int parity, hipStream_t s)
     hipLaunchKernelGGL(body_predict_kernel, dim3(b.n_bodies), dim3(256), 0, s, b, parity);
 }
 
+// the pose part of every bead record from a stored pose of its body, one thread per bead
+__global__ __launch_bounds__(256) void records_from_poses_kernel(const Body* bodies, int par,
+                                                                 const Bead* beads, BeadRec* recs,
+                                                                 int n_beads)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n_beads) return;
+    const Bead bd = beads[k];
+    const Body& B = bodies[bd.body];
+    double r[3];
+    write_bead_pose(B.pose[par], B.fixed != 0, bd.off, recs[k], r);
+}
+
+void launch_records_from_poses(const Body* bodies, int par, const Bead* beads, BeadRec* recs,
+                               int n_beads, hipStream_t s)
+{
+    if (n_beads <= 0) return;
+    hipLaunchKernelGGL(records_from_poses_kernel, dim3((n_beads + 255) / 256), dim3(256), 0, s,
+                       bodies, par, beads, recs, n_beads);
+}
+
 // finish every body after MD step k of the fluid step (one workgroup per body)
 __global__ __launch_bounds__(256) void body_substep_kernel(const BodyArgs ba,
                                                            const int64_t* step_ptr,

@@ -233,9 +233,10 @@ void launch_observe(const StepArgs<Real>& a, bool masked, int32_t tile0, int32_t
                     Real* fields, double* partials, double* pops_out, hipStream_t s);
 
 // ------------------------------------------------------------------ reverse pass
-// Arguments of one reverse step (fixed bodies, deterministic fluid).  The forward state of the
-// step is pulled from a.src (post-collision populations of the previous step); the spread
-// force of the step must have been recomputed into a.gforce / a.flags by the coupling kernel.
+// Arguments of one reverse step (deterministic fluid).  The forward state of the step is
+// pulled from a.src (post-collision populations of the previous step); the spread force of
+// the step must have been recomputed into a.gforce / a.flags by the coupling kernel, and the
+// bead records must hold the step's bead positions and velocities.
 template <typename Real>
 struct AdjArgs {
     StepArgs<Real> a;
@@ -250,7 +251,36 @@ struct AdjArgs {
     double* dgam;               // accumulated dJ/dgamma, per bead
     double* Jpart;              // accumulated objective, per bead
     int32_t n_beads;
+    // With free bodies (body_adj != null) the bead pass takes the adjoint of each body's force
+    // and lab torque from body_adj (6 per body), accumulates dr in the body frame of the
+    // step's pose (snap[body].pose[pose_par]) and leaves 12 sums per bead in bead_sums for
+    // the body pass: the adjoints of the bead position and velocity, the rotation sum
+    // d x dbar + (w x d) x vbar and d x vbar (d = r - R, dbar and vbar the adjoints of the
+    // arm and the velocity, w the lab angular velocity).  Without, dr is in the lab frame and
+    // the body force's adjoint is the weight.
+    const double* body_adj;
+    const Body* snap;
+    int32_t pose_par;
+    double* bead_sums;
 };
+
+// The body pass of a reverse step with free bodies (one MD step per fluid step).  in: the
+// bodies before the step (their pose of the step at pose[par]); out: after it; adj: the
+// adjoint of each body's state after the step (19 doubles: position, quaternion, velocity,
+// body-frame angular velocity, force, body-frame torque).  pre: writes the adjoint of the
+// step's body force and lab torque (6 per body) for the bead pass; post: adds the bead sums
+// and takes adj back through the second half kick, the drift, the rotation and the first
+// half kick, to the adjoint of the state before the step.  Fixed bodies: weights only.
+constexpr int kBodyAdjWords = 19;
+constexpr int kBeadSumWords = 12;
+void launch_adjoint_body_pre(const Body* in, int par, const double* weights, const double* adj,
+                             double* body_adj, int n_bodies, hipStream_t s);
+void launch_adjoint_body_post(const Body* in, const Body* out, int par, const double* bead_sums,
+                              double* adj, int n_bodies, hipStream_t s);
+// the pose part of every bead record from its body's pose[par] (the records a step's coupling
+// reads), for recomputing the steps of a window
+void launch_records_from_poses(const Body* bodies, int par, const Bead* beads, BeadRec* recs,
+                               int n_beads, hipStream_t s);
 
 // node pass: transposed streaming + collision VJP (writes lam_cur, lamF, consumes the force)
 template <typename Real>

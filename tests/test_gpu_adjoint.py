@@ -11,6 +11,9 @@
   gradients against the FP64 ones;
 - the same sphere over the first 40 steps (a window whose 41 states of 40 MB the oracle
   holds), FP64 and FP32 against the oracle's FP64 reverse pass;
+- a free body (moving and spinning, so the reverse pass runs through the rigid-body
+  integrator) next to a fixed one, periodic and in pores, FP64 and FP32, against the oracle's
+  reverse pass; the context afterwards continues exactly as one that only stepped forward;
 - the torch.autograd.Function wrapper; error codes.
 """
 import numpy as np
@@ -186,6 +189,95 @@ def test_adjoint_leaves_the_forward_state(precision):
     assert np.array_equal(s1.populations(), s2.populations())
 
 
+FREE = dict(mass=40.0, inertia=(40.0, 45.0, 50.0), vel=(0.004, -0.002, 0.003),
+            omega=(0.01, -0.015, 0.02))
+
+
+def _free_case(masked):
+    """Body 0 of _case made free (moving and spinning at the start, anisotropic inertia),
+    body 1 fixed.  The start is shifted so that no bead of the free body passes within 8e-4 of
+    a cell face during the window (so neither side crosses a kink of the weights)."""
+    shape, mask, pp, bodies = _case(masked)
+    offs, c, q, _ = bodies[0]
+    return shape, mask, pp, [(offs, c + 0.047, q, W.GAMMA_FREE), bodies[1]]
+
+
+def _gpu_free(shape, mask, pp, bodies, precision):
+    from paper_1604_01829_amd import lbrb
+    nb = sum(len(b[0]) for b in bodies)
+    params = lbrb.make_params(precision=precision, kT=0.0, max_bodies=len(bodies),
+                              max_beads=nb, **pp)
+    sim = lbrb.Simulation(params, lbrb.make_replicas([(shape, 7)]))
+    if mask is not None:
+        sim.set_mask(0, mask)
+    offs, c, q, g = bodies[0]
+    sim.add_body(0, offs, FREE["mass"], FREE["inertia"], c, quat=q, vel=FREE["vel"],
+                 omega=FREE["omega"], gamma=g)
+    offs, c, q, g = bodies[1]
+    sim.add_body(0, offs, 1.0, (1, 1, 1), c, quat=q, gamma=g, fixed=True)
+    return sim
+
+
+def _oracle_free(shape, mask, pp, bodies):
+    sim = po.OracleSim(shape, po.make_params(**pp))
+    if mask is not None:
+        sim.set_mask(mask)
+    offs, c, q, g = bodies[0]
+    sim.add_body(offs, FREE["mass"], FREE["inertia"], c, quat=q, vel=FREE["vel"],
+                 omega=FREE["omega"], gamma=g)
+    offs, c, q, g = bodies[1]
+    sim.add_body(offs, 1.0, (1, 1, 1), c, quat=q, gamma=g, fixed=True)
+    return sim
+
+
+@pytest.mark.parametrize("masked", [False, True, "long"], ids=["periodic", "pore", "long pore"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_free_body_adjoint_matches_oracle(masked, precision):
+    """The reverse pass through the rigid-body integrator (a free body next to a fixed one)
+    against the oracle's, itself pinned by central differences of the oracle's forward run;
+    segments of 5, 5 and 3 steps, so that replays rewrite the moving bead records."""
+    shape, mask, pp, bodies = _free_case(masked)
+    T, K = 13, 5
+    a = _weights(T, len(bodies), seed=23)
+    print(f"free-body adjoint vs oracle: {masked} {precision} T={T} K={K}", flush=True)
+    Jo, dgo, doo = _oracle_free(shape, mask, pp, bodies).adjoint(T, a)
+    sim = _gpu_free(shape, mask, pp, bodies, precision)
+    Jg, dgg, dog = sim.adjoint(T, a, checkpoint_every=K)
+    sim.close()
+    print(f"  J rel {abs(Jg - Jo) / abs(Jo):.2e}  dgamma rel "
+          f"{np.abs(dgg - dgo).max() / np.abs(dgo).max():.2e}  doffsets rel "
+          f"{np.abs(dog - doo).max() / np.abs(doo).max():.2e}", flush=True)
+    if precision == "f64":
+        tJ, tg, to = 1e-12, 1e-10, 1e-10
+    else:
+        tJ, tg, to = 2e-6, 5e-6, 5e-6
+    assert abs(Jg - Jo) <= tJ * abs(Jo), (Jg, Jo)
+    assert np.abs(dgg - dgo).max() <= tg * np.abs(dgo).max(), (dgg, dgo)
+    assert np.abs(dog - doo).max() <= to * np.abs(doo).max(), np.abs(dog - doo).max()
+
+
+def test_free_body_adjoint_leaves_the_forward_state():
+    """After the reverse pass (whose replays rewrite the bead records) the context continues
+    exactly as one that only stepped forward."""
+    shape, mask, pp, bodies = _free_case(False)
+    T = 9
+    a = _weights(T, len(bodies))
+    s1 = _gpu_free(shape, mask, pp, bodies, "f64")
+    s1.adjoint(T, a, checkpoint_every=4)
+    s2 = _gpu_free(shape, mask, pp, bodies, "f64")
+    s2.step(T)
+    for s in (s1, s2):
+        s.step(3)
+    assert np.array_equal(s1.populations(), s2.populations())
+    _, b1, _, _ = s1.observables(0)
+    _, b2, _, _ = s2.observables(0)
+    for x, y in zip(b1, b2):
+        for k in ("pos", "quat", "vel", "omega", "force", "torque"):
+            assert np.array_equal(x[k], y[k]), k
+    s1.close()
+    s2.close()
+
+
 def _config5(precision):
     from paper_1604_01829_amd import lbrb
     wl = W.workload(5)
@@ -328,9 +420,10 @@ def test_adjoint_error_codes():
                            sum(len(b[0]) for b in bodies))
     assert e.value.code == lbrb.LB_ERR_ARG
     sim.close()
-    # a free body or a thermal fluid is refused
+    # several MD steps per fluid step or a thermal fluid are refused
     nb = sum(len(b[0]) for b in bodies)
-    params = lbrb.make_params(precision="f64", kT=0.0, max_bodies=2, max_beads=nb, **pp)
+    params = lbrb.make_params(precision="f64", kT=0.0, max_bodies=2, max_beads=nb, md_substeps=2,
+                              **pp)
     sim = lbrb.Simulation(params, lbrb.make_replicas([(shape, 7)]))
     sim.add_body(0, bodies[0][0], 1.0, (1, 1, 1), bodies[0][1], gamma=0.1, fixed=True)
     sim.add_body(0, bodies[1][0], 1.0, (1, 1, 1), bodies[1][1], gamma=0.1, fixed=False)
