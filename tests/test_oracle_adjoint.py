@@ -6,7 +6,9 @@
   to individual bead offsets, against central differences of J computed by re-running the
   forward oracle, in a periodic box and in a pore with bounce-back walls.  Beads are chosen
   away from cell faces so that the finite difference does not cross a kink of the
-  trilinear weights.
+  trilinear weights;
+- the same for a free body (moving and spinning, anisotropic inertia) beside a fixed one, so
+  that the derivative runs through both half kicks, the drift and the quaternion rotation.
 """
 import numpy as np
 import pytest
