@@ -338,6 +338,70 @@ def test_full_size_sphere_window_gradient():
     assert np.abs(do32 - do).max() <= 1e-5 * np.abs(do).max()
 
 
+def _free_sphere_sim(precision, gamma=None, offsets=None):
+    """Workload 5's sphere released: free, spinning slowly at the start, in the same uniform
+    flow, at the paper's free-body friction."""
+    import copy
+    from paper_1604_01829_amd import lbrb
+    w = copy.deepcopy(W.workload(5))
+    b = w["replicas"][0]["bodies"][0]
+    w["params"]["kT"] = 0.0
+    b["fixed"] = False
+    b["omega"] = np.array([0.002, -0.001, 0.0015])
+    b["gamma"] = W.GAMMA_FREE if gamma is None else gamma
+    if offsets is not None:
+        b["offsets"] = offsets
+    return w, lbrb.simulation_from_workload(w, precision=precision)
+
+
+def test_full_size_free_sphere_window_gradient():
+    """64^3, the R = 4 sphere (401 beads) free in the uniform flow, 100 steps, checkpoints every
+    20 steps: the FP64 reverse pass through the rigid-body integrator against central
+    differences of FP64 forward runs of the library, and FP32 against FP64."""
+    T, K = 100, 20
+    a = np.zeros((T, 1, 3))
+    a[:, 0, 0] = 1.0 / T
+    print("full-size free-sphere adjoint: f64", flush=True)
+    w, sim = _free_sphere_sim("f64")
+    J, dg, do = sim.adjoint(T, a, checkpoint_every=K)
+    _, bs, _, _ = sim.observables(0)
+    moved = float(np.linalg.norm(bs[0]["pos"] - w["replicas"][0]["bodies"][0]["pos"]))
+    sim.close()
+    assert moved > 1e-3, moved                  # the flow carries the sphere along
+    g0 = W.GAMMA_FREE
+    h = 1e-5 * g0
+    fd = (_forward_J(_free_sphere_sim("f64", gamma=g0 + h)[1], T, a)
+          - _forward_J(_free_sphere_sim("f64", gamma=g0 - h)[1], T, a)) / (2 * h)
+    print(f"  moved {moved:.4f}  J {J:.6e}  dJ/dgamma {dg[0]:.9e}  central difference {fd:.9e}",
+          flush=True)
+    assert abs(fd - dg[0]) <= 1e-6 * abs(fd), (fd, dg[0])
+    # the offsets along the gradient's own direction (every bead moves by at most h): one
+    # bead's derivative alone (~1e-7) sits at the rounding noise of J over 100 steps divided
+    # by 2h (measured ~4e-11), the directional one lies far above it
+    offs = np.asarray(w["replicas"][0]["bodies"][0]["offsets"], dtype=np.float64)
+    v = do / np.abs(do).max()
+    h = 1e-6
+    fd = (_forward_J(_free_sphere_sim("f64", offsets=offs + h * v)[1], T, a)
+          - _forward_J(_free_sphere_sim("f64", offsets=offs - h * v)[1], T, a)) / (2 * h)
+    D = float(np.sum(do * v))
+    print(f"  offsets along the gradient: adjoint {D:.9e}  central difference {fd:.9e}",
+          flush=True)
+    assert abs(fd - D) <= 1e-4 * abs(D), (fd, D)
+    print("full-size free-sphere adjoint: f32", flush=True)
+    _, sim = _free_sphere_sim("f32")
+    J32, dg32, do32 = sim.adjoint(T, a, checkpoint_every=K)
+    sim.close()
+    print(f"  FP32 vs FP64: J rel {abs(J32 - J) / abs(J):.2e}  dgamma rel "
+          f"{abs(dg32[0] - dg[0]) / abs(dg[0]):.2e}  doffsets rel "
+          f"{np.abs(do32 - do).max() / np.abs(do).max():.2e}", flush=True)
+    assert abs(J32 - J) <= 1e-5 * abs(J)
+    # the free body follows the flow, so its drag hardly depends on gamma (d ln J / d ln gamma
+    # is ~4e-3 here): dJ/dgamma is a near-cancellation of terms of size J/gamma, and FP32
+    # rounding is relative to those terms
+    assert abs(dg32[0] - dg[0]) <= 1e-5 * max(abs(dg[0]), abs(J) / g0)
+    assert np.abs(do32 - do).max() <= 1e-5 * np.abs(do).max()
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_full_size_sphere_against_the_oracle_adjoint(precision):
     """64^3, R = 4 fixed sphere (401 beads), u0 = (0.01, 0, 0): J = drag along x averaged over
@@ -357,6 +421,30 @@ def test_full_size_sphere_against_the_oracle_adjoint(precision):
     Jo, dgo, doo = orc.adjoint(T, a)
     print(f"  oracle J {Jo:.9e} dJ/dgamma {dgo[0]:.9e}", flush=True)
     sim = _config5_sim(wl, precision, None, None)
+    J, dg, do = sim.adjoint(T, a, checkpoint_every=K)
+    sim.close()
+    eJ = abs(J - Jo) / abs(Jo)
+    eg = abs(dg[0] - dgo[0]) / abs(dgo[0])
+    eo = float(np.abs(do - doo).max() / np.abs(doo).max())
+    print(f"  GPU {precision}: J rel {eJ:.2e}  dgamma rel {eg:.2e}  doffsets rel {eo:.2e}",
+          flush=True)
+    tJ, tg = (1e-12, 1e-10) if precision == "f64" else (5e-6, 5e-6)
+    assert eJ <= tJ and eg <= tg and eo <= tg
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_full_size_free_sphere_against_the_oracle_adjoint(precision):
+    """64^3, the R = 4 sphere (401 beads) free in the uniform flow: J = drag along x averaged
+    over a 40-step window, checkpoints every 20 steps on the GPU, every state kept by the
+    oracle; the tolerances of the small boxes."""
+    T, K = 40, 20
+    a = np.zeros((T, 1, 3))
+    a[:, 0, 0] = 1.0 / T
+    print(f"64^3 free sphere, {T}-step window, {precision}: oracle reverse pass", flush=True)
+    from tests.helpers import oracle_from_workload
+    w, sim = _free_sphere_sim(precision)
+    Jo, dgo, doo = oracle_from_workload(w).adjoint(T, a)
+    print(f"  oracle J {Jo:.9e} dJ/dgamma {dgo[0]:.9e}", flush=True)
     J, dg, do = sim.adjoint(T, a, checkpoint_every=K)
     sim.close()
     eJ = abs(J - Jo) / abs(Jo)
