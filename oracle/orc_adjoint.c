@@ -8,8 +8,10 @@
  * (a = (1/T, 0, 0) for every step gives the time-averaged drag along x).  Derivatives are
  * taken with respect to each body's bead friction gamma_b and each bead's body-frame offset.
  *
- * Scope: a deterministic fluid (kT = 0), one MD step per fluid step, no excluded volume;
- * boundary masks allowed; bodies fixed or free.  The window's initial state (populations and
+ * Scope: a deterministic fluid (kT = 0), one or several MD steps per fluid step (the MD
+ * steps of a fluid step all read the same populations and each spreads -h times its bead
+ * forces), no excluded volume; boundary masks allowed; bodies fixed or free.  F_b(n) is the
+ * force of the last MD step of fluid step n (the body force a fluid step leaves).  The window's initial state (populations and
  * body states, including the force and torque of the step before the window) is held fixed.
  * The adjoint of one step is the transpose of each of its parts, taken in reverse order:
  *   streaming with halfway bounce-back  ->  lambda*_i(y) = lambda_i(y + c_i) if y + c_i is a
@@ -30,7 +32,8 @@
  * with the adjoint of the body state carried from step to step.  The rotation matrix is
  * differentiated entry by entry in the quaternion's components.
  * Every pre-collision state of the window is kept in memory (19 * N doubles per step), and
- * every body state before each step.
+ * every body state before each fluid step; the reverse of a fluid step first recomputes its
+ * MD steps (poses, bead forces, body states) from the state before it.
  */
 #include "oracle.h"
 
@@ -46,9 +49,10 @@ const uint8_t* orc_box_mask(const orc_sim* s);
 int orc_box_body(const orc_sim* s, int b, const double** offsets, int* n_beads, double pos[3],
                  double quat[4], double* gamma, int* fixed);
 double orc_box_kT(const orc_sim* s);
-int orc_box_plain_md(const orc_sim* s);
+int orc_box_md_steps(const orc_sim* s);
 int orc_box_body_mass(const orc_sim* s, int b, double* mass, double inertia[3]);
 int orc_box_first_half(const orc_sim* s, int b, const double state[19], double h, double out[13]);
+int orc_box_second_half(const orc_sim* s, int b, const double in[19], double h, double out[19]);
 
 /* the basis, its norms and the weights, read once into tables (the same values) */
 static double AE[19][19], AB[19], AW[19];
@@ -235,8 +239,9 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
     const int nx = dims[0], ny = dims[1], nz = dims[2];
     const int64_t N = (int64_t)nx * ny * nz;
     const uint8_t* mask = orc_box_mask(s);
-    const double h = 1.0;   /* one MD step per fluid step */
-    if (orc_box_kT(s) != 0.0 || !orc_box_plain_md(s) || n_steps < 0) return -1;
+    const int m = orc_box_md_steps(s);
+    if (orc_box_kT(s) != 0.0 || m < 1 || n_steps < 0) return -1;
+    const double h = 1.0 / m;   /* MD step */
     adj_tables();   /* before the parallel node loop */
 
     int total_beads = 0;
@@ -246,13 +251,19 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
         total_beads += nb;
     }
 
-    /* forward pass, keeping every pre-collision state and every body state before each step
-     * (and after the last) */
+    /* forward pass, keeping every pre-collision state and every body state before each fluid
+     * step (and after the last) */
     const size_t nbs = (size_t)(n_bodies > 0 ? n_bodies : 1);
+    const size_t ntb = (size_t)(total_beads > 0 ? total_beads : 1);
     double* states = (double*)malloc(sizeof(double) * 19 * N * (size_t)(n_steps + 1));
     double* bst = (double*)malloc(sizeof(double) * S_N * nbs * (size_t)(n_steps + 1));
-    double* bead_F = (double*)malloc(sizeof(double) * 3 * (size_t)(total_beads > 0 ? total_beads : 1));
-    if (!states || !bst || !bead_F) { free(states); free(bst); free(bead_F); return -1; }
+    double* bead_F = (double*)malloc(sizeof(double) * 3 * ntb * (size_t)m);   /* per MD step */
+    double* sub = (double*)malloc(sizeof(double) * S_N * nbs * (size_t)(m + 1));
+    double* pose = (double*)malloc(sizeof(double) * 13 * nbs * (size_t)m);
+    if (!states || !bst || !bead_F || !sub || !pose) {
+        free(states); free(bst); free(bead_F); free(sub); free(pose);
+        return -1;
+    }
     double J = 0.0;
     for (int n = 0; n <= n_steps; ++n) {
         for (int b = 0; b < n_bodies; ++b) orc_body_state(s, b, bst + ((size_t)n * nbs + b) * S_N);
@@ -274,44 +285,61 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
     double* lam_F = (double*)calloc((size_t)3 * N, sizeof(double));
     double* lam_u = (double*)calloc((size_t)3 * N, sizeof(double));
     double* g = (double*)calloc((size_t)3 * N, sizeof(double));
-    double* bstate = (double*)calloc(S_N * nbs, sizeof(double));       /* adjoint of the body state after the step */
-    double* pose = (double*)calloc(13 * nbs, sizeof(double));          /* pose of the step per body */
+    double* bstate = (double*)calloc(S_N * nbs, sizeof(double));   /* adjoint of the body state */
     for (int b = 0; b < n_bodies; ++b) dJ_dgamma[b] = 0.0;
     for (int k = 0; k < 3 * total_beads; ++k) dJ_doffsets[k] = 0.0;
+#define SUB(b, k) (sub + ((size_t)(k) * nbs + (b)) * S_N)
+#define POSE(b, k) (pose + ((size_t)(k) * nbs + (b)) * 13)
     for (int n = n_steps - 1; n >= 0; --n) {
         const double* f = states + (size_t)n * 19 * N;
-        /* the pose of every body in step n, and the spread force recomputed from f^n */
+        /* the MD steps of fluid step n again: poses, bead forces, body states, spread force */
         memset(g, 0, sizeof(double) * 3 * N);
-        for (int b = 0, kb = 0; b < n_bodies; ++b) {
-            const double* off; int nb; double pos0[3], q0[4], gamma; int fixed;
-            orc_box_body(s, b, &off, &nb, pos0, q0, &gamma, &fixed);
-            double* P = pose + 13 * (size_t)b;
-            orc_box_first_half(s, b, bst + ((size_t)n * nbs + b) * S_N, h, P);
-            double R[3][3];
-            rotmat(P + S_QUAT, R);
-            for (int k = 0; k < nb; ++k, ++kb) {
-                const double* bk = off + 3 * k;
-                double r[3], v[3] = {0, 0, 0}, e[3];
-                cross3(P + S_OM, bk, e);
+        for (int b = 0; b < n_bodies; ++b) memcpy(SUB(b, 0), bst + ((size_t)n * nbs + b) * S_N, sizeof(double) * S_N);
+        for (int k = 0; k < m; ++k)
+            for (int b = 0, kb = 0; b < n_bodies; ++b) {
+                const double* off; int nb; double pos0[3], q0[4], gamma; int fixed;
+                orc_box_body(s, b, &off, &nb, pos0, q0, &gamma, &fixed);
+                double* P = POSE(b, k);
+                orc_box_first_half(s, b, SUB(b, k), h, P);
+                double R[3][3];
+                rotmat(P + S_QUAT, R);
+                double Fs[3] = {0, 0, 0}, Ts[3] = {0, 0, 0};
+                for (int j = 0; j < nb; ++j, ++kb) {
+                    const double* bk = off + 3 * j;
+                    double d[3], r[3], v[3] = {0, 0, 0}, e[3];
+                    cross3(P + S_OM, bk, e);
+                    for (int a = 0; a < 3; ++a) {
+                        d[a] = R[a][0] * bk[0] + R[a][1] * bk[1] + R[a][2] * bk[2];
+                        r[a] = P[S_POS + a] + d[a];
+                        if (!fixed) v[a] = P[S_VEL + a] + R[a][0] * e[0] + R[a][1] * e[1] + R[a][2] * e[2];
+                    }
+                    int64_t idx[8]; double w[8], uk[3] = {0, 0, 0};
+                    orc_trilinear(nx, ny, nz, r, idx, w);
+                    for (int c = 0; c < 8; ++c) {
+                        if (mask[idx[c]]) continue;
+                        double rho, u[3];
+                        node_u(f, N, idx[c], p->g_ext, &rho, u);
+                        for (int a = 0; a < 3; ++a) uk[a] += w[c] * u[a];
+                    }
+                    double* F = bead_F + 3 * ((size_t)k * ntb + kb);
+                    for (int a = 0; a < 3; ++a) F[a] = -gamma * (v[a] - uk[a]);
+                    for (int c = 0; c < 8; ++c) {
+                        if (mask[idx[c]]) continue;
+                        for (int a = 0; a < 3; ++a) g[3 * idx[c] + a] -= w[c] * (h * F[a]);
+                    }
+                    double dxF[3];
+                    cross3(d, F, dxF);
+                    for (int a = 0; a < 3; ++a) { Fs[a] += F[a]; Ts[a] += dxF[a]; }
+                }
+                /* the state the MD step leaves: its pose, the second half kick */
+                double mid[S_N];
+                memcpy(mid, P, sizeof(double) * 13);
                 for (int a = 0; a < 3; ++a) {
-                    r[a] = P[S_POS + a] + R[a][0] * bk[0] + R[a][1] * bk[1] + R[a][2] * bk[2];
-                    if (!fixed) v[a] = P[S_VEL + a] + R[a][0] * e[0] + R[a][1] * e[1] + R[a][2] * e[2];
+                    mid[S_F + a] = Fs[a];
+                    mid[S_T + a] = R[0][a] * Ts[0] + R[1][a] * Ts[1] + R[2][a] * Ts[2];
                 }
-                int64_t idx[8]; double w[8], uk[3] = {0, 0, 0};
-                orc_trilinear(nx, ny, nz, r, idx, w);
-                for (int c = 0; c < 8; ++c) {
-                    if (mask[idx[c]]) continue;
-                    double rho, u[3];
-                    node_u(f, N, idx[c], p->g_ext, &rho, u);
-                    for (int a = 0; a < 3; ++a) uk[a] += w[c] * u[a];
-                }
-                for (int a = 0; a < 3; ++a) bead_F[3 * (size_t)kb + a] = -gamma * (v[a] - uk[a]);
-                for (int c = 0; c < 8; ++c) {
-                    if (mask[idx[c]]) continue;
-                    for (int a = 0; a < 3; ++a) g[3 * idx[c] + a] -= w[c] * h * bead_F[3 * (size_t)kb + a];
-                }
+                orc_box_second_half(s, b, mid, h, SUB(b, k + 1));
             }
-        }
         /* streaming transpose and collision VJP (each node writes only its own entries) */
 #pragma omp parallel for schedule(static)
         for (int z = 0; z < nz; ++z)
@@ -337,24 +365,26 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
                     for (int i = 0; i < 19; ++i) lam_n[i * N + here] = lin[i];
                     for (int a = 0; a < 3; ++a) lam_F[3 * here + a] = lF[a];
                 }
-        /* coupling and body transpose */
+        /* coupling and body transpose, MD steps in reverse order */
         memset(lam_u, 0, sizeof(double) * 3 * N);
+        for (int k = m - 1; k >= 0; --k)
         for (int b = 0, kb = 0; b < n_bodies; ++b) {
             const double* off; int nb; double pos0[3], q0[4], gamma; int fixed;
             orc_box_body(s, b, &off, &nb, pos0, q0, &gamma, &fixed);
             double mass, I[3];
             orc_box_body_mass(s, b, &mass, I);
-            const double* P = pose + 13 * (size_t)b;
-            const double* in = bst + ((size_t)n * nbs + b) * S_N;         /* before step n */
-            const double* out = bst + ((size_t)(n + 1) * nbs + b) * S_N;  /* after step n */
-            double* ab = bstate + S_N * (size_t)b;                        /* adjoint of `out` */
+            const double* P = POSE(b, k);
+            const double* in = SUB(b, k);        /* before MD step k */
+            const double* out = SUB(b, k + 1);   /* after it */
+            double* ab = bstate + S_N * (size_t)b;   /* adjoint of `out` */
             double R[3][3];
             rotmat(P + S_QUAT, R);
             /* second half kick: V_out = V_m + h F/2M, w_out = w_m + h (tau - w_m x I w_m)/2I */
             double Fbar[3], taubar[3], Vmbar[3], wmbar[3], mu[3], Tbar[3], T[3], Qbar[3][3];
             double Rcbar[3], qcbar[4];
             for (int a = 0; a < 3; ++a) {
-                Fbar[a] = dJ_dF[((size_t)n * n_bodies + b) * 3 + a];
+                /* the objective takes the force of the last MD step of the fluid step */
+                Fbar[a] = k == m - 1 ? dJ_dF[((size_t)n * n_bodies + b) * 3 + a] : 0.0;
                 Tbar[a] = 0.0;
             }
             memset(Qbar, 0, sizeof Qbar);
@@ -378,8 +408,8 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
                 for (int a = 0; a < 3; ++a)
                     for (int c = 0; c < 3; ++c) Qbar[a][c] += T[a] * taubar[c];
             }
-            for (int k = 0; k < nb; ++k, ++kb) {
-                const double* bk = off + 3 * k;
+            for (int j = 0; j < nb; ++j, ++kb) {
+                const double* bk = off + 3 * j;
                 double d[3], r[3], e[3], v[3] = {0, 0, 0};
                 cross3(P + S_OM, bk, e);
                 for (int a = 0; a < 3; ++a) {
@@ -392,7 +422,7 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
                 /* fractional position inside the cell, for the weight gradients */
                 double fr[3];
                 for (int a = 0; a < 3; ++a) { const double sa = r[a] - 0.5; fr[a] = sa - floor(sa); }
-                const double* Fk = bead_F + 3 * (size_t)kb;
+                const double* Fk = bead_F + 3 * ((size_t)k * ntb + kb);
                 /* adjoint of the bead force: the objective and the body sums, the torque sum
                  * T = sum d x F, and the spreading g -= w h F */
                 double lFk[3], uc[8][3], uk[3] = {0, 0, 0}, TxD[3];
@@ -521,7 +551,9 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
             }
             for (int a = 0; a < 4; ++a) ab[S_QUAT + a] = qibar[a];
         }
-        /* node velocities depend on f^n */
+#undef SUB
+#undef POSE
+        /* node velocities depend on f^n (every MD step of the fluid step samples them) */
         for (int64_t x = 0; x < N; ++x) {
             if (mask[x]) continue;
             const double lu[3] = {lam_u[3 * x], lam_u[3 * x + 1], lam_u[3 * x + 2]};
@@ -538,7 +570,7 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
     }
     /* the box ends at the last state of the window */
     orc_box_set_f(s, states + (size_t)n_steps * 19 * N);
-    free(states); free(bst); free(bead_F); free(lam); free(lam_n); free(lam_F); free(lam_u);
-    free(g); free(bstate); free(pose);
+    free(states); free(bst); free(bead_F); free(sub); free(pose); free(lam); free(lam_n);
+    free(lam_F); free(lam_u); free(g); free(bstate);
     return 0;
 }

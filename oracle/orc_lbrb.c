@@ -784,13 +784,13 @@ const double* orc_box_f(const orc_sim* s) { return s->f; }
 void orc_box_set_f(orc_sim* s, const double* f) { memcpy(s->f, f, sizeof(double) * 19 * (size_t)s->n); }
 const uint8_t* orc_box_mask(const orc_sim* s) { return s->mask; }
 double orc_box_kT(const orc_sim* s) { return s->p.kT; }
-/* 1 if every fluid step is one MD step without excluded volume                            */
-int orc_box_plain_md(const orc_sim* s)
+/* MD steps per fluid step when there is no excluded volume, else 0                         */
+int orc_box_md_steps(const orc_sim* s)
 {
-    if (s->p.md_substeps > 1 || s->n_sites > 0) return 0;
+    if (s->n_sites > 0) return 0;
     for (int b = 0; b < s->n_bodies; ++b)
         if (s->bodies[b].n_ev > 0) return 0;
-    return 1;
+    return s->p.md_substeps > 1 ? s->p.md_substeps : 1;
 }
 int orc_box_body_mass(const orc_sim* s, int b, double* mass, double inertia[3])
 {
@@ -819,6 +819,32 @@ int orc_box_first_half(const orc_sim* s, int b, const double state[19], double h
         out[a] = t.pos[a];
         out[7 + a] = t.vel[a];
         out[10 + a] = t.omega[a];
+    }
+    for (int a = 0; a < 4; ++a) out[3 + a] = t.quat[a];
+    return 0;
+}
+/* the second half of an MD step of length h (body_second_half) applied to body b: in and out
+ * in the layout of orc_body_state; in holds the step's pose and velocities after the first
+ * half, and the step's force and body-frame torque                                        */
+int orc_box_second_half(const orc_sim* s, int b, const double in[19], double h, double out[19])
+{
+    if (b < 0 || b >= s->n_bodies) return -1;
+    orc_body t = s->bodies[b];
+    for (int a = 0; a < 3; ++a) {
+        t.pos[a] = in[a];
+        t.vel[a] = in[7 + a];
+        t.omega[a] = in[10 + a];
+        t.force[a] = in[13 + a];
+        t.torque_body[a] = in[16 + a];
+    }
+    for (int a = 0; a < 4; ++a) t.quat[a] = in[3 + a];
+    body_second_half(&t, h);
+    for (int a = 0; a < 3; ++a) {
+        out[a] = t.pos[a];
+        out[7 + a] = t.vel[a];
+        out[10 + a] = t.omega[a];
+        out[13 + a] = t.force[a];
+        out[16 + a] = t.torque_body[a];
     }
     for (int a = 0; a < 4; ++a) out[3 + a] = t.quat[a];
     return 0;
