@@ -85,9 +85,10 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
         // the body force F = sum F_k and the lab torque T = sum d_k x F_k
         const double* bj = A.body_adj + 6 * (int64_t)body;
         const double* dv = X.dv;
-        lFk[0] = bj[0] + (bj[4] * dv[2] - bj[5] * dv[1]) - s6[3];
-        lFk[1] = bj[1] + (bj[5] * dv[0] - bj[3] * dv[2]) - s6[4];
-        lFk[2] = bj[2] + (bj[3] * dv[1] - bj[4] * dv[0]) - s6[5];
+        const double h = A.spread_h;
+        lFk[0] = bj[0] + (bj[4] * dv[2] - bj[5] * dv[1]) - h * s6[3];
+        lFk[1] = bj[1] + (bj[5] * dv[0] - bj[3] * dv[2]) - h * s6[4];
+        lFk[2] = bj[2] + (bj[3] * dv[1] - bj[4] * dv[0]) - h * s6[5];
     } else {
         for (int ax = 0; ax < 3; ++ax) lFk[ax] = an[ax] - s6[3 + ax];
     }
@@ -97,6 +98,7 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
     if (local >= 0) {
         double su = 0.0, sF = 0.0;
         for (int ax = 0; ax < 3; ++ax) { su += uc[ax] * luk[ax]; sF += Fk[ax] * lFc[ax]; }
+        if constexpr (FREE) sF *= A.spread_h;
         for (int ax = 0; ax < 3; ++ax) dr[ax] = gw[ax] * (su - sF);
         // this corner's share of the sampled velocity's adjoint, through u to the populations
         const double l0 = w * luk[0] * ir, l1 = w * luk[1] * ir, l2 = w * luk[2] * ir;

@@ -746,13 +746,15 @@ int build_wca(lb_ctx* c)
 // population buffers, the adjoints of the node force and velocity, the per-step objective
 // weights, the per-bead accumulators, and room to restore the bead forces afterwards; for
 // free bodies the body table before every step of the window (and after the last), the
-// adjoint of the body states, of each step's body force and torque, the bead pass's sums
-// and room to restore the bead records.
+// adjoint of the body states, of each MD step's body force and torque, the bead pass's sums,
+// the body tables between the MD steps of one fluid step, zero weights (the objective takes
+// the last MD step's force) and room to restore the bead records.
 struct AdjPlan {
     int32_t n_ck = 0, n_seg = 0;
     size_t state = 0;
     size_t off_ck, off_seg, off_lam0, off_lam1, off_lamF, off_w, off_dr, off_dg, off_J,
-        off_bf, off_save, off_snap, off_badj, off_bin, off_bsum, off_recs, total;
+        off_bf, off_save, off_snap, off_badj, off_bin, off_bsum, off_recs, off_scr, off_zero,
+        total;
 };
 
 bool any_free(const lb_ctx* c)
@@ -761,6 +763,11 @@ bool any_free(const lb_ctx* c)
         if (!B.fixed) return true;
     return false;
 }
+
+// the reverse pass runs the body passes (free bodies, or several MD steps per fluid step);
+// otherwise it runs the fixed-body schedule, with a fluid step's coupling fused into the
+// next reverse step's bead launch
+bool body_passes(const lb_ctx* c) { return any_free(c) || md_steps(c) > 1; }
 
 bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
 {
@@ -784,32 +791,67 @@ bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
     ap.off_dr = take(sizeof(double) * 3 * nb);
     ap.off_dg = take(sizeof(double) * nb);
     ap.off_J = take(sizeof(double) * nb);
-    ap.off_bf = take(sizeof(double) * 6 * nb);
+    const int m = md_steps(c);
+    ap.off_bf = take(sizeof(double) * 3 * nb * (size_t)std::max(2, m));   // bead forces per MD step
     ap.off_save = take(sizeof(double) * 6 * nb);
-    if (any_free(c)) {
+    if (body_passes(c)) {
         ap.off_snap = take(sizeof(Body) * nbod * ((size_t)T + 1));
         ap.off_badj = take(sizeof(double) * kBodyAdjWords * nbod);
         ap.off_bin = take(sizeof(double) * 6 * nbod);
         ap.off_bsum = take(sizeof(double) * kBeadSumWords * nb);
         ap.off_recs = take(sizeof(BeadRec) * nb);
+        ap.off_scr = take(sizeof(Body) * nbod * (size_t)std::max(1, m - 1));
+        ap.off_zero = take(sizeof(double) * 3 * nbod);
     } else {
         ap.off_snap = ap.off_badj = ap.off_bin = ap.off_bsum = ap.off_recs = 0;
+        ap.off_scr = ap.off_zero = 0;
     }
     ap.total = o;
     return true;
 }
 
-// forward step without finishing the bodies, src -> dst.  Fixed bodies: the records hold the
-// only pose; free bodies: the records are first written from the stored body table `bodies`
-// of the step.
+// The couplings of a recomputed fluid step from its stored body table `table` (the bodies
+// before the step): the records of its first MD step from the table's pose, then per MD step
+// k the coupling, bead forces into bf + k * nbf; between MD steps the bodies are finished as
+// the forward step does, into scr + k * n_bodies (the table before MD step k + 1; the
+// finishing also writes that step's records).
+template <typename Real>
+void enqueue_recoupling(lb_ctx* c, hipStream_t s, const StepArgs<Real>& a, int64_t step,
+                        const Body* table, Body* scr, double* bf, size_t nbf)
+{
+    const int m = md_steps(c);
+    if (c->n_beads <= 0) return;
+    launch_records_from_poses(table, (int)((step * m) & 1), c->d_beads, c->d_recs, c->n_beads, s);
+    CoupleArgs ca = couple_args(c);
+    for (int k = 0; k < m; ++k) {
+        ca.md_step = (uint32_t)k;
+        ca.bead_force = bf + nbf * (size_t)k;
+        launch_couple<Real>(a, ca, s);
+        if (k + 1 < m) {
+            const Body* from = k == 0 ? table : scr + (size_t)c->n_bodies * (k - 1);
+            Body* to = scr + (size_t)c->n_bodies * k;
+            (void)hipMemcpyAsync(to, from, sizeof(Body) * (size_t)c->n_bodies, hipMemcpyDeviceToDevice, s);
+            BodyArgs ba = body_args(c);
+            ba.bodies = to;
+            ba.bead_force = ca.bead_force;
+            launch_body_substep(ba, nullptr, step, k, s);
+        }
+    }
+}
+
+// forward step without finishing the bodies, src -> dst.  Fixed bodies with one MD step: the
+// records hold the only pose; otherwise the couplings are recomputed from the stored body
+// table `bodies` of the step (enqueue_recoupling).
 template <typename Real>
 void enqueue_replay(lb_ctx* c, hipStream_t s, const void* src, void* dst, int64_t step,
-                    const Body* bodies)
+                    const Body* bodies, Body* scr, double* bf, size_t nbf)
 {
     StepArgs<Real> ag[2] = {step_args_on<Real>(c, 0, src, dst), step_args_on<Real>(c, 1, src, dst)};
     for (auto& a : ag) a.step_arg = step;
-    if (bodies) launch_records_from_poses(bodies, (int)(step & 1), c->d_beads, c->d_recs, c->n_beads, s);
-    if (c->n_beads > 0) launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], couple_args(c), s);
+    if (bodies)
+        enqueue_recoupling<Real>(c, s, any_masked(c) ? ag[1] : ag[0], step, bodies, scr, bf, nbf);
+    else if (c->n_beads > 0)
+        launch_couple<Real>(any_masked(c) ? ag[1] : ag[0], couple_args(c), s);
     for (int g = 0; g < 2; ++g)
         if (ag[g].n_tiles > 0)
             launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, nullptr, s);
@@ -821,8 +863,9 @@ void enqueue_replay(lb_ctx* c, hipStream_t s, const void* src, void* dst, int64_
 // launch); prev_src: the state of step - 1, whose coupling then runs in this step's bead launch
 // (nullptr: none, as at the start of a segment, whose states the replay rewrites first).
 // The bead forces of a reverse step go to one of two buffers by the parity of n.
-// snap: with free bodies, the stored body tables of the window (the step's records are
-// written from table n, the body pass reads tables n and n + 1); prev_src is then null.
+// snap: with body passes, the stored body tables of the window (the couplings are recomputed
+// from table n; the MD steps' body passes read the tables before and after each of them:
+// table n, the scratch tables of the recompute, table n + 1); prev_src is then null.
 template <typename Real>
 void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, const Real* lam_next,
                      Real* lam_cur, char* ws, const AdjPlan& ap, int64_t n, bool coupled,
@@ -854,28 +897,45 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
         X.n_beads = c->n_beads;
         if (snap) {
             X.body_adj = (const double*)(ws + ap.off_bin);
-            X.snap = snap + (size_t)c->n_bodies * n;
-            X.pose_par = (int32_t)(step & 1);
             X.bead_sums = (double*)(ws + ap.off_bsum);
+            X.spread_h = 1.0 / md_steps(c);
         }
     }
     const int cg = any_masked(c) ? 1 : 0;
-    if (snap && c->n_beads > 0)
-        launch_records_from_poses(snap + (size_t)c->n_bodies * n, (int)(step & 1), c->d_beads,
-                                  c->d_recs, c->n_beads, s);
+    if (snap) {
+        // the MD steps of fluid step n: recompute their couplings (the spread force the node
+        // pass takes, each MD step's bead forces and the body tables between them), then the
+        // node pass, then each MD step's body and bead passes in reverse order
+        const int m = md_steps(c);
+        const size_t nb = (size_t)c->n_bodies;
+        const Body* t0 = snap + nb * n;
+        Body* scr = (Body*)(ws + ap.off_scr);
+        enqueue_recoupling<Real>(c, s, A[cg].a, step, t0, scr, bf, nbf);
+        for (int g = 0; g < 2; ++g) launch_adjoint_step<Real>(A[g], g == 1, s);
+        if (c->n_beads <= 0) return;
+        auto table = [&](int k) { return k == 0 ? t0 : k == m ? t0 + nb : scr + nb * (k - 1); };
+        double* badj = (double*)(ws + ap.off_badj);
+        const double* zero = (const double*)(ws + ap.off_zero);
+        const double* weights = A[cg].weights;
+        for (int k = m - 1; k >= 0; --k) {
+            const int par = (int)((step * m + k) & 1);
+            AdjArgs<Real> X = A[cg];
+            X.weights = k == m - 1 ? weights : zero;   // the objective takes the last MD step
+            X.bead_force = bf + nbf * (size_t)k;
+            X.snap = table(k);
+            X.pose_par = par;
+            launch_records_from_poses(table(k), par, c->d_beads, c->d_recs, c->n_beads, s);
+            launch_adjoint_body_pre(table(k), par, X.weights, badj, (double*)(ws + ap.off_bin),
+                                    c->n_bodies, s);
+            launch_adjoint_beads<Real>(X, s);
+            launch_adjoint_body_post(table(k), table(k + 1), par, (const double*)(ws + ap.off_bsum),
+                                     badj, c->n_bodies, s);
+        }
+        return;
+    }
     if (c->n_beads > 0 && !coupled) launch_couple<Real>(A[cg].a, coupling(n), s);
     for (int g = 0; g < 2; ++g) launch_adjoint_step<Real>(A[g], g == 1, s);
     if (c->n_beads <= 0) return;
-    if (snap) {
-        const Body* in = snap + (size_t)c->n_bodies * n;
-        double* badj = (double*)(ws + ap.off_badj);
-        launch_adjoint_body_pre(in, (int)(step & 1), A[cg].weights, badj, (double*)(ws + ap.off_bin),
-                                c->n_bodies, s);
-        launch_adjoint_beads<Real>(A[cg], s);
-        launch_adjoint_body_post(in, in + c->n_bodies, (int)(step & 1), (const double*)(ws + ap.off_bsum),
-                                 badj, c->n_bodies, s);
-        return;
-    }
     if (prev_src) {
         StepArgs<Real> pa = step_args_on<Real>(c, cg, prev_src, nullptr);
         pa.step_arg = step - 1;
@@ -893,8 +953,8 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
     auto ck = [&](int k) { return (void*)(ws + ap.off_ck + ap.state * k); };
     auto seg = [&](int k) { return (void*)(ws + ap.off_seg + ap.state * k); };
     const int64_t step0 = c->step;
-    // free bodies: the body table before every step of the window and after the last
-    const bool fb = any_free(c);
+    // with body passes: the body table before every step of the window and after the last
+    const bool fb = body_passes(c);
     Body* snap = fb ? (Body*)(ws + ap.off_snap) : nullptr;
     const size_t table = sizeof(Body) * (size_t)c->n_bodies;
     if (fb) HIP_TRY(c, hipMemcpyAsync(snap, c->d_bodies, table, hipMemcpyDeviceToDevice, s));
@@ -926,13 +986,15 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
         auto state = [&](int32_t j) { return j == 0 ? ck(sg) : seg(j - 1); };
         for (int32_t j = 0; j + 1 < n1 - n0; ++j)
             enqueue_replay<Real>(c, s, state(j), state(j + 1), step0 + n0 + j,
-                                 fb ? snap + (size_t)c->n_bodies * (n0 + j) : nullptr);
+                                 fb ? snap + (size_t)c->n_bodies * (n0 + j) : nullptr,
+                                 (Body*)(ws + ap.off_scr), (double*)(ws + ap.off_bf),
+                                 3 * (size_t)std::max<int32_t>(c->n_beads, 1));
         HIP_TRY(c, hipGetLastError());
         for (int32_t n = n1 - 1; n >= n0; --n) {
             // the coupling of step n - 1 joins this step's bead launch when its state is at
             // hand and nothing in between rewrites the force accumulators: inside a segment,
-            // and across segments of one step each (no replays); not with free bodies, whose
-            // records change from step to step
+            // and across segments of one step each (no replays); not with body passes, whose
+            // records change from MD step to MD step
             const void* prev = fb ? nullptr
                                   : n > n0 ? state(n - 1 - n0) : (K == 1 && n > 0 ? ck(n - 1) : nullptr);
             enqueue_adjoint<Real>(c, s, state(n - n0), step0 + n, lam[nxt], lam[nxt ^ 1], ws, ap, n,
@@ -1828,9 +1890,8 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     if (c->p.kT != 0.0) return fail(c, LB_ERR_STATE, "the reverse pass needs kT = 0");
     bool any_ev = false;
     for (const EvHost& E : c->ev) any_ev = any_ev || !E.off.empty();
-    if (md_steps(c) > 1 || any_ev || c->n_sites > 0)
-        return fail(c, LB_ERR_STATE,
-                    "the reverse pass needs one MD step per fluid step and no excluded volume");
+    if (any_ev || c->n_sites > 0)
+        return fail(c, LB_ERR_STATE, "the reverse pass needs a context without excluded volume");
     for (int r = 0; r < c->n_rep; ++r)
         if (c->reps[r].masked == 2)
             return fail(c, LB_ERR_STATE, "the reverse pass needs masks of one fluid run per row");
@@ -1847,9 +1908,12 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_dr, 0, sizeof(double) * 3 * nb, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_dg, 0, sizeof(double) * nb, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_J, 0, sizeof(double) * nb, s));
-    if (any_free(c))
+    if (body_passes(c)) {
         HIP_TRY(c, hipMemsetAsync(ws + ap.off_badj, 0,
                                   sizeof(double) * kBodyAdjWords * std::max<int32_t>(c->n_bodies, 1), s));
+        HIP_TRY(c, hipMemsetAsync(ws + ap.off_zero, 0,
+                                  sizeof(double) * 3 * std::max<int32_t>(c->n_bodies, 1), s));
+    }
     {
         const int rc = prepare_bodies(c, s);
         if (rc != LB_OK) return rc;
@@ -1871,7 +1935,7 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     double Jsum = 0.0;
     for (int32_t k = 0; k < c->n_beads; ++k) Jsum += jp[k];
     if (J) *J = Jsum;
-    const bool body_frame = any_free(c);   // the bead pass then accumulated body-frame values
+    const bool body_frame = body_passes(c);   // the bead pass then accumulated body-frame values
     for (int32_t b = 0; b < c->n_bodies; ++b) {
         const Body& B = bs[b];
         const double* R = B.pose[parity].rot;   // body -> lab; a fixed body keeps one pose

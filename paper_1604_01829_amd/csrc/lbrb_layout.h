@@ -258,19 +258,21 @@ struct AdjArgs {
     // d x dbar + (w x d) x vbar and d x vbar (d = r - R, dbar and vbar the adjoints of the
     // arm and the velocity, w the lab angular velocity).  Without, dr is in the lab frame and
     // the body force's adjoint is the weight.
+    // The spread force of an MD step is -spread_h times its bead forces (1 / MD steps).
     const double* body_adj;
     const Body* snap;
     int32_t pose_par;
     double* bead_sums;
+    double spread_h;
 };
 
-// The body pass of a reverse step with free bodies (one MD step per fluid step).  in: the
-// bodies before the step (their pose of the step at pose[par]); out: after it; adj: the
-// adjoint of each body's state after the step (19 doubles: position, quaternion, velocity,
-// body-frame angular velocity, force, body-frame torque).  pre: writes the adjoint of the
-// step's body force and lab torque (6 per body) for the bead pass; post: adds the bead sums
-// and takes adj back through the second half kick, the drift, the rotation and the first
-// half kick, to the adjoint of the state before the step.  Fixed bodies: weights only.
+// The body pass of one MD step of a reverse step.  in: the bodies before the MD step (its
+// pose at pose[par]); out: after it; adj: the adjoint of each body's state after the MD step
+// (19 doubles: position, quaternion, velocity, body-frame angular velocity, force, body-frame
+// torque).  pre: writes the adjoint of the MD step's body force and lab torque (6 per body)
+// for the bead pass; post: adds the bead sums and takes adj back through the second half
+// kick, the drift, the rotation and the first half kick, to the adjoint of the state before
+// the MD step.  Fixed bodies: weights only.
 constexpr int kBodyAdjWords = 19;
 constexpr int kBeadSumWords = 12;
 void launch_adjoint_body_pre(const Body* in, int par, const double* weights, const double* adj,

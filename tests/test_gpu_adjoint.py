@@ -202,11 +202,11 @@ def _free_case(masked):
     return shape, mask, pp, [(offs, c + 0.047, q, W.GAMMA_FREE), bodies[1]]
 
 
-def _gpu_free(shape, mask, pp, bodies, precision):
+def _gpu_free(shape, mask, pp, bodies, precision, md=1):
     from paper_1604_01829_amd import lbrb
     nb = sum(len(b[0]) for b in bodies)
     params = lbrb.make_params(precision=precision, kT=0.0, max_bodies=len(bodies),
-                              max_beads=nb, **pp)
+                              max_beads=nb, md_substeps=md, **pp)
     sim = lbrb.Simulation(params, lbrb.make_replicas([(shape, 7)]))
     if mask is not None:
         sim.set_mask(0, mask)
@@ -218,8 +218,8 @@ def _gpu_free(shape, mask, pp, bodies, precision):
     return sim
 
 
-def _oracle_free(shape, mask, pp, bodies):
-    sim = po.OracleSim(shape, po.make_params(**pp))
+def _oracle_free(shape, mask, pp, bodies, md=1):
+    sim = po.OracleSim(shape, po.make_params(md_substeps=md, **pp))
     if mask is not None:
         sim.set_mask(mask)
     offs, c, q, g = bodies[0]
@@ -230,18 +230,21 @@ def _oracle_free(shape, mask, pp, bodies):
     return sim
 
 
-@pytest.mark.parametrize("masked", [False, True, "long"], ids=["periodic", "pore", "long pore"])
+@pytest.mark.parametrize("masked,md", [(False, 1), (True, 1), ("long", 1), (False, 2), (True, 3)],
+                         ids=["periodic", "pore", "long pore", "periodic-2md", "pore-3md"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_free_body_adjoint_matches_oracle(masked, precision):
+def test_free_body_adjoint_matches_oracle(masked, md, precision):
     """The reverse pass through the rigid-body integrator (a free body next to a fixed one)
     against the oracle's, itself pinned by central differences of the oracle's forward run;
-    segments of 5, 5 and 3 steps, so that replays rewrite the moving bead records."""
+    segments of 5, 5 and 3 steps, so that replays rewrite the moving bead records; one MD step
+    per fluid step, and two or three (the paper's scheme: the MD steps of a fluid step on the
+    frozen fluid, recomputed with the body tables between them)."""
     shape, mask, pp, bodies = _free_case(masked)
     T, K = 13, 5
     a = _weights(T, len(bodies), seed=23)
-    print(f"free-body adjoint vs oracle: {masked} {precision} T={T} K={K}", flush=True)
-    Jo, dgo, doo = _oracle_free(shape, mask, pp, bodies).adjoint(T, a)
-    sim = _gpu_free(shape, mask, pp, bodies, precision)
+    print(f"free-body adjoint vs oracle: {masked} md={md} {precision} T={T} K={K}", flush=True)
+    Jo, dgo, doo = _oracle_free(shape, mask, pp, bodies, md).adjoint(T, a)
+    sim = _gpu_free(shape, mask, pp, bodies, precision, md)
     Jg, dgg, dog = sim.adjoint(T, a, checkpoint_every=K)
     sim.close()
     print(f"  J rel {abs(Jg - Jo) / abs(Jo):.2e}  dgamma rel "
@@ -254,6 +257,37 @@ def test_free_body_adjoint_matches_oracle(masked, precision):
     assert abs(Jg - Jo) <= tJ * abs(Jo), (Jg, Jo)
     assert np.abs(dgg - dgo).max() <= tg * np.abs(dgo).max(), (dgg, dgo)
     assert np.abs(dog - doo).max() <= to * np.abs(doo).max(), np.abs(dog - doo).max()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_fixed_bodies_with_two_md_steps_match_oracle(precision):
+    """Two fixed bodies, two MD steps per fluid step: the couplings of both MD steps spread
+    half their force each, and only the last one's force enters the objective."""
+    shape, mask, pp, bodies = _case(True)
+    T, K = 9, 4
+    a = _weights(T, len(bodies))
+    osim = po.OracleSim(shape, po.make_params(md_substeps=2, **pp))
+    osim.set_mask(mask)
+    for offs, c, q, g in bodies:
+        osim.add_body(offs, 1.0, (1, 1, 1), c, quat=q, gamma=g, fixed=True)
+    Jo, dgo, doo = osim.adjoint(T, a)
+    from paper_1604_01829_amd import lbrb
+    nb = sum(len(b[0]) for b in bodies)
+    params = lbrb.make_params(precision=precision, kT=0.0, max_bodies=len(bodies), max_beads=nb,
+                              md_substeps=2, **pp)
+    sim = lbrb.Simulation(params, lbrb.make_replicas([(shape, 7)]))
+    sim.set_mask(0, mask)
+    for offs, c, q, g in bodies:
+        sim.add_body(0, offs, 1.0, (1, 1, 1), c, quat=q, gamma=g, fixed=True)
+    Jg, dgg, dog = sim.adjoint(T, a, checkpoint_every=K)
+    sim.close()
+    print(f"  J rel {abs(Jg - Jo) / abs(Jo):.2e}  dgamma rel "
+          f"{np.abs(dgg - dgo).max() / np.abs(dgo).max():.2e}  doffsets rel "
+          f"{np.abs(dog - doo).max() / np.abs(doo).max():.2e}", flush=True)
+    tJ, tg = (1e-12, 1e-10) if precision == "f64" else (2e-6, 5e-6)
+    assert abs(Jg - Jo) <= tJ * abs(Jo), (Jg, Jo)
+    assert np.abs(dgg - dgo).max() <= tg * np.abs(dgo).max(), (dgg, dgo)
+    assert np.abs(dog - doo).max() <= tg * np.abs(doo).max(), np.abs(dog - doo).max()
 
 
 def test_free_body_adjoint_leaves_the_forward_state():
@@ -508,13 +542,14 @@ def test_adjoint_error_codes():
                            sum(len(b[0]) for b in bodies))
     assert e.value.code == lbrb.LB_ERR_ARG
     sim.close()
-    # several MD steps per fluid step or a thermal fluid are refused
+    # excluded volume or a thermal fluid are refused
     nb = sum(len(b[0]) for b in bodies)
-    params = lbrb.make_params(precision="f64", kT=0.0, max_bodies=2, max_beads=nb, md_substeps=2,
-                              **pp)
+    params = lbrb.make_params(precision="f64", kT=0.0, max_bodies=2, max_beads=nb,
+                              wca_epsilon=1.0, max_ev_sites=8, **pp)
     sim = lbrb.Simulation(params, lbrb.make_replicas([(shape, 7)]))
     sim.add_body(0, bodies[0][0], 1.0, (1, 1, 1), bodies[0][1], gamma=0.1, fixed=True)
     sim.add_body(0, bodies[1][0], 1.0, (1, 1, 1), bodies[1][1], gamma=0.1, fixed=False)
+    sim.set_excluded_volume(0, 1, np.zeros((1, 3)), 0.5)
     with pytest.raises(lbrb.LBError) as e:
         sim.adjoint(4, a)
     assert e.value.code == lbrb.LB_ERR_STATE
