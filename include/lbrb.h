@@ -99,8 +99,7 @@ int lb_init(const lb_params* params, const lb_replica* replicas, int32_t n_repli
  * Storage is per (y,z) row from its first to its last fluid node: rows with one fluid run
  * (pores along z, slabs, channels) store fluid nodes only; rows with several runs also store
  * the boundary nodes between the runs, which then cost one node update each and a mirror of
- * their fluid neighbours' reflected populations after every step.  The reverse pass
- * (lb_rb_adjoint) needs masks whose rows hold one fluid run each.  Only before the first step
+ * their fluid neighbours' reflected populations after every step.  Only before the first step
  * (LB_ERR_STATE otherwise).  Re-initialises that replica's fluid to equilibrium.            */
 int lb_set_boundary_mask(lb_ctx* ctx, int32_t replica, const uint8_t* host_mask);
 
@@ -363,8 +362,7 @@ int lb_set_tuning(lb_ctx* ctx, const lb_tuning* settings);
  *   dJ_dgamma   [n_bodies];
  *   dJ_doffsets [n_beads][3], body frame.
  * Synchronises the stream.  Errors: LB_ERR_ARG (window, workspace, missing arrays),
- * LB_ERR_STATE (kT > 0, excluded-volume or static sites, or a mask with a row of several
- * fluid runs).  The adjoint runs in the context precision; its
+ * LB_ERR_STATE (kT > 0, excluded-volume or static sites).  The adjoint runs in the context precision; its
  * atomic accumulation of sampled-velocity adjoints into the population adjoint is not
  * order-deterministic.                                                                    */
 size_t lb_adjoint_workspace_bytes(const lb_ctx* ctx, int32_t n_steps, int32_t checkpoint_every);

@@ -44,6 +44,16 @@ __global__ __launch_bounds__(kNodeBlock) void adj_node_kernel(const AdjArgs<Real
     int x, y, z;
     RowDesc self;
     locate<MASKED>(R, a.rows, t.row_lo, t.row_hi, local, x, y, z, self);
+    if (MASKED && R.masked == 2 && a.hole[R.base + local] != 0) {
+        // a hole is a boundary node: no adjoint of its own (the transposed mirror later fills
+        // the slots its fluid neighbours read)
+        const int64_t g = R.base + local;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) A.lam_cur[pop_at(i, g)] = (Real)0;
+        for (int ax = 0; ax < 3; ++ax) A.lamF[(int64_t)ax * a.N + g] = (Real)0;
+        if (a.flags[g]) a.flags[g] = 0;
+        return;
+    }
     Real d[Q], lam[Q];
     pull<Real, MASKED, 1>(a.src, a.N, R, a.rowinfo, x, y, z, local, self, d);
     pull<Real, MASKED, -1>(A.lam_next, a.N, R, a.rowinfo, x, y, z, local, self, lam);

@@ -56,6 +56,8 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
         const RowDesc self = a.rowinfo[X.row_base + py + X.ny * sz];
         const int off = sx - self.xlo;
         local = (unsigned)off < (unsigned)self.len ? self.start + off : -1;
+        // a hole is a boundary node: no velocity sampled, no force spread
+        if (masked == 2 && local >= 0 && a.hole[X.base + local] != 0) local = -1;
         if (local >= 0) pull<Real, true, 1>(a.src, a.N, R, a.rowinfo, sx, py, sz, local, self, d);
     } else {
         local = px + (int64_t)X.nx * (py + (int64_t)X.ny * pz);

@@ -856,6 +856,9 @@ void enqueue_replay(lb_ctx* c, hipStream_t s, const void* src, void* dst, int64_
         if (ag[g].n_tiles > 0)
             launch_node_step<Real>(ag[g], g == 1, c->n_beads > 0, nullptr, s);
     if (c->n_links > 0) launch_wall_links<Real>(ag[0].dst, c->d_links, c->n_links, s);
+    if (!c->hole_tiles.empty())
+        launch_mirror_holes<Real>(ag[0].dst, c->d_reps, c->d_rows, c->d_rowinfo, c->d_hole_tiles,
+                                  (int32_t)c->hole_tiles.size(), c->hole, s);
 }
 
 // one reverse step at forward step `step` (index n of the window), forward state pulled from
@@ -999,6 +1002,10 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
                                   : n > n0 ? state(n - 1 - n0) : (K == 1 && n > 0 ? ck(n - 1) : nullptr);
             enqueue_adjoint<Real>(c, s, state(n - n0), step0 + n, lam[nxt], lam[nxt ^ 1], ws, ap, n,
                                   coupled, prev, snap);
+            if (!c->hole_tiles.empty())   // the step's adjoint is complete: transposed mirror
+                launch_mirror_holes_transposed<Real>(lam[nxt ^ 1], c->d_reps, c->d_rows, c->d_rowinfo,
+                                                     c->d_hole_tiles, (int32_t)c->hole_tiles.size(),
+                                                     c->hole, s);
             coupled = prev != nullptr;
             nxt ^= 1;
         }
@@ -1892,9 +1899,6 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     for (const EvHost& E : c->ev) any_ev = any_ev || !E.off.empty();
     if (any_ev || c->n_sites > 0)
         return fail(c, LB_ERR_STATE, "the reverse pass needs a context without excluded volume");
-    for (int r = 0; r < c->n_rep; ++r)
-        if (c->reps[r].masked == 2)
-            return fail(c, LB_ERR_STATE, "the reverse pass needs masks of one fluid run per row");
     if (c->n_bodies > 0 && (!dJ_dF || !dJ_dgamma || !dJ_doffsets))
         return fail(c, LB_ERR_ARG, "missing objective weights or gradient outputs");
     char* ws = (char*)dev_ws;

@@ -37,7 +37,10 @@ void launch_wall_links(Real* f, const WallLink* links, int64_t n_links, hipStrea
 // reflected value carries) every hole copies f*_opp(i)(x) into its slot i for each fluid
 // neighbour x = h + c_i.  Holes are updated like fluid nodes by the node kernel (their values
 // are never read), and every other consumer -- coupling, observables, export -- treats them as
-// boundary nodes.
+// boundary nodes.  The reverse pass zeroes the holes' adjoints in its node pass and, once a
+// reverse step's adjoint is complete, runs the transposed mirror: for each fluid neighbour
+// x = h + c_i, slot opp(i) of h takes lambda_i(x); the transposed pull of x along c_opp(i)
+// then reads x's own lambda_i there, the transpose of the bounce-back above.
 struct ReplicaDesc;
 struct RowDesc;
 struct NodeTile;
@@ -45,6 +48,10 @@ template <typename Real>
 void launch_mirror_holes(Real* f, const ReplicaDesc* reps, const RowDesc* rows,
                          const RowDesc* rowinfo, const NodeTile* tiles, int32_t n_tiles,
                          const uint8_t* hole, hipStream_t s);
+template <typename Real>
+void launch_mirror_holes_transposed(Real* lam, const ReplicaDesc* reps, const RowDesc* rows,
+                                    const RowDesc* rowinfo, const NodeTile* tiles, int32_t n_tiles,
+                                    const uint8_t* hole, hipStream_t s);
 
 }  // namespace lbrb
 

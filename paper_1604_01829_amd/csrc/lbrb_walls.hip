@@ -25,8 +25,11 @@ void launch_wall_links(Real* f, const WallLink* links, int64_t n_links, hipStrea
                        links, n_links);
 }
 
-// one thread per stored node of the tiles of replicas with holes
-template <typename Real>
+// one thread per stored node of the tiles of replicas with holes.  TRANSPOSED: the reverse
+// pass's mirror, slot opp(i) of the hole takes population i of x (lambda_opp(i)(h) =
+// lambda_i(h + c_i)), so that the transposed pull at a fluid node y = h - c_j reads, from the
+// hole's slot j, its own lambda_opp(j)(y): the transpose of halfway bounce-back.
+template <typename Real, bool TRANSPOSED>
 __global__ __launch_bounds__(kNodeBlock) void mirror_holes_kernel(Real* f, const ReplicaDesc* reps,
                                                                   const RowDesc* rows,
                                                                   const RowDesc* rowinfo,
@@ -52,7 +55,8 @@ __global__ __launch_bounds__(kNodeBlock) void mirror_holes_kernel(Real* f, const
         if ((unsigned)off >= (unsigned)rd.len) continue;       // not stored: boundary node
         const int64_t gx = R.base + rd.start + off;
         if (hole[gx] != 0) continue;                             // another hole
-        f[pop_at(i, g)] = f[pop_at(opposite_of(i), gx)];
+        if (TRANSPOSED) f[pop_at(opposite_of(i), g)] = f[pop_at(i, gx)];
+        else f[pop_at(i, g)] = f[pop_at(opposite_of(i), gx)];
     }
 }
 
@@ -62,8 +66,18 @@ void launch_mirror_holes(Real* f, const ReplicaDesc* reps, const RowDesc* rows,
                          const uint8_t* hole, hipStream_t s)
 {
     if (n_tiles <= 0) return;
-    hipLaunchKernelGGL((mirror_holes_kernel<Real>), dim3(n_tiles), dim3(kNodeBlock), 0, s, f, reps,
-                       rows, rowinfo, tiles, hole);
+    hipLaunchKernelGGL((mirror_holes_kernel<Real, false>), dim3(n_tiles), dim3(kNodeBlock), 0, s, f,
+                       reps, rows, rowinfo, tiles, hole);
+}
+
+template <typename Real>
+void launch_mirror_holes_transposed(Real* lam, const ReplicaDesc* reps, const RowDesc* rows,
+                                    const RowDesc* rowinfo, const NodeTile* tiles, int32_t n_tiles,
+                                    const uint8_t* hole, hipStream_t s)
+{
+    if (n_tiles <= 0) return;
+    hipLaunchKernelGGL((mirror_holes_kernel<Real, true>), dim3(n_tiles), dim3(kNodeBlock), 0, s,
+                       lam, reps, rows, rowinfo, tiles, hole);
 }
 
 template void launch_mirror_holes<float>(float*, const ReplicaDesc*, const RowDesc*,
@@ -72,6 +86,12 @@ template void launch_mirror_holes<float>(float*, const ReplicaDesc*, const RowDe
 template void launch_mirror_holes<double>(double*, const ReplicaDesc*, const RowDesc*,
                                           const RowDesc*, const NodeTile*, int32_t,
                                           const uint8_t*, hipStream_t);
+template void launch_mirror_holes_transposed<float>(float*, const ReplicaDesc*, const RowDesc*,
+                                                    const RowDesc*, const NodeTile*, int32_t,
+                                                    const uint8_t*, hipStream_t);
+template void launch_mirror_holes_transposed<double>(double*, const ReplicaDesc*, const RowDesc*,
+                                                     const RowDesc*, const NodeTile*, int32_t,
+                                                     const uint8_t*, hipStream_t);
 template void launch_wall_links<float>(float*, const WallLink*, int64_t, hipStream_t);
 template void launch_wall_links<double>(double*, const WallLink*, int64_t, hipStream_t);
 

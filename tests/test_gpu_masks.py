@@ -187,14 +187,46 @@ def test_pore_with_a_baffle_stored_along_the_pore(precision, moving):
     gpu.close()
 
 
-def test_reverse_pass_refuses_holes():
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_reverse_pass_with_holes_matches_oracle(precision):
+    """The reverse pass in the obstacle box (rows with two fluid runs, so the block and the
+    plate are stored as holes): a free sphere in the flow and a fixed one whose stencils reach
+    into the block, against the oracle's reverse pass (which reads the mask directly)."""
+    from tests.helpers import oracle_from_workload
     rng = np.random.default_rng(3)
-    wl = dict(name="obstacle", precision="f64", steps=4, params=W.default_params(),
+    free = _sphere(np.array([15.4, 14.1, 15.2]), 2.0, rng)
+    fixed = _sphere(np.array([13.8, 9.0, 10.5]), 1.5, rng, fixed=True)
+    wl = dict(name="obstacle", precision=precision, steps=11,
+              params=W.default_params(kT=0.0, g_ext=(2e-6, -1e-6, 3e-6), tau_shear=0.8,
+                                      tau_bulk=1.1, tau_odd=0.9, tau_even=1.2),
               replicas=[dict(shape=(20, 18, 22), seed=1, mask=obstacle_mask(),
-                             bodies=[_sphere(np.array([15.4, 14.1, 15.2]), 2.0, rng,
-                                             fixed=True)])])
+                             bodies=[free, fixed])])
+    # some bead of the fixed sphere samples a node of the block
+    pos = fixed["pos"] + fixed["offsets"] @ _rotation(fixed["quat"]).T
+    lo = np.floor(pos - 0.5).astype(int)
+    m = obstacle_mask()
+    assert any(m[(lo[k, 2] + dz) % 22, (lo[k, 1] + dy) % 18, (lo[k, 0] + dx) % 20] == 1
+               for k in range(len(pos)) for dx in (0, 1) for dy in (0, 1) for dz in (0, 1))
+    T, K = 11, 4
+    a = np.zeros((T, 2, 3))
+    a[:, 0, 0] = 1.0 / T
+    a += 0.02 * rng.standard_normal(a.shape)
+    print(f"reverse pass with holes: {precision}", flush=True)
+    Jo, dgo, doo = oracle_from_workload(wl).adjoint(T, a)
     sim = gpu_from_workload(wl)
-    with pytest.raises(lbrb.LBError) as e:
-        sim.adjoint(4, np.zeros((4, 1, 3)), checkpoint_every=2)
-    assert e.value.code == lbrb.LB_ERR_STATE
+    Jg, dgg, dog = sim.adjoint(T, a, checkpoint_every=K)
     sim.close()
+    print(f"  J rel {abs(Jg - Jo) / abs(Jo):.2e}  dgamma rel "
+          f"{np.abs(dgg - dgo).max() / np.abs(dgo).max():.2e}  doffsets rel "
+          f"{np.abs(dog - doo).max() / np.abs(doo).max():.2e}", flush=True)
+    tJ, tg = (1e-12, 1e-10) if precision == "f64" else (2e-6, 5e-6)
+    assert abs(Jg - Jo) <= tJ * abs(Jo), (Jg, Jo)
+    assert np.abs(dgg - dgo).max() <= tg * np.abs(dgo).max(), (dgg, dgo)
+    assert np.abs(dog - doo).max() <= tg * np.abs(doo).max(), np.abs(dog - doo).max()
+
+
+def _rotation(q):
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
