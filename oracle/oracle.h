@@ -167,9 +167,9 @@ void     orc_collide_vjp(const orc_params* p, const double f_in[19], const doubl
  * (dJ_dgamma[n_bodies]) and every bead offset (dJ_doffsets: total beads * 3, bodies in
  * order), holding the window's initial state fixed.  Bodies may be fixed or free (the
  * derivative then runs through the rigid-body integrator as well), with one or several MD
- * steps per fluid step (F_b(n): the force of the fluid step's last MD step).  Requires
- * kT = 0 and no excluded-volume or wall sites; p must be the box's parameters.
- * Returns 0, or -1 on a violated requirement.                                              */
+ * steps per fluid step (F_b(n): the force of the fluid step's last MD step) and with WCA
+ * excluded volume (body sites and static sites).  Requires kT = 0; p must be the box's
+ * parameters.  Returns 0, or -1 on a violated requirement.                                 */
 int      orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies,
                      const double* dJ_dF, double* J_out, double* dJ_dgamma, double* dJ_doffsets);
 

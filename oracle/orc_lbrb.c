@@ -784,13 +784,24 @@ const double* orc_box_f(const orc_sim* s) { return s->f; }
 void orc_box_set_f(orc_sim* s, const double* f) { memcpy(s->f, f, sizeof(double) * 19 * (size_t)s->n); }
 const uint8_t* orc_box_mask(const orc_sim* s) { return s->mask; }
 double orc_box_kT(const orc_sim* s) { return s->p.kT; }
-/* MD steps per fluid step when there is no excluded volume, else 0                         */
-int orc_box_md_steps(const orc_sim* s)
+/* MD steps per fluid step                                                                 */
+int orc_box_md_steps(const orc_sim* s) { return s->p.md_substeps > 1 ? s->p.md_substeps : 1; }
+/* body b's excluded-volume sites (body-frame offsets) and their radius                      */
+int orc_box_ev(const orc_sim* s, int b, const double** offsets, int* n, double* radius)
 {
-    if (s->n_sites > 0) return 0;
-    for (int b = 0; b < s->n_bodies; ++b)
-        if (s->bodies[b].n_ev > 0) return 0;
-    return s->p.md_substeps > 1 ? s->p.md_substeps : 1;
+    if (b < 0 || b >= s->n_bodies) return -1;
+    *offsets = s->bodies[b].ev_offsets;
+    *n = s->bodies[b].n_ev;
+    *radius = s->bodies[b].ev_radius;
+    return 0;
+}
+/* the static sites (lab positions, radii)                                                  */
+int orc_box_sites(const orc_sim* s, const double** pos, const double** radius, int* n)
+{
+    *pos = s->site_pos;
+    *radius = s->site_radius;
+    *n = s->n_sites;
+    return 0;
 }
 int orc_box_body_mass(const orc_sim* s, int b, double* mass, double inertia[3])
 {

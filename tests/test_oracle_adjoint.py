@@ -8,7 +8,10 @@
   away from cell faces so that the finite difference does not cross a kink of the
   trilinear weights;
 - the same for a free body (moving and spinning, anisotropic inertia) beside a fixed one, so
-  that the derivative runs through both half kicks, the drift and the quaternion rotation.
+  that the derivative runs through both half kicks, the drift and the quaternion rotation,
+  with one, two and three MD steps per fluid step;
+- two free bodies whose excluded-volume sites press on each other and on a plane of pore
+  beads (WCA pairs active throughout, none near the cutoff), one and two MD steps.
 """
 import numpy as np
 import pytest
@@ -189,4 +192,109 @@ def test_free_body_window_gradient_matches_finite_difference(masked, md):
             om["offs"][k, a] -= h
             fd = (_run_free(shape, mask, params, op, fixed, steps, weights)
                   - _run_free(shape, mask, params, om, fixed, steps, weights)) / (2 * h)
+            assert abs(fd - do[k, a]) < 1e-5 * scale + 1e-13, (k, a, fd, do[k, a])
+
+
+def _wca_case():
+    """Two free bodies with excluded-volume sites next to each other and to a plane of static
+    sites (pore beads), in a periodic box with a weak flow, WCA pairs active throughout."""
+    shape = (14, 13, 12)
+    params = po.make_params(u0=(0.004, 0.0, 0.001), tau_shear=0.9, tau_bulk=1.2, tau_odd=1.05,
+                            tau_even=0.8, g_ext=(1e-5, 0.0, 0.0), wca_epsilon=1e-3)
+    axes = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float)
+    bodies = [dict(offs=W.sphere_beads(2.0, 24), mass=40.0, inertia=(40.0, 45.0, 50.0),
+                   centre=np.array([5.3, 6.1, 3.3]), vel=(0.002, -0.001, 0.0005),
+                   omega=(0.004, -0.003, 0.005), gamma=W.GAMMA_FREE, ev=(1.0 * axes, 0.8)),
+              dict(offs=W.sphere_beads(1.5, 12), mass=15.0, inertia=(8.0, 9.0, 10.0),
+                   centre=np.array([8.8, 6.1, 3.3]), vel=(-0.001, 0.0005, 0.0),
+                   omega=(-0.002, 0.004, 0.001), gamma=W.GAMMA_FREE, ev=(0.8 * axes, 0.8))]
+    gx, gy = np.meshgrid(np.arange(14) + 0.5, np.arange(13) + 0.5, indexing="ij")
+    walls = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, 1.0)], axis=1)
+    return shape, params, bodies, walls
+
+
+def _run_wca(shape, params, bodies, walls, steps, weights, adjoint=False, pairs=None):
+    sim = po.OracleSim(shape, params)
+    for j, b in enumerate(bodies):
+        sim.add_body(b["offs"], b["mass"], b["inertia"], b["centre"], vel=b["vel"],
+                     omega=b["omega"], gamma=b["gamma"])
+        sim.set_excluded_volume(j, *b["ev"])
+    sim.add_wall_sites(walls, 0.5)
+    if adjoint:
+        return sim.adjoint(steps, weights)
+    J = 0.0
+    for n in range(steps):
+        sim.step(1)
+        st = [sim.body_state(j) for j in range(len(bodies))]
+        for j in range(len(bodies)):
+            J += float(weights[n, j] @ st[j]["force"])
+        if pairs is not None:
+            pairs.append(st)
+    return J
+
+
+@pytest.mark.parametrize("md", [1, 2])
+def test_excluded_volume_window_gradient_matches_finite_difference(md):
+    """The reverse pass through the WCA pair forces (body-body and body-pore-bead pairs, whose
+    Jacobian moves both partners' positions and rotations) against central differences of
+    the forward oracle; no pair distance comes near the cutoff during the window."""
+    from scipy.spatial.transform import Rotation
+    shape, params, bodies, walls = _wca_case()
+    params.md_substeps = md
+    steps = 12
+    rng = np.random.default_rng(29)
+    weights = np.zeros((steps, 2, 3))
+    weights[:, 0, 0] = 1.0 / steps
+    weights += 0.02 * rng.standard_normal(weights.shape)
+    J, dg, do = _run_wca(shape, params, bodies, walls, steps, weights, adjoint=True)
+    states = []
+    assert abs(J - _run_wca(shape, params, bodies, walls, steps, weights, pairs=states)) < 1e-15
+    # WCA pairs are active, and none within 1e-3 of the cutoff, at the end of every step
+    cut = 2.0 ** (1.0 / 6.0)
+    active, margin = 0, 1.0
+    for st in states:
+        sites = []
+        for j, b in enumerate(bodies):
+            q = st[j]["quat"]
+            Rm = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+            sites.append(st[j]["pos"] + b["ev"][0] @ Rm.T)
+        for x in sites[0]:
+            for y, sig in [(y, 1.6) for y in sites[1]] + [(w, 1.3) for w in walls]:
+                d = x - y
+                d -= np.array(shape) * np.round(d / np.array(shape))
+                r = np.linalg.norm(d)
+                margin = min(margin, abs(r - cut * sig))
+                active += r < cut * sig
+        for y in sites[1]:
+            for w in walls:
+                d = y - w
+                d -= np.array(shape) * np.round(d / np.array(shape))
+                r = np.linalg.norm(d)
+                margin = min(margin, abs(r - cut * 1.3))
+                active += r < cut * 1.3
+    assert active >= 2 * steps and margin > 1e-3, (active, margin)
+    h = 1e-6
+    for b in range(2):
+        bp = [dict(x) for x in bodies]
+        bm = [dict(x) for x in bodies]
+        bp[b]["gamma"] += h
+        bm[b]["gamma"] -= h
+        fd = (_run_wca(shape, params, bp, walls, steps, weights)
+              - _run_wca(shape, params, bm, walls, steps, weights)) / (2 * h)
+        # relative to the larger of the two: the small body's derivative (~1e-5 of J's scale)
+        # sits near the rounding noise of J divided by 2h
+        assert abs(fd - dg[b]) < 1e-6 * np.abs(dg).max() + 1e-12, (b, fd, dg[b])
+    scale = np.abs(do).max()
+    n0 = len(bodies[0]["offs"])
+    for k in (0, 7, 19, n0 + 3, n0 + 8):
+        b, kk = (0, k) if k < n0 else (1, k - n0)
+        for a in range(3):
+            bp = [dict(x) for x in bodies]
+            bm = [dict(x) for x in bodies]
+            bp[b]["offs"] = bodies[b]["offs"].copy()
+            bm[b]["offs"] = bodies[b]["offs"].copy()
+            bp[b]["offs"][kk, a] += h
+            bm[b]["offs"][kk, a] -= h
+            fd = (_run_wca(shape, params, bp, walls, steps, weights)
+                  - _run_wca(shape, params, bm, walls, steps, weights)) / (2 * h)
             assert abs(fd - do[k, a]) < 1e-5 * scale + 1e-13, (k, a, fd, do[k, a])
