@@ -129,15 +129,17 @@ __device__ __forceinline__ void qmul(const double a[4], const double b[4], doubl
     o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
 }
 
-__global__ __launch_bounds__(64) void adj_body_pre_kernel(const Body* in, int par,
+__global__ __launch_bounds__(64) void adj_body_pre_kernel(const Body* in, const Body* out, int par,
                                                           const double* weights, const double* adj,
-                                                          double* body_adj, int n)
+                                                          double* body_adj, double* J, int n)
 {
     const int b = blockIdx.x * 64 + threadIdx.x;
     if (b >= n) return;
     const Body& B = in[b];
     const double* a = weights + 3 * (int64_t)b;
     double* o = body_adj + 6 * (int64_t)b;
+    const double* Fo = out[b].force;
+    J[b] += a[0] * Fo[0] + a[1] * Fo[1] + a[2] * Fo[2];
     if (B.fixed) {
         for (int k = 0; k < 3; ++k) { o[k] = a[k]; o[3 + k] = 0.0; }
         return;
@@ -155,7 +157,8 @@ __global__ __launch_bounds__(64) void adj_body_pre_kernel(const Body* in, int pa
 }
 
 __global__ __launch_bounds__(256) void adj_body_post_kernel(const Body* in, const Body* out, int par,
-                                                            const double* bead_sums, double* adj)
+                                                            const double* bead_sums, double* adj,
+                                                            double* wadj)
 {
     const Body& B = in[blockIdx.x];
     if (B.fixed) return;   // uniform over the workgroup
@@ -197,7 +200,12 @@ __global__ __launch_bounds__(256) void adj_body_post_kernel(const Body* in, cons
         T[r] = rot[3 * r] * tq[0] + rot[3 * r + 1] * tq[1] + rot[3 * r + 2] * tq[2];
     }
     cross3(Tb, T, th);
-    for (int k = 0; k < 3; ++k) th[k] += S[6 + k];
+    double* wa = wadj + 6 * (int64_t)blockIdx.x;   // the excluded-volume pass's share
+    for (int k = 0; k < 3; ++k) {
+        th[k] += S[6 + k] + wa[3 + k];
+        Rc[k] += wa[k];
+    }
+    for (int k = 0; k < 6; ++k) wa[k] = 0.0;
     // the pose's quaternion: its own adjoint plus the rotation's
     const double* qc = P.quat;
     const double t2[4] = {0.0, 2.0 * th[0], 2.0 * th[1], 2.0 * th[2]};
@@ -246,20 +254,157 @@ __global__ __launch_bounds__(256) void adj_body_post_kernel(const Body* in, cons
     for (int k = 0; k < 4; ++k) ab[3 + k] = qib[k];
 }
 
-void launch_adjoint_body_pre(const Body* in, int par, const double* weights, const double* adj,
-                             double* body_adj, int n_bodies, hipStream_t s)
+void launch_adjoint_body_pre(const Body* in, const Body* out, int par, const double* weights,
+                             const double* adj, double* body_adj, double* J, int n_bodies,
+                             hipStream_t s)
 {
     if (n_bodies <= 0) return;
-    hipLaunchKernelGGL(adj_body_pre_kernel, dim3((n_bodies + 63) / 64), dim3(64), 0, s, in, par,
-                       weights, adj, body_adj, n_bodies);
+    hipLaunchKernelGGL(adj_body_pre_kernel, dim3((n_bodies + 63) / 64), dim3(64), 0, s, in, out,
+                       par, weights, adj, body_adj, J, n_bodies);
 }
 
 void launch_adjoint_body_post(const Body* in, const Body* out, int par, const double* bead_sums,
-                              double* adj, int n_bodies, hipStream_t s)
+                              double* adj, double* wadj, int n_bodies, hipStream_t s)
 {
     if (n_bodies <= 0) return;
     hipLaunchKernelGGL(adj_body_post_kernel, dim3(n_bodies), dim3(256), 0, s, in, out, par,
-                       bead_sums, adj);
+                       bead_sums, adj, wadj);
+}
+
+// ------------------------------------------------------------------ excluded volume
+
+__device__ __forceinline__ void min_image3(const double a[3], const double b[3], const double L[3],
+                                           double d[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        d[k] = a[k] - b[k];
+        d[k] -= L[k] * round(d[k] / L[k]);
+    }
+}
+
+// WCA pair at separation d: the force on the first site is c d; returns false beyond the
+// cutoff, else c and its derivative c' with respect to |d|^2
+__device__ __forceinline__ bool wca_pair_c(double eps, double sigma, const double d[3], double& c,
+                                           double& cp)
+{
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (!(r2 < 1.2599210498948732 * sigma * sigma)) return false;   // 2^(1/3) sigma^2
+    const double s2 = sigma * sigma / r2, s6 = s2 * s2 * s2, s12 = s6 * s6;
+    c = 24.0 * eps * (2.0 * s12 - s6) / r2;
+    cp = 24.0 * eps * (4.0 * s6 - 14.0 * s12) / (r2 * r2);
+    return true;
+}
+
+__device__ __forceinline__ int coarse_cell(double x, double L, double w, int n)
+{
+    const double xw = x - L * floor(x / L);
+    const int c = (int)(xw / w);
+    return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
+// one workgroup per body with excluded-volume sites, one thread per site
+__global__ __launch_bounds__(256) void adj_wca_kernel(const BodyArgs ba, int par,
+                                                      const double* body_adj, double* wadj)
+{
+    const int b = blockIdx.x;
+    const Body& B = ba.bodies[b];
+    if (B.n_ev == 0) return;   // uniform over the workgroup
+    const Pose& P = B.pose[par];
+    const WcaRep W = ba.wrep[B.replica];
+    const double L[3] = {(double)B.box.nx, (double)B.box.ny, (double)B.box.nz};
+    const double eps = ba.wca_eps;
+    const double* bj = body_adj + 6 * (int64_t)b;   // Fbar_b, Tbar_b (lab)
+    const bool free_b = B.fixed == 0;
+    double acc[6] = {0, 0, 0, 0, 0, 0};             // this body's centre and angle adjoints
+    for (int k = threadIdx.x; k < B.n_ev; k += blockDim.x) {
+        const double* off = ba.ev[B.first_ev + k].off;
+        double d[3], x[3], g[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            d[ax] = P.rot[3 * ax] * off[0] + P.rot[3 * ax + 1] * off[1] + P.rot[3 * ax + 2] * off[2];
+            x[ax] = P.pos[ax] + d[ax];
+        }
+        g[0] = bj[0] + (bj[4] * d[2] - bj[5] * d[1]);
+        g[1] = bj[1] + (bj[5] * d[0] - bj[3] * d[2]);
+        g[2] = bj[2] + (bj[3] * d[1] - bj[4] * d[0]);
+        // one pair at separation dd: the adjoint of the separation (df/dd g) and the force
+        auto pair = [&](const double dd[3], double sigma, double db[3], double f[3]) {
+            double c, cp;
+            if (!wca_pair_c(eps, sigma, dd, c, cp)) return false;
+            const double dg = dd[0] * g[0] + dd[1] * g[1] + dd[2] * g[2];
+            for (int ax = 0; ax < 3; ++ax) {
+                db[ax] = c * g[ax] + 2.0 * cp * dg * dd[ax];
+                f[ax] = c * dd[ax];
+            }
+            return true;
+        };
+        // the site's own share: x = R + d; d also the torque's arm
+        auto own = [&](const double db[3], const double f[3]) {
+            if (!free_b) return;
+            const double a0 = db[0] + (f[1] * bj[5] - f[2] * bj[4]);
+            const double a1 = db[1] + (f[2] * bj[3] - f[0] * bj[5]);
+            const double a2 = db[2] + (f[0] * bj[4] - f[1] * bj[3]);
+            acc[0] += db[0]; acc[1] += db[1]; acc[2] += db[2];
+            acc[3] += d[1] * a2 - d[2] * a1;
+            acc[4] += d[2] * a0 - d[0] * a2;
+            acc[5] += d[0] * a1 - d[1] * a0;
+        };
+        if (W.cx > 0) {   // static sites: the coarse cell's neighbourhood holds every one in range
+            const int cell = W.cell0 + coarse_cell(x[0], L[0], W.cw[0], W.cx) +
+                             W.cx * (coarse_cell(x[1], L[1], W.cw[1], W.cy) +
+                                     W.cy * coarse_cell(x[2], L[2], W.cw[2], W.cz));
+            for (int i = ba.nb_start[cell]; i < ba.nb_start[cell + 1]; ++i) {
+                const WallSite ws = ba.nb_sites[i];
+                double dd[3], db[3], f[3];
+                min_image3(x, ws.p, L, dd);
+                if (pair(dd, B.ev_radius + ws.radius, db, f)) own(db, f);
+            }
+        }
+        for (int j = 0; j < W.n_bodies; ++j) {   // the other bodies' sites
+            const int o = ba.rep_bodies[W.first_body + j];
+            if (o == b) continue;
+            const Body& O = ba.bodies[o];
+            if (O.n_ev == 0) continue;
+            const Pose& Q = O.pose[par];
+            double dc[3];
+            min_image3(P.pos, Q.pos, L, dc);
+            const double reach = B.ev_reach + O.ev_reach + 1.1224620483093730 * (B.ev_radius + O.ev_radius);
+            if (!(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2] < reach * reach)) continue;
+            const bool free_o = O.fixed == 0;
+            for (int m = 0; m < O.n_ev; ++m) {
+                const double* oo = ba.ev[O.first_ev + m].off;
+                double dq[3], y[3], dd[3], db[3], f[3];
+                for (int ax = 0; ax < 3; ++ax) {
+                    dq[ax] = Q.rot[3 * ax] * oo[0] + Q.rot[3 * ax + 1] * oo[1] + Q.rot[3 * ax + 2] * oo[2];
+                    y[ax] = Q.pos[ax] + dq[ax];
+                }
+                min_image3(x, y, L, dd);
+                if (!pair(dd, B.ev_radius + O.ev_radius, db, f)) continue;
+                own(db, f);
+                if (free_o) {   // y = R_o + d_o enters the separation with the opposite sign
+                    double* wo = wadj + 6 * (int64_t)o;
+                    atomicAdd(wo + 0, -db[0]);
+                    atomicAdd(wo + 1, -db[1]);
+                    atomicAdd(wo + 2, -db[2]);
+                    atomicAdd(wo + 3, -(dq[1] * db[2] - dq[2] * db[1]));
+                    atomicAdd(wo + 4, -(dq[2] * db[0] - dq[0] * db[2]));
+                    atomicAdd(wo + 5, -(dq[0] * db[1] - dq[1] * db[0]));
+                }
+            }
+        }
+    }
+    if (!free_b) return;   // uniform
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        for (int k = 0; k < 6; ++k) acc[k] += __shfl_down(acc[k], m, 64);
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 6; ++k) atomicAdd(wadj + 6 * (int64_t)b + k, acc[k]);
+}
+
+void launch_adjoint_wca(const BodyArgs& ba, int par, const double* body_adj, double* wadj,
+                        hipStream_t s)
+{
+    if (ba.n_bodies <= 0 || !ba.wca_ft) return;
+    hipLaunchKernelGGL(adj_wca_kernel, dim3(ba.n_bodies), dim3(256), 0, s, ba, par, body_adj, wadj);
 }
 
 template void launch_adjoint_step<float>(const AdjArgs<float>&, bool, hipStream_t);

@@ -122,9 +122,9 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
         const Pose& P = A.snap[body].pose[A.pose_par];
         const double* w = P.omega_lab;
         const double* d = X.dv;
+        // (the objective is taken from the body forces by the body pass)
         double lv[3], db[3], y[3];
         for (int ax = 0; ax < 3; ++ax) {
-            jp += an[ax] * Fk[ax];
             dg += lFk[ax] * (s6[ax] - X.v[ax]);
             lv[ax] = -X.gamma * lFk[ax];
         }

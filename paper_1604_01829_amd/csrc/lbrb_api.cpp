@@ -754,7 +754,7 @@ struct AdjPlan {
     size_t state = 0;
     size_t off_ck, off_seg, off_lam0, off_lam1, off_lamF, off_w, off_dr, off_dg, off_J,
         off_bf, off_save, off_snap, off_badj, off_bin, off_bsum, off_recs, off_scr, off_zero,
-        total;
+        off_wadj, off_Jb, total;
 };
 
 bool any_free(const lb_ctx* c)
@@ -764,10 +764,19 @@ bool any_free(const lb_ctx* c)
     return false;
 }
 
-// the reverse pass runs the body passes (free bodies, or several MD steps per fluid step);
-// otherwise it runs the fixed-body schedule, with a fluid step's coupling fused into the
-// next reverse step's bead launch
-bool body_passes(const lb_ctx* c) { return any_free(c) || md_steps(c) > 1; }
+// excluded-volume forces act (from the sites as set, whether or not their tables are built)
+bool has_wca(const lb_ctx* c)
+{
+    if (!(c->p.wca_epsilon > 0.0)) return false;
+    for (const EvHost& E : c->ev)
+        if (!E.off.empty()) return true;
+    return false;
+}
+
+// the reverse pass runs the body passes (free bodies, several MD steps per fluid step, or
+// excluded volume); otherwise it runs the fixed-body schedule, with a fluid step's coupling
+// fused into the next reverse step's bead launch
+bool body_passes(const lb_ctx* c) { return any_free(c) || md_steps(c) > 1 || has_wca(c); }
 
 bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
 {
@@ -802,9 +811,11 @@ bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
         ap.off_recs = take(sizeof(BeadRec) * nb);
         ap.off_scr = take(sizeof(Body) * nbod * (size_t)std::max(1, m - 1));
         ap.off_zero = take(sizeof(double) * 3 * nbod);
+        ap.off_wadj = take(sizeof(double) * 6 * nbod);
+        ap.off_Jb = take(sizeof(double) * nbod);
     } else {
         ap.off_snap = ap.off_badj = ap.off_bin = ap.off_bsum = ap.off_recs = 0;
-        ap.off_scr = ap.off_zero = 0;
+        ap.off_scr = ap.off_zero = ap.off_wadj = ap.off_Jb = 0;
     }
     ap.total = o;
     return true;
@@ -826,9 +837,11 @@ void enqueue_recoupling(lb_ctx* c, hipStream_t s, const StepArgs<Real>& a, int64
     for (int k = 0; k < m; ++k) {
         ca.md_step = (uint32_t)k;
         ca.bead_force = bf + nbf * (size_t)k;
-        launch_couple<Real>(a, ca, s);
+        const Body* from = k == 0 ? table : scr + (size_t)c->n_bodies * (k - 1);
+        BodyArgs wb = body_args(c);   // the excluded volume at the MD step's poses
+        wb.bodies = const_cast<Body*>(from);
+        launch_couple<Real>(a, ca, s, LaunchEvents{}, &wb);
         if (k + 1 < m) {
-            const Body* from = k == 0 ? table : scr + (size_t)c->n_bodies * (k - 1);
             Body* to = scr + (size_t)c->n_bodies * k;
             (void)hipMemcpyAsync(to, from, sizeof(Body) * (size_t)c->n_bodies, hipMemcpyDeviceToDevice, s);
             BodyArgs ba = body_args(c);
@@ -918,6 +931,8 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
         if (c->n_beads <= 0) return;
         auto table = [&](int k) { return k == 0 ? t0 : k == m ? t0 + nb : scr + nb * (k - 1); };
         double* badj = (double*)(ws + ap.off_badj);
+        double* bin = (double*)(ws + ap.off_bin);
+        double* wadj = (double*)(ws + ap.off_wadj);
         const double* zero = (const double*)(ws + ap.off_zero);
         const double* weights = A[cg].weights;
         for (int k = m - 1; k >= 0; --k) {
@@ -928,11 +943,16 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
             X.snap = table(k);
             X.pose_par = par;
             launch_records_from_poses(table(k), par, c->d_beads, c->d_recs, c->n_beads, s);
-            launch_adjoint_body_pre(table(k), par, X.weights, badj, (double*)(ws + ap.off_bin),
-                                    c->n_bodies, s);
+            launch_adjoint_body_pre(table(k), table(k + 1), par, X.weights, badj, bin,
+                                    (double*)(ws + ap.off_Jb), c->n_bodies, s);
             launch_adjoint_beads<Real>(X, s);
+            if (has_wca(c)) {
+                BodyArgs wb = body_args(c);
+                wb.bodies = const_cast<Body*>(table(k));
+                launch_adjoint_wca(wb, par, bin, wadj, s);
+            }
             launch_adjoint_body_post(table(k), table(k + 1), par, (const double*)(ws + ap.off_bsum),
-                                     badj, c->n_bodies, s);
+                                     badj, wadj, c->n_bodies, s);
         }
         return;
     }
@@ -1895,10 +1915,10 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     if (!dev_ws || ((uintptr_t)dev_ws % kAlign) != 0 || ws_bytes < ap.total)
         return fail(c, LB_ERR_ARG, "reverse-pass workspace missing, misaligned or too small");
     if (c->p.kT != 0.0) return fail(c, LB_ERR_STATE, "the reverse pass needs kT = 0");
-    bool any_ev = false;
-    for (const EvHost& E : c->ev) any_ev = any_ev || !E.off.empty();
-    if (any_ev || c->n_sites > 0)
-        return fail(c, LB_ERR_STATE, "the reverse pass needs a context without excluded volume");
+    if (c->wca_dirty) {
+        const int rc = build_wca(c);
+        if (rc != LB_OK) return rc;
+    }
     if (c->n_bodies > 0 && (!dJ_dF || !dJ_dgamma || !dJ_doffsets))
         return fail(c, LB_ERR_ARG, "missing objective weights or gradient outputs");
     char* ws = (char*)dev_ws;
@@ -1913,10 +1933,11 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_dg, 0, sizeof(double) * nb, s));
     HIP_TRY(c, hipMemsetAsync(ws + ap.off_J, 0, sizeof(double) * nb, s));
     if (body_passes(c)) {
-        HIP_TRY(c, hipMemsetAsync(ws + ap.off_badj, 0,
-                                  sizeof(double) * kBodyAdjWords * std::max<int32_t>(c->n_bodies, 1), s));
-        HIP_TRY(c, hipMemsetAsync(ws + ap.off_zero, 0,
-                                  sizeof(double) * 3 * std::max<int32_t>(c->n_bodies, 1), s));
+        const size_t nbod = (size_t)std::max<int32_t>(c->n_bodies, 1);
+        HIP_TRY(c, hipMemsetAsync(ws + ap.off_badj, 0, sizeof(double) * kBodyAdjWords * nbod, s));
+        HIP_TRY(c, hipMemsetAsync(ws + ap.off_zero, 0, sizeof(double) * 3 * nbod, s));
+        HIP_TRY(c, hipMemsetAsync(ws + ap.off_wadj, 0, sizeof(double) * 6 * nbod, s));
+        HIP_TRY(c, hipMemsetAsync(ws + ap.off_Jb, 0, sizeof(double) * nbod, s));
     }
     {
         const int rc = prepare_bodies(c, s);
@@ -1938,6 +1959,11 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
     HIP_TRY(c, hipStreamSynchronize(s));
     double Jsum = 0.0;
     for (int32_t k = 0; k < c->n_beads; ++k) Jsum += jp[k];
+    if (body_passes(c) && c->n_bodies > 0) {   // the body passes took J from the body forces
+        std::vector<double> jb(c->n_bodies);
+        HIP_TRY(c, hipMemcpy(jb.data(), ws + ap.off_Jb, sizeof(double) * jb.size(), hipMemcpyDeviceToHost));
+        for (double v : jb) Jsum += v;
+    }
     if (J) *J = Jsum;
     const bool body_frame = body_passes(c);   // the bead pass then accumulated body-frame values
     for (int32_t b = 0; b < c->n_bodies; ++b) {

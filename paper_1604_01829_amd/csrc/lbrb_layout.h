@@ -275,10 +275,21 @@ struct AdjArgs {
 // the MD step.  Fixed bodies: weights only.
 constexpr int kBodyAdjWords = 19;
 constexpr int kBeadSumWords = 12;
-void launch_adjoint_body_pre(const Body* in, int par, const double* weights, const double* adj,
-                             double* body_adj, int n_bodies, hipStream_t s);
+// pre also adds weights . (force after the MD step, excluded volume included) into J[b].
+// post also adds the excluded-volume pass's adjoint of the pose (wadj, 6 per body: centre,
+// lab angle vector) and clears it.
+void launch_adjoint_body_pre(const Body* in, const Body* out, int par, const double* weights,
+                             const double* adj, double* body_adj, double* J, int n_bodies,
+                             hipStream_t s);
 void launch_adjoint_body_post(const Body* in, const Body* out, int par, const double* bead_sums,
-                              double* adj, int n_bodies, hipStream_t s);
+                              double* adj, double* wadj, int n_bodies, hipStream_t s);
+// The excluded-volume pass of one MD step of a reverse step: for every WCA pair of a body's
+// site (ba.bodies at pose[par]) with a static site or another body's site, the pair force's
+// Jacobian takes the adjoint of the force on the first site (Fbar_b + Tbar_b x d, from
+// body_adj) to both sites' positions, and the torque's arm adds f x Tbar_b: into wadj of the
+// free bodies involved (atomic adds).
+void launch_adjoint_wca(const BodyArgs& ba, int par, const double* body_adj, double* wadj,
+                        hipStream_t s);
 // the pose part of every bead record from its body's pose[par] (the records a step's coupling
 // reads), for recomputing the steps of a window
 void launch_records_from_poses(const Body* bodies, int par, const Bead* beads, BeadRec* recs,

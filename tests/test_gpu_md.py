@@ -192,14 +192,14 @@ def test_md_errors():
     s.add_wall_sites(0, rep["wall_sites"][0][:10], 12.0)
     assert code(s.step, 1) == lbrb.LB_ERR_ARG
     s.close()
-    # the reverse pass needs one MD step per fluid step (and no excluded volume)
+    # the reverse pass runs with several MD steps per fluid step and with excluded volume
+    # (its values are checked against the oracle's reverse pass in test_gpu_adjoint)
     for kw in (dict(md_substeps=2), dict(md_substeps=1, max_ev_sites=len(inner))):
         s = sim_with(fixed=True, kT=0.0, **kw)
         if "max_ev_sites" in kw:
             s.set_excluded_volume(0, 0, inner, 0.5)
-        with pytest.raises(lbrb.LBError) as ei:
-            s.adjoint(2, np.zeros((2, 1, 3)), 1)
-        assert ei.value.code == lbrb.LB_ERR_STATE
+        J, dg, do = s.adjoint(2, np.ones((2, 1, 3)), 1)
+        assert np.isfinite(J) and np.all(np.isfinite(dg)) and np.all(np.isfinite(do))
         s.close()
 
 
