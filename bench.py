@@ -375,10 +375,31 @@ def compare_runs(args, wl4):
     sim.adjoint(T, a, 1)
     t_all = time.perf_counter() - t0
     sim.close()
+    # the same sphere released: free, so the reverse pass also runs through the rigid-body
+    # integrator (body passes around the bead pass, records rewritten per recomputed step)
+    b5 = wl5["replicas"][0]["bodies"][0]
+    b5["fixed"] = False
+    b5["gamma"] = W.GAMMA_FREE
+    b5["omega"] = np.array([0.002, -0.001, 0.0015])
+    sim = lbrb.simulation_from_workload(wl5, precision="f32")
+    sim.set_graph_steps(100)
+    sim.adjoint(T, a, K)                    # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(T)
+    torch.cuda.synchronize()
+    t_ffwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sim.adjoint(T, a, K)
+    t_fadj = time.perf_counter() - t0
+    sim.close()
     out["adjoint"] = {"window_steps": T, "checkpoint_every": K, "forward_ms": round(t_fwd * 1e3, 3),
                       "adjoint_ms": round(t_adj * 1e3, 3), "ratio": round(t_adj / t_fwd, 2),
                       "all_states_kept_ms": round(t_all * 1e3, 3),
-                      "all_states_kept_ratio": round(t_all / t_fwd, 2)}
+                      "all_states_kept_ratio": round(t_all / t_fwd, 2),
+                      "free_body_forward_ms": round(t_ffwd * 1e3, 3),
+                      "free_body_adjoint_ms": round(t_fadj * 1e3, 3),
+                      "free_body_ratio": round(t_fadj / t_ffwd, 2)}
     return out
 
 
