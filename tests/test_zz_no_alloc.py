@@ -3,8 +3,9 @@ cannot allocate device memory) against lb_rb_adjoint with a caller workspace, th
 C-ABI: two calls in a row on one GPU, the second with a smaller box and window, so the second
 runs on whatever the first left in the scratch array; FP64 (gradients to 1e-12 relative: the
 atomic accumulation of sampled-velocity adjoints is not order-deterministic) and FP32 (1e-6);
-the contexts end in the same state bit for bit; a window beyond the array is refused before
-anything runs.
+the contexts end in the same state bit for bit; the same with a free body and two MD steps
+per fluid step (the body passes' tables and sums in the array); a window beyond the array is
+refused before anything runs.
 """
 import numpy as np
 import pytest
@@ -51,6 +52,28 @@ def test_noalloc_reverse_pass_matches_the_workspace_one(precision):
         assert 0 < need <= lbrb.LB_NOALLOC_SCRATCH_BYTES
         print(f"  call {k}: box {shape}, window {T}, checkpoints every {K}, {need} bytes",
               flush=True)
+        want = ref.adjoint(T, a, checkpoint_every=K)
+        got = sim.adjoint_noalloc(T, a, checkpoint_every=K)
+        _compare(want, got, tol)
+        assert np.array_equal(_state(ref), _state(sim))
+        ref.close()
+        sim.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_noalloc_reverse_pass_with_free_bodies(precision):
+    """The body passes (a free body beside a fixed one, two MD steps per fluid step, then one)
+    on the scratch array: body tables, body adjoints and bead sums live there too."""
+    from tests.test_gpu_adjoint import _free_case, _gpu_free
+    tol = 1e-12 if precision == "f64" else 1e-6
+    for k, (masked, md, T, K) in enumerate(((False, 2, 9, 4), (True, 1, 6, 3))):
+        shape, mask, pp, bodies = _free_case(masked)
+        a = _weights(T, len(bodies), seed=11 + k)
+        ref = _gpu_free(shape, mask, pp, bodies, precision, md)
+        sim = _gpu_free(shape, mask, pp, bodies, precision, md)
+        need = lbrb.lb_adjoint_workspace_bytes(sim.ctx, T, K)
+        assert 0 < need <= lbrb.LB_NOALLOC_SCRATCH_BYTES
+        print(f"  call {k}: free body, {md} MD steps, window {T}, {need} bytes", flush=True)
         want = ref.adjoint(T, a, checkpoint_every=K)
         got = sim.adjoint_noalloc(T, a, checkpoint_every=K)
         _compare(want, got, tol)
