@@ -529,6 +529,68 @@ def test_full_size_free_sphere_against_the_oracle_adjoint(precision):
     assert eJ <= tJ and eg <= tg and eo <= tg
 
 
+def _confined_sim(precision, gamma0=None, offsets0=None):
+    """The paper's confined scheme at full size (workload 2's pore and 32 free spheres, two MD
+    steps per fluid step, WCA inner layers and pore beads at eps = the workload's kT),
+    deterministic, with a pressure gradient along the pore."""
+    from paper_1604_01829_amd import lbrb
+    w = W.confined_md_workload(substeps=2)
+    w["params"]["kT"] = 0.0
+    w["params"]["g_ext"] = (0.0, 0.0, 2e-6)
+    b0 = w["replicas"][0]["bodies"][0]
+    if gamma0 is not None:
+        b0["gamma"] = gamma0
+    if offsets0 is not None:
+        b0["offsets"] = offsets0
+    return w, lbrb.simulation_from_workload(w, precision=precision)
+
+
+def test_full_size_confined_pore_gradient():
+    """128 x 128 x 256 pore, 32 free spheres, two MD steps per fluid step, WCA between inner
+    layers and with 2,958 pore beads: J = drag of sphere 0 along the pore averaged over 30
+    steps (checkpoints every 10).  FP64 against central differences of FP64 forward runs of
+    the library (its gamma, its offsets along the gradient's direction), FP32 against FP64."""
+    import time
+    import torch
+    T, K = 30, 10
+    a = np.zeros((T, 32, 3))
+    a[:, 0, 2] = 1.0 / T
+    print("confined pore, full size: f64 reverse pass", flush=True)
+    w, sim = _confined_sim("f64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, dg, do = sim.adjoint(T, a, checkpoint_every=K)
+    t_adj = time.perf_counter() - t0
+    sim.close()
+    g0 = w["replicas"][0]["bodies"][0]["gamma"]
+    h = 1e-5 * g0
+    fd = (_forward_J(_confined_sim("f64", gamma0=g0 + h)[1], T, a)
+          - _forward_J(_confined_sim("f64", gamma0=g0 - h)[1], T, a)) / (2 * h)
+    print(f"  J {J:.6e}  dJ/dgamma_0 {dg[0]:.9e}  central difference {fd:.9e}  "
+          f"reverse pass {t_adj * 1e3:.1f} ms", flush=True)
+    assert abs(fd - dg[0]) <= 1e-6 * max(abs(fd), abs(J) / g0), (fd, dg[0])
+    offs = np.asarray(w["replicas"][0]["bodies"][0]["offsets"], dtype=np.float64)
+    n0 = len(offs)
+    v = do[:n0] / np.abs(do[:n0]).max()
+    hh = 1e-6
+    fdo = (_forward_J(_confined_sim("f64", offsets0=offs + hh * v)[1], T, a)
+           - _forward_J(_confined_sim("f64", offsets0=offs - hh * v)[1], T, a)) / (2 * hh)
+    D = float(np.sum(do[:n0] * v))
+    print(f"  offsets of sphere 0 along the gradient: adjoint {D:.9e}  central difference "
+          f"{fdo:.9e}", flush=True)
+    assert abs(fdo - D) <= 1e-4 * abs(D), (fdo, D)
+    print("confined pore, full size: f32 reverse pass", flush=True)
+    _, sim = _confined_sim("f32")
+    J32, dg32, do32 = sim.adjoint(T, a, checkpoint_every=K)
+    sim.close()
+    print(f"  FP32 vs FP64: J rel {abs(J32 - J) / abs(J):.2e}  dgamma rel "
+          f"{np.abs(dg32 - dg).max() / np.abs(dg).max():.2e}  doffsets rel "
+          f"{np.abs(do32 - do).max() / np.abs(do).max():.2e}", flush=True)
+    assert abs(J32 - J) <= 1e-5 * abs(J)
+    assert np.abs(dg32 - dg).max() <= 1e-5 * max(np.abs(dg).max(), abs(J) / g0)
+    assert np.abs(do32 - do).max() <= 1e-5 * np.abs(do).max()
+
+
 def test_autograd_function_returns_the_library_gradient():
     import torch
     from paper_1604_01829_amd import lbrb
