@@ -168,8 +168,9 @@ void     orc_collide_vjp(const orc_params* p, const double f_in[19], const doubl
  * order), holding the window's initial state fixed.  Bodies may be fixed or free (the
  * derivative then runs through the rigid-body integrator as well), with one or several MD
  * steps per fluid step (F_b(n): the force of the fluid step's last MD step) and with WCA
- * excluded volume (body sites and static sites).  Requires kT = 0; p must be the box's
- * parameters.  Returns 0, or -1 on a violated requirement.                                 */
+ * excluded volume (body sites and static sites); for kT > 0 the pathwise derivative at the
+ * forward run's noise draws.  p must be the box's parameters.  Returns 0, or -1 on a
+ * violated requirement.                                                                   */
 int      orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies,
                      const double* dJ_dF, double* J_out, double* dJ_dgamma, double* dJ_doffsets);
 

@@ -8,7 +8,10 @@
  * (a = (1/T, 0, 0) for every step gives the time-averaged drag along x).  Derivatives are
  * taken with respect to each body's bead friction gamma_b and each bead's body-frame offset.
  *
- * Scope: a deterministic fluid (kT = 0), one or several MD steps per fluid step (the MD
+ * Scope: a deterministic or a thermal fluid (for kT > 0 the derivative is pathwise: the noise
+ * draws of every step are those of the forward run, counter-based, and the bead noise
+ * amplitude sqrt(2 kT gamma / h) is differentiated in gamma; the fluid's noise enters the
+ * collision additively and leaves its Jacobian unchanged), one or several MD steps per fluid step (the MD
  * steps of a fluid step all read the same populations and each spreads -h times its bead
  * forces), WCA excluded volume (Sec. 2.1 inner layers, Sec. 2.3 pore beads); boundary masks
  * allowed; bodies fixed or free.  F_b(n) is the force of the last MD step of fluid step n
@@ -57,6 +60,7 @@ double orc_box_kT(const orc_sim* s);
 int orc_box_md_steps(const orc_sim* s);
 int orc_box_ev(const orc_sim* s, int b, const double** offsets, int* n, double* radius);
 int orc_box_sites(const orc_sim* s, const double** pos, const double** radius, int* n);
+int orc_box_bead_uniforms(const orc_sim* s, int64_t step, int bead, int k_md, double out[3]);
 int orc_box_body_mass(const orc_sim* s, int b, double* mass, double inertia[3]);
 int orc_box_first_half(const orc_sim* s, int b, const double state[19], double h, double out[13]);
 int orc_box_second_half(const orc_sim* s, int b, const double in[19], double h, double out[19]);
@@ -325,7 +329,9 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
     const int64_t N = (int64_t)nx * ny * nz;
     const uint8_t* mask = orc_box_mask(s);
     const int m = orc_box_md_steps(s);
-    if (orc_box_kT(s) != 0.0 || n_steps < 0) return -1;
+    if (n_steps < 0) return -1;
+    const double kT = orc_box_kT(s);
+    const int64_t step0 = orc_step_count(s);
     const double h = 1.0 / m;   /* MD step */
     adj_tables();   /* before the parallel node loop */
 
@@ -414,6 +420,12 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
                     }
                     double* F = bead_F + 3 * ((size_t)k * ntb + kb);
                     for (int a = 0; a < 3; ++a) F[a] = -gamma * (v[a] - uk[a]);
+                    if (kT > 0.0) {   /* the forward run's bead noise of this MD step */
+                        const double amp = sqrt(2.0 * kT * gamma / h) * sqrt(12.0);
+                        double un[3];
+                        orc_box_bead_uniforms(s, step0 + n, kb, k, un);
+                        for (int a = 0; a < 3; ++a) F[a] += amp * un[a];
+                    }
                     for (int c = 0; c < 8; ++c) {
                         if (mask[idx[c]]) continue;
                         for (int a = 0; a < 3; ++a) g[3 * idx[c] + a] -= w[c] * (h * F[a]);
@@ -539,10 +551,13 @@ int orc_adjoint(orc_sim* s, const orc_params* p, int n_steps, int n_bodies, cons
                             lFk[a] -= w[c] * h * lam_F[3 * idx[c] + a];
                         }
                     }
-                    /* F_k = -gamma (v_k - u_k) */
+                    /* F_k = -gamma (v_k - u_k) + sqrt(2 kT gamma / h) xi_k: the noise term
+                     * F_k + gamma (v_k - u_k) scales with sqrt(gamma) */
                     double luk[3], lv[3];
                     for (int a = 0; a < 3; ++a) {
                         dJ_dgamma[b] += lFk[a] * (uk[a] - v[a]);
+                        if (kT > 0.0 && gamma > 0.0)
+                            dJ_dgamma[b] += lFk[a] * (Fk[a] + gamma * (v[a] - uk[a])) / (2.0 * gamma);
                         luk[a] = gamma * lFk[a];
                         lv[a] = -gamma * lFk[a];
                     }

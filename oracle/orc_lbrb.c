@@ -795,6 +795,15 @@ int orc_box_ev(const orc_sim* s, int b, const double** offsets, int* n, double* 
     *radius = s->bodies[b].ev_radius;
     return 0;
 }
+/* the uniforms (in (-1/2, 1/2)) of the bead noise that fluid step `step`, MD step k_md gives
+ * bead `bead` (its index over all bodies in order), as couple_body draws them              */
+int orc_box_bead_uniforms(const orc_sim* s, int64_t step, int bead, int k_md, double out[3])
+{
+    uint32_t words[4];
+    draw(s, step, (uint32_t)bead, 1u, (uint32_t)k_md, words);
+    for (int a = 0; a < 3; ++a) out[a] = orc_uniform16(half_of(words, a));
+    return 0;
+}
 /* the static sites (lab positions, radii)                                                  */
 int orc_box_sites(const orc_sim* s, const double** pos, const double** radius, int* n)
 {

@@ -372,7 +372,7 @@ class OracleSim:
         rc = lib().orc_adjoint(self._h, ctypes.byref(self.params), int(n_steps), self.n_bodies,
                                _dp(a), _dp(J), _dp(dg), _dp(do))
         if rc != 0:
-            raise RuntimeError("orc_adjoint: needs kT = 0")
+            raise RuntimeError("orc_adjoint failed")
         return float(J[0]), dg, do.reshape(-1, 3)
 
     def bead_forces(self, b):

@@ -144,17 +144,22 @@ def _run_free(shape, mask, params, free, fixed, steps, weights, adjoint=False, p
     return J
 
 
-@pytest.mark.parametrize("masked,md", [(False, 1), (True, 1), (False, 2), (True, 3)],
-                         ids=["periodic", "pore", "periodic-2md", "pore-3md"])
-def test_free_body_window_gradient_matches_finite_difference(masked, md):
+@pytest.mark.parametrize("masked,md,kT", [(False, 1, 0.0), (True, 1, 0.0), (False, 2, 0.0),
+                                           (True, 3, 0.0), (False, 1, 4e-5), (True, 2, 4e-5)],
+                         ids=["periodic", "pore", "periodic-2md", "pore-3md", "periodic-thermal",
+                              "pore-2md-thermal"])
+def test_free_body_window_gradient_matches_finite_difference(masked, md, kT):
     """The reverse pass through the rigid-body integrator (both half kicks, the drift, the
     quaternion rotation and the moving bead positions and velocities) against central
     differences of J re-run by the forward oracle, for a free body next to a fixed one; with
     one MD step per fluid step, and with two and three (the paper's scheme: several MD steps
-    on the frozen fluid, each spreading its share of the bead force)."""
+    on the frozen fluid, each spreading its share of the bead force); deterministic, and
+    thermal (the pathwise derivative: every run draws the same counter-based noise, and the
+    bead noise amplitude sqrt(2 kT gamma / h) depends on gamma)."""
     from scipy.spatial.transform import Rotation
     shape, mask, params, free, fixed = _free_case(masked)
     params.md_substeps = md
+    params.kT = kT
     steps = 12
     rng = np.random.default_rng(19)
     weights = np.zeros((steps, 2, 3))
