@@ -351,7 +351,10 @@ int lb_set_tuning(lb_ctx* ctx, const lb_tuning* settings);
  * per fluid step (Sec. 2.3), F_b(n) is the force of the fluid step's last MD step (the body
  * force lb_observables reports) and every MD step is differentiated.  WCA excluded volume
  * (Sec. 2.1 inner layers, Sec. 2.3 pore beads) is differentiated through its pair forces,
- * and its force on a body counts in F_b(n).  Requires kT = 0.
+ * and its force on a body counts in F_b(n).  With kT > 0 the derivative is pathwise: the
+ * recomputed steps draw the forward run's counter-based noise, and the bead noise amplitude
+ * sqrt(2 kT gamma / dt) is differentiated in gamma (the fluid's noise is additive and leaves
+ * the collision's Jacobian unchanged).
  * The call advances the context by n_steps steps (its state afterwards is that of
  * lb_rb_step(n_steps)), keeping the post-collision state every checkpoint_every steps in the
  * caller's device workspace dev_ws (256-byte aligned, at least
@@ -364,7 +367,7 @@ int lb_set_tuning(lb_ctx* ctx, const lb_tuning* settings);
  *   dJ_dgamma   [n_bodies];
  *   dJ_doffsets [n_beads][3], body frame.
  * Synchronises the stream.  Errors: LB_ERR_ARG (window, workspace, missing arrays),
- * LB_ERR_STATE (kT > 0), or the excluded-volume table errors of lb_rb_step.  The adjoint runs in the context precision; its
+ * or the excluded-volume table errors of lb_rb_step.  The adjoint runs in the context precision; its
  * atomic accumulation of sampled-velocity adjoints into the population adjoint is not
  * order-deterministic.                                                                    */
 size_t lb_adjoint_workspace_bytes(const lb_ctx* ctx, int32_t n_steps, int32_t checkpoint_every);

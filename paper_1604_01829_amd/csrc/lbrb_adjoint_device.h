@@ -124,8 +124,12 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
         const double* d = X.dv;
         // (the objective is taken from the body forces by the body pass)
         double lv[3], db[3], y[3];
+        // thermal: F_k also holds sqrt(2 kT gamma / h) xi_k = F_k + gamma (v_k - u_k), whose
+        // derivative in gamma is itself over 2 gamma (the noise draws are the forward run's)
+        const bool noise = a.thermal && X.gamma > 0.0;
         for (int ax = 0; ax < 3; ++ax) {
             dg += lFk[ax] * (s6[ax] - X.v[ax]);
+            if (noise) dg += lFk[ax] * (Fk[ax] + X.gamma * (X.v[ax] - s6[ax])) / (2.0 * X.gamma);
             lv[ax] = -X.gamma * lFk[ax];
         }
         db[0] = dr[0] + (Fk[1] * bj[5] - Fk[2] * bj[4]);
@@ -150,9 +154,11 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
         o[10] = d[2] * lv[0] - d[0] * lv[2];
         o[11] = d[0] * lv[1] - d[1] * lv[0];
     } else {
+        const bool noise = a.thermal && X.gamma > 0.0;   // as above, with v_k = 0
         for (int ax = 0; ax < 3; ++ax) {
             jp += an[ax] * Fk[ax];
             dg += lFk[ax] * s6[ax];
+            if (noise) dg += lFk[ax] * (Fk[ax] - X.gamma * s6[ax]) / (2.0 * X.gamma);
             A.dr[3 * (int64_t)bead + ax] += dr[ax];
         }
     }

@@ -1914,7 +1914,6 @@ int lb_rb_adjoint(lb_ctx* c, int32_t n_steps, int32_t checkpoint_every, void* de
         return fail(c, LB_ERR_ARG, "the window needs n_steps >= 1 and checkpoint_every >= 1");
     if (!dev_ws || ((uintptr_t)dev_ws % kAlign) != 0 || ws_bytes < ap.total)
         return fail(c, LB_ERR_ARG, "reverse-pass workspace missing, misaligned or too small");
-    if (c->p.kT != 0.0) return fail(c, LB_ERR_STATE, "the reverse pass needs kT = 0");
     if (c->wca_dirty) {
         const int rc = build_wca(c);
         if (rc != LB_OK) return rc;

@@ -53,7 +53,8 @@ def _case(masked):
 def _gpu(shape, mask, pp, bodies, precision):
     from paper_1604_01829_amd import lbrb
     nb = sum(len(b[0]) for b in bodies)
-    params = lbrb.make_params(precision=precision, kT=0.0, max_bodies=len(bodies),
+    pp = dict(pp)
+    params = lbrb.make_params(precision=precision, kT=pp.pop("kT", 0.0), max_bodies=len(bodies),
                               max_beads=nb, **pp)
     sim = lbrb.Simulation(params, lbrb.make_replicas([(shape, 7)]))
     if mask is not None:
@@ -205,7 +206,8 @@ def _free_case(masked):
 def _gpu_free(shape, mask, pp, bodies, precision, md=1):
     from paper_1604_01829_amd import lbrb
     nb = sum(len(b[0]) for b in bodies)
-    params = lbrb.make_params(precision=precision, kT=0.0, max_bodies=len(bodies),
+    pp = dict(pp)
+    params = lbrb.make_params(precision=precision, kT=pp.pop("kT", 0.0), max_bodies=len(bodies),
                               max_beads=nb, md_substeps=md, **pp)
     sim = lbrb.Simulation(params, lbrb.make_replicas([(shape, 7)]))
     if mask is not None:
@@ -318,6 +320,47 @@ def test_excluded_volume_adjoint_matches_oracle(md, precision):
                            omega=b["omega"], gamma=b["gamma"])
         sim.set_excluded_volume(0, bid, *b["ev"])
     sim.add_wall_sites(0, walls, 0.5)
+    Jg, dgg, dog = sim.adjoint(T, a, checkpoint_every=K)
+    sim.close()
+    print(f"  J rel {abs(Jg - Jo) / abs(Jo):.2e}  dgamma rel "
+          f"{np.abs(dgg - dgo).max() / np.abs(dgo).max():.2e}  doffsets rel "
+          f"{np.abs(dog - doo).max() / np.abs(doo).max():.2e}", flush=True)
+    tJ, tg = (1e-12, 1e-10) if precision == "f64" else (2e-6, 5e-6)
+    assert abs(Jg - Jo) <= tJ * abs(Jo), (Jg, Jo)
+    assert np.abs(dgg - dgo).max() <= tg * np.abs(dgo).max(), (dgg, dgo)
+    assert np.abs(dog - doo).max() <= tg * np.abs(doo).max(), np.abs(dog - doo).max()
+
+
+@pytest.mark.parametrize("free,md", [(False, 1), (True, 1), (True, 2)],
+                         ids=["fixed", "free", "free-2md"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_thermal_adjoint_matches_oracle(free, md, precision):
+    """Thermal fluid and bead noise (kT = 4e-5, the oracle seeded as the replica): the pathwise
+    reverse pass (every recomputed step draws the forward run's counter-based noise; the bead
+    noise amplitude is differentiated in gamma) against the oracle's; fixed bodies take the
+    fused schedule, a free body the body passes."""
+    T, K = 11, 4
+    if free:
+        shape, mask, pp, bodies = _free_case(False)
+    else:
+        shape, mask, pp, bodies = _case(False)
+    pp = dict(pp, kT=4e-5)
+    a = _weights(T, len(bodies), seed=31)
+    print(f"thermal adjoint vs oracle: free={free} md={md} {precision}", flush=True)
+    if free:
+        orc = po.OracleSim(shape, po.make_params(md_substeps=md, seed=7, **pp))
+        offs, c, q, g = bodies[0]
+        orc.add_body(offs, FREE["mass"], FREE["inertia"], c, quat=q, vel=FREE["vel"],
+                     omega=FREE["omega"], gamma=g)
+        offs, c, q, g = bodies[1]
+        orc.add_body(offs, 1.0, (1, 1, 1), c, quat=q, gamma=g, fixed=True)
+        sim = _gpu_free(shape, mask, pp, bodies, precision, md)
+    else:
+        orc = po.OracleSim(shape, po.make_params(seed=7, **pp))
+        for offs, c, q, g in bodies:
+            orc.add_body(offs, 1.0, (1, 1, 1), c, quat=q, gamma=g, fixed=True)
+        sim = _gpu(shape, mask, pp, bodies, precision)
+    Jo, dgo, doo = orc.adjoint(T, a)
     Jg, dgg, dog = sim.adjoint(T, a, checkpoint_every=K)
     sim.close()
     print(f"  J rel {abs(Jg - Jo) / abs(Jo):.2e}  dgamma rel "
@@ -642,15 +685,6 @@ def test_adjoint_error_codes():
         lbrb.lb_rb_adjoint(sim.ctx, 4, 2, ws.data_ptr(), nbytes - 1, a, 2,
                            sum(len(b[0]) for b in bodies))
     assert e.value.code == lbrb.LB_ERR_ARG
-    sim.close()
-    # a thermal fluid is refused (its derivative is a stochastic object)
-    nb = sum(len(b[0]) for b in bodies)
-    params = lbrb.make_params(precision="f64", kT=1e-5, max_bodies=1, max_beads=nb, **pp)
-    sim = lbrb.Simulation(params, lbrb.make_replicas([(shape, 7)]))
-    sim.add_body(0, bodies[0][0], 1.0, (1, 1, 1), bodies[0][1], gamma=0.1, fixed=True)
-    with pytest.raises(lbrb.LBError) as e:
-        sim.adjoint(4, a[:, :1])
-    assert e.value.code == lbrb.LB_ERR_STATE
     sim.close()
 
 
