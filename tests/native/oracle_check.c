@@ -180,11 +180,38 @@ static void adjoint_case(void)
         for (int d = 0; d < 3; ++d) Jf += w[3 * n + d] * st[13 + d];
     }
     CHECK(fabs(J - Jf) <= 1e-12 * (fabs(Jf) + 1e-30), "J equals the forward sum");
-    /* requirements: a thermal box is refused */
-    orc_params pt = params(1e-4, 1, 0.0, 3);
+    /* the general reverse pass: a thermal box, a free body next to a fixed one, two MD steps
+     * per fluid step and WCA sites on both bodies and a few static sites; J again equals the
+     * forward sum (same seed, same noise) and everything stays finite */
+    orc_params pt = params(1e-4, 2, 1e-3, 3);
     orc_sim* t = orc_create(nx, ny, nz, &pt);
-    add_sphere(t, 1.5, 16, c, 1, 2.0);
-    CHECK(orc_adjoint(t, &pt, T, 1, w, &J, &dg, doff) != 0, "thermal refused");
+    orc_sim* tf = orc_create(nx, ny, nz, &pt);
+    const double c2[3] = {2.0, 4.6, 4.1};
+    const double ev[6] = {1.0, 0.0, 0.0, -1.0, 0.0, 0.0};
+    const double sites[6] = {5.0, 1.2, 3.8, 5.3, 7.7, 3.9};
+    orc_sim* both[2] = {t, tf};
+    for (int k = 0; k < 2; ++k) {
+        add_sphere(both[k], 1.5, 16, c, 0, 0.2);
+        add_sphere(both[k], 1.0, 8, c2, 1, 0.2);
+        CHECK(orc_set_excluded_volume(both[k], 0, ev, 2, 0.5) == 0, "excluded volume 0");
+        CHECK(orc_set_excluded_volume(both[k], 1, ev, 2, 0.5) == 0, "excluded volume 1");
+        CHECK(orc_add_wall_sites(both[k], sites, 2, 0.5) == 0, "wall sites");
+    }
+    double w2[6 * T], dg2[2], doff2[3 * 24];
+    for (int k = 0; k < 6 * T; ++k) w2[k] = 0.1 * (k % 7) - 0.3;
+    CHECK(orc_adjoint(t, &pt, T, 2, w2, &J, dg2, doff2) == 0, "general reverse pass");
+    CHECK(isfinite(J) && finite_all(dg2, 2) && finite_all(doff2, 72), "general adjoint finite");
+    Jf = 0.0;
+    for (int n = 0; n < T; ++n) {
+        CHECK(orc_step(tf, 1) == 0, "forward");
+        for (int bb = 0; bb < 2; ++bb) {
+            double st[19];
+            CHECK(orc_body_state(tf, bb, st) == 0, "body state");
+            for (int d = 0; d < 3; ++d) Jf += w2[6 * n + 3 * bb + d] * st[13 + d];
+        }
+    }
+    CHECK(fabs(J - Jf) <= 1e-12 * (fabs(Jf) + 1e-30), "general J equals the forward sum");
+    orc_destroy(tf);
     double lin[19], lout[19], lF[3], f[19], F[3] = {1e-4, -2e-4, 3e-5};
     const double u[3] = {0.01, -0.02, 0.005};
     orc_equilibrium(1.02, u, f);
