@@ -942,7 +942,9 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
             X.bead_force = bf + nbf * (size_t)k;
             X.snap = table(k);
             X.pose_par = par;
-            launch_records_from_poses(table(k), par, c->d_beads, c->d_recs, c->n_beads, s);
+            // the recompute left the records of the last MD step in place
+            if (k != m - 1)
+                launch_records_from_poses(table(k), par, c->d_beads, c->d_recs, c->n_beads, s);
             launch_adjoint_body_pre(table(k), table(k + 1), par, X.weights, badj, bin,
                                     (double*)(ws + ap.off_Jb), c->n_bodies, s);
             launch_adjoint_beads<Real>(X, s);
