@@ -152,6 +152,71 @@ def test_batch_of_a_periodic_and_a_pore_replica(precision):
         assert np.abs(got - want).max() <= to * np.abs(want).max(), np.abs(got - want).max()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_with_free_bodies_wca_noise_and_md_steps(precision):
+    """One context, two replicas, every feature of the body passes at once: thermal noise, two
+    MD steps per fluid step, WCA (replica 0: two free bodies pressing on each other and on
+    pore beads; replica 1: a pore with a free and a fixed body); the objective and gradients
+    against each replica's own oracle reverse pass, in global body and bead order."""
+    from paper_1604_01829_amd import lbrb
+    from tests.test_oracle_adjoint import _wca_case
+    s0, p0, b0, walls = _wca_case()
+    s1, mask, _, b1 = _free_case(True)
+    kT, md, T, K = 4e-5, 2, 9, 4
+    common = dict(u0=tuple(p0.u0), tau_shear=p0.tau_shear, tau_bulk=p0.tau_bulk,
+                  tau_odd=p0.tau_odd, tau_even=p0.tau_even, g_ext=tuple(p0.g_ext))
+    a = _weights(T, 4, seed=41)
+    print(f"batch with free bodies, WCA, noise, {md} MD steps: {precision}", flush=True)
+    # oracles, seeded as their replicas
+    o0 = po.OracleSim(s0, po.make_params(kT=kT, md_substeps=md, wca_epsilon=p0.wca_epsilon,
+                                         seed=7, **common))
+    for j, b in enumerate(b0):
+        o0.add_body(b["offs"], b["mass"], b["inertia"], b["centre"], vel=b["vel"],
+                    omega=b["omega"], gamma=b["gamma"])
+        o0.set_excluded_volume(j, *b["ev"])
+    o0.add_wall_sites(walls, 0.5)
+    o1 = po.OracleSim(s1, po.make_params(kT=kT, md_substeps=md, wca_epsilon=p0.wca_epsilon,
+                                         seed=8, **common))
+    o1.set_mask(mask)
+    offs, c, q, g = b1[0]
+    o1.add_body(offs, FREE["mass"], FREE["inertia"], c, quat=q, vel=FREE["vel"],
+                omega=FREE["omega"], gamma=g)
+    offs, c, q, g = b1[1]
+    o1.add_body(offs, 1.0, (1, 1, 1), c, quat=q, gamma=g, fixed=True)
+    J0, dg0, do0 = o0.adjoint(T, a[:, :2])
+    J1, dg1, do1 = o1.adjoint(T, a[:, 2:])
+    # the library, both replicas in one context
+    nb = sum(len(b["offs"]) for b in b0) + sum(len(b[0]) for b in b1)
+    params = lbrb.make_params(precision=precision, kT=kT, max_bodies=4, max_beads=nb,
+                              md_substeps=md, wca_epsilon=p0.wca_epsilon, max_ev_sites=16,
+                              max_wall_sites=len(walls), **common)
+    sim = lbrb.Simulation(params, lbrb.make_replicas([(s0, 7), (s1, 8)]))
+    sim.set_mask(1, mask)
+    for b in b0:
+        bid = sim.add_body(0, b["offs"], b["mass"], b["inertia"], b["centre"], vel=b["vel"],
+                           omega=b["omega"], gamma=b["gamma"])
+        sim.set_excluded_volume(0, bid, *b["ev"])
+    sim.add_wall_sites(0, walls, 0.5)
+    offs, c, q, g = b1[0]
+    sim.add_body(1, offs, FREE["mass"], FREE["inertia"], c, quat=q, vel=FREE["vel"],
+                 omega=FREE["omega"], gamma=g)
+    offs, c, q, g = b1[1]
+    sim.add_body(1, offs, 1.0, (1, 1, 1), c, quat=q, gamma=g, fixed=True)
+    Jg, dgg, dog = sim.adjoint(T, a, checkpoint_every=K)
+    sim.close()
+    Jo = J0 + J1
+    tJ, tg = (1e-12, 1e-10) if precision == "f64" else (2e-6, 5e-6)
+    print(f"  J rel {abs(Jg - Jo) / abs(Jo):.2e}", flush=True)
+    assert abs(Jg - Jo) <= tJ * abs(Jo), (Jg, Jo)
+    for got, want in ((dgg[:2], dg0), (dgg[2:], dg1)):
+        assert np.abs(got - want).max() <= tg * np.abs(want).max(), (got, want)
+    n0 = sum(len(b["offs"]) for b in b0)
+    for got, want in ((dog[:n0], do0), (dog[n0:], do1)):
+        err = np.abs(got - want).max() / np.abs(want).max()
+        print(f"  doffsets rel {err:.2e}", flush=True)
+        assert err <= tg, err
+
+
 def test_checkpoint_interval_does_not_change_the_gradient():
     shape, mask, pp, bodies = _case(True)
     T = 12
