@@ -17,10 +17,10 @@
 //              into lambda^n (atomic adds where beads share a node) and no pass over the
 //              sampled nodes follows.
 // The forward state f^n is re-pulled from the stored post-collision populations of step n-1.
-// With free bodies two small launches frame the bead pass (the rigid-body integrator of
-// Sec. 2.3 and the virtual-site kinematics of Sec. 1.2, transposed):
-//   adj_body_pre : per body, the adjoint of the step's force and lab torque from the adjoint
-//                  of the state after the step (the second half kick) and the weights;
+// With free bodies the bead pass forms each body's force and torque adjoint from the adjoint
+// of its state after the step (the second half kick) and the weights, and one small launch
+// follows it (the rigid-body integrator of Sec. 2.3 and the virtual-site kinematics of
+// Sec. 1.2, transposed):
 //   adj_body_post: per body, the bead pass's sums (fixed order), then the second half kick,
 //                  the torque's body-frame rotation, the bead kinematics, the rotation of the
 //                  quaternion, the drift and the first half kick, transposed: the adjoint of
@@ -129,38 +129,17 @@ __device__ __forceinline__ void qmul(const double a[4], const double b[4], doubl
     o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
 }
 
-__global__ __launch_bounds__(64) void adj_body_pre_kernel(const Body* in, const Body* out, int par,
-                                                          const double* weights, const double* adj,
-                                                          double* body_adj, double* J, int n)
-{
-    const int b = blockIdx.x * 64 + threadIdx.x;
-    if (b >= n) return;
-    const Body& B = in[b];
-    const double* a = weights + 3 * (int64_t)b;
-    double* o = body_adj + 6 * (int64_t)b;
-    const double* Fo = out[b].force;
-    J[b] += a[0] * Fo[0] + a[1] * Fo[1] + a[2] * Fo[2];
-    if (B.fixed) {
-        for (int k = 0; k < 3; ++k) { o[k] = a[k]; o[3 + k] = 0.0; }
-        return;
-    }
-    // V_out = V_m + dt F/2M and w_out = w_m + dt (tau - w_m x I w_m)/2I, tau = Q^T T
-    const double* ab = adj + kBodyAdjWords * (int64_t)b;
-    const double* rot = B.pose[par].rot;
-    const double hh = 0.5 * B.dt;
-    double tb[3];
-    for (int k = 0; k < 3; ++k) {
-        o[k] = ab[13 + k] + a[k] + hh * ab[7 + k] / B.mass;
-        tb[k] = ab[16 + k] + hh * ab[10 + k] / B.inertia[k];
-    }
-    for (int r = 0; r < 3; ++r) o[3 + r] = rot[3 * r] * tb[0] + rot[3 * r + 1] * tb[1] + rot[3 * r + 2] * tb[2];
-}
-
 __global__ __launch_bounds__(256) void adj_body_post_kernel(const Body* in, const Body* out, int par,
+                                                            const double* weights,
                                                             const double* bead_sums, double* adj,
-                                                            double* wadj)
+                                                            double* wadj, double* J)
 {
     const Body& B = in[blockIdx.x];
+    if (threadIdx.x == 0) {   // the objective: the weight on the force after the MD step
+        const double* a = weights + 3 * (int64_t)blockIdx.x;
+        const double* Fo = out[blockIdx.x].force;
+        J[blockIdx.x] += a[0] * Fo[0] + a[1] * Fo[1] + a[2] * Fo[2];
+    }
     if (B.fixed) return;   // uniform over the workgroup
     const int first = B.first_bead, nb = B.n_beads, tid = threadIdx.x;
     double acc[kBeadSumWords];
@@ -254,21 +233,13 @@ __global__ __launch_bounds__(256) void adj_body_post_kernel(const Body* in, cons
     for (int k = 0; k < 4; ++k) ab[3 + k] = qib[k];
 }
 
-void launch_adjoint_body_pre(const Body* in, const Body* out, int par, const double* weights,
-                             const double* adj, double* body_adj, double* J, int n_bodies,
-                             hipStream_t s)
-{
-    if (n_bodies <= 0) return;
-    hipLaunchKernelGGL(adj_body_pre_kernel, dim3((n_bodies + 63) / 64), dim3(64), 0, s, in, out,
-                       par, weights, adj, body_adj, J, n_bodies);
-}
-
-void launch_adjoint_body_post(const Body* in, const Body* out, int par, const double* bead_sums,
-                              double* adj, double* wadj, int n_bodies, hipStream_t s)
+void launch_adjoint_body_post(const Body* in, const Body* out, int par, const double* weights,
+                              const double* bead_sums, double* adj, double* wadj, double* J,
+                              int n_bodies, hipStream_t s)
 {
     if (n_bodies <= 0) return;
     hipLaunchKernelGGL(adj_body_post_kernel, dim3(n_bodies), dim3(256), 0, s, in, out, par,
-                       bead_sums, adj, wadj);
+                       weights, bead_sums, adj, wadj, J);
 }
 
 // ------------------------------------------------------------------ excluded volume
@@ -304,7 +275,8 @@ __device__ __forceinline__ int coarse_cell(double x, double L, double w, int n)
 
 // one workgroup per body with excluded-volume sites, one thread per site
 __global__ __launch_bounds__(256) void adj_wca_kernel(const BodyArgs ba, int par,
-                                                      const double* body_adj, double* wadj)
+                                                      const double* weights, const double* adj,
+                                                      double* wadj)
 {
     const int b = blockIdx.x;
     const Body& B = ba.bodies[b];
@@ -313,7 +285,8 @@ __global__ __launch_bounds__(256) void adj_wca_kernel(const BodyArgs ba, int par
     const WcaRep W = ba.wrep[B.replica];
     const double L[3] = {(double)B.box.nx, (double)B.box.ny, (double)B.box.nz};
     const double eps = ba.wca_eps;
-    const double* bj = body_adj + 6 * (int64_t)b;   // Fbar_b, Tbar_b (lab)
+    double bj[6];   // Fbar_b, Tbar_b (lab)
+    force_torque_adjoint(B, P.rot, adj + kBodyAdjWords * (int64_t)b, weights + 3 * (int64_t)b, bj);
     const bool free_b = B.fixed == 0;
     double acc[6] = {0, 0, 0, 0, 0, 0};             // this body's centre and angle adjoints
     for (int k = threadIdx.x; k < B.n_ev; k += blockDim.x) {
@@ -400,11 +373,12 @@ __global__ __launch_bounds__(256) void adj_wca_kernel(const BodyArgs ba, int par
         for (int k = 0; k < 6; ++k) atomicAdd(wadj + 6 * (int64_t)b + k, acc[k]);
 }
 
-void launch_adjoint_wca(const BodyArgs& ba, int par, const double* body_adj, double* wadj,
-                        hipStream_t s)
+void launch_adjoint_wca(const BodyArgs& ba, int par, const double* weights, const double* adj,
+                        double* wadj, hipStream_t s)
 {
     if (ba.n_bodies <= 0 || !ba.wca_ft) return;
-    hipLaunchKernelGGL(adj_wca_kernel, dim3(ba.n_bodies), dim3(256), 0, s, ba, par, body_adj, wadj);
+    hipLaunchKernelGGL(adj_wca_kernel, dim3(ba.n_bodies), dim3(256), 0, s, ba, par, weights, adj,
+                       wadj);
 }
 
 template void launch_adjoint_step<float>(const AdjArgs<float>&, bool, hipStream_t);

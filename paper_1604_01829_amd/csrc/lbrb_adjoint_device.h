@@ -9,10 +9,33 @@ namespace lbrb {
 // Lanes per workgroup of the bead pass: one wave, so that its atomics issue from every XCD.
 constexpr int kAdjBeadBlock = 64;
 
+// The adjoint of an MD step's body force F and lab torque T (6 values) from the adjoint ab of
+// the body's state after the step (19 words: position, quaternion, velocity, body-frame
+// angular velocity, force, body-frame torque) and the objective's weight a: the second half
+// kick V += dt F/2M, w += dt (tau - w x I w)/2I with tau = Q^T T (rot: Q of the step's pose,
+// row-major); a fixed body takes the weight alone.
+__device__ __forceinline__ void force_torque_adjoint(const Body& B, const double* rot,
+                                                     const double* ab, const double* a,
+                                                     double out[6])
+{
+    if (B.fixed) {
+        for (int k = 0; k < 3; ++k) { out[k] = a[k]; out[3 + k] = 0.0; }
+        return;
+    }
+    const double hh = 0.5 * B.dt;
+    double tb[3];
+    for (int k = 0; k < 3; ++k) {
+        out[k] = ab[13 + k] + a[k] + hh * ab[7 + k] / B.mass;
+        tb[k] = ab[16 + k] + hh * ab[10 + k] / B.inertia[k];
+    }
+    for (int r = 0; r < 3; ++r)
+        out[3 + r] = rot[3 * r] * tb[0] + rot[3 * r + 1] * tb[1] + rot[3 * r + 2] * tb[2];
+}
+
 // Bead pass for lane `tid` (8 lanes per bead, one per stencil corner): the transpose of
 // spreading, friction and interpolation, and of the velocity sampling; with FREE also of the
 // torque sum and of the bead kinematics (the adjoint of the body force and torque comes from
-// A.body_adj).  Lanes past the last bead return at once (the 8 lanes of a bead leave
+// the body's state adjoint A.body_adj).  Lanes past the last bead return at once (the 8 lanes of a bead leave
 // together).
 template <typename Real, bool FREE = false>
 __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
@@ -82,10 +105,12 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
         for (int k = 0; k < 6; ++k) s6[k] += __shfl_xor(s6[k], m, 8);
     const double* Fk = A.bead_force + 3 * (int64_t)bead;
     const double* an = A.weights + 3 * (int64_t)body;
-    double lFk[3], luk[3];
+    double lFk[3], luk[3], bj[6];
     if constexpr (FREE) {
         // the body force F = sum F_k and the lab torque T = sum d_k x F_k
-        const double* bj = A.body_adj + 6 * (int64_t)body;
+        const Body& Bd = A.snap[body];
+        force_torque_adjoint(Bd, Bd.pose[A.pose_par].rot, A.body_adj + kBodyAdjWords * (int64_t)body,
+                             an, bj);
         const double* dv = X.dv;
         const double h = A.spread_h;
         lFk[0] = bj[0] + (bj[4] * dv[2] - bj[5] * dv[1]) - h * s6[3];
@@ -118,7 +143,6 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
     if constexpr (FREE) {
         // F_k = -gamma (v_k - u_k); the arm d = Q b enters the torque, d and v = V + w x d the
         // kinematics; dr is kept in the body frame of the step's pose
-        const double* bj = A.body_adj + 6 * (int64_t)body;
         const Pose& P = A.snap[body].pose[A.pose_par];
         const double* w = P.omega_lab;
         const double* d = X.dv;

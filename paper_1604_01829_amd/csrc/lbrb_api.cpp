@@ -746,14 +746,14 @@ int build_wca(lb_ctx* c)
 // population buffers, the adjoints of the node force and velocity, the per-step objective
 // weights, the per-bead accumulators, and room to restore the bead forces afterwards; for
 // free bodies the body table before every step of the window (and after the last), the
-// adjoint of the body states, of each MD step's body force and torque, the bead pass's sums,
+// adjoint of the body states, the bead pass's sums,
 // the body tables between the MD steps of one fluid step, zero weights (the objective takes
 // the last MD step's force) and room to restore the bead records.
 struct AdjPlan {
     int32_t n_ck = 0, n_seg = 0;
     size_t state = 0;
     size_t off_ck, off_seg, off_lam0, off_lam1, off_lamF, off_w, off_dr, off_dg, off_J,
-        off_bf, off_save, off_snap, off_badj, off_bin, off_bsum, off_recs, off_scr, off_zero,
+        off_bf, off_save, off_snap, off_badj, off_bsum, off_recs, off_scr, off_zero,
         off_wadj, off_Jb, total;
 };
 
@@ -806,7 +806,6 @@ bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
     if (body_passes(c)) {
         ap.off_snap = take(sizeof(Body) * nbod * ((size_t)T + 1));
         ap.off_badj = take(sizeof(double) * kBodyAdjWords * nbod);
-        ap.off_bin = take(sizeof(double) * 6 * nbod);
         ap.off_bsum = take(sizeof(double) * kBeadSumWords * nb);
         ap.off_recs = take(sizeof(BeadRec) * nb);
         ap.off_scr = take(sizeof(Body) * nbod * (size_t)std::max(1, m - 1));
@@ -814,7 +813,7 @@ bool make_adj_plan(const lb_ctx* c, int32_t T, int32_t K, AdjPlan& ap)
         ap.off_wadj = take(sizeof(double) * 6 * nbod);
         ap.off_Jb = take(sizeof(double) * nbod);
     } else {
-        ap.off_snap = ap.off_badj = ap.off_bin = ap.off_bsum = ap.off_recs = 0;
+        ap.off_snap = ap.off_badj = ap.off_bsum = ap.off_recs = 0;
         ap.off_scr = ap.off_zero = ap.off_wadj = ap.off_Jb = 0;
     }
     ap.total = o;
@@ -912,7 +911,7 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
         X.Jpart = (double*)(ws + ap.off_J);
         X.n_beads = c->n_beads;
         if (snap) {
-            X.body_adj = (const double*)(ws + ap.off_bin);
+            X.body_adj = (const double*)(ws + ap.off_badj);
             X.bead_sums = (double*)(ws + ap.off_bsum);
             X.spread_h = 1.0 / md_steps(c);
         }
@@ -931,7 +930,6 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
         if (c->n_beads <= 0) return;
         auto table = [&](int k) { return k == 0 ? t0 : k == m ? t0 + nb : scr + nb * (k - 1); };
         double* badj = (double*)(ws + ap.off_badj);
-        double* bin = (double*)(ws + ap.off_bin);
         double* wadj = (double*)(ws + ap.off_wadj);
         const double* zero = (const double*)(ws + ap.off_zero);
         const double* weights = A[cg].weights;
@@ -945,16 +943,15 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
             // the recompute left the records of the last MD step in place
             if (k != m - 1)
                 launch_records_from_poses(table(k), par, c->d_beads, c->d_recs, c->n_beads, s);
-            launch_adjoint_body_pre(table(k), table(k + 1), par, X.weights, badj, bin,
-                                    (double*)(ws + ap.off_Jb), c->n_bodies, s);
             launch_adjoint_beads<Real>(X, s);
             if (has_wca(c)) {
                 BodyArgs wb = body_args(c);
                 wb.bodies = const_cast<Body*>(table(k));
-                launch_adjoint_wca(wb, par, bin, wadj, s);
+                launch_adjoint_wca(wb, par, X.weights, badj, wadj, s);
             }
-            launch_adjoint_body_post(table(k), table(k + 1), par, (const double*)(ws + ap.off_bsum),
-                                     badj, wadj, c->n_bodies, s);
+            launch_adjoint_body_post(table(k), table(k + 1), par, X.weights,
+                                     (const double*)(ws + ap.off_bsum), badj, wadj,
+                                     (double*)(ws + ap.off_Jb), c->n_bodies, s);
         }
         return;
     }

@@ -251,8 +251,9 @@ struct AdjArgs {
     double* dgam;               // accumulated dJ/dgamma, per bead
     double* Jpart;              // accumulated objective, per bead
     int32_t n_beads;
-    // With free bodies (body_adj != null) the bead pass takes the adjoint of each body's force
-    // and lab torque from body_adj (6 per body), accumulates dr in the body frame of the
+    // With the body passes (body_adj != null: the adjoint of each body's state after the MD
+    // step, kBodyAdjWords per body) the bead pass forms the adjoint of the body's force and
+    // lab torque from it (force_torque_adjoint), accumulates dr in the body frame of the
     // step's pose (snap[body].pose[pose_par]) and leaves 12 sums per bead in bead_sums for
     // the body pass: the adjoints of the bead position and velocity, the rotation sum
     // d x dbar + (w x d) x vbar and d x vbar (d = r - R, dbar and vbar the adjoints of the
@@ -266,30 +267,26 @@ struct AdjArgs {
     double spread_h;
 };
 
-// The body pass of one MD step of a reverse step.  in: the bodies before the MD step (its
-// pose at pose[par]); out: after it; adj: the adjoint of each body's state after the MD step
-// (19 doubles: position, quaternion, velocity, body-frame angular velocity, force, body-frame
-// torque).  pre: writes the adjoint of the MD step's body force and lab torque (6 per body)
-// for the bead pass; post: adds the bead sums and takes adj back through the second half
-// kick, the drift, the rotation and the first half kick, to the adjoint of the state before
-// the MD step.  Fixed bodies: weights only.
+// The body pass of one MD step of a reverse step, after its bead and excluded-volume passes.
+// in: the bodies before the MD step (its pose at pose[par]); out: after it; adj: the adjoint
+// of each body's state after the MD step (kBodyAdjWords doubles: position, quaternion,
+// velocity, body-frame angular velocity, force, body-frame torque).  Adds weights . (force
+// after the MD step, excluded volume included) into J[b]; for a free body adds the bead sums
+// and the excluded-volume pass's adjoint of the pose (wadj, 6 per body: centre, lab angle
+// vector; cleared), and takes adj back through the second half kick, the drift, the rotation
+// and the first half kick, to the adjoint of the state before the MD step.
 constexpr int kBodyAdjWords = 19;
 constexpr int kBeadSumWords = 12;
-// pre also adds weights . (force after the MD step, excluded volume included) into J[b].
-// post also adds the excluded-volume pass's adjoint of the pose (wadj, 6 per body: centre,
-// lab angle vector) and clears it.
-void launch_adjoint_body_pre(const Body* in, const Body* out, int par, const double* weights,
-                             const double* adj, double* body_adj, double* J, int n_bodies,
-                             hipStream_t s);
-void launch_adjoint_body_post(const Body* in, const Body* out, int par, const double* bead_sums,
-                              double* adj, double* wadj, int n_bodies, hipStream_t s);
+void launch_adjoint_body_post(const Body* in, const Body* out, int par, const double* weights,
+                              const double* bead_sums, double* adj, double* wadj, double* J,
+                              int n_bodies, hipStream_t s);
 // The excluded-volume pass of one MD step of a reverse step: for every WCA pair of a body's
 // site (ba.bodies at pose[par]) with a static site or another body's site, the pair force's
-// Jacobian takes the adjoint of the force on the first site (Fbar_b + Tbar_b x d, from
-// body_adj) to both sites' positions, and the torque's arm adds f x Tbar_b: into wadj of the
-// free bodies involved (atomic adds).
-void launch_adjoint_wca(const BodyArgs& ba, int par, const double* body_adj, double* wadj,
-                        hipStream_t s);
+// Jacobian takes the adjoint of the force on the first site (Fbar_b + Tbar_b x d, formed from
+// the state adjoint adj and the weights) to both sites' positions, and the torque's arm adds
+// f x Tbar_b: into wadj of the free bodies involved (atomic adds).
+void launch_adjoint_wca(const BodyArgs& ba, int par, const double* weights, const double* adj,
+                        double* wadj, hipStream_t s);
 // the pose part of every bead record from its body's pose[par] (the records a step's coupling
 // reads), for recomputing the steps of a window
 void launch_records_from_poses(const Body* bodies, int par, const Bead* beads, BeadRec* recs,
