@@ -43,11 +43,32 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
     const StepArgs<Real>& a = A.a;
     const int bead = tid >> 3, corner = tid & 7;
     if (bead >= A.n_beads) return;   // the 8 lanes of a bead leave together
-    // the bead record the forward coupling of this step read: lab position, arm, velocity,
-    // friction, replica geometry
+    // the bead record: friction and replica geometry, and for fixed bodies also the lab
+    // position (the only pose); with FREE the position, arm and velocity come from the step's
+    // stored pose, as the body finishing wrote them into the records of the step (the records
+    // may already hold the previous step's, for a coupling recompute sharing this launch)
     const BeadRec X = load_record(A.recs + bead);
     const int32_t body = A.beads[bead].body;
-    const double r[3] = {X.r[0], X.r[1], X.r[2]};
+    double r[3], arm[3], vel[3];
+    if constexpr (FREE) {
+        const Body& Bd = A.snap[body];
+        const Pose& P = Bd.pose[A.pose_par];
+        const double* off = A.beads[bead].off;
+        for (int ax = 0; ax < 3; ++ax) {
+            arm[ax] = P.rot[3 * ax] * off[0] + P.rot[3 * ax + 1] * off[1] + P.rot[3 * ax + 2] * off[2];
+            r[ax] = P.pos[ax] + arm[ax];
+        }
+        if (Bd.fixed) {
+            vel[0] = vel[1] = vel[2] = 0.0;
+        } else {
+            const double* wl = P.omega_lab;
+            vel[0] = P.vel[0] + (wl[1] * arm[2] - wl[2] * arm[1]);
+            vel[1] = P.vel[1] + (wl[2] * arm[0] - wl[0] * arm[2]);
+            vel[2] = P.vel[2] + (wl[0] * arm[1] - wl[1] * arm[0]);
+        }
+    } else {
+        for (int ax = 0; ax < 3; ++ax) { r[ax] = X.r[ax]; arm[ax] = X.dv[ax]; vel[ax] = X.v[ax]; }
+    }
     double fr[3];
     int i0[3];
     i0[0] = wrap_floor(r[0] - 0.5, X.nx, fr[0]);
@@ -111,7 +132,7 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
         const Body& Bd = A.snap[body];
         force_torque_adjoint(Bd, Bd.pose[A.pose_par].rot, A.body_adj + kBodyAdjWords * (int64_t)body,
                              an, bj);
-        const double* dv = X.dv;
+        const double* dv = arm;
         const double h = A.spread_h;
         lFk[0] = bj[0] + (bj[4] * dv[2] - bj[5] * dv[1]) - h * s6[3];
         lFk[1] = bj[1] + (bj[5] * dv[0] - bj[3] * dv[2]) - h * s6[4];
@@ -145,15 +166,15 @@ __device__ __forceinline__ void adj_bead_lanes(const AdjArgs<Real>& A, int tid)
         // kinematics; dr is kept in the body frame of the step's pose
         const Pose& P = A.snap[body].pose[A.pose_par];
         const double* w = P.omega_lab;
-        const double* d = X.dv;
+        const double* d = arm;
         // (the objective is taken from the body forces by the body pass)
         double lv[3], db[3], y[3];
         // thermal: F_k also holds sqrt(2 kT gamma / h) xi_k = F_k + gamma (v_k - u_k), whose
         // derivative in gamma is itself over 2 gamma (the noise draws are the forward run's)
         const bool noise = a.thermal && X.gamma > 0.0;
         for (int ax = 0; ax < 3; ++ax) {
-            dg += lFk[ax] * (s6[ax] - X.v[ax]);
-            if (noise) dg += lFk[ax] * (Fk[ax] + X.gamma * (X.v[ax] - s6[ax])) / (2.0 * X.gamma);
+            dg += lFk[ax] * (s6[ax] - vel[ax]);
+            if (noise) dg += lFk[ax] * (Fk[ax] + X.gamma * (vel[ax] - s6[ax])) / (2.0 * X.gamma);
             lv[ax] = -X.gamma * lFk[ax];
         }
         db[0] = dr[0] + (Fk[1] * bj[5] - Fk[2] * bj[4]);

@@ -917,6 +917,36 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
         }
     }
     const int cg = any_masked(c) ? 1 : 0;
+    if (snap && md_steps(c) == 1 && !has_wca(c)) {
+        // one MD step and no excluded volume: the fixed-body schedule with the body pass after
+        // the bead launch.  The bead pass takes the positions from the stored pose of step n,
+        // so the records may hold step n - 1's for the coupling recompute sharing its launch.
+        const size_t nb = (size_t)c->n_bodies;
+        const Body* t0 = snap + nb * n;
+        const int par = (int)(step & 1);
+        if (c->n_beads > 0 && !coupled) {
+            launch_records_from_poses(t0, par, c->d_beads, c->d_recs, c->n_beads, s);
+            launch_couple<Real>(A[cg].a, coupling(n), s);
+        }
+        for (int g = 0; g < 2; ++g) launch_adjoint_step<Real>(A[g], g == 1, s);
+        if (c->n_beads <= 0) return;
+        AdjArgs<Real> X = A[cg];
+        X.snap = t0;
+        X.pose_par = par;
+        if (prev_src) {
+            launch_records_from_poses(t0 - nb, (int)((step - 1) & 1), c->d_beads, c->d_recs,
+                                      c->n_beads, s);
+            StepArgs<Real> pa = step_args_on<Real>(c, cg, prev_src, nullptr);
+            pa.step_arg = step - 1;
+            launch_couple_adj_bead<Real>(pa, coupling(n - 1), X, s);
+        } else {
+            launch_adjoint_beads<Real>(X, s);
+        }
+        launch_adjoint_body_post(t0, t0 + nb, par, X.weights, (const double*)(ws + ap.off_bsum),
+                                 (double*)(ws + ap.off_badj), (double*)(ws + ap.off_wadj),
+                                 (double*)(ws + ap.off_Jb), c->n_bodies, s);
+        return;
+    }
     if (snap) {
         // the MD steps of fluid step n: recompute their couplings (the spread force the node
         // pass takes, each MD step's bead forces and the body tables between them), then the
@@ -977,6 +1007,10 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
     const int64_t step0 = c->step;
     // with body passes: the body table before every step of the window and after the last
     const bool fb = body_passes(c);
+    // a fluid step's coupling recompute shares the next reverse step's bead launch (not with
+    // several MD steps or excluded volume, whose couplings are recomputed with the body
+    // finishing between them)
+    const bool fused = !fb || (md_steps(c) == 1 && !has_wca(c));
     Body* snap = fb ? (Body*)(ws + ap.off_snap) : nullptr;
     const size_t table = sizeof(Body) * (size_t)c->n_bodies;
     if (fb) HIP_TRY(c, hipMemcpyAsync(snap, c->d_bodies, table, hipMemcpyDeviceToDevice, s));
@@ -1015,10 +1049,9 @@ int run_adjoint(lb_ctx* c, int32_t T, int32_t K, char* ws, const AdjPlan& ap)
         for (int32_t n = n1 - 1; n >= n0; --n) {
             // the coupling of step n - 1 joins this step's bead launch when its state is at
             // hand and nothing in between rewrites the force accumulators: inside a segment,
-            // and across segments of one step each (no replays); not with body passes, whose
-            // records change from MD step to MD step
-            const void* prev = fb ? nullptr
-                                  : n > n0 ? state(n - 1 - n0) : (K == 1 && n > 0 ? ck(n - 1) : nullptr);
+            // and across segments of one step each (no replays)
+            const void* prev = !fused ? nullptr
+                                      : n > n0 ? state(n - 1 - n0) : (K == 1 && n > 0 ? ck(n - 1) : nullptr);
             enqueue_adjoint<Real>(c, s, state(n - n0), step0 + n, lam[nxt], lam[nxt ^ 1], ws, ap, n,
                                   coupled, prev, snap);
             if (!c->hole_tiles.empty())   // the step's adjoint is complete: transposed mirror

@@ -905,8 +905,9 @@ void launch_couple(const StepArgs<Real>& a, const CoupleArgs& c, hipStream_t s,
 // has consumed those of step n) and its bead forces into the other of two buffers; the bead
 // pass reads step n's bead forces, the force adjoints and adds into the population adjoint.
 // The first n_cb workgroups couple (with the coupling's XCD pattern); each later workgroup
-// runs the bead pass on its first wave.
-template <typename Real>
+// runs the bead pass on its first wave.  FREE: the bead pass of the body passes, which takes
+// the bead positions from the step's stored poses while the records hold step n-1's.
+template <typename Real, bool FREE>
 __global__ __launch_bounds__(kCoupleBlock) void couple_adj_bead_kernel(const StepArgs<Real> a,
                                                                       const CoupleArgs c,
                                                                       const AdjArgs<Real> A,
@@ -918,7 +919,7 @@ __global__ __launch_bounds__(kCoupleBlock) void couple_adj_bead_kernel(const Ste
         return;
     }
     if ((int)threadIdx.x < kAdjBeadBlock)
-        adj_bead_lanes<Real>(A, ((int)blockIdx.x - n_cb) * kAdjBeadBlock + (int)threadIdx.x);
+        adj_bead_lanes<Real, FREE>(A, ((int)blockIdx.x - n_cb) * kAdjBeadBlock + (int)threadIdx.x);
 }
 
 template <typename Real>
@@ -928,8 +929,12 @@ void launch_couple_adj_bead(const StepArgs<Real>& a, const CoupleArgs& c, const 
     if (c.n_beads <= 0) return;
     const int n_cb = (c.n_beads * kBeadLanes + kCoupleBlock - 1) / kCoupleBlock;
     const int n_ab = (A.n_beads * kBeadLanes + kAdjBeadBlock - 1) / kAdjBeadBlock;
-    hipLaunchKernelGGL((couple_adj_bead_kernel<Real>), dim3(n_cb + n_ab), dim3(kCoupleBlock), 0,
-                       s, a, c, A, n_cb);
+    if (A.body_adj)
+        hipLaunchKernelGGL((couple_adj_bead_kernel<Real, true>), dim3(n_cb + n_ab),
+                           dim3(kCoupleBlock), 0, s, a, c, A, n_cb);
+    else
+        hipLaunchKernelGGL((couple_adj_bead_kernel<Real, false>), dim3(n_cb + n_ab),
+                           dim3(kCoupleBlock), 0, s, a, c, A, n_cb);
 }
 
 // pose of the coming step and its bead records, one workgroup per body
