@@ -225,6 +225,36 @@ def test_reverse_pass_with_holes_matches_oracle(precision):
     assert np.abs(dog - doo).max() <= tg * np.abs(doo).max(), np.abs(dog - doo).max()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_reverse_pass_in_the_baffled_pore_stored_along_it(precision):
+    """The reverse pass in the baffled pore, which the library stores in rows along z with
+    holes in the rows through the baffle (axes exchanged: the transposed mirror and the
+    transposed pull take c_i in storage coordinates), thermal, with the baffle moving, against
+    the oracle's reverse pass."""
+    from tests.helpers import oracle_from_workload
+    wl = baffle_case(precision, 4e-5, walls={2: (1e-3, 0.0, -5e-4)})
+    nb = len(wl["replicas"][0]["bodies"])
+    assert nb >= 1
+    T, K = 10, 4
+    rng = np.random.default_rng(8)
+    a = np.zeros((T, nb, 3))
+    a[:, 0, 2] = 1.0 / T
+    a += 0.02 * rng.standard_normal(a.shape)
+    print(f"reverse pass, baffled pore stored along z: {precision}", flush=True)
+    Jo, dgo, doo = oracle_from_workload(wl).adjoint(T, a)
+    sim = gpu_from_workload(wl)
+    assert sim.row_axis(0) == 2
+    Jg, dgg, dog = sim.adjoint(T, a, checkpoint_every=K)
+    sim.close()
+    print(f"  J rel {abs(Jg - Jo) / abs(Jo):.2e}  dgamma rel "
+          f"{np.abs(dgg - dgo).max() / np.abs(dgo).max():.2e}  doffsets rel "
+          f"{np.abs(dog - doo).max() / np.abs(doo).max():.2e}", flush=True)
+    tJ, tg = (1e-12, 1e-10) if precision == "f64" else (2e-6, 5e-6)
+    assert abs(Jg - Jo) <= tJ * abs(Jo), (Jg, Jo)
+    assert np.abs(dgg - dgo).max() <= tg * np.abs(dgo).max(), (dgg, dgo)
+    assert np.abs(dog - doo).max() <= tg * np.abs(doo).max(), np.abs(dog - doo).max()
+
+
 def _rotation(q):
     w, x, y, z = q
     return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
