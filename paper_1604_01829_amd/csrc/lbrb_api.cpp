@@ -878,9 +878,12 @@ void enqueue_replay(lb_ctx* c, hipStream_t s, const void* src, void* dst, int64_
 // launch); prev_src: the state of step - 1, whose coupling then runs in this step's bead launch
 // (nullptr: none, as at the start of a segment, whose states the replay rewrites first).
 // The bead forces of a reverse step go to one of two buffers by the parity of n.
-// snap: with body passes, the stored body tables of the window (the couplings are recomputed
-// from table n; the MD steps' body passes read the tables before and after each of them:
-// table n, the scratch tables of the recompute, table n + 1); prev_src is then null.
+// snap: with body passes, the stored body tables of the window.  With one MD step and no
+// excluded volume the schedule above holds, the records written from table n - 1 for the
+// shared coupling and the body pass reading tables n and n + 1; otherwise the couplings of
+// step n are recomputed from table n, the MD steps' body passes read the tables before and
+// after each of them (table n, the scratch tables of the recompute, table n + 1), and
+// prev_src is null.
 template <typename Real>
 void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, const Real* lam_next,
                      Real* lam_cur, char* ws, const AdjPlan& ap, int64_t n, bool coupled,
