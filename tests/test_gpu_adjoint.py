@@ -519,14 +519,14 @@ def test_full_size_sphere_window_gradient():
     assert np.abs(do32 - do).max() <= 1e-5 * np.abs(do).max()
 
 
-def _free_sphere_sim(precision, gamma=None, offsets=None):
+def _free_sphere_sim(precision, gamma=None, offsets=None, kT=0.0):
     """Workload 5's sphere released: free, spinning slowly at the start, in the same uniform
     flow, at the paper's free-body friction."""
     import copy
     from paper_1604_01829_amd import lbrb
     w = copy.deepcopy(W.workload(5))
     b = w["replicas"][0]["bodies"][0]
-    w["params"]["kT"] = 0.0
+    w["params"]["kT"] = kT
     b["fixed"] = False
     b["omega"] = np.array([0.002, -0.001, 0.0015])
     b["gamma"] = W.GAMMA_FREE if gamma is None else gamma
@@ -611,6 +611,27 @@ def test_full_size_sphere_against_the_oracle_adjoint(precision):
           flush=True)
     tJ, tg = (1e-12, 1e-10) if precision == "f64" else (5e-6, 5e-6)
     assert eJ <= tJ and eg <= tg and eo <= tg
+
+
+def test_full_size_thermal_free_sphere_gradient():
+    """64^3, the released R = 4 sphere in a thermal fluid (kT = 4e-5), 60 steps, checkpoints
+    every 20: the pathwise FP64 gradient in gamma (the bead noise amplitude scales with
+    sqrt(gamma)) against central differences of FP64 forward runs of the library, which draw
+    the same counter-based noise."""
+    T, K = 60, 20
+    a = np.zeros((T, 1, 3))
+    a[:, 0, 0] = 1.0 / T
+    kT = 4e-5
+    print("full-size thermal free-sphere adjoint: f64", flush=True)
+    _, sim = _free_sphere_sim("f64", kT=kT)
+    J, dg, do = sim.adjoint(T, a, checkpoint_every=K)
+    sim.close()
+    g0 = W.GAMMA_FREE
+    h = 1e-5 * g0
+    fd = (_forward_J(_free_sphere_sim("f64", gamma=g0 + h, kT=kT)[1], T, a)
+          - _forward_J(_free_sphere_sim("f64", gamma=g0 - h, kT=kT)[1], T, a)) / (2 * h)
+    print(f"  J {J:.6e}  dJ/dgamma {dg[0]:.9e}  central difference {fd:.9e}", flush=True)
+    assert abs(fd - dg[0]) <= 1e-6 * max(abs(fd), abs(J) / g0), (fd, dg[0])
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
