@@ -273,14 +273,23 @@ __device__ __forceinline__ int coarse_cell(double x, double L, double w, int n)
     return c < 0 ? 0 : (c >= n ? n - 1 : c);
 }
 
-// one workgroup per body with excluded-volume sites, one thread per site
-__global__ __launch_bounds__(256) void adj_wca_kernel(const BodyArgs ba, int par,
-                                                      const double* weights, const double* adj,
-                                                      double* wadj)
+// Workgroups of kWcaAdjBlock lanes along blockIdx.y over one body's sites (blockIdx.x),
+// eight lanes per site: lane `sub` of a site takes the entries sub, sub + 8, ... of the site's
+// coarse-cell neighbourhood list (skipped when the site's fine cell is flagged clear of every
+// static site) and of each other body's sites in reach.  Each pair's share for the partner goes
+// out by atomic adds; the site's own shares are summed over the workgroup (shuffles, LDS, fixed
+// order) and added once.
+constexpr int kWcaAdjBlock = 256;
+constexpr int kWcaAdjLanes = 8;
+
+__global__ __launch_bounds__(kWcaAdjBlock) void adj_wca_kernel(const BodyArgs ba, int par,
+                                                               const double* weights,
+                                                               const double* adj, double* wadj)
 {
     const int b = blockIdx.x;
     const Body& B = ba.bodies[b];
-    if (B.n_ev == 0) return;   // uniform over the workgroup
+    const int per_wg = kWcaAdjBlock / kWcaAdjLanes;
+    if (B.n_ev == 0 || (int)blockIdx.y * per_wg >= B.n_ev) return;   // uniform over the workgroup
     const Pose& P = B.pose[par];
     const WcaRep W = ba.wrep[B.replica];
     const double L[3] = {(double)B.box.nx, (double)B.box.ny, (double)B.box.nz};
@@ -288,8 +297,10 @@ __global__ __launch_bounds__(256) void adj_wca_kernel(const BodyArgs ba, int par
     double bj[6];   // Fbar_b, Tbar_b (lab)
     force_torque_adjoint(B, P.rot, adj + kBodyAdjWords * (int64_t)b, weights + 3 * (int64_t)b, bj);
     const bool free_b = B.fixed == 0;
+    const int k = blockIdx.y * per_wg + (int)threadIdx.x / kWcaAdjLanes;
+    const int sub = (int)threadIdx.x % kWcaAdjLanes;
     double acc[6] = {0, 0, 0, 0, 0, 0};             // this body's centre and angle adjoints
-    for (int k = threadIdx.x; k < B.n_ev; k += blockDim.x) {
+    if (k < B.n_ev) {
         const double* off = ba.ev[B.first_ev + k].off;
         double d[3], x[3], g[3];
         for (int ax = 0; ax < 3; ++ax) {
@@ -321,11 +332,16 @@ __global__ __launch_bounds__(256) void adj_wca_kernel(const BodyArgs ba, int par
             acc[4] += d[2] * a0 - d[0] * a2;
             acc[5] += d[0] * a1 - d[1] * a0;
         };
-        if (W.cx > 0) {   // static sites: the coarse cell's neighbourhood holds every one in range
+        // static sites: the coarse cell's neighbourhood holds every one in range; the fine flag
+        // tells whether any can be
+        if (W.cx > 0 &&
+            ba.near[W.fine0 + coarse_cell(x[0], L[0], W.fw[0], W.gx) +
+                    W.gx * (coarse_cell(x[1], L[1], W.fw[1], W.gy) +
+                            W.gy * coarse_cell(x[2], L[2], W.fw[2], W.gz))] != 0) {
             const int cell = W.cell0 + coarse_cell(x[0], L[0], W.cw[0], W.cx) +
                              W.cx * (coarse_cell(x[1], L[1], W.cw[1], W.cy) +
                                      W.cy * coarse_cell(x[2], L[2], W.cw[2], W.cz));
-            for (int i = ba.nb_start[cell]; i < ba.nb_start[cell + 1]; ++i) {
+            for (int i = ba.nb_start[cell] + sub; i < ba.nb_start[cell + 1]; i += kWcaAdjLanes) {
                 const WallSite ws = ba.nb_sites[i];
                 double dd[3], db[3], f[3];
                 min_image3(x, ws.p, L, dd);
@@ -343,7 +359,7 @@ __global__ __launch_bounds__(256) void adj_wca_kernel(const BodyArgs ba, int par
             const double reach = B.ev_reach + O.ev_reach + 1.1224620483093730 * (B.ev_radius + O.ev_radius);
             if (!(dc[0] * dc[0] + dc[1] * dc[1] + dc[2] * dc[2] < reach * reach)) continue;
             const bool free_o = O.fixed == 0;
-            for (int m = 0; m < O.n_ev; ++m) {
+            for (int m = sub; m < O.n_ev; m += kWcaAdjLanes) {
                 const double* oo = ba.ev[O.first_ev + m].off;
                 double dq[3], y[3], dd[3], db[3], f[3];
                 for (int ax = 0; ax < 3; ++ax) {
@@ -368,17 +384,23 @@ __global__ __launch_bounds__(256) void adj_wca_kernel(const BodyArgs ba, int par
     if (!free_b) return;   // uniform
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1)
-        for (int k = 0; k < 6; ++k) acc[k] += __shfl_down(acc[k], m, 64);
+        for (int q = 0; q < 6; ++q) acc[q] += __shfl_down(acc[q], m, 64);
+    __shared__ double part[kWcaAdjBlock / 64][6];
     if ((threadIdx.x & 63) == 0)
-        for (int k = 0; k < 6; ++k) atomicAdd(wadj + 6 * (int64_t)b + k, acc[k]);
+        for (int q = 0; q < 6; ++q) part[threadIdx.x >> 6][q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 6; ++q)
+            atomicAdd(wadj + 6 * (int64_t)b + q, (part[0][q] + part[1][q]) + (part[2][q] + part[3][q]));
 }
 
 void launch_adjoint_wca(const BodyArgs& ba, int par, const double* weights, const double* adj,
-                        double* wadj, hipStream_t s)
+                        double* wadj, int max_ev, hipStream_t s)
 {
-    if (ba.n_bodies <= 0 || !ba.wca_ft) return;
-    hipLaunchKernelGGL(adj_wca_kernel, dim3(ba.n_bodies), dim3(256), 0, s, ba, par, weights, adj,
-                       wadj);
+    if (ba.n_bodies <= 0 || !ba.wca_ft || max_ev <= 0) return;
+    const int per_wg = kWcaAdjBlock / kWcaAdjLanes;
+    hipLaunchKernelGGL(adj_wca_kernel, dim3(ba.n_bodies, (max_ev + per_wg - 1) / per_wg),
+                       dim3(kWcaAdjBlock), 0, s, ba, par, weights, adj, wadj);
 }
 
 template void launch_adjoint_step<float>(const AdjArgs<float>&, bool, hipStream_t);

@@ -764,6 +764,14 @@ bool any_free(const lb_ctx* c)
     return false;
 }
 
+// the most excluded-volume sites of any body
+int max_ev_sites(const lb_ctx* c)
+{
+    size_t m = 0;
+    for (const EvHost& E : c->ev) m = std::max(m, E.off.size() / 3);
+    return (int)m;
+}
+
 // excluded-volume forces act (from the sites as set, whether or not their tables are built)
 bool has_wca(const lb_ctx* c)
 {
@@ -980,7 +988,7 @@ void enqueue_adjoint(lb_ctx* c, hipStream_t s, const void* src, int64_t step, co
             if (has_wca(c)) {
                 BodyArgs wb = body_args(c);
                 wb.bodies = const_cast<Body*>(table(k));
-                launch_adjoint_wca(wb, par, X.weights, badj, wadj, s);
+                launch_adjoint_wca(wb, par, X.weights, badj, wadj, max_ev_sites(c), s);
             }
             launch_adjoint_body_post(table(k), table(k + 1), par, X.weights,
                                      (const double*)(ws + ap.off_bsum), badj, wadj,

@@ -284,9 +284,10 @@ void launch_adjoint_body_post(const Body* in, const Body* out, int par, const do
 // site (ba.bodies at pose[par]) with a static site or another body's site, the pair force's
 // Jacobian takes the adjoint of the force on the first site (Fbar_b + Tbar_b x d, formed from
 // the state adjoint adj and the weights) to both sites' positions, and the torque's arm adds
-// f x Tbar_b: into wadj of the free bodies involved (atomic adds).
+// f x Tbar_b: into wadj of the free bodies involved (atomic adds).  max_ev: the most sites of
+// any body.
 void launch_adjoint_wca(const BodyArgs& ba, int par, const double* weights, const double* adj,
-                        double* wadj, hipStream_t s);
+                        double* wadj, int max_ev, hipStream_t s);
 // the pose part of every bead record from its body's pose[par] (the records a step's coupling
 // reads), for recomputing the steps of a window
 void launch_records_from_poses(const Body* bodies, int par, const Bead* beads, BeadRec* recs,
