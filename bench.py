@@ -362,6 +362,7 @@ def compare_runs(args, wl4):
     sim.set_graph_steps(100)
     sim.step(200)
     sim.adjoint(T, a, K)                    # warm-up of the reverse pass
+    sim.step(T)                             # and of the forward's graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(T)
@@ -384,6 +385,7 @@ def compare_runs(args, wl4):
     sim = lbrb.simulation_from_workload(wl5, precision="f32")
     sim.set_graph_steps(100)
     sim.adjoint(T, a, K)                    # warm-up
+    sim.step(T)                             # and of the forward's graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(T)
